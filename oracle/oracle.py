@@ -1,0 +1,404 @@
+"""FP64 CPU oracle for the Tucker compression of Matern / Slater covariance tensors.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg
+of ``bench.py`` may import this module.  It shares no code with the GPU library and neither
+imports the other.  The heavy loops live in ``oracle.c`` (explicit loops, IEEE double, no
+BLAS/LAPACK); this file strings them together in the order the paper describes.
+
+Paper: Litvinenko et al., "Tucker tensor analysis of Matern functions in spatial statistics"
+(arXiv 1711.06874).
+
+Readings where the paper is silent (each one is also listed in the design notes):
+  * grid: centred vertex grid x_i = -b + i h, h = 2b/(n-1) (Sec. 3.7 eq. (3.25)); the offset
+    layout x_i = i h holds the generator at every node difference (Sec. 3.6 needs the
+    generator at offsets 0..n-1 to build Toeplitz factors defined by their first column);
+  * Slater family sigma2 * exp(-alpha (r/ell)^p) (Sec. 3.7 eq. (3.27) with amplitude/scale);
+  * HOSVD factors from the Gram matrices A_(k) A_(k)^T (same subspaces as the SVD of A_(k),
+    Sec. 3.2); eigenvectors signed so the largest-magnitude entry is positive;
+  * eps rank rule (not given in the paper): per mode, the smallest r with
+    sum_{i>r} lambda_i <= eps^2 ||A||^2 / 3, the standard HOSVD truncation, which guarantees
+    a relative Frobenius error <= eps;
+  * HOOI: Gauss-Seidel sweeps over modes 1,2,3, core from the last single-hole tensor;
+    "converged" means | ||G|| - ||G_prev|| | <= 1e-13 ||A|| (at most 50 sweeps).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+MATERN, SLATER, GAUSS = 0, 1, 2
+CENTERED, OFFSET = 0, 1
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so with gcc (OpenMP, no fast-math, no FP contraction)."""
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O3", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
+                               "-Wall", "-o", tmp, src, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.tko_kernel.restype = ctypes.c_double
+    lib.tko_kernel.argtypes = [ctypes.c_int] + [ctypes.c_double] * 6
+    lib.tko_grid_coords.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, dp]
+    lib.tko_grid_eval.argtypes = [ctypes.c_int] + [ctypes.c_double] * 5 + [ip, dp, ctypes.c_int, dp]
+    lib.tko_gram.argtypes = [dp, ip, ctypes.c_int, dp]
+    lib.tko_jacobi_eig.restype = ctypes.c_int
+    lib.tko_jacobi_eig.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_double]
+    lib.tko_mode_product.argtypes = [dp, ip, ctypes.c_int, dp, ctypes.c_int, dp]
+    lib.tko_sumsq.restype = ctypes.c_double
+    lib.tko_sumsq.argtypes = [dp, ctypes.c_size_t]
+    lib.tko_diff_sumsq.restype = ctypes.c_double
+    lib.tko_diff_sumsq.argtypes = [dp, dp, ctypes.c_size_t]
+    lib.tko_cov_rows.argtypes = [dp, ip, ip, ip, dp, ctypes.POINTER(ctypes.c_longlong),
+                                 ctypes.c_int, dp]
+    lib.tko_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(v):
+    arr = (ctypes.c_int * len(v))(*[int(x) for x in v])
+    return arr
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return int(_load().tko_num_threads())
+
+
+# ----------------------------------------------------------------------------------------
+# Covariance functions and the collocation tensor
+# ----------------------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class Kernel:
+    family: int = MATERN
+    nu: float = 0.5
+    ell: float = 1.0
+    sigma2: float = 1.0
+    alpha: float = 1.0
+    p: float = 1.0
+
+
+@dataclass(frozen=True)
+class Grid:
+    n: tuple = (8, 8, 8)
+    b: tuple = (1.0, 1.0, 1.0)
+    layout: int = CENTERED
+
+
+def kernel_value(k: Kernel, r: float) -> float:
+    """Covariance value at distance r (Sec. 2.2 eq. (2.3); Sec. 3.7 eq. (3.27))."""
+    return float(_load().tko_kernel(k.family, k.nu, k.ell, k.sigma2, k.alpha, k.p, float(r)))
+
+
+def grid_coords(n: int, b: float, layout: int) -> np.ndarray:
+    x = np.empty(n, dtype=np.float64)
+    _load().tko_grid_coords(int(n), float(b), int(layout), _dp(x))
+    return x
+
+
+def grid_eval(k: Kernel, g: Grid) -> np.ndarray:
+    """Collocation tensor A[i0,i1,i2] = k(||x_i||) on the grid (Sec. 3.7 eq. (3.25))."""
+    A = np.empty(tuple(g.n), dtype=np.float64)
+    _load().tko_grid_eval(k.family, k.nu, k.ell, k.sigma2, k.alpha, k.p, _ip(g.n),
+                          (ctypes.c_double * 3)(*g.b), int(g.layout), _dp(A))
+    return A
+
+
+# ----------------------------------------------------------------------------------------
+# Linear-algebra primitives
+# ----------------------------------------------------------------------------------------
+
+def gram(X: np.ndarray, mode: int) -> np.ndarray:
+    """G_k = X_(k) X_(k)^T (Sec. 3.2: HOSVD works on the mode unfoldings)."""
+    X = _f64(X)
+    d = X.shape
+    G = np.empty((d[mode], d[mode]), dtype=np.float64)
+    _load().tko_gram(_dp(X), _ip(d), int(mode), _dp(G))
+    return G
+
+
+def jacobi_eig(S: np.ndarray, max_sweeps: int = 60, tol: float = 1e-15):
+    """Full symmetric eigendecomposition by two-sided Jacobi; descending, sign-normalised."""
+    S = _f64(S)
+    n = S.shape[0]
+    lam = np.empty(n, dtype=np.float64)
+    V = np.empty((n, n), dtype=np.float64)
+    sweeps = _load().tko_jacobi_eig(n, _dp(S), _dp(lam), _dp(V), int(max_sweeps), float(tol))
+    return lam, V, int(sweeps)
+
+
+def mode_product(X: np.ndarray, mode: int, M: np.ndarray) -> np.ndarray:
+    """Y = X x_mode M with M of shape (J, X.shape[mode]) (Sec. 3.1 contracted products)."""
+    X = _f64(X)
+    M = _f64(M)
+    d = list(X.shape)
+    assert M.shape[1] == d[mode]
+    e = list(d)
+    e[mode] = M.shape[0]
+    Y = np.empty(tuple(e), dtype=np.float64)
+    _load().tko_mode_product(_dp(X), _ip(d), int(mode), _dp(M), int(M.shape[0]), _dp(Y))
+    return Y
+
+
+def sumsq(X: np.ndarray) -> float:
+    X = _f64(X)
+    return float(_load().tko_sumsq(_dp(X), X.size))
+
+
+def diff_sumsq(X: np.ndarray, Y: np.ndarray) -> float:
+    X = _f64(X)
+    Y = _f64(Y)
+    assert X.shape == Y.shape
+    return float(_load().tko_diff_sumsq(_dp(X), _dp(Y), X.size))
+
+
+# ----------------------------------------------------------------------------------------
+# Tucker format: HOSVD, eps rank rule, HOOI (Sec. 3.1 eq. (3.4), Sec. 3.2)
+# ----------------------------------------------------------------------------------------
+
+@dataclass
+class Tucker:
+    U: list                      # three factor matrices, n_k x r_k, orthonormal columns
+    core: np.ndarray             # r1 x r2 x r3
+    norm_a2: float = 0.0         # ||A||_F^2
+    rel_err: float = float("nan")
+    lambdas: list = field(default_factory=list)   # HOSVD Gram eigenvalues per mode (all n_k)
+    history: list = field(default_factory=list)   # ||core|| after every HOOI mode update
+    sweeps: int = 0
+
+    @property
+    def ranks(self):
+        return tuple(int(u.shape[1]) for u in self.U)
+
+
+def project_core(A: np.ndarray, U) -> np.ndarray:
+    """G = A x_1 U1^T x_2 U2^T x_3 U3^T."""
+    X = A
+    for k in range(3):
+        X = mode_product(X, k, U[k].T)
+    return X
+
+
+def reconstruct(core: np.ndarray, U) -> np.ndarray:
+    """A_(r) = G x_1 U1 x_2 U2 x_3 U3 (Sec. 3.1, Tucker format in contracted-product form)."""
+    X = core
+    for k in (2, 1, 0):
+        X = mode_product(X, k, U[k])
+    return X
+
+
+def hosvd_factors(A: np.ndarray):
+    """Full eigendecompositions of the three mode Grams: (lambda_k, V_k) for k = 0,1,2."""
+    out = []
+    for k in range(3):
+        lam, V, sweeps = jacobi_eig(gram(A, k))
+        if sweeps < 0:
+            raise RuntimeError("Jacobi did not converge")
+        out.append((lam, V))
+    return out
+
+
+def eps_ranks(lambdas, norm_a2: float, eps: float, cap=None):
+    """Per-mode truncation: smallest r >= 1 with sum_{i>r} lambda_i <= eps^2 ||A||^2 / 3."""
+    ranks = []
+    for k, lam in enumerate(lambdas):
+        budget = eps * eps * norm_a2 / 3.0
+        n = lam.shape[0]
+        r = n
+        for cand in range(1, n + 1):
+            tail = float(np.sum(np.maximum(lam[cand:], 0.0)))
+            if tail <= budget:
+                r = cand
+                break
+        if cap is not None:
+            r = min(r, int(cap[k]))
+        ranks.append(r)
+    return tuple(ranks)
+
+
+def hosvd(A: np.ndarray, ranks, factors=None) -> Tucker:
+    """Truncated HOSVD: U_k = leading r_k eigenvectors of A_(k)A_(k)^T, G = A x_k U_k^T."""
+    A = _f64(A)
+    if factors is None:
+        factors = hosvd_factors(A)
+    U = [factors[k][1][:, : min(int(ranks[k]), A.shape[k])].copy() for k in range(3)]
+    core = project_core(A, U)
+    na2 = sumsq(A)
+    t = Tucker(U=U, core=core, norm_a2=na2, lambdas=[f[0] for f in factors])
+    t.rel_err = rel_error(A, t)
+    return t
+
+
+def hooi(A: np.ndarray, init: Tucker, sweeps=None, converge_tol: float = 1e-13,
+         max_sweeps: int = 50) -> Tucker:
+    """Tucker-ALS (HOOI), Sec. 3.2: for each mode, build the single-hole tensor
+    B_k = A x_{j != k} U_j^T with the latest factors and replace U_k by the leading r_k
+    eigenvectors of B_(k) B_(k)^T; the core is B_3 x_3 U_3^T after the last update.
+
+    sweeps=None runs to convergence (| ||G|| - ||G_prev|| | <= converge_tol ||A||)."""
+    A = _f64(A)
+    U = [u.copy() for u in init.U]
+    r = [u.shape[1] for u in U]
+    na = float(np.sqrt(init.norm_a2 if init.norm_a2 > 0 else sumsq(A)))
+    prev = float(np.sqrt(sumsq(init.core)))
+    history = [prev]
+    nsweeps = sweeps if sweeps is not None else max_sweeps
+    done = 0
+    core = init.core
+    for _ in range(nsweeps):
+        for k in range(3):
+            B = A
+            for j in range(3):
+                if j != k:
+                    B = mode_product(B, j, U[j].T)
+            lam, V, s = jacobi_eig(gram(B, k))
+            if s < 0:
+                raise RuntimeError("Jacobi did not converge")
+            U[k] = V[:, : r[k]].copy()
+            core = mode_product(B, k, U[k].T)
+            history.append(float(np.sqrt(sumsq(core))))
+        done += 1
+        cur = history[-1]
+        if sweeps is None and abs(cur - prev) <= converge_tol * na:
+            break
+        prev = cur
+    t = Tucker(U=U, core=core, norm_a2=init.norm_a2, lambdas=init.lambdas, history=history,
+               sweeps=done)
+    t.rel_err = rel_error(A, t)
+    return t
+
+
+def rel_error(A: np.ndarray, t: Tucker) -> float:
+    """E_FN = ||A - A_(r)||_F / ||A||_F with an explicit reconstruction (Sec. 3.7 eq. (3.26))."""
+    Ah = reconstruct(t.core, t.U)
+    return float(np.sqrt(diff_sumsq(A, Ah) / sumsq(A)))
+
+
+def compress(k: Kernel, g: Grid, ranks=None, eps: float = 0.0, sweeps=2,
+             A: np.ndarray = None) -> Tucker:
+    """Task 1 of Sec. 2.1 on the collocation tensor: HOSVD (fixed ranks or the eps rule),
+    then `sweeps` HOOI sweeps (None = to convergence, 0 = HOSVD only)."""
+    if A is None:
+        A = grid_eval(k, g)
+    factors = hosvd_factors(A)
+    na2 = sumsq(A)
+    if ranks is None:
+        if not eps > 0:
+            raise ValueError("either ranks or eps > 0 is required")
+        ranks = eps_ranks([f[0] for f in factors], na2, eps)
+    ranks = tuple(min(int(r), A.shape[i]) for i, r in enumerate(ranks))
+    t = hosvd(A, ranks, factors)
+    if sweeps != 0:
+        t = hooi(A, t, sweeps=sweeps)
+    return t
+
+
+# ----------------------------------------------------------------------------------------
+# Covariance operator in Kronecker-Toeplitz form (Sec. 3.6, Sec. 4 eq. (4.1), (4.3))
+# ----------------------------------------------------------------------------------------
+
+def cov_offsets(g: Grid):
+    """(off, m): the operator acts on m_k points per axis with T_{ij} = u[off_k + |i-j|].
+    Offset layout: off = 0, m = n.  Odd centred layout n = 2k+1: off = k (the origin node),
+    m = k+1 (the non-negative sector).  Even centred grids have no origin node: None."""
+    off, m = [], []
+    for n in g.n:
+        if g.layout == OFFSET:
+            off.append(0)
+            m.append(n)
+        elif n % 2 == 1:
+            off.append((n - 1) // 2)
+            m.append((n + 1) // 2)
+        else:
+            return None
+    return tuple(off), tuple(m)
+
+
+def cov_matvec_rows(t: Tucker, g: Grid, z: np.ndarray, rows) -> np.ndarray:
+    """y_i = sum_j C_ij z_j for the requested flat row indices, with the covariance generated
+    by the reconstructed Tucker tensor: C_ij = A_(r)(off + |i - j|) (per axis)."""
+    om = cov_offsets(g)
+    if om is None:
+        raise ValueError("covariance operator needs an origin node (offset or odd centred grid)")
+    off, m = om
+    Q = _f64(reconstruct(t.core, t.U))
+    z = _f64(z).reshape(-1)
+    assert z.size == m[0] * m[1] * m[2]
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    y = np.empty(rows.size, dtype=np.float64)
+    _load().tko_cov_rows(_dp(Q), _ip(Q.shape), _ip(off), _ip(m), _dp(z),
+                         rows.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), int(rows.size),
+                         _dp(y))
+    return y
+
+
+def cov_matvec(t: Tucker, g: Grid, z: np.ndarray) -> np.ndarray:
+    om = cov_offsets(g)
+    if om is None:
+        raise ValueError("covariance operator needs an origin node")
+    m = om[1]
+    return cov_matvec_rows(t, g, z, np.arange(m[0] * m[1] * m[2])).reshape(m)
+
+
+def cov_trace(t: Tucker, g: Grid) -> float:
+    """trace(C) = (number of points) * A_(r)(origin): every diagonal entry of the Toeplitz
+    covariance is the generator's value at offset 0 (Sec. 4, trace/diag via the origin)."""
+    om = cov_offsets(g)
+    if om is None:
+        raise ValueError("covariance operator needs an origin node")
+    off, m = om
+    Q = reconstruct(t.core, t.U)
+    return float(m[0] * m[1] * m[2] * Q[off[0], off[1], off[2]])
+
+
+def cov_trace_kron(t: Tucker, g: Grid) -> float:
+    """trace(sum_abc G_abc T(u1a) (x) T(u2b) (x) T(u3c)) = sum_abc G_abc prod_k trace T(u_k)
+    (Sec. 4 eq. (4.3)); trace T(u) = m * u[off]."""
+    om = cov_offsets(g)
+    if om is None:
+        raise ValueError("covariance operator needs an origin node")
+    off, m = om
+    tr = [m[k] * t.U[k][off[k], :] for k in range(3)]
+    total = 0.0
+    r = t.core.shape
+    for a in range(r[0]):
+        for b in range(r[1]):
+            for c in range(r[2]):
+                total += t.core[a, b, c] * tr[0][a] * tr[1][b] * tr[2][c]
+    return float(total)
+
+
+def quadratic_form(t: Tucker, g: Grid, z: np.ndarray) -> float:
+    """z^T C z with the plain matrix-vector product."""
+    y = cov_matvec(t, g, z)
+    return float(np.dot(_f64(z).reshape(-1), y.reshape(-1)))

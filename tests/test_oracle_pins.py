@@ -1,0 +1,410 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+None of these compare the oracle with itself: each checks it against a library routine used
+only here (scipy / numpy), a closed form, an invariant, a special case with a textbook answer,
+brute force on tiny inputs, or the values the paper prints (Table 4.2).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy import special
+
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- covariance functions ----
+
+@pytest.mark.parametrize("nu", [0.5, 1.5, 2.5])
+@pytest.mark.parametrize("ell", [0.05, 0.3, 1.0])
+def test_matern_matches_scipy_bessel(oracle, nu, ell):
+    """Sec. 2.2 eq. (2.3) evaluated with scipy's K_nu and Gamma."""
+    for r in [1e-6, 0.01, 0.1, 0.5, 1.0, 1.7]:
+        s = np.sqrt(2 * nu) * r / ell
+        if s > 600:
+            continue
+        ref = 2.0 ** (1 - nu) / special.gamma(nu) * s ** nu * special.kv(nu, s)
+        got = oracle.kernel_value(oracle.Kernel(oracle.MATERN, nu=nu, ell=ell, sigma2=2.0), r)
+        assert got == pytest.approx(2.0 * ref, rel=1e-12, abs=1e-300)
+
+
+@pytest.mark.parametrize("nu", [0.5, 1.5, 2.5])
+def test_matern_closed_forms(oracle, nu):
+    """The half-integer closed forms: e^{-s}, (1+s)e^{-s}, (1+s+s^2/3)e^{-s}."""
+    ell = 0.37
+    for r in np.linspace(0.0, 2.0, 23):
+        s = np.sqrt(2 * nu) * r / ell
+        poly = {0.5: 1.0, 1.5: 1.0 + s, 2.5: 1.0 + s + s * s / 3.0}[nu]
+        assert oracle.kernel_value(oracle.Kernel(oracle.MATERN, nu=nu, ell=ell), r) == \
+            pytest.approx(poly * np.exp(-s), rel=1e-13, abs=1e-300)
+
+
+def test_kernel_at_zero_is_variance(oracle):
+    for fam, kw in [(oracle.MATERN, dict(nu=0.5)), (oracle.MATERN, dict(nu=1.5)),
+                    (oracle.MATERN, dict(nu=2.5)), (oracle.SLATER, dict(p=0.1)),
+                    (oracle.GAUSS, {})]:
+        assert oracle.kernel_value(oracle.Kernel(fam, ell=0.2, sigma2=3.5, **kw), 0.0) == 3.5
+
+
+def test_unsupported_nu_is_nan(oracle):
+    assert np.isnan(oracle.kernel_value(oracle.Kernel(oracle.MATERN, nu=0.7), 0.3))
+
+
+def test_slater_p1_equals_exponential_matern(oracle):
+    for ell in (0.1, 0.3, 1.0):
+        for r in np.linspace(0.0, 1.8, 19):
+            a = oracle.kernel_value(oracle.Kernel(oracle.SLATER, alpha=1.0, p=1.0, ell=ell), r)
+            b = oracle.kernel_value(oracle.Kernel(oracle.MATERN, nu=0.5, ell=ell), r)
+            assert a == pytest.approx(b, rel=1e-14, abs=1e-300)
+
+
+# ------------------------------------------------------------------------------- grid ----
+
+def test_grid_coordinates(oracle):
+    x = oracle.grid_coords(9, 2.0, oracle.CENTERED)
+    np.testing.assert_allclose(x, np.linspace(-2.0, 2.0, 9), rtol=0, atol=1e-15)
+    y = oracle.grid_coords(9, 2.0, oracle.OFFSET)
+    np.testing.assert_allclose(y, np.linspace(0.0, 4.0, 9), rtol=0, atol=1e-15)
+
+
+def test_grid_values_direct(oracle):
+    """Entries against a direct numpy evaluation of the closed form on explicit coordinates."""
+    k = oracle.Kernel(oracle.MATERN, nu=1.5, ell=0.3, sigma2=1.7)
+    g = oracle.Grid(n=(5, 6, 7), b=(1.0, 0.5, 2.0), layout=oracle.CENTERED)
+    A = oracle.grid_eval(k, g)
+    xs = [np.linspace(-b, b, n) for n, b in zip(g.n, g.b)]
+    X, Y, Z = np.meshgrid(*xs, indexing="ij")
+    s = np.sqrt(3.0) * np.sqrt(X ** 2 + Y ** 2 + Z ** 2) / 0.3
+    np.testing.assert_allclose(A, 1.7 * (1 + s) * np.exp(-s), rtol=1e-13, atol=0)
+
+
+def test_grid_symmetries(oracle):
+    k = oracle.Kernel(oracle.MATERN, nu=2.5, ell=0.4)
+    A = oracle.grid_eval(k, oracle.Grid(n=(11, 11, 11)))
+    np.testing.assert_allclose(A, A[::-1, :, :], rtol=1e-14)
+    np.testing.assert_allclose(A, A[:, ::-1, ::-1], rtol=1e-14)
+    np.testing.assert_allclose(A, A.transpose(1, 0, 2), rtol=1e-14)
+    np.testing.assert_allclose(A, A.transpose(2, 1, 0), rtol=1e-14)
+
+
+# ------------------------------------------------------------------------------- Gram ----
+
+@pytest.mark.parametrize("shape", [(3, 4, 5), (8, 8, 8), (7, 2, 6)])
+def test_gram_bruteforce(oracle, shape):
+    X = synth.random_tensor(shape, 1)
+    subs = ["ajk,bjk->ab", "iaj,ibj->ab", "ija,ijb->ab"]
+    for k in range(3):
+        G = oracle.gram(X, k)
+        np.testing.assert_allclose(G, np.einsum(subs[k], X, X), rtol=1e-13, atol=1e-13)
+        assert np.trace(G) == pytest.approx(np.sum(X * X), rel=1e-13)
+        np.testing.assert_array_equal(G, G.T)
+        assert np.linalg.eigvalsh(G).min() > -1e-12 * np.trace(G)
+
+
+def test_gram_equal_modes_on_symmetric_tensor(oracle):
+    A = oracle.grid_eval(oracle.Kernel(oracle.MATERN, nu=0.5, ell=0.3), oracle.Grid(n=(9, 9, 9)))
+    G = [oracle.gram(A, k) for k in range(3)]
+    np.testing.assert_allclose(G[0], G[1], rtol=1e-13)
+    np.testing.assert_allclose(G[0], G[2], rtol=1e-13)
+
+
+# ------------------------------------------------------------------------------ eigen ----
+
+def _sign_fix(V):
+    V = V.copy()
+    for j in range(V.shape[1]):
+        a = np.abs(V[:, j])
+        lead = int(np.nonzero(a >= a.max() * (1 - 1e-10))[0][0])
+        if V[lead, j] < 0:
+            V[:, j] = -V[:, j]
+    return V
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 20, 33])
+def test_jacobi_matches_eigh(oracle, n):
+    rng = np.random.default_rng(n)
+    B = rng.standard_normal((n, n))
+    S = B + B.T
+    lam, V, sweeps = oracle.jacobi_eig(S)
+    assert sweeps >= 0
+    ref_l, ref_v = np.linalg.eigh(S)
+    order = np.argsort(-ref_l, kind="stable")
+    np.testing.assert_allclose(lam, ref_l[order], rtol=0, atol=1e-13 * np.linalg.norm(S))
+    np.testing.assert_allclose(V, _sign_fix(ref_v[:, order]), rtol=0, atol=1e-11)
+    np.testing.assert_allclose(V.T @ V, np.eye(n), atol=1e-14 * max(n, 1) ** 0.5 * 10)
+    resid = S @ V - V * lam[None, :]
+    assert np.abs(resid).max() <= 1e-13 * np.linalg.norm(S)
+    assert np.all(np.diff(lam) <= 0)
+
+
+def test_jacobi_gram_spectrum_and_trace(oracle):
+    A = oracle.grid_eval(oracle.Kernel(oracle.MATERN, nu=0.5, ell=0.3), oracle.Grid(n=(24, 20, 16)))
+    for k in range(3):
+        G = oracle.gram(A, k)
+        lam, V, _ = oracle.jacobi_eig(G)
+        assert np.sum(lam) == pytest.approx(np.trace(G), rel=1e-13)
+        assert np.abs(G @ V - V * lam).max() <= 1e-13 * np.linalg.norm(G)
+        np.testing.assert_allclose(lam[:6], np.linalg.eigvalsh(G)[::-1][:6], rtol=0,
+                                   atol=1e-13 * np.linalg.norm(G))
+
+
+def test_jacobi_repeated_eigenvalues(oracle):
+    rng = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(rng.standard_normal((10, 10)))
+    d = np.array([5.0, 5.0, 5.0, 2.0, 2.0, 1.0, 0.0, 0.0, -1.0, -1.0])
+    S = (Q * d) @ Q.T
+    lam, V, _ = oracle.jacobi_eig(S)
+    np.testing.assert_allclose(lam, np.sort(d)[::-1], atol=1e-13)
+    np.testing.assert_allclose(V.T @ V, np.eye(10), atol=1e-13)
+    assert np.abs(S @ V - V * lam).max() <= 1e-13 * 10
+
+
+# -------------------------------------------------------------------- mode products ----
+
+def test_mode_product_bruteforce(oracle):
+    X = synth.random_tensor((4, 5, 6), 2)
+    rng = np.random.default_rng(5)
+    subs = ["ja,abc->jbc", "jb,abc->ajc", "jc,abc->abj"]
+    for k in range(3):
+        M = rng.standard_normal((3, X.shape[k]))
+        np.testing.assert_allclose(oracle.mode_product(X, k, M), np.einsum(subs[k], M, X),
+                                   rtol=1e-13, atol=1e-13)
+
+
+# -------------------------------------------------------------------------- HOSVD ----
+
+def test_full_rank_is_exact(oracle):
+    """Full rank gives an exact representation (Sec. 1 list of properties)."""
+    X = synth.random_tensor((5, 6, 7), 3)
+    t = oracle.hosvd(X, X.shape)
+    assert t.rel_err <= 1e-13
+    np.testing.assert_allclose(oracle.reconstruct(t.core, t.U), X, atol=1e-13)
+    for u in t.U:
+        np.testing.assert_allclose(u.T @ u, np.eye(u.shape[1]), atol=1e-13)
+
+
+def test_gaussian_is_rank_one(oracle):
+    """Separable covariance (Sec. 4.4): the Gaussian kernel is a rank-1 tensor."""
+    A = oracle.grid_eval(oracle.Kernel(oracle.GAUSS, ell=0.6), oracle.Grid(n=(12, 10, 14)))
+    t = oracle.hosvd(A, (1, 1, 1))
+    assert t.rel_err <= 1e-13
+    # eps^2 must stay above the Gram route's FP64 noise (~1e-16 relative eigenvalues)
+    assert oracle.eps_ranks(t.lambdas, t.norm_a2, 1e-6) == (1, 1, 1)
+
+
+def test_separable_exponential_is_rank_one(oracle):
+    """Sec. 3.1: exp(x1 + x2 + x3) discretised on a tensor grid is canonical rank 1."""
+    xs = [np.linspace(-1, 1, n) for n in (9, 11, 13)]
+    A = np.exp(xs[0][:, None, None] + xs[1][None, :, None] + xs[2][None, None, :])
+    t = oracle.hosvd(A, (1, 1, 1))
+    assert t.rel_err <= 1e-13
+
+
+def test_two_dimensional_case_is_svd(oracle):
+    """Sec. 3.1: for d = 2 the orthogonal Tucker decomposition is the SVD."""
+    A3 = oracle.grid_eval(oracle.Kernel(oracle.MATERN, nu=0.5, ell=0.3),
+                          oracle.Grid(n=(30, 24, 5)))
+    A = np.ascontiguousarray(A3[:, :, 1:2])        # a 30 x 24 x 1 tensor (d = 2)
+    M = A[:, :, 0]
+    s = np.linalg.svd(M, compute_uv=False)
+    Usvd, _, _ = np.linalg.svd(M)
+    for r in (1, 2, 3, 4):
+        t = oracle.hosvd(A, (r, r, 1))
+        expect = np.sqrt(np.sum(s[r:] ** 2)) / np.sqrt(np.sum(s ** 2))
+        assert expect > 1e-6          # above the Gram route's FP64 floor (~sqrt(u))
+        assert t.rel_err == pytest.approx(expect, rel=1e-6)
+        # same leading left singular subspace
+        P = t.U[0] @ t.U[0].T
+        Ps = Usvd[:, :r] @ Usvd[:, :r].T
+        assert np.abs(P - Ps).max() < 1e-8
+
+
+def _c1_tensor(oracle, n=32):
+    return oracle.grid_eval(oracle.Kernel(oracle.MATERN, nu=0.5, ell=0.3), oracle.Grid(n=(n, n, n)))
+
+
+def test_hosvd_sandwich_bound(oracle):
+    """HOSVD error bound: max_k tau_k <= E^2 <= sum_k tau_k (De Lathauwer et al.)."""
+    A = oracle.grid_eval(oracle.Kernel(oracle.MATERN, nu=1.5, ell=0.25),
+                         oracle.Grid(n=(20, 16, 12)))
+    f = oracle.hosvd_factors(A)
+    na2 = oracle.sumsq(A)
+    for r in (1, 2, 4, 6):
+        t = oracle.hosvd(A, (r, r, r), f)
+        tau = [np.sum(f[k][0][r:]) / na2 for k in range(3)]
+        e2 = t.rel_err ** 2
+        assert max(tau) * (1 - 1e-9) <= e2 <= sum(tau) * (1 + 1e-9) + 1e-28
+
+
+def test_hosvd_error_decays_exponentially(oracle):
+    """Sec. 3.7: E_FN decays exponentially in the Tucker rank (above the FP64 floor of the
+    Gram route) and never increases with r (nested subspaces)."""
+    A = _c1_tensor(oracle, 40)
+    f = oracle.hosvd_factors(A)
+    errs = [oracle.hosvd(A, (r, r, r), f).rel_err for r in range(1, 13)]
+    assert all(b <= a * (1 + 1e-9) for a, b in zip(errs, errs[1:]))
+    pre = [e for e in errs if e > 1e-7]
+    slope = np.polyfit(np.arange(len(pre)), np.log(pre), 1)[0]
+    assert slope < -0.8          # at least a factor e^0.8 per rank
+    assert pre[-1] < 1e-5
+
+
+def test_eps_rule_meets_tolerance(oracle):
+    A = oracle.grid_eval(oracle.Kernel(oracle.MATERN, nu=2.5, ell=0.3), oracle.Grid(n=(28, 28, 28)))
+    for eps in (1e-2, 1e-4, 1e-6):
+        t = oracle.compress(oracle.Kernel(), oracle.Grid(), eps=eps, sweeps=0, A=A)
+        assert t.rel_err <= eps
+        smaller = [max(1, r - 1) for r in t.ranks]
+        if smaller != list(t.ranks):
+            worse = oracle.hosvd(A, smaller)
+            assert worse.rel_err > t.rel_err
+
+
+def test_pythagoras(oracle):
+    """Orthogonal projection: ||A||^2 = ||G||^2 + ||A - A_r||^2."""
+    A = _c1_tensor(oracle, 24)
+    for r in (1, 3, 5):
+        t = oracle.hosvd(A, (r, r, r))
+        na2 = oracle.sumsq(A)
+        assert oracle.sumsq(t.core) + t.rel_err ** 2 * na2 == pytest.approx(na2, rel=1e-13)
+
+
+# --------------------------------------------------------------------------- HOOI ----
+
+def test_hooi_improves_and_is_monotone(oracle):
+    A = oracle.grid_eval(oracle.Kernel(oracle.MATERN, nu=0.5, ell=0.2),
+                         oracle.Grid(n=(22, 18, 26)))
+    for r in (2, 4):
+        h0 = oracle.hosvd(A, (r, r + 1, r))
+        h = oracle.hooi(A, h0, sweeps=None)
+        assert h.rel_err <= h0.rel_err * (1 + 1e-12)
+        hist = np.asarray(h.history)
+        assert np.all(np.diff(hist) >= -1e-12 * hist[0])
+        na2 = oracle.sumsq(A)
+        assert oracle.sumsq(h.core) + h.rel_err ** 2 * na2 == pytest.approx(na2, rel=1e-12)
+
+
+def _table_case(oracle, n, ranks_to_check):
+    tab = json.load(open(os.path.join(GOLDEN, "table_4_2.json")))
+    b = tab["box_half_width"]
+    printed = tab["printed"][str(n)]
+    excluded = set(tab["excluded"].get(str(n), []))
+    A = oracle.grid_eval(oracle.Kernel(oracle.SLATER, alpha=1.0, p=1.0, ell=1.0),
+                         oracle.Grid(n=(n, n, n), b=(b, b, b)))
+    f = oracle.hosvd_factors(A)
+    c = (n - 1) // 2
+    for r in ranks_to_check:
+        if r in excluded:
+            continue
+        h = oracle.hooi(A, oracle.hosvd(A, (r, r, r), f), sweeps=None)
+        err = 1.0 - oracle.reconstruct(h.core, h.U)[c, c, c]
+        want = printed[r - 1]
+        assert err == pytest.approx(want, rel=tab["rel_tol"]), (n, r, err, want)
+        # the origin value is also the relative trace error of the covariance (odd grid)
+        g = oracle.Grid(n=(n, n, n), b=(b, b, b))
+        m = (n + 1) // 2
+        assert oracle.cov_trace(h, g) == pytest.approx((1.0 - err) * m ** 3, rel=1e-12)
+
+
+def test_table_4_2_n129(oracle):
+    _table_case(oracle, 129, range(1, 11))
+
+
+@pytest.mark.slow
+def test_table_4_2_n257(oracle):
+    _table_case(oracle, 257, range(1, 11))
+
+
+# ------------------------------------------------------------ covariance operator ----
+
+def _dense_cov_from_generator(Q, off, m):
+    """Dense matrix C[(i),(j)] = Q[off + |i - j|] built by plain index arithmetic."""
+    idx = np.array(np.unravel_index(np.arange(m[0] * m[1] * m[2]), m)).T
+    N = idx.shape[0]
+    C = np.empty((N, N))
+    for a in range(N):
+        d = np.abs(idx - idx[a]) + np.asarray(off)
+        C[a] = Q[d[:, 0], d[:, 1], d[:, 2]]
+    return C
+
+
+@pytest.mark.parametrize("layout,n", [(1, (6, 5, 7)), (0, (7, 5, 9))])
+def test_cov_matvec_bruteforce(oracle, layout, n):
+    k = oracle.Kernel(oracle.MATERN, nu=1.5, ell=0.5)
+    g = oracle.Grid(n=n, b=(1.0, 0.7, 1.3), layout=layout)
+    A = oracle.grid_eval(k, g)
+    t = oracle.hosvd(A, (3, 2, 4))
+    off, m = oracle.cov_offsets(g)
+    z = synth.normal_vector(m, 1).astype(np.float64)
+    y = oracle.cov_matvec(t, g, z)
+    C = _dense_cov_from_generator(oracle.reconstruct(t.core, t.U), off, m)
+    np.testing.assert_allclose(y.reshape(-1), C @ z.reshape(-1), rtol=1e-12, atol=1e-12)
+    # symmetry <y, C z> = <C y, z>
+    w = synth.normal_vector(m, 2).astype(np.float64)
+    assert np.dot(w.reshape(-1), y.reshape(-1)) == pytest.approx(
+        np.dot(oracle.cov_matvec(t, g, w).reshape(-1), z.reshape(-1)), rel=1e-12)
+
+
+def test_cov_full_rank_is_exact_covariance(oracle):
+    """At full rank the operator is the covariance matrix C_ij = c(||x_i - x_j||) (Sec. 3.6)."""
+    k = oracle.Kernel(oracle.MATERN, nu=0.5, ell=0.4, sigma2=1.3)
+    g = oracle.Grid(n=(5, 6, 4), b=(1.0, 1.0, 1.0), layout=oracle.OFFSET)
+    A = oracle.grid_eval(k, g)
+    t = oracle.hosvd(A, A.shape)
+    xs = [np.linspace(-1, 1, n) for n in g.n]
+    P = np.stack(np.meshgrid(*xs, indexing="ij"), -1).reshape(-1, 3)
+    D = np.sqrt(((P[:, None, :] - P[None, :, :]) ** 2).sum(-1))
+    C = 1.3 * np.exp(-D / 0.4)
+    z = synth.normal_vector(g.n, 3).astype(np.float64)
+    np.testing.assert_allclose(oracle.cov_matvec(t, g, z).reshape(-1), C @ z.reshape(-1),
+                               rtol=1e-12, atol=1e-12)
+    assert oracle.cov_trace(t, g) == pytest.approx(1.3 * np.prod(g.n), rel=1e-12)
+
+
+def test_cov_separable_vector_lemma(oracle):
+    """Sec. 4 eq. (4.1) / Lemma 4.1: for separable z the product is a sum of Kronecker terms
+    sum_abc G_abc (T1a z1) (x) (T2b z2) (x) (T3c z3)."""
+    k = oracle.Kernel(oracle.MATERN, nu=2.5, ell=0.6)
+    g = oracle.Grid(n=(6, 7, 5), layout=oracle.OFFSET)
+    t = oracle.hosvd(oracle.grid_eval(k, g), (3, 3, 2))
+    rng = np.random.default_rng(9)
+    zs = [rng.standard_normal(n) for n in g.n]
+    z = np.einsum("i,j,k->ijk", *zs)
+    y = oracle.cov_matvec(t, g, z)
+
+    def toep(u):
+        n = u.shape[0]
+        return u[np.abs(np.arange(n)[:, None] - np.arange(n)[None, :])]
+
+    r = t.core.shape
+    ref = np.zeros(g.n)
+    for a in range(r[0]):
+        for b in range(r[1]):
+            for c in range(r[2]):
+                f = [toep(t.U[0][:, a]) @ zs[0], toep(t.U[1][:, b]) @ zs[1],
+                     toep(t.U[2][:, c]) @ zs[2]]
+                ref += t.core[a, b, c] * np.einsum("i,j,k->ijk", *f)
+    np.testing.assert_allclose(y, ref, rtol=1e-11, atol=1e-12)
+
+
+def test_trace_formulas_agree(oracle):
+    for layout, n in ((1, (8, 6, 7)), (0, (9, 7, 11))):
+        g = oracle.Grid(n=n, layout=layout)
+        t = oracle.hosvd(oracle.grid_eval(oracle.Kernel(oracle.MATERN, nu=0.5, ell=0.3), g), (4, 3, 5))
+        assert oracle.cov_trace(t, g) == pytest.approx(oracle.cov_trace_kron(t, g), rel=1e-12)
+
+
+def test_even_centred_grid_has_no_covariance(oracle):
+    assert oracle.cov_offsets(oracle.Grid(n=(8, 8, 8))) is None
+
+
+def test_quadratic_form_is_dot(oracle):
+    g = oracle.Grid(n=(5, 6, 4), layout=oracle.OFFSET)
+    t = oracle.hosvd(oracle.grid_eval(oracle.Kernel(oracle.MATERN, nu=1.5, ell=0.5), g), (2, 2, 2))
+    z = synth.normal_vector(g.n, 4).astype(np.float64)
+    C = _dense_cov_from_generator(oracle.reconstruct(t.core, t.U), (0, 0, 0), g.n)
+    assert oracle.quadratic_form(t, g, z) == pytest.approx(z.reshape(-1) @ C @ z.reshape(-1),
+                                                           rel=1e-12)
