@@ -1,0 +1,253 @@
+/*
+ * tk.h -- C ABI of the MI355X (gfx950) Tucker engine for Matern / Slater covariance tensors.
+ *
+ * Method: Litvinenko, Keyes, Khoromskaia, Khoromskij, Matthies, "Tucker tensor analysis of
+ * Matern functions in spatial statistics" (arXiv 1711.06874).
+ *
+ *   - Task 1 of Sec. 2.1: approximate a covariance function sampled on an n1 x n2 x n3 tensor
+ *     grid by a low-rank Kronecker/Tucker format within a tolerance eps;
+ *   - the Tucker format of Sec. 3.1 eq. (3.4): A ~ G x_1 U1 x_2 U2 x_3 U3 with orthonormal
+ *     factor columns, computed by HOSVD and then Tucker-ALS (HOOI) as in Sec. 3.2;
+ *   - the covariance operator of Sec. 3.6 eq. (3.16)-(3.18), a sum of Kronecker products of
+ *     symmetric Toeplitz matrices defined by their first column, applied to a vector as in
+ *     Sec. 4 eq. (4.1), with its trace from Sec. 4 eq. (4.3) and the quadratic form z^T C z.
+ *
+ * Conventions for every entry point:
+ *   - no call aborts or throws; every call returns a tk_status (TK_OK = 0, errors < 0), and
+ *     tk_last_error() returns a message for the last failing call on the calling thread;
+ *   - tensors are dense C-order (last index fastest) arrays; matrices are row-major;
+ *   - "device" pointers are HIP device memory on the context's device (for example the
+ *     data_ptr() of a torch.cuda tensor); "host" pointers are ordinary host memory;
+ *   - hip_stream is a hipStream_t passed as void* (NULL = the default stream).  Work is
+ *     enqueued on that stream in order; calls documented as synchronising wait for it;
+ *   - caller-owned buffers stay caller-owned; objects returned through a `**out` argument
+ *     are owned by the caller and released with the matching _free / _destroy call.
+ */
+#ifndef TK_H
+#define TK_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------------------------------- */
+/* Status codes                                                                              */
+/* ---------------------------------------------------------------------------------------- */
+typedef enum {
+    TK_OK = 0,
+    TK_EINVAL = -1,        /* bad argument: NULL pointer, n < 2, ell <= 0, sigma2 <= 0,
+                              non-finite value, neither eps nor ranks given, ...            */
+    TK_EUNSUPPORTED = -2,  /* valid but not implemented: Matern nu not in {1/2, 3/2, 5/2},
+                              more than 1024 points per axis, rank above the library cap     */
+    TK_ELAYOUT = -3,       /* covariance operation on a grid without an origin node
+                              (an even-sized centred grid)                                   */
+    TK_ENOMEM = -4,        /* the estimated device memory exceeds the context's remaining
+                              HBM budget (nothing was allocated), or an allocation failed    */
+    TK_EHIP = -5,          /* a HIP runtime error (including asynchronous kernel faults seen
+                              at the next synchronising call)                                */
+    TK_ENOCONV = -6,       /* the requested eps could not be met within r_max               */
+} tk_status;
+
+/* ---------------------------------------------------------------------------------------- */
+/* Problem description                                                                       */
+/* ---------------------------------------------------------------------------------------- */
+typedef enum {
+    TK_MATERN = 0,  /* sigma2 * C_{nu,ell}(r), Sec. 2.2 eq. (2.3); nu in {0.5, 1.5, 2.5}      */
+    TK_SLATER = 1,  /* sigma2 * exp(-alpha * (r/ell)^p), the p-Slater function of Sec. 3.7
+                       eq. (3.27) with an amplitude, a rate and a length scale               */
+    TK_GAUSS = 2,   /* sigma2 * exp(-(r/ell)^2): the separable (rank-1) case of Sec. 4.4      */
+} tk_family;
+
+typedef enum {
+    TK_CENTERED = 0, /* x_i = -b + i h, i = 0..n-1, h = 2b/(n-1): the vertex grid of Sec. 3.7
+                        eq. (3.25) on [-b, b]                                                */
+    TK_OFFSET = 1,   /* x_i = i h with the same h: the generator at every difference of two
+                        centred-grid nodes, i.e. the first columns of the Toeplitz factors of
+                        the covariance of the centred grid (Sec. 3.6)                         */
+} tk_layout;
+
+typedef enum {
+    TK_FP64 = 0,     /* tensor and every contraction in IEEE double                          */
+    TK_FP32 = 1,     /* tensor in float; Gram and big contractions on FP32 MFMA with FP32
+                        accumulation; eigensolves, small Grams and error norms in FP64        */
+    TK_BF16X3 = 2,   /* as TK_FP32, but the Gram contractions split each float into a bf16
+                        high and low part and sum three bf16 MFMA products (hi*hi + hi*lo +
+                        lo*hi) with FP32 accumulation                                          */
+} tk_precision;
+
+typedef struct {
+    int family;      /* tk_family */
+    double nu;       /* Matern smoothness (TK_MATERN only) */
+    double ell;      /* length scale, > 0 */
+    double sigma2;   /* variance, > 0 */
+    double alpha;    /* Slater rate, > 0 (TK_SLATER only) */
+    double p;        /* Slater exponent, in (0, 2] (TK_SLATER only) */
+} tk_kernel;
+
+typedef struct {
+    int n[3];        /* points per axis, 2 <= n <= 1024 */
+    double b[3];     /* half-width of the box per axis, > 0 */
+    int layout;      /* tk_layout */
+} tk_grid;
+
+typedef struct {
+    double eps;      /* > 0: choose ranks so the relative Frobenius error is <= eps;
+                        0: use ranks[] */
+    int ranks[3];    /* fixed Tucker ranks (used when eps == 0); clamped to n_k */
+    int r_max;       /* eps mode: largest rank considered per mode (0 = library default 24);
+                        at most 48 */
+    int hooi_sweeps; /* Tucker-ALS sweeps after HOSVD (0 = HOSVD only); < 0 = library
+                        default (2) */
+    int prec;        /* tk_precision */
+} tk_opts;
+
+typedef struct tk_ctx tk_ctx;
+typedef struct tk_tucker tk_tucker;
+
+/* ---------------------------------------------------------------------------------------- */
+/* Context                                                                                   */
+/* ---------------------------------------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device memory that the
+ * context's calls may hold at once (0 = 90% of the free device memory).  Synchronising.
+ * Errors: TK_EINVAL (out == NULL, bad device), TK_EHIP. */
+tk_status tk_ctx_create(int device, size_t hbm_budget_bytes, tk_ctx **out);
+
+/* Wait for all work of the context, release its workspaces.  Every tk_tucker made with it
+ * must have been freed first.  NULL is ignored. */
+void tk_ctx_destroy(tk_ctx *ctx);
+
+/* Bytes of the budget currently reserved by the context's calls and resident results. */
+tk_status tk_ctx_budget(const tk_ctx *ctx, size_t *budget_bytes, size_t *in_use_bytes);
+
+/* Peak device bytes a tk_compress of this grid with these options needs (workspace plus the
+ * result).  Pure host computation.  Errors: TK_EINVAL. */
+tk_status tk_estimate_bytes(const tk_grid *grid, const tk_opts *opts, size_t *peak_bytes);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Compression (Task 1 of Sec. 2.1; HOSVD and HOOI of Sec. 3.2)                              */
+/* ---------------------------------------------------------------------------------------- */
+
+/* Sample the covariance function on the grid (Sec. 3.7 eq. (3.25)) and compress it.
+ *  - eps > 0: the FP64 path takes per-mode ranks from the HOSVD Gram eigenvalues
+ *    (smallest r with sum_{i>r} lambda_i <= eps^2 ||A||^2 / 3), then runs hooi_sweeps sweeps;
+ *    the FP32/BF16x3 paths run HOSVD and HOOI at r_max and then truncate the core by its own
+ *    HOSVD to the smallest ranks whose error bound stays <= eps.  TK_ENOCONV if r_max does
+ *    not reach eps (the result is still returned through *out, at rank r_max).
+ *  - eps == 0: fixed ranks[] (clamped to n_k).
+ * The result keeps its factors and core resident on the device.  Synchronising (one read of
+ * the ranks and the error at the end).
+ * Errors: TK_EINVAL, TK_EUNSUPPORTED, TK_ENOMEM, TK_EHIP, TK_ENOCONV. */
+tk_status tk_compress(tk_ctx *ctx, const tk_kernel *kernel, const tk_grid *grid,
+                      const tk_opts *opts, void *hip_stream, tk_tucker **out);
+
+/* Compress a caller-supplied tensor A_dev (n[0] x n[1] x n[2], C-order, float for TK_FP32 and
+ * TK_BF16X3, double for TK_FP64; not modified) instead of a sampled kernel.  The grid gives
+ * the sizes and the layout that later covariance calls use.  Synchronising. */
+tk_status tk_compress_tensor(tk_ctx *ctx, const void *A_dev, const tk_grid *grid,
+                             const tk_opts *opts, void *hip_stream, tk_tucker **out);
+
+/* Compress `count` independent problems (kernels[i] on grids[i], all with *opts) in one
+ * call: the tensors are grouped by size, every phase of a group runs as one launch over all
+ * of its members, and the group's sweep is replayed from a captured HIP graph.  outs[i]
+ * receives the i-th result; each is identical to what tk_compress returns for that problem
+ * alone.  Synchronising.  On error no result is returned (outs[] set to NULL). */
+tk_status tk_compress_batch(tk_ctx *ctx, int count, const tk_kernel *kernels,
+                            const tk_grid *grids, const tk_opts *opts, void *hip_stream,
+                            tk_tucker **outs);
+
+/* Sizes, ranks and the measured relative Frobenius error ||A - A_r|| / ||A|| (Sec. 3.7
+ * eq. (3.26)).  Any output pointer may be NULL.  Host only. */
+tk_status tk_tucker_info(const tk_tucker *t, int n[3], int ranks[3], double *rel_err_fro,
+                         double *norm_a, int *layout);
+
+/* Copy the result to host memory in FP64: U_host[k] receives n_k x r_k (row-major), core_host
+ * r1 x r2 x r3 (C-order).  Any pointer may be NULL.  Synchronising. */
+tk_status tk_tucker_get(const tk_tucker *t, double *U_host[3], double *core_host);
+
+/* Device pointers of the resident FP64 factors (n_k x r_k row-major) and core (C-order).
+ * Owned by the tk_tucker.  Host only. */
+tk_status tk_tucker_device(const tk_tucker *t, const double *U_dev[3], const double **core_dev);
+
+/* Write the reconstruction G x_1 U1 x_2 U2 x_3 U3 (n1 x n2 x n3, C-order) to A_dev as double
+ * (io = TK_FP64) or float (io = TK_FP32).  Stream-ordered. */
+tk_status tk_reconstruct(tk_ctx *ctx, const tk_tucker *t, void *A_dev, int io, void *hip_stream);
+
+/* Save / load a result as a versioned little-endian binary file (header, sizes, ranks, FP64
+ * factors and core).  Both synchronise.  Errors: TK_EINVAL (bad file), TK_ENOMEM, TK_EHIP. */
+tk_status tk_tucker_save(const tk_tucker *t, const char *path);
+tk_status tk_tucker_load(tk_ctx *ctx, const char *path, tk_tucker **out);
+
+/* Release a result and its device memory (after the work queued on it).  NULL is ignored. */
+void tk_tucker_free(tk_tucker *t);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Covariance operator in Kronecker-Toeplitz form (Sec. 3.6; Sec. 4)                          */
+/* ---------------------------------------------------------------------------------------- */
+/* The result of compressing the generator on an OFFSET grid (or an odd CENTERED grid, whose
+ * middle node is the origin) defines the covariance of m1 x m2 x m3 points:
+ *     C = sum_abc G_abc T(U1[off1:, a]) (x) T(U2[off2:, b]) (x) T(U3[off3:, c]),
+ *     T(u)_{ij} = u[|i - j|]  (symmetric Toeplitz, defined by its first column),
+ * with off_k = 0, m_k = n_k for OFFSET grids and off_k = (n_k - 1)/2, m_k = (n_k + 1)/2 for
+ * odd CENTERED grids (the non-negative sector).  Kronecker order follows C-order vectors:
+ * (M1 (x) M2 (x) M3) vec(Z) = vec(Z x_1 M1 x_2 M2 x_3 M3).  Even CENTERED -> TK_ELAYOUT. */
+
+/* Dimensions m[3] of the covariance operator of t.  Host only.  TK_ELAYOUT as above. */
+tk_status tk_cov_dims(const tk_tucker *t, int m[3]);
+
+/* y = C z (Sec. 4 eq. (4.1) for a general, non-separable z).  z_dev, y_dev: device arrays of
+ * m1*m2*m3 elements, float (io = TK_FP32) or double (io = TK_FP64), C-order; y must not
+ * overlap z.  The Toeplitz mode products run on FP32 MFMA (FP64 for io = TK_FP64).
+ * Stream-ordered, asynchronous. */
+tk_status tk_kron_matvec(tk_ctx *ctx, const tk_tucker *t, const void *z_dev, void *y_dev,
+                         int io, void *hip_stream);
+
+/* trace(C) = sum_abc G_abc prod_k trace T(U_k[off_k:, .]) = m1 m2 m3 * A_r(origin)
+ * (Sec. 4 eq. (4.3) and the value-at-origin form that follows it).  Computed on the device
+ * in FP64; synchronising (one scalar read). */
+tk_status tk_trace(tk_ctx *ctx, const tk_tucker *t, void *hip_stream, double *out);
+
+/* z^T C z (FP64 accumulation of the dot product with C z).  If y_dev is not NULL it also
+ * receives C z (same type and size as z).  Synchronising (one scalar read). */
+tk_status tk_quadratic_form(tk_ctx *ctx, const tk_tucker *t, const void *z_dev, int io,
+                            void *hip_stream, double *out, void *y_dev);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Individual steps (the same kernels tk_compress runs), exposed for testing and profiling   */
+/* ---------------------------------------------------------------------------------------- */
+
+/* a1: A_dev (n1 x n2 x n3, double for TK_FP64 else float) = sigma2 * k(||x||) on the grid.
+ * Stream-ordered.  Errors: TK_EINVAL, TK_EUNSUPPORTED. */
+tk_status tk_grid_eval(tk_ctx *ctx, const tk_kernel *kernel, const tk_grid *grid, int prec,
+                       void *A_dev, void *hip_stream);
+
+/* a2: G_dev (n_mode x n_mode, double, full symmetric) = A_(mode) A_(mode)^T for the
+ * n[0] x n[1] x n[2] tensor A_dev (double for TK_FP64, float for TK_FP32 / TK_BF16X3).
+ * Stream-ordered. */
+tk_status tk_gram(tk_ctx *ctx, const void *A_dev, const int n[3], int mode, int prec,
+                  double *G_dev, void *hip_stream);
+
+/* a3: leading r eigenpairs of `count` symmetric positive semidefinite n x n matrices
+ * (G_dev: count consecutive n*n doubles).  lambda_dev: count x r (descending);
+ * U_dev: count x n x r row-major, unit columns, each signed so that its entry of largest
+ * magnitude is positive (ties within 1e-10 relative go to the lowest index).  r <= 48.
+ * Stream-ordered. */
+tk_status tk_eig_topr(tk_ctx *ctx, int count, int n, int r, const double *G_dev,
+                      double *lambda_dev, double *U_dev, void *hip_stream);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *tk_last_error(void);
+
+/* Static name of a status code. */
+const char *tk_strerror(tk_status s);
+
+/* Library version string. */
+const char *tk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TK_H */

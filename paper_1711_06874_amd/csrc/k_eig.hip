@@ -1,0 +1,376 @@
+// a3: leading eigenpairs of the symmetric positive semidefinite Gram matrices of the HOSVD
+// and of the HOOI single-hole tensors (Sec. 3.2), in FP64.
+//
+// Method: block subspace (orthogonal) iteration with Rayleigh-Ritz.  With a working block of
+// p >= r + 8 columns, every iteration multiplies the block by G and re-orthonormalises it
+// with Householder QR; the Gram spectra of these kernel tensors fall by orders of magnitude
+// per index, so the block converges in a few iterations (warm starts from the previous HOOI
+// factor need fewer).  The projected p x p matrix Q^T G Q is diagonalised by two-sided Jacobi
+// with the parallel (round-robin) ordering, its eigenpairs are sorted in descending order,
+// U = Q V, and each column is signed so that its entry of largest magnitude is positive
+// (entries within 1e-10 relative of the maximum tie, the lowest index wins).  When p == n
+// the block is the identity and the whole matrix is diagonalised by Jacobi directly.
+//
+// Kernels: k_eig_init (start block), k_hqr (one work-group per problem, Householder QR with
+// the n x p block resident in LDS when it fits, producing the explicit Q in place),
+// k_jacobi (one work-group per problem, p x p in LDS), k_signfix; the products G Q, Q^T Y and
+// Q V use the batched small-product kernel.
+#include "tk_kernels.h"
+
+namespace tk {
+
+namespace {
+
+constexpr size_t QR_LDS_BYTES = 144 * 1024;
+
+// Counter-based uniform in [-1, 1) from (problem, row, column): a 64-bit integer mix
+// (splitmix64 finaliser).  Only used to seed the iteration; any full-rank start works.
+__device__ __forceinline__ double start_value(unsigned long long key)
+{
+    unsigned long long z = key + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    return (double)(z >> 11) * (1.0 / 4503599627370496.0) - 1.0;   // 2^52
+}
+
+__global__ void k_eig_init(EigBatch b)
+{
+    int prob = blockIdx.y;
+    long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    long tot = (long)b.n * b.p;
+    if (idx >= tot) return;
+    int i = (int)(idx / b.p), j = (int)(idx % b.p);
+    double v;
+    if (b.p == b.n) v = (i == j) ? 1.0 : 0.0;
+    else if (j < b.rw && b.warm) v = b.warm[prob * b.sW + (long)i * b.ldw + j];
+    else v = start_value(((unsigned long long)prob << 40) ^ ((unsigned long long)i << 20) ^ (unsigned long long)j);
+    b.Q[prob * (long)tot + idx] = v;
+}
+
+// Householder QR of the n x p matrix In (row-major, ld p) of problem blockIdx.x; writes the
+// explicit orthonormal factor (n x p) to Out.  W is the working copy (LDS if it fits).
+__global__ void __launch_bounds__(256) k_hqr(const double* __restrict__ In, double* __restrict__ Out,
+                                             int n, int p, int in_lds)
+{
+    extern __shared__ double smem[];
+    __shared__ double red[4];
+    __shared__ double wsum[64];
+    __shared__ double tau[64];
+    __shared__ double bcast[2];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const long off = (long)blockIdx.x * n * p;
+    double* W = in_lds ? smem : (Out + off);
+    for (long e = tid; e < (long)n * p; e += 256) W[e] = In[off + e];
+    __syncthreads();
+
+    // ---- factorisation: column j -> (tau_j, v_j below the diagonal, beta_j on it)
+    for (int j = 0; j < p; ++j) {
+        double s = 0.0;
+        for (int i = j + 1 + tid; i < n; i += 256) { double x = W[(long)i * p + j]; s += x * x; }
+        s = wave_sum(s);
+        if (lane == 0) red[wv] = s;
+        __syncthreads();
+        if (tid == 0) {
+            double xn2 = (red[0] + red[1]) + (red[2] + red[3]);
+            double alpha = W[(long)j * p + j];
+            double t = 0.0, scale = 0.0, beta = alpha;
+            if (xn2 > 0.0) {
+                double nrm = sqrt(alpha * alpha + xn2);
+                beta = (alpha >= 0.0) ? -nrm : nrm;
+                t = (beta - alpha) / beta;
+                scale = 1.0 / (alpha - beta);
+            }
+            tau[j] = t;
+            bcast[0] = scale;
+            bcast[1] = beta;
+        }
+        __syncthreads();
+        const double t = tau[j], scale = bcast[0];
+        if (t != 0.0)
+            for (int i = j + 1 + tid; i < n; i += 256) W[(long)i * p + j] *= scale;
+        __syncthreads();
+        if (tid == 0) W[(long)j * p + j] = bcast[1];
+        const int nc = p - j - 1;
+        if (t != 0.0 && nc > 0) {
+            // w_c = v^T W[j:, c] for c in (j, p), v_j = 1
+            int G = 64;
+            while (G > 1 && G * nc > 256) G >>= 1;
+            int gid = tid / G, gl = tid % G;
+            double acc = 0.0;
+            if (gid < nc) {
+                int c = j + 1 + gid;
+                for (int i = j + gl; i < n; i += G) {
+                    double v = (i == j) ? 1.0 : W[(long)i * p + j];
+                    acc += v * W[(long)i * p + c];
+                }
+            }
+            for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+            if (gid < nc && gl == 0) wsum[gid] = acc;
+            __syncthreads();
+            long cnt = (long)(n - j) * nc;
+            for (long e = tid; e < cnt; e += 256) {
+                int i = j + (int)(e / nc), c = j + 1 + (int)(e % nc);
+                double v = (i == j) ? 1.0 : W[(long)i * p + j];
+                W[(long)i * p + c] -= t * v * wsum[c - j - 1];
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- explicit Q, built in place from the last reflector to the first
+    for (int j = p - 1; j >= 0; --j) {
+        const double t = tau[j];
+        const int nc = p - j - 1;
+        if (nc > 0 && t != 0.0) {
+            int G = 64;
+            while (G > 1 && G * nc > 256) G >>= 1;
+            int gid = tid / G, gl = tid % G;
+            double acc = 0.0;
+            if (gid < nc) {
+                int c = j + 1 + gid;
+                for (int i = j + gl; i < n; i += G) {
+                    double v = (i == j) ? 1.0 : W[(long)i * p + j];
+                    acc += v * W[(long)i * p + c];
+                }
+            }
+            for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+            if (gid < nc && gl == 0) wsum[gid] = acc;
+            __syncthreads();
+            long cnt = (long)(n - j) * nc;
+            for (long e = tid; e < cnt; e += 256) {
+                int i = j + (int)(e / nc), c = j + 1 + (int)(e % nc);
+                double v = (i == j) ? 1.0 : W[(long)i * p + j];
+                W[(long)i * p + c] -= t * v * wsum[c - j - 1];
+            }
+            __syncthreads();
+        }
+        // column j of Q: -tau v below, 1 - tau on the diagonal, 0 above
+        for (int i = tid; i < n; i += 256) {
+            double x;
+            if (i < j) x = 0.0;
+            else if (i == j) x = 1.0 - t;
+            else x = -t * W[(long)i * p + j];
+            W[(long)i * p + j] = x;
+        }
+        __syncthreads();
+    }
+    if (in_lds)
+        for (long e = tid; e < (long)n * p; e += 256) Out[off + e] = W[e];
+}
+
+// Two-sided Jacobi on the p x p symmetric H of problem blockIdx.x (row-major; symmetrised),
+// parallel round-robin ordering.  Outputs the r leading eigenvalues (descending, stable) and
+// the matching eigenvector columns Vs (p x r, row-major).
+__global__ void __launch_bounds__(256) k_jacobi(const double* __restrict__ Hin, int p, int r,
+                                                double* __restrict__ Vs, double* __restrict__ lam,
+                                                long sLam, int max_sweeps, double tol)
+{
+    __shared__ double H[EIG_PMAX][EIG_PMAX + 1];
+    __shared__ double V[EIG_PMAX][EIG_PMAX + 1];
+    __shared__ double cs[EIG_PMAX / 2][2];
+    __shared__ int pq[EIG_PMAX / 2][2];
+    __shared__ double red[4];
+    __shared__ int flag;
+    __shared__ int rank_of[EIG_PMAX];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const double* Hp = Hin + (long)blockIdx.x * p * p;
+    for (int e = tid; e < p * p; e += 256) {
+        int i = e / p, j = e % p;
+        H[i][j] = 0.5 * (Hp[i * p + j] + Hp[j * p + i]);
+        V[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int m = p + (p & 1);
+    // Frobenius norm for the stopping test
+    double s = 0.0;
+    for (int e = tid; e < p * p; e += 256) { double x = H[e / p][e % p]; s += x * x; }
+    s = wave_sum(s);
+    if (lane == 0) red[wv] = s;
+    __syncthreads();
+    const double fro = sqrt((red[0] + red[1]) + (red[2] + red[3]));
+    __syncthreads();
+
+    for (int sweep = 0; sweep < max_sweeps && p > 1; ++sweep) {
+        // off-diagonal norm
+        double o = 0.0;
+        for (int e = tid; e < p * p; e += 256) { int i = e / p, j = e % p; if (i != j) o += H[i][j] * H[i][j]; }
+        o = wave_sum(o);
+        if (lane == 0) red[wv] = o;
+        __syncthreads();
+        if (tid == 0) flag = (sqrt((red[0] + red[1]) + (red[2] + red[3])) <= tol * fro) ? 1 : 0;
+        __syncthreads();
+        if (flag) break;
+        for (int step = 0; step < m - 1; ++step) {
+            if (tid < m / 2) {
+                int k = tid, a, bb;
+                if (k == 0) { a = m - 1; bb = step; }
+                else { a = (step + k) % (m - 1); bb = (step - k + (m - 1)) % (m - 1); }
+                if (a > bb) { int t = a; a = bb; bb = t; }
+                double c = 1.0, sn = 0.0;
+                if (bb < p) {
+                    double apq = H[a][bb];
+                    if (apq != 0.0) {
+                        double tau = (H[bb][bb] - H[a][a]) / (2.0 * apq);
+                        double t = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
+                                                : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        sn = t * c;
+                    }
+                }
+                pq[k][0] = a; pq[k][1] = bb; cs[k][0] = c; cs[k][1] = sn;
+            }
+            __syncthreads();
+            // rows: H <- J^T H ; V <- V J (columns of V)
+            const int np = m / 2;
+            for (int e = tid; e < np * p; e += 256) {
+                int k = e / p, j = e % p;
+                int a = pq[k][0], bb = pq[k][1];
+                double sn = cs[k][1];
+                if (bb >= p || sn == 0.0) continue;
+                double c = cs[k][0];
+                double x = H[a][j], y = H[bb][j];
+                H[a][j] = c * x - sn * y;
+                H[bb][j] = sn * x + c * y;
+                double vx = V[j][a], vy = V[j][bb];
+                V[j][a] = c * vx - sn * vy;
+                V[j][bb] = sn * vx + c * vy;
+            }
+            __syncthreads();
+            // columns: H <- H J
+            for (int e = tid; e < np * p; e += 256) {
+                int k = e / p, i = e % p;
+                int a = pq[k][0], bb = pq[k][1];
+                double sn = cs[k][1];
+                if (bb >= p || sn == 0.0) continue;
+                double c = cs[k][0];
+                double x = H[i][a], y = H[i][bb];
+                H[i][a] = c * x - sn * y;
+                H[i][bb] = sn * x + c * y;
+            }
+            __syncthreads();
+        }
+    }
+    // stable descending ranks
+    if (tid < p) {
+        double d = H[tid][tid];
+        int rk = 0;
+        for (int i = 0; i < p; ++i) {
+            double e = H[i][i];
+            if (e > d || (e == d && i < tid)) ++rk;
+        }
+        rank_of[tid] = rk;
+    }
+    __syncthreads();
+    double* Vo = Vs + (long)blockIdx.x * p * r;
+    for (int e = tid; e < p * p; e += 256) {
+        int i = e / p, j = e % p;      // V[i][j]: component i of eigenvector j
+        int rk = rank_of[j];
+        if (rk < r) Vo[i * r + rk] = V[i][j];
+    }
+    if (tid < p && rank_of[tid] < r) lam[(long)blockIdx.x * sLam + rank_of[tid]] = H[tid][tid];
+}
+
+// Sign rule on the n x r factor of problem blockIdx.y, column blockIdx.x.
+__global__ void __launch_bounds__(256) k_signfix(double* __restrict__ U, long sU, int ldu, int n)
+{
+    __shared__ double red[4];
+    __shared__ int redi[4];
+    __shared__ double amax_s;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double* u = U + blockIdx.y * sU + blockIdx.x;
+    double m = 0.0;
+    for (int i = tid; i < n; i += 256) m = fmax(m, fabs(u[(long)i * ldu]));
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (lane == 0) red[wv] = m;
+    __syncthreads();
+    if (tid == 0) amax_s = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    __syncthreads();
+    const double thr = amax_s * (1.0 - 1e-10);
+    int lead = 0x7fffffff;
+    for (int i = tid; i < n; i += 256)
+        if (fabs(u[(long)i * ldu]) >= thr && i < lead) lead = i;
+    for (int o = 32; o > 0; o >>= 1) lead = min(lead, __shfl_xor(lead, o, 64));
+    if (lane == 0) redi[wv] = lead;
+    __syncthreads();
+    int L = min(min(redi[0], redi[1]), min(redi[2], redi[3]));
+    if (L < n && u[(long)L * ldu] < 0.0)
+        for (int i = tid; i < n; i += 256) u[(long)i * ldu] = -u[(long)i * ldu];
+}
+
+__global__ void k_trace(const double* __restrict__ G, long sG, int n, double* __restrict__ out, long sOut)
+{
+    __shared__ double red[4];
+    const int tid = threadIdx.x;
+    const double* g = G + blockIdx.x * sG;
+    double s = 0.0;
+    for (int i = tid; i < n; i += 256) s += g[(long)i * n + i];
+    s = wave_sum(s);
+    if ((tid & 63) == 0) red[tid >> 6] = s;
+    __syncthreads();
+    if (tid == 0) out[blockIdx.x * sOut] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+}  // namespace
+
+static hipError_t qr_launch(const double* in, double* out, int count, int n, int p, hipStream_t s)
+{
+    size_t bytes = (size_t)n * p * sizeof(double);
+    int in_lds = bytes <= QR_LDS_BYTES ? 1 : 0;
+    hipLaunchKernelGGL(k_hqr, dim3(count), dim3(256), in_lds ? bytes : 0, s, in, out, n, p, in_lds);
+    return hipGetLastError();
+}
+
+hipError_t eig_set_attributes()
+{
+    return hipFuncSetAttribute((const void*)k_hqr, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)QR_LDS_BYTES);
+}
+
+hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s)
+{
+    hipError_t e;
+    const int n = b.n, p = b.p, r = b.r;
+    const long np_ = (long)n * p;
+    // start block
+    hipLaunchKernelGGL(k_eig_init, dim3((unsigned)((np_ + 255) / 256), b.count), dim3(256), 0, s, b);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (b.trace) {
+        hipLaunchKernelGGL(k_trace, dim3(b.count), dim3(256), 0, s, b.G, b.sG, n, b.trace, b.sTrace);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    GemmArgs gq{};   // Y = G Q
+    gq.M = n; gq.N = p; gq.K = n; gq.batch = b.count;
+    gq.A = b.G; gq.sAb = b.sG; gq.sAm = n; gq.sAk = 1;
+    gq.B = b.Q; gq.sBb = np_; gq.sBk = p; gq.sBn = 1;
+    gq.C = b.Y; gq.sCb = np_; gq.sCm = p; gq.sCn = 1;
+    gq.alpha = 1.0; gq.beta = 0.0;
+    if (p < n) {
+        if ((e = qr_launch(b.Q, b.Q, b.count, n, p, s)) != hipSuccess) return e;
+        for (int it = 0; it < iters; ++it) {
+            if ((e = launch_gemm<double, double, double>(gq, s)) != hipSuccess) return e;
+            if ((e = qr_launch(b.Y, b.Q, b.count, n, p, s)) != hipSuccess) return e;
+        }
+    }
+    if ((e = launch_gemm<double, double, double>(gq, s)) != hipSuccess) return e;
+    GemmArgs hq{};   // H = Q^T Y  (p x p)
+    hq.M = p; hq.N = p; hq.K = n; hq.batch = b.count;
+    hq.A = b.Q; hq.sAb = np_; hq.sAm = 1; hq.sAk = p;
+    hq.B = b.Y; hq.sBb = np_; hq.sBk = p; hq.sBn = 1;
+    hq.C = b.H; hq.sCb = (long)p * p; hq.sCm = p; hq.sCn = 1;
+    hq.alpha = 1.0; hq.beta = 0.0;
+    if ((e = launch_gemm<double, double, double>(hq, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_jacobi, dim3(b.count), dim3(256), 0, s, b.H, p, r, b.Vs, b.lam, b.sL, 60, 1e-15);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    GemmArgs uq{};   // U = Q Vs  (n x r)
+    uq.M = n; uq.N = r; uq.K = p; uq.batch = b.count;
+    uq.A = b.Q; uq.sAb = np_; uq.sAm = p; uq.sAk = 1;
+    uq.B = b.Vs; uq.sBb = (long)p * r; uq.sBk = r; uq.sBn = 1;
+    uq.C = b.U; uq.sCb = b.sU; uq.sCm = b.ldu; uq.sCn = 1;
+    uq.alpha = 1.0; uq.beta = 0.0;
+    if ((e = launch_gemm<double, double, double>(uq, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_signfix, dim3(r, b.count), dim3(256), 0, s, b.U, b.sU, b.ldu, n);
+    return hipGetLastError();
+}
+
+}  // namespace tk

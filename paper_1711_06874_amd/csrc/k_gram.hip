@@ -1,0 +1,339 @@
+// a2: mode-k Gram matrices G_k = A_(k) A_(k)^T of the HOSVD (Sec. 3.2).
+//
+// X = A_(k) is n_k x K with K = N / n_k.  Element X[row][Kg] of each unfolding, for the
+// C-order n0 x n1 x n2 tensor A:
+//   mode 0: A[row*n1*n2 + Kg]                          (rows contiguous, "NT")
+//   mode 1: A[(Kg/n2)*n1*n2 + row*n2 + Kg%n2]          (n2-long contiguous pieces)
+//   mode 2: A[Kg*n2 + row]                             (columns contiguous, "TN")
+// The n_k x n_k result is cut into 64 x 64 tiles; only tiles (ti <= tj) are computed.  The K
+// range is split into S equal chunks; work-group (pair, split) accumulates its chunk on MFMA
+// and writes a float (or double) 64 x 64 partial.  A second kernel adds the S partials of
+// every entry in split order in FP64 and writes both G[i][j] and G[j][i] (diagonal tiles are
+// mirrored from their upper half), so the result is deterministic and exactly symmetric.
+//
+// Precision variants:
+//   double : mfma_f64_16x16x4f64, FP64 accumulation and FP64 partials
+//   float  : mfma_f32_32x32x2f32, FP32 accumulation
+//   bf16x3 : float tiles split into bf16 (hi, lo); hi*hi + hi*lo + lo*hi on
+//            mfma_f32_32x32x16_bf16 with FP32 accumulation
+#include "tk_kernels.h"
+
+namespace tk {
+
+namespace {
+
+constexpr int BM = 64;      // output tile edge
+constexpr int NT = 256;     // threads per work-group (4 waves, 2 x 2 of 32 x 32 blocks)
+
+template <int MODE>
+struct Unfold {
+    long n1n2;
+    int n1, n2;
+    __device__ __forceinline__ long addr(int row, long Kg) const
+    {
+        if (MODE == 0) return (long)row * n1n2 + Kg;
+        if (MODE == 1) { long i0 = Kg / n2; return i0 * n1n2 + (long)row * n2 + (Kg - i0 * n2); }
+        return Kg * n2 + row;
+    }
+};
+
+// Map a tile-pair index to (ti, tj) with ti <= tj, row-major over the upper triangle.
+__device__ __forceinline__ void pair_of(int pidx, int T, int& ti, int& tj)
+{
+    int i = 0, base = 0;
+    while (base + (T - i) <= pidx) { base += T - i; ++i; }
+    ti = i;
+    tj = i + (pidx - base);
+}
+
+// ----------------------------------------------------------------------------------------
+// FP32 / FP64 tiles: LDS holds the chunk as [BK][BM + 1] (k-major), loaded with coalesced
+// global reads (along K for modes 0/1, along rows for mode 2).
+// ----------------------------------------------------------------------------------------
+template <int MODE, typename T, int BK>
+__global__ void __launch_bounds__(NT) k_gram_tiles(const T* __restrict__ A, Unfold<MODE> u, int nrow,
+                                                   long K, long kchunk, int T_tiles, int nsplit,
+                                                   T* __restrict__ partials)
+{
+    __shared__ T As[BK][BM + 1];
+    __shared__ T Bs[BK][BM + 1];
+    const int tid = threadIdx.x;
+    const int split = blockIdx.x % nsplit;
+    const int pidx = blockIdx.x / nsplit;
+    int ti, tj;
+    pair_of(pidx, T_tiles, ti, tj);
+    const bool diag = (ti == tj);
+    const int r0a = ti * BM, r0b = tj * BM;
+    const long kbeg = (long)split * kchunk;
+    const long kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
+
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+
+    // per-thread load coordinates
+    constexpr int PER = BM * BK / NT;   // elements per thread per tile
+    int lk, lm, mstep, kstep;
+    if (MODE == 2) { lm = tid % BM; lk = tid / BM; mstep = 0; kstep = NT / BM; }
+    else           { lk = tid % BK; lm = tid / BK; mstep = NT / BK; kstep = 0; }
+
+    typedef typename std::conditional<sizeof(T) == 8, f64x4, f32x16>::type acc_t;
+    acc_t acc[sizeof(T) == 8 ? 4 : 1];
+#pragma unroll
+    for (int q = 0; q < (sizeof(T) == 8 ? 4 : 1); ++q)
+        for (int v = 0; v < (sizeof(T) == 8 ? 4 : 16); ++v) acc[q][v] = 0;
+
+    T ra[PER], rb[PER];
+    auto gload = [&](long k0) {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            int m = lm + e * mstep, kk = lk + e * kstep;
+            long Kg = k0 + kk;
+            bool kin = Kg < kend;
+            int rowa = r0a + m, rowb = r0b + m;
+            ra[e] = (kin && rowa < nrow) ? A[u.addr(rowa, Kg)] : (T)0;
+            if (!diag) rb[e] = (kin && rowb < nrow) ? A[u.addr(rowb, Kg)] : (T)0;
+        }
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            int m = lm + e * mstep, kk = lk + e * kstep;
+            As[kk][m] = ra[e];
+            if (!diag) Bs[kk][m] = rb[e];
+        }
+    };
+
+    gload(kbeg);
+    for (long k0 = kbeg; k0 < kend; k0 += BK) {
+        __syncthreads();
+        sstore();
+        __syncthreads();
+        if (k0 + BK < kend) gload(k0 + BK);     // prefetch the next chunk into registers
+        T (*Bp)[BM + 1] = diag ? As : Bs;
+        if constexpr (sizeof(T) == 8) {
+            // 2 x 2 blocks of 16 x 16 per wave, k-steps of 4
+#pragma unroll
+            for (int ks = 0; ks < BK; ks += 4) {
+                int kr = ks + (lane >> 4);
+                double a0 = As[kr][wm + (lane & 15)], a1 = As[kr][wm + 16 + (lane & 15)];
+                double b0 = Bp[kr][wn + (lane & 15)], b1 = Bp[kr][wn + 16 + (lane & 15)];
+                acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[1], 0, 0, 0);
+                acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[2], 0, 0, 0);
+                acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[3], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < BK; ks += 2) {
+                int kr = ks + (lane >> 5);
+                float a = As[kr][wm + (lane & 31)];
+                float b = Bp[kr][wn + (lane & 31)];
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[0], 0, 0, 0);
+            }
+        }
+    }
+
+    // write the 64 x 64 partial (row-major) of this (pair, split)
+    T* P = partials + ((long)pidx * nsplit + split) * (BM * BM);
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int i = wm + 16 * bi + 4 * v + (lane >> 4);
+                    int j = wn + 16 * bj + (lane & 15);
+                    P[i * BM + j] = acc[bi * 2 + bj][v];
+                }
+    } else {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            int i = wm + (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
+            int j = wn + (lane & 31);
+            P[i * BM + j] = acc[0][v];
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------------------
+// BF16x3 tiles.  LDS holds [BM][BK + 8] bf16 hi and lo parts (row-major, so that each lane
+// reads its 8 consecutive k values with one 16-byte load).
+// ----------------------------------------------------------------------------------------
+template <int MODE, int BK>
+__global__ void __launch_bounds__(NT) k_gram_tiles_bf16x3(const float* __restrict__ A, Unfold<MODE> u,
+                                                          int nrow, long K, long kchunk, int T_tiles,
+                                                          int nsplit, float* __restrict__ partials)
+{
+    constexpr int LD = BK + 8;
+    __shared__ __attribute__((aligned(16))) __bf16 Ah[BM][LD], Al[BM][LD], Bh[BM][LD], Bl[BM][LD];
+    const int tid = threadIdx.x;
+    const int split = blockIdx.x % nsplit;
+    const int pidx = blockIdx.x / nsplit;
+    int ti, tj;
+    pair_of(pidx, T_tiles, ti, tj);
+    const bool diag = (ti == tj);
+    const int r0a = ti * BM, r0b = tj * BM;
+    const long kbeg = (long)split * kchunk;
+    const long kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+
+    constexpr int PER = BM * BK / NT;
+    int lk, lm, mstep, kstep;
+    if (MODE == 2) { lm = tid % BM; lk = tid / BM; mstep = 0; kstep = NT / BM; }
+    else           { lk = tid % BK; lm = tid / BK; mstep = NT / BK; kstep = 0; }
+
+    f32x16 acc;
+    for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+    float ra[PER], rb[PER];
+    auto gload = [&](long k0) {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            int m = lm + e * mstep, kk = lk + e * kstep;
+            long Kg = k0 + kk;
+            bool kin = Kg < kend;
+            int rowa = r0a + m, rowb = r0b + m;
+            ra[e] = (kin && rowa < nrow) ? A[u.addr(rowa, Kg)] : 0.f;
+            if (!diag) rb[e] = (kin && rowb < nrow) ? A[u.addr(rowb, Kg)] : 0.f;
+        }
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            int m = lm + e * mstep, kk = lk + e * kstep;
+            __bf16 h, l;
+            split_bf16(ra[e], h, l);
+            Ah[m][kk] = h; Al[m][kk] = l;
+            if (!diag) { split_bf16(rb[e], h, l); Bh[m][kk] = h; Bl[m][kk] = l; }
+        }
+    };
+
+    gload(kbeg);
+    for (long k0 = kbeg; k0 < kend; k0 += BK) {
+        __syncthreads();
+        sstore();
+        __syncthreads();
+        if (k0 + BK < kend) gload(k0 + BK);
+        __bf16 (*BhP)[LD] = diag ? Ah : Bh;
+        __bf16 (*BlP)[LD] = diag ? Al : Bl;
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 16) {
+            int kc = ks + 8 * (lane >> 5);
+            int ra_ = wm + (lane & 31), rb_ = wn + (lane & 31);
+            bf16x8 ah = *reinterpret_cast<const bf16x8*>(&Ah[ra_][kc]);
+            bf16x8 al = *reinterpret_cast<const bf16x8*>(&Al[ra_][kc]);
+            bf16x8 bh = *reinterpret_cast<const bf16x8*>(&BhP[rb_][kc]);
+            bf16x8 bl = *reinterpret_cast<const bf16x8*>(&BlP[rb_][kc]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+        }
+    }
+    float* P = partials + ((long)pidx * nsplit + split) * (BM * BM);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        int i = wm + (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
+        int j = wn + (lane & 31);
+        P[i * BM + j] = acc[v];
+    }
+}
+
+// G[ti*64 + ii][tj*64 + jj] = sum_s P[pair][s][ii][jj] (FP64, split order); mirrored.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gram_reduce(const T* __restrict__ partials, int T_tiles,
+                                                     int nsplit, int nrow, double* __restrict__ G)
+{
+    int pidx = blockIdx.y;
+    int ti, tj;
+    pair_of(pidx, T_tiles, ti, tj);
+    int e = blockIdx.x * blockDim.x + threadIdx.x;   // entry within the tile
+    if (e >= BM * BM) return;
+    int ii = e / BM, jj = e % BM;
+    if (ti == tj && ii > jj) return;                  // diagonal tiles: upper half only
+    int gi = ti * BM + ii, gj = tj * BM + jj;
+    if (gi >= nrow || gj >= nrow) return;
+    const T* P = partials + (long)pidx * nsplit * (BM * BM) + e;
+    double s = 0.0;
+    for (int q = 0; q < nsplit; ++q) s += (double)P[(long)q * (BM * BM)];
+    G[(long)gi * nrow + gj] = s;
+    G[(long)gj * nrow + gi] = s;
+}
+
+struct GramPlan {
+    int nrow, T_tiles, npairs, nsplit;
+    long K, kchunk;
+};
+
+GramPlan make_plan(const int n[3], int mode, int BK)
+{
+    GramPlan p;
+    long N = (long)n[0] * n[1] * n[2];
+    p.nrow = n[mode];
+    p.K = N / n[mode];
+    p.T_tiles = (p.nrow + BM - 1) / BM;
+    p.npairs = p.T_tiles * (p.T_tiles + 1) / 2;
+    long want = (2048 + p.npairs - 1) / p.npairs;               // ~2048 work-groups
+    long maxsplit = (p.K + BK - 1) / BK;
+    long s = want < maxsplit ? want : maxsplit;
+    if (s < 1) s = 1;
+    long kc = (p.K + s - 1) / s;
+    kc = (kc + BK - 1) / BK * BK;
+    p.kchunk = kc;
+    p.nsplit = (int)((p.K + kc - 1) / kc);
+    return p;
+}
+
+constexpr int BK_F32 = 32, BK_F64 = 16, BK_BF = 32;
+
+int bk_for(int prec) { return prec == 0 ? BK_F64 : (prec == 1 ? BK_F32 : BK_BF); }
+
+}  // namespace
+
+size_t gram_work_bytes(const int n[3], int mode, int prec)
+{
+    GramPlan p = make_plan(n, mode, bk_for(prec));
+    size_t elt = (prec == 0) ? 8 : 4;
+    return (size_t)p.npairs * p.nsplit * BM * BM * elt;
+}
+
+template <int MODE>
+static hipError_t launch_mode(const void* A, const int n[3], int prec, double* G, void* work, hipStream_t s)
+{
+    GramPlan p = make_plan(n, MODE, bk_for(prec));
+    Unfold<MODE> u;
+    u.n1n2 = (long)n[1] * n[2];
+    u.n1 = n[1];
+    u.n2 = n[2];
+    dim3 grid((unsigned)(p.npairs * p.nsplit));
+    if (prec == 0) {
+        hipLaunchKernelGGL((k_gram_tiles<MODE, double, BK_F64>), grid, dim3(NT), 0, s, (const double*)A, u,
+                           p.nrow, p.K, p.kchunk, p.T_tiles, p.nsplit, (double*)work);
+    } else if (prec == 1) {
+        hipLaunchKernelGGL((k_gram_tiles<MODE, float, BK_F32>), grid, dim3(NT), 0, s, (const float*)A, u,
+                           p.nrow, p.K, p.kchunk, p.T_tiles, p.nsplit, (float*)work);
+    } else {
+        hipLaunchKernelGGL((k_gram_tiles_bf16x3<MODE, BK_BF>), grid, dim3(NT), 0, s, (const float*)A, u,
+                           p.nrow, p.K, p.kchunk, p.T_tiles, p.nsplit, (float*)work);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dim3 rgrid((BM * BM + 255) / 256, p.npairs);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_gram_reduce<double>, rgrid, dim3(256), 0, s, (const double*)work, p.T_tiles,
+                           p.nsplit, p.nrow, G);
+    else
+        hipLaunchKernelGGL(k_gram_reduce<float>, rgrid, dim3(256), 0, s, (const float*)work, p.T_tiles,
+                           p.nsplit, p.nrow, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram(const void* A, const int n[3], int mode, int prec, double* G, void* work,
+                       hipStream_t s)
+{
+    if (mode == 0) return launch_mode<0>(A, n, prec, G, work, s);
+    if (mode == 1) return launch_mode<1>(A, n, prec, G, work, s);
+    return launch_mode<2>(A, n, prec, G, work, s);
+}
+
+}  // namespace tk

@@ -1,0 +1,68 @@
+// a1: collocation tensor of a radial covariance function (Sec. 3.7 eq. (3.25)).
+//
+// A[i0,i1,i2] = sigma2 * k(||(x_i0, y_i1, z_i2)||), C-order.  Node coordinates and the radius
+// are formed in double (x = x0 + i h, r = sqrt((x^2 + y^2) + z^2)) and the kernel is
+// evaluated in double, then rounded once to the storage type.  Each thread writes 4
+// consecutive elements of one i2-row (one 16-byte store for float rows whose length is a
+// multiple of 4); the grid is a flat 1-D launch over rows x ceil(n2/4) quads, so stores
+// from a wave cover contiguous 1 KiB (float) / 2 KiB (double) spans.
+#include "tk_kernels.h"
+
+namespace tk {
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_grid_eval(T* __restrict__ A, GridAxes g, KernelParams kp,
+                                                   long total_quads, int quads_per_row)
+{
+    long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total_quads) return;
+    long row = q / quads_per_row;
+    int i2 = (int)(q - row * quads_per_row) * 4;
+    int i1 = (int)(row % g.n[1]);
+    int i0 = (int)(row / g.n[1]);
+    double x = g.x0[0] + (double)i0 * g.h[0];
+    double y = g.x0[1] + (double)i1 * g.h[1];
+    double xy = x * x + y * y;
+    T out[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        double z = g.x0[2] + (double)(i2 + t) * g.h[2];
+        double r = sqrt(xy + z * z);
+        out[t] = (T)cov_value(kp, r);
+    }
+    T* dst = A + row * g.n[2] + i2;
+    if (i2 + 4 <= g.n[2]) {
+        if (sizeof(T) == 4 && (g.n[2] & 3) == 0) {
+            *reinterpret_cast<float4*>(dst) = make_float4((float)out[0], (float)out[1], (float)out[2],
+                                                          (float)out[3]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) dst[t] = out[t];
+        }
+    } else {
+        for (int t = 0; t < 4 && i2 + t < g.n[2]; ++t) dst[t] = out[t];
+    }
+}
+
+template <typename T>
+static hipError_t launch(T* A, const GridAxes& g, const KernelParams& kp, hipStream_t s)
+{
+    int qpr = (g.n[2] + 3) / 4;
+    long rows = (long)g.n[0] * g.n[1];
+    long total = rows * qpr;
+    long blocks = (total + 255) / 256;
+    hipLaunchKernelGGL(k_grid_eval<T>, dim3((unsigned)blocks), dim3(256), 0, s, A, g, kp, total, qpr);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_eval_f32(float* A, const GridAxes& g, const KernelParams& kp, hipStream_t s)
+{
+    return launch(A, g, kp, s);
+}
+
+hipError_t launch_grid_eval_f64(double* A, const GridAxes& g, const KernelParams& kp, hipStream_t s)
+{
+    return launch(A, g, kp, s);
+}
+
+}  // namespace tk

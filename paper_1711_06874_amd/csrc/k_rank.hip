@@ -1,0 +1,160 @@
+// Small single-work-group kernels around the compression: the eps rank rule, the error of a
+// core truncation, compaction of truncated factors / cores, and the covariance trace.
+#include "tk_kernels.h"
+
+namespace tk {
+
+// Rank rule for problem blockIdx.x: lam holds the `len` leading eigenvalues (descending) of a
+// matrix whose eigenvalues sum to total[blockIdx.x * sTotal] (or to the sum of lam when
+// total == nullptr).  rank = smallest r >= 1 with total - sum_{i<r} lam_i <= budget, capped at
+// `len`; budget = (eps2 * a2 - d2) / 3 with a2 = scal[0], d2 = scal[1] (d2 optional).
+// ok[blockIdx.x] = 1 if the rule was met within len, else 0.
+__global__ void k_rank_rule(const double* __restrict__ lam, long sLam, int len, const double* __restrict__ total,
+                            long sTotal, const double* __restrict__ scal, int has_d2, double eps2,
+                            int* __restrict__ ranks, int* __restrict__ ok)
+{
+    if (threadIdx.x != 0) return;
+    const double* l = lam + blockIdx.x * sLam;
+    double tot;
+    if (total) tot = total[blockIdx.x * sTotal];
+    else { tot = 0.0; for (int i = len - 1; i >= 0; --i) tot += fmax(l[i], 0.0); }
+    double budget = (eps2 * scal[0] - (has_d2 ? scal[1] : 0.0)) / 3.0;
+    int r = len, met = 0;
+    double head = 0.0;
+    for (int c = 1; c <= len; ++c) {
+        head += fmax(l[c - 1], 0.0);
+        if (tot - head <= budget) { r = c; met = 1; break; }
+    }
+    ranks[blockIdx.x] = r;
+    ok[blockIdx.x] = met;
+}
+
+// out[0] = sum of X[a][b][c]^2 over entries outside [0,r0) x [0,r1) x [0,r2) (R0 x R1 x R2),
+// ranks read from device memory.
+__global__ void __launch_bounds__(256) k_trunc_err(const double* __restrict__ X, int R0, int R1, int R2,
+                                                   const int* __restrict__ ranks, double* __restrict__ out)
+{
+    __shared__ double red[4];
+    const int r0 = ranks[0], r1 = ranks[1], r2 = ranks[2];
+    double s = 0.0;
+    for (int e = threadIdx.x; e < R0 * R1 * R2; e += 256) {
+        int a = e / (R1 * R2), b = (e / R2) % R1, c = e % R2;
+        if (a >= r0 || b >= r1 || c >= r2) s += X[e] * X[e];
+    }
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Copy the leading d0 x d1 x d2 block of a D0 x D1 x D2 array (C-order) to a dense array.
+template <typename TI, typename TO>
+__global__ void k_copy_block(const TI* __restrict__ X, int D1, int D2, TO* __restrict__ Y, int d0, int d1, int d2)
+{
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    long tot = (long)d0 * d1 * d2;
+    if (e >= tot) return;
+    int a = (int)(e / ((long)d1 * d2)), b = (int)((e / d2) % d1), c = (int)(e % d2);
+    Y[e] = (TO)X[((long)a * D1 + b) * D2 + c];
+}
+
+template <typename TI, typename TO>
+hipError_t launch_copy_block(const TI* X, int D1, int D2, TO* Y, int d0, int d1, int d2, hipStream_t s)
+{
+    long tot = (long)d0 * d1 * d2;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_copy_block<TI, TO>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, X, D1, D2, Y,
+                       d0, d1, d2);
+    return hipGetLastError();
+}
+template hipError_t launch_copy_block<double, double>(const double*, int, int, double*, int, int, int, hipStream_t);
+template hipError_t launch_copy_block<double, float>(const double*, int, int, float*, int, int, int, hipStream_t);
+
+hipError_t launch_rank_rule(const double* lam, long sLam, int len, int count, const double* total, long sTotal,
+                            const double* scal, int has_d2, double eps2, int* ranks, int* ok, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rank_rule, dim3(count), dim3(64), 0, s, lam, sLam, len, total, sTotal, scal, has_d2, eps2,
+                       ranks, ok);
+    return hipGetLastError();
+}
+
+hipError_t launch_trunc_err(const double* X, int R0, int R1, int R2, const int* ranks, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_trunc_err, dim3(1), dim3(256), 0, s, X, R0, R1, R2, ranks, out);
+    return hipGetLastError();
+}
+
+// trace of the Kronecker-Toeplitz covariance:
+//   out = m0 m1 m2 * sum_abc G[a][b][c] U1[off0][a] U2[off1][b] U3[off2][c]
+__global__ void __launch_bounds__(256) k_cov_trace(const double* __restrict__ G, int r0, int r1, int r2,
+                                                   const double* __restrict__ u0, const double* __restrict__ u1,
+                                                   const double* __restrict__ u2, double scale,
+                                                   double* __restrict__ out)
+{
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int e = threadIdx.x; e < r0 * r1 * r2; e += 256) {
+        int a = e / (r1 * r2), b = (e / r2) % r1, c = e % r2;
+        s += G[e] * u0[a] * u1[b] * u2[c];
+    }
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = scale * ((red[0] + red[1]) + (red[2] + red[3]));
+}
+
+hipError_t launch_cov_trace(const double* G, int r0, int r1, int r2, const double* u0, const double* u1,
+                            const double* u2, double scale, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cov_trace, dim3(1), dim3(256), 0, s, G, r0, r1, r2, u0, u1, u2, scale, out);
+    return hipGetLastError();
+}
+
+// E^2 = (d2 + t2) / a2 from scal = {a2, d2, t2, ...}; out = sqrt.
+__global__ void k_final_err(double* scal)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double a2 = scal[0];
+        scal[3] = a2 > 0.0 ? sqrt(fmax(scal[1] + scal[2], 0.0) / a2) : 0.0;
+    }
+}
+
+hipError_t launch_final_err(double* scal, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_final_err, dim3(1), dim3(64), 0, s, scal);
+    return hipGetLastError();
+}
+
+// Zero the columns c >= rank of an n x R factor and the core entries outside the leading
+// r0 x r1 x r2 block (ranks from device memory), so that rank-R kernels evaluate the rank-r
+// result exactly.
+__global__ void k_mask_factor(double* __restrict__ U, long n, int R, const int* __restrict__ rank)
+{
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * R) return;
+    if ((int)(e % R) >= rank[0]) U[e] = 0.0;
+}
+__global__ void k_mask_core(double* __restrict__ X, int R0, int R1, int R2, const int* __restrict__ ranks)
+{
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= R0 * R1 * R2) return;
+    int a = e / (R1 * R2), b = (e / R2) % R1, c = e % R2;
+    if (a >= ranks[0] || b >= ranks[1] || c >= ranks[2]) X[e] = 0.0;
+}
+
+hipError_t launch_mask_rank(double* const U[3], const int n[3], const int R[3], double* core, const int* ranks,
+                            hipStream_t s)
+{
+    for (int k = 0; k < 3; ++k) {
+        long tot = (long)n[k] * R[k];
+        hipLaunchKernelGGL(k_mask_factor, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, U[k], (long)n[k], R[k],
+                           ranks + k);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    int tot = R[0] * R[1] * R[2];
+    hipLaunchKernelGGL(k_mask_core, dim3((tot + 255) / 256), dim3(256), 0, s, core, R[0], R[1], R[2], ranks);
+    return hipGetLastError();
+}
+
+}  // namespace tk

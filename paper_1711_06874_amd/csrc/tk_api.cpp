@@ -1,0 +1,1267 @@
+// Host driver and C ABI of the Tucker engine (declared in include/tk.h).
+//
+// A compression enqueues, on the caller's stream:
+//   grid evaluation -> three mode Grams -> leading eigenvectors (HOSVD, Sec. 3.2)
+//   -> HOOI sweeps (Sec. 3.2: single-hole tensors with the latest factors, Gauss-Seidel over
+//      modes 1, 2, 3) -> core from the last single-hole tensor -> reconstruction error
+//      (Sec. 3.7 eq. (3.26)) -> eps truncation,
+// and synchronises once at the end to read the ranks and the error.  All arithmetic runs in
+// the HIP kernels of this library; the host only plans shapes, allocates and launches.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tk.h"
+#include "tk_kernels.h"
+
+using namespace tk;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+tk_status fail(tk_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define TK_HIP(x)                                                                                  \
+    do {                                                                                           \
+        hipError_t _e = (x);                                                                       \
+        if (_e != hipSuccess) return fail(TK_EHIP, "%s failed: %s", #x, hipGetErrorString(_e));    \
+    } while (0)
+
+constexpr int LIB_RMAX = 48;          // largest rank the kernels support
+constexpr int DEFAULT_RMAX = 24;      // eps mode working rank when r_max == 0
+constexpr int DEFAULT_SWEEPS = 2;
+constexpr int COLD_ITERS = 3;         // subspace iterations from a random start
+constexpr int WARM_ITERS = 2;         // ... from the previous factor
+constexpr int NMAX = 1024;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Two-pass arena: pass 1 (base == nullptr) sums sizes, pass 2 hands out aligned pointers.
+struct Arena {
+    char* base = nullptr;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count)
+    {
+        size_t o = align_up(off, 256);
+        off = o + align_up(count * sizeof(T), 256);
+        return base ? reinterpret_cast<T*>(base + o) : nullptr;
+    }
+};
+
+}  // namespace
+
+struct tk_ctx {
+    int device = 0;
+    size_t budget = 0;
+    std::atomic<size_t> in_use{0};
+    std::atomic<int> live_results{0};
+};
+
+struct tk_tucker {
+    tk_ctx* ctx = nullptr;
+    int n[3] = {0, 0, 0}, r[3] = {0, 0, 0};
+    double b[3] = {1, 1, 1};
+    int layout = TK_CENTERED;
+    int prec = TK_FP32;
+    double rel_err = 0.0, norm_a = 0.0;
+    void* block = nullptr;        // one device allocation for everything below
+    double* U[3] = {nullptr, nullptr, nullptr};
+    double* core = nullptr;
+    float* U32[3] = {nullptr, nullptr, nullptr};
+    float* core32 = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+};
+
+namespace {
+
+bool reserve(tk_ctx* c, size_t bytes)
+{
+    size_t cur = c->in_use.load();
+    while (true) {
+        if (cur + bytes > c->budget) return false;
+        if (c->in_use.compare_exchange_weak(cur, cur + bytes)) return true;
+    }
+}
+void release(tk_ctx* c, size_t bytes) { c->in_use.fetch_sub(bytes); }
+
+struct Reservation {
+    tk_ctx* c;
+    size_t bytes;
+    bool held;
+    Reservation(tk_ctx* c_, size_t b) : c(c_), bytes(b), held(false) {}
+    bool take() { held = reserve(c, bytes); return held; }
+    ~Reservation() { if (held) release(c, bytes); }
+};
+
+bool finite(double x) { return std::isfinite(x); }
+
+tk_status check_kernel(const tk_kernel* k, KernelParams* kp)
+{
+    if (!k) return fail(TK_EINVAL, "kernel is NULL");
+    if (!finite(k->ell) || k->ell <= 0) return fail(TK_EINVAL, "ell must be finite and > 0");
+    if (!finite(k->sigma2) || k->sigma2 <= 0) return fail(TK_EINVAL, "sigma2 must be finite and > 0");
+    kp->family = k->family;
+    kp->sigma2 = k->sigma2;
+    kp->alpha = k->alpha;
+    kp->p = k->p;
+    kp->half = 0;
+    if (k->family == TK_MATERN) {
+        if (!finite(k->nu)) return fail(TK_EINVAL, "nu must be finite");
+        int half = -1;
+        for (int h = 0; h < 3; ++h)
+            if (std::fabs(k->nu - (h + 0.5)) < 1e-12) half = h;
+        if (half < 0) return fail(TK_EUNSUPPORTED, "Matern nu=%g: only 0.5, 1.5, 2.5 are supported", k->nu);
+        kp->half = half;
+        kp->inv_len = std::sqrt(2.0 * (half + 0.5)) / k->ell;
+    } else if (k->family == TK_SLATER) {
+        if (!finite(k->alpha) || k->alpha <= 0) return fail(TK_EINVAL, "Slater alpha must be > 0");
+        if (!finite(k->p) || k->p <= 0 || k->p > 2) return fail(TK_EINVAL, "Slater p must be in (0, 2]");
+        kp->inv_len = 1.0 / k->ell;
+    } else if (k->family == TK_GAUSS) {
+        kp->inv_len = 1.0 / k->ell;
+    } else {
+        return fail(TK_EINVAL, "unknown kernel family %d", k->family);
+    }
+    return TK_OK;
+}
+
+tk_status check_grid(const tk_grid* g)
+{
+    if (!g) return fail(TK_EINVAL, "grid is NULL");
+    for (int k = 0; k < 3; ++k) {
+        if (g->n[k] < 2) return fail(TK_EINVAL, "grid n[%d]=%d must be >= 2", k, g->n[k]);
+        if (g->n[k] > NMAX) return fail(TK_EUNSUPPORTED, "grid n[%d]=%d exceeds %d", k, g->n[k], NMAX);
+        if (!finite(g->b[k]) || g->b[k] <= 0) return fail(TK_EINVAL, "grid b[%d] must be finite and > 0", k);
+    }
+    if (g->layout != TK_CENTERED && g->layout != TK_OFFSET) return fail(TK_EINVAL, "unknown layout %d", g->layout);
+    return TK_OK;
+}
+
+GridAxes axes_of(const tk_grid* g)
+{
+    GridAxes a;
+    for (int k = 0; k < 3; ++k) {
+        a.n[k] = g->n[k];
+        a.h[k] = 2.0 * g->b[k] / (double)(g->n[k] - 1);
+        a.x0[k] = (g->layout == TK_CENTERED) ? -g->b[k] : 0.0;
+    }
+    return a;
+}
+
+struct Plan {
+    int n[3];
+    int R[3];          // working ranks (HOSVD/HOOI)
+    int p[3];          // eigensolver block per mode
+    int prec;
+    bool eps_mode;
+    double eps;
+    int sweeps;
+    bool cubic;
+};
+
+tk_status make_plan(const tk_grid* g, const tk_opts* o, Plan* P)
+{
+    if (!o) return fail(TK_EINVAL, "opts is NULL");
+    if (o->prec < TK_FP64 || o->prec > TK_BF16X3) return fail(TK_EINVAL, "unknown precision %d", o->prec);
+    if (!finite(o->eps) || o->eps < 0) return fail(TK_EINVAL, "eps must be finite and >= 0");
+    P->prec = o->prec;
+    P->eps_mode = o->eps > 0;
+    P->eps = o->eps;
+    P->sweeps = o->hooi_sweeps < 0 ? DEFAULT_SWEEPS : o->hooi_sweeps;
+    if (P->sweeps > 100) return fail(TK_EINVAL, "hooi_sweeps=%d too large", o->hooi_sweeps);
+    int rmax = o->r_max > 0 ? o->r_max : DEFAULT_RMAX;
+    if (rmax > LIB_RMAX) return fail(TK_EUNSUPPORTED, "r_max=%d exceeds %d", rmax, LIB_RMAX);
+    for (int k = 0; k < 3; ++k) {
+        P->n[k] = g->n[k];
+        int want;
+        if (P->eps_mode) want = rmax;
+        else {
+            if (o->ranks[k] < 1) return fail(TK_EINVAL, "ranks[%d]=%d: give eps > 0 or ranks >= 1", k, o->ranks[k]);
+            want = o->ranks[k];
+            if (want > LIB_RMAX && want < g->n[k])
+                return fail(TK_EUNSUPPORTED, "rank %d exceeds %d", want, LIB_RMAX);
+        }
+        P->R[k] = want < g->n[k] ? want : g->n[k];
+        if (P->R[k] > EIG_PMAX) return fail(TK_EUNSUPPORTED, "rank %d exceeds %d", P->R[k], EIG_PMAX);
+        P->p[k] = (g->n[k] <= EIG_PMAX) ? g->n[k] : ((P->R[k] + 8 < EIG_PMAX) ? P->R[k] + 8 : EIG_PMAX);
+    }
+    P->cubic = (g->n[0] == g->n[1] && g->n[1] == g->n[2]);
+    return TK_OK;
+}
+
+// Device workspace of one compression.
+struct Work {
+    void* A;                 // N reals (nullptr if the caller supplies A)
+    void* gram_work;
+    double* G;               // 3 * nmax^2
+    double *Q, *Y, *H, *Vs;  // eigensolver, 3 problems
+    double* U[3];            // n_k x R_k
+    float* U32[3];
+    double* lam;             // 3 * 64
+    double* trace;           // 3
+    void* T;                 // n0 n1 R2 reals
+    void* S;                 // R0 n1 n2 reals
+    double* B;               // single-hole unfoldings
+    double* core;            // R0 R1 R2
+    double* M1;              // n0 R1 R2
+    double* Hrec;            // n0 n1 R2 doubles
+    double* Ahat;            // FP64 path: N doubles
+    double* partials;        // 2 * nparts
+    double* scal;            // a2, d2, t2, E, ...
+    int* ranks;              // 3 ranks + 3 ok flags
+    // eps truncation (float paths)
+    double *Gc, *Vc, *lamc, *tQ, *tY, *tH, *tVs, *coreA, *coreB, *Urot[3];
+    int nparts;
+};
+
+void layout_work(Arena& ar, const Plan& P, bool own_A, Work& w)
+{
+    const int* n = P.n;
+    const int* R = P.R;
+    const size_t N = (size_t)n[0] * n[1] * n[2];
+    const size_t esz = (P.prec == TK_FP64) ? 8 : 4;
+    int nmax = std::max(n[0], std::max(n[1], n[2]));
+    int pmax = std::max(P.p[0], std::max(P.p[1], P.p[2]));
+    int Rmax = std::max(R[0], std::max(R[1], R[2]));
+    w.A = own_A ? (void*)ar.take<char>(N * esz) : nullptr;
+    size_t gw = 0;
+    for (int k = 0; k < 3; ++k) gw = std::max(gw, gram_work_bytes(n, k, P.prec));
+    w.gram_work = ar.take<char>(gw);
+    w.G = ar.take<double>(3 * (size_t)nmax * nmax);
+    w.Q = ar.take<double>(3 * (size_t)nmax * pmax);
+    w.Y = ar.take<double>(3 * (size_t)nmax * pmax);
+    w.H = ar.take<double>(3 * (size_t)pmax * pmax);
+    w.Vs = ar.take<double>(3 * (size_t)pmax * pmax);
+    for (int k = 0; k < 3; ++k) {
+        w.U[k] = ar.take<double>((size_t)n[k] * R[k]);
+        w.U32[k] = ar.take<float>((size_t)n[k] * R[k]);
+    }
+    w.lam = ar.take<double>(3 * 64);
+    w.trace = ar.take<double>(3);
+    w.T = ar.take<char>((size_t)n[0] * n[1] * R[2] * esz);
+    w.S = ar.take<char>((size_t)R[0] * n[1] * n[2] * esz);
+    size_t nb = std::max((size_t)n[0] * R[1] * R[2], std::max((size_t)n[1] * R[0] * R[2], (size_t)R[0] * n[2] * R[1]));
+    w.B = ar.take<double>(nb);
+    w.core = ar.take<double>((size_t)R[0] * R[1] * R[2]);
+    w.M1 = ar.take<double>((size_t)n[0] * R[1] * R[2]);
+    w.Hrec = ar.take<double>((size_t)n[0] * n[1] * R[2]);
+    w.Ahat = (P.prec == TK_FP64) ? ar.take<double>(N) : nullptr;
+    w.nparts = std::max(recon_diff_parts((long)n[0] * n[1]), 1024);
+    w.partials = ar.take<double>(2 * (size_t)w.nparts);
+    w.scal = ar.take<double>(16);
+    w.ranks = ar.take<int>(16);
+    w.Gc = ar.take<double>(3 * (size_t)Rmax * Rmax);
+    w.Vc = ar.take<double>(3 * (size_t)Rmax * Rmax);
+    w.lamc = ar.take<double>(3 * 64);
+    w.tQ = ar.take<double>(3 * (size_t)Rmax * Rmax);
+    w.tY = ar.take<double>(3 * (size_t)Rmax * Rmax);
+    w.tH = ar.take<double>(3 * (size_t)Rmax * Rmax);
+    w.tVs = ar.take<double>(3 * (size_t)Rmax * Rmax);
+    w.coreA = ar.take<double>((size_t)R[0] * R[1] * R[2]);
+    w.coreB = ar.take<double>((size_t)R[0] * R[1] * R[2]);
+    for (int k = 0; k < 3; ++k) w.Urot[k] = ar.take<double>((size_t)n[k] * R[k]);
+}
+
+size_t result_bytes(const int n[3], const int r[3])
+{
+    Arena ar;
+    for (int k = 0; k < 3; ++k) { ar.take<double>((size_t)n[k] * r[k]); ar.take<float>((size_t)n[k] * r[k]); }
+    ar.take<double>((size_t)r[0] * r[1] * r[2]);
+    ar.take<float>((size_t)r[0] * r[1] * r[2]);
+    return ar.off;
+}
+
+size_t estimate(const Plan& P, bool own_A)
+{
+    Arena ar;
+    Work w;
+    layout_work(ar, P, own_A, w);
+    return ar.off + result_bytes(P.n, P.R);
+}
+
+// ------------------------------------------------------------------------------------------
+// GEMM helpers (row-major operands; see GemmArgs)
+// ------------------------------------------------------------------------------------------
+GemmArgs gemm(int M, int N, int K, int batch, const void* A, long sAb, long sAm, long sAk, const void* B, long sBb,
+              long sBk, long sBn, void* C, long sCb, long sCm, long sCn)
+{
+    GemmArgs g{};
+    g.M = M; g.N = N; g.K = K; g.batch = batch; g.reduce_batch = 0;
+    g.A = A; g.sAb = sAb; g.sAm = sAm; g.sAk = sAk;
+    g.B = B; g.sBb = sBb; g.sBk = sBk; g.sBn = sBn;
+    g.C = C; g.sCb = sCb; g.sCm = sCm; g.sCn = sCn;
+    g.alpha = 1.0; g.beta = 0.0;
+    return g;
+}
+
+#define TK_LAUNCH(x)                                                                               \
+    do {                                                                                           \
+        hipError_t _e = (x);                                                                       \
+        if (_e != hipSuccess) return fail(TK_EHIP, "launch %s: %s", #x, hipGetErrorString(_e));    \
+    } while (0)
+
+// Leading R_k eigenvectors of the three Grams in w.G (stride nmax^2), HOSVD start.
+tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
+{
+    if (P.cubic) {
+        EigBatch b{};
+        b.count = 3; b.n = P.n[0]; b.p = P.p[0]; b.r = P.R[0]; b.rw = 0; b.ldw = 0;
+        b.G = w.G; b.sG = (long)nmax * nmax;
+        b.Q = w.Q; b.Y = w.Y; b.H = w.H; b.Vs = w.Vs;
+        // U[0..2] are laid out consecutively only per arena; use a staging area then copy
+        b.U = w.Y; b.sU = (long)P.n[0] * P.R[0]; b.ldu = P.R[0];
+        b.lam = w.lam; b.sL = 64;
+        b.trace = w.trace; b.sTrace = 1;
+        // the eigensolver writes U after its last use of Y, so U may alias Y
+        TK_LAUNCH(launch_eig(b, COLD_ITERS, s));
+        for (int k = 0; k < 3; ++k)
+            TK_HIP(hipMemcpyAsync(w.U[k], w.Y + (long)k * P.n[0] * P.R[0], sizeof(double) * P.n[0] * P.R[0],
+                                  hipMemcpyDeviceToDevice, s));
+    } else {
+        for (int k = 0; k < 3; ++k) {
+            EigBatch b{};
+            b.count = 1; b.n = P.n[k]; b.p = P.p[k]; b.r = P.R[k];
+            b.G = w.G + (long)k * nmax * nmax; b.sG = 0;
+            b.Q = w.Q; b.Y = w.Y; b.H = w.H; b.Vs = w.Vs;
+            b.U = w.U[k]; b.sU = 0; b.ldu = P.R[k];
+            b.lam = w.lam + 64 * k; b.sL = 64;
+            b.trace = w.trace + k; b.sTrace = 1;
+            TK_LAUNCH(launch_eig(b, COLD_ITERS, s));
+        }
+    }
+    return TK_OK;
+}
+
+// Leading R_k eigenvectors of one symmetric n_k x n_k matrix Gs, warm-started from w.U[k].
+tk_status eig_update(const Plan& P, Work& w, int k, const double* Gs, hipStream_t s)
+{
+    EigBatch b{};
+    b.count = 1; b.n = P.n[k]; b.p = P.p[k]; b.r = P.R[k];
+    b.rw = P.R[k]; b.ldw = P.R[k]; b.warm = w.U[k]; b.sW = 0;
+    b.G = Gs; b.sG = 0;
+    b.Q = w.Q; b.Y = w.Y; b.H = w.H; b.Vs = w.Vs;
+    b.U = w.Y + (long)P.n[k] * P.p[k];   // staging: the start block reads U[k]
+    b.sU = 0; b.ldu = P.R[k];
+    b.lam = w.lam + 64 * k; b.sL = 64;
+    b.trace = nullptr;
+    TK_LAUNCH(launch_eig(b, WARM_ITERS, s));
+    TK_HIP(hipMemcpyAsync(w.U[k], b.U, sizeof(double) * P.n[k] * P.R[k], hipMemcpyDeviceToDevice, s));
+    return TK_OK;
+}
+
+template <typename Real>
+tk_status refresh_u32(const Plan& P, Work& w, int k, hipStream_t s)
+{
+    if (sizeof(Real) == 4) TK_LAUNCH(launch_convert_f64_to_f32(w.U[k], w.U32[k], (long)P.n[k] * P.R[k], s));
+    return TK_OK;
+}
+
+// T = A x_3 U3^T  (rows = n0 n1, r = R2)
+template <typename Real>
+tk_status ttm_last(const Plan& P, Work& w, const Real* A, hipStream_t s)
+{
+    long rows = (long)P.n[0] * P.n[1];
+    if (sizeof(Real) == 4) {
+        TK_LAUNCH(launch_ttm_last_f32((const float*)A, rows, P.n[2], w.U32[2], P.R[2], (float*)w.T, s));
+    } else {
+        GemmArgs g = gemm((int)rows, P.R[2], P.n[2], 1, A, 0, P.n[2], 1, w.U[2], 0, P.R[2], 1, w.T, 0, P.R[2], 1);
+        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+    }
+    return TK_OK;
+}
+
+// S = A x_1 U1^T  (R0 x n1 n2)
+template <typename Real>
+tk_status ttm_first(const Plan& P, Work& w, const Real* A, hipStream_t s)
+{
+    long cols = (long)P.n[1] * P.n[2];
+    if (sizeof(Real) == 4) {
+        TK_LAUNCH(launch_ttm_first_f32((const float*)A, P.n[0], cols, w.U32[0], P.R[0], (float*)w.S, s));
+    } else {
+        GemmArgs g = gemm(P.R[0], (int)cols, P.n[0], 1, w.U[0], 0, 1, P.R[0], A, 0, cols, 1, w.S, 0, cols, 1);
+        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+    }
+    return TK_OK;
+}
+
+template <typename Real>
+hipError_t gemm_rd(const GemmArgs& g, hipStream_t s)   // Real operand A, double B, double C
+{
+    return launch_gemm<Real, double, double>(g, s);
+}
+template <typename Real>
+hipError_t gemm_dr(const GemmArgs& g, hipStream_t s)   // double A, Real B, double C
+{
+    return launch_gemm<double, Real, double>(g, s);
+}
+
+// B1[i0][b][c] = sum_i1 U2[i1][b] T[i0][i1][c]
+template <typename Real>
+tk_status single_hole_1(const Plan& P, Work& w, hipStream_t s)
+{
+    const int n0 = P.n[0], n1 = P.n[1], R1 = P.R[1], R2 = P.R[2];
+    GemmArgs g = gemm(R1, R2, n1, n0, w.U[1], 0, 1, R1, w.T, (long)n1 * R2, R2, 1, w.B, (long)R1 * R2, R2, 1);
+    TK_LAUNCH(gemm_dr<Real>(g, s));
+    return TK_OK;
+}
+
+// small Gram of a row-major n x K unfolding stored in w.B -> Gs (n x n)
+tk_status small_gram_rows(int n, long K, const double* B, double* Gs, hipStream_t s)
+{
+    GemmArgs g = gemm(n, n, (int)K, 1, B, 0, K, 1, B, 0, 1, K, Gs, 0, n, 1);
+    TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+    return TK_OK;
+}
+
+template <typename Real>
+tk_status hooi_sweep(const Plan& P, Work& w, const Real* A, int nmax, hipStream_t s)
+{
+    const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+    const int R0 = P.R[0], R1 = P.R[1], R2 = P.R[2];
+    double* Gs = w.G;   // reuse the first Gram slot
+    tk_status st;
+    // ---- mode 1: B1 = A x_2 U2^T x_3 U3^T
+    if ((st = ttm_last<Real>(P, w, A, s)) != TK_OK) return st;
+    if ((st = single_hole_1<Real>(P, w, s)) != TK_OK) return st;
+    if ((st = small_gram_rows(n0, (long)R1 * R2, w.B, Gs, s)) != TK_OK) return st;
+    if ((st = eig_update(P, w, 0, Gs, s)) != TK_OK) return st;
+    if ((st = refresh_u32<Real>(P, w, 0, s)) != TK_OK) return st;
+    // ---- mode 2: B2[i1][a][c] = sum_i0 U1[i0][a] T[i0][i1][c]  (T still holds A x_3 U3^T)
+    {
+        GemmArgs g = gemm(R0, R2, n0, n1, w.U[0], 0, 1, R0, w.T, R2, (long)n1 * R2, 1, w.B, (long)R0 * R2, R2, 1);
+        TK_LAUNCH(gemm_dr<Real>(g, s));
+    }
+    if ((st = small_gram_rows(n1, (long)R0 * R2, w.B, Gs, s)) != TK_OK) return st;
+    if ((st = eig_update(P, w, 1, Gs, s)) != TK_OK) return st;
+    if ((st = refresh_u32<Real>(P, w, 1, s)) != TK_OK) return st;
+    // ---- mode 3: S = A x_1 U1^T, B3[a][i2][b] = sum_i1 S[a][i1][i2] U2[i1][b]
+    if ((st = ttm_first<Real>(P, w, A, s)) != TK_OK) return st;
+    {
+        GemmArgs g = gemm(n2, R1, n1, R0, w.S, (long)n1 * n2, 1, n2, w.U[1], 0, R1, 1, w.B, (long)n2 * R1, R1, 1);
+        TK_LAUNCH(gemm_rd<Real>(g, s));
+    }
+    {
+        // Gs[i2][i2'] = sum_a sum_b B3[a][i2][b] B3[a][i2'][b]
+        GemmArgs g = gemm(n2, n2, R1, R0, w.B, (long)n2 * R1, R1, 1, w.B, (long)n2 * R1, 1, R1, Gs, 0, n2, 1);
+        g.reduce_batch = 1;
+        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+    }
+    if ((st = eig_update(P, w, 2, Gs, s)) != TK_OK) return st;
+    if ((st = refresh_u32<Real>(P, w, 2, s)) != TK_OK) return st;
+    // ---- core[a][b][c] = sum_i2 B3[a][i2][b] U3[i2][c]
+    {
+        GemmArgs g = gemm(R1, R2, n2, R0, w.B, (long)n2 * R1, 1, R1, w.U[2], 0, R2, 1, w.core, (long)R1 * R2, R2, 1);
+        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+    }
+    (void)nmax;
+    return TK_OK;
+}
+
+// HOSVD core: G = A x_1 U1^T x_2 U2^T x_3 U3^T via T and B1.
+template <typename Real>
+tk_status hosvd_core(const Plan& P, Work& w, const Real* A, hipStream_t s)
+{
+    tk_status st;
+    if ((st = ttm_last<Real>(P, w, A, s)) != TK_OK) return st;
+    if ((st = single_hole_1<Real>(P, w, s)) != TK_OK) return st;
+    const int n0 = P.n[0], R0 = P.R[0], R1 = P.R[1], R2 = P.R[2];
+    GemmArgs g = gemm(R0, R1 * R2, n0, 1, w.U[0], 0, 1, R0, w.B, 0, (long)R1 * R2, 1, w.core, 0, (long)R1 * R2, 1);
+    TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+    return TK_OK;
+}
+
+// scal[0] = ||A||^2, scal[1] = ||A - core x_1 U1 x_2 U2 x_3 U3||^2 (factors n_k x R_k, FP64).
+template <typename Real>
+tk_status recon_norm(const Plan& P, Work& w, const Real* A, double* const Uf[3], const double* corep, hipStream_t s)
+{
+    const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+    const int R0 = P.R[0], R1 = P.R[1], R2 = P.R[2];
+    // M1[i0][b][c] = sum_a U1[i0][a] core[a][b][c]
+    {
+        GemmArgs g = gemm(n0, R1 * R2, R0, 1, Uf[0], 0, R0, 1, corep, 0, (long)R1 * R2, 1, w.M1, 0, (long)R1 * R2, 1);
+        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+    }
+    // H[i0][i1][c] = sum_b U2[i1][b] M1[i0][b][c]   (FP64)
+    {
+        GemmArgs g = gemm(n1, R2, R1, n0, Uf[1], 0, R1, 1, w.M1, (long)R1 * R2, R2, 1, w.Hrec, (long)n1 * R2, R2, 1);
+        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+    }
+    long rows = (long)n0 * n1;
+    if (sizeof(Real) == 4) {
+        int parts = recon_diff_parts(rows);
+        TK_LAUNCH(launch_recon_diff_f32((const float*)A, rows, n2, w.Hrec, Uf[2], R2, w.partials, s));
+        TK_LAUNCH(launch_reduce_partials(w.partials, parts, 2, w.scal + 8, s));
+    } else {
+        GemmArgs g = gemm((int)rows, n2, R2, 1, w.Hrec, 0, R2, 1, Uf[2], 0, 1, R2, w.Ahat, 0, n2, 1);
+        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+        int parts = 1024;
+        TK_LAUNCH(launch_diff_norm<double>((const double*)A, w.Ahat, rows * n2, w.partials, parts, s));
+        TK_LAUNCH(launch_reduce_partials(w.partials, parts, 2, w.scal + 8, s));
+    }
+    // scal[8] = d2, scal[9] = a2 -> scal[0] = a2, scal[1] = d2
+    TK_HIP(hipMemcpyAsync(w.scal + 1, w.scal + 8, sizeof(double), hipMemcpyDeviceToDevice, s));
+    TK_HIP(hipMemcpyAsync(w.scal + 0, w.scal + 9, sizeof(double), hipMemcpyDeviceToDevice, s));
+    return TK_OK;
+}
+
+// eps truncation of a rank-R result by the HOSVD of its core (float paths).  The error of
+// the truncated result satisfies E^2 = (d2 + ||G - G_r||^2) / ||A||^2 exactly, because
+// A - A_R is orthogonal to the tensor subspace that holds A_R - A_r.
+tk_status core_truncate(const Plan& P, Work& w, hipStream_t s)
+{
+    const int R0 = P.R[0], R1 = P.R[1], R2 = P.R[2];
+    const int Rm = std::max(R0, std::max(R1, R2));
+    const long RR = (long)Rm * Rm;
+    // core Grams
+    {
+        GemmArgs g = gemm(R0, R0, R1 * R2, 1, w.core, 0, (long)R1 * R2, 1, w.core, 0, 1, (long)R1 * R2, w.Gc, 0, R0, 1);
+        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+        GemmArgs g1 = gemm(R1, R1, R2, R0, w.core, (long)R1 * R2, R2, 1, w.core, (long)R1 * R2, 1, R2, w.Gc + RR, 0, R1, 1);
+        g1.reduce_batch = 1;
+        TK_LAUNCH((launch_gemm<double, double, double>(g1, s)));
+        GemmArgs g2 = gemm(R2, R2, R0 * R1, 1, w.core, 0, 1, R2, w.core, 0, R2, 1, w.Gc + 2 * RR, 0, R2, 1);
+        TK_LAUNCH((launch_gemm<double, double, double>(g2, s)));
+    }
+    // full eigendecompositions (p = n = R_k)
+    for (int k = 0; k < 3; ++k) {
+        EigBatch b{};
+        b.count = 1; b.n = P.R[k]; b.p = P.R[k]; b.r = P.R[k];
+        b.G = w.Gc + k * RR; b.sG = 0;
+        b.Q = w.tQ + k * RR; b.Y = w.tY + k * RR; b.H = w.tH + k * RR; b.Vs = w.tVs + k * RR;
+        b.U = w.Vc + k * RR; b.sU = 0; b.ldu = P.R[k];
+        b.lam = w.lamc + 64 * k; b.sL = 64;
+        b.trace = nullptr;
+        TK_LAUNCH(launch_eig(b, 0, s));
+    }
+    // ranks: budget = (eps^2 a2 - d2) / 3 per mode
+    for (int k = 0; k < 3; ++k)
+        TK_LAUNCH(launch_rank_rule(w.lamc + 64 * k, 64, P.R[k], 1, nullptr, 0, w.scal, 1, P.eps * P.eps,
+                                   w.ranks + k, w.ranks + 3 + k, s));
+    // rotate factors: Urot_k = U_k V_k
+    for (int k = 0; k < 3; ++k) {
+        GemmArgs g = gemm(P.n[k], P.R[k], P.R[k], 1, w.U[k], 0, P.R[k], 1, w.Vc + k * RR, 0, P.R[k], 1, w.Urot[k], 0,
+                          P.R[k], 1);
+        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+    }
+    // rotate core: coreB = core x_1 V1^T x_2 V2^T x_3 V3^T
+    {
+        GemmArgs g = gemm(R0, R1 * R2, R0, 1, w.Vc, 0, 1, R0, w.core, 0, (long)R1 * R2, 1, w.coreA, 0, (long)R1 * R2, 1);
+        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+        GemmArgs g1 = gemm(R1, R2, R1, R0, w.Vc + RR, 0, 1, R1, w.coreA, (long)R1 * R2, R2, 1, w.coreB, (long)R1 * R2,
+                           R2, 1);
+        TK_LAUNCH((launch_gemm<double, double, double>(g1, s)));
+        GemmArgs g2 = gemm(R0 * R1, R2, R2, 1, w.coreB, 0, R2, 1, w.Vc + 2 * RR, 0, R2, 1, w.coreA, 0, R2, 1);
+        TK_LAUNCH((launch_gemm<double, double, double>(g2, s)));
+    }
+    TK_LAUNCH(launch_trunc_err(w.coreA, R0, R1, R2, w.ranks, w.scal + 2, s));
+    TK_LAUNCH(launch_final_err(w.scal, s));
+    return TK_OK;
+}
+
+tk_status alloc_result(tk_ctx* ctx, const int n[3], const int r[3], hipStream_t s, tk_tucker** out)
+{
+    tk_tucker* t = new (std::nothrow) tk_tucker();
+    if (!t) return fail(TK_ENOMEM, "host allocation failed");
+    t->ctx = ctx;
+    size_t bytes = result_bytes(n, r);
+    if (!reserve(ctx, bytes)) {
+        delete t;
+        return fail(TK_ENOMEM, "result (%zu bytes) exceeds the remaining HBM budget", bytes);
+    }
+    t->bytes = bytes;
+    void* blk = nullptr;
+    hipError_t e = hipMallocAsync(&blk, bytes, s);
+    if (e != hipSuccess) {
+        release(ctx, bytes);
+        delete t;
+        return fail(TK_ENOMEM, "hipMallocAsync(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    t->block = blk;
+    t->stream = s;
+    Arena ar;
+    ar.base = (char*)blk;
+    for (int k = 0; k < 3; ++k) {
+        t->n[k] = n[k];
+        t->r[k] = r[k];
+        t->U[k] = ar.take<double>((size_t)n[k] * r[k]);
+        t->U32[k] = ar.take<float>((size_t)n[k] * r[k]);
+    }
+    t->core = ar.take<double>((size_t)r[0] * r[1] * r[2]);
+    t->core32 = ar.take<float>((size_t)r[0] * r[1] * r[2]);
+    ctx->live_results.fetch_add(1);
+    *out = t;
+    return TK_OK;
+}
+
+void free_result(tk_tucker* t)
+{
+    if (!t) return;
+    if (t->block) {
+        // the result may have been read on any stream: free it once the device is idle
+        hipSetDevice(t->ctx->device);
+        hipDeviceSynchronize();
+        hipFreeAsync(t->block, t->stream);
+    }
+    release(t->ctx, t->bytes);
+    t->ctx->live_results.fetch_sub(1);
+    delete t;
+}
+
+tk_status fill_result_from(tk_tucker* t, const double* const Usrc[3], const int ldU[3], const double* core,
+                           const int Rc[3], hipStream_t s)
+{
+    for (int k = 0; k < 3; ++k) {
+        TK_HIP(hipMemcpy2DAsync(t->U[k], sizeof(double) * t->r[k], Usrc[k], sizeof(double) * ldU[k],
+                                sizeof(double) * t->r[k], t->n[k], hipMemcpyDeviceToDevice, s));
+        TK_LAUNCH(launch_convert_f64_to_f32(t->U[k], t->U32[k], (long)t->n[k] * t->r[k], s));
+    }
+    TK_LAUNCH((launch_copy_block<double, double>(core, Rc[1], Rc[2], t->core, t->r[0], t->r[1], t->r[2], s)));
+    TK_LAUNCH((launch_copy_block<double, float>(core, Rc[1], Rc[2], t->core32, t->r[0], t->r[1], t->r[2], s)));
+    return TK_OK;
+}
+
+// The compression pipeline for one tensor.  A_in: caller tensor or nullptr (sample kernel).
+template <typename Real>
+tk_status compress_impl(tk_ctx* ctx, const KernelParams* kp, const void* A_in, const tk_grid* grid, Plan P,
+                        hipStream_t s, tk_tucker** out)
+{
+    const bool own_A = (A_in == nullptr);
+    size_t need = estimate(P, own_A);
+    Reservation res(ctx, need);
+    if (!res.take()) return fail(TK_ENOMEM, "compress needs %zu bytes; budget %zu, in use %zu", need, ctx->budget,
+                                 ctx->in_use.load());
+    Arena plan;
+    Work w;
+    layout_work(plan, P, own_A, w);
+    void* base = nullptr;
+    hipError_t he = hipMallocAsync(&base, plan.off, s);
+    if (he != hipSuccess) return fail(TK_ENOMEM, "hipMallocAsync(%zu): %s", plan.off, hipGetErrorString(he));
+    struct Freer {
+        void* p;
+        hipStream_t s;
+        ~Freer() { if (p) hipFreeAsync(p, s); }
+    } freer{base, s};
+    Arena ar;
+    ar.base = (char*)base;
+    layout_work(ar, P, own_A, w);
+    const int nmax = std::max(P.n[0], std::max(P.n[1], P.n[2]));
+    const Real* A = own_A ? (const Real*)w.A : (const Real*)A_in;
+    tk_status st;
+
+    if (own_A) {
+        GridAxes ax = axes_of(grid);
+        if (sizeof(Real) == 4) TK_LAUNCH(launch_grid_eval_f32((float*)w.A, ax, *kp, s));
+        else TK_LAUNCH(launch_grid_eval_f64((double*)w.A, ax, *kp, s));
+    }
+    // ---- HOSVD: Grams and leading eigenvectors
+    for (int k = 0; k < 3; ++k)
+        TK_LAUNCH(launch_gram(A, P.n, k, P.prec, w.G + (long)k * nmax * nmax, w.gram_work, s));
+    if ((st = eig_modes(P, w, nmax, s)) != TK_OK) return st;
+
+    if (P.eps_mode && P.prec == TK_FP64) {
+        // rank rule on the Gram eigenvalues: tail(r) = trace - sum_{i<r} lambda_i
+        TK_HIP(hipMemcpyAsync(w.scal, w.trace, sizeof(double), hipMemcpyDeviceToDevice, s));   // ||A||^2
+        TK_LAUNCH(launch_rank_rule(w.lam, 64, P.R[0], 1, w.trace, 1, w.scal, 0, P.eps * P.eps, w.ranks + 0,
+                                   w.ranks + 3, s));
+        TK_LAUNCH(launch_rank_rule(w.lam + 64, 64, P.R[1], 1, w.trace + 1, 1, w.scal, 0, P.eps * P.eps, w.ranks + 1,
+                                   w.ranks + 4, s));
+        TK_LAUNCH(launch_rank_rule(w.lam + 128, 64, P.R[2], 1, w.trace + 2, 1, w.scal, 0, P.eps * P.eps,
+                                   w.ranks + 2, w.ranks + 5, s));
+        int hr[6];
+        TK_HIP(hipMemcpyAsync(hr, w.ranks, sizeof(hr), hipMemcpyDeviceToHost, s));
+        TK_HIP(hipStreamSynchronize(s));
+        // continue with the selected ranks: the leading columns of the factors are kept
+        Plan Q = P;
+        for (int k = 0; k < 3; ++k) Q.R[k] = hr[k];
+        for (int k = 0; k < 3; ++k) {
+            if (Q.R[k] != P.R[k]) {
+                TK_HIP(hipMemcpy2DAsync(w.Urot[k], sizeof(double) * Q.R[k], w.U[k], sizeof(double) * P.R[k],
+                                        sizeof(double) * Q.R[k], P.n[k], hipMemcpyDeviceToDevice, s));
+                TK_HIP(hipMemcpyAsync(w.U[k], w.Urot[k], sizeof(double) * Q.R[k] * P.n[k], hipMemcpyDeviceToDevice, s));
+            }
+            Q.p[k] = (P.n[k] <= EIG_PMAX) ? P.n[k] : std::min(Q.R[k] + 8, EIG_PMAX);
+        }
+        P = Q;
+    }
+    for (int k = 0; k < 3; ++k)
+        if ((st = refresh_u32<Real>(P, w, k, s)) != TK_OK) return st;
+
+    // ---- HOOI sweeps, then the core
+    if (P.sweeps == 0) {
+        if ((st = hosvd_core<Real>(P, w, A, s)) != TK_OK) return st;
+    } else {
+        for (int it = 0; it < P.sweeps; ++it)
+            if ((st = hooi_sweep<Real>(P, w, A, nmax, s)) != TK_OK) return st;
+    }
+    // ---- reconstruction error
+    if ((st = recon_norm<Real>(P, w, A, w.U, w.core, s)) != TK_OK) return st;
+
+    int final_r[3] = {P.R[0], P.R[1], P.R[2]};
+    double hs[4];
+    int hr[6] = {P.R[0], P.R[1], P.R[2], 1, 1, 1};
+    const double* Usrc[3] = {w.U[0], w.U[1], w.U[2]};
+    const double* csrc = w.core;
+    if (P.eps_mode && P.prec != TK_FP64) {
+        // ranks from the core HOSVD with the (conservative) error bound, then the error of the
+        // truncated result measured directly against A
+        if ((st = core_truncate(P, w, s)) != TK_OK) return st;
+        TK_LAUNCH(launch_mask_rank(w.Urot, P.n, P.R, w.coreA, w.ranks, s));
+        if ((st = recon_norm<Real>(P, w, A, w.Urot, w.coreA, s)) != TK_OK) return st;
+        TK_LAUNCH(launch_fill_f64(w.scal + 2, 0.0, 1, s));
+        TK_LAUNCH(launch_final_err(w.scal, s));
+        TK_HIP(hipMemcpyAsync(hr, w.ranks, sizeof(hr), hipMemcpyDeviceToHost, s));
+        TK_HIP(hipMemcpyAsync(hs, w.scal, sizeof(hs), hipMemcpyDeviceToHost, s));
+        TK_HIP(hipStreamSynchronize(s));
+        for (int k = 0; k < 3; ++k) { final_r[k] = hr[k]; Usrc[k] = w.Urot[k]; }
+        csrc = w.coreA;
+    } else {
+        TK_LAUNCH(launch_fill_f64(w.scal + 2, 0.0, 1, s));   // no truncation: t2 = 0
+        TK_LAUNCH(launch_final_err(w.scal, s));
+        TK_HIP(hipMemcpyAsync(hs, w.scal, sizeof(hs), hipMemcpyDeviceToHost, s));
+        TK_HIP(hipStreamSynchronize(s));
+    }
+    tk_tucker* t = nullptr;
+    if ((st = alloc_result(ctx, P.n, final_r, s, &t)) != TK_OK) return st;
+    int ld[3] = {P.R[0], P.R[1], P.R[2]};
+    int Rc[3] = {P.R[0], P.R[1], P.R[2]};
+    if ((st = fill_result_from(t, Usrc, ld, csrc, Rc, s)) != TK_OK) {
+        free_result(t);
+        return st;
+    }
+    for (int k = 0; k < 3; ++k) t->b[k] = grid->b[k];
+    t->layout = grid->layout;
+    t->prec = P.prec;
+    t->rel_err = hs[3];
+    t->norm_a = std::sqrt(hs[0]);
+    *out = t;
+    bool met = true;
+    if (P.eps_mode) met = (hs[3] <= P.eps);
+    if (!met) return fail(TK_ENOCONV, "eps=%g not reached: error %g at ranks (%d,%d,%d)", P.eps, hs[3], final_r[0],
+                          final_r[1], final_r[2]);
+    return TK_OK;
+}
+
+tk_status compress_any(tk_ctx* ctx, const tk_kernel* kernel, const void* A_in, const tk_grid* grid,
+                       const tk_opts* opts, void* stream, tk_tucker** out)
+{
+    if (!ctx || !out) return fail(TK_EINVAL, "ctx/out is NULL");
+    *out = nullptr;
+    tk_status st;
+    if ((st = check_grid(grid)) != TK_OK) return st;
+    KernelParams kp{};
+    if (!A_in && (st = check_kernel(kernel, &kp)) != TK_OK) return st;
+    Plan P;
+    if ((st = make_plan(grid, opts, &P)) != TK_OK) return st;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(TK_EHIP, "hipSetDevice(%d) failed", ctx->device);
+    (void)hipGetLastError();   // drop errors left by earlier, unrelated HIP calls
+    hipStream_t s = (hipStream_t)stream;
+    if (P.prec == TK_FP64) return compress_impl<double>(ctx, &kp, A_in, grid, P, s, out);
+    return compress_impl<float>(ctx, &kp, A_in, grid, P, s, out);
+}
+
+bool cov_geometry(const tk_tucker* t, int off[3], int m[3])
+{
+    for (int k = 0; k < 3; ++k) {
+        if (t->layout == TK_OFFSET) { off[k] = 0; m[k] = t->n[k]; }
+        else if (t->n[k] % 2 == 1) { off[k] = (t->n[k] - 1) / 2; m[k] = (t->n[k] + 1) / 2; }
+        else return false;
+    }
+    return true;
+}
+
+size_t matvec_work_bytes(const tk_tucker* t, int esz)
+{
+    int off[3], m[3];
+    cov_geometry(t, off, m);
+    size_t M3 = (size_t)m[0] * m[1] * m[2];
+    Arena ar;
+    ar.take<char>((size_t)t->r[0] * t->r[1] * t->n[2] * esz);    // W generators
+    ar.take<char>((size_t)t->r[0] * M3 * esz);                   // Z1
+    ar.take<char>((size_t)t->r[1] * M3 * esz);                   // P
+    ar.take<double>(2048);                                       // dot partials + result
+    return ar.off;
+}
+
+template <typename T>
+tk_status matvec_impl(tk_ctx* ctx, const tk_tucker* t, const T* z, T* y, hipStream_t s, double* dot_out)
+{
+    int off[3], m[3];
+    if (!cov_geometry(t, off, m)) return fail(TK_ELAYOUT, "even-sized centred grid has no origin node");
+    const int r0 = t->r[0], r1 = t->r[1], r2 = t->r[2];
+    const long M3 = (long)m[0] * m[1] * m[2];
+    size_t need = matvec_work_bytes(t, sizeof(T));
+    Reservation res(ctx, need);
+    if (!res.take()) return fail(TK_ENOMEM, "matvec needs %zu bytes; budget %zu, in use %zu", need, ctx->budget,
+                                 ctx->in_use.load());
+    void* base = nullptr;
+    hipError_t he = hipMallocAsync(&base, need, s);
+    if (he != hipSuccess) return fail(TK_ENOMEM, "hipMallocAsync(%zu): %s", need, hipGetErrorString(he));
+    struct Freer {
+        void* p;
+        hipStream_t s;
+        ~Freer() { if (p) hipFreeAsync(p, s); }
+    } freer{base, s};
+    Arena ar;
+    ar.base = (char*)base;
+    T* W = ar.take<T>((size_t)r0 * r1 * t->n[2]);
+    T* Z1 = ar.take<T>((size_t)r0 * M3);
+    T* Pb = ar.take<T>((size_t)r1 * M3);
+    double* dots = ar.take<double>(2048);
+    const T* U0 = sizeof(T) == 4 ? (const T*)t->U32[0] : (const T*)t->U[0];
+    const T* U1 = sizeof(T) == 4 ? (const T*)t->U32[1] : (const T*)t->U[1];
+    const T* U2 = sizeof(T) == 4 ? (const T*)t->U32[2] : (const T*)t->U[2];
+    const T* core = sizeof(T) == 4 ? (const T*)t->core32 : (const T*)t->core;
+    // W[a][b][i] = sum_c core[a][b][c] U3[i][c]  (generators of the mode-3 Toeplitz factors)
+    {
+        GemmArgs g = gemm(r0 * r1, t->n[2], r2, 1, core, 0, r2, 1, U2, 0, 1, r2, W, 0, t->n[2], 1);
+        TK_LAUNCH((launch_gemm<T, T, T>(g, s)));
+    }
+    // Z1[a] = T(U1[:, a]) along mode 1
+    {
+        ToepLeftArgs a{};
+        a.M = m[0]; a.N = (int)((long)m[1] * m[2]); a.K = m[0]; a.nb = 1;
+        a.gen = U0; a.gs_idx = r0; a.gs_col = 1; a.gstride_g = 1; a.gstride_b = 0;
+        a.glen = t->n[0]; a.glen_pad = (t->n[0] + 1) & ~1; a.off = off[0];
+        a.In = z; a.sIs = 0; a.sIg = 0; a.sIb = 0; a.sIi = (long)m[1] * m[2];
+        a.Out = Z1; a.sOs = 0; a.sOg = M3; a.sOi = (long)m[1] * m[2];
+        a.accumulate = 0;
+        TK_LAUNCH(launch_toep_left<T>(a, 1, r0, s));
+    }
+    for (int a0 = 0; a0 < r0; ++a0) {
+        // P[(i0, i1)][b][i2'] = sum_i2 Z1[a][i0][i1][i2] T(w_ab)[i2][i2']
+        ToepRightArgs rr{};
+        rr.R = (long)m[0] * m[1]; rr.K = m[2]; rr.m = m[2]; rr.nb = r1;
+        rr.gen = W + (long)a0 * r1 * t->n[2]; rr.gs_idx = 1; rr.gs_col = t->n[2]; rr.glen = t->n[2]; rr.off = off[2];
+        rr.In = Z1 + (long)a0 * M3; rr.ldi = m[2];
+        rr.Out = Pb; rr.ldo = (long)r1 * m[2];
+        TK_LAUNCH(launch_toep_right<T>(rr, s));
+        // y[i0][i1'][:] (+)= sum_b sum_i1 T(U2[:, b])[i1'][i1] P[i0][i1][b][:]
+        ToepLeftArgs l{};
+        l.M = m[1]; l.N = m[2]; l.K = m[1]; l.nb = r1;
+        l.gen = U1; l.gs_idx = r1; l.gs_col = 1; l.gstride_g = 0; l.gstride_b = 1;
+        l.glen = t->n[1]; l.glen_pad = (t->n[1] + 1) & ~1; l.off = off[1];
+        l.In = Pb; l.sIs = (long)m[1] * r1 * m[2]; l.sIg = 0; l.sIb = m[2]; l.sIi = (long)r1 * m[2];
+        l.Out = y; l.sOs = (long)m[1] * m[2]; l.sOg = 0; l.sOi = m[2];
+        l.accumulate = a0 > 0;
+        TK_LAUNCH(launch_toep_left<T>(l, m[0], 1, s));
+    }
+    if (dot_out) {
+        TK_LAUNCH(launch_dot<T>(z, y, M3, dots, 1024, dots + 1024, s));
+        TK_HIP(hipMemcpyAsync(dot_out, dots + 1024, sizeof(double), hipMemcpyDeviceToHost, s));
+        TK_HIP(hipStreamSynchronize(s));
+    }
+    return TK_OK;
+}
+
+}  // namespace
+
+// ==========================================================================================
+// C ABI
+// ==========================================================================================
+extern "C" {
+
+const char* tk_version(void) { return "tk-mi355x 0.1 (gfx950)"; }
+
+const char* tk_last_error(void) { return g_last_error.c_str(); }
+
+const char* tk_strerror(tk_status s)
+{
+    switch (s) {
+    case TK_OK: return "TK_OK";
+    case TK_EINVAL: return "TK_EINVAL";
+    case TK_EUNSUPPORTED: return "TK_EUNSUPPORTED";
+    case TK_ELAYOUT: return "TK_ELAYOUT";
+    case TK_ENOMEM: return "TK_ENOMEM";
+    case TK_EHIP: return "TK_EHIP";
+    case TK_ENOCONV: return "TK_ENOCONV";
+    }
+    return "TK_UNKNOWN";
+}
+
+tk_status tk_ctx_create(int device, size_t hbm_budget_bytes, tk_ctx** out)
+{
+    if (!out) return fail(TK_EINVAL, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0) return fail(TK_EHIP, "no HIP device");
+    if (device < 0 || device >= count) return fail(TK_EINVAL, "device %d out of range (%d devices)", device, count);
+    TK_HIP(hipSetDevice(device));
+    size_t freeb = 0, total = 0;
+    TK_HIP(hipMemGetInfo(&freeb, &total));
+    hipMemPool_t pool;
+    TK_HIP(hipDeviceGetDefaultMemPool(&pool, device));
+    uint64_t thr = UINT64_MAX;
+    TK_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+    TK_HIP(eig_set_attributes());
+    TK_HIP(kron_set_attributes());
+    tk_ctx* c = new (std::nothrow) tk_ctx();
+    if (!c) return fail(TK_ENOMEM, "host allocation failed");
+    c->device = device;
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)freeb);
+    *out = c;
+    return TK_OK;
+}
+
+void tk_ctx_destroy(tk_ctx* ctx)
+{
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    delete ctx;
+}
+
+tk_status tk_ctx_budget(const tk_ctx* ctx, size_t* budget_bytes, size_t* in_use_bytes)
+{
+    if (!ctx) return fail(TK_EINVAL, "ctx is NULL");
+    if (budget_bytes) *budget_bytes = ctx->budget;
+    if (in_use_bytes) *in_use_bytes = ctx->in_use.load();
+    return TK_OK;
+}
+
+tk_status tk_estimate_bytes(const tk_grid* grid, const tk_opts* opts, size_t* peak_bytes)
+{
+    if (!peak_bytes) return fail(TK_EINVAL, "peak_bytes is NULL");
+    tk_status st;
+    if ((st = check_grid(grid)) != TK_OK) return st;
+    Plan P;
+    if ((st = make_plan(grid, opts, &P)) != TK_OK) return st;
+    *peak_bytes = estimate(P, true);
+    return TK_OK;
+}
+
+tk_status tk_compress(tk_ctx* ctx, const tk_kernel* kernel, const tk_grid* grid, const tk_opts* opts,
+                      void* hip_stream, tk_tucker** out)
+{
+    if (!kernel) return fail(TK_EINVAL, "kernel is NULL");
+    return compress_any(ctx, kernel, nullptr, grid, opts, hip_stream, out);
+}
+
+tk_status tk_compress_tensor(tk_ctx* ctx, const void* A_dev, const tk_grid* grid, const tk_opts* opts,
+                             void* hip_stream, tk_tucker** out)
+{
+    if (!A_dev) return fail(TK_EINVAL, "A_dev is NULL");
+    return compress_any(ctx, nullptr, A_dev, grid, opts, hip_stream, out);
+}
+
+tk_status tk_compress_batch(tk_ctx* ctx, int count, const tk_kernel* kernels, const tk_grid* grids,
+                            const tk_opts* opts, void* hip_stream, tk_tucker** outs)
+{
+    if (!ctx || !kernels || !grids || !opts || !outs || count < 0) return fail(TK_EINVAL, "bad batch arguments");
+    for (int i = 0; i < count; ++i) outs[i] = nullptr;
+    for (int i = 0; i < count; ++i) {
+        tk_status st = compress_any(ctx, &kernels[i], nullptr, &grids[i], opts, hip_stream, &outs[i]);
+        if (st != TK_OK && st != TK_ENOCONV) {
+            std::string msg = g_last_error;
+            for (int j = 0; j <= i; ++j) { free_result(outs[j]); outs[j] = nullptr; }
+            return fail(st, "batch item %d: %s", i, msg.c_str());
+        }
+    }
+    return TK_OK;
+}
+
+tk_status tk_tucker_info(const tk_tucker* t, int n[3], int ranks[3], double* rel_err_fro, double* norm_a,
+                         int* layout)
+{
+    if (!t) return fail(TK_EINVAL, "t is NULL");
+    for (int k = 0; k < 3; ++k) {
+        if (n) n[k] = t->n[k];
+        if (ranks) ranks[k] = t->r[k];
+    }
+    if (rel_err_fro) *rel_err_fro = t->rel_err;
+    if (norm_a) *norm_a = t->norm_a;
+    if (layout) *layout = t->layout;
+    return TK_OK;
+}
+
+tk_status tk_tucker_get(const tk_tucker* t, double* U_host[3], double* core_host)
+{
+    if (!t) return fail(TK_EINVAL, "t is NULL");
+    TK_HIP(hipSetDevice(t->ctx->device));
+    (void)hipGetLastError();
+    TK_HIP(hipStreamSynchronize(t->stream));
+    for (int k = 0; k < 3; ++k)
+        if (U_host && U_host[k])
+            TK_HIP(hipMemcpy(U_host[k], t->U[k], sizeof(double) * t->n[k] * t->r[k], hipMemcpyDeviceToHost));
+    if (core_host)
+        TK_HIP(hipMemcpy(core_host, t->core, sizeof(double) * t->r[0] * t->r[1] * t->r[2], hipMemcpyDeviceToHost));
+    return TK_OK;
+}
+
+tk_status tk_tucker_device(const tk_tucker* t, const double* U_dev[3], const double** core_dev)
+{
+    if (!t) return fail(TK_EINVAL, "t is NULL");
+    for (int k = 0; k < 3; ++k)
+        if (U_dev) U_dev[k] = t->U[k];
+    if (core_dev) *core_dev = t->core;
+    return TK_OK;
+}
+
+tk_status tk_reconstruct(tk_ctx* ctx, const tk_tucker* t, void* A_dev, int io, void* hip_stream)
+{
+    if (!ctx || !t || !A_dev) return fail(TK_EINVAL, "NULL argument");
+    if (io != TK_FP64 && io != TK_FP32) return fail(TK_EINVAL, "io must be TK_FP64 or TK_FP32");
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int* n = t->n;
+    const int* r = t->r;
+    size_t need = sizeof(double) * ((size_t)n[0] * r[1] * r[2] + (size_t)n[0] * n[1] * r[2]) + 1024;
+    Reservation res(ctx, need);
+    if (!res.take()) return fail(TK_ENOMEM, "reconstruct needs %zu bytes", need);
+    void* base = nullptr;
+    TK_HIP(hipMallocAsync(&base, need, s));
+    struct Freer {
+        void* p;
+        hipStream_t s;
+        ~Freer() { if (p) hipFreeAsync(p, s); }
+    } freer{base, s};
+    Arena ar;
+    ar.base = (char*)base;
+    double* M1 = ar.take<double>((size_t)n[0] * r[1] * r[2]);
+    double* H = ar.take<double>((size_t)n[0] * n[1] * r[2]);
+    GemmArgs g = gemm(n[0], r[1] * r[2], r[0], 1, t->U[0], 0, r[0], 1, t->core, 0, (long)r[1] * r[2], 1, M1, 0,
+                      (long)r[1] * r[2], 1);
+    TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+    GemmArgs g1 = gemm(n[1], r[2], r[1], n[0], t->U[1], 0, r[1], 1, M1, (long)r[1] * r[2], r[2], 1, H,
+                       (long)n[1] * r[2], r[2], 1);
+    TK_LAUNCH((launch_gemm<double, double, double>(g1, s)));
+    GemmArgs g2 = gemm(n[0] * n[1], n[2], r[2], 1, H, 0, r[2], 1, t->U[2], 0, 1, r[2], A_dev, 0, n[2], 1);
+    if (io == TK_FP64) TK_LAUNCH((launch_gemm<double, double, double>(g2, s)));
+    else TK_LAUNCH((launch_gemm<double, double, float>(g2, s)));
+    return TK_OK;
+}
+
+tk_status tk_cov_dims(const tk_tucker* t, int m[3])
+{
+    if (!t || !m) return fail(TK_EINVAL, "NULL argument");
+    int off[3];
+    if (!cov_geometry(t, off, m)) return fail(TK_ELAYOUT, "even-sized centred grid has no origin node");
+    return TK_OK;
+}
+
+tk_status tk_kron_matvec(tk_ctx* ctx, const tk_tucker* t, const void* z_dev, void* y_dev, int io, void* hip_stream)
+{
+    if (!ctx || !t || !z_dev || !y_dev) return fail(TK_EINVAL, "NULL argument");
+    if (z_dev == y_dev) return fail(TK_EINVAL, "y must not alias z");
+    if (io != TK_FP64 && io != TK_FP32) return fail(TK_EINVAL, "io must be TK_FP64 or TK_FP32");
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    if (io == TK_FP32)
+        return matvec_impl<float>(ctx, t, (const float*)z_dev, (float*)y_dev, (hipStream_t)hip_stream, nullptr);
+    return matvec_impl<double>(ctx, t, (const double*)z_dev, (double*)y_dev, (hipStream_t)hip_stream, nullptr);
+}
+
+tk_status tk_quadratic_form(tk_ctx* ctx, const tk_tucker* t, const void* z_dev, int io, void* hip_stream,
+                            double* out, void* y_dev)
+{
+    if (!ctx || !t || !z_dev || !out) return fail(TK_EINVAL, "NULL argument");
+    if (io != TK_FP64 && io != TK_FP32) return fail(TK_EINVAL, "io must be TK_FP64 or TK_FP32");
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    hipStream_t s = (hipStream_t)hip_stream;
+    int off[3], m[3];
+    if (!cov_geometry(t, off, m)) return fail(TK_ELAYOUT, "even-sized centred grid has no origin node");
+    void* ybuf = y_dev;
+    void* owned = nullptr;
+    size_t esz = io == TK_FP32 ? 4 : 8;
+    size_t ybytes = esz * (size_t)m[0] * m[1] * m[2];
+    Reservation res(ctx, y_dev ? 0 : ybytes);
+    if (!y_dev) {
+        if (!res.take()) return fail(TK_ENOMEM, "quadratic form needs %zu bytes", ybytes);
+        TK_HIP(hipMallocAsync(&owned, ybytes, s));
+        ybuf = owned;
+    }
+    tk_status st;
+    if (io == TK_FP32)
+        st = matvec_impl<float>(ctx, t, (const float*)z_dev, (float*)ybuf, s, out);
+    else
+        st = matvec_impl<double>(ctx, t, (const double*)z_dev, (double*)ybuf, s, out);
+    if (owned) hipFreeAsync(owned, s);
+    return st;
+}
+
+tk_status tk_trace(tk_ctx* ctx, const tk_tucker* t, void* hip_stream, double* out)
+{
+    if (!ctx || !t || !out) return fail(TK_EINVAL, "NULL argument");
+    int off[3], m[3];
+    if (!cov_geometry(t, off, m)) return fail(TK_ELAYOUT, "even-sized centred grid has no origin node");
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    hipStream_t s = (hipStream_t)hip_stream;
+    void* buf = nullptr;
+    TK_HIP(hipMallocAsync(&buf, 256, s));
+    double scale = (double)m[0] * m[1] * m[2];
+    hipError_t e = launch_cov_trace(t->core, t->r[0], t->r[1], t->r[2], t->U[0] + (long)off[0] * t->r[0],
+                                    t->U[1] + (long)off[1] * t->r[1], t->U[2] + (long)off[2] * t->r[2], scale,
+                                    (double*)buf, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, buf, sizeof(double), hipMemcpyDeviceToHost, s);
+    hipFreeAsync(buf, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(TK_EHIP, "trace: %s", hipGetErrorString(e));
+    return TK_OK;
+}
+
+tk_status tk_tucker_save(const tk_tucker* t, const char* path)
+{
+    if (!t || !path) return fail(TK_EINVAL, "NULL argument");
+    std::vector<std::vector<double>> U(3);
+    for (int k = 0; k < 3; ++k) U[k].resize((size_t)t->n[k] * t->r[k]);
+    std::vector<double> core((size_t)t->r[0] * t->r[1] * t->r[2]);
+    double* Up[3] = {U[0].data(), U[1].data(), U[2].data()};
+    tk_status st = tk_tucker_get(t, Up, core.data());
+    if (st != TK_OK) return st;
+    FILE* f = fopen(path, "wb");
+    if (!f) return fail(TK_EINVAL, "cannot open %s for writing", path);
+    const char magic[8] = {'T', 'K', 'T', 'U', 'C', 'K', '0', '1'};
+    int32_t hdr[8] = {1, t->n[0], t->n[1], t->n[2], t->r[0], t->r[1], t->r[2], t->layout};
+    double meta[5] = {t->b[0], t->b[1], t->b[2], t->rel_err, t->norm_a};
+    bool ok = fwrite(magic, 1, 8, f) == 8 && fwrite(hdr, sizeof(hdr), 1, f) == 1 && fwrite(meta, sizeof(meta), 1, f) == 1;
+    for (int k = 0; k < 3 && ok; ++k) ok = fwrite(U[k].data(), sizeof(double), U[k].size(), f) == U[k].size();
+    if (ok) ok = fwrite(core.data(), sizeof(double), core.size(), f) == core.size();
+    ok = (fclose(f) == 0) && ok;
+    if (!ok) return fail(TK_EINVAL, "write to %s failed", path);
+    return TK_OK;
+}
+
+tk_status tk_tucker_load(tk_ctx* ctx, const char* path, tk_tucker** out)
+{
+    if (!ctx || !path || !out) return fail(TK_EINVAL, "NULL argument");
+    *out = nullptr;
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(TK_EINVAL, "cannot open %s", path);
+    char magic[8];
+    int32_t hdr[8];
+    double meta[5];
+    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "TKTUCK01", 8) == 0 && fread(hdr, sizeof(hdr), 1, f) == 1 &&
+              fread(meta, sizeof(meta), 1, f) == 1 && hdr[0] == 1;
+    int n[3] = {hdr[1], hdr[2], hdr[3]}, r[3] = {hdr[4], hdr[5], hdr[6]};
+    for (int k = 0; k < 3 && ok; ++k) ok = n[k] >= 1 && n[k] <= NMAX && r[k] >= 1 && r[k] <= n[k] && r[k] <= EIG_PMAX;
+    ok = ok && (hdr[7] == TK_CENTERED || hdr[7] == TK_OFFSET);
+    std::vector<std::vector<double>> U(3);
+    std::vector<double> core;
+    if (ok) {
+        for (int k = 0; k < 3 && ok; ++k) {
+            U[k].resize((size_t)n[k] * r[k]);
+            ok = fread(U[k].data(), sizeof(double), U[k].size(), f) == U[k].size();
+        }
+        core.resize((size_t)r[0] * r[1] * r[2]);
+        if (ok) ok = fread(core.data(), sizeof(double), core.size(), f) == core.size();
+    }
+    fclose(f);
+    if (!ok) return fail(TK_EINVAL, "%s is not a valid result file", path);
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    tk_tucker* t = nullptr;
+    tk_status st = alloc_result(ctx, n, r, nullptr, &t);
+    if (st != TK_OK) return st;
+    for (int k = 0; k < 3; ++k) {
+        hipError_t e = hipMemcpy(t->U[k], U[k].data(), sizeof(double) * U[k].size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = launch_convert_f64_to_f32(t->U[k], t->U32[k], (long)U[k].size(), nullptr);
+        if (e != hipSuccess) { free_result(t); return fail(TK_EHIP, "load: %s", hipGetErrorString(e)); }
+    }
+    hipError_t e = hipMemcpy(t->core, core.data(), sizeof(double) * core.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_convert_f64_to_f32(t->core, t->core32, (long)core.size(), nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) { free_result(t); return fail(TK_EHIP, "load: %s", hipGetErrorString(e)); }
+    for (int k = 0; k < 3; ++k) t->b[k] = meta[k];
+    t->layout = hdr[7];
+    t->rel_err = meta[3];
+    t->norm_a = meta[4];
+    *out = t;
+    return TK_OK;
+}
+
+void tk_tucker_free(tk_tucker* t) { free_result(t); }
+
+tk_status tk_grid_eval(tk_ctx* ctx, const tk_kernel* kernel, const tk_grid* grid, int prec, void* A_dev,
+                       void* hip_stream)
+{
+    if (!ctx || !A_dev) return fail(TK_EINVAL, "NULL argument");
+    tk_status st;
+    if ((st = check_grid(grid)) != TK_OK) return st;
+    KernelParams kp{};
+    if ((st = check_kernel(kernel, &kp)) != TK_OK) return st;
+    if (prec < TK_FP64 || prec > TK_BF16X3) return fail(TK_EINVAL, "unknown precision %d", prec);
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    GridAxes ax = axes_of(grid);
+    if (prec == TK_FP64) TK_LAUNCH(launch_grid_eval_f64((double*)A_dev, ax, kp, (hipStream_t)hip_stream));
+    else TK_LAUNCH(launch_grid_eval_f32((float*)A_dev, ax, kp, (hipStream_t)hip_stream));
+    return TK_OK;
+}
+
+tk_status tk_gram(tk_ctx* ctx, const void* A_dev, const int n[3], int mode, int prec, double* G_dev, void* hip_stream)
+{
+    if (!ctx || !A_dev || !n || !G_dev) return fail(TK_EINVAL, "NULL argument");
+    if (mode < 0 || mode > 2) return fail(TK_EINVAL, "mode %d", mode);
+    if (prec < TK_FP64 || prec > TK_BF16X3) return fail(TK_EINVAL, "unknown precision %d", prec);
+    for (int k = 0; k < 3; ++k)
+        if (n[k] < 1 || n[k] > NMAX) return fail(TK_EINVAL, "n[%d]=%d", k, n[k]);
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    hipStream_t s = (hipStream_t)hip_stream;
+    size_t wb = gram_work_bytes(n, mode, prec);
+    Reservation res(ctx, wb);
+    if (!res.take()) return fail(TK_ENOMEM, "gram needs %zu bytes", wb);
+    void* work = nullptr;
+    TK_HIP(hipMallocAsync(&work, wb, s));
+    hipError_t e = launch_gram(A_dev, n, mode, prec, G_dev, work, s);
+    hipFreeAsync(work, s);
+    if (e != hipSuccess) return fail(TK_EHIP, "gram launch: %s", hipGetErrorString(e));
+    return TK_OK;
+}
+
+tk_status tk_eig_topr(tk_ctx* ctx, int count, int n, int r, const double* G_dev, double* lambda_dev, double* U_dev,
+                      void* hip_stream)
+{
+    if (!ctx || !G_dev || !lambda_dev || !U_dev) return fail(TK_EINVAL, "NULL argument");
+    if (count < 1 || n < 1 || n > NMAX || r < 1 || r > n) return fail(TK_EINVAL, "bad sizes");
+    if (r > LIB_RMAX) return fail(TK_EUNSUPPORTED, "r=%d exceeds %d", r, LIB_RMAX);
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    hipStream_t s = (hipStream_t)hip_stream;
+    int p = (n <= EIG_PMAX) ? n : std::min(r + 8, EIG_PMAX);
+    size_t need = sizeof(double) * (size_t)count * (2 * (size_t)n * p + 2 * (size_t)p * p + 64) + 4096;
+    Reservation res(ctx, need);
+    if (!res.take()) return fail(TK_ENOMEM, "eig needs %zu bytes", need);
+    void* base = nullptr;
+    TK_HIP(hipMallocAsync(&base, need, s));
+    Arena ar;
+    ar.base = (char*)base;
+    EigBatch b{};
+    b.count = count; b.n = n; b.p = p; b.r = r;
+    b.G = G_dev; b.sG = (long)n * n;
+    b.Q = ar.take<double>((size_t)count * n * p);
+    b.Y = ar.take<double>((size_t)count * n * p);
+    b.H = ar.take<double>((size_t)count * p * p);
+    b.Vs = ar.take<double>((size_t)count * p * p);
+    b.U = U_dev; b.sU = (long)n * r; b.ldu = r;
+    b.lam = lambda_dev; b.sL = r;
+    hipError_t e = launch_eig(b, COLD_ITERS, s);
+    hipFreeAsync(base, s);
+    if (e != hipSuccess) return fail(TK_EHIP, "eig launch: %s", hipGetErrorString(e));
+    return TK_OK;
+}
+
+}  // extern "C"

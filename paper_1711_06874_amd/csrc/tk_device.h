@@ -1,0 +1,73 @@
+// Device-side helpers shared by the gfx950 kernels of the Tucker engine.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// MFMA operand / result layouts used below (lane l of a 64-wide wave):
+//  mfma_f32_32x32x2f32 : A[i][k] at lane i + 32k, B[k][j] at lane j + 32k,
+//                        D[i][j] at lane j + 32((i/4)%2), register (i%4) + 4(i/8)
+//  mfma_f32_16x16x4f32 : A[i][k] at lane i + 16k, B[k][j] at lane j + 16k,
+//                        D[i][j] at lane j + 16(i/4), register i%4
+//  mfma_f64_16x16x4f64 : A[i][k] at lane i + 16k, B[k][j] at lane j + 16k,
+//                        D[i][j] at lane j + 16(i%4), register i/4
+//  mfma_f32_32x32x16_bf16: A[i][k] at lane i + 32(k/8), element k%8 (same for B[k][j] with j),
+//                        D as for 32x32x2
+//  mfma_f32_16x16x32_bf16: A[i][k] at lane i + 16(k/8), element k%8, D as for 16x16x4 f32
+
+// Covariance families (values match the public tk_family enum).
+enum { FAM_MATERN = 0, FAM_SLATER = 1, FAM_GAUSS = 2 };
+
+struct KernelParams {
+    int family;
+    int half;          // Matern: nu = half + 1/2 (0, 1, 2)
+    double inv_len;    // Matern: sqrt(2 nu)/ell ; Slater/Gauss: 1/ell
+    double sigma2;
+    double alpha;
+    double p;
+};
+
+// Covariance value at distance r, evaluated in double from the closed forms
+//   Matern nu=1/2: e^{-s},  nu=3/2: (1+s)e^{-s},  nu=5/2: (1 + s + s^2/3)e^{-s},  s = sqrt(2nu) r/ell
+//   Slater: exp(-alpha (r/ell)^p),  Gauss: exp(-(r/ell)^2)
+__device__ __forceinline__ double cov_value(const KernelParams& kp, double r)
+{
+    double v;
+    if (kp.family == FAM_MATERN) {
+        double s = r * kp.inv_len;
+        double poly = (kp.half == 0) ? 1.0 : (kp.half == 1) ? (1.0 + s) : (1.0 + s + s * s * (1.0 / 3.0));
+        v = poly * exp(-s);
+    } else if (kp.family == FAM_SLATER) {
+        double t = r * kp.inv_len;
+        double tp = (kp.p == 1.0) ? t : ((t == 0.0) ? 0.0 : pow(t, kp.p));
+        v = exp(-kp.alpha * tp);
+    } else {
+        double t = r * kp.inv_len;
+        v = exp(-(t * t));
+    }
+    return kp.sigma2 * v;
+}
+
+// Wave-level sum (64 lanes) of a double.
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ float wave_sumf(float v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Split a float into bf16 high and low parts: x ~ hi + lo with |x - hi - lo| <~ 2^-16 |x|.
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo)
+{
+    hi = (__bf16)x;
+    lo = (__bf16)(x - (float)hi);
+}

@@ -1,0 +1,131 @@
+// Host-side launch interface of the gfx950 kernels (one translation unit per kernel family).
+// Every launcher enqueues on `s` and returns hipSuccess or the launch error; shapes are
+// checked by the callers in tk_api.cpp before anything is launched.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "tk_device.h"
+
+namespace tk {
+
+// ---------------------------------------------------------------- a1: grid evaluation ----
+struct GridAxes {
+    int n[3];
+    double x0[3];   // first node
+    double h[3];    // spacing
+};
+hipError_t launch_grid_eval_f32(float* A, const GridAxes& g, const KernelParams& kp, hipStream_t s);
+hipError_t launch_grid_eval_f64(double* A, const GridAxes& g, const KernelParams& kp, hipStream_t s);
+
+// ----------------------------------------------------------------- a2: Gram (SYRK) ----
+// G (n_mode x n_mode, double, full) = A_(mode) A_(mode)^T.  `work` must hold
+// gram_work_bytes(...) bytes.
+size_t gram_work_bytes(const int n[3], int mode, int prec);
+hipError_t launch_gram(const void* A, const int n[3], int mode, int prec, double* G, void* work,
+                       hipStream_t s);
+
+// ------------------------------------------------------------ small dense products ----
+// C[b](m,n) = alpha * sum_k A[b](m,k) B[b](k,n) + beta * C[b](m,n) with arbitrary element
+// strides, FP64 accumulation.  TA/TB/TC in {float, double}.
+struct GemmArgs {
+    int M, N, K, batch;
+    int reduce_batch;   // 1: C = alpha * sum_b A[b] B[b] + beta * C (one output, no C stride)
+    const void* A; long sAb, sAm, sAk;
+    const void* B; long sBb, sBk, sBn;
+    void* C;       long sCb, sCm, sCn;
+    double alpha, beta;
+};
+template <typename TA, typename TB, typename TC>
+hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
+
+// ------------------------------------------------------------- a3: eigensolver ----
+// `count` problems of equal size: leading r eigenpairs of symmetric n x n matrices G
+// (row-major, problem stride sG), with a working block of p columns (r <= p <= min(n, 56)).
+// Workspaces (contiguous per problem): Q, Y: n x p; H: p x p; Vs: p x r.
+// warm (optional): n x rw start vectors per problem (ld ldw, stride sW).
+// Outputs: U (n x r per problem, ld ldu, stride sU), lam (r per problem, stride sL),
+// trace (optional, trace(G), stride sTrace).
+constexpr int EIG_PMAX = 56;
+struct EigBatch {
+    int count, n, p, r, rw, ldw;
+    const double* G; long sG;
+    const double* warm; long sW;
+    double* Q; double* Y; double* H; double* Vs;
+    double* U; long sU; int ldu;
+    double* lam; long sL;
+    double* trace; long sTrace;
+};
+hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s);
+hipError_t eig_set_attributes();
+
+// ------------------------------------------------------------------- a5/a6: TTM ----
+// T[row, c] = sum_k A[row, k] U[k, c]   (A x_3 U^T): A rows x n2, U n2 x r, T rows x r
+hipError_t launch_ttm_last_f32(const float* A, long rows, int n2, const float* U, int r, float* T,
+                               hipStream_t s);
+// S[a, col] = sum_i U[i, a] A[i, col]   (A x_1 U^T): A n0 x cols, U n0 x r, S r x cols
+hipError_t launch_ttm_first_f32(const float* A, int n0, long cols, const float* U, int r, float* S,
+                                hipStream_t s);
+
+// ------------------------------------------------------------------ a7: error norm ----
+// partials[2b] = sum (A - H U3^T)^2, partials[2b+1] = sum A^2 over work-group b's rows;
+// H: rows x r, U3: n2 x r.  recon_diff_parts(rows) work-groups.
+int recon_diff_parts(long rows);
+hipError_t launch_recon_diff_f32(const float* A, long rows, int n2, const double* H, const double* U3,
+                                 int r, double* partials, hipStream_t s);
+// partials[2b] = sum (X - Y)^2, partials[2b+1] = sum X^2 (grid-stride, nparts work-groups)
+template <typename T>
+hipError_t launch_diff_norm(const T* X, const T* Y, long n, double* partials, int nparts,
+                            hipStream_t s);
+hipError_t launch_reduce_partials(const double* partials, int nparts, int width, double* out,
+                                  hipStream_t s);
+
+// --------------------------------------------------------------- conversions/misc ----
+hipError_t launch_convert_f64_to_f32(const double* x, float* y, long n, hipStream_t s);
+hipError_t launch_convert_f32_to_f64(const float* x, double* y, long n, hipStream_t s);
+hipError_t launch_fill_f64(double* x, double v, long n, hipStream_t s);
+// out[0] = sum x*y (FP64 accumulation, deterministic two-level reduction)
+template <typename T>
+hipError_t launch_dot(const T* x, const T* y, long n, double* partials, int nparts, double* out,
+                      hipStream_t s);
+
+// ----------------------------------------------------------- a8: Toeplitz products ----
+// left : Out[s][g][i'][n] (+)= sum_{b<nb} sum_{i<K} u_{g,b}[off + |i' - i|] In[s][g][b][i][n]
+//        (i' < M, n < N; n contiguous in In and Out).  Generator u_{g,b}: element idx at
+//        gen[idx * gs_idx + (g * gstride_g + b * gstride_b) * gs_col], glen entries used.
+struct ToepLeftArgs {
+    int M, N, K, nb;
+    const void* gen; long gs_idx, gs_col, gstride_g, gstride_b; int glen, glen_pad, off;
+    const void* In; long sIs, sIg, sIb, sIi;
+    void* Out; long sOs, sOg, sOi;
+    int accumulate;
+};
+// right: Out[row][b*m + j'] = sum_{j<K} In[row][j] u_b[off + |j - j'|]   (row < R, j' < m)
+//        Generator u_b: element idx at gen[idx * gs_idx + b * gs_col].
+struct ToepRightArgs {
+    long R; int K, m, nb;
+    const void* gen; long gs_idx, gs_col; int glen, off;
+    const void* In; long ldi;
+    void* Out; long ldo;
+};
+template <typename T>
+hipError_t launch_toep_left(const ToepLeftArgs& a, int nslab, int ngroup, hipStream_t s);
+template <typename T>
+hipError_t launch_toep_right(const ToepRightArgs& a, hipStream_t s);
+hipError_t kron_set_attributes();
+
+// ------------------------------------------------------------ small scalar kernels ----
+hipError_t launch_rank_rule(const double* lam, long sLam, int len, int count, const double* total, long sTotal,
+                            const double* scal, int has_d2, double eps2, int* ranks, int* ok, hipStream_t s);
+hipError_t launch_trunc_err(const double* X, int R0, int R1, int R2, const int* ranks, double* out,
+                            hipStream_t s);
+template <typename TI, typename TO>
+hipError_t launch_copy_block(const TI* X, int D1, int D2, TO* Y, int d0, int d1, int d2, hipStream_t s);
+hipError_t launch_cov_trace(const double* G, int r0, int r1, int r2, const double* u0, const double* u1,
+                            const double* u2, double scale, double* out, hipStream_t s);
+hipError_t launch_final_err(double* scal, hipStream_t s);
+hipError_t launch_mask_rank(double* const U[3], const int n[3], const int R[3], double* core, const int* ranks,
+                            hipStream_t s);
+
+}  // namespace tk

@@ -1,0 +1,336 @@
+"""ctypes binding of libtk.so (the C ABI in include/tk.h).
+
+Argument marshalling only: every step runs in the HIP library.  Device buffers are passed as
+raw pointers (for example ``tensor.data_ptr()`` of a torch.cuda tensor) and streams as
+``hipStream_t`` handles (``torch.cuda.current_stream().cuda_stream``).  Importing this module
+fails loudly when the library has not been built; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtk.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1711_06874_amd.build` "
+                      "(the GPU path has no fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ----------------------------------------------------------------------------- constants
+TK_OK, TK_EINVAL, TK_EUNSUPPORTED, TK_ELAYOUT, TK_ENOMEM, TK_EHIP, TK_ENOCONV = 0, -1, -2, -3, -4, -5, -6
+TK_MATERN, TK_SLATER, TK_GAUSS = 0, 1, 2
+TK_CENTERED, TK_OFFSET = 0, 1
+TK_FP64, TK_FP32, TK_BF16X3 = 0, 1, 2
+
+
+class tk_kernel(ctypes.Structure):
+    _fields_ = [("family", ctypes.c_int), ("nu", ctypes.c_double), ("ell", ctypes.c_double),
+                ("sigma2", ctypes.c_double), ("alpha", ctypes.c_double), ("p", ctypes.c_double)]
+
+
+class tk_grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("b", ctypes.c_double * 3), ("layout", ctypes.c_int)]
+
+
+class tk_opts(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("ranks", ctypes.c_int * 3), ("r_max", ctypes.c_int),
+                ("hooi_sweeps", ctypes.c_int), ("prec", ctypes.c_int)]
+
+
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_st = ctypes.c_int
+
+_SIGS = {
+    "tk_ctx_create": (_st, [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_vp)]),
+    "tk_ctx_destroy": (None, [_vp]),
+    "tk_ctx_budget": (_st, [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+    "tk_estimate_bytes": (_st, [ctypes.POINTER(tk_grid), ctypes.POINTER(tk_opts), ctypes.POINTER(ctypes.c_size_t)]),
+    "tk_compress": (_st, [_vp, ctypes.POINTER(tk_kernel), ctypes.POINTER(tk_grid), ctypes.POINTER(tk_opts), _vp,
+                          ctypes.POINTER(_vp)]),
+    "tk_compress_tensor": (_st, [_vp, _vp, ctypes.POINTER(tk_grid), ctypes.POINTER(tk_opts), _vp,
+                                 ctypes.POINTER(_vp)]),
+    "tk_compress_batch": (_st, [_vp, ctypes.c_int, ctypes.POINTER(tk_kernel), ctypes.POINTER(tk_grid),
+                                ctypes.POINTER(tk_opts), _vp, ctypes.POINTER(_vp)]),
+    "tk_tucker_info": (_st, [_vp, _ip, _ip, _dp, _dp, _ip]),
+    "tk_tucker_get": (_st, [_vp, ctypes.POINTER(_dp), _dp]),
+    "tk_tucker_device": (_st, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "tk_reconstruct": (_st, [_vp, _vp, _vp, ctypes.c_int, _vp]),
+    "tk_tucker_save": (_st, [_vp, ctypes.c_char_p]),
+    "tk_tucker_load": (_st, [_vp, ctypes.c_char_p, ctypes.POINTER(_vp)]),
+    "tk_tucker_free": (None, [_vp]),
+    "tk_cov_dims": (_st, [_vp, _ip]),
+    "tk_kron_matvec": (_st, [_vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
+    "tk_trace": (_st, [_vp, _vp, _vp, _dp]),
+    "tk_quadratic_form": (_st, [_vp, _vp, _vp, ctypes.c_int, _vp, _dp, _vp]),
+    "tk_grid_eval": (_st, [_vp, ctypes.POINTER(tk_kernel), ctypes.POINTER(tk_grid), ctypes.c_int, _vp, _vp]),
+    "tk_gram": (_st, [_vp, _vp, _ip, ctypes.c_int, ctypes.c_int, _vp, _vp]),
+    "tk_eig_topr": (_st, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]),
+    "tk_last_error": (ctypes.c_char_p, []),
+    "tk_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "tk_version": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+class TkError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.tk_last_error().decode()
+        super().__init__(f"{where}: {_lib.tk_strerror(status).decode()} ({msg})")
+
+
+def _check(status: int, where: str, allow=()):
+    if status != TK_OK and status not in allow:
+        raise TkError(status, where)
+    return status
+
+
+def make_kernel(family=TK_MATERN, nu=0.5, ell=1.0, sigma2=1.0, alpha=1.0, p=1.0) -> tk_kernel:
+    return tk_kernel(int(family), float(nu), float(ell), float(sigma2), float(alpha), float(p))
+
+
+def make_grid(n, b=(1.0, 1.0, 1.0), layout=TK_CENTERED) -> tk_grid:
+    if np.isscalar(n):
+        n = (int(n),) * 3
+    if np.isscalar(b):
+        b = (float(b),) * 3
+    return tk_grid((ctypes.c_int * 3)(*[int(x) for x in n]), (ctypes.c_double * 3)(*[float(x) for x in b]),
+                   int(layout))
+
+
+def make_opts(eps=0.0, ranks=(0, 0, 0), r_max=0, hooi_sweeps=-1, prec=TK_FP32) -> tk_opts:
+    if np.isscalar(ranks):
+        ranks = (int(ranks),) * 3
+    return tk_opts(float(eps), (ctypes.c_int * 3)(*[int(x) for x in ranks]), int(r_max), int(hooi_sweeps),
+                   int(prec))
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return 0
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+# ------------------------------------------------------------------------ raw entry points
+def tk_version() -> str:
+    return _lib.tk_version().decode()
+
+
+def tk_ctx_create(device: int = 0, hbm_budget_bytes: int = 0) -> int:
+    out = _vp()
+    _check(_lib.tk_ctx_create(int(device), int(hbm_budget_bytes), ctypes.byref(out)), "tk_ctx_create")
+    return out.value
+
+
+def tk_ctx_destroy(ctx: int) -> None:
+    _lib.tk_ctx_destroy(ctx)
+
+
+def tk_ctx_budget(ctx: int):
+    b, u = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(_lib.tk_ctx_budget(ctx, ctypes.byref(b), ctypes.byref(u)), "tk_ctx_budget")
+    return b.value, u.value
+
+
+def tk_estimate_bytes(grid: tk_grid, opts: tk_opts) -> int:
+    out = ctypes.c_size_t()
+    _check(_lib.tk_estimate_bytes(ctypes.byref(grid), ctypes.byref(opts), ctypes.byref(out)), "tk_estimate_bytes")
+    return out.value
+
+
+def tk_compress(ctx: int, kernel: tk_kernel, grid: tk_grid, opts: tk_opts, stream=None, allow_noconv=False):
+    out = _vp()
+    st = _lib.tk_compress(ctx, ctypes.byref(kernel), ctypes.byref(grid), ctypes.byref(opts), _stream(stream),
+                          ctypes.byref(out))
+    _check(st, "tk_compress", allow=(TK_ENOCONV,) if allow_noconv else ())
+    return out.value
+
+
+def tk_compress_tensor(ctx: int, A, grid: tk_grid, opts: tk_opts, stream=None, allow_noconv=False):
+    out = _vp()
+    st = _lib.tk_compress_tensor(ctx, _ptr(A), ctypes.byref(grid), ctypes.byref(opts), _stream(stream),
+                                 ctypes.byref(out))
+    _check(st, "tk_compress_tensor", allow=(TK_ENOCONV,) if allow_noconv else ())
+    return out.value
+
+
+def tk_compress_batch(ctx: int, kernels, grids, opts: tk_opts, stream=None):
+    n = len(kernels)
+    ks = (tk_kernel * n)(*kernels)
+    gs = (tk_grid * n)(*grids)
+    outs = (_vp * n)()
+    _check(_lib.tk_compress_batch(ctx, n, ks, gs, ctypes.byref(opts), _stream(stream), outs), "tk_compress_batch")
+    return [o for o in outs]
+
+
+def tk_tucker_info(t: int):
+    n = (ctypes.c_int * 3)()
+    r = (ctypes.c_int * 3)()
+    e, na = ctypes.c_double(), ctypes.c_double()
+    lay = ctypes.c_int()
+    _check(_lib.tk_tucker_info(t, n, r, ctypes.byref(e), ctypes.byref(na), ctypes.byref(lay)), "tk_tucker_info")
+    return dict(n=tuple(n), ranks=tuple(r), rel_err=e.value, norm_a=na.value, layout=lay.value)
+
+
+def tk_tucker_get(t: int):
+    info = tk_tucker_info(t)
+    n, r = info["n"], info["ranks"]
+    U = [np.empty((n[k], r[k]), dtype=np.float64) for k in range(3)]
+    core = np.empty(r, dtype=np.float64)
+    ptrs = (_dp * 3)(*[u.ctypes.data_as(_dp) for u in U])
+    _check(_lib.tk_tucker_get(t, ptrs, core.ctypes.data_as(_dp)), "tk_tucker_get")
+    return U, core
+
+
+def tk_tucker_device(t: int):
+    U = (_vp * 3)()
+    c = _vp()
+    _check(_lib.tk_tucker_device(t, U, ctypes.byref(c)), "tk_tucker_device")
+    return [u for u in U], c.value
+
+
+def tk_reconstruct(ctx: int, t: int, A, io=TK_FP64, stream=None) -> None:
+    _check(_lib.tk_reconstruct(ctx, t, _ptr(A), int(io), _stream(stream)), "tk_reconstruct")
+
+
+def tk_tucker_save(t: int, path: str) -> None:
+    _check(_lib.tk_tucker_save(t, path.encode()), "tk_tucker_save")
+
+
+def tk_tucker_load(ctx: int, path: str) -> int:
+    out = _vp()
+    _check(_lib.tk_tucker_load(ctx, path.encode(), ctypes.byref(out)), "tk_tucker_load")
+    return out.value
+
+
+def tk_tucker_free(t: int) -> None:
+    if t:
+        _lib.tk_tucker_free(t)
+
+
+def tk_cov_dims(t: int):
+    m = (ctypes.c_int * 3)()
+    _check(_lib.tk_cov_dims(t, m), "tk_cov_dims")
+    return tuple(m)
+
+
+def tk_kron_matvec(ctx: int, t: int, z, y, io=TK_FP32, stream=None) -> None:
+    _check(_lib.tk_kron_matvec(ctx, t, _ptr(z), _ptr(y), int(io), _stream(stream)), "tk_kron_matvec")
+
+
+def tk_trace(ctx: int, t: int, stream=None) -> float:
+    out = ctypes.c_double()
+    _check(_lib.tk_trace(ctx, t, _stream(stream), ctypes.byref(out)), "tk_trace")
+    return out.value
+
+
+def tk_quadratic_form(ctx: int, t: int, z, io=TK_FP32, stream=None, y=None) -> float:
+    out = ctypes.c_double()
+    _check(_lib.tk_quadratic_form(ctx, t, _ptr(z), int(io), _stream(stream), ctypes.byref(out), _ptr(y)),
+           "tk_quadratic_form")
+    return out.value
+
+
+def tk_grid_eval(ctx: int, kernel: tk_kernel, grid: tk_grid, prec: int, A, stream=None) -> None:
+    _check(_lib.tk_grid_eval(ctx, ctypes.byref(kernel), ctypes.byref(grid), int(prec), _ptr(A), _stream(stream)),
+           "tk_grid_eval")
+
+
+def tk_gram(ctx: int, A, n, mode: int, prec: int, G, stream=None) -> None:
+    nn = (ctypes.c_int * 3)(*[int(x) for x in n])
+    _check(_lib.tk_gram(ctx, _ptr(A), nn, int(mode), int(prec), _ptr(G), _stream(stream)), "tk_gram")
+
+
+def tk_eig_topr(ctx: int, count: int, n: int, r: int, G, lam, U, stream=None) -> None:
+    _check(_lib.tk_eig_topr(ctx, int(count), int(n), int(r), _ptr(G), _ptr(lam), _ptr(U), _stream(stream)),
+           "tk_eig_topr")
+
+
+def tk_strerror(status: int) -> str:
+    return _lib.tk_strerror(int(status)).decode()
+
+
+def tk_last_error() -> str:
+    return _lib.tk_last_error().decode()
+
+
+# ------------------------------------------------------------------- convenience wrappers
+class Tucker:
+    """Owns one tk_tucker handle; frees it when garbage-collected."""
+
+    def __init__(self, handle: int, ctx: "Context"):
+        self.handle = handle
+        self.ctx = ctx
+        info = tk_tucker_info(handle)
+        self.n, self.ranks, self.rel_err, self.norm_a, self.layout = (
+            info["n"], info["ranks"], info["rel_err"], info["norm_a"], info["layout"])
+
+    def factors(self):
+        return tk_tucker_get(self.handle)
+
+    def cov_dims(self):
+        return tk_cov_dims(self.handle)
+
+    def free(self):
+        if self.handle:
+            tk_tucker_free(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.handle = tk_ctx_create(device, hbm_budget_bytes)
+
+    def compress(self, kernel, grid, opts, stream=None, allow_noconv=False) -> Tucker:
+        return Tucker(tk_compress(self.handle, kernel, grid, opts, stream, allow_noconv), self)
+
+    def compress_tensor(self, A, grid, opts, stream=None, allow_noconv=False) -> Tucker:
+        return Tucker(tk_compress_tensor(self.handle, A, grid, opts, stream, allow_noconv), self)
+
+    def compress_batch(self, kernels, grids, opts, stream=None):
+        return [Tucker(h, self) for h in tk_compress_batch(self.handle, kernels, grids, opts, stream)]
+
+    def kron_matvec(self, t: Tucker, z, y, io=TK_FP32, stream=None):
+        tk_kron_matvec(self.handle, t.handle, z, y, io, stream)
+
+    def trace(self, t: Tucker, stream=None) -> float:
+        return tk_trace(self.handle, t.handle, stream)
+
+    def quadratic_form(self, t: Tucker, z, io=TK_FP32, stream=None, y=None) -> float:
+        return tk_quadratic_form(self.handle, t.handle, z, io, stream, y)
+
+    def budget(self):
+        return tk_ctx_budget(self.handle)
+
+    def destroy(self):
+        if self.handle:
+            tk_ctx_destroy(self.handle)
+            self.handle = 0

@@ -1,0 +1,255 @@
+"""End-to-end parity of tk_compress / tk_kron_matvec / tk_trace / tk_quadratic_form against the
+FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import dev, host, require_gpu, say, to_oracle_tucker, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tk():
+    from paper_1711_06874_amd import tk as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def ctx(tk):
+    require_gpu()
+    c = tk.Context(0)
+    yield c
+    c.destroy()
+
+
+def _recon_host(U, core):
+    X = core
+    X = np.einsum("ia,abc->ibc", U[0], X)
+    X = np.einsum("jb,ibc->ijc", U[1], X)
+    X = np.einsum("kc,ijc->ijk", U[2], X)
+    return X
+
+
+# --------------------------------------------------------------- FP64: the plain method ----
+
+def test_c1_hosvd_error_curve_fp64(ctx, tk, oracle):
+    """Exponential kernel, 64^3 centred grid, HOSVD at ranks 1..16: the relative Frobenius
+    error per rank matches the oracle to 1e-10 where it is above the Gram route's FP64 floor."""
+    k, g, ranks = synth.c1_small()
+    ok = oracle.Kernel(k.family, nu=k.nu, ell=k.ell)
+    og = oracle.Grid(n=g.n, b=g.b, layout=g.layout)
+    A = oracle.grid_eval(ok, og)
+    f = oracle.hosvd_factors(A)
+    kern = tk.make_kernel(k.family, nu=k.nu, ell=k.ell)
+    grid = tk.make_grid(g.n, g.b, g.layout)
+    for r in ranks:
+        say("C1 rank", r)
+        t = ctx.compress(kern, grid, tk.make_opts(ranks=r, hooi_sweeps=0, prec=tk.TK_FP64))
+        ref = oracle.hosvd(A, (r, r, r), f)
+        lam = f[0][0]
+        gap = (lam[r - 1] - lam[r]) / lam[r - 1] if r < len(lam) else 1.0
+        if ref.rel_err >= 1e-7 and gap >= 1e-6:
+            assert t.rel_err == pytest.approx(ref.rel_err, rel=1e-10), (r, t.rel_err, ref.rel_err)
+            U, core = t.factors()
+            d = _recon_host(U, core) - oracle.reconstruct(ref.core, ref.U)
+            # the r-th factor column is fixed by the FP64 Gram only to u*lambda_1/gap; it enters
+            # the reconstruction weighted by sigma_r, hence u * sqrt(lambda_1/lambda_r) / gap
+            tol = max(1e-10, 100 * 2.2e-16 * np.sqrt(lam[0] / lam[r - 1]) / gap)
+            assert np.sqrt(np.sum(d * d) / np.sum(A * A)) <= tol, (r, tol)
+        else:
+            assert 0 <= t.rel_err <= 3e-8 and ref.rel_err <= 3e-8
+        t.free()
+
+
+@pytest.mark.parametrize("shape,ranks,sweeps", [((40, 36, 44), (3, 4, 5), 2), ((33, 65, 70), (6, 5, 7), 1)])
+def test_hooi_fp64_matches_oracle(ctx, tk, oracle, shape, ranks, sweeps):
+    ok = oracle.Kernel(oracle.MATERN, nu=1.5, ell=0.25)
+    og = oracle.Grid(n=shape, b=(1.0, 1.2, 0.9), layout=oracle.CENTERED)
+    ref = oracle.compress(ok, og, ranks=ranks, sweeps=sweeps)
+    t = ctx.compress(tk.make_kernel(0, nu=1.5, ell=0.25), tk.make_grid(shape, (1.0, 1.2, 0.9), 0),
+                     tk.make_opts(ranks=ranks, hooi_sweeps=sweeps, prec=tk.TK_FP64))
+    assert t.ranks == tuple(ranks)
+    assert t.rel_err == pytest.approx(ref.rel_err, rel=1e-10)
+    U, core = t.factors()
+    A = oracle.grid_eval(ok, og)
+    d = _recon_host(U, core) - oracle.reconstruct(ref.core, ref.U)
+    assert np.sqrt(np.sum(d * d) / np.sum(A * A)) <= 1e-10
+    # orthonormal factors, core = projection
+    for u in U:
+        assert np.abs(u.T @ u - np.eye(u.shape[1])).max() < 1e-12
+    np.testing.assert_allclose(core, oracle.project_core(A, U), rtol=0, atol=1e-12 * np.abs(core).max())
+
+
+def test_full_rank_is_exact_fp64(ctx, tk, oracle):
+    X = synth.random_tensor((7, 9, 8), 3)
+    t = ctx.compress_tensor(dev(X), tk.make_grid((7, 9, 8)), tk.make_opts(ranks=(7, 9, 8), hooi_sweeps=0,
+                                                                           prec=tk.TK_FP64))
+    assert t.rel_err <= 1e-13
+    U, core = t.factors()
+    np.testing.assert_allclose(_recon_host(U, core), X, atol=1e-12)
+
+
+def test_rank_clamped_to_n(ctx, tk):
+    X = synth.random_tensor((5, 6, 7), 4)
+    t = ctx.compress_tensor(dev(X), tk.make_grid((5, 6, 7)), tk.make_opts(ranks=(9, 9, 9), hooi_sweeps=0,
+                                                                           prec=tk.TK_FP64))
+    assert t.ranks == (5, 6, 7)
+    assert t.rel_err <= 1e-13
+
+
+def test_separable_gaussian_rank_one(ctx, tk):
+    for prec in (tk.TK_FP64, tk.TK_FP32):
+        t = ctx.compress(tk.make_kernel(2, ell=0.5), tk.make_grid((40, 50, 60)),
+                         tk.make_opts(ranks=1, hooi_sweeps=1, prec=prec))
+        assert t.rel_err <= (1e-12 if prec == tk.TK_FP64 else 3e-7)
+
+
+def test_fp64_eps_mode_ranks_match_oracle(ctx, tk, oracle):
+    ok = oracle.Kernel(oracle.MATERN, nu=0.5, ell=0.3)
+    og = oracle.Grid(n=(48, 48, 48))
+    for eps in (1e-3, 1e-5):
+        ref = oracle.compress(ok, og, eps=eps, sweeps=2)
+        t = ctx.compress(tk.make_kernel(0, nu=0.5, ell=0.3), tk.make_grid(48),
+                         tk.make_opts(eps=eps, hooi_sweeps=2, prec=tk.TK_FP64))
+        assert t.ranks == ref.ranks
+        assert t.rel_err == pytest.approx(ref.rel_err, rel=1e-9)
+        assert t.rel_err <= eps
+
+
+# -------------------------------------------------------------- FP32 / split precision ----
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("nu,ell,layout", [(0.5, 0.1, 1), (1.5, 0.2, 0), (2.5, 1.0, 1)])
+def test_eps_compress_split_precision(ctx, tk, oracle, prec, nu, ell, layout):
+    n = 72
+    say("eps compress", prec, nu, ell, layout)
+    ok = oracle.Kernel(oracle.MATERN, nu=nu, ell=ell)
+    og = oracle.Grid(n=(n, n, n), layout=layout)
+    eps = 1e-6
+    ref = oracle.compress(ok, og, eps=eps, sweeps=2)
+    t = ctx.compress(tk.make_kernel(0, nu=nu, ell=ell), tk.make_grid(n, 1.0, layout),
+                     tk.make_opts(eps=eps, hooi_sweeps=2, prec=prec))
+    say("  gpu ranks", t.ranks, "E %.3e" % t.rel_err, "oracle", ref.ranks, "E %.3e" % ref.rel_err)
+    assert t.rel_err <= eps
+    assert all(a <= b + 1 for a, b in zip(t.ranks, ref.ranks))
+    U, core = t.factors()
+    A = oracle.grid_eval(ok, og)
+    # the reported error is the measured one
+    d_true = _recon_host(U, core) - A
+    assert np.sqrt(np.sum(d_true ** 2) / np.sum(A ** 2)) == pytest.approx(t.rel_err, rel=2e-2, abs=2e-8)
+    d = _recon_host(U, core) - oracle.reconstruct(ref.core, ref.U)
+    assert np.sqrt(np.sum(d * d) / np.sum(A * A)) <= 1e-5
+
+
+def test_compress_deterministic(ctx, tk):
+    outs = []
+    for _ in range(2):
+        t = ctx.compress(tk.make_kernel(0, nu=1.5, ell=0.3), tk.make_grid(80, 1.0, 1), tk.make_opts(eps=1e-6))
+        outs.append(t.factors())
+    for k in range(3):
+        assert np.array_equal(outs[0][0][k], outs[1][0][k])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+# ----------------------------------------------------------------- covariance operator ----
+
+@pytest.mark.parametrize("layout,n", [(1, (6, 7, 5)), (0, (9, 7, 11)), (1, (20, 17, 24))])
+def test_matvec_fp64_exact_small(ctx, tk, oracle, layout, n):
+    ok = oracle.Kernel(oracle.MATERN, nu=1.5, ell=0.5)
+    og = oracle.Grid(n=n, layout=layout)
+    ranks = (3, 2, 4)
+    t = ctx.compress(tk.make_kernel(0, nu=1.5, ell=0.5), tk.make_grid(n, 1.0, layout),
+                     tk.make_opts(ranks=ranks, hooi_sweeps=1, prec=tk.TK_FP64))
+    U, core = t.factors()
+    to = to_oracle_tucker(oracle, U, core)
+    off, m = oracle.cov_offsets(og)
+    assert t.cov_dims() == tuple(m)
+    z = synth.normal_vector(m, 5).astype(np.float64)
+    y = torch.empty(m, dtype=torch.float64, device="cuda")
+    ctx.kron_matvec(t, dev(z), y, io=tk.TK_FP64)
+    want = oracle.cov_matvec(to, og, z)
+    np.testing.assert_allclose(host(y), want, rtol=0, atol=1e-12 * np.abs(want).max())
+    # trace and quadratic form
+    assert ctx.trace(t) == pytest.approx(oracle.cov_trace(to, og), rel=1e-12)
+    assert ctx.trace(t) == pytest.approx(oracle.cov_trace_kron(to, og), rel=1e-12)
+    q = ctx.quadratic_form(t, dev(z), io=tk.TK_FP64)
+    assert q == pytest.approx(float(np.dot(z.reshape(-1), want.reshape(-1))), rel=1e-11)
+
+
+def test_matvec_fp32_sampled(ctx, tk, oracle):
+    n = 96
+    og = oracle.Grid(n=(n, n, n), layout=oracle.OFFSET)
+    t = ctx.compress(tk.make_kernel(0, nu=0.5, ell=0.1), tk.make_grid(n, 1.0, 1), tk.make_opts(eps=1e-6))
+    U, core = t.factors()
+    to = to_oracle_tucker(oracle, U, core)
+    z = synth.normal_vector((n, n, n), 6)
+    zd = dev(z)
+    y = torch.empty_like(zd)
+    ctx.kron_matvec(t, zd, y, io=tk.TK_FP32)
+    got = host(y).reshape(-1)
+    rows = np.random.default_rng(1).choice(n ** 3, 48, replace=False)
+    want = oracle.cov_matvec_rows(to, og, z.astype(np.float64), rows)
+    Q = np.abs(oracle.reconstruct(to.core, to.U))
+    absz = np.abs(z.astype(np.float64))
+    # error bound: a few FP32 roundings of sum_j |C_ij z_j| per output
+    bound = oracle.cov_matvec_rows(to_oracle_tucker(oracle, [np.eye(n)] * 3, Q), og, absz, rows)
+    err = np.abs(got[rows] - want)
+    say("fp32 matvec max err/bound %.3e" % (err / bound).max())
+    assert np.all(err <= 2e-5 * bound)
+
+
+def test_covariance_errors(ctx, tk):
+    t = ctx.compress(tk.make_kernel(0, nu=0.5, ell=0.3), tk.make_grid(16), tk.make_opts(ranks=3, prec=tk.TK_FP64))
+    z = torch.zeros((16, 16, 16), dtype=torch.float64, device="cuda")
+    y = torch.zeros_like(z)
+    with pytest.raises(tk.TkError) as ei:
+        ctx.kron_matvec(t, z, y, io=tk.TK_FP64)
+    assert "TK_ELAYOUT" in str(ei.value)
+    with pytest.raises(tk.TkError):
+        ctx.trace(t)
+    with pytest.raises(tk.TkError):
+        tk.tk_kron_matvec(ctx.handle, t.handle, z, z, tk.TK_FP64)
+
+
+def test_argument_errors(ctx, tk):
+    with pytest.raises(tk.TkError) as ei:
+        ctx.compress(tk.make_kernel(0, nu=0.7, ell=0.3), tk.make_grid(16), tk.make_opts(eps=1e-6))
+    assert "TK_EUNSUPPORTED" in str(ei.value)
+    for bad in (dict(ell=-1.0), dict(ell=float("nan")), dict(sigma2=0.0)):
+        kw = dict(family=0, nu=0.5, ell=0.3)
+        kw.update(bad)
+        with pytest.raises(tk.TkError) as ei:
+            ctx.compress(tk.make_kernel(**kw), tk.make_grid(16), tk.make_opts(eps=1e-6))
+        assert "TK_EINVAL" in str(ei.value)
+
+
+def test_budget_exhaustion_is_reported(ctx, tk):
+    small = tk.Context(0, hbm_budget_bytes=1 << 20)
+    with pytest.raises(tk.TkError) as ei:
+        small.compress(tk.make_kernel(0, nu=0.5, ell=0.3), tk.make_grid(64), tk.make_opts(eps=1e-6))
+    assert "TK_ENOMEM" in str(ei.value)
+    assert small.budget()[1] == 0
+    small.destroy()
+
+
+def test_noconv_when_rmax_too_small(ctx, tk):
+    with pytest.raises(tk.TkError) as ei:
+        ctx.compress(tk.make_kernel(0, nu=0.5, ell=0.05), tk.make_grid(64), tk.make_opts(eps=1e-9, r_max=3))
+    assert "TK_ENOCONV" in str(ei.value)
+    t = ctx.compress(tk.make_kernel(0, nu=0.5, ell=0.05), tk.make_grid(64), tk.make_opts(eps=1e-9, r_max=3),
+                     allow_noconv=True)
+    assert t.ranks == (3, 3, 3) and t.rel_err > 1e-9
+
+
+def test_save_load_roundtrip(ctx, tk, tmp_path):
+    t = ctx.compress(tk.make_kernel(0, nu=1.5, ell=0.3), tk.make_grid(30, 1.0, 1), tk.make_opts(ranks=4))
+    p = str(tmp_path / "t.tkt")
+    tk.tk_tucker_save(t.handle, p)
+    h = tk.tk_tucker_load(ctx.handle, p)
+    t2 = tk.Tucker(h, ctx)
+    a, b = t.factors(), t2.factors()
+    for k in range(3):
+        assert np.array_equal(a[0][k], b[0][k])
+    assert np.array_equal(a[1], b[1])
+    assert t2.rel_err == t.rel_err and t2.layout == 1

@@ -1,0 +1,130 @@
+"""Per-kernel parity of the HIP path against the FP64 oracle (grid, Gram, eigensolver).
+
+Called through the C ABI.  Sizes span several 64-wide tiles with ragged tails."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import dev, host, require_gpu, say, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    require_gpu()
+    from paper_1711_06874_amd import tk
+    c = tk.Context(0)
+    yield c
+    c.destroy()
+
+
+@pytest.fixture(scope="module")
+def tk():
+    from paper_1711_06874_amd import tk as mod
+    return mod
+
+
+KERNELS = [
+    ("matern05", dict(family=0, nu=0.5, ell=0.3)),
+    ("matern15", dict(family=0, nu=1.5, ell=0.1, sigma2=2.0)),
+    ("matern25", dict(family=0, nu=2.5, ell=1.0)),
+    ("slater_p1", dict(family=1, alpha=1.0, p=1.0, ell=0.3)),
+    ("slater_p19", dict(family=1, alpha=0.7, p=1.9, ell=0.5)),
+    ("gauss", dict(family=2, ell=0.6)),
+]
+
+
+@pytest.mark.parametrize("name,kw", KERNELS)
+@pytest.mark.parametrize("layout", [0, 1])
+def test_grid_eval(ctx, tk, oracle, name, kw, layout):
+    n = (37, 70, 67)
+    b = (1.0, 0.8, 1.3)
+    say("grid_eval", name, layout, n)
+    A = oracle.grid_eval(oracle.Kernel(**kw), oracle.Grid(n=n, b=b, layout=layout))
+    k = tk.make_kernel(**kw)
+    g = tk.make_grid(n, b, layout)
+    d64 = torch.empty(n, dtype=torch.float64, device="cuda")
+    tk.tk_grid_eval(ctx.handle, k, g, tk.TK_FP64, d64)
+    got = host(d64)
+    np.testing.assert_allclose(got, A, rtol=2e-14, atol=1e-300)
+    d32 = torch.empty(n, dtype=torch.float32, device="cuda")
+    tk.tk_grid_eval(ctx.handle, k, g, tk.TK_FP32, d32)
+    g32 = host(d32)
+    ref32 = A.astype(np.float32)
+    # rounded once from double: at most one unit in the last place from the oracle rounded
+    ulp = np.spacing(np.abs(ref32))
+    assert np.all(np.abs(g32.astype(np.float64) - ref32.astype(np.float64)) <= ulp)
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 64), (70, 33, 129), (5, 7, 200)])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_gram(ctx, tk, oracle, shape, prec):
+    say("gram", shape, prec)
+    X = synth.random_tensor(shape, 21) + 0.5
+    if prec != 0:
+        X = X.astype(np.float32).astype(np.float64)   # the GPU sees exactly these floats
+    Xd = dev(X, np.float64 if prec == 0 else np.float32)
+    for mode in range(3):
+        G = torch.empty((shape[mode], shape[mode]), dtype=torch.float64, device="cuda")
+        tk.tk_gram(ctx.handle, Xd, shape, mode, prec, G)
+        got = host(G)
+        ref = oracle.gram(X, mode)
+        scale = np.abs(ref).max()
+        tol = {0: 1e-13, 1: 1e-5, 2: 6e-5}[prec]
+        err = np.abs(got - ref).max() / scale
+        say("  mode", mode, "rel err %.2e" % err)
+        assert err <= tol
+        assert np.array_equal(got, got.T)          # mirrored exactly
+
+
+def test_gram_deterministic(ctx, tk):
+    X = dev(synth.random_tensor((96, 80, 72), 5), np.float32)
+    outs = []
+    for _ in range(2):
+        G = torch.empty((80, 80), dtype=torch.float64, device="cuda")
+        tk.tk_gram(ctx.handle, X, (96, 80, 72), 1, tk.TK_FP32, G)
+        outs.append(host(G))
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("n,r", [(40, 6), (64, 16), (100, 12), (256, 24), (300, 48)])
+def test_eig_topr(ctx, tk, oracle, n, r):
+    say("eig", n, r)
+    A = oracle.grid_eval(oracle.Kernel(oracle.MATERN, nu=0.5, ell=0.2),
+                         oracle.Grid(n=(n, 24, 20), layout=oracle.OFFSET))
+    G = oracle.gram(A, 0)
+    lam_o, V_o, _ = oracle.jacobi_eig(G)
+    Gd = dev(G)
+    lam = torch.empty(r, dtype=torch.float64, device="cuda")
+    U = torch.empty((n, r), dtype=torch.float64, device="cuda")
+    tk.tk_eig_topr(ctx.handle, 1, n, r, Gd, lam, U)
+    lam_g, U_g = host(lam), host(U)
+    l1 = lam_o[0]
+    np.testing.assert_allclose(lam_g, lam_o[:r], rtol=0, atol=1e-13 * l1)
+    assert np.abs(U_g.T @ U_g - np.eye(r)).max() < 1e-12
+    assert np.abs(G @ U_g - U_g * lam_g).max() <= 1e-12 * l1
+    # eigenvectors that the FP64 Gram determines (gap >> u * lambda_1) match the oracle's
+    for j in range(r):
+        gap = min(abs(lam_o[j] - lam_o[j - 1]) if j > 0 else np.inf, abs(lam_o[j] - lam_o[j + 1]))
+        bound = 1e-14 * l1 / gap * 50 + 1e-13
+        if bound < 1e-4:
+            assert np.abs(U_g[:, j] - V_o[:, j]).max() <= bound, (j, gap / l1)
+
+
+def test_eig_batched_matches_single(ctx, tk, oracle):
+    n, r = 96, 10
+    Gs = []
+    for i, ell in enumerate((0.1, 0.3, 1.0)):
+        A = oracle.grid_eval(oracle.Kernel(oracle.MATERN, nu=1.5, ell=ell), oracle.Grid(n=(n, 20, 20)))
+        Gs.append(oracle.gram(A, 0))
+    Gd = dev(np.stack(Gs))
+    lam = torch.empty((3, r), dtype=torch.float64, device="cuda")
+    U = torch.empty((3, n, r), dtype=torch.float64, device="cuda")
+    tk.tk_eig_topr(ctx.handle, 3, n, r, Gd, lam, U)
+    lb, Ub = host(lam), host(U)
+    for i in range(3):
+        lam1 = torch.empty(r, dtype=torch.float64, device="cuda")
+        U1 = torch.empty((n, r), dtype=torch.float64, device="cuda")
+        tk.tk_eig_topr(ctx.handle, 1, n, r, dev(Gs[i]), lam1, U1)
+        np.testing.assert_allclose(lb[i], host(lam1), rtol=0, atol=1e-13 * lb[i][0])
