@@ -212,8 +212,8 @@ static double fro_norm(const double *A, int n)
  * holds the matching unit eigenvectors in its columns, each signed so that its entry of
  * largest magnitude is positive (entries within 1e-10 relative of that maximum count as
  * ties, and the lowest index among them decides).
- * Stops when off(A) <= tol * ||S||_F or after max_sweeps sweeps; returns the number of
- * sweeps done (or -1 if it did not converge). */
+ * Stops when off(A) <= max(tol, n u) * ||S||_F (u = 2^-52) or after max_sweeps sweeps;
+ * returns the number of sweeps done (or -1 if it did not converge). */
 int tko_jacobi_eig(int n, const double *S, double *lambda, double *V, int max_sweeps, double tol)
 {
     int m = n + (n & 1);                    /* round-robin needs an even player count */
@@ -226,6 +226,9 @@ int tko_jacobi_eig(int n, const double *S, double *lambda, double *V, int max_sw
     memset(W, 0, sizeof(double) * (size_t)n * n);
     for (int i = 0; i < n; ++i) W[(size_t)i * n + i] = 1.0;
 
+    /* off(A) cannot be driven much below n u ||A||_F in floating point (each rotation leaves
+     * O(u) residue in the rows it touches), so the tolerance is never set below that level */
+    if (tol < (double)n * 2.220446049250313e-16) tol = (double)n * 2.220446049250313e-16;
     double fnorm = fro_norm(A, n);
     int sweeps = 0, converged = 0;
     if (n == 1 || off_norm(A, n) <= tol * fnorm) converged = 1;
