@@ -1,0 +1,227 @@
+"""Benchmark: Tucker-compressed Matern grids per second at n = 256^3, eps = 1e-6 (one MI355X).
+
+One step = the whole path over one batch: for each of the 9 Matern covariances
+(nu in {1/2, 3/2, 5/2} x ell in {0.1, 0.3, 1.0}, sigma2 = 1) sampled on the 256^3 offset grid of
+[-1, 1]^3 (h = 2/255): tk_compress (grid evaluation, three Gram contractions, eigensolves,
+2 HOOI sweeps, core, error norm, eps truncation), then tk_quadratic_form with a seeded N(0,1)
+FP32 vector (the Kronecker-Toeplitz covariance matvec y = C z, returned, and z^T y), then
+tk_trace.  Inputs (the z vectors) are resident in HBM before the timed region.
+
+Prints one JSON line (see the keys below).  --gpus N with N > 1 exits: this build runs on one
+GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"hbm_GBs": 8000.0, "fp32_mfma_TFs": 157.3, "fp64_mfma_TFs": 78.6, "bf16_mfma_TFs": 2516.6}
+
+
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=float), q)) if xs else None
+
+
+def kernel_source_hash(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_1711_06874_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(n, rows_sample, seed_stream):
+    """Time the FP64 oracle on a bounded sample of the same workload: one 256^3 compress
+    (Matern 1/2, ell = 0.1, eps = 1e-6, 2 HOOI sweeps) plus `rows_sample` rows of the plain
+    covariance product; the matvec time is extrapolated to all n^3 rows."""
+    import numpy as np
+    from oracle import oracle as o
+    import synth
+    o.build()
+    k = o.Kernel(o.MATERN, nu=0.5, ell=0.1)
+    g = o.Grid(n=(n, n, n), layout=o.OFFSET)
+    t0 = time.perf_counter()
+    t = o.compress(k, g, eps=1e-6, sweeps=2)
+    t1 = time.perf_counter()
+    z = synth.normal_vector((n, n, n), seed_stream).astype(np.float64)
+    rows = (np.arange(rows_sample, dtype=np.int64) * 1000003) % (n ** 3)
+    t2 = time.perf_counter()
+    o.cov_matvec_rows(t, g, z, rows)
+    t3 = time.perf_counter()
+    per_row = (t3 - t2) / rows_sample
+    grid_s = (t1 - t0) + per_row * n ** 3
+    return {
+        "value": 1.0 / grid_s, "unit": "grids/s", "cores": o.num_threads(), "kind": "oracle",
+        "sample": (f"one {n}^3 Matern nu=1/2 ell=0.1 compress (eps 1e-6, 2 HOOI sweeps) = {t1 - t0:.2f} s, "
+                   f"plus {rows_sample} rows of the plain covariance product ({per_row * 1e3:.1f} ms/row) "
+                   f"extrapolated to all {n ** 3} rows"),
+        "compress_s": t1 - t0, "matvec_row_s": per_row,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--prec", choices=["fp32", "bf16x3"], default="fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=128)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run 5 plain device-to-device copies of BYTES bytes (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        x = torch.ones(args.calibrate_copy // 4, dtype=torch.float32, device="cuda")
+        yb = torch.empty_like(x)
+        for _ in range(5):
+            yb.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy}))
+        return
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    from paper_1711_06874_amd import tk
+
+    torch.cuda.set_device(0)
+    n = args.n
+    prec = tk.TK_FP32 if args.prec == "fp32" else tk.TK_BF16X3
+    ctx = tk.Context(0)
+    kernels = synth.c2_kernels(include_slater=False)
+    tkernels = [tk.make_kernel(k.family, nu=k.nu, ell=k.ell, sigma2=k.sigma2) for k in kernels]
+    grid = tk.make_grid(n, 1.0, tk.TK_OFFSET)
+    opts = tk.make_opts(eps=1e-6, hooi_sweeps=2, prec=prec)
+    zs = [torch.from_numpy(synth.normal_vector((n, n, n), i + 1)).cuda() for i in range(len(kernels))]
+    y = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    lat = {"compress": [], "matvec_quadform": [], "trace": []}
+    ranks_seen = []
+
+    def step(record):
+        for i, k in enumerate(tkernels):
+            t0 = time.perf_counter()
+            t = ctx.compress(k, grid, opts, stream)
+            t1 = time.perf_counter()
+            ctx.quadratic_form(t, zs[i], io=tk.TK_FP32, stream=stream, y=y)
+            t2 = time.perf_counter()
+            ctx.trace(t, stream)
+            t3 = time.perf_counter()
+            if record:
+                lat["compress"].append((t1 - t0) * 1e3)
+                lat["matvec_quadform"].append((t2 - t1) * 1e3)
+                lat["trace"].append((t3 - t2) * 1e3)
+                ranks_seen.append((t.ranks, t.rel_err))
+            t.free()
+
+    for _ in range(args.warmup):
+        step(False)
+    tk.tk_profile_reset()
+    tk.tk_profile_enable(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    tk.tk_profile_enable(False)
+    elapsed = t_end - t_start
+    grids = len(tkernels) * args.steps
+    value = grids / elapsed
+
+    # ---- per-kernel-class timing (HIP events around each launch, same timed region)
+    prof = {}
+    for name, cls in tk.PROF_CLASSES.items():
+        launches, ms = tk.tk_profile_read(cls)
+        prof[name] = {"launches": launches, "ms": ms}
+    tk.tk_profile_reset()
+
+    # ---- algorithmic work of each class over the timed region
+    N = n ** 3
+    work = {k: 0.0 for k in prof}
+    for (r, _e) in ranks_seen:
+        r0, r1, r2 = r
+        work["grid"] += 4.0 * N                                   # bytes written (FP32)
+        work["gram"] += 3 * float(n) ** 3 * (n + 1)               # unique Gram entries x 2 flops
+        work["ttm"] += 0.0
+        work["toep_right"] += r0 * 2.0 * N * n * r1               # flops
+        work["toep_left"] += 2.0 * N * n * r0 + r0 * 2.0 * N * n * r1
+        work["norm"] += 4.0 * N                                   # bytes read
+    # TTM: every launch streams the 4 N-byte tensor once (its outputs are n^2 r floats)
+    work["ttm"] = 4.0 * N * prof["ttm"]["launches"]
+    work["norm"] = 4.0 * N * prof["norm"]["launches"]
+    bound = {"grid": ("hbm", "GB/s", PEAK["hbm_GBs"]), "gram": ("mfma", "TFLOP/s", PEAK["fp32_mfma_TFs"]),
+             "ttm": ("hbm", "GB/s", PEAK["hbm_GBs"]), "norm": ("hbm", "GB/s", PEAK["hbm_GBs"]),
+             "toep_right": ("mfma", "TFLOP/s", PEAK["fp32_mfma_TFs"]),
+             "toep_left": ("mfma", "TFLOP/s", PEAK["fp32_mfma_TFs"])}
+    if prec == tk.TK_BF16X3:
+        bound["gram"] = ("mfma", "TFLOP/s", PEAK["bf16_mfma_TFs"] / 3.0)
+    kernels_out = {}
+    for name, (b, unit, peak) in bound.items():
+        ms = prof[name]["ms"]
+        if ms <= 0:
+            continue
+        scale = 1e-9 if unit == "GB/s" else 1e-12
+        achieved = work[name] * scale / (ms * 1e-3)
+        kernels_out[name] = {"bound": b, "unit": unit, "ms_total": ms, "launches": prof[name]["launches"],
+                             "achieved": achieved, "peak": peak, "frac": achieved / peak}
+    for name in ("eig", "small"):
+        kernels_out[name] = {"bound": "latency", "ms_total": prof[name]["ms"], "launches": prof[name]["launches"]}
+    dom = max((k for k in kernels_out if "achieved" in kernels_out[k]), key=lambda k: kernels_out[k]["ms_total"])
+    d = kernels_out[dom]
+
+    # HBM traffic from rocprofv3 counters, valid only for the kernel source it was taken on
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tfile):
+        try:
+            tj = json.load(open(tfile))
+            ent = tj.get(dom)
+            if ent and ent.get("source_hash") == kernel_source_hash(ent["sources"]):
+                traffic = ent["bytes_per_launch"]
+        except Exception:
+            traffic = None
+
+    roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
+                "frac": d["frac"], "traffic": traffic}
+
+    out = {
+        "metric": "Tucker-compressed Matern grids/sec at n=256^3, eps=1e-6",
+        "value": value, "unit": "grids/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if prec == tk.TK_FP32 else "bf16x3+f32", "data": "synthetic",
+        "config": {"workload": f"9 Matern covariances (nu 1/2,3/2,5/2 x ell 0.1,0.3,1.0) on the {n}^3 offset grid "
+                               f"of [-1,1]^3: compress at eps 1e-6 with 2 HOOI sweeps, covariance matvec + "
+                               f"quadratic form with a seeded N(0,1) vector, trace",
+                   "n": n, "grids_per_step": len(tkernels), "eps": 1e-6, "hooi_sweeps": 2,
+                   "precision": args.prec},
+        "latency_ms": {k: {"p50": percentile(v, 50), "p99": percentile(v, 99)} for k, v in lat.items()},
+        "ranks": sorted(set(r for r, _ in ranks_seen)),
+        "max_rel_err": max(e for _, e in ranks_seen),
+        "roofline": roofline,
+        "kernels": kernels_out,
+    }
+    ctx.destroy()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_rows, 1)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -237,6 +237,20 @@ tk_status tk_gram(tk_ctx *ctx, const void *A_dev, const int n[3], int mode, int 
 tk_status tk_eig_topr(tk_ctx *ctx, int count, int n, int r, const double *G_dev,
                       double *lambda_dev, double *U_dev, void *hip_stream);
 
+/* ---------------------------------------------------------------------------------------- */
+/* Kernel timing                                                                              */
+/* ---------------------------------------------------------------------------------------- */
+/* When enabled, every launch of the classes below is bracketed by HIP events recorded on the
+ * stream it runs on (process-wide, all contexts).  tk_profile_read synchronises on the
+ * recorded events and returns the number of launches and their summed duration in ms. */
+typedef enum {
+    TK_PROF_GRID = 0, TK_PROF_GRAM = 1, TK_PROF_EIG = 2, TK_PROF_TTM = 3, TK_PROF_NORM = 4,
+    TK_PROF_TOEP_RIGHT = 5, TK_PROF_TOEP_LEFT = 6, TK_PROF_SMALL = 7, TK_PROF_COUNT = 8
+} tk_prof_class;
+tk_status tk_profile_enable(int on);
+tk_status tk_profile_reset(void);
+tk_status tk_profile_read(int cls, long long *launches, double *total_ms);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char *tk_last_error(void);
 

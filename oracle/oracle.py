@@ -347,11 +347,16 @@ def cov_offsets(g: Grid):
 def cov_matvec_rows(t: Tucker, g: Grid, z: np.ndarray, rows) -> np.ndarray:
     """y_i = sum_j C_ij z_j for the requested flat row indices, with the covariance generated
     by the reconstructed Tucker tensor: C_ij = A_(r)(off + |i - j|) (per axis)."""
+    return cov_rows_from_generator(reconstruct(t.core, t.U), g, z, rows)
+
+
+def cov_rows_from_generator(Q: np.ndarray, g: Grid, z: np.ndarray, rows) -> np.ndarray:
+    """y_i = sum_j Q(off + |i - j|) z_j (per-axis offsets) for a generator tensor Q."""
     om = cov_offsets(g)
     if om is None:
         raise ValueError("covariance operator needs an origin node (offset or odd centred grid)")
     off, m = om
-    Q = _f64(reconstruct(t.core, t.U))
+    Q = _f64(Q)
     z = _f64(z).reshape(-1)
     assert z.size == m[0] * m[1] * m[2]
     rows = np.ascontiguousarray(rows, dtype=np.int64)

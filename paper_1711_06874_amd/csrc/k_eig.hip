@@ -189,6 +189,8 @@ __global__ void __launch_bounds__(256) k_jacobi(const double* __restrict__ Hin, 
     if (lane == 0) red[wv] = s;
     __syncthreads();
     const double fro = sqrt((red[0] + red[1]) + (red[2] + red[3]));
+    // off(H) stalls near p u ||H||_F in floating point: never ask for less
+    tol = fmax(tol, (double)p * 2.220446049250313e-16);
     __syncthreads();
 
     for (int sweep = 0; sweep < max_sweeps && p > 1; ++sweep) {

@@ -68,6 +68,50 @@ struct Arena {
     }
 };
 
+// ---- kernel timing: events around launches of selected classes ----------------------------
+struct ProfRec {
+    int cls;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+std::atomic<bool> g_prof_on{false};
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t pool_event()
+{
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct ProfScope {
+    int cls;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    ProfScope(int c, hipStream_t st) : cls(c), s(st)
+    {
+        if (!g_prof_on.load()) return;
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        a = pool_event();
+        if (a) (void)hipEventRecord(a, s);
+    }
+    ~ProfScope()
+    {
+        if (!a) return;
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        hipEvent_t b = pool_event();
+        if (!b) return;
+        (void)hipEventRecord(b, s);
+        g_prof.push_back({cls, a, b});
+    }
+};
+
 }  // namespace
 
 struct tk_ctx {
@@ -334,7 +378,10 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
         b.lam = w.lam; b.sL = 64;
         b.trace = w.trace; b.sTrace = 1;
         // the eigensolver writes U after its last use of Y, so U may alias Y
-        TK_LAUNCH(launch_eig(b, COLD_ITERS, s));
+        {
+            ProfScope ps(TK_PROF_EIG, s);
+            TK_LAUNCH(launch_eig(b, COLD_ITERS, s));
+        }
         for (int k = 0; k < 3; ++k)
             TK_HIP(hipMemcpyAsync(w.U[k], w.Y + (long)k * P.n[0] * P.R[0], sizeof(double) * P.n[0] * P.R[0],
                                   hipMemcpyDeviceToDevice, s));
@@ -347,6 +394,7 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
             b.U = w.U[k]; b.sU = 0; b.ldu = P.R[k];
             b.lam = w.lam + 64 * k; b.sL = 64;
             b.trace = w.trace + k; b.sTrace = 1;
+            ProfScope ps(TK_PROF_EIG, s);
             TK_LAUNCH(launch_eig(b, COLD_ITERS, s));
         }
     }
@@ -365,7 +413,10 @@ tk_status eig_update(const Plan& P, Work& w, int k, const double* Gs, hipStream_
     b.sU = 0; b.ldu = P.R[k];
     b.lam = w.lam + 64 * k; b.sL = 64;
     b.trace = nullptr;
-    TK_LAUNCH(launch_eig(b, WARM_ITERS, s));
+    {
+        ProfScope ps(TK_PROF_EIG, s);
+        TK_LAUNCH(launch_eig(b, WARM_ITERS, s));
+    }
     TK_HIP(hipMemcpyAsync(w.U[k], b.U, sizeof(double) * P.n[k] * P.R[k], hipMemcpyDeviceToDevice, s));
     return TK_OK;
 }
@@ -382,6 +433,7 @@ template <typename Real>
 tk_status ttm_last(const Plan& P, Work& w, const Real* A, hipStream_t s)
 {
     long rows = (long)P.n[0] * P.n[1];
+    ProfScope ps(TK_PROF_TTM, s);
     if (sizeof(Real) == 4) {
         TK_LAUNCH(launch_ttm_last_f32((const float*)A, rows, P.n[2], w.U32[2], P.R[2], (float*)w.T, s));
     } else {
@@ -396,6 +448,7 @@ template <typename Real>
 tk_status ttm_first(const Plan& P, Work& w, const Real* A, hipStream_t s)
 {
     long cols = (long)P.n[1] * P.n[2];
+    ProfScope ps(TK_PROF_TTM, s);
     if (sizeof(Real) == 4) {
         TK_LAUNCH(launch_ttm_first_f32((const float*)A, P.n[0], cols, w.U32[0], P.R[0], (float*)w.S, s));
     } else {
@@ -508,6 +561,7 @@ tk_status recon_norm(const Plan& P, Work& w, const Real* A, double* const Uf[3],
         TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
     }
     long rows = (long)n0 * n1;
+    ProfScope ps(TK_PROF_NORM, s);
     if (sizeof(Real) == 4) {
         int parts = recon_diff_parts(rows);
         TK_LAUNCH(launch_recon_diff_f32((const float*)A, rows, n2, w.Hrec, Uf[2], R2, w.partials, s));
@@ -671,12 +725,15 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kp, const void* A_in, c
 
     if (own_A) {
         GridAxes ax = axes_of(grid);
+        ProfScope ps(TK_PROF_GRID, s);
         if (sizeof(Real) == 4) TK_LAUNCH(launch_grid_eval_f32((float*)w.A, ax, *kp, s));
         else TK_LAUNCH(launch_grid_eval_f64((double*)w.A, ax, *kp, s));
     }
     // ---- HOSVD: Grams and leading eigenvectors
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 3; ++k) {
+        ProfScope ps(TK_PROF_GRAM, s);
         TK_LAUNCH(launch_gram(A, P.n, k, P.prec, w.G + (long)k * nmax * nmax, w.gram_work, s));
+    }
     if ((st = eig_modes(P, w, nmax, s)) != TK_OK) return st;
 
     if (P.eps_mode && P.prec == TK_FP64) {
@@ -846,6 +903,7 @@ tk_status matvec_impl(tk_ctx* ctx, const tk_tucker* t, const T* z, T* y, hipStre
         a.In = z; a.sIs = 0; a.sIg = 0; a.sIb = 0; a.sIi = (long)m[1] * m[2];
         a.Out = Z1; a.sOs = 0; a.sOg = M3; a.sOi = (long)m[1] * m[2];
         a.accumulate = 0;
+        ProfScope ps(TK_PROF_TOEP_LEFT, s);
         TK_LAUNCH(launch_toep_left<T>(a, 1, r0, s));
     }
     for (int a0 = 0; a0 < r0; ++a0) {
@@ -855,7 +913,10 @@ tk_status matvec_impl(tk_ctx* ctx, const tk_tucker* t, const T* z, T* y, hipStre
         rr.gen = W + (long)a0 * r1 * t->n[2]; rr.gs_idx = 1; rr.gs_col = t->n[2]; rr.glen = t->n[2]; rr.off = off[2];
         rr.In = Z1 + (long)a0 * M3; rr.ldi = m[2];
         rr.Out = Pb; rr.ldo = (long)r1 * m[2];
-        TK_LAUNCH(launch_toep_right<T>(rr, s));
+        {
+            ProfScope ps(TK_PROF_TOEP_RIGHT, s);
+            TK_LAUNCH(launch_toep_right<T>(rr, s));
+        }
         // y[i0][i1'][:] (+)= sum_b sum_i1 T(U2[:, b])[i1'][i1] P[i0][i1][b][:]
         ToepLeftArgs l{};
         l.M = m[1]; l.N = m[2]; l.K = m[1]; l.nb = r1;
@@ -864,6 +925,7 @@ tk_status matvec_impl(tk_ctx* ctx, const tk_tucker* t, const T* z, T* y, hipStre
         l.In = Pb; l.sIs = (long)m[1] * r1 * m[2]; l.sIg = 0; l.sIb = m[2]; l.sIi = (long)r1 * m[2];
         l.Out = y; l.sOs = (long)m[1] * m[2]; l.sOg = 0; l.sOi = m[2];
         l.accumulate = a0 > 0;
+        ProfScope ps(TK_PROF_TOEP_LEFT, s);
         TK_LAUNCH(launch_toep_left<T>(l, m[0], 1, s));
     }
     if (dot_out) {
@@ -882,6 +944,43 @@ tk_status matvec_impl(tk_ctx* ctx, const tk_tucker* t, const T* z, T* y, hipStre
 extern "C" {
 
 const char* tk_version(void) { return "tk-mi355x 0.1 (gfx950)"; }
+
+tk_status tk_profile_enable(int on)
+{
+    g_prof_on.store(on != 0);
+    return TK_OK;
+}
+
+tk_status tk_profile_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto& r : g_prof) {
+        (void)hipEventSynchronize(r.b);
+        g_event_pool.push_back(r.a);
+        g_event_pool.push_back(r.b);
+    }
+    g_prof.clear();
+    return TK_OK;
+}
+
+tk_status tk_profile_read(int cls, long long* launches, double* total_ms)
+{
+    if (cls < 0 || cls >= TK_PROF_COUNT || !launches || !total_ms) return fail(TK_EINVAL, "bad profile query");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    long long n = 0;
+    double ms = 0.0;
+    for (auto& r : g_prof) {
+        if (r.cls != cls) continue;
+        TK_HIP(hipEventSynchronize(r.b));
+        float t = 0.f;
+        TK_HIP(hipEventElapsedTime(&t, r.a, r.b));
+        ms += t;
+        ++n;
+    }
+    *launches = n;
+    *total_ms = ms;
+    return TK_OK;
+}
 
 const char* tk_last_error(void) { return g_last_error.c_str(); }
 

@@ -72,6 +72,9 @@ _SIGS = {
     "tk_grid_eval": (_st, [_vp, ctypes.POINTER(tk_kernel), ctypes.POINTER(tk_grid), ctypes.c_int, _vp, _vp]),
     "tk_gram": (_st, [_vp, _vp, _ip, ctypes.c_int, ctypes.c_int, _vp, _vp]),
     "tk_eig_topr": (_st, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]),
+    "tk_profile_enable": (_st, [ctypes.c_int]),
+    "tk_profile_reset": (_st, []),
+    "tk_profile_read": (_st, [ctypes.c_int, ctypes.POINTER(ctypes.c_longlong), _dp]),
     "tk_last_error": (ctypes.c_char_p, []),
     "tk_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "tk_version": (ctypes.c_char_p, []),
@@ -266,6 +269,25 @@ def tk_gram(ctx: int, A, n, mode: int, prec: int, G, stream=None) -> None:
 def tk_eig_topr(ctx: int, count: int, n: int, r: int, G, lam, U, stream=None) -> None:
     _check(_lib.tk_eig_topr(ctx, int(count), int(n), int(r), _ptr(G), _ptr(lam), _ptr(U), _stream(stream)),
            "tk_eig_topr")
+
+
+PROF_CLASSES = {"grid": 0, "gram": 1, "eig": 2, "ttm": 3, "norm": 4, "toep_right": 5, "toep_left": 6,
+                "small": 7}
+
+
+def tk_profile_enable(on: bool = True) -> None:
+    _check(_lib.tk_profile_enable(1 if on else 0), "tk_profile_enable")
+
+
+def tk_profile_reset() -> None:
+    _check(_lib.tk_profile_reset(), "tk_profile_reset")
+
+
+def tk_profile_read(cls: int):
+    n = ctypes.c_longlong()
+    ms = ctypes.c_double()
+    _check(_lib.tk_profile_read(int(cls), ctypes.byref(n), ctypes.byref(ms)), "tk_profile_read")
+    return n.value, ms.value
 
 
 def tk_strerror(status: int) -> str:

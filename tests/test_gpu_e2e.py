@@ -193,7 +193,7 @@ def test_matvec_fp32_sampled(ctx, tk, oracle):
     Q = np.abs(oracle.reconstruct(to.core, to.U))
     absz = np.abs(z.astype(np.float64))
     # error bound: a few FP32 roundings of sum_j |C_ij z_j| per output
-    bound = oracle.cov_matvec_rows(to_oracle_tucker(oracle, [np.eye(n)] * 3, Q), og, absz, rows)
+    bound = oracle.cov_rows_from_generator(Q, og, absz, rows)
     err = np.abs(got[rows] - want)
     say("fp32 matvec max err/bound %.3e" % (err / bound).max())
     assert np.all(err <= 2e-5 * bound)
@@ -253,3 +253,47 @@ def test_save_load_roundtrip(ctx, tk, tmp_path):
         assert np.array_equal(a[0][k], b[0][k])
     assert np.array_equal(a[1], b[1])
     assert t2.rel_err == t.rel_err and t2.layout == 1
+
+
+# ------------------------------------------------- full size, in the benchmark's launch setup ----
+
+@pytest.mark.parametrize("nu,ell", [(0.5, 0.1), (2.5, 1.0)])
+def test_bench_configuration_256(ctx, tk, oracle, nu, ell):
+    """256^3 offset grid, eps 1e-6, 2 HOOI sweeps, FP32 -- exactly what bench.py times -- on
+    sampled outputs: error <= eps, ranks within one of the oracle's, reconstruction and
+    covariance matvec rows against the FP64 oracle."""
+    n, eps = 256, 1e-6
+    og = oracle.Grid(n=(n, n, n), layout=oracle.OFFSET)
+    ok = oracle.Kernel(oracle.MATERN, nu=nu, ell=ell)
+    say("full size", nu, ell)
+    stream = torch.cuda.current_stream()
+    t = ctx.compress(tk.make_kernel(0, nu=nu, ell=ell), tk.make_grid(n, 1.0, tk.TK_OFFSET),
+                     tk.make_opts(eps=eps, hooi_sweeps=2, prec=tk.TK_FP32), stream)
+    ref = oracle.compress(ok, og, eps=eps, sweeps=2)
+    say("  gpu", t.ranks, "%.3e" % t.rel_err, "oracle", ref.ranks, "%.3e" % ref.rel_err)
+    assert t.rel_err <= eps
+    assert all(a <= b + 1 for a, b in zip(t.ranks, ref.ranks))
+    U, core = t.factors()
+    rng = np.random.default_rng(7)
+    idx = rng.integers(0, n, size=(4096, 3))
+    def at(Uf, G):
+        return np.einsum("sa,sb,sc,abc->s", Uf[0][idx[:, 0]], Uf[1][idx[:, 1]], Uf[2][idx[:, 2]], G)
+    A_s = np.array([oracle.kernel_value(ok, np.sqrt(np.sum((2.0 / (n - 1) * i) ** 2))) for i in idx])
+    d = at(U, core) - at(ref.U, ref.core)
+    assert np.sqrt(np.mean(d * d)) / np.sqrt(np.mean(A_s * A_s)) <= 1e-5
+    # covariance matvec through the quadratic form (as timed), sampled rows
+    z = synth.normal_vector((n, n, n), 1)
+    zd = dev(z)
+    y = torch.empty_like(zd)
+    q = ctx.quadratic_form(t, zd, io=tk.TK_FP32, stream=stream, y=y)
+    got = host(y).reshape(-1)
+    rows = rng.choice(n ** 3, 24, replace=False)
+    to = to_oracle_tucker(oracle, U, core)
+    Q = oracle.reconstruct(to.core, to.U)
+    want = oracle.cov_rows_from_generator(Q, og, z.astype(np.float64), rows)
+    bound = oracle.cov_rows_from_generator(np.abs(Q), og, np.abs(z.astype(np.float64)), rows)
+    say("  matvec max err/bound %.3e" % (np.abs(got[rows] - want) / bound).max())
+    assert np.all(np.abs(got[rows] - want) <= 2e-5 * bound)
+    assert q == pytest.approx(float(np.dot(z.reshape(-1).astype(np.float64), got.astype(np.float64))), rel=1e-6)
+    tr = ctx.trace(t)
+    assert tr == pytest.approx(oracle.cov_trace_kron(to, og), rel=1e-12)
