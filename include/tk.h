@@ -204,6 +204,16 @@ tk_status tk_cov_dims(const tk_tucker *t, int m[3]);
 tk_status tk_kron_matvec(tk_ctx *ctx, const tk_tucker *t, const void *z_dev, void *y_dev,
                          int io, void *hip_stream);
 
+/* Matvec algorithm of a context: TK_MV_AUTO (default: the FFT form for io = TK_FP32, dense
+ * Toeplitz mode products for TK_FP64), TK_MV_FFT (FP32 only), TK_MV_DENSE.
+ * FFT form: every Toeplitz factor embeds in a circulant of length L >= 2m - 1 (Sec. 3.6:
+ * O(n log n) Toeplitz products), so C = P F^-H diag(chat) F P^T with F the 3-D DFT and chat
+ * the Tucker tensor with DFT'd, circulant-embedded factors; five FP32 FFT passes.
+ * Dense form: r1 + 2 r1 r2 mode products with the Toeplitz matrices on MFMA.
+ * Errors: TK_EINVAL. */
+typedef enum { TK_MV_AUTO = 0, TK_MV_FFT = 1, TK_MV_DENSE = 2 } tk_matvec_method;
+tk_status tk_set_matvec_method(tk_ctx *ctx, int method);
+
 /* trace(C) = sum_abc G_abc prod_k trace T(U_k[off_k:, .]) = m1 m2 m3 * A_r(origin)
  * (Sec. 4 eq. (4.3) and the value-at-origin form that follows it).  Computed on the device
  * in FP64; synchronising (one scalar read). */
@@ -245,7 +255,8 @@ tk_status tk_eig_topr(tk_ctx *ctx, int count, int n, int r, const double *G_dev,
  * recorded events and returns the number of launches and their summed duration in ms. */
 typedef enum {
     TK_PROF_GRID = 0, TK_PROF_GRAM = 1, TK_PROF_EIG = 2, TK_PROF_TTM = 3, TK_PROF_NORM = 4,
-    TK_PROF_TOEP_RIGHT = 5, TK_PROF_TOEP_LEFT = 6, TK_PROF_SMALL = 7, TK_PROF_COUNT = 8
+    TK_PROF_TOEP_RIGHT = 5, TK_PROF_TOEP_LEFT = 6, TK_PROF_SMALL = 7, TK_PROF_FFT = 8,
+    TK_PROF_COUNT = 9
 } tk_prof_class;
 tk_status tk_profile_enable(int on);
 tk_status tk_profile_reset(void);

@@ -50,98 +50,111 @@ __global__ void k_eig_init(EigBatch b)
 
 // Householder QR of the n x p matrix In (row-major, ld p) of problem blockIdx.x; writes the
 // explicit orthonormal factor (n x p) to Out.  W is the working copy (LDS if it fits).
+//
+// Per column j three barrier-separated phases, with no integer division in any loop:
+//   A: finish column j-1 (scale its reflector below the diagonal, store beta on it) and form
+//      ||W[j+1:, j]||^2;
+//   B: every thread derives (tau, scale, beta) of column j from the reduction, and the groups
+//      form w_c = v^T W[j:, c] for c > j from the *unscaled* column (w_c = W[j][c] + scale *
+//      sum_{i>j} W[i][j] W[i][c]), so column j is not touched in this phase;
+//   C: W[i][c] -= tau v_i w_c for i >= j, c > j (one column per thread, rows strided).
+// The explicit Q is then formed in place from the last reflector to the first.
 __global__ void __launch_bounds__(256) k_hqr(const double* __restrict__ In, double* __restrict__ Out,
                                              int n, int p, int in_lds)
 {
     extern __shared__ double smem[];
     __shared__ double red[4];
     __shared__ double wsum[64];
-    __shared__ double tau[64];
-    __shared__ double bcast[2];
+    __shared__ double tau_s[64];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const long off = (long)blockIdx.x * n * p;
     double* W = in_lds ? smem : (Out + off);
-    for (long e = tid; e < (long)n * p; e += 256) W[e] = In[off + e];
+    for (int e = tid; e < n * p; e += 256) W[e] = In[off + e];
     __syncthreads();
 
-    // ---- factorisation: column j -> (tau_j, v_j below the diagonal, beta_j on it)
+    double prev_scale = 0.0, prev_beta = 0.0, prev_tau = 0.0;
     for (int j = 0; j < p; ++j) {
+        // ---- phase A
+        if (j > 0) {
+            if (prev_tau != 0.0)
+                for (int i = j + tid; i < n; i += 256) W[i * p + (j - 1)] *= prev_scale;
+            if (tid == 0) W[(j - 1) * p + (j - 1)] = prev_beta;
+        }
         double s = 0.0;
-        for (int i = j + 1 + tid; i < n; i += 256) { double x = W[(long)i * p + j]; s += x * x; }
+        for (int i = j + 1 + tid; i < n; i += 256) { double x = W[i * p + j]; s += x * x; }
         s = wave_sum(s);
         if (lane == 0) red[wv] = s;
         __syncthreads();
-        if (tid == 0) {
-            double xn2 = (red[0] + red[1]) + (red[2] + red[3]);
-            double alpha = W[(long)j * p + j];
-            double t = 0.0, scale = 0.0, beta = alpha;
-            if (xn2 > 0.0) {
-                double nrm = sqrt(alpha * alpha + xn2);
-                beta = (alpha >= 0.0) ? -nrm : nrm;
-                t = (beta - alpha) / beta;
-                scale = 1.0 / (alpha - beta);
-            }
-            tau[j] = t;
-            bcast[0] = scale;
-            bcast[1] = beta;
+        // ---- phase B
+        const double xn2 = (red[0] + red[1]) + (red[2] + red[3]);
+        const double alpha = W[j * p + j];
+        double t = 0.0, scale = 0.0, beta = alpha;
+        if (xn2 > 0.0) {
+            double nrm = sqrt(alpha * alpha + xn2);
+            beta = (alpha >= 0.0) ? -nrm : nrm;
+            t = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
         }
-        __syncthreads();
-        const double t = tau[j], scale = bcast[0];
-        if (t != 0.0)
-            for (int i = j + 1 + tid; i < n; i += 256) W[(long)i * p + j] *= scale;
-        __syncthreads();
-        if (tid == 0) W[(long)j * p + j] = bcast[1];
+        if (tid == 0) tau_s[j] = t;
         const int nc = p - j - 1;
+        int G = 64;
+        while (G > 1 && G * nc > 256) G >>= 1;
         if (t != 0.0 && nc > 0) {
-            // w_c = v^T W[j:, c] for c in (j, p), v_j = 1
-            int G = 64;
-            while (G > 1 && G * nc > 256) G >>= 1;
-            int gid = tid / G, gl = tid % G;
+            const int gid = tid / G, gl = tid & (G - 1);
             double acc = 0.0;
             if (gid < nc) {
-                int c = j + 1 + gid;
-                for (int i = j + gl; i < n; i += G) {
-                    double v = (i == j) ? 1.0 : W[(long)i * p + j];
-                    acc += v * W[(long)i * p + c];
-                }
+                const int c = j + 1 + gid;
+                for (int i = j + 1 + gl; i < n; i += G) acc += W[i * p + j] * W[i * p + c];
             }
             for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-            if (gid < nc && gl == 0) wsum[gid] = acc;
-            __syncthreads();
-            long cnt = (long)(n - j) * nc;
-            for (long e = tid; e < cnt; e += 256) {
-                int i = j + (int)(e / nc), c = j + 1 + (int)(e % nc);
-                double v = (i == j) ? 1.0 : W[(long)i * p + j];
-                W[(long)i * p + c] -= t * v * wsum[c - j - 1];
+            if (gid < nc && gl == 0) wsum[gid] = W[j * p + j + 1 + gid] + scale * acc;
+        }
+        __syncthreads();
+        // ---- phase C
+        if (t != 0.0 && nc > 0) {
+            const int per = 256 / nc;             // threads per column
+            const int cc = tid % nc, r0 = tid / nc;
+            if (r0 < per) {
+                const int c = j + 1 + cc;
+                const double tw = t * wsum[cc];
+                if (r0 == 0) W[j * p + c] -= tw;
+                for (int i = j + 1 + r0; i < n; i += per) W[i * p + c] -= tw * scale * W[i * p + j];
             }
         }
         __syncthreads();
+        prev_scale = scale;
+        prev_beta = beta;
+        prev_tau = t;
     }
+    // finish the last column
+    if (prev_tau != 0.0)
+        for (int i = p + tid; i < n; i += 256) W[i * p + (p - 1)] *= prev_scale;
+    if (tid == 0) W[(p - 1) * p + (p - 1)] = prev_beta;
+    __syncthreads();
 
     // ---- explicit Q, built in place from the last reflector to the first
     for (int j = p - 1; j >= 0; --j) {
-        const double t = tau[j];
+        const double t = tau_s[j];
         const int nc = p - j - 1;
         if (nc > 0 && t != 0.0) {
             int G = 64;
             while (G > 1 && G * nc > 256) G >>= 1;
-            int gid = tid / G, gl = tid % G;
+            const int gid = tid / G, gl = tid & (G - 1);
             double acc = 0.0;
             if (gid < nc) {
-                int c = j + 1 + gid;
-                for (int i = j + gl; i < n; i += G) {
-                    double v = (i == j) ? 1.0 : W[(long)i * p + j];
-                    acc += v * W[(long)i * p + c];
-                }
+                const int c = j + 1 + gid;
+                for (int i = j + 1 + gl; i < n; i += G) acc += W[i * p + j] * W[i * p + c];
             }
             for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-            if (gid < nc && gl == 0) wsum[gid] = acc;
+            if (gid < nc && gl == 0) wsum[gid] = W[j * p + j + 1 + gid] + acc;
             __syncthreads();
-            long cnt = (long)(n - j) * nc;
-            for (long e = tid; e < cnt; e += 256) {
-                int i = j + (int)(e / nc), c = j + 1 + (int)(e % nc);
-                double v = (i == j) ? 1.0 : W[(long)i * p + j];
-                W[(long)i * p + c] -= t * v * wsum[c - j - 1];
+            const int per = 256 / nc;
+            const int cc = tid % nc, r0 = tid / nc;
+            if (r0 < per) {
+                const int c = j + 1 + cc;
+                const double tw = t * wsum[cc];
+                if (r0 == 0) W[j * p + c] -= tw;
+                for (int i = j + 1 + r0; i < n; i += per) W[i * p + c] -= tw * W[i * p + j];
             }
             __syncthreads();
         }
@@ -150,13 +163,13 @@ __global__ void __launch_bounds__(256) k_hqr(const double* __restrict__ In, doub
             double x;
             if (i < j) x = 0.0;
             else if (i == j) x = 1.0 - t;
-            else x = -t * W[(long)i * p + j];
-            W[(long)i * p + j] = x;
+            else x = -t * W[i * p + j];
+            W[i * p + j] = x;
         }
         __syncthreads();
     }
     if (in_lds)
-        for (long e = tid; e < (long)n * p; e += 256) Out[off + e] = W[e];
+        for (int e = tid; e < n * p; e += 256) Out[off + e] = W[e];
 }
 
 // Two-sided Jacobi on the p x p symmetric H of problem blockIdx.x (row-major; symmetrised),
@@ -196,7 +209,9 @@ __global__ void __launch_bounds__(256) k_jacobi(const double* __restrict__ Hin, 
     for (int sweep = 0; sweep < max_sweeps && p > 1; ++sweep) {
         // off-diagonal norm
         double o = 0.0;
-        for (int e = tid; e < p * p; e += 256) { int i = e / p, j = e % p; if (i != j) o += H[i][j] * H[i][j]; }
+        if ((tid & 63) < p)
+            for (int i = tid >> 6; i < p; i += 4)
+                if (i != (tid & 63)) o += H[i][tid & 63] * H[i][tid & 63];
         o = wave_sum(o);
         if (lane == 0) red[wv] = o;
         __syncthreads();
@@ -223,32 +238,36 @@ __global__ void __launch_bounds__(256) k_jacobi(const double* __restrict__ Hin, 
                 pq[k][0] = a; pq[k][1] = bb; cs[k][0] = c; cs[k][1] = sn;
             }
             __syncthreads();
-            // rows: H <- J^T H ; V <- V J (columns of V)
+            // rows: H <- J^T H ; V <- V J (columns of V).  Thread (k0 = tid/64, j = tid%64)
+            // handles column j of pairs k0, k0 + 4, ...
             const int np = m / 2;
-            for (int e = tid; e < np * p; e += 256) {
-                int k = e / p, j = e % p;
-                int a = pq[k][0], bb = pq[k][1];
-                double sn = cs[k][1];
-                if (bb >= p || sn == 0.0) continue;
-                double c = cs[k][0];
-                double x = H[a][j], y = H[bb][j];
-                H[a][j] = c * x - sn * y;
-                H[bb][j] = sn * x + c * y;
-                double vx = V[j][a], vy = V[j][bb];
-                V[j][a] = c * vx - sn * vy;
-                V[j][bb] = sn * vx + c * vy;
+            const int jj = tid & 63, k0 = tid >> 6;
+            if (jj < p) {
+                for (int k = k0; k < np; k += 4) {
+                    int a = pq[k][0], bb = pq[k][1];
+                    double sn = cs[k][1];
+                    if (bb >= p || sn == 0.0) continue;
+                    double c = cs[k][0];
+                    double x = H[a][jj], y = H[bb][jj];
+                    H[a][jj] = c * x - sn * y;
+                    H[bb][jj] = sn * x + c * y;
+                    double vx = V[jj][a], vy = V[jj][bb];
+                    V[jj][a] = c * vx - sn * vy;
+                    V[jj][bb] = sn * vx + c * vy;
+                }
             }
             __syncthreads();
-            // columns: H <- H J
-            for (int e = tid; e < np * p; e += 256) {
-                int k = e / p, i = e % p;
-                int a = pq[k][0], bb = pq[k][1];
-                double sn = cs[k][1];
-                if (bb >= p || sn == 0.0) continue;
-                double c = cs[k][0];
-                double x = H[i][a], y = H[i][bb];
-                H[i][a] = c * x - sn * y;
-                H[i][bb] = sn * x + c * y;
+            // columns: H <- H J  (thread handles row jj)
+            if (jj < p) {
+                for (int k = k0; k < np; k += 4) {
+                    int a = pq[k][0], bb = pq[k][1];
+                    double sn = cs[k][1];
+                    if (bb >= p || sn == 0.0) continue;
+                    double c = cs[k][0];
+                    double x = H[jj][a], y = H[jj][bb];
+                    H[jj][a] = c * x - sn * y;
+                    H[jj][bb] = sn * x + c * y;
+                }
             }
             __syncthreads();
         }
@@ -348,7 +367,8 @@ hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s)
     gq.C = b.Y; gq.sCb = np_; gq.sCm = p; gq.sCn = 1;
     gq.alpha = 1.0; gq.beta = 0.0;
     if (p < n) {
-        if ((e = qr_launch(b.Q, b.Q, b.count, n, p, s)) != hipSuccess) return e;
+        const bool start_orthonormal = b.warm && b.rw == p;   // previous factor, no extra columns
+        if (!start_orthonormal && (e = qr_launch(b.Q, b.Q, b.count, n, p, s)) != hipSuccess) return e;
         for (int it = 0; it < iters; ++it) {
             if ((e = launch_gemm<double, double, double>(gq, s)) != hipSuccess) return e;
             if ((e = qr_launch(b.Y, b.Q, b.count, n, p, s)) != hipSuccess) return e;

@@ -239,25 +239,32 @@ __global__ void __launch_bounds__(NT) k_gram_tiles_bf16x3(const float* __restric
     }
 }
 
-// G[ti*64 + ii][tj*64 + jj] = sum_s P[pair][s][ii][jj] (FP64, split order); mirrored.
+// G[ti*64 + ii][tj*64 + jj] = sum_s P[pair][s][ii][jj] in FP64; mirrored.  Each entry is
+// summed by 4 threads (thread g takes splits g, g + 4, g + 8, ... in order) and the four
+// sums are added in the fixed order g = 0, 1, 2, 3, so the result does not depend on timing.
 template <typename T>
 __global__ void __launch_bounds__(256) k_gram_reduce(const T* __restrict__ partials, int T_tiles,
                                                      int nsplit, int nrow, double* __restrict__ G)
 {
-    int pidx = blockIdx.y;
+    __shared__ double part[4][64];
+    const int pidx = blockIdx.y;
     int ti, tj;
     pair_of(pidx, T_tiles, ti, tj);
-    int e = blockIdx.x * blockDim.x + threadIdx.x;   // entry within the tile
-    if (e >= BM * BM) return;
-    int ii = e / BM, jj = e % BM;
-    if (ti == tj && ii > jj) return;                  // diagonal tiles: upper half only
-    int gi = ti * BM + ii, gj = tj * BM + jj;
-    if (gi >= nrow || gj >= nrow) return;
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;             // entry within the tile
     const T* P = partials + (long)pidx * nsplit * (BM * BM) + e;
     double s = 0.0;
-    for (int q = 0; q < nsplit; ++q) s += (double)P[(long)q * (BM * BM)];
-    G[(long)gi * nrow + gj] = s;
-    G[(long)gj * nrow + gi] = s;
+    for (int q = g; q < nsplit; q += 4) s += (double)P[(long)q * (BM * BM)];
+    part[g][lane] = s;
+    __syncthreads();
+    if (g != 0) return;
+    const int ii = e / BM, jj = e % BM;
+    if (ti == tj && ii > jj) return;                  // diagonal tiles: upper half only
+    const int gi = ti * BM + ii, gj = tj * BM + jj;
+    if (gi >= nrow || gj >= nrow) return;
+    const double v = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+    G[(long)gi * nrow + gj] = v;
+    G[(long)gj * nrow + gi] = v;
 }
 
 struct GramPlan {
@@ -318,7 +325,7 @@ static hipError_t launch_mode(const void* A, const int n[3], int prec, double* G
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dim3 rgrid((BM * BM + 255) / 256, p.npairs);
+    dim3 rgrid(BM * BM / 64, p.npairs);
     if (prec == 0)
         hipLaunchKernelGGL(k_gram_reduce<double>, rgrid, dim3(256), 0, s, (const double*)work, p.T_tiles,
                            p.nsplit, p.nrow, G);

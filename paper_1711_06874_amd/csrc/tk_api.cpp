@@ -49,8 +49,10 @@ tk_status fail(tk_status s, const char* fmt, ...)
 constexpr int LIB_RMAX = 48;          // largest rank the kernels support
 constexpr int DEFAULT_RMAX = 24;      // eps mode working rank when r_max == 0
 constexpr int DEFAULT_SWEEPS = 2;
-constexpr int COLD_ITERS = 3;         // subspace iterations from a random start
-constexpr int WARM_ITERS = 2;         // ... from the previous factor
+constexpr int COLD_ITERS = 3;         // subspace iterations from a random start (FP64 path)
+constexpr int COLD_ITERS_F32 = 2;     // ... float paths (HOOI refines the subspaces anyway)
+constexpr int WARM_ITERS = 2;         // ... from the previous factor (FP64 path: exact HOOI steps)
+constexpr int WARM_ITERS_F32 = 1;     // ... float paths: one block power step per HOOI update
 constexpr int NMAX = 1024;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -116,6 +118,7 @@ struct ProfScope {
 
 struct tk_ctx {
     int device = 0;
+    int matvec_method = TK_MV_AUTO;
     size_t budget = 0;
     std::atomic<size_t> in_use{0};
     std::atomic<int> live_results{0};
@@ -380,7 +383,7 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
         // the eigensolver writes U after its last use of Y, so U may alias Y
         {
             ProfScope ps(TK_PROF_EIG, s);
-            TK_LAUNCH(launch_eig(b, COLD_ITERS, s));
+            TK_LAUNCH(launch_eig(b, P.prec == TK_FP64 ? COLD_ITERS : COLD_ITERS_F32, s));
         }
         for (int k = 0; k < 3; ++k)
             TK_HIP(hipMemcpyAsync(w.U[k], w.Y + (long)k * P.n[0] * P.R[0], sizeof(double) * P.n[0] * P.R[0],
@@ -395,7 +398,7 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
             b.lam = w.lam + 64 * k; b.sL = 64;
             b.trace = w.trace + k; b.sTrace = 1;
             ProfScope ps(TK_PROF_EIG, s);
-            TK_LAUNCH(launch_eig(b, COLD_ITERS, s));
+            TK_LAUNCH(launch_eig(b, P.prec == TK_FP64 ? COLD_ITERS : COLD_ITERS_F32, s));
         }
     }
     return TK_OK;
@@ -405,7 +408,11 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
 tk_status eig_update(const Plan& P, Work& w, int k, const double* Gs, hipStream_t s)
 {
     EigBatch b{};
-    b.count = 1; b.n = P.n[k]; b.p = P.p[k]; b.r = P.R[k];
+    // warm start from the current factor.  Float paths: the block is the factor itself
+    // (orthonormal, no QR) and one power step per HOOI update; FP64: oversampled block and
+    // converged eigenvectors, so every HOOI step is exact as in the oracle.
+    b.count = 1; b.n = P.n[k]; b.r = P.R[k];
+    b.p = (P.n[k] <= EIG_PMAX) ? P.n[k] : (P.prec == TK_FP64 ? P.p[k] : P.R[k]);
     b.rw = P.R[k]; b.ldw = P.R[k]; b.warm = w.U[k]; b.sW = 0;
     b.G = Gs; b.sG = 0;
     b.Q = w.Q; b.Y = w.Y; b.H = w.H; b.Vs = w.Vs;
@@ -415,7 +422,7 @@ tk_status eig_update(const Plan& P, Work& w, int k, const double* Gs, hipStream_
     b.trace = nullptr;
     {
         ProfScope ps(TK_PROF_EIG, s);
-        TK_LAUNCH(launch_eig(b, WARM_ITERS, s));
+        TK_LAUNCH(launch_eig(b, P.prec == TK_FP64 ? WARM_ITERS : WARM_ITERS_F32, s));
     }
     TK_HIP(hipMemcpyAsync(w.U[k], b.U, sizeof(double) * P.n[k] * P.R[k], hipMemcpyDeviceToDevice, s));
     return TK_OK;
@@ -936,6 +943,131 @@ tk_status matvec_impl(tk_ctx* ctx, const tk_tucker* t, const T* z, T* y, hipStre
     return TK_OK;
 }
 
+int next_pow2(int x)
+{
+    int L = 1;
+    while (L < x) L <<= 1;
+    return L;
+}
+
+int ilog2(int L)
+{
+    int l = 0;
+    while ((1 << l) < L) ++l;
+    return l;
+}
+
+// y = C z by the 3-D DFT (see k_fft.hip); FP32 data.
+tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, hipStream_t s, double* dot_out)
+{
+    int off[3], m[3];
+    if (!cov_geometry(t, off, m)) return fail(TK_ELAYOUT, "even-sized centred grid has no origin node");
+    const int r0 = t->r[0], r1 = t->r[1], r2 = t->r[2];
+    int L[3], lg[3];
+    for (int k = 0; k < 3; ++k) {
+        L[k] = next_pow2(std::max(2 * m[k] - 1, 2));
+        lg[k] = ilog2(L[k]);
+    }
+    const int H2 = L[2] / 2 + 1;
+    const long M3 = (long)m[0] * m[1] * m[2];
+    Arena plan;
+    auto lay = [&](Arena& ar, double** Uh0, double** Uh1, double** Uh2, double** M1, float** Hs, float** Uh3,
+                   float2** A1, float2** A2, double** dots, float2** tw) {
+        for (int k = 0; k < 3; ++k) tw[k] = ar.take<float2>((size_t)L[k]);
+        *Uh0 = ar.take<double>((size_t)L[0] * r0);
+        *Uh1 = ar.take<double>((size_t)L[1] * r1);
+        *Uh2 = ar.take<double>((size_t)H2 * r2);
+        *M1 = ar.take<double>((size_t)L[0] * r1 * r2);
+        *Hs = ar.take<float>((size_t)L[0] * L[1] * r2);
+        *Uh3 = ar.take<float>((size_t)H2 * r2);
+        *A1 = ar.take<float2>((size_t)m[0] * m[1] * H2);
+        *A2 = ar.take<float2>((size_t)m[0] * L[1] * H2);
+        *dots = ar.take<double>(2048);
+    };
+    double *Uh0, *Uh1, *Uh2, *M1, *dots;
+    float *Hs, *Uh3;
+    float2 *A1, *A2;
+    float2* tw[3];
+    lay(plan, &Uh0, &Uh1, &Uh2, &M1, &Hs, &Uh3, &A1, &A2, &dots, tw);
+    Reservation res(ctx, plan.off);
+    if (!res.take()) return fail(TK_ENOMEM, "matvec needs %zu bytes; budget %zu, in use %zu", plan.off, ctx->budget,
+                                 ctx->in_use.load());
+    void* base = nullptr;
+    hipError_t he = hipMallocAsync(&base, plan.off, s);
+    if (he != hipSuccess) return fail(TK_ENOMEM, "hipMallocAsync(%zu): %s", plan.off, hipGetErrorString(he));
+    struct Freer {
+        void* p;
+        hipStream_t s;
+        ~Freer() { if (p) (void)hipFreeAsync(p, s); }
+    } freer{base, s};
+    Arena ar;
+    ar.base = (char*)base;
+    lay(ar, &Uh0, &Uh1, &Uh2, &M1, &Hs, &Uh3, &A1, &A2, &dots, tw);
+    for (int k = 0; k < 3; ++k) TK_LAUNCH(launch_twiddles(tw[k], L[k], s));
+    {
+        ProfScope ps(TK_PROF_SMALL, s);
+        // Fourier-side factors and Hs[f0][f1][c] = sum_ab G_abc Uh1[f0][a] Uh2[f1][b]
+        TK_LAUNCH(launch_fourier_factor(t->U[0], r0, off[0], m[0], L[0], L[0], Uh0, s));
+        TK_LAUNCH(launch_fourier_factor(t->U[1], r1, off[1], m[1], L[1], L[1], Uh1, s));
+        TK_LAUNCH(launch_fourier_factor(t->U[2], r2, off[2], m[2], L[2], H2, Uh2, s));
+        GemmArgs g = gemm(L[0], r1 * r2, r0, 1, Uh0, 0, r0, 1, t->core, 0, (long)r1 * r2, 1, M1, 0, (long)r1 * r2, 1);
+        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+        GemmArgs g1 = gemm(L[1], r2, r1, L[0], Uh1, 0, r1, 1, M1, (long)r1 * r2, r2, 1, Hs, (long)L[1] * r2, r2, 1);
+        TK_LAUNCH((launch_gemm<double, double, float>(g1, s)));
+        TK_LAUNCH(launch_convert_f64_to_f32(Uh2, Uh3, (long)H2 * r2, s));
+    }
+    ProfScope ps(TK_PROF_FFT, s);
+    FftPassArgs a{};
+    // P1: axis 2 forward, real rows of m2 -> H2 complex
+    a = FftPassArgs{};
+    a.L = L[2]; a.logL = lg[2]; a.F = fft_fibres_per_block(L[2], 0);
+    a.n_inner = m[0] * m[1]; a.len_in = m[2]; a.len_out = H2;
+    a.s_in_o = 0; a.s_in_i = m[2]; a.s_in_k = 1; a.s_out_o = 0; a.s_out_i = H2; a.s_out_k = 1;
+    a.in = z; a.out = A1; a.in_real = 1; a.out_real = 0; a.mode = 0; a.scale = 1.f; a.tw = tw[2];
+    TK_LAUNCH(launch_fft_pass(a, 1, s));
+    // P2: axis 1 forward, fibres (i0, f2) over i1
+    a = FftPassArgs{};
+    a.L = L[1]; a.logL = lg[1]; a.F = fft_fibres_per_block(L[1], 0);
+    a.n_inner = H2; a.len_in = m[1]; a.len_out = L[1];
+    a.s_in_o = (long)m[1] * H2; a.s_in_i = 1; a.s_in_k = H2;
+    a.s_out_o = (long)L[1] * H2; a.s_out_i = 1; a.s_out_k = H2;
+    a.in = A1; a.out = A2; a.mode = 0; a.scale = 1.f; a.tw = tw[1];
+    TK_LAUNCH(launch_fft_pass(a, m[0], s));
+    // P3: axis 0 forward, times chat, inverse; fibres (f1, f2) over i0, in place
+    a = FftPassArgs{};
+    a.L = L[0]; a.logL = lg[0]; a.F = fft_fibres_per_block(L[0], r2);
+    a.n_inner = H2; a.len_in = m[0]; a.len_out = m[0];
+    a.s_in_o = H2; a.s_in_i = 1; a.s_in_k = (long)L[1] * H2;
+    a.s_out_o = H2; a.s_out_i = 1; a.s_out_k = (long)L[1] * H2;
+    a.in = A2; a.out = A2; a.mode = 3; a.scale = 1.f;
+    a.Hs = Hs; a.Uh3 = Uh3; a.r2 = r2; a.L1 = L[1]; a.tw = tw[0];
+    TK_LAUNCH(launch_fft_pass(a, L[1], s));
+    // P4: axis 1 inverse, keep i1 < m1
+    a = FftPassArgs{};
+    a.L = L[1]; a.logL = lg[1]; a.F = fft_fibres_per_block(L[1], 0);
+    a.n_inner = H2; a.len_in = L[1]; a.len_out = m[1];
+    a.s_in_o = (long)L[1] * H2; a.s_in_i = 1; a.s_in_k = H2;
+    a.s_out_o = (long)m[1] * H2; a.s_out_i = 1; a.s_out_k = H2;
+    a.in = A2; a.out = A1; a.mode = 1; a.scale = 1.f; a.tw = tw[1];
+    TK_LAUNCH(launch_fft_pass(a, m[0], s));
+    // P5: axis 2 inverse from the half spectrum, real part, keep i2 < m2, scale
+    a = FftPassArgs{};
+    a.L = L[2]; a.logL = lg[2]; a.F = fft_fibres_per_block(L[2], 0);
+    a.n_inner = m[0] * m[1]; a.len_in = H2; a.len_out = m[2];
+    a.s_in_o = 0; a.s_in_i = H2; a.s_in_k = 1; a.s_out_o = 0; a.s_out_i = m[2]; a.s_out_k = 1;
+    a.in = A1; a.out = y; a.out_real = 1; a.mode = 2; a.tw = tw[2];
+    a.scale = (float)(1.0 / ((double)L[0] * L[1] * L[2]));
+    TK_LAUNCH(launch_fft_pass(a, 1, s));
+    if (dot_out) {
+        TK_LAUNCH(launch_dot<float>(z, y, M3, dots, 1024, dots + 1024, s));
+        TK_HIP(hipMemcpyAsync(dot_out, dots + 1024, sizeof(double), hipMemcpyDeviceToHost, s));
+        TK_HIP(hipStreamSynchronize(s));
+    }
+    return TK_OK;
+}
+
+bool use_fft(const tk_ctx* ctx, int io) { return io == TK_FP32 && ctx->matvec_method != TK_MV_DENSE; }
+
 }  // namespace
 
 // ==========================================================================================
@@ -1014,6 +1146,7 @@ tk_status tk_ctx_create(int device, size_t hbm_budget_bytes, tk_ctx** out)
     TK_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
     TK_HIP(eig_set_attributes());
     TK_HIP(kron_set_attributes());
+    TK_HIP(fft_set_attributes());
     tk_ctx* c = new (std::nothrow) tk_ctx();
     if (!c) return fail(TK_ENOMEM, "host allocation failed");
     c->device = device;
@@ -1028,6 +1161,13 @@ void tk_ctx_destroy(tk_ctx* ctx)
     hipSetDevice(ctx->device);
     hipDeviceSynchronize();
     delete ctx;
+}
+
+tk_status tk_set_matvec_method(tk_ctx* ctx, int method)
+{
+    if (!ctx || method < TK_MV_AUTO || method > TK_MV_DENSE) return fail(TK_EINVAL, "bad matvec method");
+    ctx->matvec_method = method;
+    return TK_OK;
 }
 
 tk_status tk_ctx_budget(const tk_ctx* ctx, size_t* budget_bytes, size_t* in_use_bytes)
@@ -1166,6 +1306,9 @@ tk_status tk_kron_matvec(tk_ctx* ctx, const tk_tucker* t, const void* z_dev, voi
     if (io != TK_FP64 && io != TK_FP32) return fail(TK_EINVAL, "io must be TK_FP64 or TK_FP32");
     TK_HIP(hipSetDevice(ctx->device));
     (void)hipGetLastError();
+    if (io == TK_FP64 && ctx->matvec_method == TK_MV_FFT) return fail(TK_EINVAL, "the FFT matvec is FP32 only");
+    if (use_fft(ctx, io))
+        return matvec_fft(ctx, t, (const float*)z_dev, (float*)y_dev, (hipStream_t)hip_stream, nullptr);
     if (io == TK_FP32)
         return matvec_impl<float>(ctx, t, (const float*)z_dev, (float*)y_dev, (hipStream_t)hip_stream, nullptr);
     return matvec_impl<double>(ctx, t, (const double*)z_dev, (double*)y_dev, (hipStream_t)hip_stream, nullptr);
@@ -1192,7 +1335,10 @@ tk_status tk_quadratic_form(tk_ctx* ctx, const tk_tucker* t, const void* z_dev, 
         ybuf = owned;
     }
     tk_status st;
-    if (io == TK_FP32)
+    if (io == TK_FP64 && ctx->matvec_method == TK_MV_FFT) st = fail(TK_EINVAL, "the FFT matvec is FP32 only");
+    else if (use_fft(ctx, io))
+        st = matvec_fft(ctx, t, (const float*)z_dev, (float*)ybuf, s, out);
+    else if (io == TK_FP32)
         st = matvec_impl<float>(ctx, t, (const float*)z_dev, (float*)ybuf, s, out);
     else
         st = matvec_impl<double>(ctx, t, (const double*)z_dev, (double*)ybuf, s, out);

@@ -115,6 +115,25 @@ template <typename T>
 hipError_t launch_toep_right(const ToepRightArgs& a, hipStream_t s);
 hipError_t kron_set_attributes();
 
+// ---------------------------------------------------- a8: FFT form of the matvec ----
+struct FftPassArgs {
+    int L, logL, F;            // transform length 2^logL, fibres per work-group
+    int n_inner;               // fibres along the inner index
+    int len_in, len_out;       // valid input length (zero padded to L), output length kept
+    long s_in_o, s_in_i, s_in_k, s_out_o, s_out_i, s_out_k;   // element strides
+    const void* in; void* out;
+    int in_real, out_real, mode;
+    float scale;
+    const float* Hs; const float* Uh3; int r2, L1;             // mode 3 only
+    const float2* tw;                                          // exp(-2 pi i q / L), q < L
+};
+hipError_t launch_twiddles(float2* tw, int L, hipStream_t s);
+size_t fft_lds_bytes(int L, int F, int r2);
+int fft_fibres_per_block(int L, int r2);   // r2: P3 scratch floats per fibre (0 for the other passes)
+hipError_t launch_fft_pass(const FftPassArgs& a, long n_outer, hipStream_t s);
+hipError_t launch_fourier_factor(const double* U, int r, int off, int m, int L, int nf, double* Uh, hipStream_t s);
+hipError_t fft_set_attributes();
+
 // ------------------------------------------------------------ small scalar kernels ----
 hipError_t launch_rank_rule(const double* lam, long sLam, int len, int count, const double* total, long sTotal,
                             const double* scal, int has_d2, double eps2, int* ranks, int* ok, hipStream_t s);

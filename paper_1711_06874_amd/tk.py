@@ -72,6 +72,7 @@ _SIGS = {
     "tk_grid_eval": (_st, [_vp, ctypes.POINTER(tk_kernel), ctypes.POINTER(tk_grid), ctypes.c_int, _vp, _vp]),
     "tk_gram": (_st, [_vp, _vp, _ip, ctypes.c_int, ctypes.c_int, _vp, _vp]),
     "tk_eig_topr": (_st, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]),
+    "tk_set_matvec_method": (_st, [_vp, ctypes.c_int]),
     "tk_profile_enable": (_st, [ctypes.c_int]),
     "tk_profile_reset": (_st, []),
     "tk_profile_read": (_st, [ctypes.c_int, ctypes.POINTER(ctypes.c_longlong), _dp]),
@@ -272,7 +273,12 @@ def tk_eig_topr(ctx: int, count: int, n: int, r: int, G, lam, U, stream=None) ->
 
 
 PROF_CLASSES = {"grid": 0, "gram": 1, "eig": 2, "ttm": 3, "norm": 4, "toep_right": 5, "toep_left": 6,
-                "small": 7}
+                "small": 7, "fft": 8}
+TK_MV_AUTO, TK_MV_FFT, TK_MV_DENSE = 0, 1, 2
+
+
+def tk_set_matvec_method(ctx: int, method: int) -> None:
+    _check(_lib.tk_set_matvec_method(ctx, int(method)), "tk_set_matvec_method")
 
 
 def tk_profile_enable(on: bool = True) -> None:
@@ -351,6 +357,9 @@ class Context:
 
     def budget(self):
         return tk_ctx_budget(self.handle)
+
+    def set_matvec_method(self, method: int):
+        tk_set_matvec_method(self.handle, method)
 
     def destroy(self):
         if self.handle:

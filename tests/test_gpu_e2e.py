@@ -297,3 +297,32 @@ def test_bench_configuration_256(ctx, tk, oracle, nu, ell):
     assert q == pytest.approx(float(np.dot(z.reshape(-1).astype(np.float64), got.astype(np.float64))), rel=1e-6)
     tr = ctx.trace(t)
     assert tr == pytest.approx(oracle.cov_trace_kron(to, og), rel=1e-12)
+
+
+@pytest.mark.parametrize("layout,n", [(1, (6, 7, 5)), (0, (9, 7, 11)), (1, (20, 17, 24)), (0, (3, 5, 7)),
+                                      (1, (33, 40, 64)), (1, (2, 2, 3))])
+def test_matvec_fft_matches_oracle_and_dense(ctx, tk, oracle, layout, n):
+    """The FFT form (circulant embedding of every Toeplitz factor, Sec. 3.6) against the plain
+    product of the oracle and against the dense Toeplitz mode products."""
+    og = oracle.Grid(n=n, layout=layout)
+    ranks = tuple(min(4, x) for x in n)
+    t = ctx.compress(tk.make_kernel(0, nu=0.5, ell=0.4), tk.make_grid(n, 1.0, layout),
+                     tk.make_opts(ranks=ranks, hooi_sweeps=1, prec=tk.TK_FP64))
+    U, core = t.factors()
+    to = to_oracle_tucker(oracle, U, core)
+    off, m = oracle.cov_offsets(og)
+    z = synth.normal_vector(m, 9)
+    want = oracle.cov_matvec(to, og, z.astype(np.float64)).reshape(-1)
+    Q = oracle.reconstruct(to.core, to.U)
+    rows = np.arange(int(np.prod(m)))
+    bound = oracle.cov_rows_from_generator(np.abs(Q), og, np.abs(z.astype(np.float64)), rows)
+    outs = {}
+    for name, method in (("fft", tk.TK_MV_FFT), ("dense", tk.TK_MV_DENSE)):
+        ctx.set_matvec_method(method)
+        y = torch.empty(m, dtype=torch.float32, device="cuda")
+        ctx.kron_matvec(t, dev(z), y, io=tk.TK_FP32)
+        outs[name] = host(y).reshape(-1).astype(np.float64)
+        say(name, "max err/bound %.3e" % (np.abs(outs[name] - want) / bound).max())
+    ctx.set_matvec_method(tk.TK_MV_AUTO)
+    for name in outs:
+        assert np.all(np.abs(outs[name] - want) <= 2e-5 * bound), name
