@@ -149,14 +149,22 @@ tk_status tk_compress(tk_ctx *ctx, const tk_kernel *kernel, const tk_grid *grid,
 tk_status tk_compress_tensor(tk_ctx *ctx, const void *A_dev, const tk_grid *grid,
                              const tk_opts *opts, void *hip_stream, tk_tucker **out);
 
-/* Compress `count` independent problems (kernels[i] on grids[i], all with *opts) in one
- * call: the tensors are grouped by size, every phase of a group runs as one launch over all
- * of its members, and the group's sweep is replayed from a captured HIP graph.  outs[i]
- * receives the i-th result; each is identical to what tk_compress returns for that problem
- * alone.  Synchronising.  On error no result is returned (outs[] set to NULL). */
+/* Compress `count` independent problems (kernels[i] on grids[i], sizes may differ, all with
+ * *opts) in one call.  The problems run concurrently, each on one of the context's worker
+ * streams (tk_ctx_set_workers, default 4) with its own host worker, so that the
+ * latency-bound eigensolves of one problem overlap the bandwidth-bound passes of others.
+ * They start after the work queued on hip_stream.  Admission follows the HBM budget: a
+ * problem that does not fit while others are running waits for one of them to finish.
+ * outs[i] receives the i-th result, identical to what tk_compress returns for that problem
+ * alone; result i is tied to a worker stream that lives as long as the context.
+ * Synchronising.  On error no result is returned (outs[] set to NULL). */
 tk_status tk_compress_batch(tk_ctx *ctx, int count, const tk_kernel *kernels,
                             const tk_grid *grids, const tk_opts *opts, void *hip_stream,
                             tk_tucker **outs);
+
+/* Number of worker streams / host workers tk_compress_batch uses (1..16; default 4, the
+ * number of hardware queues a process gets by default).  Host only. */
+tk_status tk_ctx_set_workers(tk_ctx *ctx, int workers);
 
 /* Sizes, ranks and the measured relative Frobenius error ||A - A_r|| / ||A|| (Sec. 3.7
  * eq. (3.26)).  Any output pointer may be NULL.  Host only. */
@@ -256,7 +264,7 @@ tk_status tk_eig_topr(tk_ctx *ctx, int count, int n, int r, const double *G_dev,
 typedef enum {
     TK_PROF_GRID = 0, TK_PROF_GRAM = 1, TK_PROF_EIG = 2, TK_PROF_TTM = 3, TK_PROF_NORM = 4,
     TK_PROF_TOEP_RIGHT = 5, TK_PROF_TOEP_LEFT = 6, TK_PROF_SMALL = 7, TK_PROF_FFT = 8,
-    TK_PROF_COUNT = 9
+    TK_PROF_FFT_AXIS0 = 9, TK_PROF_COUNT = 10
 } tk_prof_class;
 tk_status tk_profile_enable(int on);
 tk_status tk_profile_reset(void);

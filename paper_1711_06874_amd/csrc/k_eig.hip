@@ -292,6 +292,255 @@ __global__ void __launch_bounds__(256) k_jacobi(const double* __restrict__ Hin, 
     if (tid < p && rank_of[tid] < r) lam[(long)blockIdx.x * sLam + rank_of[tid]] = H[tid][tid];
 }
 
+
+// ---------------------------------------------------------------------------------------------
+// Householder QR with each row of the n x p block held in one thread's registers (n <= NT,
+// p <= PM).  Per column one block reduction gives both the squared norm below the diagonal and
+// the products of that part of the column with every later column:
+//     S[c] = sum_{i > j} W[i][j] W[i][c],  c = j..p-1,
+// so with scale = 1 / (alpha - beta) the reflector v = (1, scale W[j+1:, j]) satisfies
+// v^T W[j:, c] = W[j][c] + scale S[c].  The reduction goes through an LDS transpose T[c][i]
+// (two barriers).  The explicit Q is then accumulated backwards in the same registers.
+
+// S[c] = sum_i x_i w_i[c] for c in [c0, p): x is this thread's multiplier (0 for rows that take
+// no part).  T holds PM x NT doubles.
+template <int PM, int NT>
+__device__ __forceinline__ void block_col_sums(double* T, double* S, const double (&w)[PM], double x, int c0, int p)
+{
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < PM; ++c)
+        if (c >= c0 && c < p) T[c * NT + t] = x * w[c];
+    __syncthreads();
+    const int nc = p - c0;
+    int G = 64;
+    while (G > 1 && G * nc > NT) G >>= 1;
+    const int c = c0 + t / G, g = t & (G - 1);
+    double acc = 0.0;
+    if (t / G < nc) {
+        const double* row = T + c * NT;
+#pragma unroll 4
+        for (int k = g; k < NT; k += G) acc += row[k];
+    }
+    for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (t / G < nc && g == 0) S[c] = acc;
+    __syncthreads();
+}
+
+template <int PM, int NT>
+__global__ void __launch_bounds__(NT) k_hqr_reg(const double* __restrict__ In, double* __restrict__ Out, int n, int p)
+{
+    extern __shared__ double T[];
+    __shared__ double S[PM];
+    __shared__ double rowjb[2][PM];     // row j, double-buffered by column parity
+    __shared__ double taus[PM];
+    const int i = threadIdx.x;
+    const long off = (long)blockIdx.x * n * p;
+    const bool live = i < n;
+    double w[PM];
+#pragma unroll
+    for (int c = 0; c < PM; ++c) w[c] = (live && c < p) ? In[off + (long)i * p + c] : 0.0;
+
+    for (int j = 0; j < p; ++j) {
+        double x = 0.0;
+#pragma unroll
+        for (int c = 0; c < PM; ++c)
+            if (c == j) x = w[c];
+        double* rowj = rowjb[j & 1];
+        if (i == j) {
+#pragma unroll
+            for (int c = 0; c < PM; ++c) rowj[c] = w[c];
+        }
+        block_col_sums<PM, NT>(T, S, w, (live && i > j) ? x : 0.0, j, p);
+        const double xn2 = S[j];
+        const double alpha = rowj[j];
+        double t = 0.0, scale = 0.0, beta = alpha;
+        if (xn2 > 0.0) {
+            const double nrm = sqrt(alpha * alpha + xn2);
+            beta = (alpha >= 0.0) ? -nrm : nrm;
+            t = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        if (i == 0) taus[j] = t;
+        const double v = (i == j) ? 1.0 : ((live && i > j) ? x * scale : 0.0);
+        if (t != 0.0) {
+#pragma unroll
+            for (int c = 0; c < PM; ++c)
+                if (c > j && c < p) w[c] -= t * v * (rowj[c] + scale * S[c]);
+        }
+        // column j: beta on the diagonal, the scaled reflector below it
+        const double nj = (i == j) ? beta : ((i > j) ? x * scale : x);
+#pragma unroll
+        for (int c = 0; c < PM; ++c)
+            if (c == j) w[c] = nj;
+    }
+    // explicit Q, from the last reflector to the first, in place
+    for (int j = p - 1; j >= 0; --j) {
+        double x = 0.0;
+#pragma unroll
+        for (int c = 0; c < PM; ++c)
+            if (c == j) x = w[c];
+        const double v = (i == j) ? 1.0 : ((live && i > j) ? x : 0.0);
+        const double t = taus[j];
+        if (j + 1 < p) {
+            block_col_sums<PM, NT>(T, S, w, v, j + 1, p);
+            if (t != 0.0) {
+#pragma unroll
+                for (int c = 0; c < PM; ++c)
+                    if (c > j && c < p) w[c] -= t * v * S[c];
+            }
+        }
+        const double qj = (i < j) ? 0.0 : ((i == j) ? 1.0 - t : -t * v);
+#pragma unroll
+        for (int c = 0; c < PM; ++c)
+            if (c == j) w[c] = qj;
+    }
+    if (live) {
+#pragma unroll
+        for (int c = 0; c < PM; ++c)
+            if (c < p) Out[off + (long)i * p + c] = w[c];
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Two-sided Jacobi on a p x p symmetric matrix (p <= JW_PMAX) by one wavefront, parallel
+// round-robin ordering.  After the rotations of a step are formed, every 2 x 2 block (P, Q) of
+// the pair partition is replaced by J_P^T B J_Q in one pass (upper blocks, mirrored), the
+// diagonal blocks by the closed form (a_pp - t a_pq, a_qq + t a_pq, 0), and the rows of V by
+// V J.  Stops when off(H) <= max(tol, p u) ||H||_F or after max_sweeps sweeps.
+constexpr int JW_PMAX = 32;
+
+__global__ void __launch_bounds__(64) k_jacobi_w(const double* __restrict__ Hin, long sH, int p, int r,
+                                                 double* __restrict__ Vs, long sV, int ldv, double* __restrict__ lam,
+                                                 long sLam, int max_sweeps, double tol)
+{
+    __shared__ double H[JW_PMAX][JW_PMAX + 1];
+    __shared__ double V[JW_PMAX][JW_PMAX + 1];
+    __shared__ double cs[JW_PMAX / 2][3];          // c, s, t
+    __shared__ int pq[JW_PMAX / 2][2];
+    __shared__ int rank_of[JW_PMAX];
+    const int lane = threadIdx.x;
+    const double* Hp = Hin + (long)blockIdx.x * sH;
+    for (int e = lane; e < p * p; e += 64) {
+        const int i = e / p, j = e - (e / p) * p;
+        H[i][j] = 0.5 * (Hp[(long)i * p + j] + Hp[(long)j * p + i]);
+        V[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int m = p + (p & 1);
+    const int np = m / 2;
+    double f = 0.0;
+    for (int e = lane; e < p * p; e += 64) {
+        const double x = H[e / p][e - (e / p) * p];
+        f += x * x;
+    }
+    const double fro = sqrt(wave_sum(f));
+    tol = fmax(tol, (double)p * 2.220446049250313e-16);
+    const int nblk = np * (np + 1) / 2;
+
+    for (int sweep = 0; sweep < max_sweeps && p > 1; ++sweep) {
+        double o = 0.0;
+        for (int e = lane; e < p * p; e += 64) {
+            const int i = e / p, j = e - (e / p) * p;
+            if (i != j) o += H[i][j] * H[i][j];
+        }
+        if (sqrt(wave_sum(o)) <= tol * fro) break;
+        for (int step = 0; step < m - 1; ++step) {
+            if (lane < np) {
+                int a, bb;
+                if (lane == 0) { a = m - 1; bb = step; }
+                else { a = (step + lane) % (m - 1); bb = (step - lane + (m - 1)) % (m - 1); }
+                if (a > bb) { const int q = a; a = bb; bb = q; }
+                double c = 1.0, sn = 0.0, t = 0.0;
+                if (bb < p) {
+                    const double apq = H[a][bb];
+                    if (apq != 0.0) {
+                        // t = tan(theta) of the smaller rotation annihilating a_pq
+                        const double d = H[bb][bb] - H[a][a];
+                        const double den = fabs(d) + sqrt(d * d + 4.0 * apq * apq);
+                        t = 2.0 * apq / den;
+                        if (d < 0.0) t = -t;
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        sn = t * c;
+                    }
+                }
+                pq[lane][0] = a; pq[lane][1] = bb;
+                cs[lane][0] = c; cs[lane][1] = sn; cs[lane][2] = t;
+            }
+            __syncthreads();
+            // 2 x 2 blocks (P <= Q) of H
+            for (int e = lane; e < nblk; e += 64) {
+                // e -> (P, Q) with P <= Q, row-major over the upper triangle
+                int P = 0, rem = e;
+                while (rem >= np - P) { rem -= np - P; ++P; }
+                const int Q = P + rem;
+                const int a = pq[P][0], b = pq[P][1], a2 = pq[Q][0], b2 = pq[Q][1];
+                const double cP = cs[P][0], sP = cs[P][1], tP = cs[P][2];
+                const double cQ = cs[Q][0], sQ = cs[Q][1];
+                if (P == Q) {
+                    if (b < p && tP != 0.0) {
+                        const double apq = H[a][b];
+                        H[a][a] -= tP * apq;
+                        H[b][b] += tP * apq;
+                        H[a][b] = 0.0;
+                        H[b][a] = 0.0;
+                    }
+                } else {
+                    // rows a, b (pair P) x columns a2, b2 (pair Q); the padding index (>= p) is skipped
+                    const bool rb = b < p, cb = b2 < p;
+                    const double x00 = H[a][a2];
+                    const double x01 = cb ? H[a][b2] : 0.0;
+                    const double x10 = rb ? H[b][a2] : 0.0;
+                    const double x11 = (rb && cb) ? H[b][b2] : 0.0;
+                    // rows: [x0; x1] <- J_P^T [x0; x1]
+                    const double y00 = cP * x00 - sP * x10, y10 = sP * x00 + cP * x10;
+                    const double y01 = cP * x01 - sP * x11, y11 = sP * x01 + cP * x11;
+                    // columns: [y.0 y.1] <- [y.0 y.1] J_Q
+                    const double z00 = cQ * y00 - sQ * y01, z01 = sQ * y00 + cQ * y01;
+                    const double z10 = cQ * y10 - sQ * y11, z11 = sQ * y10 + cQ * y11;
+                    H[a][a2] = z00; H[a2][a] = z00;
+                    if (cb) { H[a][b2] = z01; H[b2][a] = z01; }
+                    if (rb) { H[b][a2] = z10; H[a2][b] = z10; }
+                    if (rb && cb) { H[b][b2] = z11; H[b2][b] = z11; }
+                }
+            }
+            // V <- V J: lane handles row (lane % 32) and half of the pairs
+            {
+                const int row = lane & 31, half = lane >> 5;
+                if (row < p) {
+                    for (int k = half; k < np; k += 2) {
+                        const int a = pq[k][0], b = pq[k][1];
+                        if (b >= p) continue;
+                        const double c = cs[k][0], sn = cs[k][1];
+                        const double x = V[row][a], y = V[row][b];
+                        V[row][a] = c * x - sn * y;
+                        V[row][b] = sn * x + c * y;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // stable descending ranks
+    if (lane < p) {
+        const double d = H[lane][lane];
+        int rk = 0;
+        for (int i = 0; i < p; ++i) {
+            const double e = H[i][i];
+            if (e > d || (e == d && i < lane)) ++rk;
+        }
+        rank_of[lane] = rk;
+    }
+    __syncthreads();
+    double* Vo = Vs + (long)blockIdx.x * sV;
+    for (int e = lane; e < p * p; e += 64) {
+        const int i = e / p, j = e - (e / p) * p;
+        const int rk = rank_of[j];
+        if (rk < r) Vo[(long)i * ldv + rk] = V[i][j];
+    }
+    if (lane < p && rank_of[lane] < r) lam[(long)blockIdx.x * sLam + rank_of[lane]] = H[lane][lane];
+}
+
 // Sign rule on the n x r factor of problem blockIdx.y, column blockIdx.x.
 __global__ void __launch_bounds__(256) k_signfix(double* __restrict__ U, long sU, int ldu, int n)
 {
@@ -319,6 +568,37 @@ __global__ void __launch_bounds__(256) k_signfix(double* __restrict__ U, long sU
         for (int i = tid; i < n; i += 256) u[(long)i * ldu] = -u[(long)i * ldu];
 }
 
+// Sign rule on column blockIdx.x of U (n rows, ld ldu); the same flip is applied to column
+// blockIdx.x of V (nv rows, ld ldv).
+__global__ void __launch_bounds__(256) k_signfix_pair(double* __restrict__ U, int ldu, int n, double* __restrict__ V,
+                                                      int ldv, int nv)
+{
+    __shared__ double red[4];
+    __shared__ int redi[4];
+    __shared__ double amax_s;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double* u = U + blockIdx.x;
+    double m = 0.0;
+    for (int i = tid; i < n; i += 256) m = fmax(m, fabs(u[(long)i * ldu]));
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (lane == 0) red[wv] = m;
+    __syncthreads();
+    if (tid == 0) amax_s = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    __syncthreads();
+    const double thr = amax_s * (1.0 - 1e-10);
+    int lead = 0x7fffffff;
+    for (int i = tid; i < n; i += 256)
+        if (fabs(u[(long)i * ldu]) >= thr && i < lead) lead = i;
+    for (int o = 32; o > 0; o >>= 1) lead = min(lead, __shfl_xor(lead, o, 64));
+    if (lane == 0) redi[wv] = lead;
+    __syncthreads();
+    const int L = min(min(redi[0], redi[1]), min(redi[2], redi[3]));
+    if (L < n && u[(long)L * ldu] < 0.0) {
+        for (int i = tid; i < n; i += 256) u[(long)i * ldu] = -u[(long)i * ldu];
+        for (int i = tid; i < nv; i += 256) V[(long)i * ldv + blockIdx.x] = -V[(long)i * ldv + blockIdx.x];
+    }
+}
+
 __global__ void k_trace(const double* __restrict__ G, long sG, int n, double* __restrict__ out, long sOut)
 {
     __shared__ double red[4];
@@ -336,16 +616,53 @@ __global__ void k_trace(const double* __restrict__ G, long sG, int n, double* __
 
 static hipError_t qr_launch(const double* in, double* out, int count, int n, int p, hipStream_t s)
 {
+    if (n <= 512 && p <= 32) {
+        const int nt = n <= 256 ? 256 : 512;
+        const size_t lds = sizeof(double) * (size_t)(p <= 16 ? 16 : 32) * nt;
+        if (p <= 16) {
+            if (nt == 256) hipLaunchKernelGGL((k_hqr_reg<16, 256>), dim3(count), dim3(256), lds, s, in, out, n, p);
+            else hipLaunchKernelGGL((k_hqr_reg<16, 512>), dim3(count), dim3(512), lds, s, in, out, n, p);
+        } else {
+            if (nt == 256) hipLaunchKernelGGL((k_hqr_reg<32, 256>), dim3(count), dim3(256), lds, s, in, out, n, p);
+            else hipLaunchKernelGGL((k_hqr_reg<32, 512>), dim3(count), dim3(512), lds, s, in, out, n, p);
+        }
+        return hipGetLastError();
+    }
     size_t bytes = (size_t)n * p * sizeof(double);
     int in_lds = bytes <= QR_LDS_BYTES ? 1 : 0;
     hipLaunchKernelGGL(k_hqr, dim3(count), dim3(256), in_lds ? bytes : 0, s, in, out, n, p, in_lds);
     return hipGetLastError();
 }
 
+// Jacobi on `count` p x p matrices (stride sH) -> leading r eigenvectors (stride sV, ld ldv)
+static hipError_t jacobi_launch(const double* H, long sH, int count, int p, int r, double* V, long sV, int ldv,
+                                double* lam, long sL, hipStream_t s)
+{
+    if (p <= JW_PMAX) {
+        hipLaunchKernelGGL(k_jacobi_w, dim3(count), dim3(64), 0, s, H, sH, p, r, V, sV, ldv, lam, sL, 60, 1e-15);
+        return hipGetLastError();
+    }
+    if (sH != (long)p * p || sV != (long)p * r || ldv != r) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_jacobi, dim3(count), dim3(256), 0, s, H, p, r, V, lam, sL, 60, 1e-15);
+    return hipGetLastError();
+}
+
+hipError_t launch_signfix_pair(double* U, int ldu, int n, double* V, int ldv, int nv, int r, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_signfix_pair, dim3(r), dim3(256), 0, s, U, ldu, n, V, ldv, nv);
+    return hipGetLastError();
+}
+
 hipError_t eig_set_attributes()
 {
-    return hipFuncSetAttribute((const void*)k_hqr, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)QR_LDS_BYTES);
+    hipError_t e = hipFuncSetAttribute((const void*)k_hqr, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)QR_LDS_BYTES);
+    if (e != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_hqr_reg<32, 512>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)(sizeof(double) * 32 * 512))) != hipSuccess)
+        return e;
+    return hipFuncSetAttribute((const void*)k_hqr_reg<16, 512>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(sizeof(double) * 16 * 512));
 }
 
 hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s)
@@ -353,13 +670,21 @@ hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s)
     hipError_t e;
     const int n = b.n, p = b.p, r = b.r;
     const long np_ = (long)n * p;
-    // start block
-    hipLaunchKernelGGL(k_eig_init, dim3((unsigned)((np_ + 255) / 256), b.count), dim3(256), 0, s, b);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (b.trace) {
         hipLaunchKernelGGL(k_trace, dim3(b.count), dim3(256), 0, s, b.G, b.sG, n, b.trace, b.sTrace);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    if (p == n && p <= JW_PMAX) {
+        // the block is the identity: diagonalise G itself
+        if ((e = jacobi_launch(b.G, b.count > 1 ? b.sG : 0, b.count, p, r, b.U, b.sU, b.ldu, b.lam, b.sL, s)) !=
+            hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_signfix, dim3(r, b.count), dim3(256), 0, s, b.U, b.sU, b.ldu, n);
+        return hipGetLastError();
+    }
+    // start block
+    hipLaunchKernelGGL(k_eig_init, dim3((unsigned)((np_ + 255) / 256), b.count), dim3(256), 0, s, b);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     GemmArgs gq{};   // Y = G Q
     gq.M = n; gq.N = p; gq.K = n; gq.batch = b.count;
     gq.A = b.G; gq.sAb = b.sG; gq.sAm = n; gq.sAk = 1;
@@ -374,6 +699,15 @@ hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s)
             if ((e = qr_launch(b.Y, b.Q, b.count, n, p, s)) != hipSuccess) return e;
         }
     }
+    if (b.span_only) {
+        // the block spans G^iters W: hand it over as the factor (ld p == r)
+        if (!(b.warm && b.rw == p && p == r && p < n && iters > 0)) return hipErrorInvalidValue;
+        for (long c = 0; c < b.count; ++c)
+            if ((e = hipMemcpy2DAsync(b.U + c * b.sU, sizeof(double) * b.ldu, b.Q + c * np_, sizeof(double) * p,
+                                      sizeof(double) * p, n, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+                return e;
+        return hipSuccess;
+    }
     if ((e = launch_gemm<double, double, double>(gq, s)) != hipSuccess) return e;
     GemmArgs hq{};   // H = Q^T Y  (p x p)
     hq.M = p; hq.N = p; hq.K = n; hq.batch = b.count;
@@ -382,8 +716,8 @@ hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s)
     hq.C = b.H; hq.sCb = (long)p * p; hq.sCm = p; hq.sCn = 1;
     hq.alpha = 1.0; hq.beta = 0.0;
     if ((e = launch_gemm<double, double, double>(hq, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_jacobi, dim3(b.count), dim3(256), 0, s, b.H, p, r, b.Vs, b.lam, b.sL, 60, 1e-15);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = jacobi_launch(b.H, (long)p * p, b.count, p, r, b.Vs, (long)p * r, r, b.lam, b.sL, s)) != hipSuccess)
+        return e;
     GemmArgs uq{};   // U = Q Vs  (n x r)
     uq.M = n; uq.N = r; uq.K = p; uq.batch = b.count;
     uq.A = b.Q; uq.sAb = np_; uq.sAm = p; uq.sAk = 1;

@@ -31,7 +31,7 @@ namespace tk {
 namespace {
 
 constexpr int FFT_LDS_COMPLEX = 8192;
-constexpr int FFT_THREADS = 512;
+constexpr int FFT_THREADS = 1024;
 constexpr size_t FFT_LDS_MAX = 96 * 1024;
 
 // LDS position of complex element x of a block: one spare slot after every 16 values, so the
@@ -138,7 +138,7 @@ __device__ __forceinline__ void stockham_stage(float2* X, const float2* __restri
 
 // Stockham FFT, in place, of F fibres of length L = 2^logL at X[pd(f * L + k)] (natural order
 // in and out); tw[q] = exp(-2 pi i q / L), q < L.
-__device__ void fft_lds(float2* X, const float2* tw, int F, int logL, bool inv)
+__device__ __forceinline__ void fft_lds(float2* X, const float2* tw, int F, int logL, bool inv)
 {
     int lns = 0, rem = logL;
     while (rem > 0) {
@@ -151,117 +151,119 @@ __device__ void fft_lds(float2* X, const float2* tw, int F, int logL, bool inv)
     }
 }
 
-// R[f][f0] *= chat = sum_c Hs[f0][o][c] Uh3s[f][c] for f < nf (RB >= r2 registers per row).
-template <int RB>
-__device__ void times_chat(float2* R, int L, int nf, const float* __restrict__ Hs, int L1, long o,
-                           const float* u3s, int r2)
+// X[f][f0] *= chat[f0][f1 = o][f2 = i0 + f] = sum_c Hs[o][f0][c] Uh3[i0 + f][c] for f < nf.  Each thread
+// owns frequencies f0 and keeps its Hs row (r2p <= 4 * RB4 floats, zero padded) in registers.
+template <int RB4>
+__device__ __forceinline__ void times_chat(float2* X, int L, int nf, const float* __restrict__ Hs, long o,
+                                           const float* u3s, int r2p)
 {
-    for (int f0 = threadIdx.x; f0 < L; f0 += blockDim.x) {
-        const float* h = Hs + ((long)f0 * L1 + o) * r2;
-        float hr[RB];
+    const int n4 = r2p >> 2;
+    for (int f0 = threadIdx.x; f0 < L; f0 += FFT_THREADS) {
+        const float4* h = reinterpret_cast<const float4*>(Hs + ((long)o * L + f0) * r2p);
+        float4 hr[RB4];
 #pragma unroll
-        for (int c = 0; c < RB; ++c) hr[c] = (c < r2) ? h[c] : 0.f;
+        for (int c = 0; c < RB4; ++c) hr[c] = (c < n4) ? h[c] : make_float4(0.f, 0.f, 0.f, 0.f);
         for (int f = 0; f < nf; ++f) {
+            const float4* u = reinterpret_cast<const float4*>(u3s + f * r2p);
             float chat = 0.f;
 #pragma unroll
-            for (int c = 0; c < RB; ++c)
-                if (c < r2) chat += hr[c] * u3s[f * r2 + c];
-            const float2 v = R[pd(f * L + f0)];
-            R[pd(f * L + f0)] = make_float2(v.x * chat, v.y * chat);
+            for (int c = 0; c < RB4; ++c) {
+                if (c < n4) {
+                    const float4 w = u[c];
+                    chat += hr[c].x * w.x + hr[c].y * w.y + hr[c].z * w.z + hr[c].w * w.w;
+                }
+            }
+            float2& v = X[pd(f * L + f0)];
+            v = make_float2(v.x * chat, v.y * chat);
         }
     }
 }
 
-__device__ void load_twiddles(float2* tw, const float2* __restrict__ gtw, int L)
-{
-    for (int q = threadIdx.x; q < L; q += blockDim.x) tw[q] = gtw[q];
-}
-
 }  // namespace
 
-// Generic pass.  Fibre (o, i) of the pass: input element k (k < len_in) at
-//   in + o * s_in_o + i * s_in_i + k * s_in_k   (float2, or float when in_real)
-// and output element k (k < len_out) at out + o * s_out_o + i * s_out_i + k * s_out_k.
-// Work-group: F fibres (o, i0 + f), f < F, i0 = blockIdx.x * F, o = blockIdx.y.
-// mode 0: forward C2C / R2C;  mode 1: inverse C2C;  mode 2: inverse from a half spectrum
-// (Hermitian extension of len_in = L/2 + 1 values), real output;  mode 3: forward, times
-// chat, inverse (the P3 pass; fibres are (f1 = o, f2 = i)).
+// One pass over F fibres per work-group, fibre f = i0 + f_local (i0 = blockIdx.x * F), outer index
+// o = blockIdx.y.  Element k of a fibre sits at
+//   CONTIG:   base + o * s_o + f * s_i + k          (rows; P1 and P5)
+//   !CONTIG:  base + o * s_o + f + k * s_k          (neighbouring fibres adjacent; P2, P3, P4)
+// MODE 0: forward (real input when IN_REAL);  1: inverse;  2: inverse from the half spectrum
+// (len_in = L/2 + 1, Hermitian extension), real output times scale;  3: forward, times chat,
+// inverse (P3).  Inputs beyond len_in are zero; the first len_out outputs are stored.
+template <int MODE, bool IN_REAL, bool CONTIG>
 __global__ void __launch_bounds__(FFT_THREADS) k_fft_pass(FftPassArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) float2 fsm[];
-    const int L = a.L, logL = a.logL, F = a.F;      // F: power of two <= FFT_THREADS
+    constexpr int NT = FFT_THREADS;
+    constexpr int QMAX = FFT_LDS_COMPLEX / FFT_THREADS;
+    const int L = a.L, logL = a.logL, F = a.F, logF = a.logF;
+    const int FL = F << logL;
     float2* tw = fsm;
     float2* X = fsm + L;
     const long o = blockIdx.y;
     const int i0 = blockIdx.x * F;
     const int nf = (a.n_inner - i0 < F) ? (a.n_inner - i0) : F;
     const int tid = threadIdx.x;
-    constexpr int NT = FFT_THREADS;
-    load_twiddles(tw, a.tw, L);
-    for (int e = tid; e < pd(F * L); e += NT) X[e] = make_float2(0.f, 0.f);
-    __syncthreads();
-    // ---- load (zero padded), natural order.  Contiguous fibres: threads walk k; strided
-    // fibres: threads walk neighbouring fibres (f = tid % F), which are contiguous in memory.
     const int len_in = a.len_in;
-    auto put = [&](int f, int k, float2 v) {
-        X[pd(f * L + k)] = v;
-        if (a.mode == 2 && k > 0 && k < (L >> 1)) X[pd(f * L + (L - k))] = make_float2(v.x, -v.y);
-    };
-    auto get = [&](long idx) -> float2 {
-        if (a.in_real) return make_float2(((const float*)a.in)[idx], 0.f);
-        return ((const float2*)a.in)[idx];
-    };
-    // every thread first issues all of its loads (up to QMAX), then scatters them into LDS
-    constexpr int QMAX = FFT_LDS_COMPLEX / FFT_THREADS;
-    const int total_in = nf * len_in;
+    // ---- every global load is issued first (zero for padding and for fibres past the end)
     float2 buf[QMAX];
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
         const int e = tid + NT * q;
-        if (e < total_in) {
-            int f, k;
-            if (a.s_in_k == 1) { f = e / len_in; k = e - f * len_in; }
-            else { f = e % nf; k = e / nf; }
-            buf[q] = get(o * a.s_in_o + (long)(i0 + f) * a.s_in_i + (long)k * a.s_in_k);
+        const int f = CONTIG ? (e >> logL) : (e & (F - 1));
+        const int k = CONTIG ? (e & (L - 1)) : (e >> logF);
+        buf[q] = make_float2(0.f, 0.f);
+        if (e < FL && f < nf && k < len_in) {
+            const long idx = CONTIG ? o * a.s_in_o + (long)(i0 + f) * a.s_in_i + k
+                                    : o * a.s_in_o + (i0 + f) + (long)k * a.s_in_k;
+            if (IN_REAL) buf[q].x = static_cast<const float*>(a.in)[idx];
+            else buf[q] = static_cast<const float2*>(a.in)[idx];
         }
+    }
+    for (int q = tid; q < L; q += NT) tw[q] = a.tw[q];
+    float* u3s = reinterpret_cast<float*>(X + pd(FL));
+    if (MODE == 3) {
+        const int r2p = a.r2p;
+        for (int e = tid; e < F * r2p; e += NT) u3s[e] = (e < nf * r2p) ? a.Uh3[(long)i0 * r2p + e] : 0.f;
     }
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
         const int e = tid + NT * q;
-        if (e < total_in) {
-            int f, k;
-            if (a.s_in_k == 1) { f = e / len_in; k = e - f * len_in; }
-            else { f = e % nf; k = e / nf; }
-            put(f, k, buf[q]);
+        const int f = CONTIG ? (e >> logL) : (e & (F - 1));
+        const int k = CONTIG ? (e & (L - 1)) : (e >> logF);
+        if (e < FL) {
+            if (MODE == 2) {
+                // half spectrum: k <= L/2 given, L - k filled with the conjugate
+                if (k < len_in) {
+                    X[pd(f * L + k)] = buf[q];
+                    if (k > 0 && k < (L >> 1)) X[pd(f * L + (L - k))] = make_float2(buf[q].x, -buf[q].y);
+                }
+            } else {
+                X[pd(f * L + k)] = buf[q];
+            }
         }
     }
     __syncthreads();
-    fft_lds(X, tw, F, logL, a.mode == 1 || a.mode == 2);
-    float2* R = X;
-    if (a.mode == 3) {
-        // times chat[f0][f1 = o][f2] = sum_c Hs[f0][f1][c] Uh3[f2][c]: each thread owns frequencies
-        // f0 and reuses the Hs row for all fibres of the block
-        float* u3s = reinterpret_cast<float*>(X + pd(F * L));      // F * r2 floats after the data
-        for (int e = tid; e < nf * a.r2; e += NT) u3s[e] = a.Uh3[(long)i0 * a.r2 + e];
-        __syncthreads();
-        if (a.r2 <= 16) times_chat<16>(R, L, nf, a.Hs, a.L1, o, u3s, a.r2);
-        else if (a.r2 <= 32) times_chat<32>(R, L, nf, a.Hs, a.L1, o, u3s, a.r2);
-        else times_chat<48>(R, L, nf, a.Hs, a.L1, o, u3s, a.r2);
+    fft_lds(X, tw, F, logL, MODE == 1 || MODE == 2);
+    if (MODE == 3) {
+        if (a.r2p <= 16) times_chat<4>(X, L, nf, a.Hs, o, u3s, a.r2p);
+        else if (a.r2p <= 32) times_chat<8>(X, L, nf, a.Hs, o, u3s, a.r2p);
+        else times_chat<12>(X, L, nf, a.Hs, o, u3s, a.r2p);
         __syncthreads();
         fft_lds(X, tw, F, logL, true);
     }
-    // ---- store the first len_out entries
+    // ---- store the first len_out entries of each fibre
     const int len_out = a.len_out;
-    auto put_out = [&](long idx, float2 v) {
-        if (a.out_real) ((float*)a.out)[idx] = v.x * a.scale;
-        else ((float2*)a.out)[idx] = make_float2(v.x * a.scale, v.y * a.scale);
-    };
-    const int total_out = nf * len_out;
-    for (int e = tid; e < total_out; e += NT) {
-        int f, k;
-        if (a.s_out_k == 1) { f = e / len_out; k = e - f * len_out; }
-        else { f = e % nf; k = e / nf; }
-        put_out(o * a.s_out_o + (long)(i0 + f) * a.s_out_i + (long)k * a.s_out_k, R[pd(f * L + k)]);
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+        const int e = tid + NT * q;
+        const int f = CONTIG ? (e >> logL) : (e & (F - 1));
+        const int k = CONTIG ? (e & (L - 1)) : (e >> logF);
+        if (e < FL && f < nf && k < len_out) {
+            const float2 v = X[pd(f * L + k)];
+            const long idx = CONTIG ? o * a.s_out_o + (long)(i0 + f) * a.s_out_i + k
+                                    : o * a.s_out_o + (i0 + f) + (long)k * a.s_out_k;
+            if (MODE == 2) static_cast<float*>(a.out)[idx] = v.x * a.scale;
+            else static_cast<float2*>(a.out)[idx] = make_float2(v.x * a.scale, v.y * a.scale);
+        }
     }
 }
 
@@ -303,26 +305,86 @@ __global__ void __launch_bounds__(256) k_fourier_factor(const double* __restrict
     Uh[e] = u[0] + 2.0 * s;
 }
 
-size_t fft_lds_bytes(int L, int F, int r2)
+size_t fft_lds_bytes(int L, int F, int r2p)
 {
-    size_t fl = (size_t)F * L;
-    // twiddles, the data (padded), and F * r2 floats of scratch for the P3 pass
-    return sizeof(float2) * ((size_t)L + fl + (fl >> 4)) + sizeof(float) * (size_t)F * r2;
+    const size_t fl = (size_t)F * L;
+    // twiddles, the data (padded), and F * r2p floats of Uh3 rows for the P3 pass
+    return sizeof(float2) * ((size_t)L + fl + (fl >> 4)) + sizeof(float) * (size_t)F * r2p;
 }
 
-int fft_fibres_per_block(int L, int r2)
+int fft_fibres_per_block(int L, int r2p)
 {
     int F = FFT_LDS_COMPLEX / L;
     if (F > FFT_THREADS) F = FFT_THREADS;
     if (F < 1) F = 1;
-    while (F > 1 && fft_lds_bytes(L, F, r2) > FFT_LDS_MAX) F >>= 1;
+    while (F > 1 && fft_lds_bytes(L, F, r2p) > FFT_LDS_MAX) F >>= 1;
     return F;
 }
 
-hipError_t launch_fft_pass(const FftPassArgs& a, long n_outer, hipStream_t s)
+namespace {
+template <int MODE, bool IN_REAL, bool CONTIG>
+hipError_t launch_pass_t(const FftPassArgs& a, long n_outer, size_t lds, hipStream_t s)
 {
     dim3 grid((unsigned)((a.n_inner + a.F - 1) / a.F), (unsigned)n_outer);
-    hipLaunchKernelGGL(k_fft_pass, grid, dim3(FFT_THREADS), fft_lds_bytes(a.L, a.F, a.mode == 3 ? a.r2 : 0), s, a);
+    hipLaunchKernelGGL((k_fft_pass<MODE, IN_REAL, CONTIG>), grid, dim3(FFT_THREADS), lds, s, a);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_fft_pass(const FftPassArgs& a, long n_outer, hipStream_t s)
+{
+    if (a.L < 2 || (1 << a.logL) != a.L || a.F < 1 || (1 << a.logF) != a.F || a.F * a.L > FFT_LDS_COMPLEX ||
+        a.F > FFT_THREADS || n_outer < 1 || a.n_inner < 1 || a.len_in > a.L || a.len_out > a.L)
+        return hipErrorInvalidValue;
+    const bool contig_in = a.s_in_k == 1, contig_out = a.s_out_k == 1;
+    if (contig_in != contig_out || (!contig_in && (a.s_in_i != 1 || a.s_out_i != 1))) return hipErrorInvalidValue;
+    if (a.mode == 3 && (a.r2p < 4 || (a.r2p & 3) || a.r2p > 48)) return hipErrorInvalidValue;
+    if (a.mode == 2 && a.len_in != a.L / 2 + 1) return hipErrorInvalidValue;
+    const size_t lds = fft_lds_bytes(a.L, a.F, a.mode == 3 ? a.r2p : 0);
+    if (lds > FFT_LDS_MAX) return hipErrorInvalidValue;
+    if (a.mode == 0 && a.in_real && contig_in) return launch_pass_t<0, true, true>(a, n_outer, lds, s);
+    if (a.mode == 0 && !a.in_real && !contig_in) return launch_pass_t<0, false, false>(a, n_outer, lds, s);
+    if (a.mode == 1 && !a.in_real && !contig_in) return launch_pass_t<1, false, false>(a, n_outer, lds, s);
+    if (a.mode == 2 && !a.in_real && contig_in) return launch_pass_t<2, false, true>(a, n_outer, lds, s);
+    if (a.mode == 3 && !a.in_real && !contig_in) return launch_pass_t<3, false, false>(a, n_outer, lds, s);
+    return hipErrorInvalidValue;
+}
+
+// Y[i][c] = c < cols ? (float)X[i * cols + c] : 0 for c < cols_pad.
+__global__ void k_f64_to_f32_padded(const double* __restrict__ X, long rows, int cols, int cols_pad,
+                                    float* __restrict__ Y)
+{
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * cols_pad) return;
+    const long i = e / cols_pad;
+    const int c = (int)(e - i * cols_pad);
+    Y[e] = (c < cols) ? (float)X[i * cols + c] : 0.f;
+}
+
+hipError_t launch_f64_to_f32_padded(const double* X, long rows, int cols, int cols_pad, float* Y, hipStream_t s)
+{
+    const long tot = rows * cols_pad;
+    hipLaunchKernelGGL(k_f64_to_f32_padded, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, X, rows, cols,
+                       cols_pad, Y);
+    return hipGetLastError();
+}
+
+// X[i][c] = 0 for cols <= c < cols_pad (rows of length cols_pad).
+__global__ void k_zero_pad_cols(float* __restrict__ X, long rows, int cols, int cols_pad)
+{
+    const int w = cols_pad - cols;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * w) return;
+    const long i = e / w;
+    X[i * cols_pad + cols + (int)(e - i * w)] = 0.f;
+}
+
+hipError_t launch_zero_pad_cols(float* X, long rows, int cols, int cols_pad, hipStream_t s)
+{
+    if (cols_pad <= cols) return hipSuccess;
+    const long tot = rows * (cols_pad - cols);
+    hipLaunchKernelGGL(k_zero_pad_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, X, rows, cols,
+                       cols_pad);
     return hipGetLastError();
 }
 
@@ -336,7 +398,14 @@ hipError_t launch_fourier_factor(const double* U, int r, int off, int m, int L, 
 
 hipError_t fft_set_attributes()
 {
-    return hipFuncSetAttribute((const void*)k_fft_pass, hipFuncAttributeMaxDynamicSharedMemorySize, (int)FFT_LDS_MAX);
+    const void* ks[] = {(const void*)k_fft_pass<0, true, true>, (const void*)k_fft_pass<0, false, false>,
+                        (const void*)k_fft_pass<1, false, false>, (const void*)k_fft_pass<2, false, true>,
+                        (const void*)k_fft_pass<3, false, false>};
+    for (const void* k : ks) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)FFT_LDS_MAX);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace tk

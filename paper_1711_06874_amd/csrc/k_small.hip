@@ -4,19 +4,21 @@
 //
 // The products are batched, with arbitrary element strides on every operand, FP64
 // accumulation and a 32 x 32 output tile per 256-thread work-group (2 x 2 outputs per
-// thread); operands are staged through LDS in 16-deep K chunks.
+// thread); operands are staged through LDS in 64-deep K chunks, the next chunk being loaded into
+// registers while the current one is multiplied.
 #include "tk_kernels.h"
 
 namespace tk {
 
 namespace {
 constexpr int GT = 32;   // output tile edge
-constexpr int GK = 16;   // K chunk
+constexpr int GK = 64;   // K chunk
 }
 
 template <typename TA, typename TB, typename TC>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g)
 {
+    constexpr int PER = GT * GK / 256;     // elements of each operand a thread stages per chunk
     __shared__ double As[GK][GT + 1];
     __shared__ double Bs[GK][GT + 1];
     const int tid = threadIdx.x;
@@ -29,42 +31,55 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g)
     const long b_first = g.reduce_batch ? 0 : (long)blockIdx.y;
     const long b_last = g.reduce_batch ? (long)g.batch : (long)blockIdx.y + 1;
     TC* C = (TC*)g.C + (g.reduce_batch ? 0 : (long)blockIdx.y * g.sCb);
-    for (long b = b_first; b < b_last; ++b) {
-    const TA* A = (const TA*)g.A + b * g.sAb;
-    const TB* B = (const TB*)g.B + b * g.sBb;
-    for (int k0 = 0; k0 < g.K; k0 += GK) {
-        // each thread stages 2 elements of each operand
+    const int kchunks = (g.K + GK - 1) / GK;
+    const long nchunks = (b_last - b_first) * kchunks;
+    // staging positions: consecutive threads walk the unit-stride index of each operand
+    int am[PER], ak[PER], bn[PER], bk[PER];
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            int idx = tid + e * 256;
-            // A tile: rows m (32) x k (16); consecutive threads walk m when sAm == 1, else k
-            int am, ak;
-            if (g.sAm == 1) { am = idx % GT; ak = idx / GT; } else { ak = idx % GK; am = idx / GK; }
-            int gm = m0 + am, gk = k0 + ak;
-            As[ak][am] = (gm < g.M && gk < g.K) ? (double)A[gm * g.sAm + gk * g.sAk] : 0.0;
-            int bn, bk;
-            if (g.sBn == 1) { bn = idx % GT; bk = idx / GT; } else { bk = idx % GK; bn = idx / GK; }
-            int gn = n0 + bn, gk2 = k0 + bk;
-            Bs[bk][bn] = (gn < g.N && gk2 < g.K) ? (double)B[gk2 * g.sBk + gn * g.sBn] : 0.0;
+    for (int e = 0; e < PER; ++e) {
+        const int idx = tid + e * 256;
+        if (g.sAm == 1) { am[e] = idx % GT; ak[e] = idx / GT; } else { ak[e] = idx % GK; am[e] = idx / GK; }
+        if (g.sBn == 1) { bn[e] = idx % GT; bk[e] = idx / GT; } else { bk[e] = idx % GK; bn[e] = idx / GK; }
+    }
+    double ra[PER], rb[PER];
+    auto load = [&](long q) {
+        const long b = b_first + q / kchunks;
+        const int k0 = (int)(q % kchunks) * GK;
+        const TA* A = (const TA*)g.A + b * g.sAb;
+        const TB* B = (const TB*)g.B + b * g.sBb;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int gm = m0 + am[e], gk = k0 + ak[e];
+            ra[e] = (gm < g.M && gk < g.K) ? (double)A[(long)gm * g.sAm + (long)gk * g.sAk] : 0.0;
+            const int gn = n0 + bn[e], gk2 = k0 + bk[e];
+            rb[e] = (gn < g.N && gk2 < g.K) ? (double)B[(long)gk2 * g.sBk + (long)gn * g.sBn] : 0.0;
+        }
+    };
+    if (nchunks > 0) load(0);
+    for (long q = 0; q < nchunks; ++q) {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            As[ak[e]][am[e]] = ra[e];
+            Bs[bk[e]][bn[e]] = rb[e];
         }
         __syncthreads();
-#pragma unroll
+        if (q + 1 < nchunks) load(q + 1);     // in flight while this chunk is multiplied
+#pragma unroll 16
         for (int kk = 0; kk < GK; ++kk) {
-            double a0 = As[kk][ty], a1 = As[kk][ty + 16];
-            double b0 = Bs[kk][tx], b1 = Bs[kk][tx + 16];
+            const double a0 = As[kk][ty], a1 = As[kk][ty + 16];
+            const double b0 = Bs[kk][tx], b1 = Bs[kk][tx + 16];
             acc[0][0] += a0 * b0; acc[0][1] += a0 * b1;
             acc[1][0] += a1 * b0; acc[1][1] += a1 * b1;
         }
         __syncthreads();
     }
-    }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            int gm = m0 + ty + 16 * i, gn = n0 + tx + 16 * j;
+            const int gm = m0 + ty + 16 * i, gn = n0 + tx + 16 * j;
             if (gm < g.M && gn < g.N) {
-                TC* c = C + gm * g.sCm + gn * g.sCn;
+                TC* c = C + (long)gm * g.sCm + (long)gn * g.sCn;
                 double v = g.alpha * acc[i][j];
                 if (g.beta != 0.0) v += g.beta * (double)(*c);
                 *c = (TC)v;

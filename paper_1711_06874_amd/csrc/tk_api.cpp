@@ -9,13 +9,16 @@
 // the HIP kernels of this library; the host only plans shapes, allocates and launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <condition_variable>
 #include <mutex>
+#include <thread>
 #include <new>
 #include <string>
 #include <vector>
@@ -122,6 +125,18 @@ struct tk_ctx {
     size_t budget = 0;
     std::atomic<size_t> in_use{0};
     std::atomic<int> live_results{0};
+    // scalar readbacks go through pinned host slots (and matching device slots) handed out per
+    // call, so concurrent calls on different streams do not share a staging buffer
+    static constexpr int kSlots = 64;
+    static constexpr size_t kSlotBytes = 256;
+    char* pinned = nullptr;
+    char* dev_slots = nullptr;
+    std::mutex slot_mu;
+    uint64_t slot_used = 0;
+    // streams of the batch workers, created on first use, destroyed with the context
+    std::mutex pool_mu;
+    std::vector<hipStream_t> streams;
+    int workers = 4;
 };
 
 struct tk_tucker {
@@ -368,6 +383,51 @@ GemmArgs gemm(int M, int N, int K, int batch, const void* A, long sAb, long sAm,
         if (_e != hipSuccess) return fail(TK_EHIP, "launch %s: %s", #x, hipGetErrorString(_e));    \
     } while (0)
 
+// A pinned host slot and its device twin, held for the duration of one call.
+struct Slot {
+    tk_ctx* c;
+    int i = -1;
+    explicit Slot(tk_ctx* ctx) : c(ctx)
+    {
+        std::lock_guard<std::mutex> g(c->slot_mu);
+        for (int k = 0; k < tk_ctx::kSlots; ++k)
+            if (!(c->slot_used >> k & 1)) {
+                c->slot_used |= 1ull << k;
+                i = k;
+                break;
+            }
+    }
+    ~Slot()
+    {
+        if (i < 0) return;
+        std::lock_guard<std::mutex> g(c->slot_mu);
+        c->slot_used &= ~(1ull << i);
+    }
+    char* host() const { return c->pinned + (size_t)i * tk_ctx::kSlotBytes; }
+    char* dev() const { return c->dev_slots + (size_t)i * tk_ctx::kSlotBytes; }
+};
+
+// Copy up to two small device ranges (together <= kSlotBytes) to host memory, stream-ordered,
+// and wait once.
+tk_status readback(tk_ctx* ctx, hipStream_t s, const void* src0, size_t bytes0, void* dst0,
+                   const void* src1 = nullptr, size_t bytes1 = 0, void* dst1 = nullptr)
+{
+    Slot slot(ctx);
+    const size_t off1 = (bytes0 + 15) & ~(size_t)15;
+    if (slot.i < 0 || off1 + bytes1 > tk_ctx::kSlotBytes) {
+        TK_HIP(hipMemcpyAsync(dst0, src0, bytes0, hipMemcpyDeviceToHost, s));
+        if (bytes1) TK_HIP(hipMemcpyAsync(dst1, src1, bytes1, hipMemcpyDeviceToHost, s));
+        TK_HIP(hipStreamSynchronize(s));
+        return TK_OK;
+    }
+    TK_HIP(hipMemcpyAsync(slot.host(), src0, bytes0, hipMemcpyDeviceToHost, s));
+    if (bytes1) TK_HIP(hipMemcpyAsync(slot.host() + off1, src1, bytes1, hipMemcpyDeviceToHost, s));
+    TK_HIP(hipStreamSynchronize(s));
+    std::memcpy(dst0, slot.host(), bytes0);
+    if (bytes1) std::memcpy(dst1, slot.host() + off1, bytes1);
+    return TK_OK;
+}
+
 // Leading R_k eigenvectors of the three Grams in w.G (stride nmax^2), HOSVD start.
 tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
 {
@@ -410,9 +470,12 @@ tk_status eig_update(const Plan& P, Work& w, int k, const double* Gs, hipStream_
     EigBatch b{};
     // warm start from the current factor.  Float paths: the block is the factor itself
     // (orthonormal, no QR) and one power step per HOOI update; FP64: oversampled block and
-    // converged eigenvectors, so every HOOI step is exact as in the oracle.
+    // converged eigenvectors, so every HOOI step is exact as in the oracle.  With the eps rule
+    // on a float path the factors are rotated to the core's HOSVD basis at the end, so a HOOI
+    // update only has to deliver the subspace: the power-stepped block itself, orthonormalised.
     b.count = 1; b.n = P.n[k]; b.r = P.R[k];
     b.p = (P.n[k] <= EIG_PMAX) ? P.n[k] : (P.prec == TK_FP64 ? P.p[k] : P.R[k]);
+    b.span_only = (P.eps_mode && P.prec != TK_FP64 && b.p == b.r && b.p < b.n) ? 1 : 0;
     b.rw = P.R[k]; b.ldw = P.R[k]; b.warm = w.U[k]; b.sW = 0;
     b.G = Gs; b.sG = 0;
     b.Q = w.Q; b.Y = w.Y; b.H = w.H; b.Vs = w.Vs;
@@ -604,16 +667,27 @@ tk_status core_truncate(const Plan& P, Work& w, hipStream_t s)
         GemmArgs g2 = gemm(R2, R2, R0 * R1, 1, w.core, 0, 1, R2, w.core, 0, R2, 1, w.Gc + 2 * RR, 0, R2, 1);
         TK_LAUNCH((launch_gemm<double, double, double>(g2, s)));
     }
-    // full eigendecompositions (p = n = R_k)
-    for (int k = 0; k < 3; ++k) {
+    // full eigendecompositions (p = n = R_k); one launch for the three modes when the ranks agree
+    if (R0 == R1 && R1 == R2) {
         EigBatch b{};
-        b.count = 1; b.n = P.R[k]; b.p = P.R[k]; b.r = P.R[k];
-        b.G = w.Gc + k * RR; b.sG = 0;
-        b.Q = w.tQ + k * RR; b.Y = w.tY + k * RR; b.H = w.tH + k * RR; b.Vs = w.tVs + k * RR;
-        b.U = w.Vc + k * RR; b.sU = 0; b.ldu = P.R[k];
-        b.lam = w.lamc + 64 * k; b.sL = 64;
+        b.count = 3; b.n = R0; b.p = R0; b.r = R0;
+        b.G = w.Gc; b.sG = RR;
+        b.Q = w.tQ; b.Y = w.tY; b.H = w.tH; b.Vs = w.tVs;     // problem strides R0^2 == RR
+        b.U = w.Vc; b.sU = RR; b.ldu = R0;
+        b.lam = w.lamc; b.sL = 64;
         b.trace = nullptr;
         TK_LAUNCH(launch_eig(b, 0, s));
+    } else {
+        for (int k = 0; k < 3; ++k) {
+            EigBatch b{};
+            b.count = 1; b.n = P.R[k]; b.p = P.R[k]; b.r = P.R[k];
+            b.G = w.Gc + k * RR; b.sG = 0;
+            b.Q = w.tQ + k * RR; b.Y = w.tY + k * RR; b.H = w.tH + k * RR; b.Vs = w.tVs + k * RR;
+            b.U = w.Vc + k * RR; b.sU = 0; b.ldu = P.R[k];
+            b.lam = w.lamc + 64 * k; b.sL = 64;
+            b.trace = nullptr;
+            TK_LAUNCH(launch_eig(b, 0, s));
+        }
     }
     // ranks: budget = (eps^2 a2 - d2) / 3 per mode
     for (int k = 0; k < 3; ++k)
@@ -624,6 +698,8 @@ tk_status core_truncate(const Plan& P, Work& w, hipStream_t s)
         GemmArgs g = gemm(P.n[k], P.R[k], P.R[k], 1, w.U[k], 0, P.R[k], 1, w.Vc + k * RR, 0, P.R[k], 1, w.Urot[k], 0,
                           P.R[k], 1);
         TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+        // sign rule on the rotated factor; the flips go into V_k so that the core follows
+        TK_LAUNCH(launch_signfix_pair(w.Urot[k], P.R[k], P.n[k], w.Vc + k * RR, P.R[k], P.R[k], P.R[k], s));
     }
     // rotate core: coreB = core x_1 V1^T x_2 V2^T x_3 V3^T
     {
@@ -753,8 +829,7 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kp, const void* A_in, c
         TK_LAUNCH(launch_rank_rule(w.lam + 128, 64, P.R[2], 1, w.trace + 2, 1, w.scal, 0, P.eps * P.eps,
                                    w.ranks + 2, w.ranks + 5, s));
         int hr[6];
-        TK_HIP(hipMemcpyAsync(hr, w.ranks, sizeof(hr), hipMemcpyDeviceToHost, s));
-        TK_HIP(hipStreamSynchronize(s));
+        if ((st = readback(ctx, s, w.ranks, sizeof(hr), hr)) != TK_OK) return st;
         // continue with the selected ranks: the leading columns of the factors are kept
         Plan Q = P;
         for (int k = 0; k < 3; ++k) Q.R[k] = hr[k];
@@ -794,16 +869,13 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kp, const void* A_in, c
         if ((st = recon_norm<Real>(P, w, A, w.Urot, w.coreA, s)) != TK_OK) return st;
         TK_LAUNCH(launch_fill_f64(w.scal + 2, 0.0, 1, s));
         TK_LAUNCH(launch_final_err(w.scal, s));
-        TK_HIP(hipMemcpyAsync(hr, w.ranks, sizeof(hr), hipMemcpyDeviceToHost, s));
-        TK_HIP(hipMemcpyAsync(hs, w.scal, sizeof(hs), hipMemcpyDeviceToHost, s));
-        TK_HIP(hipStreamSynchronize(s));
+        if ((st = readback(ctx, s, w.ranks, sizeof(hr), hr, w.scal, sizeof(hs), hs)) != TK_OK) return st;
         for (int k = 0; k < 3; ++k) { final_r[k] = hr[k]; Usrc[k] = w.Urot[k]; }
         csrc = w.coreA;
     } else {
         TK_LAUNCH(launch_fill_f64(w.scal + 2, 0.0, 1, s));   // no truncation: t2 = 0
         TK_LAUNCH(launch_final_err(w.scal, s));
-        TK_HIP(hipMemcpyAsync(hs, w.scal, sizeof(hs), hipMemcpyDeviceToHost, s));
-        TK_HIP(hipStreamSynchronize(s));
+        if ((st = readback(ctx, s, w.scal, sizeof(hs), hs)) != TK_OK) return st;
     }
     tk_tucker* t = nullptr;
     if ((st = alloc_result(ctx, P.n, final_r, s, &t)) != TK_OK) return st;
@@ -937,8 +1009,8 @@ tk_status matvec_impl(tk_ctx* ctx, const tk_tucker* t, const T* z, T* y, hipStre
     }
     if (dot_out) {
         TK_LAUNCH(launch_dot<T>(z, y, M3, dots, 1024, dots + 1024, s));
-        TK_HIP(hipMemcpyAsync(dot_out, dots + 1024, sizeof(double), hipMemcpyDeviceToHost, s));
-        TK_HIP(hipStreamSynchronize(s));
+        tk_status rs = readback(ctx, s, dots + 1024, sizeof(double), dot_out);
+        if (rs != TK_OK) return rs;
     }
     return TK_OK;
 }
@@ -969,6 +1041,8 @@ tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, 
         lg[k] = ilog2(L[k]);
     }
     const int H2 = L[2] / 2 + 1;
+    const int H2p = (H2 + 15) & ~15;     // row pitch of the half spectra: whole 128-byte lines per 16 fibres
+    const int r2p = (r2 + 3) & ~3;
     const long M3 = (long)m[0] * m[1] * m[2];
     Arena plan;
     auto lay = [&](Arena& ar, double** Uh0, double** Uh1, double** Uh2, double** M1, float** Hs, float** Uh3,
@@ -978,10 +1052,10 @@ tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, 
         *Uh1 = ar.take<double>((size_t)L[1] * r1);
         *Uh2 = ar.take<double>((size_t)H2 * r2);
         *M1 = ar.take<double>((size_t)L[0] * r1 * r2);
-        *Hs = ar.take<float>((size_t)L[0] * L[1] * r2);
-        *Uh3 = ar.take<float>((size_t)H2 * r2);
-        *A1 = ar.take<float2>((size_t)m[0] * m[1] * H2);
-        *A2 = ar.take<float2>((size_t)m[0] * L[1] * H2);
+        *Hs = ar.take<float>((size_t)L[0] * L[1] * r2p);
+        *Uh3 = ar.take<float>((size_t)H2 * r2p);
+        *A1 = ar.take<float2>((size_t)m[0] * m[1] * H2p);
+        *A2 = ar.take<float2>((size_t)m[0] * L[1] * H2p);
         *dots = ar.take<double>(2048);
     };
     double *Uh0, *Uh1, *Uh2, *M1, *dots;
@@ -1006,62 +1080,71 @@ tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, 
     for (int k = 0; k < 3; ++k) TK_LAUNCH(launch_twiddles(tw[k], L[k], s));
     {
         ProfScope ps(TK_PROF_SMALL, s);
-        // Fourier-side factors and Hs[f0][f1][c] = sum_ab G_abc Uh1[f0][a] Uh2[f1][b]
+        // Fourier-side factors and Hs[f1][f0][c] = sum_ab G_abc Uh1[f0][a] Uh2[f1][b] (c padded to r2p)
         TK_LAUNCH(launch_fourier_factor(t->U[0], r0, off[0], m[0], L[0], L[0], Uh0, s));
         TK_LAUNCH(launch_fourier_factor(t->U[1], r1, off[1], m[1], L[1], L[1], Uh1, s));
         TK_LAUNCH(launch_fourier_factor(t->U[2], r2, off[2], m[2], L[2], H2, Uh2, s));
         GemmArgs g = gemm(L[0], r1 * r2, r0, 1, Uh0, 0, r0, 1, t->core, 0, (long)r1 * r2, 1, M1, 0, (long)r1 * r2, 1);
         TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
-        GemmArgs g1 = gemm(L[1], r2, r1, L[0], Uh1, 0, r1, 1, M1, (long)r1 * r2, r2, 1, Hs, (long)L[1] * r2, r2, 1);
+        GemmArgs g1 = gemm(L[1], r2, r1, L[0], Uh1, 0, r1, 1, M1, (long)r1 * r2, r2, 1, Hs, r2p, (long)L[0] * r2p, 1);
         TK_LAUNCH((launch_gemm<double, double, float>(g1, s)));
-        TK_LAUNCH(launch_convert_f64_to_f32(Uh2, Uh3, (long)H2 * r2, s));
+        TK_LAUNCH(launch_zero_pad_cols(Hs, (long)L[0] * L[1], r2, r2p, s));
+        TK_LAUNCH(launch_f64_to_f32_padded(Uh2, H2, r2, r2p, Uh3, s));
     }
-    ProfScope ps(TK_PROF_FFT, s);
     FftPassArgs a{};
-    // P1: axis 2 forward, real rows of m2 -> H2 complex
-    a = FftPassArgs{};
-    a.L = L[2]; a.logL = lg[2]; a.F = fft_fibres_per_block(L[2], 0);
-    a.n_inner = m[0] * m[1]; a.len_in = m[2]; a.len_out = H2;
-    a.s_in_o = 0; a.s_in_i = m[2]; a.s_in_k = 1; a.s_out_o = 0; a.s_out_i = H2; a.s_out_k = 1;
-    a.in = z; a.out = A1; a.in_real = 1; a.out_real = 0; a.mode = 0; a.scale = 1.f; a.tw = tw[2];
-    TK_LAUNCH(launch_fft_pass(a, 1, s));
-    // P2: axis 1 forward, fibres (i0, f2) over i1
-    a = FftPassArgs{};
-    a.L = L[1]; a.logL = lg[1]; a.F = fft_fibres_per_block(L[1], 0);
-    a.n_inner = H2; a.len_in = m[1]; a.len_out = L[1];
-    a.s_in_o = (long)m[1] * H2; a.s_in_i = 1; a.s_in_k = H2;
-    a.s_out_o = (long)L[1] * H2; a.s_out_i = 1; a.s_out_k = H2;
-    a.in = A1; a.out = A2; a.mode = 0; a.scale = 1.f; a.tw = tw[1];
-    TK_LAUNCH(launch_fft_pass(a, m[0], s));
-    // P3: axis 0 forward, times chat, inverse; fibres (f1, f2) over i0, in place
-    a = FftPassArgs{};
-    a.L = L[0]; a.logL = lg[0]; a.F = fft_fibres_per_block(L[0], r2);
-    a.n_inner = H2; a.len_in = m[0]; a.len_out = m[0];
-    a.s_in_o = H2; a.s_in_i = 1; a.s_in_k = (long)L[1] * H2;
-    a.s_out_o = H2; a.s_out_i = 1; a.s_out_k = (long)L[1] * H2;
-    a.in = A2; a.out = A2; a.mode = 3; a.scale = 1.f;
-    a.Hs = Hs; a.Uh3 = Uh3; a.r2 = r2; a.L1 = L[1]; a.tw = tw[0];
-    TK_LAUNCH(launch_fft_pass(a, L[1], s));
-    // P4: axis 1 inverse, keep i1 < m1
-    a = FftPassArgs{};
-    a.L = L[1]; a.logL = lg[1]; a.F = fft_fibres_per_block(L[1], 0);
-    a.n_inner = H2; a.len_in = L[1]; a.len_out = m[1];
-    a.s_in_o = (long)L[1] * H2; a.s_in_i = 1; a.s_in_k = H2;
-    a.s_out_o = (long)m[1] * H2; a.s_out_i = 1; a.s_out_k = H2;
-    a.in = A2; a.out = A1; a.mode = 1; a.scale = 1.f; a.tw = tw[1];
-    TK_LAUNCH(launch_fft_pass(a, m[0], s));
-    // P5: axis 2 inverse from the half spectrum, real part, keep i2 < m2, scale
-    a = FftPassArgs{};
-    a.L = L[2]; a.logL = lg[2]; a.F = fft_fibres_per_block(L[2], 0);
-    a.n_inner = m[0] * m[1]; a.len_in = H2; a.len_out = m[2];
-    a.s_in_o = 0; a.s_in_i = H2; a.s_in_k = 1; a.s_out_o = 0; a.s_out_i = m[2]; a.s_out_k = 1;
-    a.in = A1; a.out = y; a.out_real = 1; a.mode = 2; a.tw = tw[2];
-    a.scale = (float)(1.0 / ((double)L[0] * L[1] * L[2]));
-    TK_LAUNCH(launch_fft_pass(a, 1, s));
+    {
+        ProfScope ps(TK_PROF_FFT, s);
+        // P1: axis 2 forward, real rows of m2 -> H2 complex
+        a = FftPassArgs{};
+        a.L = L[2]; a.logL = lg[2]; a.F = fft_fibres_per_block(L[2], 0); a.logF = ilog2(a.F);
+        a.n_inner = m[0] * m[1]; a.len_in = m[2]; a.len_out = H2;
+        a.s_in_o = 0; a.s_in_i = m[2]; a.s_in_k = 1; a.s_out_o = 0; a.s_out_i = H2p; a.s_out_k = 1;
+        a.in = z; a.out = A1; a.in_real = 1; a.out_real = 0; a.mode = 0; a.scale = 1.f; a.tw = tw[2];
+        TK_LAUNCH(launch_fft_pass(a, 1, s));
+        // P2: axis 1 forward, fibres (i0, f2) over i1
+        a = FftPassArgs{};
+        a.L = L[1]; a.logL = lg[1]; a.F = fft_fibres_per_block(L[1], 0); a.logF = ilog2(a.F);
+        a.n_inner = H2; a.len_in = m[1]; a.len_out = L[1];
+        a.s_in_o = (long)m[1] * H2p; a.s_in_i = 1; a.s_in_k = H2p;
+        a.s_out_o = (long)L[1] * H2p; a.s_out_i = 1; a.s_out_k = H2p;
+        a.in = A1; a.out = A2; a.mode = 0; a.scale = 1.f; a.tw = tw[1];
+        TK_LAUNCH(launch_fft_pass(a, m[0], s));
+    }
+    {
+        ProfScope ps(TK_PROF_FFT_AXIS0, s);
+        // P3: axis 0 forward, times chat, inverse; fibres (f1, f2) over i0, in place
+        a = FftPassArgs{};
+        a.L = L[0]; a.logL = lg[0]; a.F = fft_fibres_per_block(L[0], r2p); a.logF = ilog2(a.F);
+        a.n_inner = H2; a.len_in = m[0]; a.len_out = m[0];
+        a.s_in_o = H2p; a.s_in_i = 1; a.s_in_k = (long)L[1] * H2p;
+        a.s_out_o = H2p; a.s_out_i = 1; a.s_out_k = (long)L[1] * H2p;
+        a.in = A2; a.out = A2; a.mode = 3; a.scale = 1.f;
+        a.Hs = Hs; a.Uh3 = Uh3; a.r2p = r2p; a.tw = tw[0];
+        TK_LAUNCH(launch_fft_pass(a, L[1], s));
+    }
+    {
+        ProfScope ps(TK_PROF_FFT, s);
+        // P4: axis 1 inverse, keep i1 < m1
+        a = FftPassArgs{};
+        a.L = L[1]; a.logL = lg[1]; a.F = fft_fibres_per_block(L[1], 0); a.logF = ilog2(a.F);
+        a.n_inner = H2; a.len_in = L[1]; a.len_out = m[1];
+        a.s_in_o = (long)L[1] * H2p; a.s_in_i = 1; a.s_in_k = H2p;
+        a.s_out_o = (long)m[1] * H2p; a.s_out_i = 1; a.s_out_k = H2p;
+        a.in = A2; a.out = A1; a.mode = 1; a.scale = 1.f; a.tw = tw[1];
+        TK_LAUNCH(launch_fft_pass(a, m[0], s));
+        // P5: axis 2 inverse from the half spectrum, real part, keep i2 < m2, scale
+        a = FftPassArgs{};
+        a.L = L[2]; a.logL = lg[2]; a.F = fft_fibres_per_block(L[2], 0); a.logF = ilog2(a.F);
+        a.n_inner = m[0] * m[1]; a.len_in = H2; a.len_out = m[2];
+        a.s_in_o = 0; a.s_in_i = H2p; a.s_in_k = 1; a.s_out_o = 0; a.s_out_i = m[2]; a.s_out_k = 1;
+        a.in = A1; a.out = y; a.out_real = 1; a.mode = 2; a.tw = tw[2];
+        a.scale = (float)(1.0 / ((double)L[0] * L[1] * L[2]));
+        TK_LAUNCH(launch_fft_pass(a, 1, s));
+    }
     if (dot_out) {
         TK_LAUNCH(launch_dot<float>(z, y, M3, dots, 1024, dots + 1024, s));
-        TK_HIP(hipMemcpyAsync(dot_out, dots + 1024, sizeof(double), hipMemcpyDeviceToHost, s));
-        TK_HIP(hipStreamSynchronize(s));
+        tk_status rs = readback(ctx, s, dots + 1024, sizeof(double), dot_out);
+        if (rs != TK_OK) return rs;
     }
     return TK_OK;
 }
@@ -1151,6 +1234,13 @@ tk_status tk_ctx_create(int device, size_t hbm_budget_bytes, tk_ctx** out)
     if (!c) return fail(TK_ENOMEM, "host allocation failed");
     c->device = device;
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)freeb);
+    const size_t slot_bytes = (size_t)tk_ctx::kSlots * tk_ctx::kSlotBytes;
+    if (hipHostMalloc((void**)&c->pinned, slot_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&c->dev_slots, slot_bytes) != hipSuccess) {
+        if (c->pinned) (void)hipHostFree(c->pinned);
+        delete c;
+        return fail(TK_ENOMEM, "staging buffers (%zu bytes)", slot_bytes);
+    }
     *out = c;
     return TK_OK;
 }
@@ -1160,7 +1250,17 @@ void tk_ctx_destroy(tk_ctx* ctx)
     if (!ctx) return;
     hipSetDevice(ctx->device);
     hipDeviceSynchronize();
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->dev_slots) (void)hipFree(ctx->dev_slots);
+    for (hipStream_t st : ctx->streams) (void)hipStreamDestroy(st);
     delete ctx;
+}
+
+tk_status tk_ctx_set_workers(tk_ctx* ctx, int workers)
+{
+    if (!ctx || workers < 1 || workers > 16) return fail(TK_EINVAL, "workers must be in 1..16");
+    ctx->workers = workers;
+    return TK_OK;
 }
 
 tk_status tk_set_matvec_method(tk_ctx* ctx, int method)
@@ -1208,12 +1308,79 @@ tk_status tk_compress_batch(tk_ctx* ctx, int count, const tk_kernel* kernels, co
 {
     if (!ctx || !kernels || !grids || !opts || !outs || count < 0) return fail(TK_EINVAL, "bad batch arguments");
     for (int i = 0; i < count; ++i) outs[i] = nullptr;
+    if (count == 0) return TK_OK;
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    const int W = std::min(count, ctx->workers);
+    std::vector<hipStream_t> ws(W);
+    {
+        std::lock_guard<std::mutex> g(ctx->pool_mu);
+        while ((int)ctx->streams.size() < W) {
+            hipStream_t st;
+            TK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            ctx->streams.push_back(st);
+        }
+        for (int i = 0; i < W; ++i) ws[i] = ctx->streams[i];
+    }
+    // the items start after the work already queued on the caller's stream
+    hipEvent_t fork;
+    TK_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    TK_HIP(hipEventRecord(fork, (hipStream_t)hip_stream));
+    std::atomic<int> next{0};
+    std::mutex mu;
+    std::condition_variable cv;
+    int running = 0;
+    long finished = 0;
+    std::vector<tk_status> st(count, TK_OK);
+    std::vector<std::string> msg(count);
+    auto worker = [&](int wi) {
+        if (hipSetDevice(ctx->device) != hipSuccess) return;
+        hipStream_t s = ws[wi];
+        if (hipStreamWaitEvent(s, fork, 0) != hipSuccess) return;
+        for (;;) {
+            const int i = next.fetch_add(1);
+            if (i >= count) break;
+            for (;;) {
+                long seen;
+                {
+                    std::lock_guard<std::mutex> g(mu);
+                    ++running;
+                    seen = finished;
+                }
+                const tk_status r = compress_any(ctx, &kernels[i], nullptr, &grids[i], opts, s, &outs[i]);
+                bool retry = false;
+                {
+                    std::lock_guard<std::mutex> g(mu);
+                    --running;
+                    // out of budget while others hold memory: wait for one of them, then retry
+                    retry = (r == TK_ENOMEM && (running > 0 || finished != seen));
+                    if (!retry) ++finished;
+                }
+                cv.notify_all();
+                if (retry) {
+                    std::unique_lock<std::mutex> lk(mu);
+                    cv.wait(lk, [&] { return finished != seen || running == 0; });
+                    continue;
+                }
+                st[i] = r;
+                if (r != TK_OK) msg[i] = g_last_error;
+                break;
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    th.reserve(W);
+    for (int i = 0; i < W; ++i) th.emplace_back(worker, i);
+    for (auto& t : th) t.join();
+    (void)hipEventDestroy(fork);
     for (int i = 0; i < count; ++i) {
-        tk_status st = compress_any(ctx, &kernels[i], nullptr, &grids[i], opts, hip_stream, &outs[i]);
-        if (st != TK_OK && st != TK_ENOCONV) {
-            std::string msg = g_last_error;
-            for (int j = 0; j <= i; ++j) { free_result(outs[j]); outs[j] = nullptr; }
-            return fail(st, "batch item %d: %s", i, msg.c_str());
+        if (outs[i] == nullptr && st[i] == TK_OK) {
+            st[i] = TK_EHIP;
+            msg[i] = "worker could not start (hipSetDevice / hipStreamWaitEvent failed)";
+        }
+        if (st[i] != TK_OK && st[i] != TK_ENOCONV) {
+            for (int j = 0; j < count; ++j) { free_result(outs[j]); outs[j] = nullptr; }
+            return fail(st[i], "batch item %d: %s", i, msg[i].c_str());
         }
     }
     return TK_OK;
@@ -1354,15 +1521,15 @@ tk_status tk_trace(tk_ctx* ctx, const tk_tucker* t, void* hip_stream, double* ou
     TK_HIP(hipSetDevice(ctx->device));
     (void)hipGetLastError();
     hipStream_t s = (hipStream_t)hip_stream;
-    void* buf = nullptr;
-    TK_HIP(hipMallocAsync(&buf, 256, s));
+    Slot slot(ctx);
+    if (slot.i < 0) return fail(TK_EHIP, "trace: all %d staging slots busy", tk_ctx::kSlots);
     double scale = (double)m[0] * m[1] * m[2];
     hipError_t e = launch_cov_trace(t->core, t->r[0], t->r[1], t->r[2], t->U[0] + (long)off[0] * t->r[0],
                                     t->U[1] + (long)off[1] * t->r[1], t->U[2] + (long)off[2] * t->r[2], scale,
-                                    (double*)buf, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(out, buf, sizeof(double), hipMemcpyDeviceToHost, s);
-    hipFreeAsync(buf, s);
+                                    (double*)slot.dev(), s);
+    if (e == hipSuccess) e = hipMemcpyAsync(slot.host(), slot.dev(), sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) std::memcpy(out, slot.host(), sizeof(double));
     if (e != hipSuccess) return fail(TK_EHIP, "trace: %s", hipGetErrorString(e));
     return TK_OK;
 }

@@ -56,8 +56,14 @@ struct EigBatch {
     double* U; long sU; int ldu;
     double* lam; long sL;
     double* trace; long sTrace;
+    int span_only;   // 1: warm start with p == r == rw < n; U = orthonormal basis of span(G^iters W), no
+                     // Rayleigh-Ritz (for callers that rotate the factors afterwards)
 };
 hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s);
+// Sign rule on the columns of U (n x r, ld ldu): a column whose entry of largest magnitude (ties
+// within 1e-10 relative, lowest index) is negative is negated, together with column c of V
+// (nv x r, ld ldv).
+hipError_t launch_signfix_pair(double* U, int ldu, int n, double* V, int ldv, int nv, int r, hipStream_t s);
 hipError_t eig_set_attributes();
 
 // ------------------------------------------------------------------- a5/a6: TTM ----
@@ -117,19 +123,21 @@ hipError_t kron_set_attributes();
 
 // ---------------------------------------------------- a8: FFT form of the matvec ----
 struct FftPassArgs {
-    int L, logL, F;            // transform length 2^logL, fibres per work-group
+    int L, logL, F, logF;      // transform length 2^logL, fibres per work-group 2^logF
     int n_inner;               // fibres along the inner index
     int len_in, len_out;       // valid input length (zero padded to L), output length kept
     long s_in_o, s_in_i, s_in_k, s_out_o, s_out_i, s_out_k;   // element strides
     const void* in; void* out;
     int in_real, out_real, mode;
     float scale;
-    const float* Hs; const float* Uh3; int r2, L1;             // mode 3 only
+    const float* Hs; const float* Uh3; int r2p;               // mode 3: Hs[f1][f0][c], Uh3[f2][c], c < r2p
     const float2* tw;                                          // exp(-2 pi i q / L), q < L
 };
 hipError_t launch_twiddles(float2* tw, int L, hipStream_t s);
-size_t fft_lds_bytes(int L, int F, int r2);
-int fft_fibres_per_block(int L, int r2);   // r2: P3 scratch floats per fibre (0 for the other passes)
+size_t fft_lds_bytes(int L, int F, int r2p);
+int fft_fibres_per_block(int L, int r2p);   // r2p: P3 scratch floats per fibre (0 for the other passes)
+hipError_t launch_f64_to_f32_padded(const double* X, long rows, int cols, int cols_pad, float* Y, hipStream_t s);
+hipError_t launch_zero_pad_cols(float* X, long rows, int cols, int cols_pad, hipStream_t s);
 hipError_t launch_fft_pass(const FftPassArgs& a, long n_outer, hipStream_t s);
 hipError_t launch_fourier_factor(const double* U, int r, int off, int m, int L, int nf, double* Uh, hipStream_t s);
 hipError_t fft_set_attributes();

@@ -73,6 +73,7 @@ _SIGS = {
     "tk_gram": (_st, [_vp, _vp, _ip, ctypes.c_int, ctypes.c_int, _vp, _vp]),
     "tk_eig_topr": (_st, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "tk_set_matvec_method": (_st, [_vp, ctypes.c_int]),
+    "tk_ctx_set_workers": (_st, [_vp, ctypes.c_int]),
     "tk_profile_enable": (_st, [ctypes.c_int]),
     "tk_profile_reset": (_st, []),
     "tk_profile_read": (_st, [ctypes.c_int, ctypes.POINTER(ctypes.c_longlong), _dp]),
@@ -273,7 +274,7 @@ def tk_eig_topr(ctx: int, count: int, n: int, r: int, G, lam, U, stream=None) ->
 
 
 PROF_CLASSES = {"grid": 0, "gram": 1, "eig": 2, "ttm": 3, "norm": 4, "toep_right": 5, "toep_left": 6,
-                "small": 7, "fft": 8}
+                "small": 7, "fft": 8, "fft_axis0": 9}
 TK_MV_AUTO, TK_MV_FFT, TK_MV_DENSE = 0, 1, 2
 
 
@@ -360,6 +361,9 @@ class Context:
 
     def set_matvec_method(self, method: int):
         tk_set_matvec_method(self.handle, method)
+
+    def set_workers(self, workers: int):
+        _check(_lib.tk_ctx_set_workers(self.handle, workers), "tk_ctx_set_workers")
 
     def destroy(self):
         if self.handle:
