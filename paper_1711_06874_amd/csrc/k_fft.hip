@@ -19,24 +19,81 @@
 // with H2 = L2/2 + 1.  chat is evaluated on the fly in P3 from Hs[f0][f1][c] = sum_ab
 // G_abc Uh1[f0][a] Uh2[f1][b] and Uh3.
 //
-// Each work-group transforms F fibres of length L together in LDS (F L <= 8192 complex
-// values, two ping-pong buffers): a mixed radix-8/4/2 Stockham autosort FFT, natural order in
-// and out, one radix-R butterfly per thread per stage, twiddles exp(-/+ 2 pi i q / L) from a
-// table computed once per matvec with double-precision sincospi (512-thread work-groups).  Global loads and stores are
-// coalesced: along the fibre when it is contiguous, across neighbouring fibres otherwise.
+// Each fibre is transformed by P = L / V lanes of one wavefront holding V values each (V = 8
+// for 8 <= L <= 512, L / 64 above, L below 8), FW = 64 / P fibres per wavefront.  Lane p keeps
+// the natural-order values X[p + P v] (v < V) in registers.  The FFT is a Stockham autosort
+// of radix-8 stages (then 4 or 2): in stage s (Ns = 8^s) butterfly j = p + P b, b < V / R,
+// takes the natural slots b + (V / R) r, multiplies by exp(-/+ 2 pi i (j mod Ns) r / (Ns R))
+// and writes output r to position (j / Ns) Ns R + (j mod Ns) + r Ns.  The first stage thus reads
+// the natural order straight from registers and the last one leaves it there; the stages in
+// between exchange through the fibre's own LDS buffer with wavefront-level ordering only.
+// Because m <= L / 2 for every axis of the embedding, forward transforms see zeros in the upper
+// half and inverse transforms need only the lower half: both are pruned at compile time.
+//
+// Passes with contiguous fibres (P1, P5) load and store the registers directly (coalesced
+// along the fibre).  Strided passes (P2, P3, P4) stage a tile of F neighbouring fibres
+// (F x 8 bytes per row) through LDS, read and written across fibres.  The transform length
+// is a template parameter (2 <= L <= 2048), so all index arithmetic is compile-time.
 #include "tk_kernels.h"
 
 namespace tk {
 
 namespace {
 
-constexpr int FFT_LDS_COMPLEX = 8192;
-constexpr int FFT_THREADS = 1024;
-constexpr size_t FFT_LDS_MAX = 96 * 1024;
+constexpr int FFT_MAX_LOGL = 11;
 
-// LDS position of complex element x of a block: one spare slot after every 16 values, so the
-// power-of-two strides of the Stockham stages do not pile onto a few banks.
-__device__ __forceinline__ int pd(int x) { return x + (x >> 4); }
+// widest padded Uh3 row of the P3 pass is 48 floats
+template <int LOGL>
+struct Shape {
+    static constexpr int L = 1 << LOGL;
+    static constexpr int V = (L < 8) ? L : (L <= 512 ? 8 : L / 64);   // values per lane
+    static constexpr int P = L / V;                                    // lanes per fibre
+    static constexpr int FW = 64 / P;                                  // fibres per wavefront
+    static constexpr int NW = (L <= 512) ? 16 : 8192 / L;              // wavefronts per work-group
+    static constexpr int NT = 64 * NW;
+    static constexpr int F = NW * FW;                                  // fibres per work-group
+    static constexpr int LB = L + L / 8 + 1;                           // LDS stride between fibre buffers
+    static constexpr int CS = (L + 15) / 16 * 16 + 4;                 // row stride of the multiplier table
+    static constexpr int NS = (LOGL + 2) / 3;                          // stages
+    static constexpr int QT = F * L / NT;                              // tile elements per thread
+    // LDS of the P3 pass: the tile, the spectral multipliers and (when it fits) the Uh3 rows
+    static constexpr size_t LDS_TILE = sizeof(float2) * (size_t)F * LB;
+    static constexpr bool STAGE_U3 = LDS_TILE + sizeof(float) * (size_t)F * (CS + 48) <= 150 * 1024;
+    static constexpr size_t LDS_CORE = LDS_TILE + sizeof(float) * (size_t)F * (CS + (STAGE_U3 ? 48 : 0));
+};
+
+// log2 of the radix of stage s: 3 while at least 3 bits remain, then the rest
+__host__ __device__ constexpr int stage_lr(int logl, int s) { return (logl - 3 * s >= 3) ? 3 : logl - 3 * s; }
+
+// twiddles a lane needs in stages 1..S-1: sum over those stages of (V / R) (R - 1)
+template <int LOGL>
+__host__ __device__ constexpr int tw_offset(int S)
+{
+    int n = 0;
+    for (int s = 1; s < S; ++s) {
+        const int R = 1 << stage_lr(LOGL, s);
+        n += (Shape<LOGL>::V / R) * (R - 1);
+    }
+    return n;
+}
+// In the P3 pass (two transforms per fibre, occupancy already set by its LDS) a lane keeps its
+// twiddles in registers when there are at most 16 of them; the other passes load them per use.
+template <int LOGL, bool WANT>
+struct TwRegs {
+    static constexpr int N = tw_offset<LOGL>(Shape<LOGL>::NS);
+    static constexpr bool IN_REGS = WANT && N <= 16;
+    float2 w[IN_REGS && N > 0 ? N : 1];
+};
+
+// LDS position of element k of a fibre buffer: one spare slot per 8 values
+__device__ __forceinline__ int pos(int k) { return k + (k >> 3); }
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 {
@@ -45,227 +102,368 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 // multiply by -i (forward) or +i (inverse)
-__device__ __forceinline__ float2 cmul_mi(float2 a, bool inv) { return inv ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x); }
+template <bool INV>
+__device__ __forceinline__ float2 cmul_mi(float2 a) { return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x); }
 
-__device__ __forceinline__ void dft2(float2* v)
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2 (&v)[R])
 {
-    const float2 a = v[0], b = v[1];
-    v[0] = cadd(a, b);
-    v[1] = csub(a, b);
-}
-
-__device__ __forceinline__ void dft4(float2* v, bool inv)
-{
-    const float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-    const float2 t2 = cadd(v[1], v[3]), t3 = cmul_mi(csub(v[1], v[3]), inv);
-    v[0] = cadd(t0, t2);
-    v[2] = csub(t0, t2);
-    v[1] = cadd(t1, t3);
-    v[3] = csub(t1, t3);
-}
-
-__device__ __forceinline__ void dft8(float2* v, bool inv)
-{
-    float2 e[4] = {v[0], v[2], v[4], v[6]};
-    float2 o[4] = {v[1], v[3], v[5], v[7]};
-    dft4(e, inv);
-    dft4(o, inv);
-    const float h = 0.70710678118654752f;
-    // o[k] *= W8^k, W8 = exp(-/+ i pi / 4)
-    o[1] = inv ? make_float2(h * (o[1].x - o[1].y), h * (o[1].x + o[1].y))
-               : make_float2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));
-    o[2] = cmul_mi(o[2], inv);
-    o[3] = inv ? make_float2(-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y))
-               : make_float2(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));
-    for (int k = 0; k < 4; ++k) {
-        v[k] = cadd(e[k], o[k]);
-        v[k + 4] = csub(e[k], o[k]);
+    if constexpr (R == 2) {
+        const float2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        const float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        const float2 t2 = cadd(v[1], v[3]), t3 = cmul_mi<INV>(csub(v[1], v[3]));
+        v[0] = cadd(t0, t2);
+        v[2] = csub(t0, t2);
+        v[1] = cadd(t1, t3);
+        v[3] = csub(t1, t3);
+    } else {
+        float2 e[4] = {v[0], v[2], v[4], v[6]};
+        float2 o[4] = {v[1], v[3], v[5], v[7]};
+        dft<4, INV>(e);
+        dft<4, INV>(o);
+        const float h = 0.70710678118654752f;
+        // o[k] *= exp(-/+ i pi k / 4)
+        o[1] = INV ? make_float2(h * (o[1].x - o[1].y), h * (o[1].x + o[1].y))
+                   : make_float2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));
+        o[2] = cmul_mi<INV>(o[2]);
+        o[3] = INV ? make_float2(-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y))
+                   : make_float2(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = cadd(e[k], o[k]);
+            v[k + 4] = csub(e[k], o[k]);
+        }
     }
 }
 
-// One Stockham stage of radix R = 2^LR over F fibres, in place: every thread reads all of its
-// butterflies' inputs into registers (at most FFT_LDS_COMPLEX / FFT_THREADS values), the block
-// synchronises, and the outputs are written to their new positions.  Ns = 2^lns.
-template <int LR>
-__device__ __forceinline__ void stockham_stage(float2* X, const float2* __restrict__ tw, int F, int logL, int lns,
-                                               bool inv)
+template <int LOGL, int S, bool TWR>
+__device__ __forceinline__ void load_twiddles_from(TwRegs<LOGL, TWR>& tr, int p, const float2* __restrict__ tw)
 {
-    constexpr int R = 1 << LR;
-    constexpr int NB = (FFT_LDS_COMPLEX / FFT_THREADS) / R;     // butterflies per thread
-    const int L = 1 << logL;
-    const int Ns = 1 << lns;
-    const int lq = logL - LR;
-    const int Q = 1 << lq;
-    const int nbf = F << lq;
-    float2 v[NB][R];
+    if constexpr (S < Shape<LOGL>::NS) {
+        constexpr int LR = stage_lr(LOGL, S), R = 1 << LR, B = Shape<LOGL>::V / R;
+        constexpr int LNS = 3 * S, TWS = LOGL - LNS - LR;
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const int e = threadIdx.x + FFT_THREADS * b;
-        if (e < nbf) {
-            const int f = e >> lq, j = e & (Q - 1);
-            const int k = j & (Ns - 1);
-            const int sf = f * L;
-            const int twstep = k << (logL - lns - LR);       // q = k r L / (Ns R)
+        for (int b = 0; b < B; ++b) {
+            const int k = (p + Shape<LOGL>::P * b) & ((1 << LNS) - 1);
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                float2 x = X[pd(sf + j + r * Q)];
-                if (r > 0 && k > 0) {
-                    float2 w = tw[(twstep * r) & (L - 1)];
-                    if (inv) w.y = -w.y;
-                    x = cmul(x, w);
-                }
-                v[b][r] = x;
+            for (int r = 1; r < R; ++r) tr.w[tw_offset<LOGL>(S) + b * (R - 1) + (r - 1)] = tw[(k * r) << TWS];
+        }
+        load_twiddles_from<LOGL, S + 1, TWR>(tr, p, tw);
+    }
+}
+
+// Stage S of the transform of the fibre whose buffer is fb, lane p of the fibre.
+template <int LOGL, int S, bool INV, bool HALF_IN, bool TWR>
+__device__ __forceinline__ void fft_stage(float2 (&x)[Shape<LOGL>::V], float2* fb, int p,
+                                          const float2* __restrict__ tw, const TwRegs<LOGL, TWR>& tr)
+{
+    using Sh = Shape<LOGL>;
+    constexpr int V = Sh::V, P = Sh::P;
+    constexpr int LR = stage_lr(LOGL, S), R = 1 << LR, B = V / R;
+    constexpr int LNS = 3 * S, NSZ = 1 << LNS;
+    constexpr bool LAST = (S == Sh::NS - 1);
+    constexpr int TWS = LOGL - LNS - LR;        // twiddle index step: L / (Ns R) = 2^TWS
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int j = p + P * b;
+        const int k = j & (NSZ - 1);
+        float2 u[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            // stage 0 of a forward transform of zero-padded data: the upper half is zero
+            if (HALF_IN && S == 0 && (b + B * r) >= V / 2) {
+                u[r] = make_float2(0.f, 0.f);
+                continue;
             }
-            if (R == 8) dft8(v[b], inv);
-            else if (R == 4) dft4(v[b], inv);
-            else dft2(v[b]);
+            float2 v = x[b + B * r];
+            if (S > 0 && r > 0) {
+                float2 w;
+                if constexpr (TwRegs<LOGL, TWR>::IN_REGS) w = tr.w[tw_offset<LOGL>(S) + b * (R - 1) + (r - 1)];
+                else w = tw[(k * r) << TWS];
+                if (INV) w.y = -w.y;
+                v = cmul(v, w);
+            }
+            u[r] = v;
+        }
+        dft<R, INV>(u);
+        if (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[b + B * r] = u[r];
+        } else {
+            const int base = ((j >> LNS) << (LNS + LR)) + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) fb[pos(base + r * NSZ)] = u[r];
         }
     }
-    __syncthreads();
+    if (!LAST) {
+        wave_sync();
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const int e = threadIdx.x + FFT_THREADS * b;
-        if (e < nbf) {
-            const int f = e >> lq, j = e & (Q - 1);
-            const int k = j & (Ns - 1);
-            const int df = f * L + ((j >> lns) << (lns + LR)) + k;
-#pragma unroll
-            for (int r = 0; r < R; ++r) X[pd(df + (r << lns))] = v[b][r];
-        }
-    }
-    __syncthreads();
-}
-
-// Stockham FFT, in place, of F fibres of length L = 2^logL at X[pd(f * L + k)] (natural order
-// in and out); tw[q] = exp(-2 pi i q / L), q < L.
-__device__ __forceinline__ void fft_lds(float2* X, const float2* tw, int F, int logL, bool inv)
-{
-    int lns = 0, rem = logL;
-    while (rem > 0) {
-        const int lr = (rem >= 3) ? 3 : rem;          // radix 8, then 4 or 2
-        if (lr == 3) stockham_stage<3>(X, tw, F, logL, lns, inv);
-        else if (lr == 2) stockham_stage<2>(X, tw, F, logL, lns, inv);
-        else stockham_stage<1>(X, tw, F, logL, lns, inv);
-        lns += lr;
-        rem -= lr;
+        for (int v = 0; v < V; ++v) x[v] = fb[pos(p + P * v)];
+        wave_sync();
     }
 }
 
-// X[f][f0] *= chat[f0][f1 = o][f2 = i0 + f] = sum_c Hs[o][f0][c] Uh3[i0 + f][c] for f < nf.  Each thread
-// owns frequencies f0 and keeps its Hs row (r2p <= 4 * RB4 floats, zero padded) in registers.
-template <int RB4>
-__device__ __forceinline__ void times_chat(float2* X, int L, int nf, const float* __restrict__ Hs, long o,
-                                           const float* u3s, int r2p)
+template <int LOGL, int S, bool INV, bool HALF_IN, bool TWR>
+__device__ __forceinline__ void fft_stages(float2 (&x)[Shape<LOGL>::V], float2* fb, int p,
+                                           const float2* __restrict__ tw, const TwRegs<LOGL, TWR>& tr)
 {
-    const int n4 = r2p >> 2;
-    for (int f0 = threadIdx.x; f0 < L; f0 += FFT_THREADS) {
-        const float4* h = reinterpret_cast<const float4*>(Hs + ((long)o * L + f0) * r2p);
-        float4 hr[RB4];
+    if constexpr (S < Shape<LOGL>::NS) {
+        fft_stage<LOGL, S, INV, HALF_IN, TWR>(x, fb, p, tw, tr);
+        fft_stages<LOGL, S + 1, INV, HALF_IN, TWR>(x, fb, p, tw, tr);
+    }
+}
+
+// The twiddles exp(-2 pi i (j mod Ns) r / (Ns R)) of lane p in stages 1.. (forward sign).
+template <int LOGL, bool TWR>
+__device__ __forceinline__ void load_twiddles(TwRegs<LOGL, TWR>& tr, int p, const float2* __restrict__ tw)
+{
+    if constexpr (TwRegs<LOGL, TWR>::IN_REGS && TwRegs<LOGL, TWR>::N > 0) {
+        load_twiddles_from<LOGL, 1, TWR>(tr, p, tw);
+    }
+}
+
+// ct[ff][f0] (row stride CS) = chat[f0][o][i0 + ff] = sum_c Uh3[i0 + ff][c] Hs[o][f0][c] for the F
+// fibres of the work-group: an (F x r2p) x (r2p x L) product on mfma_f32_16x16x4f32, 16 x 16
+// output tiles shared out over the wavefronts (operand A: row lane % 16, k lane / 16; B: k
+// lane / 16, column lane % 16; result v of a lane: row 4 (lane / 16) + v, column lane % 16).
+// The Uh3 rows of the work-group are staged in LDS (u3s, F x r2p) when they fit.
+template <int LOGL>
+__device__ __forceinline__ void chat_table(float* ct, float* u3s, long o, int i0, int nf, int r2p,
+                                           const float* __restrict__ Hs, const float* __restrict__ Uh3)
+{
+    using Sh = Shape<LOGL>;
+    constexpr int L = Sh::L, NT = Sh::NT, F = Sh::F, NW = Sh::NW, CS = Sh::CS;
+    constexpr int TR = (F + 15) / 16, TC = (L + 15) / 16;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if constexpr (Sh::STAGE_U3) {
+        for (int e = tid; e < F * r2p; e += NT) u3s[e] = (e < nf * r2p) ? Uh3[(long)i0 * r2p + e] : 0.f;
+        __syncthreads();
+    }
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int t = wv; t < TR * TC; t += NW) {
+        const int tr = t % TR, tc = t / TR;
+        const int ff = 16 * tr + lr, f0 = 16 * tc + lr;
+        const float* urow = Sh::STAGE_U3 ? u3s + (ff < F ? ff : 0) * r2p
+                                         : Uh3 + (long)((ff < nf) ? i0 + ff : i0) * r2p;
+        const float* hrow = Hs + ((long)o * L + (f0 < L ? f0 : 0)) * r2p;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < r2p; ks += 4) {
+            const float av = (ff < F) ? urow[ks + lk] : 0.f;
+            const float bv = (f0 < L) ? hrow[ks + lk] : 0.f;
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+        }
 #pragma unroll
-        for (int c = 0; c < RB4; ++c) hr[c] = (c < n4) ? h[c] : make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int f = 0; f < nf; ++f) {
-            const float4* u = reinterpret_cast<const float4*>(u3s + f * r2p);
-            float chat = 0.f;
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * tr + 4 * lk + v;
+            if (row < F && f0 < L) ct[row * CS + f0] = acc[v];
+        }
+    }
+}
+
+// Pass kinds
+enum { PK_R2C = 0, PK_FWD = 1, PK_CORE = 2, PK_INV = 3, PK_C2R = 4 };
+
+// Chunk c of a pass: F fibres (i0 = (c mod nbx) F, ...) of outer index o = c / nbx.  In the P3
+// pass the work-groups of one XCD (work-group ids are dealt to the 8 XCDs in turn) walk the
+// outer planes o = xcd (mod 8), so that each plane's transformed core is read into one L2.
+struct Chunk {
+    long o;
+    int i0;
+};
+
+template <int F>
+__device__ __forceinline__ bool chunk_at(long j, int nbx, long n_outer, bool xcd_planes, Chunk* ch)
+{
+    const long G = gridDim.x;
+    long c;
+    if (xcd_planes) {
+        const long x = blockIdx.x & 7, slot = blockIdx.x >> 3, nslot = G >> 3;
+        const long q = slot + j * nslot;                       // index within the XCD's planes
+        const long plane = (q / nbx) * 8 + x;
+        if (plane >= n_outer) return false;
+        c = plane * nbx + q % nbx;
+    } else {
+        c = blockIdx.x + j * G;
+        if (c >= (long)nbx * n_outer) return false;
+    }
+    ch->o = c / nbx;
+    ch->i0 = (int)(c % nbx) * F;
+    return true;
+}
+
+template <int LOGL, int PK>
+__global__ void __launch_bounds__(Shape<LOGL>::NT) k_fft_pass(FftPassArgs a)
+{
+    using Sh = Shape<LOGL>;
+    constexpr int L = Sh::L, V = Sh::V, P = Sh::P, F = Sh::F, NT = Sh::NT, LB = Sh::LB;
+    constexpr bool CONTIG = (PK == PK_R2C || PK == PK_C2R);
+    extern __shared__ __attribute__((aligned(16))) float2 fsm[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int q = lane / P, p = lane - q * P;          // fibre within the wavefront, lane within the fibre
+    const int f = wv * Sh::FW + q;                     // fibre within the chunk
+    // contiguous passes pair the rows: n_inner rows make (n_inner + 1) / 2 fibres
+    const int nfib = CONTIG ? (a.n_inner + 1) / 2 : a.n_inner;
+    const int nbx = (nfib + F - 1) / F;
+    const bool xcd_planes = (PK == PK_CORE) && (a.n_outer % 8 == 0) && (gridDim.x % 8 == 0);
+    float2* fb = fsm + f * LB;
+    TwRegs<LOGL, PK == PK_CORE> tr;
+    load_twiddles<LOGL, PK == PK_CORE>(tr, p, a.tw);
+
+    // ---- loads of one chunk into registers: rows of the pair (contiguous) or the tile (strided)
+    constexpr int KIN = (PK == PK_INV) ? L : L / 2;    // forward passes: only the lower half is non-zero
+    constexpr int VIN = (PK == PK_INV) ? V : V / 2;
+    constexpr int NREG = CONTIG ? V : Sh::QT;
+    float2 pre[NREG];
+    auto fetch = [&](const Chunk& ch) {
+        const int nf = (nfib - ch.i0 < F) ? (nfib - ch.i0) : F;
+        if constexpr (CONTIG) {
+            const long ra = 2L * (ch.i0 + f), rb = ra + 1;
+            const bool la = f < nf && ra < a.n_inner, lb = f < nf && rb < a.n_inner;
 #pragma unroll
-            for (int c = 0; c < RB4; ++c) {
-                if (c < n4) {
-                    const float4 w = u[c];
-                    chat += hr[c].x * w.x + hr[c].y * w.y + hr[c].z * w.z + hr[c].w * w.w;
+            for (int v = 0; v < V; ++v) {
+                const int k = p + P * v;
+                pre[v] = make_float2(0.f, 0.f);
+                if constexpr (PK == PK_R2C) {
+                    const float* in = static_cast<const float*>(a.in) + ch.o * a.s_in_o;
+                    if (v < V / 2 && k < a.len_in) {
+                        if (la) pre[v].x = in[ra * a.s_in_i + k];
+                        if (lb) pre[v].y = in[rb * a.s_in_i + k];
+                    }
+                } else {
+                    // half spectra k <= L / 2 given; above it the conjugate of L - k.  Z = Xa + i Xb.
+                    const float2* in = static_cast<const float2*>(a.in) + ch.o * a.s_in_o;
+                    const int kk = (k <= L / 2) ? k : L - k;
+                    const float sg = (k <= L / 2) ? 1.f : -1.f;
+                    float2 xa = make_float2(0.f, 0.f), xb = make_float2(0.f, 0.f);
+                    if (la) xa = in[ra * a.s_in_i + kk];
+                    if (lb) xb = in[rb * a.s_in_i + kk];
+                    pre[v] = make_float2(xa.x - sg * xb.y, sg * xa.y + xb.x);
                 }
             }
-            float2& v = X[pd(f * L + f0)];
-            v = make_float2(v.x * chat, v.y * chat);
+        } else {
+            const float2* in = static_cast<const float2*>(a.in);
+            const long base = ch.o * a.s_in_o + ch.i0;
+#pragma unroll
+            for (int t = 0; t < Sh::QT; ++t) {
+                const int e = tid + NT * t;
+                const int ff = e & (F - 1), k = e / F;
+                pre[t] = make_float2(0.f, 0.f);
+                if (k < KIN && ff < nf && k < a.len_in) pre[t] = in[base + ff + (long)k * a.s_in_k];
+            }
         }
+    };
+
+    Chunk ch;
+    if (!chunk_at<F>(0, nbx, a.n_outer, xcd_planes, &ch)) return;
+    fetch(ch);
+    for (long j = 0;; ++j) {
+        const Chunk cur = ch;
+        const int i0 = cur.i0;
+        const long o = cur.o;
+        const int nf = (nfib - i0 < F) ? (nfib - i0) : F;
+        float2 x[V];
+        if constexpr (CONTIG) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) x[v] = pre[v];
+        } else {
+            __syncthreads();          // the previous chunk has finished reading the tile
+#pragma unroll
+            for (int t = 0; t < Sh::QT; ++t) {
+                const int e = tid + NT * t;
+                const int ff = e & (F - 1), k = e / F;
+                if (k < KIN) fsm[ff * LB + pos(k)] = pre[t];
+            }
+        }
+        // the next chunk's loads are in flight while this one is transformed
+        const bool more = chunk_at<F>(j + 1, nbx, a.n_outer, xcd_planes, &ch);
+        if (more) fetch(ch);
+        if constexpr (!CONTIG) {
+            if constexpr (PK == PK_CORE)
+                chat_table<LOGL>(reinterpret_cast<float*>(fsm + F * LB),
+                                 reinterpret_cast<float*>(fsm + F * LB) + F * Sh::CS, o, i0, nf, a.r2p, a.Hs, a.Uh3);
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < VIN; ++v) x[v] = fb[pos(p + P * v)];
+#pragma unroll
+            for (int v = VIN; v < V; ++v) x[v] = make_float2(0.f, 0.f);
+        }
+
+        // ------------------------------------------------------------ transform(s)
+        if constexpr (PK == PK_R2C || PK == PK_FWD) {
+            fft_stages<LOGL, 0, false, true>(x, fb, p, a.tw, tr);
+        } else if constexpr (PK == PK_CORE) {
+            fft_stages<LOGL, 0, false, true>(x, fb, p, a.tw, tr);
+            const float* ct = reinterpret_cast<const float*>(fsm + F * LB) + f * Sh::CS;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const float c = ct[p + P * v];
+                x[v] = make_float2(x[v].x * c, x[v].y * c);
+            }
+            fft_stages<LOGL, 0, true, false>(x, fb, p, a.tw, tr);
+        } else {
+            fft_stages<LOGL, 0, true, false>(x, fb, p, a.tw, tr);
+        }
+
+        // ------------------------------------------------------------ store
+        if constexpr (CONTIG) {
+            const long ra = 2L * (i0 + f), rb = ra + 1;
+            const bool la = f < nf && ra < a.n_inner, lb = f < nf && rb < a.n_inner;
+            if constexpr (PK == PK_R2C) {
+                // Xa[k] = (Z[k] + conj Z[L-k]) / 2, Xb[k] = (Z[k] - conj Z[L-k]) / (2i), k <= L / 2
+#pragma unroll
+                for (int v = 0; v < V; ++v) fb[pos(p + P * v)] = x[v];
+                wave_sync();
+                float2* out = static_cast<float2*>(a.out) + o * a.s_out_o;
+#pragma unroll
+                for (int v = 0; v <= V / 2 && v < V; ++v) {
+                    const int k = p + P * v;
+                    if (k <= L / 2 && k < a.len_out) {
+                        const float2 zm = fb[pos((L - k) & (L - 1))];
+                        const float2 z = x[v];
+                        if (la) out[ra * a.s_out_i + k] = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+                        if (lb) out[rb * a.s_out_i + k] = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
+                    }
+                }
+                wave_sync();          // the buffer is rewritten by the next chunk's first stage
+            } else {
+                float* out = static_cast<float*>(a.out) + o * a.s_out_o;
+#pragma unroll
+                for (int v = 0; v < V / 2; ++v) {
+                    const int k = p + P * v;
+                    if (k < a.len_out) {
+                        if (la) out[ra * a.s_out_i + k] = x[v].x * a.scale;
+                        if (lb) out[rb * a.s_out_i + k] = x[v].y * a.scale;
+                    }
+                }
+            }
+        } else {
+            // forward passes keep all L outputs; inverse ones the lower half
+            constexpr int VOUT = (PK == PK_FWD) ? V : V / 2;
+            constexpr int KOUT = (PK == PK_FWD) ? L : L / 2;
+#pragma unroll
+            for (int v = 0; v < VOUT; ++v) fb[pos(p + P * v)] = x[v];
+            __syncthreads();
+            float2* out = static_cast<float2*>(a.out);
+            const long base = o * a.s_out_o + i0;
+#pragma unroll
+            for (int t = 0; t < Sh::QT; ++t) {
+                const int e = tid + NT * t;
+                const int ff = e & (F - 1), k = e / F;
+                if (k < KOUT && ff < nf && k < a.len_out) {
+                    const float2 v = fsm[ff * LB + pos(k)];
+                    out[base + ff + (long)k * a.s_out_k] = make_float2(v.x * a.scale, v.y * a.scale);
+                }
+            }
+        }
+        if (!more) break;
     }
 }
 
 }  // namespace
-
-// One pass over F fibres per work-group, fibre f = i0 + f_local (i0 = blockIdx.x * F), outer index
-// o = blockIdx.y.  Element k of a fibre sits at
-//   CONTIG:   base + o * s_o + f * s_i + k          (rows; P1 and P5)
-//   !CONTIG:  base + o * s_o + f + k * s_k          (neighbouring fibres adjacent; P2, P3, P4)
-// MODE 0: forward (real input when IN_REAL);  1: inverse;  2: inverse from the half spectrum
-// (len_in = L/2 + 1, Hermitian extension), real output times scale;  3: forward, times chat,
-// inverse (P3).  Inputs beyond len_in are zero; the first len_out outputs are stored.
-template <int MODE, bool IN_REAL, bool CONTIG>
-__global__ void __launch_bounds__(FFT_THREADS) k_fft_pass(FftPassArgs a)
-{
-    extern __shared__ __attribute__((aligned(16))) float2 fsm[];
-    constexpr int NT = FFT_THREADS;
-    constexpr int QMAX = FFT_LDS_COMPLEX / FFT_THREADS;
-    const int L = a.L, logL = a.logL, F = a.F, logF = a.logF;
-    const int FL = F << logL;
-    float2* tw = fsm;
-    float2* X = fsm + L;
-    const long o = blockIdx.y;
-    const int i0 = blockIdx.x * F;
-    const int nf = (a.n_inner - i0 < F) ? (a.n_inner - i0) : F;
-    const int tid = threadIdx.x;
-    const int len_in = a.len_in;
-    // ---- every global load is issued first (zero for padding and for fibres past the end)
-    float2 buf[QMAX];
-#pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
-        const int e = tid + NT * q;
-        const int f = CONTIG ? (e >> logL) : (e & (F - 1));
-        const int k = CONTIG ? (e & (L - 1)) : (e >> logF);
-        buf[q] = make_float2(0.f, 0.f);
-        if (e < FL && f < nf && k < len_in) {
-            const long idx = CONTIG ? o * a.s_in_o + (long)(i0 + f) * a.s_in_i + k
-                                    : o * a.s_in_o + (i0 + f) + (long)k * a.s_in_k;
-            if (IN_REAL) buf[q].x = static_cast<const float*>(a.in)[idx];
-            else buf[q] = static_cast<const float2*>(a.in)[idx];
-        }
-    }
-    for (int q = tid; q < L; q += NT) tw[q] = a.tw[q];
-    float* u3s = reinterpret_cast<float*>(X + pd(FL));
-    if (MODE == 3) {
-        const int r2p = a.r2p;
-        for (int e = tid; e < F * r2p; e += NT) u3s[e] = (e < nf * r2p) ? a.Uh3[(long)i0 * r2p + e] : 0.f;
-    }
-#pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
-        const int e = tid + NT * q;
-        const int f = CONTIG ? (e >> logL) : (e & (F - 1));
-        const int k = CONTIG ? (e & (L - 1)) : (e >> logF);
-        if (e < FL) {
-            if (MODE == 2) {
-                // half spectrum: k <= L/2 given, L - k filled with the conjugate
-                if (k < len_in) {
-                    X[pd(f * L + k)] = buf[q];
-                    if (k > 0 && k < (L >> 1)) X[pd(f * L + (L - k))] = make_float2(buf[q].x, -buf[q].y);
-                }
-            } else {
-                X[pd(f * L + k)] = buf[q];
-            }
-        }
-    }
-    __syncthreads();
-    fft_lds(X, tw, F, logL, MODE == 1 || MODE == 2);
-    if (MODE == 3) {
-        if (a.r2p <= 16) times_chat<4>(X, L, nf, a.Hs, o, u3s, a.r2p);
-        else if (a.r2p <= 32) times_chat<8>(X, L, nf, a.Hs, o, u3s, a.r2p);
-        else times_chat<12>(X, L, nf, a.Hs, o, u3s, a.r2p);
-        __syncthreads();
-        fft_lds(X, tw, F, logL, true);
-    }
-    // ---- store the first len_out entries of each fibre
-    const int len_out = a.len_out;
-#pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
-        const int e = tid + NT * q;
-        const int f = CONTIG ? (e >> logL) : (e & (F - 1));
-        const int k = CONTIG ? (e & (L - 1)) : (e >> logF);
-        if (e < FL && f < nf && k < len_out) {
-            const float2 v = X[pd(f * L + k)];
-            const long idx = CONTIG ? o * a.s_out_o + (long)(i0 + f) * a.s_out_i + k
-                                    : o * a.s_out_o + (i0 + f) + (long)k * a.s_out_k;
-            if (MODE == 2) static_cast<float*>(a.out)[idx] = v.x * a.scale;
-            else static_cast<float2*>(a.out)[idx] = make_float2(v.x * a.scale, v.y * a.scale);
-        }
-    }
-}
 
 // tw[q] = exp(-2 pi i q / L) for q < L, from double-precision sincospi.
 __global__ void k_twiddles(float2* tw, int L)
@@ -303,51 +501,6 @@ __global__ void __launch_bounds__(256) k_fourier_factor(const double* __restrict
         s += u[(long)t * r] * ctab[ph];
     }
     Uh[e] = u[0] + 2.0 * s;
-}
-
-size_t fft_lds_bytes(int L, int F, int r2p)
-{
-    const size_t fl = (size_t)F * L;
-    // twiddles, the data (padded), and F * r2p floats of Uh3 rows for the P3 pass
-    return sizeof(float2) * ((size_t)L + fl + (fl >> 4)) + sizeof(float) * (size_t)F * r2p;
-}
-
-int fft_fibres_per_block(int L, int r2p)
-{
-    int F = FFT_LDS_COMPLEX / L;
-    if (F > FFT_THREADS) F = FFT_THREADS;
-    if (F < 1) F = 1;
-    while (F > 1 && fft_lds_bytes(L, F, r2p) > FFT_LDS_MAX) F >>= 1;
-    return F;
-}
-
-namespace {
-template <int MODE, bool IN_REAL, bool CONTIG>
-hipError_t launch_pass_t(const FftPassArgs& a, long n_outer, size_t lds, hipStream_t s)
-{
-    dim3 grid((unsigned)((a.n_inner + a.F - 1) / a.F), (unsigned)n_outer);
-    hipLaunchKernelGGL((k_fft_pass<MODE, IN_REAL, CONTIG>), grid, dim3(FFT_THREADS), lds, s, a);
-    return hipGetLastError();
-}
-}  // namespace
-
-hipError_t launch_fft_pass(const FftPassArgs& a, long n_outer, hipStream_t s)
-{
-    if (a.L < 2 || (1 << a.logL) != a.L || a.F < 1 || (1 << a.logF) != a.F || a.F * a.L > FFT_LDS_COMPLEX ||
-        a.F > FFT_THREADS || n_outer < 1 || a.n_inner < 1 || a.len_in > a.L || a.len_out > a.L)
-        return hipErrorInvalidValue;
-    const bool contig_in = a.s_in_k == 1, contig_out = a.s_out_k == 1;
-    if (contig_in != contig_out || (!contig_in && (a.s_in_i != 1 || a.s_out_i != 1))) return hipErrorInvalidValue;
-    if (a.mode == 3 && (a.r2p < 4 || (a.r2p & 3) || a.r2p > 48)) return hipErrorInvalidValue;
-    if (a.mode == 2 && a.len_in != a.L / 2 + 1) return hipErrorInvalidValue;
-    const size_t lds = fft_lds_bytes(a.L, a.F, a.mode == 3 ? a.r2p : 0);
-    if (lds > FFT_LDS_MAX) return hipErrorInvalidValue;
-    if (a.mode == 0 && a.in_real && contig_in) return launch_pass_t<0, true, true>(a, n_outer, lds, s);
-    if (a.mode == 0 && !a.in_real && !contig_in) return launch_pass_t<0, false, false>(a, n_outer, lds, s);
-    if (a.mode == 1 && !a.in_real && !contig_in) return launch_pass_t<1, false, false>(a, n_outer, lds, s);
-    if (a.mode == 2 && !a.in_real && contig_in) return launch_pass_t<2, false, true>(a, n_outer, lds, s);
-    if (a.mode == 3 && !a.in_real && !contig_in) return launch_pass_t<3, false, false>(a, n_outer, lds, s);
-    return hipErrorInvalidValue;
 }
 
 // Y[i][c] = c < cols ? (float)X[i * cols + c] : 0 for c < cols_pad.
@@ -396,16 +549,111 @@ hipError_t launch_fourier_factor(const double* U, int r, int off, int m, int L, 
     return hipGetLastError();
 }
 
-hipError_t fft_set_attributes()
+namespace {
+// resident work-groups per CU of each pass (from the occupancy calculator) and the CU count,
+// filled when the attributes are set; the passes run persistent grids of that size
+int g_resident[FFT_MAX_LOGL + 1][5];
+int g_cus = 0;
+
+template <int LOGL>
+hipError_t launch_len(FftPassArgs a, int kind, long n_outer, hipStream_t s)
 {
-    const void* ks[] = {(const void*)k_fft_pass<0, true, true>, (const void*)k_fft_pass<0, false, false>,
-                        (const void*)k_fft_pass<1, false, false>, (const void*)k_fft_pass<2, false, true>,
-                        (const void*)k_fft_pass<3, false, false>};
-    for (const void* k : ks) {
-        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)FFT_LDS_MAX);
+    using Sh = Shape<LOGL>;
+    const int nfib = (kind == PK_R2C || kind == PK_C2R) ? (a.n_inner + 1) / 2 : a.n_inner;
+    const long chunks = (long)((nfib + Sh::F - 1) / Sh::F) * n_outer;
+    const int per_cu = g_resident[LOGL][kind] > 0 ? g_resident[LOGL][kind] : 1;
+    const long slots = (long)(g_cus > 0 ? g_cus : 256) * per_cu;
+    const dim3 grid((unsigned)(chunks < slots ? chunks : slots));
+    a.n_outer = n_outer;
+    const size_t lds = (kind == PK_CORE) ? Sh::LDS_CORE : Sh::LDS_TILE;
+    switch (kind) {
+    case PK_R2C: hipLaunchKernelGGL((k_fft_pass<LOGL, PK_R2C>), grid, dim3(Sh::NT), lds, s, a); break;
+    case PK_FWD: hipLaunchKernelGGL((k_fft_pass<LOGL, PK_FWD>), grid, dim3(Sh::NT), lds, s, a); break;
+    case PK_INV: hipLaunchKernelGGL((k_fft_pass<LOGL, PK_INV>), grid, dim3(Sh::NT), lds, s, a); break;
+    case PK_C2R: hipLaunchKernelGGL((k_fft_pass<LOGL, PK_C2R>), grid, dim3(Sh::NT), lds, s, a); break;
+    default: hipLaunchKernelGGL((k_fft_pass<LOGL, PK_CORE>), grid, dim3(Sh::NT), lds, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <int LOGL>
+hipError_t set_attrs_len()
+{
+    using Sh = Shape<LOGL>;
+    const int lds = (int)Sh::LDS_TILE;
+    const int lds_core = (int)Sh::LDS_CORE;
+    const void* ks[] = {(const void*)k_fft_pass<LOGL, PK_R2C>, (const void*)k_fft_pass<LOGL, PK_FWD>,
+                        (const void*)k_fft_pass<LOGL, PK_CORE>, (const void*)k_fft_pass<LOGL, PK_INV>,
+                        (const void*)k_fft_pass<LOGL, PK_C2R>};
+    for (int i = 0; i < 5; ++i) {
+        const int bytes = (i == PK_CORE) ? lds_core : lds;
+        hipError_t e = hipFuncSetAttribute(ks[i], hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
+        int nb = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ks[i], Sh::NT, (size_t)bytes);
+        if (e != hipSuccess) return e;
+        g_resident[LOGL][i] = nb > 0 ? nb : 1;
     }
     return hipSuccess;
+}
+
+template <int LOGL>
+hipError_t set_attrs_upto()
+{
+    hipError_t e = set_attrs_len<LOGL>();
+    if constexpr (LOGL > 1) {
+        if (e == hipSuccess) e = set_attrs_upto<LOGL - 1>();
+    }
+    return e;
+}
+}  // namespace
+
+int fft_fibres_per_block(int L)
+{
+    int F = 8192 / L;
+    return F > 1024 ? 1024 : F;
+}
+
+hipError_t launch_fft_pass(const FftPassArgs& a, long n_outer, hipStream_t s)
+{
+    const int L = a.L;
+    if (a.logL < 1 || a.logL > FFT_MAX_LOGL || L != (1 << a.logL) || n_outer < 1 || a.n_inner < 1 ||
+        a.len_in < 1 || a.len_out < 1 || !a.in || !a.out || !a.tw)
+        return hipErrorInvalidValue;
+    const bool contig = a.s_in_k == 1 && a.s_out_k == 1;
+    const bool strided = a.s_in_i == 1 && a.s_out_i == 1 && !contig;
+    int kind;
+    if (a.mode == 0 && a.in_real && contig && a.len_in <= L / 2 && a.len_out <= L / 2 + 1) kind = PK_R2C;
+    else if (a.mode == 0 && !a.in_real && strided && a.len_in <= L / 2 && a.len_out <= L) kind = PK_FWD;
+    else if (a.mode == 3 && !a.in_real && strided && a.len_in <= L / 2 && a.len_out <= L / 2 && a.Hs && a.Uh3 &&
+             a.r2p >= 4 && a.r2p <= 48 && (a.r2p & 3) == 0)
+        kind = PK_CORE;
+    else if (a.mode == 1 && !a.in_real && strided && a.len_in <= L && a.len_out <= L / 2) kind = PK_INV;
+    else if (a.mode == 2 && !a.in_real && contig && a.len_in == L / 2 + 1 && a.len_out <= L / 2) kind = PK_C2R;
+    else return hipErrorInvalidValue;
+    switch (a.logL) {
+    case 1: return launch_len<1>(a, kind, n_outer, s);
+    case 2: return launch_len<2>(a, kind, n_outer, s);
+    case 3: return launch_len<3>(a, kind, n_outer, s);
+    case 4: return launch_len<4>(a, kind, n_outer, s);
+    case 5: return launch_len<5>(a, kind, n_outer, s);
+    case 6: return launch_len<6>(a, kind, n_outer, s);
+    case 7: return launch_len<7>(a, kind, n_outer, s);
+    case 8: return launch_len<8>(a, kind, n_outer, s);
+    case 9: return launch_len<9>(a, kind, n_outer, s);
+    case 10: return launch_len<10>(a, kind, n_outer, s);
+    default: return launch_len<11>(a, kind, n_outer, s);
+    }
+}
+
+hipError_t fft_set_attributes()
+{
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    g_cus = cus;
+    return set_attrs_upto<FFT_MAX_LOGL>();
 }
 
 }  // namespace tk

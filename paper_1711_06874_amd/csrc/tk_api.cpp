@@ -1096,14 +1096,14 @@ tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, 
         ProfScope ps(TK_PROF_FFT, s);
         // P1: axis 2 forward, real rows of m2 -> H2 complex
         a = FftPassArgs{};
-        a.L = L[2]; a.logL = lg[2]; a.F = fft_fibres_per_block(L[2], 0); a.logF = ilog2(a.F);
+        a.L = L[2]; a.logL = lg[2];
         a.n_inner = m[0] * m[1]; a.len_in = m[2]; a.len_out = H2;
         a.s_in_o = 0; a.s_in_i = m[2]; a.s_in_k = 1; a.s_out_o = 0; a.s_out_i = H2p; a.s_out_k = 1;
         a.in = z; a.out = A1; a.in_real = 1; a.out_real = 0; a.mode = 0; a.scale = 1.f; a.tw = tw[2];
         TK_LAUNCH(launch_fft_pass(a, 1, s));
         // P2: axis 1 forward, fibres (i0, f2) over i1
         a = FftPassArgs{};
-        a.L = L[1]; a.logL = lg[1]; a.F = fft_fibres_per_block(L[1], 0); a.logF = ilog2(a.F);
+        a.L = L[1]; a.logL = lg[1];
         a.n_inner = H2; a.len_in = m[1]; a.len_out = L[1];
         a.s_in_o = (long)m[1] * H2p; a.s_in_i = 1; a.s_in_k = H2p;
         a.s_out_o = (long)L[1] * H2p; a.s_out_i = 1; a.s_out_k = H2p;
@@ -1114,7 +1114,7 @@ tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, 
         ProfScope ps(TK_PROF_FFT_AXIS0, s);
         // P3: axis 0 forward, times chat, inverse; fibres (f1, f2) over i0, in place
         a = FftPassArgs{};
-        a.L = L[0]; a.logL = lg[0]; a.F = fft_fibres_per_block(L[0], r2p); a.logF = ilog2(a.F);
+        a.L = L[0]; a.logL = lg[0];
         a.n_inner = H2; a.len_in = m[0]; a.len_out = m[0];
         a.s_in_o = H2p; a.s_in_i = 1; a.s_in_k = (long)L[1] * H2p;
         a.s_out_o = H2p; a.s_out_i = 1; a.s_out_k = (long)L[1] * H2p;
@@ -1126,7 +1126,7 @@ tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, 
         ProfScope ps(TK_PROF_FFT, s);
         // P4: axis 1 inverse, keep i1 < m1
         a = FftPassArgs{};
-        a.L = L[1]; a.logL = lg[1]; a.F = fft_fibres_per_block(L[1], 0); a.logF = ilog2(a.F);
+        a.L = L[1]; a.logL = lg[1];
         a.n_inner = H2; a.len_in = L[1]; a.len_out = m[1];
         a.s_in_o = (long)L[1] * H2p; a.s_in_i = 1; a.s_in_k = H2p;
         a.s_out_o = (long)m[1] * H2p; a.s_out_i = 1; a.s_out_k = H2p;
@@ -1134,7 +1134,7 @@ tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, 
         TK_LAUNCH(launch_fft_pass(a, m[0], s));
         // P5: axis 2 inverse from the half spectrum, real part, keep i2 < m2, scale
         a = FftPassArgs{};
-        a.L = L[2]; a.logL = lg[2]; a.F = fft_fibres_per_block(L[2], 0); a.logF = ilog2(a.F);
+        a.L = L[2]; a.logL = lg[2];
         a.n_inner = m[0] * m[1]; a.len_in = H2; a.len_out = m[2];
         a.s_in_o = 0; a.s_in_i = H2p; a.s_in_k = 1; a.s_out_o = 0; a.s_out_i = m[2]; a.s_out_k = 1;
         a.in = A1; a.out = y; a.out_real = 1; a.mode = 2; a.tw = tw[2];

@@ -123,8 +123,9 @@ hipError_t kron_set_attributes();
 
 // ---------------------------------------------------- a8: FFT form of the matvec ----
 struct FftPassArgs {
-    int L, logL, F, logF;      // transform length 2^logL, fibres per work-group 2^logF
+    int L, logL;               // transform length 2^logL (2 <= L <= 2048)
     int n_inner;               // fibres along the inner index
+    long n_outer;              // outer index range (set by launch_fft_pass)
     int len_in, len_out;       // valid input length (zero padded to L), output length kept
     long s_in_o, s_in_i, s_in_k, s_out_o, s_out_i, s_out_k;   // element strides
     const void* in; void* out;
@@ -134,8 +135,7 @@ struct FftPassArgs {
     const float2* tw;                                          // exp(-2 pi i q / L), q < L
 };
 hipError_t launch_twiddles(float2* tw, int L, hipStream_t s);
-size_t fft_lds_bytes(int L, int F, int r2p);
-int fft_fibres_per_block(int L, int r2p);   // r2p: P3 scratch floats per fibre (0 for the other passes)
+int fft_fibres_per_block(int L);            // fibres one work-group of a pass transforms
 hipError_t launch_f64_to_f32_padded(const double* X, long rows, int cols, int cols_pad, float* Y, hipStream_t s);
 hipError_t launch_zero_pad_cols(float* X, long rows, int cols, int cols_pad, hipStream_t s);
 hipError_t launch_fft_pass(const FftPassArgs& a, long n_outer, hipStream_t s);
