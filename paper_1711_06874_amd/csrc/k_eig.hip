@@ -294,39 +294,109 @@ __global__ void __launch_bounds__(256) k_jacobi(const double* __restrict__ Hin, 
 
 
 // ---------------------------------------------------------------------------------------------
-// Householder QR with each row of the n x p block held in one thread's registers (n <= NT,
-// p <= PM).  Per column one block reduction gives both the squared norm below the diagonal and
-// the products of that part of the column with every later column:
-//     S[c] = sum_{i > j} W[i][j] W[i][c],  c = j..p-1,
-// so with scale = 1 / (alpha - beta) the reflector v = (1, scale W[j+1:, j]) satisfies
-// v^T W[j:, c] = W[j][c] + scale S[c].  The reduction goes through an LDS transpose T[c][i]
-// (two barriers).  The explicit Q is then accumulated backwards in the same registers.
-
-// S[c] = sum_i x_i w_i[c] for c in [c0, p): x is this thread's multiplier (0 for rows that take
-// no part).  T holds PM x NT doubles.
-template <int PM, int NT>
-__device__ __forceinline__ void block_col_sums(double* T, double* S, const double (&w)[PM], double x, int c0, int p)
+// S[c] = sum_i x_i w_i[c] for C0 <= c < PM: x is this thread's multiplier (0 for rows that take
+// no part).  T holds PM x NT doubles.  Everything but the row index is compile-time.
+template <int PM, int NT, int C0>
+__device__ __forceinline__ void block_col_sums(double* T, double* S, const double (&w)[PM], double x)
 {
     const int t = threadIdx.x;
 #pragma unroll
-    for (int c = 0; c < PM; ++c)
-        if (c >= c0 && c < p) T[c * NT + t] = x * w[c];
+    for (int c = C0; c < PM; ++c) T[c * NT + t] = x * w[c];
     __syncthreads();
-    const int nc = p - c0;
-    int G = 64;
-    while (G > 1 && G * nc > NT) G >>= 1;
-    const int c = c0 + t / G, g = t & (G - 1);
+    constexpr int NC = PM - C0;
+    constexpr int G = (NC * 64 <= NT) ? 64 : (NC * 32 <= NT ? 32 : (NC * 16 <= NT ? 16 : (NC * 8 <= NT ? 8 : (NC * 4 <= NT ? 4 : (NC * 2 <= NT ? 2 : 1)))));
+    const int ci = t / G, g = t & (G - 1);
     double acc = 0.0;
-    if (t / G < nc) {
-        const double* row = T + c * NT;
-#pragma unroll 4
-        for (int k = g; k < NT; k += G) acc += row[k];
+    if (ci < NC) {
+        // four independent partial sums keep the dependent chain short
+        const double* row = T + (C0 + ci) * NT;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        constexpr int NK = NT / G;
+#pragma unroll
+        for (int q = 0; q + 3 < NK; q += 4) {
+            a0 += row[g + q * G];
+            a1 += row[g + (q + 1) * G];
+            a2 += row[g + (q + 2) * G];
+            a3 += row[g + (q + 3) * G];
+        }
+#pragma unroll
+        for (int q = NK - NK % 4; q < NK; ++q) a0 += row[g + q * G];
+        acc = (a0 + a1) + (a2 + a3);
     }
+#pragma unroll
     for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (t / G < nc && g == 0) S[c] = acc;
+    if (ci < NC && g == 0) S[C0 + ci] = acc;
     __syncthreads();
 }
 
+// Householder step for column J (rows in registers, columns >= p are zero and stay zero).
+template <int PM, int NT, int J>
+__device__ __forceinline__ void qr_forward(double (&w)[PM], double* T, double* S, double (*rowjb)[PM], double* taus,
+                                           int n, int p)
+{
+    if constexpr (J < PM) {
+        if (J >= p) return;
+        const int i = threadIdx.x;
+        const bool live = i < n;
+        const double x = w[J];
+        double* rowj = rowjb[J & 1];
+        if (i == J) {
+#pragma unroll
+            for (int c = 0; c < PM; ++c) rowj[c] = w[c];
+        }
+        block_col_sums<PM, NT, J>(T, S, w, (live && i > J) ? x : 0.0);
+        const double xn2 = S[J];
+        const double alpha = rowj[J];
+        double t = 0.0, scale = 0.0, beta = alpha;
+        if (xn2 > 0.0) {
+            const double nrm = sqrt(alpha * alpha + xn2);
+            beta = (alpha >= 0.0) ? -nrm : nrm;
+            t = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        if (i == 0) taus[J] = t;
+        const double v = (i == J) ? 1.0 : ((live && i > J) ? x * scale : 0.0);
+        const double tv = t * v;
+#pragma unroll
+        for (int c = J + 1; c < PM; ++c) w[c] -= tv * (rowj[c] + scale * S[c]);
+        // column J: beta on the diagonal, the scaled reflector below it
+        w[J] = (i == J) ? beta : ((i > J) ? x * scale : x);
+        qr_forward<PM, NT, J + 1>(w, T, S, rowjb, taus, n, p);
+    }
+}
+
+// Explicit Q, column J (from the last reflector to the first, in place).
+template <int PM, int NT, int J>
+__device__ __forceinline__ void qr_backward(double (&w)[PM], double* T, double* S, const double* taus, int n, int p)
+{
+    if constexpr (J >= 0) {
+        if (J < p) {
+            const int i = threadIdx.x;
+            const double v = (i == J) ? 1.0 : ((i < n && i > J) ? w[J] : 0.0);
+            const double t = taus[J];
+            if constexpr (J + 1 < PM) {
+                if (J + 1 < p) {
+                    block_col_sums<PM, NT, J + 1>(T, S, w, v);
+                    const double tv = t * v;
+#pragma unroll
+                    for (int c = J + 1; c < PM; ++c) w[c] -= tv * S[c];
+                }
+            }
+            w[J] = (i < J) ? 0.0 : ((i == J) ? 1.0 - t : -t * v);
+        }
+        qr_backward<PM, NT, J - 1>(w, T, S, taus, n, p);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Householder QR with each row of the n x p block held in one thread's registers (n <= NT,
+// p <= PM, columns p..PM-1 carried as zeros).  Per column one block reduction gives both the
+// squared norm below the diagonal and the products of that part of the column with every later
+// column:  S[c] = sum_{i > j} W[i][j] W[i][c],  so with scale = 1 / (alpha - beta) the reflector
+// v = (1, scale W[j+1:, j]) satisfies  v^T W[j:, c] = W[j][c] + scale S[c].  The reduction goes
+// through an LDS transpose T[c][i] (two barriers).  The column loop is unrolled at compile
+// time, so every register index is static.  The explicit Q is then accumulated backwards in
+// the same registers.
 template <int PM, int NT>
 __global__ void __launch_bounds__(NT) k_hqr_reg(const double* __restrict__ In, double* __restrict__ Out, int n, int p)
 {
@@ -340,61 +410,8 @@ __global__ void __launch_bounds__(NT) k_hqr_reg(const double* __restrict__ In, d
     double w[PM];
 #pragma unroll
     for (int c = 0; c < PM; ++c) w[c] = (live && c < p) ? In[off + (long)i * p + c] : 0.0;
-
-    for (int j = 0; j < p; ++j) {
-        double x = 0.0;
-#pragma unroll
-        for (int c = 0; c < PM; ++c)
-            if (c == j) x = w[c];
-        double* rowj = rowjb[j & 1];
-        if (i == j) {
-#pragma unroll
-            for (int c = 0; c < PM; ++c) rowj[c] = w[c];
-        }
-        block_col_sums<PM, NT>(T, S, w, (live && i > j) ? x : 0.0, j, p);
-        const double xn2 = S[j];
-        const double alpha = rowj[j];
-        double t = 0.0, scale = 0.0, beta = alpha;
-        if (xn2 > 0.0) {
-            const double nrm = sqrt(alpha * alpha + xn2);
-            beta = (alpha >= 0.0) ? -nrm : nrm;
-            t = (beta - alpha) / beta;
-            scale = 1.0 / (alpha - beta);
-        }
-        if (i == 0) taus[j] = t;
-        const double v = (i == j) ? 1.0 : ((live && i > j) ? x * scale : 0.0);
-        if (t != 0.0) {
-#pragma unroll
-            for (int c = 0; c < PM; ++c)
-                if (c > j && c < p) w[c] -= t * v * (rowj[c] + scale * S[c]);
-        }
-        // column j: beta on the diagonal, the scaled reflector below it
-        const double nj = (i == j) ? beta : ((i > j) ? x * scale : x);
-#pragma unroll
-        for (int c = 0; c < PM; ++c)
-            if (c == j) w[c] = nj;
-    }
-    // explicit Q, from the last reflector to the first, in place
-    for (int j = p - 1; j >= 0; --j) {
-        double x = 0.0;
-#pragma unroll
-        for (int c = 0; c < PM; ++c)
-            if (c == j) x = w[c];
-        const double v = (i == j) ? 1.0 : ((live && i > j) ? x : 0.0);
-        const double t = taus[j];
-        if (j + 1 < p) {
-            block_col_sums<PM, NT>(T, S, w, v, j + 1, p);
-            if (t != 0.0) {
-#pragma unroll
-                for (int c = 0; c < PM; ++c)
-                    if (c > j && c < p) w[c] -= t * v * S[c];
-            }
-        }
-        const double qj = (i < j) ? 0.0 : ((i == j) ? 1.0 - t : -t * v);
-#pragma unroll
-        for (int c = 0; c < PM; ++c)
-            if (c == j) w[c] = qj;
-    }
+    qr_forward<PM, NT, 0>(w, T, S, rowjb, taus, n, p);
+    qr_backward<PM, NT, PM - 1>(w, T, S, taus, n, p);
     if (live) {
 #pragma unroll
         for (int c = 0; c < PM; ++c)
@@ -409,6 +426,10 @@ __global__ void __launch_bounds__(NT) k_hqr_reg(const double* __restrict__ In, d
 // diagonal blocks by the closed form (a_pp - t a_pq, a_qq + t a_pq, 0), and the rows of V by
 // V J.  Stops when off(H) <= max(tol, p u) ||H||_F or after max_sweeps sweeps.
 constexpr int JW_PMAX = 32;
+constexpr int JW_NP = JW_PMAX / 2;                          // pairs per step
+constexpr int JW_NBLK = JW_NP * (JW_NP + 1) / 2;            // 2 x 2 blocks (P <= Q)
+constexpr int JW_BPL = (JW_NBLK + 63) / 64;                 // blocks per lane
+constexpr int JW_VPL = JW_NP / 2;                           // V pairs per lane
 
 __global__ void __launch_bounds__(64) k_jacobi_w(const double* __restrict__ Hin, long sH, int p, int r,
                                                  double* __restrict__ Vs, long sV, int ldv, double* __restrict__ lam,
@@ -416,8 +437,9 @@ __global__ void __launch_bounds__(64) k_jacobi_w(const double* __restrict__ Hin,
 {
     __shared__ double H[JW_PMAX][JW_PMAX + 1];
     __shared__ double V[JW_PMAX][JW_PMAX + 1];
-    __shared__ double cs[JW_PMAX / 2][3];          // c, s, t
-    __shared__ int pq[JW_PMAX / 2][2];
+    __shared__ double cs[JW_NP][3];          // c, s, t
+    __shared__ int pq[JW_NP][2];
+    __shared__ unsigned char blk[JW_NBLK][2];
     __shared__ int rank_of[JW_PMAX];
     const int lane = threadIdx.x;
     const double* Hp = Hin + (long)blockIdx.x * sH;
@@ -426,9 +448,15 @@ __global__ void __launch_bounds__(64) k_jacobi_w(const double* __restrict__ Hin,
         H[i][j] = 0.5 * (Hp[(long)i * p + j] + Hp[(long)j * p + i]);
         V[i][j] = (i == j) ? 1.0 : 0.0;
     }
-    __syncthreads();
     const int m = p + (p & 1);
     const int np = m / 2;
+    const int nblk = np * (np + 1) / 2;
+    if (lane == 0) {
+        int e = 0;
+        for (int P = 0; P < np; ++P)
+            for (int Q = P; Q < np; ++Q, ++e) { blk[e][0] = (unsigned char)P; blk[e][1] = (unsigned char)Q; }
+    }
+    __syncthreads();
     double f = 0.0;
     for (int e = lane; e < p * p; e += 64) {
         const double x = H[e / p][e - (e / p) * p];
@@ -436,7 +464,6 @@ __global__ void __launch_bounds__(64) k_jacobi_w(const double* __restrict__ Hin,
     }
     const double fro = sqrt(wave_sum(f));
     tol = fmax(tol, (double)p * 2.220446049250313e-16);
-    const int nblk = np * (np + 1) / 2;
 
     for (int sweep = 0; sweep < max_sweeps && p > 1; ++sweep) {
         double o = 0.0;
@@ -468,55 +495,70 @@ __global__ void __launch_bounds__(64) k_jacobi_w(const double* __restrict__ Hin,
                 cs[lane][0] = c; cs[lane][1] = sn; cs[lane][2] = t;
             }
             __syncthreads();
-            // 2 x 2 blocks (P <= Q) of H
-            for (int e = lane; e < nblk; e += 64) {
-                // e -> (P, Q) with P <= Q, row-major over the upper triangle
-                int P = 0, rem = e;
-                while (rem >= np - P) { rem -= np - P; ++P; }
-                const int Q = P + rem;
-                const int a = pq[P][0], b = pq[P][1], a2 = pq[Q][0], b2 = pq[Q][1];
-                const double cP = cs[P][0], sP = cs[P][1], tP = cs[P][2];
-                const double cQ = cs[Q][0], sQ = cs[Q][1];
-                if (P == Q) {
-                    if (b < p && tP != 0.0) {
-                        const double apq = H[a][b];
-                        H[a][a] -= tP * apq;
-                        H[b][b] += tP * apq;
-                        H[a][b] = 0.0;
-                        H[b][a] = 0.0;
+            // ---- 2 x 2 blocks (P <= Q) of H: all loads of the lane first, then the updates
+            int ia[JW_BPL], ib[JW_BPL], ja[JW_BPL], jb[JW_BPL];
+            double x00[JW_BPL], x01[JW_BPL], x10[JW_BPL], x11[JW_BPL];
+            double cP[JW_BPL], sP[JW_BPL], tP[JW_BPL], cQ[JW_BPL], sQ[JW_BPL];
+            bool diag[JW_BPL], live[JW_BPL];
+#pragma unroll
+            for (int u = 0; u < JW_BPL; ++u) {
+                const int e = lane + 64 * u;
+                live[u] = e < nblk;
+                const int P = live[u] ? blk[e][0] : 0, Q = live[u] ? blk[e][1] : 0;
+                diag[u] = P == Q;
+                ia[u] = pq[P][0]; ib[u] = pq[P][1]; ja[u] = pq[Q][0]; jb[u] = pq[Q][1];
+                cP[u] = cs[P][0]; sP[u] = cs[P][1]; tP[u] = cs[P][2]; cQ[u] = cs[Q][0]; sQ[u] = cs[Q][1];
+                const bool rb = ib[u] < p, cb = jb[u] < p;
+                x00[u] = live[u] ? H[ia[u]][ja[u]] : 0.0;
+                x01[u] = (live[u] && cb) ? H[ia[u]][jb[u]] : 0.0;
+                x10[u] = (live[u] && rb) ? H[ib[u]][ja[u]] : 0.0;
+                x11[u] = (live[u] && rb && cb) ? H[ib[u]][jb[u]] : 0.0;
+            }
+            // ---- rows of V (row = lane % 32, pairs of one parity): loads first as well
+            const int vrow = lane & 31, vhalf = lane >> 5;
+            double vx[JW_VPL], vy[JW_VPL];
+            int va[JW_VPL], vb[JW_VPL];
+#pragma unroll
+            for (int u = 0; u < JW_VPL; ++u) {
+                const int kk = vhalf + 2 * u;
+                va[u] = (kk < np) ? pq[kk][0] : 0;
+                vb[u] = (kk < np) ? pq[kk][1] : p;
+                const bool ok = vrow < p && vb[u] < p;
+                vx[u] = ok ? V[vrow][va[u]] : 0.0;
+                vy[u] = ok ? V[vrow][vb[u]] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < JW_BPL; ++u) {
+                if (!live[u]) continue;
+                const bool rb = ib[u] < p, cb = jb[u] < p;
+                if (diag[u]) {
+                    if (rb && tP[u] != 0.0) {
+                        // closed form on the diagonal block: (a_pp - t a_pq, a_qq + t a_pq, 0)
+                        const double apq = x01[u];
+                        H[ia[u]][ia[u]] = x00[u] - tP[u] * apq;
+                        H[ib[u]][ib[u]] = x11[u] + tP[u] * apq;
+                        H[ia[u]][ib[u]] = 0.0;
+                        H[ib[u]][ia[u]] = 0.0;
                     }
                 } else {
-                    // rows a, b (pair P) x columns a2, b2 (pair Q); the padding index (>= p) is skipped
-                    const bool rb = b < p, cb = b2 < p;
-                    const double x00 = H[a][a2];
-                    const double x01 = cb ? H[a][b2] : 0.0;
-                    const double x10 = rb ? H[b][a2] : 0.0;
-                    const double x11 = (rb && cb) ? H[b][b2] : 0.0;
-                    // rows: [x0; x1] <- J_P^T [x0; x1]
-                    const double y00 = cP * x00 - sP * x10, y10 = sP * x00 + cP * x10;
-                    const double y01 = cP * x01 - sP * x11, y11 = sP * x01 + cP * x11;
-                    // columns: [y.0 y.1] <- [y.0 y.1] J_Q
-                    const double z00 = cQ * y00 - sQ * y01, z01 = sQ * y00 + cQ * y01;
-                    const double z10 = cQ * y10 - sQ * y11, z11 = sQ * y10 + cQ * y11;
-                    H[a][a2] = z00; H[a2][a] = z00;
-                    if (cb) { H[a][b2] = z01; H[b2][a] = z01; }
-                    if (rb) { H[b][a2] = z10; H[a2][b] = z10; }
-                    if (rb && cb) { H[b][b2] = z11; H[b2][b] = z11; }
+                    // rows: J_P^T [x0; x1]; columns: [y.0 y.1] J_Q
+                    const double y00 = cP[u] * x00[u] - sP[u] * x10[u], y10 = sP[u] * x00[u] + cP[u] * x10[u];
+                    const double y01 = cP[u] * x01[u] - sP[u] * x11[u], y11 = sP[u] * x01[u] + cP[u] * x11[u];
+                    const double z00 = cQ[u] * y00 - sQ[u] * y01, z01 = sQ[u] * y00 + cQ[u] * y01;
+                    const double z10 = cQ[u] * y10 - sQ[u] * y11, z11 = sQ[u] * y10 + cQ[u] * y11;
+                    H[ia[u]][ja[u]] = z00; H[ja[u]][ia[u]] = z00;
+                    if (cb) { H[ia[u]][jb[u]] = z01; H[jb[u]][ia[u]] = z01; }
+                    if (rb) { H[ib[u]][ja[u]] = z10; H[ja[u]][ib[u]] = z10; }
+                    if (rb && cb) { H[ib[u]][jb[u]] = z11; H[jb[u]][ib[u]] = z11; }
                 }
             }
-            // V <- V J: lane handles row (lane % 32) and half of the pairs
-            {
-                const int row = lane & 31, half = lane >> 5;
-                if (row < p) {
-                    for (int k = half; k < np; k += 2) {
-                        const int a = pq[k][0], b = pq[k][1];
-                        if (b >= p) continue;
-                        const double c = cs[k][0], sn = cs[k][1];
-                        const double x = V[row][a], y = V[row][b];
-                        V[row][a] = c * x - sn * y;
-                        V[row][b] = sn * x + c * y;
-                    }
-                }
+#pragma unroll
+            for (int u = 0; u < JW_VPL; ++u) {
+                const int kk = vhalf + 2 * u;
+                if (kk >= np || vrow >= p || vb[u] >= p) continue;
+                const double c = cs[kk][0], sn = cs[kk][1];
+                V[vrow][va[u]] = c * vx[u] - sn * vy[u];
+                V[vrow][vb[u]] = sn * vx[u] + c * vy[u];
             }
             __syncthreads();
         }
@@ -618,14 +660,20 @@ static hipError_t qr_launch(const double* in, double* out, int count, int n, int
 {
     if (n <= 512 && p <= 32) {
         const int nt = n <= 256 ? 256 : 512;
-        const size_t lds = sizeof(double) * (size_t)(p <= 16 ? 16 : 32) * nt;
-        if (p <= 16) {
-            if (nt == 256) hipLaunchKernelGGL((k_hqr_reg<16, 256>), dim3(count), dim3(256), lds, s, in, out, n, p);
-            else hipLaunchKernelGGL((k_hqr_reg<16, 512>), dim3(count), dim3(512), lds, s, in, out, n, p);
-        } else {
-            if (nt == 256) hipLaunchKernelGGL((k_hqr_reg<32, 256>), dim3(count), dim3(256), lds, s, in, out, n, p);
-            else hipLaunchKernelGGL((k_hqr_reg<32, 512>), dim3(count), dim3(512), lds, s, in, out, n, p);
+        const int pm = (p + 7) / 8 * 8;
+        const size_t lds = sizeof(double) * (size_t)pm * nt;
+#define TK_QR_LAUNCH(PM)                                                                                   \
+    do {                                                                                                  \
+        if (nt == 256) hipLaunchKernelGGL((k_hqr_reg<PM, 256>), dim3(count), dim3(256), lds, s, in, out, n, p); \
+        else hipLaunchKernelGGL((k_hqr_reg<PM, 512>), dim3(count), dim3(512), lds, s, in, out, n, p);          \
+    } while (0)
+        switch (pm) {
+        case 8: TK_QR_LAUNCH(8); break;
+        case 16: TK_QR_LAUNCH(16); break;
+        case 24: TK_QR_LAUNCH(24); break;
+        default: TK_QR_LAUNCH(32);
         }
+#undef TK_QR_LAUNCH
         return hipGetLastError();
     }
     size_t bytes = (size_t)n * p * sizeof(double);
@@ -658,11 +706,12 @@ hipError_t eig_set_attributes()
     hipError_t e = hipFuncSetAttribute((const void*)k_hqr, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)QR_LDS_BYTES);
     if (e != hipSuccess) return e;
-    if ((e = hipFuncSetAttribute((const void*)k_hqr_reg<32, 512>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)(sizeof(double) * 32 * 512))) != hipSuccess)
-        return e;
-    return hipFuncSetAttribute((const void*)k_hqr_reg<16, 512>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(sizeof(double) * 16 * 512));
+    const void* ks[] = {(const void*)k_hqr_reg<24, 512>, (const void*)k_hqr_reg<32, 512>};
+    const int bytes[] = {(int)(sizeof(double) * 24 * 512), (int)(sizeof(double) * 32 * 512)};
+    for (int i = 0; i < 2; ++i)
+        if ((e = hipFuncSetAttribute(ks[i], hipFuncAttributeMaxDynamicSharedMemorySize, bytes[i])) != hipSuccess)
+            return e;
+    return hipSuccess;
 }
 
 hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s)

@@ -281,6 +281,7 @@ GramPlan make_plan(const int n[3], int mode, int BK)
     p.T_tiles = (p.nrow + BM - 1) / BM;
     p.npairs = p.T_tiles * (p.T_tiles + 1) / 2;
     long want = (2048 + p.npairs - 1) / p.npairs;               // ~2048 work-groups
+    if (want > (p.K + 63) / 64) want = (p.K + 63) / 64;          // but at least 64 of K each
     long maxsplit = (p.K + BK - 1) / BK;
     long s = want < maxsplit ? want : maxsplit;
     if (s < 1) s = 1;

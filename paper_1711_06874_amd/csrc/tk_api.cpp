@@ -309,6 +309,15 @@ void layout_work(Arena& ar, const Plan& P, bool own_A, Work& w)
     w.A = own_A ? (void*)ar.take<char>(N * esz) : nullptr;
     size_t gw = 0;
     for (int k = 0; k < 3; ++k) gw = std::max(gw, gram_work_bytes(n, k, P.prec));
+    {
+        // the FP64 projected Grams of the HOOI sweep and the core Grams use the same workspace
+        const int R0 = P.R[0], R1 = P.R[1], R2 = P.R[2];
+        const int d1[3] = {n[0], R1, R2}, d2[3] = {n[1], R0, R2}, d3[3] = {R0, n[2], R1}, dc[3] = {R0, R1, R2};
+        gw = std::max(gw, gram_work_bytes(d1, 0, TK_FP64));
+        gw = std::max(gw, gram_work_bytes(d2, 0, TK_FP64));
+        gw = std::max(gw, gram_work_bytes(d3, 1, TK_FP64));
+        for (int k = 0; k < 3; ++k) gw = std::max(gw, gram_work_bytes(dc, k, TK_FP64));
+    }
     w.gram_work = ar.take<char>(gw);
     w.G = ar.take<double>(3 * (size_t)nmax * nmax);
     w.Q = ar.take<double>(3 * (size_t)nmax * pmax);
@@ -550,10 +559,11 @@ tk_status single_hole_1(const Plan& P, Work& w, hipStream_t s)
 }
 
 // small Gram of a row-major n x K unfolding stored in w.B -> Gs (n x n)
-tk_status small_gram_rows(int n, long K, const double* B, double* Gs, hipStream_t s)
+// G = mode-`mode` Gram of the small FP64 tensor B (dims d, C-order): split-K FP64 MFMA tiles
+// with a fixed-order reduction, as for the Grams of A.
+tk_status small_gram(const int d[3], int mode, const double* B, double* G, void* work, hipStream_t s)
 {
-    GemmArgs g = gemm(n, n, (int)K, 1, B, 0, K, 1, B, 0, 1, K, Gs, 0, n, 1);
-    TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+    TK_LAUNCH(launch_gram(B, d, mode, TK_FP64, G, work, s));
     return TK_OK;
 }
 
@@ -567,7 +577,10 @@ tk_status hooi_sweep(const Plan& P, Work& w, const Real* A, int nmax, hipStream_
     // ---- mode 1: B1 = A x_2 U2^T x_3 U3^T
     if ((st = ttm_last<Real>(P, w, A, s)) != TK_OK) return st;
     if ((st = single_hole_1<Real>(P, w, s)) != TK_OK) return st;
-    if ((st = small_gram_rows(n0, (long)R1 * R2, w.B, Gs, s)) != TK_OK) return st;
+    {
+        const int d[3] = {n0, R1, R2};
+        if ((st = small_gram(d, 0, w.B, Gs, w.gram_work, s)) != TK_OK) return st;
+    }
     if ((st = eig_update(P, w, 0, Gs, s)) != TK_OK) return st;
     if ((st = refresh_u32<Real>(P, w, 0, s)) != TK_OK) return st;
     // ---- mode 2: B2[i1][a][c] = sum_i0 U1[i0][a] T[i0][i1][c]  (T still holds A x_3 U3^T)
@@ -575,7 +588,10 @@ tk_status hooi_sweep(const Plan& P, Work& w, const Real* A, int nmax, hipStream_
         GemmArgs g = gemm(R0, R2, n0, n1, w.U[0], 0, 1, R0, w.T, R2, (long)n1 * R2, 1, w.B, (long)R0 * R2, R2, 1);
         TK_LAUNCH(gemm_dr<Real>(g, s));
     }
-    if ((st = small_gram_rows(n1, (long)R0 * R2, w.B, Gs, s)) != TK_OK) return st;
+    {
+        const int d[3] = {n1, R0, R2};
+        if ((st = small_gram(d, 0, w.B, Gs, w.gram_work, s)) != TK_OK) return st;
+    }
     if ((st = eig_update(P, w, 1, Gs, s)) != TK_OK) return st;
     if ((st = refresh_u32<Real>(P, w, 1, s)) != TK_OK) return st;
     // ---- mode 3: S = A x_1 U1^T, B3[a][i2][b] = sum_i1 S[a][i1][i2] U2[i1][b]
@@ -585,10 +601,9 @@ tk_status hooi_sweep(const Plan& P, Work& w, const Real* A, int nmax, hipStream_
         TK_LAUNCH(gemm_rd<Real>(g, s));
     }
     {
-        // Gs[i2][i2'] = sum_a sum_b B3[a][i2][b] B3[a][i2'][b]
-        GemmArgs g = gemm(n2, n2, R1, R0, w.B, (long)n2 * R1, R1, 1, w.B, (long)n2 * R1, 1, R1, Gs, 0, n2, 1);
-        g.reduce_batch = 1;
-        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+        // Gs[i2][i2'] = sum_a sum_b B3[a][i2][b] B3[a][i2'][b]: the mode-2 Gram of B3 (R0 x n2 x R1)
+        const int d[3] = {R0, n2, R1};
+        if ((st = small_gram(d, 1, w.B, Gs, w.gram_work, s)) != TK_OK) return st;
     }
     if ((st = eig_update(P, w, 2, Gs, s)) != TK_OK) return st;
     if ((st = refresh_u32<Real>(P, w, 2, s)) != TK_OK) return st;
@@ -657,15 +672,12 @@ tk_status core_truncate(const Plan& P, Work& w, hipStream_t s)
     const int R0 = P.R[0], R1 = P.R[1], R2 = P.R[2];
     const int Rm = std::max(R0, std::max(R1, R2));
     const long RR = (long)Rm * Rm;
-    // core Grams
+    // core Grams (R_k x R_k, leading dimension R_k, at Gc + k RR)
     {
-        GemmArgs g = gemm(R0, R0, R1 * R2, 1, w.core, 0, (long)R1 * R2, 1, w.core, 0, 1, (long)R1 * R2, w.Gc, 0, R0, 1);
-        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
-        GemmArgs g1 = gemm(R1, R1, R2, R0, w.core, (long)R1 * R2, R2, 1, w.core, (long)R1 * R2, 1, R2, w.Gc + RR, 0, R1, 1);
-        g1.reduce_batch = 1;
-        TK_LAUNCH((launch_gemm<double, double, double>(g1, s)));
-        GemmArgs g2 = gemm(R2, R2, R0 * R1, 1, w.core, 0, 1, R2, w.core, 0, R2, 1, w.Gc + 2 * RR, 0, R2, 1);
-        TK_LAUNCH((launch_gemm<double, double, double>(g2, s)));
+        const int d[3] = {R0, R1, R2};
+        tk_status st;
+        for (int k = 0; k < 3; ++k)
+            if ((st = small_gram(d, k, w.core, w.Gc + k * RR, w.gram_work, s)) != TK_OK) return st;
     }
     // full eigendecompositions (p = n = R_k); one launch for the three modes when the ranks agree
     if (R0 == R1 && R1 == R2) {
