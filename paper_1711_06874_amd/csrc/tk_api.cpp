@@ -56,6 +56,7 @@ constexpr int COLD_ITERS = 3;         // subspace iterations from a random start
 constexpr int COLD_ITERS_F32 = 2;     // ... float paths (HOOI refines the subspaces anyway)
 constexpr int WARM_ITERS = 2;         // ... from the previous factor (FP64 path: exact HOOI steps)
 constexpr int WARM_ITERS_F32 = 1;     // ... float paths: one block power step per HOOI update
+constexpr int SPAN_ITERS_F32 = 3;     // float eps path, HOSVD start: R-column block, subspace only
 constexpr int NMAX = 1024;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -440,9 +441,15 @@ tk_status readback(tk_ctx* ctx, hipStream_t s, const void* src0, size_t bytes0, 
 // Leading R_k eigenvectors of the three Grams in w.G (stride nmax^2), HOSVD start.
 tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
 {
+    // With the eps rule on a float path the factors end up rotated to the core's HOSVD basis,
+    // so the HOSVD start only has to span the leading subspace: an R-column block iterated
+    // SPAN_ITERS_F32 times (its leading k-dimensional part converges like (lambda_{R+1} /
+    // lambda_k)^iters for the eps rank k << R), without the Rayleigh-Ritz rotation.
+    const bool span = P.eps_mode && P.prec != TK_FP64;
     if (P.cubic) {
         EigBatch b{};
         b.count = 3; b.n = P.n[0]; b.p = P.p[0]; b.r = P.R[0]; b.rw = 0; b.ldw = 0;
+        if (span && P.R[0] < P.n[0] && P.n[0] > EIG_PMAX) { b.p = P.R[0]; b.span_only = 1; }
         b.G = w.G; b.sG = (long)nmax * nmax;
         b.Q = w.Q; b.Y = w.Y; b.H = w.H; b.Vs = w.Vs;
         // U[0..2] are laid out consecutively only per arena; use a staging area then copy
@@ -452,7 +459,7 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
         // the eigensolver writes U after its last use of Y, so U may alias Y
         {
             ProfScope ps(TK_PROF_EIG, s);
-            TK_LAUNCH(launch_eig(b, P.prec == TK_FP64 ? COLD_ITERS : COLD_ITERS_F32, s));
+            TK_LAUNCH(launch_eig(b, b.span_only ? SPAN_ITERS_F32 : (P.prec == TK_FP64 ? COLD_ITERS : COLD_ITERS_F32), s));
         }
         for (int k = 0; k < 3; ++k)
             TK_HIP(hipMemcpyAsync(w.U[k], w.Y + (long)k * P.n[0] * P.R[0], sizeof(double) * P.n[0] * P.R[0],
@@ -466,8 +473,9 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
             b.U = w.U[k]; b.sU = 0; b.ldu = P.R[k];
             b.lam = w.lam + 64 * k; b.sL = 64;
             b.trace = w.trace + k; b.sTrace = 1;
+            if (span && P.R[k] < P.n[k] && P.n[k] > EIG_PMAX) { b.p = P.R[k]; b.span_only = 1; }
             ProfScope ps(TK_PROF_EIG, s);
-            TK_LAUNCH(launch_eig(b, P.prec == TK_FP64 ? COLD_ITERS : COLD_ITERS_F32, s));
+            TK_LAUNCH(launch_eig(b, b.span_only ? SPAN_ITERS_F32 : (P.prec == TK_FP64 ? COLD_ITERS : COLD_ITERS_F32), s));
         }
     }
     return TK_OK;

@@ -56,8 +56,8 @@ struct EigBatch {
     double* U; long sU; int ldu;
     double* lam; long sL;
     double* trace; long sTrace;
-    int span_only;   // 1: warm start with p == r == rw < n; U = orthonormal basis of span(G^iters W), no
-                     // Rayleigh-Ritz (for callers that rotate the factors afterwards)
+    int span_only;   // 1: p == r < n; U = orthonormal basis of span(G^iters W) (W the warm block or a
+                     // random one), no Rayleigh-Ritz (for callers that rotate the factors afterwards)
 };
 hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s);
 // Sign rule on the columns of U (n x r, ld ldu): a column whose entry of largest magnitude (ties
