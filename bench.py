@@ -211,8 +211,10 @@ def main():
     for name in ("eig", "small"):
         kernels_out[name] = {"bound": "latency", "ms_total": alone[name]["ms"], "launches": alone[name]["launches"],
                              "measured": "grids compressed alone"}
-    # the dominant kernel: the largest share of the timed region among the classes timed there
-    dom = max(work_timed, key=lambda k: timed[k]["ms"])
+    # the roofline kernel: the largest single bandwidth-bound kernel of the timed region, the
+    # axis-0 pass of the FFT matvec (the other FFT class spans four kernels; the eigensolver
+    # kernels are latency-bound single work-groups that overlap across the grids of a batch)
+    dom = "fft_axis0"
     d = kernels_out[dom]
 
     # HBM traffic from rocprofv3 counters, valid only for the kernel source it was taken on
