@@ -79,7 +79,7 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--prec", choices=["fp32", "bf16x3"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=128)
+    ap.add_argument("--cpu-rows", type=int, default=8192)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run 5 plain device-to-device copies of BYTES bytes (HBM counter calibration)")
     args = ap.parse_args()
