@@ -137,8 +137,8 @@ tk_status tk_estimate_bytes(const tk_grid *grid, const tk_opts *opts, size_t *pe
  *    HOSVD to the smallest ranks whose error bound stays <= eps.  TK_ENOCONV if r_max does
  *    not reach eps (the result is still returned through *out, at rank r_max).
  *  - eps == 0: fixed ranks[] (clamped to n_k).
- * The result keeps its factors and core resident on the device.  Synchronising (one read of
- * the ranks and the error at the end).
+ * The result keeps its factors and core resident on the device.  Synchronising: when the call
+ * returns the result is complete and may be used from any stream.
  * Errors: TK_EINVAL, TK_EUNSUPPORTED, TK_ENOMEM, TK_EHIP, TK_ENOCONV. */
 tk_status tk_compress(tk_ctx *ctx, const tk_kernel *kernel, const tk_grid *grid,
                       const tk_opts *opts, void *hip_stream, tk_tucker **out);
@@ -222,6 +222,11 @@ tk_status tk_kron_matvec(tk_ctx *ctx, const tk_tucker *t, const void *z_dev, voi
 typedef enum { TK_MV_AUTO = 0, TK_MV_FFT = 1, TK_MV_DENSE = 2 } tk_matvec_method;
 tk_status tk_set_matvec_method(tk_ctx *ctx, int method);
 
+/* Device workspace bytes that tk_kron_matvec / tk_quadratic_form (with y supplied) need for t
+ * with io precision under the context's current matvec method.  Host only.
+ * Errors: TK_EINVAL, TK_ELAYOUT. */
+tk_status tk_estimate_matvec_bytes(tk_ctx *ctx, const tk_tucker *t, int io, size_t *bytes);
+
 /* trace(C) = sum_abc G_abc prod_k trace T(U_k[off_k:, .]) = m1 m2 m3 * A_r(origin)
  * (Sec. 4 eq. (4.3) and the value-at-origin form that follows it).  Computed on the device
  * in FP64; synchronising (one scalar read). */
@@ -254,6 +259,59 @@ tk_status tk_gram(tk_ctx *ctx, const void *A_dev, const int n[3], int mode, int 
  * Stream-ordered. */
 tk_status tk_eig_topr(tk_ctx *ctx, int count, int n, int r, const double *G_dev,
                       double *lambda_dev, double *U_dev, void *hip_stream);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Serving: a request loop over resident results                                            */
+/* ---------------------------------------------------------------------------------------- */
+/* Requests are queued in arrival order and run on `workers` worker threads, each with its own
+ * HIP stream.  A free worker takes the first queued request that can run now: a compress when
+ * its tk_estimate_bytes fits the context's HBM budget next to the resident results and the
+ * requests already admitted, a follow-up (matvec, trace, quadratic form) when the compress it
+ * names has finished and its tk_estimate_matvec_bytes fits.  Requests that cannot run yet stay
+ * queued while later ones go ahead, so work that arrives while others are on the GPU is
+ * admitted as workers and memory free up.  Compress results stay resident, owned by the
+ * server, until tk_server_release or tk_server_destroy.  Every result is the one the plain
+ * entry point returns for the same request alone. */
+typedef enum { TK_REQ_COMPRESS = 0, TK_REQ_MATVEC = 1, TK_REQ_TRACE = 2, TK_REQ_QUADFORM = 3 } tk_req_kind;
+typedef struct {
+    int kind;            /* tk_req_kind */
+    tk_kernel kernel;    /* compress */
+    tk_grid grid;        /* compress */
+    tk_opts opts;        /* compress */
+    long long target;    /* follow-ups: ticket of an earlier compress request */
+    const void *z_dev;   /* matvec, quadratic form: input vector (caller-owned, io precision) */
+    void *y_dev;         /* matvec: output (required); quadratic form: optional output */
+    int io;              /* TK_FP32 or TK_FP64 */
+    void *stream;        /* work queued on this HIP stream before tk_server_submit (for example the
+                            copy that fills z_dev) completes before the request starts; NULL: the
+                            legacy default stream */
+} tk_request;
+typedef struct {
+    int status;                        /* tk_status of the request */
+    int kind;
+    int ranks[3];                      /* compress */
+    double rel_err;                    /* compress */
+    double value;                      /* trace or quadratic form */
+    double t_submit, t_start, t_end;   /* seconds since tk_server_create */
+} tk_result;
+typedef struct tk_server tk_server;
+
+/* workers in 1..16.  Errors: TK_EINVAL, TK_ENOMEM, TK_EHIP. */
+tk_status tk_server_create(tk_ctx *ctx, int workers, tk_server **out);
+/* Queue a request (copied; the vectors must stay valid until the request finishes) and return
+ * its ticket.  Non-blocking.  Errors: TK_EINVAL (bad kind, missing vectors, server stopping). */
+tk_status tk_server_submit(tk_server *sv, const tk_request *req, long long *ticket);
+/* Block until the request finished and return its result (once per ticket).  A follow-up on an
+ * unknown, failed or released compress finishes with status TK_EINVAL.  Errors: TK_EINVAL
+ * (unknown or already collected ticket). */
+tk_status tk_server_wait(tk_server *sv, long long ticket, tk_result *out);
+/* The resident result of a finished compress request (owned by the server). */
+tk_status tk_server_tucker(tk_server *sv, long long compress_ticket, const tk_tucker **out);
+/* Drop a resident result (freed once the follow-ups running on it finish); later follow-ups on
+ * it fail with TK_EINVAL. */
+tk_status tk_server_release(tk_server *sv, long long compress_ticket);
+/* Finish every queued request, then free the resident results, streams and workers. */
+void tk_server_destroy(tk_server *sv);
 
 /* ---------------------------------------------------------------------------------------- */
 /* Kernel timing                                                                              */

@@ -905,6 +905,11 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kp, const void* A_in, c
         free_result(t);
         return st;
     }
+    // the result is complete when the call returns, for work on any stream
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        free_result(t);
+        return fail(TK_EHIP, "compress: %s", hipGetErrorString(hipGetLastError()));
+    }
     for (int k = 0; k < 3; ++k) t->b[k] = grid->b[k];
     t->layout = grid->layout;
     t->prec = P.prec;
@@ -1050,7 +1055,9 @@ int ilog2(int L)
 }
 
 // y = C z by the 3-D DFT (see k_fft.hip); FP32 data.
-tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, hipStream_t s, double* dot_out)
+// plan_bytes != nullptr: only report the workspace the call needs (nothing runs).
+tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, hipStream_t s, double* dot_out,
+                     size_t* plan_bytes = nullptr)
 {
     int off[3], m[3];
     if (!cov_geometry(t, off, m)) return fail(TK_ELAYOUT, "even-sized centred grid has no origin node");
@@ -1083,6 +1090,10 @@ tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, 
     float2 *A1, *A2;
     float2* tw[3];
     lay(plan, &Uh0, &Uh1, &Uh2, &M1, &Hs, &Uh3, &A1, &A2, &dots, tw);
+    if (plan_bytes) {
+        *plan_bytes = plan.off;
+        return TK_OK;
+    }
     Reservation res(ctx, plan.off);
     if (!res.take()) return fail(TK_ENOMEM, "matvec needs %zu bytes; budget %zu, in use %zu", plan.off, ctx->budget,
                                  ctx->in_use.load());
@@ -1531,6 +1542,17 @@ tk_status tk_quadratic_form(tk_ctx* ctx, const tk_tucker* t, const void* z_dev, 
         st = matvec_impl<double>(ctx, t, (const double*)z_dev, (double*)ybuf, s, out);
     if (owned) hipFreeAsync(owned, s);
     return st;
+}
+
+tk_status tk_estimate_matvec_bytes(tk_ctx* ctx, const tk_tucker* t, int io, size_t* bytes)
+{
+    if (!ctx || !t || !bytes) return fail(TK_EINVAL, "NULL argument");
+    if (io != TK_FP64 && io != TK_FP32) return fail(TK_EINVAL, "io must be TK_FP64 or TK_FP32");
+    int off[3], m[3];
+    if (!cov_geometry(t, off, m)) return fail(TK_ELAYOUT, "even-sized centred grid has no origin node");
+    if (use_fft(ctx, io)) return matvec_fft(ctx, t, nullptr, nullptr, nullptr, nullptr, bytes);
+    *bytes = matvec_work_bytes(t, io == TK_FP32 ? 4 : 8);
+    return TK_OK;
 }
 
 tk_status tk_trace(tk_ctx* ctx, const tk_tucker* t, void* hip_stream, double* out)

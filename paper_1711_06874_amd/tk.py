@@ -42,6 +42,21 @@ class tk_opts(ctypes.Structure):
                 ("hooi_sweeps", ctypes.c_int), ("prec", ctypes.c_int)]
 
 
+TK_REQ_COMPRESS, TK_REQ_MATVEC, TK_REQ_TRACE, TK_REQ_QUADFORM = 0, 1, 2, 3
+
+
+class tk_request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("kernel", tk_kernel), ("grid", tk_grid), ("opts", tk_opts),
+                ("target", ctypes.c_longlong), ("z_dev", ctypes.c_void_p), ("y_dev", ctypes.c_void_p),
+                ("io", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+class tk_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("kind", ctypes.c_int), ("ranks", ctypes.c_int * 3),
+                ("rel_err", ctypes.c_double), ("value", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_end", ctypes.c_double)]
+
+
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
@@ -74,6 +89,13 @@ _SIGS = {
     "tk_eig_topr": (_st, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "tk_set_matvec_method": (_st, [_vp, ctypes.c_int]),
     "tk_ctx_set_workers": (_st, [_vp, ctypes.c_int]),
+    "tk_estimate_matvec_bytes": (_st, [_vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "tk_server_create": (_st, [_vp, ctypes.c_int, ctypes.POINTER(_vp)]),
+    "tk_server_submit": (_st, [_vp, ctypes.POINTER(tk_request), ctypes.POINTER(ctypes.c_longlong)]),
+    "tk_server_wait": (_st, [_vp, ctypes.c_longlong, ctypes.POINTER(tk_result)]),
+    "tk_server_tucker": (_st, [_vp, ctypes.c_longlong, ctypes.POINTER(_vp)]),
+    "tk_server_release": (_st, [_vp, ctypes.c_longlong]),
+    "tk_server_destroy": (None, [_vp]),
     "tk_profile_enable": (_st, [ctypes.c_int]),
     "tk_profile_reset": (_st, []),
     "tk_profile_read": (_st, [ctypes.c_int, ctypes.POINTER(ctypes.c_longlong), _dp]),
@@ -178,6 +200,12 @@ def tk_compress_tensor(ctx: int, A, grid: tk_grid, opts: tk_opts, stream=None, a
     st = _lib.tk_compress_tensor(ctx, _ptr(A), ctypes.byref(grid), ctypes.byref(opts), _stream(stream),
                                  ctypes.byref(out))
     _check(st, "tk_compress_tensor", allow=(TK_ENOCONV,) if allow_noconv else ())
+    return out.value
+
+
+def tk_estimate_matvec_bytes(ctx: int, t: int, io: int = TK_FP32) -> int:
+    out = ctypes.c_size_t()
+    _check(_lib.tk_estimate_matvec_bytes(ctx, t, int(io), ctypes.byref(out)), "tk_estimate_matvec_bytes")
     return out.value
 
 
@@ -368,4 +396,82 @@ class Context:
     def destroy(self):
         if self.handle:
             tk_ctx_destroy(self.handle)
+            self.handle = 0
+
+
+class TuckerView:
+    """A result owned by someone else (a server); never freed from Python."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+        info = tk_tucker_info(handle)
+        self.n, self.ranks, self.rel_err, self.norm_a, self.layout = (
+            info["n"], info["ranks"], info["rel_err"], info["norm_a"], info["layout"])
+
+    def factors(self):
+        return tk_tucker_get(self.handle)
+
+
+class Server:
+    """Request loop over resident results (tk_server_*): submit returns a ticket, wait blocks
+    until that request finished and returns its result as a dict.  Work queued on `stream`
+    (default: torch's current stream) before a submit happens before that request; the vectors
+    must stay alive until the request finished."""
+
+    def __init__(self, ctx: "Context", workers: int = 4):
+        h = _vp()
+        _check(_lib.tk_server_create(ctx.handle, int(workers), ctypes.byref(h)), "tk_server_create")
+        self.handle = h.value
+        self.ctx = ctx
+
+    @staticmethod
+    def _order(stream):
+        # default: the stream the caller's device work (torch's current stream) is queued on
+        if stream is None:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    return int(torch.cuda.current_stream().cuda_stream)
+            except ImportError:
+                pass
+            return 0
+        return _stream(stream)
+
+    def _submit(self, req: tk_request) -> int:
+        t = ctypes.c_longlong()
+        _check(_lib.tk_server_submit(self.handle, ctypes.byref(req), ctypes.byref(t)), "tk_server_submit")
+        return t.value
+
+    def submit_compress(self, kernel, grid, opts, stream=None) -> int:
+        return self._submit(tk_request(kind=TK_REQ_COMPRESS, kernel=kernel, grid=grid, opts=opts,
+                                       stream=self._order(stream)))
+
+    def submit_matvec(self, target: int, z, y, io=TK_FP32, stream=None) -> int:
+        return self._submit(tk_request(kind=TK_REQ_MATVEC, target=int(target), z_dev=_ptr(z), y_dev=_ptr(y), io=io,
+                                       stream=self._order(stream)))
+
+    def submit_trace(self, target: int, stream=None) -> int:
+        return self._submit(tk_request(kind=TK_REQ_TRACE, target=int(target), stream=self._order(stream)))
+
+    def submit_quadform(self, target: int, z, io=TK_FP32, y=None, stream=None) -> int:
+        return self._submit(tk_request(kind=TK_REQ_QUADFORM, target=int(target), z_dev=_ptr(z),
+                                       y_dev=_ptr(y) if y is not None else None, io=io, stream=self._order(stream)))
+
+    def wait(self, ticket: int) -> dict:
+        r = tk_result()
+        _check(_lib.tk_server_wait(self.handle, int(ticket), ctypes.byref(r)), "tk_server_wait")
+        return dict(status=r.status, kind=r.kind, ranks=tuple(r.ranks), rel_err=r.rel_err, value=r.value,
+                    t_submit=r.t_submit, t_start=r.t_start, t_end=r.t_end)
+
+    def tucker(self, ticket: int) -> TuckerView:
+        h = _vp()
+        _check(_lib.tk_server_tucker(self.handle, int(ticket), ctypes.byref(h)), "tk_server_tucker")
+        return TuckerView(h.value)
+
+    def release(self, ticket: int):
+        _check(_lib.tk_server_release(self.handle, int(ticket)), "tk_server_release")
+
+    def destroy(self):
+        if self.handle:
+            _lib.tk_server_destroy(self.handle)
             self.handle = 0
