@@ -293,6 +293,8 @@ typedef struct {
     double rel_err;                    /* compress */
     double value;                      /* trace or quadratic form */
     double t_submit, t_start, t_end;   /* seconds since tk_server_create */
+    char error[192];                   /* status != TK_OK: the failing call's message (the
+                                          worker's tk_last_error, truncated); else empty */
 } tk_result;
 typedef struct tk_server tk_server;
 

@@ -13,6 +13,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -69,6 +70,11 @@ double secs(const tk_server* sv, Clock::time_point t)
     return std::chrono::duration<double>(t - sv->origin).count();
 }
 
+void set_error(tk_result* res, const char* msg)
+{
+    std::snprintf(res->error, sizeof(res->error), "%s", msg ? msg : "");
+}
+
 // Can request p start now?  Sets p.est.  Caller holds the lock.  Returns 1 (run), 0 (wait),
 // -1 (fails at once: sets *fail_status).
 int admissible(tk_server* sv, Pending& p, tk_status* fail_status)
@@ -114,6 +120,7 @@ void run_one(tk_server* sv, const Pending& p, hipStream_t s, tk_result* res, tk_
     const tk_request& r = p.r;
     if (p.ready && hipStreamWaitEvent(s, p.ready, 0) != hipSuccess) {
         res->status = TK_EHIP;
+        set_error(res, "hipStreamWaitEvent on the request's ready event failed");
         return;
     }
     if (r.kind == TK_REQ_COMPRESS) {
@@ -141,6 +148,7 @@ void run_one(tk_server* sv, const Pending& p, hipStream_t s, tk_result* res, tk_
         }
     }
     res->status = st;
+    if (st != TK_OK) set_error(res, tk_last_error());
 }
 
 void worker(tk_server* sv, int wi)
@@ -171,6 +179,9 @@ void worker(tk_server* sv, int wi)
         if (verdict < 0) {
             if (p.ready) (void)hipEventDestroy(p.ready);
             res.status = fst;
+            set_error(&res, p.r.kind == TK_REQ_COMPRESS ? "tk_estimate_bytes rejected the grid or options"
+                                                        : "follow-up on an unknown, failed or released compress, "
+                                                          "or its vectors were rejected");
             res.t_start = res.t_end = secs(sv, Clock::now());
             if (p.r.kind == TK_REQ_COMPRESS) sv->compress_state[p.id] = -1;
             sv->done[p.id] = res;

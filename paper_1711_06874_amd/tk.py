@@ -54,7 +54,7 @@ class tk_request(ctypes.Structure):
 class tk_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("kind", ctypes.c_int), ("ranks", ctypes.c_int * 3),
                 ("rel_err", ctypes.c_double), ("value", ctypes.c_double), ("t_submit", ctypes.c_double),
-                ("t_start", ctypes.c_double), ("t_end", ctypes.c_double)]
+                ("t_start", ctypes.c_double), ("t_end", ctypes.c_double), ("error", ctypes.c_char * 192)]
 
 
 _vp = ctypes.c_void_p
@@ -461,7 +461,8 @@ class Server:
         r = tk_result()
         _check(_lib.tk_server_wait(self.handle, int(ticket), ctypes.byref(r)), "tk_server_wait")
         return dict(status=r.status, kind=r.kind, ranks=tuple(r.ranks), rel_err=r.rel_err, value=r.value,
-                    t_submit=r.t_submit, t_start=r.t_start, t_end=r.t_end)
+                    t_submit=r.t_submit, t_start=r.t_start, t_end=r.t_end,
+                    error=r.error.decode(errors="replace"))
 
     def tucker(self, ticket: int) -> TuckerView:
         h = _vp()

@@ -68,10 +68,10 @@ def c3(n: int = 512):
 
 
 # --- uneven batch: 256 tensors -------------------------------------------------------------
-C4_SIZES = (32, 48, 64, 96, 128, 192, 256)
+BATCH_SIZES = (32, 48, 64, 96, 128, 192, 256)
 
 
-def c4_batch(count: int = 256, seed: int = MASTER_SEED, sizes=C4_SIZES):
+def uneven_batch(count: int = 256, seed: int = MASTER_SEED, sizes=BATCH_SIZES):
     """Per tensor, in order: n uniform over `sizes`, nu uniform over {1/2,3/2,5/2},
     ell = exp(U(ln 0.05, ln 1)); sigma2 = 1, centred grid on [-1,1]^3."""
     rng = np.random.default_rng(seed)
@@ -85,7 +85,7 @@ def c4_batch(count: int = 256, seed: int = MASTER_SEED, sizes=C4_SIZES):
 
 
 # --- serving: Poisson stream of mixed requests ---------------------------------------------
-C5_SIZES = (64, 128, 256, 384)
+STREAM_SIZES = (64, 128, 256, 384)
 
 
 @dataclass(frozen=True)
@@ -98,7 +98,7 @@ class Request:
     target: int = -1        # for follow-ups: index of an earlier compress request (-1: any)
 
 
-def c5_stream(rate: float, count: int, seed: int = MASTER_SEED, sizes=C5_SIZES):
+def serving_stream(rate: float, count: int, seed: int = MASTER_SEED, sizes=STREAM_SIZES):
     """Exponential inter-arrival times at `rate` req/s; 70% compress (offset layout, so the
     covariance follow-ups are defined), 30% follow-ups split evenly among matvec, trace and
     quadratic form on a uniformly chosen earlier compress."""
@@ -134,3 +134,13 @@ def random_tensor(shape, stream: int, seed: int = MASTER_SEED) -> np.ndarray:
     """Seeded U(-1,1) float64 tensor (generic non-symmetric test input)."""
     rng = np.random.default_rng([seed, 11, int(stream)])
     return rng.uniform(-1.0, 1.0, size=tuple(shape))
+
+
+def normal_vector_device(shape, stream: int, seed: int = MASTER_SEED):
+    """Seeded N(0,1) float32 vector drawn on the GPU (torch's generator keyed by seed and
+    stream): the input of follow-up requests in the serving workload, where drawing hundreds
+    of MB per request on the host would distort the arrival times."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(int(seed) * 1_000_003 + int(stream))
+    return torch.randn(tuple(shape), generator=g, device="cuda", dtype=torch.float32)

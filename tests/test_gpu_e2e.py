@@ -44,7 +44,7 @@ def test_c1_hosvd_error_curve_fp64(ctx, tk, oracle):
     kern = tk.make_kernel(k.family, nu=k.nu, ell=k.ell)
     grid = tk.make_grid(g.n, g.b, g.layout)
     for r in ranks:
-        say("C1 rank", r)
+        say("rank", r)
         t = ctx.compress(kern, grid, tk.make_opts(ranks=r, hooi_sweeps=0, prec=tk.TK_FP64))
         ref = oracle.hosvd(A, (r, r, r), f)
         lam = f[0][0]

@@ -20,7 +20,7 @@ def tk():
 
 
 @pytest.fixture(scope="module")
-def c3_results(tk, oracle):
+def study_results(tk, oracle):
     require_gpu()
     ks, gs, eps_list = synth.c3(512)
     n = gs.n[0]
@@ -73,8 +73,8 @@ def _at(U, core, idx):
 
 @pytest.mark.parametrize("eps_i", [0, 1])
 @pytest.mark.parametrize("prec", [0, 1, 2])
-def test_c3_error_and_invariants(tk, c3_results, eps_i, prec):
-    out, idx, A_s, eps_list = c3_results
+def test_precision512_error_and_invariants(tk, study_results, eps_i, prec):
+    out, idx, A_s, eps_list = study_results
     eps = eps_list[eps_i]
     ranks, E, norm_a, U, core = out[(eps, prec)]
     assert E <= eps
@@ -93,11 +93,11 @@ def test_c3_error_and_invariants(tk, c3_results, eps_i, prec):
 
 @pytest.mark.parametrize("eps_i", [0, 1])
 @pytest.mark.parametrize("prec", [1, 2])
-def test_c3_split_precision_vs_fp64(tk, c3_results, eps_i, prec):
+def test_precision512_split_precision_vs_fp64(tk, study_results, eps_i, prec):
     """Float paths against the FP64 path: ranks within one, reconstruction within 1e-5 of the
     FP64 result (relative to ||A||, on the sampled nodes), core and energy-weighted factor
     errors stated (and bounded when the ranks agree)."""
-    out, idx, A_s, eps_list = c3_results
+    out, idx, A_s, eps_list = study_results
     eps = eps_list[eps_i]
     r64, E64, _, U64, G64 = out[(eps, 0)]
     rf, Ef, _, Uf, Gf = out[(eps, prec)]

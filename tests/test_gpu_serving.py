@@ -138,16 +138,98 @@ def test_serving_errors(tk):
     sv = tk.Server(ctx, 2)
     try:
         bad = sv.submit_compress(tk.make_kernel(0, nu=0.7, ell=0.3), tk.make_grid(32, 1.0, 1), tk.make_opts(eps=1e-6))
-        assert sv.wait(bad)["status"] == tk.TK_EUNSUPPORTED
-        assert sv.wait(sv.submit_trace(bad))["status"] == tk.TK_EINVAL          # on a failed compress
+        rb = sv.wait(bad)
+        assert rb["status"] == tk.TK_EUNSUPPORTED and "nu" in rb["error"]       # the worker's message
+        rt = sv.wait(sv.submit_trace(bad))
+        assert rt["status"] == tk.TK_EINVAL and rt["error"]                      # on a failed compress
         assert sv.wait(sv.submit_trace(12345))["status"] == tk.TK_EINVAL        # unknown target
         good = sv.submit_compress(tk.make_kernel(0, nu=1.5, ell=0.3), tk.make_grid(32, 1.0, 1), tk.make_opts(eps=1e-6))
-        assert sv.wait(good)["status"] == tk.TK_OK
+        rg = sv.wait(good)
+        assert rg["status"] == tk.TK_OK and rg["error"] == ""
         assert sv.wait(sv.submit_trace(good))["status"] == tk.TK_OK
         sv.release(good)
         assert sv.wait(sv.submit_trace(good))["status"] == tk.TK_EINVAL         # released
         with pytest.raises(tk.TkError):
             sv.wait(good)                                                        # collected already
+    finally:
+        sv.destroy()
+        ctx.destroy()
+
+
+def test_serving_stream_sampled_against_oracle(tk, oracle):
+    """A short serving stream (the seeded serving mix at sizes 64 and 128, all submitted at once):
+    a seeded sample of 20 results checked against the oracle.  Compress: E <= eps and the
+    RMS reconstruction error at sampled nodes (against the oracle's tensor entries) within 4x of
+    the per-entry value E ||A||_F / sqrt(N); trace: the oracle's
+    Kronecker trace of the returned Tucker tensor; matvec and quadratic form: sampled rows of
+    y against the oracle's covariance rows of that tensor (within 2e-5 sum_j |C_ij||z_j|)."""
+    from tests.gpu_util import to_oracle_tucker
+    require_gpu()
+    reqs = synth.serving_stream(500.0, 60, sizes=(64, 128))
+    ctx = tk.Context(0)
+    sv = tk.Server(ctx, 4)
+    opts = tk.make_opts(eps=1e-6, hooi_sweeps=2, prec=1)
+    tickets, vec, spec = {}, {}, {}
+    try:
+        for q in reqs:
+            if q.kind == "compress":
+                tickets[q.rid] = sv.submit_compress(tk.make_kernel(0, nu=q.kernel.nu, ell=q.kernel.ell),
+                                                    tk.make_grid(q.grid.n, q.grid.b, q.grid.layout), opts)
+                spec[q.rid] = q
+            else:
+                target = tickets[q.target]
+                n = spec[q.target].grid.n[0]
+                if q.kind == "trace":
+                    tickets[q.rid] = sv.submit_trace(target)
+                else:
+                    zh = synth.normal_vector((n, n, n), q.rid)
+                    z = dev(zh)
+                    y = torch.empty_like(z)
+                    vec[q.rid] = (zh, z, y)
+                    tickets[q.rid] = (sv.submit_matvec(target, z, y) if q.kind == "matvec"
+                                      else sv.submit_quadform(target, z, y=y))
+        res = {rid: sv.wait(t) for rid, t in tickets.items()}
+        assert all(r["status"] == tk.TK_OK for r in res.values())
+        rng = np.random.default_rng(2000)
+        sample = rng.choice(len(reqs), size=min(20, len(reqs)), replace=False)
+        kinds = []
+        for si in sample:
+            q = reqs[int(si)]
+            kinds.append(q.kind)
+            cq = q if q.kind == "compress" else spec[q.target]
+            n = cq.grid.n[0]
+            ok = oracle.Kernel(oracle.MATERN, nu=cq.kernel.nu, ell=cq.kernel.ell)
+            og = oracle.Grid(n=(n, n, n), layout=oracle.OFFSET)
+            view = sv.tucker(tickets[cq.rid])
+            U, core = view.factors()
+            to = to_oracle_tucker(oracle, U, core)
+            if q.kind == "compress":
+                r = res[q.rid]
+                assert r["rel_err"] <= 1e-6
+                idx = rng.integers(0, n, size=(256, 3))
+                x = oracle.grid_coords(n, 1.0, oracle.OFFSET)
+                A_s = np.array([oracle.kernel_value(ok, float(np.sqrt(x[i] ** 2 + x[j] ** 2 + x[k] ** 2)))
+                                for i, j, k in idx])
+                rec = np.einsum("sa,sb,sc,abc->s", U[0][idx[:, 0]], U[1][idx[:, 1]], U[2][idx[:, 2]], core)
+                d = rec - A_s
+                # the per-entry RMS error is E ||A||_F / sqrt(N); uniform samples estimate it
+                # (the relative error of the samples themselves is meaningless when the energy
+                # sits near the origin, as for short correlation lengths)
+                assert np.sqrt(np.mean(d * d)) <= 4 * r["rel_err"] * view.norm_a / np.sqrt(n ** 3) + 1e-15
+            elif q.kind == "trace":
+                assert res[q.rid]["value"] == pytest.approx(oracle.cov_trace_kron(to, og), rel=1e-12)
+            else:
+                zh, z, y = vec[q.rid]
+                got = host(y).reshape(-1)
+                rows = rng.choice(n ** 3, 8, replace=False)
+                Q = oracle.reconstruct(to.core, to.U)
+                want = oracle.cov_rows_from_generator(Q, og, zh.astype(np.float64), rows)
+                bound = oracle.cov_rows_from_generator(np.abs(Q), og, np.abs(zh.astype(np.float64)), rows)
+                assert np.all(np.abs(got[rows] - want) <= 2e-5 * bound)
+                if q.kind == "quadform":
+                    assert res[q.rid]["value"] == pytest.approx(
+                        float(np.dot(zh.reshape(-1).astype(np.float64), got.astype(np.float64))), rel=1e-6)
+        say("checked", {k: kinds.count(k) for k in set(kinds)})
     finally:
         sv.destroy()
         ctx.destroy()
