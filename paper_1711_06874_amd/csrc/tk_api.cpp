@@ -449,7 +449,7 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
     if (P.cubic) {
         EigBatch b{};
         b.count = 3; b.n = P.n[0]; b.p = P.p[0]; b.r = P.R[0]; b.rw = 0; b.ldw = 0;
-        if (span && P.R[0] < P.n[0] && P.n[0] > EIG_PMAX) { b.p = P.R[0]; b.span_only = 1; }
+        if (span && P.R[0] < P.n[0]) { b.p = P.R[0]; b.span_only = 1; }
         b.G = w.G; b.sG = (long)nmax * nmax;
         b.Q = w.Q; b.Y = w.Y; b.H = w.H; b.Vs = w.Vs;
         // U[0..2] are laid out consecutively only per arena; use a staging area then copy
@@ -473,7 +473,7 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
             b.U = w.U[k]; b.sU = 0; b.ldu = P.R[k];
             b.lam = w.lam + 64 * k; b.sL = 64;
             b.trace = w.trace + k; b.sTrace = 1;
-            if (span && P.R[k] < P.n[k] && P.n[k] > EIG_PMAX) { b.p = P.R[k]; b.span_only = 1; }
+            if (span && P.R[k] < P.n[k]) { b.p = P.R[k]; b.span_only = 1; }
             ProfScope ps(TK_PROF_EIG, s);
             TK_LAUNCH(launch_eig(b, b.span_only ? SPAN_ITERS_F32 : (P.prec == TK_FP64 ? COLD_ITERS : COLD_ITERS_F32), s));
         }
@@ -490,9 +490,11 @@ tk_status eig_update(const Plan& P, Work& w, int k, const double* Gs, hipStream_
     // converged eigenvectors, so every HOOI step is exact as in the oracle.  With the eps rule
     // on a float path the factors are rotated to the core's HOSVD basis at the end, so a HOOI
     // update only has to deliver the subspace: the power-stepped block itself, orthonormalised.
+    // (also for n <= EIG_PMAX: a full n x n Jacobi costs far more than one block step)
     b.count = 1; b.n = P.n[k]; b.r = P.R[k];
-    b.p = (P.n[k] <= EIG_PMAX) ? P.n[k] : (P.prec == TK_FP64 ? P.p[k] : P.R[k]);
-    b.span_only = (P.eps_mode && P.prec != TK_FP64 && b.p == b.r && b.p < b.n) ? 1 : 0;
+    const bool span = P.eps_mode && P.prec != TK_FP64 && P.R[k] < P.n[k];
+    b.p = span ? P.R[k] : (P.n[k] <= EIG_PMAX) ? P.n[k] : (P.prec == TK_FP64 ? P.p[k] : P.R[k]);
+    b.span_only = span ? 1 : 0;
     b.rw = P.R[k]; b.ldw = P.R[k]; b.warm = w.U[k]; b.sW = 0;
     b.G = Gs; b.sG = 0;
     b.Q = w.Q; b.Y = w.Y; b.H = w.H; b.Vs = w.Vs;
