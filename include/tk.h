@@ -115,8 +115,10 @@ typedef struct tk_tucker tk_tucker;
  * Errors: TK_EINVAL (out == NULL, bad device), TK_EHIP. */
 tk_status tk_ctx_create(int device, size_t hbm_budget_bytes, tk_ctx **out);
 
-/* Wait for all work of the context, release its workspaces.  Every tk_tucker made with it
- * must have been freed first.  NULL is ignored. */
+/* Wait for all work of the context and release its streams and staging buffers.  Results made
+ * with it that are still alive may afterwards only be passed to tk_tucker_free (every other
+ * call on them returns TK_EINVAL); the context's bookkeeping goes with the last of them.
+ * NULL is ignored. */
 void tk_ctx_destroy(tk_ctx *ctx);
 
 /* Bytes of the budget currently reserved by the context's calls and resident results. */
@@ -150,14 +152,18 @@ tk_status tk_compress_tensor(tk_ctx *ctx, const void *A_dev, const tk_grid *grid
                              const tk_opts *opts, void *hip_stream, tk_tucker **out);
 
 /* Compress `count` independent problems (kernels[i] on grids[i], sizes may differ, all with
- * *opts) in one call.  The problems run concurrently, each on one of the context's worker
- * streams (tk_ctx_set_workers, default 4) with its own host worker, so that the
- * latency-bound eigensolves of one problem overlap the bandwidth-bound passes of others.
- * They start after the work queued on hip_stream.  Admission follows the HBM budget: a
- * problem that does not fit while others are running waits for one of them to finish.
- * outs[i] receives the i-th result, identical to what tk_compress returns for that problem
- * alone; result i is tied to a worker stream that lives as long as the context.
- * Synchronising.  On error no result is returned (outs[] set to NULL). */
+ * *opts) in one call.  Problems on the same grid share their launches: up to 32 of them (fewer
+ * if the HBM budget asks) run every step of the pipeline as one launch whose third grid
+ * dimension walks the problems, so one eigensolve or Gram launch serves them all.  Such groups
+ * (and problems that run alone: other grids, or the FP64 eps path, which reads ranks back
+ * between steps) run concurrently, largest first, on the context's worker streams
+ * (tk_ctx_set_workers, default 4) with one host worker each, so the latency-bound steps of one
+ * group overlap the bandwidth-bound passes of others.  They start after the work queued on
+ * hip_stream.  Admission follows the HBM budget: a group that does not fit while others run
+ * waits for one of them to finish.  outs[i] receives the i-th result, bitwise identical to
+ * what tk_compress returns for that problem alone (TK_ENOCONV results included).
+ * Synchronising: when the call returns every result is complete and may be used from any
+ * stream.  On error no result is returned (outs[] set to NULL). */
 tk_status tk_compress_batch(tk_ctx *ctx, int count, const tk_kernel *kernels,
                             const tk_grid *grids, const tk_opts *opts, void *hip_stream,
                             tk_tucker **outs);

@@ -36,6 +36,8 @@ __device__ __forceinline__ double start_value(unsigned long long key)
 
 __global__ void k_eig_init(EigBatch b)
 {
+    b.warm = bshift(b.warm, b.bs);
+    b.Q = bshift(b.Q, b.bs);
     int prob = blockIdx.y;
     long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     long tot = (long)b.n * b.p;
@@ -60,8 +62,10 @@ __global__ void k_eig_init(EigBatch b)
 //   C: W[i][c] -= tau v_i w_c for i >= j, c > j (one column per thread, rows strided).
 // The explicit Q is then formed in place from the last reflector to the first.
 __global__ void __launch_bounds__(256) k_hqr(const double* __restrict__ In, double* __restrict__ Out,
-                                             int n, int p, int in_lds)
+                                             int n, int p, int in_lds, long bs)
 {
+    In = bshift(In, bs);
+    Out = bshift(Out, bs);
     extern __shared__ double smem[];
     __shared__ double red[4];
     __shared__ double wsum[64];
@@ -177,8 +181,11 @@ __global__ void __launch_bounds__(256) k_hqr(const double* __restrict__ In, doub
 // the matching eigenvector columns Vs (p x r, row-major).
 __global__ void __launch_bounds__(256) k_jacobi(const double* __restrict__ Hin, int p, int r,
                                                 double* __restrict__ Vs, double* __restrict__ lam,
-                                                long sLam, int max_sweeps, double tol)
+                                                long sLam, int max_sweeps, double tol, long bs)
 {
+    Hin = bshift(Hin, bs);
+    Vs = bshift(Vs, bs);
+    lam = bshift(lam, bs);
     __shared__ double H[EIG_PMAX][EIG_PMAX + 1];
     __shared__ double V[EIG_PMAX][EIG_PMAX + 1];
     __shared__ double cs[EIG_PMAX / 2][2];
@@ -405,8 +412,11 @@ __device__ __forceinline__ void qr_backward(double (&w)[PM], double* T, double* 
 // time, so every register index is static.  The explicit Q is then accumulated backwards in
 // the same registers.
 template <int PM, int NT>
-__global__ void __launch_bounds__(NT) k_hqr_reg(const double* __restrict__ In, double* __restrict__ Out, int n, int p)
+__global__ void __launch_bounds__(NT) k_hqr_reg(const double* __restrict__ In, double* __restrict__ Out, int n, int p,
+                                                long bs)
 {
+    In = bshift(In, bs);
+    Out = bshift(Out, bs);
     extern __shared__ double T[];
     __shared__ double S[PM];
     __shared__ double rowjb[2][PM];     // row j, double-buffered by column parity
@@ -418,6 +428,9 @@ __global__ void __launch_bounds__(NT) k_hqr_reg(const double* __restrict__ In, d
 #pragma unroll
     for (int c = 0; c < PM; ++c) w[c] = (live && c < p) ? In[off + (long)i * p + c] : 0.0;
     qr_forward<PM, NT, 0>(w, T, S, rowjb, taus, n, p);
+    // thread 0 wrote the last tau after the last barrier of the forward pass, and the backward
+    // pass reads it first
+    __syncthreads();
     qr_backward<PM, NT, PM - 1>(w, T, S, taus, n, p);
     if (live) {
 #pragma unroll
@@ -440,8 +453,11 @@ constexpr int JW_VPL = JW_NP / 2;                           // V pairs per lane
 
 __global__ void __launch_bounds__(64) k_jacobi_w(const double* __restrict__ Hin, long sH, int p, int r,
                                                  double* __restrict__ Vs, long sV, int ldv, double* __restrict__ lam,
-                                                 long sLam, int max_sweeps, double tol)
+                                                 long sLam, int max_sweeps, double tol, long bs)
 {
+    Hin = bshift(Hin, bs);
+    Vs = bshift(Vs, bs);
+    lam = bshift(lam, bs);
     __shared__ double H[JW_PMAX][JW_PMAX + 1];
     __shared__ double V[JW_PMAX][JW_PMAX + 1];
     __shared__ double cs[JW_NP][3];          // c, s, t
@@ -597,8 +613,9 @@ __global__ void __launch_bounds__(64) k_jacobi_w(const double* __restrict__ Hin,
 }
 
 // Sign rule on the n x r factor of problem blockIdx.y, column blockIdx.x.
-__global__ void __launch_bounds__(256) k_signfix(double* __restrict__ U, long sU, int ldu, int n)
+__global__ void __launch_bounds__(256) k_signfix(double* __restrict__ U, long sU, int ldu, int n, long bs)
 {
+    U = bshift(U, bs);
     __shared__ double red[4];
     __shared__ int redi[4];
     __shared__ double amax_s;
@@ -619,15 +636,20 @@ __global__ void __launch_bounds__(256) k_signfix(double* __restrict__ U, long sU
     if (lane == 0) redi[wv] = lead;
     __syncthreads();
     int L = min(min(redi[0], redi[1]), min(redi[2], redi[3]));
-    if (L < n && u[(long)L * ldu] < 0.0)
+    // every thread reads the leading entry before any thread negates it
+    const bool flip = L < n && u[(long)L * ldu] < 0.0;
+    __syncthreads();
+    if (flip)
         for (int i = tid; i < n; i += 256) u[(long)i * ldu] = -u[(long)i * ldu];
 }
 
 // Sign rule on column blockIdx.x of U (n rows, ld ldu); the same flip is applied to column
 // blockIdx.x of V (nv rows, ld ldv).
 __global__ void __launch_bounds__(256) k_signfix_pair(double* __restrict__ U, int ldu, int n, double* __restrict__ V,
-                                                      int ldv, int nv)
+                                                      int ldv, int nv, long bs)
 {
+    U = bshift(U, bs);
+    V = bshift(V, bs);
     __shared__ double red[4];
     __shared__ int redi[4];
     __shared__ double amax_s;
@@ -648,14 +670,19 @@ __global__ void __launch_bounds__(256) k_signfix_pair(double* __restrict__ U, in
     if (lane == 0) redi[wv] = lead;
     __syncthreads();
     const int L = min(min(redi[0], redi[1]), min(redi[2], redi[3]));
-    if (L < n && u[(long)L * ldu] < 0.0) {
+    // every thread reads the leading entry before any thread negates it
+    const bool flip = L < n && u[(long)L * ldu] < 0.0;
+    __syncthreads();
+    if (flip) {
         for (int i = tid; i < n; i += 256) u[(long)i * ldu] = -u[(long)i * ldu];
         for (int i = tid; i < nv; i += 256) V[(long)i * ldv + blockIdx.x] = -V[(long)i * ldv + blockIdx.x];
     }
 }
 
-__global__ void k_trace(const double* __restrict__ G, long sG, int n, double* __restrict__ out, long sOut)
+__global__ void k_trace(const double* __restrict__ G, long sG, int n, double* __restrict__ out, long sOut, long bs)
 {
+    G = bshift(G, bs);
+    out = bshift(out, bs);
     __shared__ double red[4];
     const int tid = threadIdx.x;
     const double* g = G + blockIdx.x * sG;
@@ -669,16 +696,17 @@ __global__ void k_trace(const double* __restrict__ G, long sG, int n, double* __
 
 }  // namespace
 
-static hipError_t qr_launch(const double* in, double* out, int count, int n, int p, hipStream_t s)
+static hipError_t qr_launch(const double* in, double* out, int count, int n, int p, hipStream_t s, Bat bt)
 {
+    const dim3 grid(count, 1, bt.nb);
     if (n <= 512 && p <= 32) {
         const int nt = n <= 256 ? 256 : 512;
         const int pm = (p + 7) / 8 * 8;
         const size_t lds = sizeof(double) * (size_t)pm * nt;
-#define TK_QR_LAUNCH(PM)                                                                                   \
-    do {                                                                                                  \
-        if (nt == 256) hipLaunchKernelGGL((k_hqr_reg<PM, 256>), dim3(count), dim3(256), lds, s, in, out, n, p); \
-        else hipLaunchKernelGGL((k_hqr_reg<PM, 512>), dim3(count), dim3(512), lds, s, in, out, n, p);          \
+#define TK_QR_LAUNCH(PM)                                                                                         \
+    do {                                                                                                        \
+        if (nt == 256) hipLaunchKernelGGL((k_hqr_reg<PM, 256>), grid, dim3(256), lds, s, in, out, n, p, bt.bs); \
+        else hipLaunchKernelGGL((k_hqr_reg<PM, 512>), grid, dim3(512), lds, s, in, out, n, p, bt.bs);          \
     } while (0)
         switch (pm) {
         case 8: TK_QR_LAUNCH(8); break;
@@ -691,26 +719,27 @@ static hipError_t qr_launch(const double* in, double* out, int count, int n, int
     }
     size_t bytes = (size_t)n * p * sizeof(double);
     int in_lds = bytes <= QR_LDS_BYTES ? 1 : 0;
-    hipLaunchKernelGGL(k_hqr, dim3(count), dim3(256), in_lds ? bytes : 0, s, in, out, n, p, in_lds);
+    hipLaunchKernelGGL(k_hqr, grid, dim3(256), in_lds ? bytes : 0, s, in, out, n, p, in_lds, bt.bs);
     return hipGetLastError();
 }
 
 // Jacobi on `count` p x p matrices (stride sH) -> leading r eigenvectors (stride sV, ld ldv)
 static hipError_t jacobi_launch(const double* H, long sH, int count, int p, int r, double* V, long sV, int ldv,
-                                double* lam, long sL, hipStream_t s)
+                                double* lam, long sL, hipStream_t s, Bat bt)
 {
+    const dim3 grid(count, 1, bt.nb);
     if (p <= JW_PMAX) {
-        hipLaunchKernelGGL(k_jacobi_w, dim3(count), dim3(64), 0, s, H, sH, p, r, V, sV, ldv, lam, sL, 60, 1e-15);
+        hipLaunchKernelGGL(k_jacobi_w, grid, dim3(64), 0, s, H, sH, p, r, V, sV, ldv, lam, sL, 60, 1e-15, bt.bs);
         return hipGetLastError();
     }
     if (sH != (long)p * p || sV != (long)p * r || ldv != r) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_jacobi, dim3(count), dim3(256), 0, s, H, p, r, V, lam, sL, 60, 1e-15);
+    hipLaunchKernelGGL(k_jacobi, grid, dim3(256), 0, s, H, p, r, V, lam, sL, 60, 1e-15, bt.bs);
     return hipGetLastError();
 }
 
-hipError_t launch_signfix_pair(double* U, int ldu, int n, double* V, int ldv, int nv, int r, hipStream_t s)
+hipError_t launch_signfix_pair(double* U, int ldu, int n, double* V, int ldv, int nv, int r, hipStream_t s, Bat bt)
 {
-    hipLaunchKernelGGL(k_signfix_pair, dim3(r), dim3(256), 0, s, U, ldu, n, V, ldv, nv);
+    hipLaunchKernelGGL(k_signfix_pair, dim3(r, 1, bt.nb), dim3(256), 0, s, U, ldu, n, V, ldv, nv, bt.bs);
     return hipGetLastError();
 }
 
@@ -732,20 +761,23 @@ hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s)
     hipError_t e;
     const int n = b.n, p = b.p, r = b.r;
     const long np_ = (long)n * p;
+    Bat bt;
+    bt.nb = b.nb > 1 ? b.nb : 1;
+    bt.bs = b.bs;
     if (b.trace) {
-        hipLaunchKernelGGL(k_trace, dim3(b.count), dim3(256), 0, s, b.G, b.sG, n, b.trace, b.sTrace);
+        hipLaunchKernelGGL(k_trace, dim3(b.count, 1, bt.nb), dim3(256), 0, s, b.G, b.sG, n, b.trace, b.sTrace, bt.bs);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (p == n && p <= JW_PMAX) {
         // the block is the identity: diagonalise G itself
-        if ((e = jacobi_launch(b.G, b.count > 1 ? b.sG : 0, b.count, p, r, b.U, b.sU, b.ldu, b.lam, b.sL, s)) !=
+        if ((e = jacobi_launch(b.G, b.count > 1 ? b.sG : 0, b.count, p, r, b.U, b.sU, b.ldu, b.lam, b.sL, s, bt)) !=
             hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_signfix, dim3(r, b.count), dim3(256), 0, s, b.U, b.sU, b.ldu, n);
+        hipLaunchKernelGGL(k_signfix, dim3(r, b.count, bt.nb), dim3(256), 0, s, b.U, b.sU, b.ldu, n, bt.bs);
         return hipGetLastError();
     }
     // start block
-    hipLaunchKernelGGL(k_eig_init, dim3((unsigned)((np_ + 255) / 256), b.count), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_eig_init, dim3((unsigned)((np_ + 255) / 256), b.count, bt.nb), dim3(256), 0, s, b);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     GemmArgs gq{};   // Y = G Q
     gq.M = n; gq.N = p; gq.K = n; gq.batch = b.count;
@@ -753,17 +785,26 @@ hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s)
     gq.B = b.Q; gq.sBb = np_; gq.sBk = p; gq.sBn = 1;
     gq.C = b.Y; gq.sCb = np_; gq.sCm = p; gq.sCn = 1;
     gq.alpha = 1.0; gq.beta = 0.0;
+    gq.nb = bt.nb; gq.bs = bt.bs;
     if (p < n) {
         const bool start_orthonormal = b.warm && b.rw == p;   // previous factor, no extra columns
-        if (!start_orthonormal && (e = qr_launch(b.Q, b.Q, b.count, n, p, s)) != hipSuccess) return e;
+        if (!start_orthonormal && (e = qr_launch(b.Q, b.Q, b.count, n, p, s, bt)) != hipSuccess) return e;
         for (int it = 0; it < iters; ++it) {
             if ((e = launch_gemm<double, double, double>(gq, s)) != hipSuccess) return e;
-            if ((e = qr_launch(b.Y, b.Q, b.count, n, p, s)) != hipSuccess) return e;
+            if ((e = qr_launch(b.Y, b.Q, b.count, n, p, s, bt)) != hipSuccess) return e;
         }
     }
     if (b.span_only) {
         // the block spans G^iters W: hand it over as the factor (ld p == r)
         if (!(p == r && p < n && iters > 0)) return hipErrorInvalidValue;
+        if (b.ldu == p && (b.count == 1 || b.sU == np_))
+            return launch_copy_f64(b.Q, b.U, b.count * np_, s, bt);
+        if (b.ldu == p) {
+            for (long c = 0; c < b.count; ++c)
+                if ((e = launch_copy_f64(b.Q + c * np_, b.U + c * b.sU, np_, s, bt)) != hipSuccess) return e;
+            return hipSuccess;
+        }
+        if (bt.nb > 1) return hipErrorInvalidValue;
         for (long c = 0; c < b.count; ++c)
             if ((e = hipMemcpy2DAsync(b.U + c * b.sU, sizeof(double) * b.ldu, b.Q + c * np_, sizeof(double) * p,
                                       sizeof(double) * p, n, hipMemcpyDeviceToDevice, s)) != hipSuccess)
@@ -777,8 +818,9 @@ hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s)
     hq.B = b.Y; hq.sBb = np_; hq.sBk = p; hq.sBn = 1;
     hq.C = b.H; hq.sCb = (long)p * p; hq.sCm = p; hq.sCn = 1;
     hq.alpha = 1.0; hq.beta = 0.0;
+    hq.nb = bt.nb; hq.bs = bt.bs;
     if ((e = launch_gemm<double, double, double>(hq, s)) != hipSuccess) return e;
-    if ((e = jacobi_launch(b.H, (long)p * p, b.count, p, r, b.Vs, (long)p * r, r, b.lam, b.sL, s)) != hipSuccess)
+    if ((e = jacobi_launch(b.H, (long)p * p, b.count, p, r, b.Vs, (long)p * r, r, b.lam, b.sL, s, bt)) != hipSuccess)
         return e;
     GemmArgs uq{};   // U = Q Vs  (n x r)
     uq.M = n; uq.N = r; uq.K = p; uq.batch = b.count;
@@ -786,8 +828,9 @@ hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s)
     uq.B = b.Vs; uq.sBb = (long)p * r; uq.sBk = r; uq.sBn = 1;
     uq.C = b.U; uq.sCb = b.sU; uq.sCm = b.ldu; uq.sCn = 1;
     uq.alpha = 1.0; uq.beta = 0.0;
+    uq.nb = bt.nb; uq.bs = bt.bs;
     if ((e = launch_gemm<double, double, double>(uq, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_signfix, dim3(r, b.count), dim3(256), 0, s, b.U, b.sU, b.ldu, n);
+    hipLaunchKernelGGL(k_signfix, dim3(r, b.count, bt.nb), dim3(256), 0, s, b.U, b.sU, b.ldu, n, bt.bs);
     return hipGetLastError();
 }
 

@@ -53,10 +53,12 @@ __device__ __forceinline__ void pair_of(int pidx, int T, int& ti, int& tj)
 template <int MODE, typename T, int BK>
 __global__ void __launch_bounds__(NT) k_gram_tiles(const T* __restrict__ A, Unfold<MODE> u, int nrow,
                                                    long K, long kchunk, int T_tiles, int nsplit,
-                                                   T* __restrict__ partials)
+                                                   T* __restrict__ partials, long bs)
 {
     __shared__ T As[BK][BM + 1];
     __shared__ T Bs[BK][BM + 1];
+    A = bshift(A, bs);
+    partials = bshift(partials, bs);
     const int tid = threadIdx.x;
     const int split = blockIdx.x % nsplit;
     const int pidx = blockIdx.x / nsplit;
@@ -163,10 +165,12 @@ __global__ void __launch_bounds__(NT) k_gram_tiles(const T* __restrict__ A, Unfo
 template <int MODE, int BK>
 __global__ void __launch_bounds__(NT) k_gram_tiles_bf16x3(const float* __restrict__ A, Unfold<MODE> u,
                                                           int nrow, long K, long kchunk, int T_tiles,
-                                                          int nsplit, float* __restrict__ partials)
+                                                          int nsplit, float* __restrict__ partials, long bs)
 {
     constexpr int LD = BK + 8;
     __shared__ __attribute__((aligned(16))) __bf16 Ah[BM][LD], Al[BM][LD], Bh[BM][LD], Bl[BM][LD];
+    A = bshift(A, bs);
+    partials = bshift(partials, bs);
     const int tid = threadIdx.x;
     const int split = blockIdx.x % nsplit;
     const int pidx = blockIdx.x / nsplit;
@@ -244,9 +248,11 @@ __global__ void __launch_bounds__(NT) k_gram_tiles_bf16x3(const float* __restric
 // sums are added in the fixed order g = 0, 1, 2, 3, so the result does not depend on timing.
 template <typename T>
 __global__ void __launch_bounds__(256) k_gram_reduce(const T* __restrict__ partials, int T_tiles,
-                                                     int nsplit, int nrow, double* __restrict__ G)
+                                                     int nsplit, int nrow, double* __restrict__ G, long bs)
 {
     __shared__ double part[4][64];
+    partials = bshift(partials, bs);
+    G = bshift(G, bs);
     const int pidx = blockIdx.y;
     int ti, tj;
     pair_of(pidx, T_tiles, ti, tj);
@@ -306,42 +312,44 @@ size_t gram_work_bytes(const int n[3], int mode, int prec)
 }
 
 template <int MODE>
-static hipError_t launch_mode(const void* A, const int n[3], int prec, double* G, void* work, hipStream_t s)
+static hipError_t launch_mode(const void* A, const int n[3], int prec, double* G, void* work, hipStream_t s,
+                              Bat bt)
 {
     GramPlan p = make_plan(n, MODE, bk_for(prec));
     Unfold<MODE> u;
     u.n1n2 = (long)n[1] * n[2];
     u.n1 = n[1];
     u.n2 = n[2];
-    dim3 grid((unsigned)(p.npairs * p.nsplit));
+    dim3 grid((unsigned)(p.npairs * p.nsplit), 1, bt.nb);
     if (prec == 0) {
         hipLaunchKernelGGL((k_gram_tiles<MODE, double, BK_F64>), grid, dim3(NT), 0, s, (const double*)A, u,
-                           p.nrow, p.K, p.kchunk, p.T_tiles, p.nsplit, (double*)work);
+                           p.nrow, p.K, p.kchunk, p.T_tiles, p.nsplit, (double*)work, bt.bs);
     } else if (prec == 1) {
         hipLaunchKernelGGL((k_gram_tiles<MODE, float, BK_F32>), grid, dim3(NT), 0, s, (const float*)A, u,
-                           p.nrow, p.K, p.kchunk, p.T_tiles, p.nsplit, (float*)work);
+                           p.nrow, p.K, p.kchunk, p.T_tiles, p.nsplit, (float*)work, bt.bs);
     } else {
         hipLaunchKernelGGL((k_gram_tiles_bf16x3<MODE, BK_BF>), grid, dim3(NT), 0, s, (const float*)A, u,
-                           p.nrow, p.K, p.kchunk, p.T_tiles, p.nsplit, (float*)work);
+                           p.nrow, p.K, p.kchunk, p.T_tiles, p.nsplit, (float*)work, bt.bs);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dim3 rgrid(BM * BM / 64, p.npairs);
+    dim3 rgrid(BM * BM / 64, p.npairs, bt.nb);
     if (prec == 0)
         hipLaunchKernelGGL(k_gram_reduce<double>, rgrid, dim3(256), 0, s, (const double*)work, p.T_tiles,
-                           p.nsplit, p.nrow, G);
+                           p.nsplit, p.nrow, G, bt.bs);
     else
         hipLaunchKernelGGL(k_gram_reduce<float>, rgrid, dim3(256), 0, s, (const float*)work, p.T_tiles,
-                           p.nsplit, p.nrow, G);
+                           p.nsplit, p.nrow, G, bt.bs);
     return hipGetLastError();
 }
 
 hipError_t launch_gram(const void* A, const int n[3], int mode, int prec, double* G, void* work,
-                       hipStream_t s)
+                       hipStream_t s, Bat bt)
 {
-    if (mode == 0) return launch_mode<0>(A, n, prec, G, work, s);
-    if (mode == 1) return launch_mode<1>(A, n, prec, G, work, s);
-    return launch_mode<2>(A, n, prec, G, work, s);
+    if (bt.nb < 1) return hipErrorInvalidValue;
+    if (mode == 0) return launch_mode<0>(A, n, prec, G, work, s, bt);
+    if (mode == 1) return launch_mode<1>(A, n, prec, G, work, s, bt);
+    return launch_mode<2>(A, n, prec, G, work, s, bt);
 }
 
 }  // namespace tk

@@ -11,11 +11,13 @@
 namespace tk {
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_grid_eval(T* __restrict__ A, GridAxes g, KernelParams kp,
-                                                   long total_quads, int quads_per_row)
+__global__ void __launch_bounds__(256) k_grid_eval(T* __restrict__ A, GridAxes g, KernelParamsBatch kps,
+                                                   long total_quads, int quads_per_row, long bs)
 {
     long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= total_quads) return;
+    A = bshift(A, bs);
+    const KernelParams& kp = kps.k[blockIdx.z];
     long row = q / quads_per_row;
     int i2 = (int)(q - row * quads_per_row) * 4;
     int i1 = (int)(row % g.n[1]);
@@ -45,24 +47,28 @@ __global__ void __launch_bounds__(256) k_grid_eval(T* __restrict__ A, GridAxes g
 }
 
 template <typename T>
-static hipError_t launch(T* A, const GridAxes& g, const KernelParams& kp, hipStream_t s)
+static hipError_t launch(T* A, const GridAxes& g, const KernelParams* kps, hipStream_t s, Bat bt)
 {
+    if (bt.nb < 1 || bt.nb > BATCH_MAX) return hipErrorInvalidValue;
+    KernelParamsBatch kb{};
+    for (int b = 0; b < bt.nb; ++b) kb.k[b] = kps[b];
     int qpr = (g.n[2] + 3) / 4;
     long rows = (long)g.n[0] * g.n[1];
     long total = rows * qpr;
     long blocks = (total + 255) / 256;
-    hipLaunchKernelGGL(k_grid_eval<T>, dim3((unsigned)blocks), dim3(256), 0, s, A, g, kp, total, qpr);
+    hipLaunchKernelGGL(k_grid_eval<T>, dim3((unsigned)blocks, 1, bt.nb), dim3(256), 0, s, A, g, kb, total, qpr,
+                       bt.bs);
     return hipGetLastError();
 }
 
-hipError_t launch_grid_eval_f32(float* A, const GridAxes& g, const KernelParams& kp, hipStream_t s)
+hipError_t launch_grid_eval_f32(float* A, const GridAxes& g, const KernelParams* kps, hipStream_t s, Bat bt)
 {
-    return launch(A, g, kp, s);
+    return launch(A, g, kps, s, bt);
 }
 
-hipError_t launch_grid_eval_f64(double* A, const GridAxes& g, const KernelParams& kp, hipStream_t s)
+hipError_t launch_grid_eval_f64(double* A, const GridAxes& g, const KernelParams* kps, hipStream_t s, Bat bt)
 {
-    return launch(A, g, kp, s);
+    return launch(A, g, kps, s, bt);
 }
 
 }  // namespace tk

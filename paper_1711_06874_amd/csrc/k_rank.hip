@@ -11,9 +11,14 @@ namespace tk {
 // ok[blockIdx.x] = 1 if the rule was met within len, else 0.
 __global__ void k_rank_rule(const double* __restrict__ lam, long sLam, int len, const double* __restrict__ total,
                             long sTotal, const double* __restrict__ scal, int has_d2, double eps2,
-                            int* __restrict__ ranks, int* __restrict__ ok)
+                            int* __restrict__ ranks, int* __restrict__ ok, long bs)
 {
     if (threadIdx.x != 0) return;
+    lam = bshift(lam, bs);
+    total = bshift(total, bs);
+    scal = bshift(scal, bs);
+    ranks = bshift(ranks, bs);
+    ok = bshift(ok, bs);
     const double* l = lam + blockIdx.x * sLam;
     double tot;
     if (total) tot = total[blockIdx.x * sTotal];
@@ -32,9 +37,12 @@ __global__ void k_rank_rule(const double* __restrict__ lam, long sLam, int len, 
 // out[0] = sum of X[a][b][c]^2 over entries outside [0,r0) x [0,r1) x [0,r2) (R0 x R1 x R2),
 // ranks read from device memory.
 __global__ void __launch_bounds__(256) k_trunc_err(const double* __restrict__ X, int R0, int R1, int R2,
-                                                   const int* __restrict__ ranks, double* __restrict__ out)
+                                                   const int* __restrict__ ranks, double* __restrict__ out, long bs)
 {
     __shared__ double red[4];
+    X = bshift(X, bs);
+    ranks = bshift(ranks, bs);
+    out = bshift(out, bs);
     const int r0 = ranks[0], r1 = ranks[1], r2 = ranks[2];
     double s = 0.0;
     for (int e = threadIdx.x; e < R0 * R1 * R2; e += 256) {
@@ -71,16 +79,17 @@ template hipError_t launch_copy_block<double, double>(const double*, int, int, d
 template hipError_t launch_copy_block<double, float>(const double*, int, int, float*, int, int, int, hipStream_t);
 
 hipError_t launch_rank_rule(const double* lam, long sLam, int len, int count, const double* total, long sTotal,
-                            const double* scal, int has_d2, double eps2, int* ranks, int* ok, hipStream_t s)
+                            const double* scal, int has_d2, double eps2, int* ranks, int* ok, hipStream_t s, Bat bt)
 {
-    hipLaunchKernelGGL(k_rank_rule, dim3(count), dim3(64), 0, s, lam, sLam, len, total, sTotal, scal, has_d2, eps2,
-                       ranks, ok);
+    hipLaunchKernelGGL(k_rank_rule, dim3(count, 1, bt.nb), dim3(64), 0, s, lam, sLam, len, total, sTotal, scal,
+                       has_d2, eps2, ranks, ok, bt.bs);
     return hipGetLastError();
 }
 
-hipError_t launch_trunc_err(const double* X, int R0, int R1, int R2, const int* ranks, double* out, hipStream_t s)
+hipError_t launch_trunc_err(const double* X, int R0, int R1, int R2, const int* ranks, double* out, hipStream_t s,
+                            Bat bt)
 {
-    hipLaunchKernelGGL(k_trunc_err, dim3(1), dim3(256), 0, s, X, R0, R1, R2, ranks, out);
+    hipLaunchKernelGGL(k_trunc_err, dim3(1, 1, bt.nb), dim3(256), 0, s, X, R0, R1, R2, ranks, out, bt.bs);
     return hipGetLastError();
 }
 
@@ -111,49 +120,55 @@ hipError_t launch_cov_trace(const double* G, int r0, int r1, int r2, const doubl
 }
 
 // E^2 = (d2 + t2) / a2 from scal = {a2, d2, t2, ...}; out = sqrt.
-__global__ void k_final_err(double* scal)
+__global__ void k_final_err(double* scal, long bs)
 {
+    scal = bshift(scal, bs);
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         double a2 = scal[0];
         scal[3] = a2 > 0.0 ? sqrt(fmax(scal[1] + scal[2], 0.0) / a2) : 0.0;
     }
 }
 
-hipError_t launch_final_err(double* scal, hipStream_t s)
+hipError_t launch_final_err(double* scal, hipStream_t s, Bat bt)
 {
-    hipLaunchKernelGGL(k_final_err, dim3(1), dim3(64), 0, s, scal);
+    hipLaunchKernelGGL(k_final_err, dim3(1, 1, bt.nb), dim3(64), 0, s, scal, bt.bs);
     return hipGetLastError();
 }
 
 // Zero the columns c >= rank of an n x R factor and the core entries outside the leading
 // r0 x r1 x r2 block (ranks from device memory), so that rank-R kernels evaluate the rank-r
 // result exactly.
-__global__ void k_mask_factor(double* __restrict__ U, long n, int R, const int* __restrict__ rank)
+__global__ void k_mask_factor(double* __restrict__ U, long n, int R, const int* __restrict__ rank, long bs)
 {
     long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * R) return;
+    U = bshift(U, bs);
+    rank = bshift(rank, bs);
     if ((int)(e % R) >= rank[0]) U[e] = 0.0;
 }
-__global__ void k_mask_core(double* __restrict__ X, int R0, int R1, int R2, const int* __restrict__ ranks)
+__global__ void k_mask_core(double* __restrict__ X, int R0, int R1, int R2, const int* __restrict__ ranks, long bs)
 {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= R0 * R1 * R2) return;
+    X = bshift(X, bs);
+    ranks = bshift(ranks, bs);
     int a = e / (R1 * R2), b = (e / R2) % R1, c = e % R2;
     if (a >= ranks[0] || b >= ranks[1] || c >= ranks[2]) X[e] = 0.0;
 }
 
 hipError_t launch_mask_rank(double* const U[3], const int n[3], const int R[3], double* core, const int* ranks,
-                            hipStream_t s)
+                            hipStream_t s, Bat bt)
 {
     for (int k = 0; k < 3; ++k) {
         long tot = (long)n[k] * R[k];
-        hipLaunchKernelGGL(k_mask_factor, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, U[k], (long)n[k], R[k],
-                           ranks + k);
+        hipLaunchKernelGGL(k_mask_factor, dim3((unsigned)((tot + 255) / 256), 1, bt.nb), dim3(256), 0, s, U[k],
+                           (long)n[k], R[k], ranks + k, bt.bs);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     int tot = R[0] * R[1] * R[2];
-    hipLaunchKernelGGL(k_mask_core, dim3((tot + 255) / 256), dim3(256), 0, s, core, R[0], R[1], R[2], ranks);
+    hipLaunchKernelGGL(k_mask_core, dim3((tot + 255) / 256, 1, bt.nb), dim3(256), 0, s, core, R[0], R[1], R[2], ranks,
+                       bt.bs);
     return hipGetLastError();
 }
 

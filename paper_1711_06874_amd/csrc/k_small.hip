@@ -21,6 +21,9 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g)
     constexpr int PER = GT * GK / 256;     // elements of each operand a thread stages per chunk
     __shared__ double As[GK][GT + 1];
     __shared__ double Bs[GK][GT + 1];
+    g.A = bshift(g.A, g.bs);
+    g.B = bshift(g.B, g.bs);
+    g.C = bshift(g.C, g.bs);
     const int tid = threadIdx.x;
     const int tiles_n = (g.N + GT - 1) / GT;
     const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
@@ -93,7 +96,8 @@ hipError_t launch_gemm(const GemmArgs& a, hipStream_t s)
     if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return hipSuccess;
     long tiles = (long)((a.M + GT - 1) / GT) * ((a.N + GT - 1) / GT);
     unsigned gy = a.reduce_batch ? 1u : (unsigned)a.batch;
-    hipLaunchKernelGGL((k_gemm<TA, TB, TC>), dim3((unsigned)tiles, gy), dim3(256), 0, s, a);
+    const unsigned gz = a.nb > 1 ? (unsigned)a.nb : 1u;
+    hipLaunchKernelGGL((k_gemm<TA, TB, TC>), dim3((unsigned)tiles, gy, gz), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -106,26 +110,46 @@ template hipError_t launch_gemm<double, float, float>(const GemmArgs&, hipStream
 template hipError_t launch_gemm<float, double, float>(const GemmArgs&, hipStream_t);
 
 // ------------------------------------------------------------------------ conversions ----
-__global__ void k_f64_to_f32(const double* __restrict__ x, float* __restrict__ y, long n)
+__global__ void k_f64_to_f32(const double* __restrict__ x, float* __restrict__ y, long n, long bs)
 {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = (float)x[i];
+    if (i < n) bshift(y, bs)[i] = (float)bshift(x, bs)[i];
 }
 __global__ void k_f32_to_f64(const float* __restrict__ x, double* __restrict__ y, long n)
 {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) y[i] = (double)x[i];
 }
-__global__ void k_fill_f64(double* __restrict__ x, double v, long n)
+__global__ void k_fill_f64(double* __restrict__ x, double v, long n, long bs)
 {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] = v;
+    if (i < n) bshift(x, bs)[i] = v;
+}
+__global__ void k_copy_f64(const double* __restrict__ x, double* __restrict__ y, long n, long bs)
+{
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) bshift(y, bs)[i] = bshift(x, bs)[i];
 }
 
-hipError_t launch_convert_f64_to_f32(const double* x, float* y, long n, hipStream_t s)
+// dst[b * words + i] = word i of problem b's record at src + b * bs
+__global__ void k_gather_u32(const uint32_t* __restrict__ src, long bs, int words, uint32_t* __restrict__ dst)
+{
+    const int i = threadIdx.x;
+    if (i < words) dst[(long)blockIdx.z * words + i] = bshift(src, bs)[i];
+}
+
+hipError_t launch_gather_u32(const void* src, long bs, int words, void* dst, int nb, hipStream_t s)
+{
+    if (words < 1 || words > 64 || nb < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gather_u32, dim3(1, 1, nb), dim3(64), 0, s, (const uint32_t*)src, bs, words,
+                       (uint32_t*)dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_f64_to_f32(const double* x, float* y, long n, hipStream_t s, Bat bt)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n);
+    hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((n + 255) / 256), 1, bt.nb), dim3(256), 0, s, x, y, n, bt.bs);
     return hipGetLastError();
 }
 hipError_t launch_convert_f32_to_f64(const float* x, double* y, long n, hipStream_t s)
@@ -134,10 +158,16 @@ hipError_t launch_convert_f32_to_f64(const float* x, double* y, long n, hipStrea
     hipLaunchKernelGGL(k_f32_to_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, y, n);
     return hipGetLastError();
 }
-hipError_t launch_fill_f64(double* x, double v, long n, hipStream_t s)
+hipError_t launch_fill_f64(double* x, double v, long n, hipStream_t s, Bat bt)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, v, n);
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((n + 255) / 256), 1, bt.nb), dim3(256), 0, s, x, v, n, bt.bs);
+    return hipGetLastError();
+}
+hipError_t launch_copy_f64(const double* x, double* y, long n, hipStream_t s, Bat bt)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_f64, dim3((unsigned)((n + 255) / 256), 1, bt.nb), dim3(256), 0, s, x, y, n, bt.bs);
     return hipGetLastError();
 }
 
@@ -160,10 +190,12 @@ __global__ void __launch_bounds__(256) k_dot_partial(const T* __restrict__ x, co
 }
 
 __global__ void __launch_bounds__(256) k_reduce_partials(const double* __restrict__ partials, int nparts,
-                                                         int width, double* __restrict__ out)
+                                                         int width, double* __restrict__ out, long bs)
 {
     // out[w] = sum_p partials[p * width + w], fixed order per thread then a fixed tree
     __shared__ double red[256];
+    partials = bshift(partials, bs);
+    out = bshift(out, bs);
     for (int w = 0; w < width; ++w) {
         double s = 0.0;
         for (int p = threadIdx.x; p < nparts; p += 256) s += partials[(long)p * width + w];
@@ -178,9 +210,9 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const double* __restric
     }
 }
 
-hipError_t launch_reduce_partials(const double* partials, int nparts, int width, double* out, hipStream_t s)
+hipError_t launch_reduce_partials(const double* partials, int nparts, int width, double* out, hipStream_t s, Bat bt)
 {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partials, nparts, width, out);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1, 1, bt.nb), dim3(256), 0, s, partials, nparts, width, out, bt.bs);
     return hipGetLastError();
 }
 

@@ -49,8 +49,12 @@ __device__ __forceinline__ void stage_tile(float (*S)[LDA], const float* __restr
 // T = A x_3 U^T.  Work-group: 64 rows of A (4 waves x 16 rows); U chunk in LDS.
 template <int NB>
 __global__ void __launch_bounds__(256) k_ttm_last(const float* __restrict__ A, long rows, int n2,
-                                                  const float* __restrict__ U, int r, float* __restrict__ T)
+                                                  const float* __restrict__ U, int r, float* __restrict__ T,
+                                                  long bs)
 {
+    A = bshift(A, bs);
+    U = bshift(U, bs);
+    T = bshift(T, bs);
     __shared__ __attribute__((aligned(16))) float As[TR][LDA];
     __shared__ float Us[BK][NB * 16];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -89,8 +93,12 @@ __global__ void __launch_bounds__(256) k_ttm_last(const float* __restrict__ A, l
 // S = A x_1 U^T.  Work-group: 64 columns of A (4 waves x 16 columns), all n0 rows.
 template <int NB>
 __global__ void __launch_bounds__(256) k_ttm_first(const float* __restrict__ A, int n0, long cols,
-                                                   const float* __restrict__ U, int r, float* __restrict__ S)
+                                                   const float* __restrict__ U, int r, float* __restrict__ S,
+                                                   long bs)
 {
+    A = bshift(A, bs);
+    U = bshift(U, bs);
+    S = bshift(S, bs);
     __shared__ __attribute__((aligned(16))) float As[TR][LDA];   // [k = i0][col]
     __shared__ float Us[BK][NB * 16];                            // [k][a]
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -134,8 +142,12 @@ __global__ void __launch_bounds__(256) k_ttm_first(const float* __restrict__ A, 
 template <int NB>
 __global__ void __launch_bounds__(256) k_recon_diff(const float* __restrict__ A, long rows, int n2,
                                                     const double* __restrict__ H, const double* __restrict__ U3,
-                                                    int r, double* __restrict__ partials)
+                                                    int r, double* __restrict__ partials, long bs)
 {
+    A = bshift(A, bs);
+    H = bshift(H, bs);
+    U3 = bshift(U3, bs);
+    partials = bshift(partials, bs);
     __shared__ double Hs[TR][NB * 16 + 1];     // [row][c]
     __shared__ double Ut[NB * 16][TR + 1];     // [c][k] for a 64-column chunk of U3^T
     __shared__ double red[2][4];
@@ -190,8 +202,11 @@ __global__ void __launch_bounds__(256) k_recon_diff(const float* __restrict__ A,
 // Generic (any type) partial sums of (X - Y)^2 and X^2.
 template <typename T>
 __global__ void __launch_bounds__(256) k_diff_norm(const T* __restrict__ X, const T* __restrict__ Y, long n,
-                                                   double* __restrict__ partials)
+                                                   double* __restrict__ partials, long bs)
 {
+    X = bshift(X, bs);
+    Y = bshift(Y, bs);
+    partials = bshift(partials, bs);
     __shared__ double red[2][4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     double d2 = 0.0, a2 = 0.0;
@@ -213,43 +228,48 @@ __global__ void __launch_bounds__(256) k_diff_norm(const T* __restrict__ X, cons
 
 }  // namespace
 
-hipError_t launch_ttm_last_f32(const float* A, long rows, int n2, const float* U, int r, float* T, hipStream_t s)
+hipError_t launch_ttm_last_f32(const float* A, long rows, int n2, const float* U, int r, float* T, hipStream_t s,
+                               Bat bt)
 {
-    dim3 grid((unsigned)((rows + TR - 1) / TR));
-    if (r <= 16) hipLaunchKernelGGL(k_ttm_last<1>, grid, dim3(256), 0, s, A, rows, n2, U, r, T);
-    else if (r <= 32) hipLaunchKernelGGL(k_ttm_last<2>, grid, dim3(256), 0, s, A, rows, n2, U, r, T);
-    else hipLaunchKernelGGL(k_ttm_last<3>, grid, dim3(256), 0, s, A, rows, n2, U, r, T);
+    dim3 grid((unsigned)((rows + TR - 1) / TR), 1, bt.nb);
+    if (r <= 16) hipLaunchKernelGGL(k_ttm_last<1>, grid, dim3(256), 0, s, A, rows, n2, U, r, T, bt.bs);
+    else if (r <= 32) hipLaunchKernelGGL(k_ttm_last<2>, grid, dim3(256), 0, s, A, rows, n2, U, r, T, bt.bs);
+    else hipLaunchKernelGGL(k_ttm_last<3>, grid, dim3(256), 0, s, A, rows, n2, U, r, T, bt.bs);
     return hipGetLastError();
 }
 
-hipError_t launch_ttm_first_f32(const float* A, int n0, long cols, const float* U, int r, float* S, hipStream_t s)
+hipError_t launch_ttm_first_f32(const float* A, int n0, long cols, const float* U, int r, float* S, hipStream_t s,
+                                Bat bt)
 {
-    dim3 grid((unsigned)((cols + TR - 1) / TR));
-    if (r <= 16) hipLaunchKernelGGL(k_ttm_first<1>, grid, dim3(256), 0, s, A, n0, cols, U, r, S);
-    else if (r <= 32) hipLaunchKernelGGL(k_ttm_first<2>, grid, dim3(256), 0, s, A, n0, cols, U, r, S);
-    else hipLaunchKernelGGL(k_ttm_first<3>, grid, dim3(256), 0, s, A, n0, cols, U, r, S);
+    dim3 grid((unsigned)((cols + TR - 1) / TR), 1, bt.nb);
+    if (r <= 16) hipLaunchKernelGGL(k_ttm_first<1>, grid, dim3(256), 0, s, A, n0, cols, U, r, S, bt.bs);
+    else if (r <= 32) hipLaunchKernelGGL(k_ttm_first<2>, grid, dim3(256), 0, s, A, n0, cols, U, r, S, bt.bs);
+    else hipLaunchKernelGGL(k_ttm_first<3>, grid, dim3(256), 0, s, A, n0, cols, U, r, S, bt.bs);
     return hipGetLastError();
 }
 
 int recon_diff_parts(long rows) { return (int)((rows + TR - 1) / TR); }
 
 hipError_t launch_recon_diff_f32(const float* A, long rows, int n2, const double* H, const double* U3, int r,
-                                 double* partials, hipStream_t s)
+                                 double* partials, hipStream_t s, Bat bt)
 {
-    dim3 grid((unsigned)recon_diff_parts(rows));
-    if (r <= 16) hipLaunchKernelGGL(k_recon_diff<1>, grid, dim3(256), 0, s, A, rows, n2, H, U3, r, partials);
-    else if (r <= 32) hipLaunchKernelGGL(k_recon_diff<2>, grid, dim3(256), 0, s, A, rows, n2, H, U3, r, partials);
-    else hipLaunchKernelGGL(k_recon_diff<3>, grid, dim3(256), 0, s, A, rows, n2, H, U3, r, partials);
+    dim3 grid((unsigned)recon_diff_parts(rows), 1, bt.nb);
+    if (r <= 16)
+        hipLaunchKernelGGL(k_recon_diff<1>, grid, dim3(256), 0, s, A, rows, n2, H, U3, r, partials, bt.bs);
+    else if (r <= 32)
+        hipLaunchKernelGGL(k_recon_diff<2>, grid, dim3(256), 0, s, A, rows, n2, H, U3, r, partials, bt.bs);
+    else
+        hipLaunchKernelGGL(k_recon_diff<3>, grid, dim3(256), 0, s, A, rows, n2, H, U3, r, partials, bt.bs);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_diff_norm(const T* X, const T* Y, long n, double* partials, int nparts, hipStream_t s)
+hipError_t launch_diff_norm(const T* X, const T* Y, long n, double* partials, int nparts, hipStream_t s, Bat bt)
 {
-    hipLaunchKernelGGL(k_diff_norm<T>, dim3(nparts), dim3(256), 0, s, X, Y, n, partials);
+    hipLaunchKernelGGL(k_diff_norm<T>, dim3(nparts, 1, bt.nb), dim3(256), 0, s, X, Y, n, partials, bt.bs);
     return hipGetLastError();
 }
-template hipError_t launch_diff_norm<float>(const float*, const float*, long, double*, int, hipStream_t);
-template hipError_t launch_diff_norm<double>(const double*, const double*, long, double*, int, hipStream_t);
+template hipError_t launch_diff_norm<float>(const float*, const float*, long, double*, int, hipStream_t, Bat);
+template hipError_t launch_diff_norm<double>(const double*, const double*, long, double*, int, hipStream_t, Bat);
 
 }  // namespace tk

@@ -125,7 +125,10 @@ struct tk_ctx {
     int matvec_method = TK_MV_AUTO;
     size_t budget = 0;
     std::atomic<size_t> in_use{0};
-    std::atomic<int> live_results{0};
+    // results made with the context; a destroyed context is deleted with its last result
+    std::mutex life_mu;
+    int live_results = 0;
+    bool closing = false;
     // scalar readbacks go through pinned host slots (and matching device slots) handed out per
     // call, so concurrent calls on different streams do not share a staging buffer
     static constexpr int kSlots = 64;
@@ -174,6 +177,13 @@ struct Reservation {
     bool held;
     Reservation(tk_ctx* c_, size_t b) : c(c_), bytes(b), held(false) {}
     bool take() { held = reserve(c, bytes); return held; }
+    // part of the reservation passes to an object that releases it itself (a result)
+    bool hand_over(size_t b)
+    {
+        if (!held || b > bytes) return false;
+        bytes -= b;
+        return true;
+    }
     ~Reservation() { if (held) release(c, bytes); }
 };
 
@@ -296,6 +306,7 @@ struct Work {
     // eps truncation (float paths)
     double *Gc, *Vc, *lamc, *tQ, *tY, *tH, *tVs, *coreA, *coreB, *Urot[3];
     int nparts;
+    Bat bt;                  // problems sharing this layout, bt.bs bytes apart (pointers: problem 0)
 };
 
 void layout_work(Arena& ar, const Plan& P, bool own_A, Work& w)
@@ -364,12 +375,14 @@ size_t result_bytes(const int n[3], const int r[3])
     return ar.off;
 }
 
+// Device bytes of one compression (workspace, gather area of the final readback, result); the
+// same layout as compress_impl with one problem.
 size_t estimate(const Plan& P, bool own_A)
 {
     Arena ar;
     Work w;
     layout_work(ar, P, own_A, w);
-    return ar.off + result_bytes(P.n, P.R);
+    return align_up(ar.off, 256) + 256 + result_bytes(P.n, P.R);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -385,6 +398,15 @@ GemmArgs gemm(int M, int N, int K, int batch, const void* A, long sAb, long sAm,
     g.C = C; g.sCb = sCb; g.sCm = sCm; g.sCn = sCn;
     g.alpha = 1.0; g.beta = 0.0;
     return g;
+}
+
+// A small product of the compression pipeline, over every problem of the workspace batch.
+template <typename TA, typename TB, typename TC>
+hipError_t wgemm(GemmArgs g, const Work& w, hipStream_t s)
+{
+    g.nb = w.bt.nb;
+    g.bs = w.bt.bs;
+    return launch_gemm<TA, TB, TC>(g, s);
 }
 
 #define TK_LAUNCH(x)                                                                               \
@@ -446,7 +468,8 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
     // SPAN_ITERS_F32 times (its leading k-dimensional part converges like (lambda_{R+1} /
     // lambda_k)^iters for the eps rank k << R), without the Rayleigh-Ritz rotation.
     const bool span = P.eps_mode && P.prec != TK_FP64;
-    if (P.cubic) {
+    // one launch for the three modes when they share n, p and R
+    if (P.cubic && P.R[0] == P.R[1] && P.R[1] == P.R[2] && P.p[0] == P.p[1] && P.p[1] == P.p[2]) {
         EigBatch b{};
         b.count = 3; b.n = P.n[0]; b.p = P.p[0]; b.r = P.R[0]; b.rw = 0; b.ldw = 0;
         if (span && P.R[0] < P.n[0]) { b.p = P.R[0]; b.span_only = 1; }
@@ -456,14 +479,14 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
         b.U = w.Y; b.sU = (long)P.n[0] * P.R[0]; b.ldu = P.R[0];
         b.lam = w.lam; b.sL = 64;
         b.trace = w.trace; b.sTrace = 1;
+        b.nb = w.bt.nb; b.bs = w.bt.bs;
         // the eigensolver writes U after its last use of Y, so U may alias Y
         {
             ProfScope ps(TK_PROF_EIG, s);
             TK_LAUNCH(launch_eig(b, b.span_only ? SPAN_ITERS_F32 : (P.prec == TK_FP64 ? COLD_ITERS : COLD_ITERS_F32), s));
         }
         for (int k = 0; k < 3; ++k)
-            TK_HIP(hipMemcpyAsync(w.U[k], w.Y + (long)k * P.n[0] * P.R[0], sizeof(double) * P.n[0] * P.R[0],
-                                  hipMemcpyDeviceToDevice, s));
+            TK_LAUNCH(launch_copy_f64(w.Y + (long)k * P.n[0] * P.R[0], w.U[k], (long)P.n[0] * P.R[0], s, w.bt));
     } else {
         for (int k = 0; k < 3; ++k) {
             EigBatch b{};
@@ -473,6 +496,7 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
             b.U = w.U[k]; b.sU = 0; b.ldu = P.R[k];
             b.lam = w.lam + 64 * k; b.sL = 64;
             b.trace = w.trace + k; b.sTrace = 1;
+            b.nb = w.bt.nb; b.bs = w.bt.bs;
             if (span && P.R[k] < P.n[k]) { b.p = P.R[k]; b.span_only = 1; }
             ProfScope ps(TK_PROF_EIG, s);
             TK_LAUNCH(launch_eig(b, b.span_only ? SPAN_ITERS_F32 : (P.prec == TK_FP64 ? COLD_ITERS : COLD_ITERS_F32), s));
@@ -502,18 +526,19 @@ tk_status eig_update(const Plan& P, Work& w, int k, const double* Gs, hipStream_
     b.sU = 0; b.ldu = P.R[k];
     b.lam = w.lam + 64 * k; b.sL = 64;
     b.trace = nullptr;
+    b.nb = w.bt.nb; b.bs = w.bt.bs;
     {
         ProfScope ps(TK_PROF_EIG, s);
         TK_LAUNCH(launch_eig(b, P.prec == TK_FP64 ? WARM_ITERS : WARM_ITERS_F32, s));
     }
-    TK_HIP(hipMemcpyAsync(w.U[k], b.U, sizeof(double) * P.n[k] * P.R[k], hipMemcpyDeviceToDevice, s));
+    TK_LAUNCH(launch_copy_f64(b.U, w.U[k], (long)P.n[k] * P.R[k], s, w.bt));
     return TK_OK;
 }
 
 template <typename Real>
 tk_status refresh_u32(const Plan& P, Work& w, int k, hipStream_t s)
 {
-    if (sizeof(Real) == 4) TK_LAUNCH(launch_convert_f64_to_f32(w.U[k], w.U32[k], (long)P.n[k] * P.R[k], s));
+    if (sizeof(Real) == 4) TK_LAUNCH(launch_convert_f64_to_f32(w.U[k], w.U32[k], (long)P.n[k] * P.R[k], s, w.bt));
     return TK_OK;
 }
 
@@ -524,10 +549,10 @@ tk_status ttm_last(const Plan& P, Work& w, const Real* A, hipStream_t s)
     long rows = (long)P.n[0] * P.n[1];
     ProfScope ps(TK_PROF_TTM, s);
     if (sizeof(Real) == 4) {
-        TK_LAUNCH(launch_ttm_last_f32((const float*)A, rows, P.n[2], w.U32[2], P.R[2], (float*)w.T, s));
+        TK_LAUNCH(launch_ttm_last_f32((const float*)A, rows, P.n[2], w.U32[2], P.R[2], (float*)w.T, s, w.bt));
     } else {
         GemmArgs g = gemm((int)rows, P.R[2], P.n[2], 1, A, 0, P.n[2], 1, w.U[2], 0, P.R[2], 1, w.T, 0, P.R[2], 1);
-        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+        TK_LAUNCH((wgemm<double, double, double>(g, w, s)));
     }
     return TK_OK;
 }
@@ -539,23 +564,23 @@ tk_status ttm_first(const Plan& P, Work& w, const Real* A, hipStream_t s)
     long cols = (long)P.n[1] * P.n[2];
     ProfScope ps(TK_PROF_TTM, s);
     if (sizeof(Real) == 4) {
-        TK_LAUNCH(launch_ttm_first_f32((const float*)A, P.n[0], cols, w.U32[0], P.R[0], (float*)w.S, s));
+        TK_LAUNCH(launch_ttm_first_f32((const float*)A, P.n[0], cols, w.U32[0], P.R[0], (float*)w.S, s, w.bt));
     } else {
         GemmArgs g = gemm(P.R[0], (int)cols, P.n[0], 1, w.U[0], 0, 1, P.R[0], A, 0, cols, 1, w.S, 0, cols, 1);
-        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+        TK_LAUNCH((wgemm<double, double, double>(g, w, s)));
     }
     return TK_OK;
 }
 
 template <typename Real>
-hipError_t gemm_rd(const GemmArgs& g, hipStream_t s)   // Real operand A, double B, double C
+hipError_t gemm_rd(const GemmArgs& g, const Work& w, hipStream_t s)   // Real operand A, double B, double C
 {
-    return launch_gemm<Real, double, double>(g, s);
+    return wgemm<Real, double, double>(g, w, s);
 }
 template <typename Real>
-hipError_t gemm_dr(const GemmArgs& g, hipStream_t s)   // double A, Real B, double C
+hipError_t gemm_dr(const GemmArgs& g, const Work& w, hipStream_t s)   // double A, Real B, double C
 {
-    return launch_gemm<double, Real, double>(g, s);
+    return wgemm<double, Real, double>(g, w, s);
 }
 
 // B1[i0][b][c] = sum_i1 U2[i1][b] T[i0][i1][c]
@@ -564,16 +589,16 @@ tk_status single_hole_1(const Plan& P, Work& w, hipStream_t s)
 {
     const int n0 = P.n[0], n1 = P.n[1], R1 = P.R[1], R2 = P.R[2];
     GemmArgs g = gemm(R1, R2, n1, n0, w.U[1], 0, 1, R1, w.T, (long)n1 * R2, R2, 1, w.B, (long)R1 * R2, R2, 1);
-    TK_LAUNCH(gemm_dr<Real>(g, s));
+    TK_LAUNCH(gemm_dr<Real>(g, w, s));
     return TK_OK;
 }
 
 // small Gram of a row-major n x K unfolding stored in w.B -> Gs (n x n)
 // G = mode-`mode` Gram of the small FP64 tensor B (dims d, C-order): split-K FP64 MFMA tiles
 // with a fixed-order reduction, as for the Grams of A.
-tk_status small_gram(const int d[3], int mode, const double* B, double* G, void* work, hipStream_t s)
+tk_status small_gram(const int d[3], int mode, const double* B, double* G, void* work, hipStream_t s, Bat bt)
 {
-    TK_LAUNCH(launch_gram(B, d, mode, TK_FP64, G, work, s));
+    TK_LAUNCH(launch_gram(B, d, mode, TK_FP64, G, work, s, bt));
     return TK_OK;
 }
 
@@ -589,18 +614,18 @@ tk_status hooi_sweep(const Plan& P, Work& w, const Real* A, int nmax, hipStream_
     if ((st = single_hole_1<Real>(P, w, s)) != TK_OK) return st;
     {
         const int d[3] = {n0, R1, R2};
-        if ((st = small_gram(d, 0, w.B, Gs, w.gram_work, s)) != TK_OK) return st;
+        if ((st = small_gram(d, 0, w.B, Gs, w.gram_work, s, w.bt)) != TK_OK) return st;
     }
     if ((st = eig_update(P, w, 0, Gs, s)) != TK_OK) return st;
     if ((st = refresh_u32<Real>(P, w, 0, s)) != TK_OK) return st;
     // ---- mode 2: B2[i1][a][c] = sum_i0 U1[i0][a] T[i0][i1][c]  (T still holds A x_3 U3^T)
     {
         GemmArgs g = gemm(R0, R2, n0, n1, w.U[0], 0, 1, R0, w.T, R2, (long)n1 * R2, 1, w.B, (long)R0 * R2, R2, 1);
-        TK_LAUNCH(gemm_dr<Real>(g, s));
+        TK_LAUNCH(gemm_dr<Real>(g, w, s));
     }
     {
         const int d[3] = {n1, R0, R2};
-        if ((st = small_gram(d, 0, w.B, Gs, w.gram_work, s)) != TK_OK) return st;
+        if ((st = small_gram(d, 0, w.B, Gs, w.gram_work, s, w.bt)) != TK_OK) return st;
     }
     if ((st = eig_update(P, w, 1, Gs, s)) != TK_OK) return st;
     if ((st = refresh_u32<Real>(P, w, 1, s)) != TK_OK) return st;
@@ -608,19 +633,19 @@ tk_status hooi_sweep(const Plan& P, Work& w, const Real* A, int nmax, hipStream_
     if ((st = ttm_first<Real>(P, w, A, s)) != TK_OK) return st;
     {
         GemmArgs g = gemm(n2, R1, n1, R0, w.S, (long)n1 * n2, 1, n2, w.U[1], 0, R1, 1, w.B, (long)n2 * R1, R1, 1);
-        TK_LAUNCH(gemm_rd<Real>(g, s));
+        TK_LAUNCH(gemm_rd<Real>(g, w, s));
     }
     {
         // Gs[i2][i2'] = sum_a sum_b B3[a][i2][b] B3[a][i2'][b]: the mode-2 Gram of B3 (R0 x n2 x R1)
         const int d[3] = {R0, n2, R1};
-        if ((st = small_gram(d, 1, w.B, Gs, w.gram_work, s)) != TK_OK) return st;
+        if ((st = small_gram(d, 1, w.B, Gs, w.gram_work, s, w.bt)) != TK_OK) return st;
     }
     if ((st = eig_update(P, w, 2, Gs, s)) != TK_OK) return st;
     if ((st = refresh_u32<Real>(P, w, 2, s)) != TK_OK) return st;
     // ---- core[a][b][c] = sum_i2 B3[a][i2][b] U3[i2][c]
     {
         GemmArgs g = gemm(R1, R2, n2, R0, w.B, (long)n2 * R1, 1, R1, w.U[2], 0, R2, 1, w.core, (long)R1 * R2, R2, 1);
-        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+        TK_LAUNCH((wgemm<double, double, double>(g, w, s)));
     }
     (void)nmax;
     return TK_OK;
@@ -635,7 +660,7 @@ tk_status hosvd_core(const Plan& P, Work& w, const Real* A, hipStream_t s)
     if ((st = single_hole_1<Real>(P, w, s)) != TK_OK) return st;
     const int n0 = P.n[0], R0 = P.R[0], R1 = P.R[1], R2 = P.R[2];
     GemmArgs g = gemm(R0, R1 * R2, n0, 1, w.U[0], 0, 1, R0, w.B, 0, (long)R1 * R2, 1, w.core, 0, (long)R1 * R2, 1);
-    TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+    TK_LAUNCH((wgemm<double, double, double>(g, w, s)));
     return TK_OK;
 }
 
@@ -648,29 +673,29 @@ tk_status recon_norm(const Plan& P, Work& w, const Real* A, double* const Uf[3],
     // M1[i0][b][c] = sum_a U1[i0][a] core[a][b][c]
     {
         GemmArgs g = gemm(n0, R1 * R2, R0, 1, Uf[0], 0, R0, 1, corep, 0, (long)R1 * R2, 1, w.M1, 0, (long)R1 * R2, 1);
-        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+        TK_LAUNCH((wgemm<double, double, double>(g, w, s)));
     }
     // H[i0][i1][c] = sum_b U2[i1][b] M1[i0][b][c]   (FP64)
     {
         GemmArgs g = gemm(n1, R2, R1, n0, Uf[1], 0, R1, 1, w.M1, (long)R1 * R2, R2, 1, w.Hrec, (long)n1 * R2, R2, 1);
-        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+        TK_LAUNCH((wgemm<double, double, double>(g, w, s)));
     }
     long rows = (long)n0 * n1;
     ProfScope ps(TK_PROF_NORM, s);
     if (sizeof(Real) == 4) {
         int parts = recon_diff_parts(rows);
-        TK_LAUNCH(launch_recon_diff_f32((const float*)A, rows, n2, w.Hrec, Uf[2], R2, w.partials, s));
-        TK_LAUNCH(launch_reduce_partials(w.partials, parts, 2, w.scal + 8, s));
+        TK_LAUNCH(launch_recon_diff_f32((const float*)A, rows, n2, w.Hrec, Uf[2], R2, w.partials, s, w.bt));
+        TK_LAUNCH(launch_reduce_partials(w.partials, parts, 2, w.scal + 8, s, w.bt));
     } else {
         GemmArgs g = gemm((int)rows, n2, R2, 1, w.Hrec, 0, R2, 1, Uf[2], 0, 1, R2, w.Ahat, 0, n2, 1);
-        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+        TK_LAUNCH((wgemm<double, double, double>(g, w, s)));
         int parts = 1024;
-        TK_LAUNCH(launch_diff_norm<double>((const double*)A, w.Ahat, rows * n2, w.partials, parts, s));
-        TK_LAUNCH(launch_reduce_partials(w.partials, parts, 2, w.scal + 8, s));
+        TK_LAUNCH(launch_diff_norm<double>((const double*)A, w.Ahat, rows * n2, w.partials, parts, s, w.bt));
+        TK_LAUNCH(launch_reduce_partials(w.partials, parts, 2, w.scal + 8, s, w.bt));
     }
     // scal[8] = d2, scal[9] = a2 -> scal[0] = a2, scal[1] = d2
-    TK_HIP(hipMemcpyAsync(w.scal + 1, w.scal + 8, sizeof(double), hipMemcpyDeviceToDevice, s));
-    TK_HIP(hipMemcpyAsync(w.scal + 0, w.scal + 9, sizeof(double), hipMemcpyDeviceToDevice, s));
+    TK_LAUNCH(launch_copy_f64(w.scal + 8, w.scal + 1, 1, s, w.bt));
+    TK_LAUNCH(launch_copy_f64(w.scal + 9, w.scal + 0, 1, s, w.bt));
     return TK_OK;
 }
 
@@ -687,7 +712,7 @@ tk_status core_truncate(const Plan& P, Work& w, hipStream_t s)
         const int d[3] = {R0, R1, R2};
         tk_status st;
         for (int k = 0; k < 3; ++k)
-            if ((st = small_gram(d, k, w.core, w.Gc + k * RR, w.gram_work, s)) != TK_OK) return st;
+            if ((st = small_gram(d, k, w.core, w.Gc + k * RR, w.gram_work, s, w.bt)) != TK_OK) return st;
     }
     // full eigendecompositions (p = n = R_k); one launch for the three modes when the ranks agree
     if (R0 == R1 && R1 == R2) {
@@ -698,6 +723,7 @@ tk_status core_truncate(const Plan& P, Work& w, hipStream_t s)
         b.U = w.Vc; b.sU = RR; b.ldu = R0;
         b.lam = w.lamc; b.sL = 64;
         b.trace = nullptr;
+        b.nb = w.bt.nb; b.bs = w.bt.bs;
         TK_LAUNCH(launch_eig(b, 0, s));
     } else {
         for (int k = 0; k < 3; ++k) {
@@ -708,43 +734,46 @@ tk_status core_truncate(const Plan& P, Work& w, hipStream_t s)
             b.U = w.Vc + k * RR; b.sU = 0; b.ldu = P.R[k];
             b.lam = w.lamc + 64 * k; b.sL = 64;
             b.trace = nullptr;
+            b.nb = w.bt.nb; b.bs = w.bt.bs;
             TK_LAUNCH(launch_eig(b, 0, s));
         }
     }
     // ranks: budget = (eps^2 a2 - d2) / 3 per mode
     for (int k = 0; k < 3; ++k)
         TK_LAUNCH(launch_rank_rule(w.lamc + 64 * k, 64, P.R[k], 1, nullptr, 0, w.scal, 1, P.eps * P.eps,
-                                   w.ranks + k, w.ranks + 3 + k, s));
+                                   w.ranks + k, w.ranks + 3 + k, s, w.bt));
     // rotate factors: Urot_k = U_k V_k
     for (int k = 0; k < 3; ++k) {
         GemmArgs g = gemm(P.n[k], P.R[k], P.R[k], 1, w.U[k], 0, P.R[k], 1, w.Vc + k * RR, 0, P.R[k], 1, w.Urot[k], 0,
                           P.R[k], 1);
-        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+        TK_LAUNCH((wgemm<double, double, double>(g, w, s)));
         // sign rule on the rotated factor; the flips go into V_k so that the core follows
-        TK_LAUNCH(launch_signfix_pair(w.Urot[k], P.R[k], P.n[k], w.Vc + k * RR, P.R[k], P.R[k], P.R[k], s));
+        TK_LAUNCH(launch_signfix_pair(w.Urot[k], P.R[k], P.n[k], w.Vc + k * RR, P.R[k], P.R[k], P.R[k], s, w.bt));
     }
     // rotate core: coreB = core x_1 V1^T x_2 V2^T x_3 V3^T
     {
         GemmArgs g = gemm(R0, R1 * R2, R0, 1, w.Vc, 0, 1, R0, w.core, 0, (long)R1 * R2, 1, w.coreA, 0, (long)R1 * R2, 1);
-        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+        TK_LAUNCH((wgemm<double, double, double>(g, w, s)));
         GemmArgs g1 = gemm(R1, R2, R1, R0, w.Vc + RR, 0, 1, R1, w.coreA, (long)R1 * R2, R2, 1, w.coreB, (long)R1 * R2,
                            R2, 1);
-        TK_LAUNCH((launch_gemm<double, double, double>(g1, s)));
+        TK_LAUNCH((wgemm<double, double, double>(g1, w, s)));
         GemmArgs g2 = gemm(R0 * R1, R2, R2, 1, w.coreB, 0, R2, 1, w.Vc + 2 * RR, 0, R2, 1, w.coreA, 0, R2, 1);
-        TK_LAUNCH((launch_gemm<double, double, double>(g2, s)));
+        TK_LAUNCH((wgemm<double, double, double>(g2, w, s)));
     }
-    TK_LAUNCH(launch_trunc_err(w.coreA, R0, R1, R2, w.ranks, w.scal + 2, s));
-    TK_LAUNCH(launch_final_err(w.scal, s));
+    TK_LAUNCH(launch_trunc_err(w.coreA, R0, R1, R2, w.ranks, w.scal + 2, s, w.bt));
+    TK_LAUNCH(launch_final_err(w.scal, s, w.bt));
     return TK_OK;
 }
 
-tk_status alloc_result(tk_ctx* ctx, const int n[3], const int r[3], hipStream_t s, tk_tucker** out)
+// held: a reservation of the caller that covers the result (its share is handed over).
+tk_status alloc_result(tk_ctx* ctx, const int n[3], const int r[3], hipStream_t s, tk_tucker** out,
+                       Reservation* held = nullptr)
 {
     tk_tucker* t = new (std::nothrow) tk_tucker();
     if (!t) return fail(TK_ENOMEM, "host allocation failed");
     t->ctx = ctx;
     size_t bytes = result_bytes(n, r);
-    if (!reserve(ctx, bytes)) {
+    if (!(held && held->hand_over(bytes)) && !reserve(ctx, bytes)) {
         delete t;
         return fail(TK_ENOMEM, "result (%zu bytes) exceeds the remaining HBM budget", bytes);
     }
@@ -768,7 +797,10 @@ tk_status alloc_result(tk_ctx* ctx, const int n[3], const int r[3], hipStream_t 
     }
     t->core = ar.take<double>((size_t)r[0] * r[1] * r[2]);
     t->core32 = ar.take<float>((size_t)r[0] * r[1] * r[2]);
-    ctx->live_results.fetch_add(1);
+    {
+        std::lock_guard<std::mutex> g(ctx->life_mu);
+        ++ctx->live_results;
+    }
     *out = t;
     return TK_OK;
 }
@@ -780,11 +812,25 @@ void free_result(tk_tucker* t)
         // the result may have been read on any stream: free it once the device is idle
         hipSetDevice(t->ctx->device);
         hipDeviceSynchronize();
-        hipFreeAsync(t->block, t->stream);
+        hipFreeAsync(t->block, nullptr);
     }
-    release(t->ctx, t->bytes);
-    t->ctx->live_results.fetch_sub(1);
+    tk_ctx* ctx = t->ctx;
+    release(ctx, t->bytes);
     delete t;
+    bool last = false;
+    {
+        std::lock_guard<std::mutex> g(ctx->life_mu);
+        last = (--ctx->live_results == 0) && ctx->closing;
+    }
+    if (last) delete ctx;
+}
+
+// Results of a destroyed context can only be freed.
+bool usable(const tk_tucker* t)
+{
+    if (!t) return false;
+    std::lock_guard<std::mutex> g(t->ctx->life_mu);
+    return !t->ctx->closing;
 }
 
 tk_status fill_result_from(tk_tucker* t, const double* const Usrc[3], const int ldU[3], const double* core,
@@ -800,22 +846,40 @@ tk_status fill_result_from(tk_tucker* t, const double* const Usrc[3], const int 
     return TK_OK;
 }
 
-// The compression pipeline for one tensor.  A_in: caller tensor or nullptr (sample kernel).
-template <typename Real>
-tk_status compress_impl(tk_ctx* ctx, const KernelParams* kp, const void* A_in, const tk_grid* grid, Plan P,
-                        hipStream_t s, tk_tucker** out)
+// Bytes of nb workspaces of plan P laid out back to back (stride ws), plus the gather area of
+// the final readback.
+size_t batch_layout(const Plan& P, bool own_A, int nb, size_t* ws)
 {
-    const bool own_A = (A_in == nullptr);
-    size_t need = estimate(P, own_A);
-    Reservation res(ctx, need);
-    if (!res.take()) return fail(TK_ENOMEM, "compress needs %zu bytes; budget %zu, in use %zu", need, ctx->budget,
-                                 ctx->in_use.load());
     Arena plan;
     Work w;
     layout_work(plan, P, own_A, w);
+    *ws = align_up(plan.off, 256);
+    return *ws * (size_t)nb + align_up((size_t)nb * 64, 256);
+}
+
+// The compression pipeline for nb problems of one shape: problem b samples kps[b] on `grid`
+// (A_in: one caller tensor instead, nb == 1).  The problems' workspaces lie ws bytes apart and
+// every launch covers all of them (grid z), each problem running the work-groups it runs alone.
+// outs[b] / sts[b]: the result and TK_OK or TK_ENOCONV (eps not met; the result is returned
+// anyway).  Any other error is returned for the whole call, with no results.
+template <typename Real>
+tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void* A_in, const tk_grid* grid, Plan P,
+                        hipStream_t s, tk_tucker** outs, tk_status* sts)
+{
+    const bool own_A = (A_in == nullptr);
+    if (nb < 1 || nb > BATCH_MAX || (!own_A && nb != 1)) return fail(TK_EINVAL, "batch of %d problems", nb);
+    if (nb > 1 && P.eps_mode && P.prec == TK_FP64)
+        return fail(TK_EINVAL, "the FP64 eps path picks ranks between steps: one problem per call");
+    for (int b = 0; b < nb; ++b) { outs[b] = nullptr; sts[b] = TK_OK; }
+    size_t ws = 0;
+    const size_t total = batch_layout(P, own_A, nb, &ws);
+    const size_t need = total + (size_t)nb * result_bytes(P.n, P.R);
+    Reservation res(ctx, need);
+    if (!res.take()) return fail(TK_ENOMEM, "compress needs %zu bytes; budget %zu, in use %zu", need, ctx->budget,
+                                 ctx->in_use.load());
     void* base = nullptr;
-    hipError_t he = hipMallocAsync(&base, plan.off, s);
-    if (he != hipSuccess) return fail(TK_ENOMEM, "hipMallocAsync(%zu): %s", plan.off, hipGetErrorString(he));
+    hipError_t he = hipMallocAsync(&base, total, s);
+    if (he != hipSuccess) return fail(TK_ENOMEM, "hipMallocAsync(%zu): %s", total, hipGetErrorString(he));
     struct Freer {
         void* p;
         hipStream_t s;
@@ -823,7 +887,11 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kp, const void* A_in, c
     } freer{base, s};
     Arena ar;
     ar.base = (char*)base;
+    Work w;
     layout_work(ar, P, own_A, w);
+    w.bt.nb = nb;
+    w.bt.bs = (long)ws;
+    char* gather = (char*)base + ws * (size_t)nb;
     const int nmax = std::max(P.n[0], std::max(P.n[1], P.n[2]));
     const Real* A = own_A ? (const Real*)w.A : (const Real*)A_in;
     tk_status st;
@@ -831,13 +899,13 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kp, const void* A_in, c
     if (own_A) {
         GridAxes ax = axes_of(grid);
         ProfScope ps(TK_PROF_GRID, s);
-        if (sizeof(Real) == 4) TK_LAUNCH(launch_grid_eval_f32((float*)w.A, ax, *kp, s));
-        else TK_LAUNCH(launch_grid_eval_f64((double*)w.A, ax, *kp, s));
+        if (sizeof(Real) == 4) TK_LAUNCH(launch_grid_eval_f32((float*)w.A, ax, kps, s, w.bt));
+        else TK_LAUNCH(launch_grid_eval_f64((double*)w.A, ax, kps, s, w.bt));
     }
     // ---- HOSVD: Grams and leading eigenvectors
     for (int k = 0; k < 3; ++k) {
         ProfScope ps(TK_PROF_GRAM, s);
-        TK_LAUNCH(launch_gram(A, P.n, k, P.prec, w.G + (long)k * nmax * nmax, w.gram_work, s));
+        TK_LAUNCH(launch_gram(A, P.n, k, P.prec, w.G + (long)k * nmax * nmax, w.gram_work, s, w.bt));
     }
     if ((st = eig_modes(P, w, nmax, s)) != TK_OK) return st;
 
@@ -878,50 +946,82 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kp, const void* A_in, c
     // ---- reconstruction error
     if ((st = recon_norm<Real>(P, w, A, w.U, w.core, s)) != TK_OK) return st;
 
-    int final_r[3] = {P.R[0], P.R[1], P.R[2]};
-    double hs[4];
-    int hr[6] = {P.R[0], P.R[1], P.R[2], 1, 1, 1};
+    const bool trunc = P.eps_mode && P.prec != TK_FP64;
     const double* Usrc[3] = {w.U[0], w.U[1], w.U[2]};
     const double* csrc = w.core;
-    if (P.eps_mode && P.prec != TK_FP64) {
+    if (trunc) {
         // ranks from the core HOSVD with the (conservative) error bound, then the error of the
         // truncated result measured directly against A
         if ((st = core_truncate(P, w, s)) != TK_OK) return st;
-        TK_LAUNCH(launch_mask_rank(w.Urot, P.n, P.R, w.coreA, w.ranks, s));
+        TK_LAUNCH(launch_mask_rank(w.Urot, P.n, P.R, w.coreA, w.ranks, s, w.bt));
         if ((st = recon_norm<Real>(P, w, A, w.Urot, w.coreA, s)) != TK_OK) return st;
-        TK_LAUNCH(launch_fill_f64(w.scal + 2, 0.0, 1, s));
-        TK_LAUNCH(launch_final_err(w.scal, s));
-        if ((st = readback(ctx, s, w.ranks, sizeof(hr), hr, w.scal, sizeof(hs), hs)) != TK_OK) return st;
-        for (int k = 0; k < 3; ++k) { final_r[k] = hr[k]; Usrc[k] = w.Urot[k]; }
+        TK_LAUNCH(launch_fill_f64(w.scal + 2, 0.0, 1, s, w.bt));
+        TK_LAUNCH(launch_final_err(w.scal, s, w.bt));
+        for (int k = 0; k < 3; ++k) Usrc[k] = w.Urot[k];
         csrc = w.coreA;
     } else {
-        TK_LAUNCH(launch_fill_f64(w.scal + 2, 0.0, 1, s));   // no truncation: t2 = 0
-        TK_LAUNCH(launch_final_err(w.scal, s));
-        if ((st = readback(ctx, s, w.scal, sizeof(hs), hs)) != TK_OK) return st;
+        TK_LAUNCH(launch_fill_f64(w.scal + 2, 0.0, 1, s, w.bt));   // no truncation: t2 = 0
+        TK_LAUNCH(launch_final_err(w.scal, s, w.bt));
     }
-    tk_tucker* t = nullptr;
-    if ((st = alloc_result(ctx, P.n, final_r, s, &t)) != TK_OK) return st;
-    int ld[3] = {P.R[0], P.R[1], P.R[2]};
-    int Rc[3] = {P.R[0], P.R[1], P.R[2]};
-    if ((st = fill_result_from(t, Usrc, ld, csrc, Rc, s)) != TK_OK) {
-        free_result(t);
-        return st;
+    // ---- per problem: ranks (6 ints, padded to 8) and scal[0..3] (4 doubles)
+    std::vector<int> hr((size_t)nb * 8);
+    std::vector<double> hs((size_t)nb * 4);
+    if (nb == 1) {
+        int r6[6] = {P.R[0], P.R[1], P.R[2], 1, 1, 1};
+        if (trunc) { if ((st = readback(ctx, s, w.ranks, sizeof(r6), r6, w.scal, 4 * sizeof(double), hs.data())) != TK_OK) return st; }
+        else if ((st = readback(ctx, s, w.scal, 4 * sizeof(double), hs.data())) != TK_OK) return st;
+        std::memcpy(hr.data(), r6, sizeof(r6));
+    } else {
+        int* granks = (int*)gather;
+        double* gscal = (double*)(gather + (size_t)nb * 32);
+        TK_LAUNCH(launch_gather_u32(w.ranks, (long)ws, 8, granks, nb, s));
+        TK_LAUNCH(launch_gather_u32(w.scal, (long)ws, 8, gscal, nb, s));
+        TK_HIP(hipMemcpyAsync(hr.data(), granks, (size_t)nb * 32, hipMemcpyDeviceToHost, s));
+        TK_HIP(hipMemcpyAsync(hs.data(), gscal, (size_t)nb * 32, hipMemcpyDeviceToHost, s));
+        TK_HIP(hipStreamSynchronize(s));
+        if (!trunc)
+            for (int b = 0; b < nb; ++b)
+                for (int k = 0; k < 3; ++k) hr[(size_t)b * 8 + k] = P.R[k];
     }
-    // the result is complete when the call returns, for work on any stream
+    auto drop_all = [&]() {
+        for (int b = 0; b < nb; ++b) { free_result(outs[b]); outs[b] = nullptr; }
+    };
+    const int ld[3] = {P.R[0], P.R[1], P.R[2]};
+    const int Rc[3] = {P.R[0], P.R[1], P.R[2]};
+    for (int b = 0; b < nb; ++b) {
+        const long off = (long)b * (long)ws;
+        int final_r[3];
+        const double* Ub[3];
+        for (int k = 0; k < 3; ++k) {
+            final_r[k] = hr[(size_t)b * 8 + k];
+            Ub[k] = (const double*)((const char*)Usrc[k] + off);
+        }
+        const double* cb = (const double*)((const char*)csrc + off);
+        tk_tucker* t = nullptr;
+        if ((st = alloc_result(ctx, P.n, final_r, s, &t, &res)) != TK_OK) {
+            drop_all();
+            return st;
+        }
+        outs[b] = t;
+        if ((st = fill_result_from(t, Ub, ld, cb, Rc, s)) != TK_OK) {
+            drop_all();
+            return st;
+        }
+        for (int k = 0; k < 3; ++k) t->b[k] = grid->b[k];
+        t->layout = grid->layout;
+        t->prec = P.prec;
+        t->rel_err = hs[(size_t)b * 4 + 3];
+        t->norm_a = std::sqrt(hs[(size_t)b * 4 + 0]);
+        if (P.eps_mode && !(t->rel_err <= P.eps)) sts[b] = TK_ENOCONV;
+    }
+    // the results are complete when the call returns, for work on any stream
     if (hipStreamSynchronize(s) != hipSuccess) {
-        free_result(t);
+        drop_all();
         return fail(TK_EHIP, "compress: %s", hipGetErrorString(hipGetLastError()));
     }
-    for (int k = 0; k < 3; ++k) t->b[k] = grid->b[k];
-    t->layout = grid->layout;
-    t->prec = P.prec;
-    t->rel_err = hs[3];
-    t->norm_a = std::sqrt(hs[0]);
-    *out = t;
-    bool met = true;
-    if (P.eps_mode) met = (hs[3] <= P.eps);
-    if (!met) return fail(TK_ENOCONV, "eps=%g not reached: error %g at ranks (%d,%d,%d)", P.eps, hs[3], final_r[0],
-                          final_r[1], final_r[2]);
+    if (nb == 1 && sts[0] == TK_ENOCONV)
+        return fail(TK_ENOCONV, "eps=%g not reached: error %g at ranks (%d,%d,%d)", P.eps, outs[0]->rel_err,
+                    outs[0]->r[0], outs[0]->r[1], outs[0]->r[2]);
     return TK_OK;
 }
 
@@ -939,9 +1039,33 @@ tk_status compress_any(tk_ctx* ctx, const tk_kernel* kernel, const void* A_in, c
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(TK_EHIP, "hipSetDevice(%d) failed", ctx->device);
     (void)hipGetLastError();   // drop errors left by earlier, unrelated HIP calls
     hipStream_t s = (hipStream_t)stream;
-    if (P.prec == TK_FP64) return compress_impl<double>(ctx, &kp, A_in, grid, P, s, out);
-    return compress_impl<float>(ctx, &kp, A_in, grid, P, s, out);
+    tk_status one = TK_OK;
+    if (P.prec == TK_FP64) return compress_impl<double>(ctx, &kp, 1, A_in, grid, P, s, out, &one);
+    return compress_impl<float>(ctx, &kp, 1, A_in, grid, P, s, out, &one);
 }
+
+// nb <= BATCH_MAX problems on one grid with one set of options, launched together.  outs[i] /
+// sts[i] as for compress_impl.
+tk_status compress_group(tk_ctx* ctx, const tk_kernel* const* kernels, int nb, const tk_grid* grid,
+                         const tk_opts* opts, hipStream_t s, tk_tucker** outs, tk_status* sts)
+{
+    tk_status st;
+    if ((st = check_grid(grid)) != TK_OK) return st;
+    KernelParams kps[BATCH_MAX];
+    if (nb < 1 || nb > BATCH_MAX) return fail(TK_EINVAL, "batch of %d problems", nb);
+    for (int b = 0; b < nb; ++b)
+        if ((st = check_kernel(kernels[b], &kps[b])) != TK_OK) return st;
+    Plan P;
+    if ((st = make_plan(grid, opts, &P)) != TK_OK) return st;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(TK_EHIP, "hipSetDevice(%d) failed", ctx->device);
+    (void)hipGetLastError();
+    if (P.prec == TK_FP64) return compress_impl<double>(ctx, kps, nb, nullptr, grid, P, s, outs, sts);
+    return compress_impl<float>(ctx, kps, nb, nullptr, grid, P, s, outs, sts);
+}
+
+// Can problems with these options share launches?  (The FP64 eps path reads ranks back between
+// steps, so its problems run one per call.)
+bool groupable(const tk_opts* o) { return !(o->eps > 0 && o->prec == TK_FP64); }
 
 bool cov_geometry(const tk_tucker* t, int off[3], int m[3])
 {
@@ -1285,8 +1409,17 @@ void tk_ctx_destroy(tk_ctx* ctx)
     hipDeviceSynchronize();
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->dev_slots) (void)hipFree(ctx->dev_slots);
+    ctx->pinned = nullptr;
+    ctx->dev_slots = nullptr;
     for (hipStream_t st : ctx->streams) (void)hipStreamDestroy(st);
-    delete ctx;
+    ctx->streams.clear();
+    bool now = false;
+    {
+        std::lock_guard<std::mutex> g(ctx->life_mu);
+        ctx->closing = true;
+        now = (ctx->live_results == 0);
+    }
+    if (now) delete ctx;
 }
 
 tk_status tk_ctx_set_workers(tk_ctx* ctx, int workers)
@@ -1344,7 +1477,64 @@ tk_status tk_compress_batch(tk_ctx* ctx, int count, const tk_kernel* kernels, co
     if (count == 0) return TK_OK;
     TK_HIP(hipSetDevice(ctx->device));
     (void)hipGetLastError();
-    const int W = std::min(count, ctx->workers);
+    // work units: problems on the same grid share launches (chunks of at most BATCH_MAX, near
+    // equal in size), the largest units first
+    struct Unit {
+        std::vector<int> idx;
+        double cost;
+    };
+    std::vector<Unit> units;
+    {
+        std::vector<int> order(count);
+        for (int i = 0; i < count; ++i) order[i] = i;
+        auto same_grid = [&](int i, int j) {
+            const tk_grid &a = grids[i], &b = grids[j];
+            for (int k = 0; k < 3; ++k)
+                if (a.n[k] != b.n[k] || a.b[k] != b.b[k]) return false;
+            return a.layout == b.layout;
+        };
+        // every result of the batch stays allocated until the call returns
+        size_t all_results = 0;
+        for (int i = 0; i < count; ++i) {
+            Plan P;
+            if (make_plan(&grids[i], opts, &P) == TK_OK) all_results += result_bytes(P.n, P.R);
+        }
+        std::vector<char> taken(count, 0);
+        for (int i = 0; i < count; ++i) {
+            if (taken[i]) continue;
+            std::vector<int> g{i};
+            taken[i] = 1;
+            if (groupable(opts))
+                for (int j = i + 1; j < count; ++j)
+                    if (!taken[j] && same_grid(i, j)) { g.push_back(j); taken[j] = 1; }
+            const int m = (int)g.size();
+            // the largest chunk whose workspaces fit the budget beside all the batch's results
+            int cap = 1;
+            if (m > 1) {
+                Plan P;
+                if (make_plan(&grids[i], opts, &P) == TK_OK) {
+                    for (int nb = std::min(m, BATCH_MAX); nb > 1; --nb) {
+                        size_t wsz = 0;
+                        const size_t need = batch_layout(P, true, nb, &wsz) + all_results;
+                        if (need <= ctx->budget) { cap = nb; break; }
+                    }
+                }
+            }
+            const int nchunk = (m + cap - 1) / cap;
+            const double per = (double)grids[i].n[0] * grids[i].n[1] * grids[i].n[2];
+            for (int c = 0, pos = 0; c < nchunk; ++c) {
+                const int len = m / nchunk + (c < m % nchunk ? 1 : 0);
+                Unit u;
+                u.idx.assign(g.begin() + pos, g.begin() + pos + len);
+                u.cost = per * len;
+                units.push_back(std::move(u));
+                pos += len;
+            }
+        }
+        std::stable_sort(units.begin(), units.end(), [](const Unit& x, const Unit& y) { return x.cost > y.cost; });
+    }
+    const int nunits = (int)units.size();
+    const int W = std::min(nunits, ctx->workers);
     std::vector<hipStream_t> ws(W);
     {
         std::lock_guard<std::mutex> g(ctx->pool_mu);
@@ -1371,8 +1561,14 @@ tk_status tk_compress_batch(tk_ctx* ctx, int count, const tk_kernel* kernels, co
         hipStream_t s = ws[wi];
         if (hipStreamWaitEvent(s, fork, 0) != hipSuccess) return;
         for (;;) {
-            const int i = next.fetch_add(1);
-            if (i >= count) break;
+            const int ui = next.fetch_add(1);
+            if (ui >= nunits) break;
+            const Unit& u = units[ui];
+            const int nb = (int)u.idx.size();
+            std::vector<const tk_kernel*> ks(nb);
+            std::vector<tk_tucker*> os(nb, nullptr);
+            std::vector<tk_status> ss(nb, TK_OK);
+            for (int b = 0; b < nb; ++b) ks[b] = &kernels[u.idx[b]];
             for (;;) {
                 long seen;
                 {
@@ -1380,7 +1576,13 @@ tk_status tk_compress_batch(tk_ctx* ctx, int count, const tk_kernel* kernels, co
                     ++running;
                     seen = finished;
                 }
-                const tk_status r = compress_any(ctx, &kernels[i], nullptr, &grids[i], opts, s, &outs[i]);
+                tk_status r;
+                if (nb == 1) {
+                    r = compress_any(ctx, ks[0], nullptr, &grids[u.idx[0]], opts, s, &os[0]);
+                    if (r == TK_ENOCONV) { ss[0] = TK_ENOCONV; r = TK_OK; }
+                } else {
+                    r = compress_group(ctx, ks.data(), nb, &grids[u.idx[0]], opts, s, os.data(), ss.data());
+                }
                 bool retry = false;
                 {
                     std::lock_guard<std::mutex> g(mu);
@@ -1395,8 +1597,13 @@ tk_status tk_compress_batch(tk_ctx* ctx, int count, const tk_kernel* kernels, co
                     cv.wait(lk, [&] { return finished != seen || running == 0; });
                     continue;
                 }
-                st[i] = r;
-                if (r != TK_OK) msg[i] = g_last_error;
+                for (int b = 0; b < nb; ++b) {
+                    const int i = u.idx[b];
+                    outs[i] = os[b];
+                    st[i] = (r != TK_OK) ? r : ss[b];
+                    if (r != TK_OK) msg[i] = g_last_error;
+                    else if (ss[b] == TK_ENOCONV) msg[i] = "eps not reached";
+                }
                 break;
             }
         }
@@ -1436,9 +1643,10 @@ tk_status tk_tucker_info(const tk_tucker* t, int n[3], int ranks[3], double* rel
 tk_status tk_tucker_get(const tk_tucker* t, double* U_host[3], double* core_host)
 {
     if (!t) return fail(TK_EINVAL, "t is NULL");
+    if (!usable(t)) return fail(TK_EINVAL, "result of a destroyed context");
     TK_HIP(hipSetDevice(t->ctx->device));
     (void)hipGetLastError();
-    TK_HIP(hipStreamSynchronize(t->stream));
+    // results are complete when the call that made them returns
     for (int k = 0; k < 3; ++k)
         if (U_host && U_host[k])
             TK_HIP(hipMemcpy(U_host[k], t->U[k], sizeof(double) * t->n[k] * t->r[k], hipMemcpyDeviceToHost));
@@ -1450,6 +1658,7 @@ tk_status tk_tucker_get(const tk_tucker* t, double* U_host[3], double* core_host
 tk_status tk_tucker_device(const tk_tucker* t, const double* U_dev[3], const double** core_dev)
 {
     if (!t) return fail(TK_EINVAL, "t is NULL");
+    if (!usable(t)) return fail(TK_EINVAL, "result of a destroyed context");
     for (int k = 0; k < 3; ++k)
         if (U_dev) U_dev[k] = t->U[k];
     if (core_dev) *core_dev = t->core;
@@ -1459,6 +1668,7 @@ tk_status tk_tucker_device(const tk_tucker* t, const double* U_dev[3], const dou
 tk_status tk_reconstruct(tk_ctx* ctx, const tk_tucker* t, void* A_dev, int io, void* hip_stream)
 {
     if (!ctx || !t || !A_dev) return fail(TK_EINVAL, "NULL argument");
+    if (!usable(t)) return fail(TK_EINVAL, "result of a destroyed context");
     if (io != TK_FP64 && io != TK_FP32) return fail(TK_EINVAL, "io must be TK_FP64 or TK_FP32");
     TK_HIP(hipSetDevice(ctx->device));
     (void)hipGetLastError();
@@ -1502,6 +1712,7 @@ tk_status tk_cov_dims(const tk_tucker* t, int m[3])
 tk_status tk_kron_matvec(tk_ctx* ctx, const tk_tucker* t, const void* z_dev, void* y_dev, int io, void* hip_stream)
 {
     if (!ctx || !t || !z_dev || !y_dev) return fail(TK_EINVAL, "NULL argument");
+    if (!usable(t)) return fail(TK_EINVAL, "result of a destroyed context");
     if (z_dev == y_dev) return fail(TK_EINVAL, "y must not alias z");
     if (io != TK_FP64 && io != TK_FP32) return fail(TK_EINVAL, "io must be TK_FP64 or TK_FP32");
     TK_HIP(hipSetDevice(ctx->device));
@@ -1518,6 +1729,7 @@ tk_status tk_quadratic_form(tk_ctx* ctx, const tk_tucker* t, const void* z_dev, 
                             double* out, void* y_dev)
 {
     if (!ctx || !t || !z_dev || !out) return fail(TK_EINVAL, "NULL argument");
+    if (!usable(t)) return fail(TK_EINVAL, "result of a destroyed context");
     if (io != TK_FP64 && io != TK_FP32) return fail(TK_EINVAL, "io must be TK_FP64 or TK_FP32");
     TK_HIP(hipSetDevice(ctx->device));
     (void)hipGetLastError();
@@ -1560,6 +1772,7 @@ tk_status tk_estimate_matvec_bytes(tk_ctx* ctx, const tk_tucker* t, int io, size
 tk_status tk_trace(tk_ctx* ctx, const tk_tucker* t, void* hip_stream, double* out)
 {
     if (!ctx || !t || !out) return fail(TK_EINVAL, "NULL argument");
+    if (!usable(t)) return fail(TK_EINVAL, "result of a destroyed context");
     int off[3], m[3];
     if (!cov_geometry(t, off, m)) return fail(TK_ELAYOUT, "even-sized centred grid has no origin node");
     TK_HIP(hipSetDevice(ctx->device));
@@ -1581,6 +1794,7 @@ tk_status tk_trace(tk_ctx* ctx, const tk_tucker* t, void* hip_stream, double* ou
 tk_status tk_tucker_save(const tk_tucker* t, const char* path)
 {
     if (!t || !path) return fail(TK_EINVAL, "NULL argument");
+    if (!usable(t)) return fail(TK_EINVAL, "result of a destroyed context");
     std::vector<std::vector<double>> U(3);
     for (int k = 0; k < 3; ++k) U[k].resize((size_t)t->n[k] * t->r[k]);
     std::vector<double> core((size_t)t->r[0] * t->r[1] * t->r[2]);
@@ -1662,8 +1876,8 @@ tk_status tk_grid_eval(tk_ctx* ctx, const tk_kernel* kernel, const tk_grid* grid
     TK_HIP(hipSetDevice(ctx->device));
     (void)hipGetLastError();
     GridAxes ax = axes_of(grid);
-    if (prec == TK_FP64) TK_LAUNCH(launch_grid_eval_f64((double*)A_dev, ax, kp, (hipStream_t)hip_stream));
-    else TK_LAUNCH(launch_grid_eval_f32((float*)A_dev, ax, kp, (hipStream_t)hip_stream));
+    if (prec == TK_FP64) TK_LAUNCH(launch_grid_eval_f64((double*)A_dev, ax, &kp, (hipStream_t)hip_stream));
+    else TK_LAUNCH(launch_grid_eval_f32((float*)A_dev, ax, &kp, (hipStream_t)hip_stream));
     return TK_OK;
 }
 

@@ -19,6 +19,15 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 //                        D as for 32x32x2
 //  mfma_f32_16x16x32_bf16: A[i][k] at lane i + 16(k/8), element k%8, D as for 16x16x4 f32
 
+// Batched launches: grid z runs over problems of equal shape whose device workspaces lie `bs`
+// bytes apart; a kernel moves each of its workspace pointers by blockIdx.z * bs (null pointers
+// stay null).  With one problem (grid z = 1) nothing moves.
+template <typename T>
+__device__ __forceinline__ T* bshift(T* p, long bs)
+{
+    return p ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)((long)blockIdx.z * bs)) : p;
+}
+
 // Covariance families (values match the public tk_family enum).
 enum { FAM_MATERN = 0, FAM_SLATER = 1, FAM_GAUSS = 2 };
 

@@ -10,21 +10,36 @@
 
 namespace tk {
 
+// A launch over nb problems of equal shape whose workspaces lie bs bytes apart (grid z; every
+// pointer argument that lies in a workspace moves with the problem).  Each problem runs the
+// same work-groups with the same arithmetic as when launched alone.
+struct Bat {
+    int nb = 1;
+    long bs = 0;
+};
+constexpr int BATCH_MAX = 32;   // problems per batched grid evaluation (parameters passed by value)
+struct KernelParamsBatch {
+    KernelParams k[BATCH_MAX];
+};
+
 // ---------------------------------------------------------------- a1: grid evaluation ----
 struct GridAxes {
     int n[3];
     double x0[3];   // first node
     double h[3];    // spacing
 };
-hipError_t launch_grid_eval_f32(float* A, const GridAxes& g, const KernelParams& kp, hipStream_t s);
-hipError_t launch_grid_eval_f64(double* A, const GridAxes& g, const KernelParams& kp, hipStream_t s);
+// kps: bt.nb kernel parameter sets, one per problem (bt.nb <= BATCH_MAX).
+hipError_t launch_grid_eval_f32(float* A, const GridAxes& g, const KernelParams* kps, hipStream_t s,
+                                Bat bt = Bat());
+hipError_t launch_grid_eval_f64(double* A, const GridAxes& g, const KernelParams* kps, hipStream_t s,
+                                Bat bt = Bat());
 
 // ----------------------------------------------------------------- a2: Gram (SYRK) ----
 // G (n_mode x n_mode, double, full) = A_(mode) A_(mode)^T.  `work` must hold
 // gram_work_bytes(...) bytes.
 size_t gram_work_bytes(const int n[3], int mode, int prec);
 hipError_t launch_gram(const void* A, const int n[3], int mode, int prec, double* G, void* work,
-                       hipStream_t s);
+                       hipStream_t s, Bat bt = Bat());
 
 // ------------------------------------------------------------ small dense products ----
 // C[b](m,n) = alpha * sum_k A[b](m,k) B[b](k,n) + beta * C[b](m,n) with arbitrary element
@@ -36,6 +51,8 @@ struct GemmArgs {
     const void* B; long sBb, sBk, sBn;
     void* C;       long sCb, sCm, sCn;
     double alpha, beta;
+    int nb;        // problems (grid z; 0 counts as 1); A, B, C move by bs bytes per problem
+    long bs;
 };
 template <typename TA, typename TB, typename TC>
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
@@ -58,39 +75,46 @@ struct EigBatch {
     double* trace; long sTrace;
     int span_only;   // 1: p == r < n; U = orthonormal basis of span(G^iters W) (W the warm block or a
                      // random one), no Rayleigh-Ritz (for callers that rotate the factors afterwards)
+    int nb;          // batched problems (0 counts as 1): every pointer above moves by bs bytes
+    long bs;
 };
 hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s);
 // Sign rule on the columns of U (n x r, ld ldu): a column whose entry of largest magnitude (ties
 // within 1e-10 relative, lowest index) is negative is negated, together with column c of V
 // (nv x r, ld ldv).
-hipError_t launch_signfix_pair(double* U, int ldu, int n, double* V, int ldv, int nv, int r, hipStream_t s);
+hipError_t launch_signfix_pair(double* U, int ldu, int n, double* V, int ldv, int nv, int r, hipStream_t s,
+                               Bat bt = Bat());
 hipError_t eig_set_attributes();
 
 // ------------------------------------------------------------------- a5/a6: TTM ----
 // T[row, c] = sum_k A[row, k] U[k, c]   (A x_3 U^T): A rows x n2, U n2 x r, T rows x r
 hipError_t launch_ttm_last_f32(const float* A, long rows, int n2, const float* U, int r, float* T,
-                               hipStream_t s);
+                               hipStream_t s, Bat bt = Bat());
 // S[a, col] = sum_i U[i, a] A[i, col]   (A x_1 U^T): A n0 x cols, U n0 x r, S r x cols
 hipError_t launch_ttm_first_f32(const float* A, int n0, long cols, const float* U, int r, float* S,
-                                hipStream_t s);
+                                hipStream_t s, Bat bt = Bat());
 
 // ------------------------------------------------------------------ a7: error norm ----
 // partials[2b] = sum (A - H U3^T)^2, partials[2b+1] = sum A^2 over work-group b's rows;
 // H: rows x r, U3: n2 x r.  recon_diff_parts(rows) work-groups.
 int recon_diff_parts(long rows);
 hipError_t launch_recon_diff_f32(const float* A, long rows, int n2, const double* H, const double* U3,
-                                 int r, double* partials, hipStream_t s);
+                                 int r, double* partials, hipStream_t s, Bat bt = Bat());
 // partials[2b] = sum (X - Y)^2, partials[2b+1] = sum X^2 (grid-stride, nparts work-groups)
 template <typename T>
 hipError_t launch_diff_norm(const T* X, const T* Y, long n, double* partials, int nparts,
-                            hipStream_t s);
+                            hipStream_t s, Bat bt = Bat());
 hipError_t launch_reduce_partials(const double* partials, int nparts, int width, double* out,
-                                  hipStream_t s);
+                                  hipStream_t s, Bat bt = Bat());
 
 // --------------------------------------------------------------- conversions/misc ----
-hipError_t launch_convert_f64_to_f32(const double* x, float* y, long n, hipStream_t s);
+hipError_t launch_convert_f64_to_f32(const double* x, float* y, long n, hipStream_t s, Bat bt = Bat());
 hipError_t launch_convert_f32_to_f64(const float* x, double* y, long n, hipStream_t s);
-hipError_t launch_fill_f64(double* x, double v, long n, hipStream_t s);
+hipError_t launch_fill_f64(double* x, double v, long n, hipStream_t s, Bat bt = Bat());
+// y[i] = x[i] for i < n (batched copies inside workspaces)
+hipError_t launch_copy_f64(const double* x, double* y, long n, hipStream_t s, Bat bt = Bat());
+// Gather `words` 4-byte words of each of nb records src + b * bs (b < nb) into dst[b * words + i].
+hipError_t launch_gather_u32(const void* src, long bs, int words, void* dst, int nb, hipStream_t s);
 // out[0] = sum x*y (FP64 accumulation, deterministic two-level reduction)
 template <typename T>
 hipError_t launch_dot(const T* x, const T* y, long n, double* partials, int nparts, double* out,
@@ -144,15 +168,16 @@ hipError_t fft_set_attributes();
 
 // ------------------------------------------------------------ small scalar kernels ----
 hipError_t launch_rank_rule(const double* lam, long sLam, int len, int count, const double* total, long sTotal,
-                            const double* scal, int has_d2, double eps2, int* ranks, int* ok, hipStream_t s);
+                            const double* scal, int has_d2, double eps2, int* ranks, int* ok, hipStream_t s,
+                            Bat bt = Bat());
 hipError_t launch_trunc_err(const double* X, int R0, int R1, int R2, const int* ranks, double* out,
-                            hipStream_t s);
+                            hipStream_t s, Bat bt = Bat());
 template <typename TI, typename TO>
 hipError_t launch_copy_block(const TI* X, int D1, int D2, TO* Y, int d0, int d1, int d2, hipStream_t s);
 hipError_t launch_cov_trace(const double* G, int r0, int r1, int r2, const double* u0, const double* u1,
                             const double* u2, double scale, double* out, hipStream_t s);
-hipError_t launch_final_err(double* scal, hipStream_t s);
+hipError_t launch_final_err(double* scal, hipStream_t s, Bat bt = Bat());
 hipError_t launch_mask_rank(double* const U[3], const int n[3], const int R[3], double* core, const int* ranks,
-                            hipStream_t s);
+                            hipStream_t s, Bat bt = Bat());
 
 }  // namespace tk

@@ -92,3 +92,97 @@ def test_batch_empty_and_errors(tk):
             ctx.set_workers(0)
     finally:
         ctx.destroy()
+
+
+# problems on shared grids: 34 on the 33^3 centred grid (two launches of 17), 3 on the 48^3
+# offset grid (one launch of 3), one alone
+def _grouped(tk):
+    rng = np.random.default_rng(5)
+    items = [(33, 0)] * 34 + [(48, 1)] * 3 + [(40, 1)]
+    ks = [tk.make_kernel(0, nu=float(rng.choice([0.5, 1.5, 2.5])), ell=float(np.exp(rng.uniform(np.log(0.05), 0.0))))
+          for _ in items]
+    gs = [tk.make_grid(n, 1.0, lay) for (n, lay) in items]
+    return ks, gs
+
+
+@pytest.mark.parametrize("prec,eps,ranks", [(1, 1e-6, (0, 0, 0)), (2, 1e-6, (0, 0, 0)), (1, 0.0, (5, 6, 7)),
+                                            (0, 0.0, (4, 4, 6)), (0, 1e-6, (0, 0, 0))])
+def test_grouped_batch_matches_single(tk, prec, eps, ranks):
+    """Problems on one grid share every launch (grid z over the problems); each result is
+    bitwise the one the problem gets alone.  The FP64 eps path (ranks read back between steps)
+    runs its problems one per call."""
+    require_gpu()
+    ctx = tk.Context(0)
+    try:
+        ks, gs = _grouped(tk)
+        opts = tk.make_opts(eps=eps, ranks=ranks, hooi_sweeps=2, prec=prec)
+        say("grouped batch prec", prec, "eps", eps, "ranks", ranks)
+        alone = [ctx.compress(k, g, opts, allow_noconv=True) for k, g in zip(ks, gs)]
+        for workers in (4, 1):
+            ctx.set_workers(workers)
+            mix = ctx.compress_batch(ks, gs, opts)
+            for i, (a, b) in enumerate(zip(alone, mix)):
+                assert _same(a, b), f"item {i} differs in the batch"
+            for t in mix:
+                t.free()
+        for t in alone:
+            t.free()
+    finally:
+        ctx.destroy()
+
+
+def test_grouped_batch_budget_caps_launch_size(tk):
+    """A budget of about 2.5 problems: a shared-grid group is split into launches that fit."""
+    require_gpu()
+    ks, gs = _grouped(tk)
+    opts = tk.make_opts(eps=1e-6, hooi_sweeps=2, prec=1)
+    per = tk.tk_estimate_bytes(gs[0], opts)
+    ctx = tk.Context(0, hbm_budget_bytes=int(2.5 * max(per, tk.tk_estimate_bytes(gs[34], opts))))
+    try:
+        ref = []
+        for k, g in zip(ks, gs):
+            t = ctx.compress(k, g, opts)
+            ref.append((t.ranks, t.rel_err, t.factors()))
+            t.free()
+        mix = ctx.compress_batch(ks, gs, opts)
+        for i, (t, (r, e, (U, C))) in enumerate(zip(mix, ref)):
+            Ub, Cb = t.factors()
+            assert t.ranks == r and t.rel_err == e and np.array_equal(Cb, C), f"item {i}"
+            assert all(np.array_equal(x, y) for x, y in zip(U, Ub)), f"item {i}"
+        for t in mix:
+            t.free()
+    finally:
+        ctx.destroy()
+
+
+def test_concurrent_large_n_matches_single(tk):
+    """Sizes above 64 put eigensolver rows in every wave of a work-group, and concurrent
+    launches on other streams shift the waves' timing: results must still be bitwise those of
+    the problems alone (shared-grid groups and single problems, 4 and 8 workers)."""
+    require_gpu()
+    rng = np.random.default_rng(11)
+    sizes = [96] * 6 + [128] * 6 + [160, 112, 144, 100]
+    ks = [tk.make_kernel(0, nu=float(rng.choice([0.5, 1.5, 2.5])), ell=float(np.exp(rng.uniform(np.log(0.05), 0.0))))
+          for _ in sizes]
+    gs = [tk.make_grid(n, 1.0, 0) for n in sizes]
+    opts = tk.make_opts(eps=1e-6, hooi_sweeps=2, prec=1)
+    ctx = tk.Context(0)
+    try:
+        ref = []
+        for k, g in zip(ks, gs):
+            t = ctx.compress(k, g, opts)
+            ref.append((t.ranks, t.rel_err, t.factors()))
+            t.free()
+        for workers in (4, 8):
+            ctx.set_workers(workers)
+            for rep in range(2):
+                say("concurrent large n, workers", workers, "rep", rep)
+                mix = ctx.compress_batch(ks, gs, opts)
+                for i, (t, (r, e, (U, C))) in enumerate(zip(mix, ref)):
+                    Ub, Cb = t.factors()
+                    assert t.ranks == r and t.rel_err == e and np.array_equal(Cb, C), f"item {i} (n={sizes[i]})"
+                    assert all(np.array_equal(x, y) for x, y in zip(U, Ub)), f"item {i} (n={sizes[i]})"
+                for t in mix:
+                    t.free()
+    finally:
+        ctx.destroy()

@@ -62,7 +62,8 @@ def test_c1_hosvd_error_curve_fp64(ctx, tk, oracle):
         t.free()
 
 
-@pytest.mark.parametrize("shape,ranks,sweeps", [((40, 36, 44), (3, 4, 5), 2), ((33, 65, 70), (6, 5, 7), 1)])
+@pytest.mark.parametrize("shape,ranks,sweeps", [((40, 36, 44), (3, 4, 5), 2), ((33, 65, 70), (6, 5, 7), 1),
+                                                 ((36, 36, 36), (3, 5, 7), 2), ((60, 60, 60), (4, 6, 5), 1)])
 def test_hooi_fp64_matches_oracle(ctx, tk, oracle, shape, ranks, sweeps):
     ok = oracle.Kernel(oracle.MATERN, nu=1.5, ell=0.25)
     og = oracle.Grid(n=shape, b=(1.0, 1.2, 0.9), layout=oracle.CENTERED)
@@ -74,11 +75,36 @@ def test_hooi_fp64_matches_oracle(ctx, tk, oracle, shape, ranks, sweeps):
     U, core = t.factors()
     A = oracle.grid_eval(ok, og)
     d = _recon_host(U, core) - oracle.reconstruct(ref.core, ref.U)
-    assert np.sqrt(np.sum(d * d) / np.sum(A * A)) <= 1e-10
+    # the r-th column of mode k is fixed by the FP64 Gram only to u lambda_1 / gap and enters the
+    # reconstruction weighted by sigma_r: tolerance max(1e-10, 100 u sqrt(lambda_1/lambda_r) / gap)
+    tol = 1e-10
+    for k, r in enumerate(ranks):
+        M = np.moveaxis(A, k, 0).reshape(shape[k], -1)
+        lam = np.sort(np.linalg.eigvalsh(M @ M.T))[::-1]
+        gap = (lam[r - 1] - lam[r]) / lam[r - 1]
+        tol = max(tol, 100 * 2.2e-16 * np.sqrt(lam[0] / lam[r - 1]) / gap)
+    assert np.sqrt(np.sum(d * d) / np.sum(A * A)) <= tol
     # orthonormal factors, core = projection
     for u in U:
         assert np.abs(u.T @ u - np.eye(u.shape[1])).max() < 1e-12
     np.testing.assert_allclose(core, oracle.project_core(A, U), rtol=0, atol=1e-12 * np.abs(core).max())
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("n,ranks", [(48, (4, 6, 8)), (64, (7, 5, 6))])
+def test_fixed_unequal_ranks_float_matches_oracle(ctx, tk, oracle, prec, n, ranks):
+    """Cubic grid, unequal fixed ranks on the float paths (each mode its own eigensolve)."""
+    ok = oracle.Kernel(oracle.MATERN, nu=1.5, ell=0.25)
+    og = oracle.Grid(n=(n, n, n), b=(1.0, 1.2, 0.9), layout=oracle.CENTERED)
+    ref = oracle.compress(ok, og, ranks=ranks, sweeps=2)
+    t = ctx.compress(tk.make_kernel(0, nu=1.5, ell=0.25), tk.make_grid(n, (1.0, 1.2, 0.9), 0),
+                     tk.make_opts(ranks=ranks, hooi_sweeps=2, prec=prec))
+    assert t.ranks == tuple(ranks)
+    U, core = t.factors()
+    A = oracle.grid_eval(ok, og)
+    d = _recon_host(U, core) - oracle.reconstruct(ref.core, ref.U)
+    assert np.sqrt(np.sum(d * d) / np.sum(A * A)) <= 1e-5
+    assert t.rel_err == pytest.approx(ref.rel_err, rel=1e-3, abs=1e-6)
 
 
 def test_full_rank_is_exact_fp64(ctx, tk, oracle):

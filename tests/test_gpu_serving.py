@@ -19,9 +19,9 @@ def tk():
 
 # compress requests: (n, nu, ell, layout); follow-ups: (kind, index of the compress)
 _COMPRESS = [(48, 0.5, 0.1, 1), (33, 1.5, 0.3, 0), (64, 2.5, 1.0, 1), (40, 0.5, 0.3, 1), (57, 1.5, 0.1, 0),
-             (64, 0.5, 1.0, 1)]
+             (64, 0.5, 1.0, 1), (96, 1.5, 0.2, 1), (129, 2.5, 0.3, 0)]
 _FOLLOW = [("matvec", 0), ("trace", 1), ("quadform", 2), ("matvec", 3), ("quadform", 0), ("trace", 5),
-           ("matvec", 4), ("quadform", 5), ("trace", 2)]
+           ("matvec", 4), ("quadform", 5), ("trace", 2), ("matvec", 6), ("quadform", 7), ("trace", 6)]
 
 
 def _dims(tucker_or_n, layout):
