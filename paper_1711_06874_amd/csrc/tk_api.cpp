@@ -778,12 +778,14 @@ tk_status alloc_result(tk_ctx* ctx, const int n[3], const int r[3], hipStream_t 
         return fail(TK_ENOMEM, "result (%zu bytes) exceeds the remaining HBM budget", bytes);
     }
     t->bytes = bytes;
+    // results live long and are small: they come from the device heap, not from the
+    // stream-ordered pool of the (large, short-lived) workspaces, which they would fragment
     void* blk = nullptr;
-    hipError_t e = hipMallocAsync(&blk, bytes, s);
+    hipError_t e = hipMalloc(&blk, bytes);
     if (e != hipSuccess) {
         release(ctx, bytes);
         delete t;
-        return fail(TK_ENOMEM, "hipMallocAsync(%zu): %s", bytes, hipGetErrorString(e));
+        return fail(TK_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
     }
     t->block = blk;
     t->stream = s;
@@ -812,7 +814,7 @@ void free_result(tk_tucker* t)
         // the result may have been read on any stream: free it once the device is idle
         hipSetDevice(t->ctx->device);
         hipDeviceSynchronize();
-        hipFreeAsync(t->block, nullptr);
+        hipFree(t->block);
     }
     tk_ctx* ctx = t->ctx;
     release(ctx, t->bytes);

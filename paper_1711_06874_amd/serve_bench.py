@@ -1,7 +1,7 @@
 """Serving workload: a Poisson stream of mixed requests replayed in real time against the
 request loop (tk_server_*), one JSON line per arrival rate.
 
-    python -m paper_1711_06874_amd.serve_bench [--rates 50 200 500] [--count 300]
+    python -m paper_1711_06874_amd.serve_bench [--rates 10 20 50 100 200 500] [--count 2000]
                                               [--workers 4] [--budget-gib 64]
 
 70% compress requests (Matern nu in {1/2, 3/2, 5/2}, ell log-uniform on [0.05, 1], eps 1e-6,
@@ -30,7 +30,7 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=float), q)) if xs else None
 
 
-def run_rate(tk, ctx, rate, count, workers, prec):
+def run_rate(tk, ctx, rate, count, workers, prec, trace=None):
     import torch
     import synth
     reqs = synth.serving_stream(rate, count)
@@ -38,7 +38,8 @@ def run_rate(tk, ctx, rate, count, workers, prec):
     opts = tk.make_opts(eps=1e-6, hooi_sweeps=2, prec=prec)
     tickets = {}          # rid -> ticket
     sizes = {}            # compress rid -> n
-    keep = {}             # ticket -> device vectors kept alive until the request finished
+    keep = {}             # ticket -> device vectors in use until the request finished
+    spare = {}            # n -> free (z, y) pairs: vectors are reused, not reallocated per request
     order = []            # (ticket, kind, rid)
     results = {}
     lock = threading.Lock()
@@ -52,7 +53,11 @@ def run_rate(tk, ctx, rate, count, workers, prec):
             r = sv.wait(t)
             with lock:
                 results[t] = (kind, rid, r)
-                keep.pop(t, None)
+                pair = keep.pop(t, None)
+                if pair is not None:
+                    spare.setdefault(pair[0].shape[0], []).append(pair)
+                if len(results) % 250 == 0:
+                    print("rate %g: %d of %d finished" % (rate, len(results), len(reqs)), file=sys.stderr, flush=True)
 
     th = threading.Thread(target=collector)
     th.start()
@@ -73,12 +78,18 @@ def run_rate(tk, ctx, rate, count, workers, prec):
                 if q.kind == "trace":
                     t = sv.submit_trace(target)
                 else:
-                    z = synth.normal_vector_device((n, n, n), q.rid)
-                    y = torch.empty_like(z)
+                    with lock:
+                        free = spare.get(n)
+                        pair = free.pop() if free else None
+                    if pair is None:
+                        pair = (torch.empty((n, n, n), dtype=torch.float32, device="cuda"),
+                                torch.empty((n, n, n), dtype=torch.float32, device="cuda"))
+                    z, y = pair
+                    synth.fill_normal_device(z, q.rid)
                     t = (sv.submit_matvec(target, z, y) if q.kind == "matvec"
                          else sv.submit_quadform(target, z, y=y))
                     with lock:
-                        keep[t] = (z, y)
+                        keep[t] = pair
             tickets[q.rid] = t
             with lock:
                 order.append((t, q.kind, q.rid))
@@ -86,6 +97,14 @@ def run_rate(tk, ctx, rate, count, workers, prec):
         th.join()
     finally:
         sv.destroy()
+    if trace:
+        n_of = {rid: n for rid, n in sizes.items()}
+        with open(trace, "a") as f:
+            for t, (kind, rid, r) in sorted(results.items(), key=lambda kv: kv[1][2]["t_submit"]):
+                q = reqs[rid]
+                n = n_of.get(rid if kind == "compress" else q.target, 0)
+                f.write("%g,%d,%s,%d,%.6f,%.6f,%.6f,%d\n" % (rate, rid, kind, n, r["t_submit"], r["t_start"],
+                                                             r["t_end"], r["status"]))
     by = {}
     t_first, t_last, failures, eps_miss = None, None, [], 0
     for t, (kind, rid, r) in results.items():
@@ -115,11 +134,13 @@ def run_rate(tk, ctx, rate, count, workers, prec):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--rates", type=float, nargs="+", default=[50.0, 200.0, 500.0])
-    ap.add_argument("--count", type=int, default=300)
+    ap.add_argument("--rates", type=float, nargs="+", default=[10.0, 20.0, 50.0, 100.0, 200.0, 500.0])
+    ap.add_argument("--count", type=int, default=2000)
     ap.add_argument("--workers", type=int, default=4)
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--prec", choices=["fp32", "bf16x3"], default="fp32")
+    ap.add_argument("--trace", default=None, help="append one CSV row per request: rate, id, kind, n, "
+                                                  "t_submit, t_start, t_end, status")
     args = ap.parse_args()
     import torch
     from paper_1711_06874_amd import tk
@@ -128,7 +149,7 @@ def main():
     prec = tk.TK_FP32 if args.prec == "fp32" else tk.TK_BF16X3
     try:
         for rate in args.rates:
-            out = run_rate(tk, ctx, rate, args.count, args.workers, prec)
+            out = run_rate(tk, ctx, rate, args.count, args.workers, prec, args.trace)
             out.update({"workers": args.workers, "budget_gib": args.budget_gib, "precision": args.prec,
                         "workload": "Poisson stream: 70% compress (Matern, offset grid n in {64,128,256,384}, "
                                     "eps 1e-6), 30% matvec / trace / quadratic form on earlier results"})

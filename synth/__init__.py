@@ -144,3 +144,12 @@ def normal_vector_device(shape, stream: int, seed: int = MASTER_SEED):
     g = torch.Generator(device="cuda")
     g.manual_seed(int(seed) * 1_000_003 + int(stream))
     return torch.randn(tuple(shape), generator=g, device="cuda", dtype=torch.float32)
+
+
+def fill_normal_device(x, stream: int, seed: int = MASTER_SEED):
+    """Refill an existing float32 device tensor with the draws of normal_vector_device."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(int(seed) * 1_000_003 + int(stream))
+    x.normal_(generator=g)
+    return x
