@@ -27,6 +27,7 @@
 #define TK_H
 
 #include <stddef.h>
+#include <stdint.h>
 
 #ifdef __cplusplus
 extern "C" {
@@ -168,6 +169,25 @@ tk_status tk_compress_batch(tk_ctx *ctx, int count, const tk_kernel *kernels,
                             const tk_grid *grids, const tk_opts *opts, void *hip_stream,
                             tk_tucker **outs);
 
+/* Compress 1..32 problems that share one grid and one set of options in a single pass on
+ * hip_stream: every step of the pipeline is one launch over all of them (as for a group inside
+ * tk_compress_batch).  outs[i] / statuses[i]: the result of kernels[i], bitwise what tk_compress
+ * returns for it alone, and TK_OK or TK_ENOCONV (eps not reached; the result is returned
+ * anyway).  The FP64 eps path runs the problems one after another.  Synchronising: the results
+ * are complete when the call returns.  Errors (no results): TK_EINVAL, TK_EUNSUPPORTED,
+ * TK_ENOMEM (the group's workspaces and results exceed the budget), TK_EHIP. */
+tk_status tk_compress_group(tk_ctx *ctx, int count, const tk_kernel *kernels, const tk_grid *grid,
+                            const tk_opts *opts, void *hip_stream, tk_tucker **outs, int *statuses);
+
+/* Workspaces: each call takes its device workspace from a block the context keeps per HIP
+ * stream, grown when a call needs more and reused by the next call on that stream, so calls in
+ * steady state allocate nothing.  The budget charges each call's workspace while the call runs;
+ * an idle block (at most two per stream: the largest workspace a call on it needed, and a
+ * quadratic form's own y) is not charged.  tk_ctx_release_stream frees the blocks of a stream
+ * (call it before destroying a stream the context has worked on); tk_ctx_destroy frees all.
+ * Errors: TK_EINVAL (ctx NULL, a call on the stream still running), TK_EHIP. */
+tk_status tk_ctx_release_stream(tk_ctx *ctx, void *hip_stream);
+
 /* Number of worker streams / host workers tk_compress_batch uses (1..16; default 4, the
  * number of hardware queues a process gets by default).  Host only. */
 tk_status tk_ctx_set_workers(tk_ctx *ctx, int workers);
@@ -288,10 +308,14 @@ typedef struct {
     const void *z_dev;   /* matvec, quadratic form: input vector (caller-owned, io precision) */
     void *y_dev;         /* matvec: output (required); quadratic form: optional output */
     int io;              /* TK_FP32 or TK_FP64 */
-    void *stream;        /* work queued on this HIP stream before tk_server_submit (for example the
-                            copy that fills z_dev) completes before the request starts; NULL: the
-                            legacy default stream */
+    void *stream;        /* matvec, quadratic form: work queued on this HIP stream before
+                            tk_server_submit (for example the copy that fills z_dev) completes before
+                            the request starts; NULL: the legacy default stream; TK_STREAM_READY:
+                            the vectors are complete already (no ordering with any stream, so the
+                            request never waits behind unrelated work of that stream).  Compress and
+                            trace requests have no device inputs and are never ordered. */
 } tk_request;
+#define TK_STREAM_READY ((void *)(intptr_t)-1)
 typedef struct {
     int status;                        /* tk_status of the request */
     int kind;
@@ -306,6 +330,12 @@ typedef struct tk_server tk_server;
 
 /* workers in 1..16.  Errors: TK_EINVAL, TK_ENOMEM, TK_EHIP. */
 tk_status tk_server_create(tk_ctx *ctx, int workers, tk_server **out);
+/* Continuous batching: a worker that takes a compress request also takes the queued compress
+ * requests with the same grid and options (up to max_group in all, while their estimates fit
+ * the budget) and runs them as one tk_compress_group pass; each result is bitwise the one the
+ * request gets alone.  max_group in 1..32 (1: one request per pass); default 32.
+ * Errors: TK_EINVAL. */
+tk_status tk_server_set_batching(tk_server *sv, int max_group);
 /* Queue a request (copied; the vectors must stay valid until the request finishes) and return
  * its ticket.  Non-blocking.  Errors: TK_EINVAL (bad kind, missing vectors, server stopping). */
 tk_status tk_server_submit(tk_server *sv, const tk_request *req, long long *ticket);

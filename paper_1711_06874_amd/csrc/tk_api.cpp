@@ -17,7 +17,9 @@
 #include <cstdio>
 #include <cstring>
 #include <condition_variable>
+#include <map>
 #include <mutex>
+#include <utility>
 #include <thread>
 #include <new>
 #include <string>
@@ -141,6 +143,15 @@ struct tk_ctx {
     std::mutex pool_mu;
     std::vector<hipStream_t> streams;
     int workers = 4;
+    // per-stream workspaces (slot 0: a call's workspace, slot 1: a quadratic form's own y),
+    // grown when a call needs more and kept for the next call on the stream
+    struct WsBlock {
+        void* ptr = nullptr;
+        size_t bytes = 0;
+        bool busy = false;
+    };
+    std::mutex ws_mu;
+    std::map<std::pair<hipStream_t, int>, WsBlock> ws;
 };
 
 struct tk_tucker {
@@ -186,6 +197,68 @@ struct Reservation {
     }
     ~Reservation() { if (held) release(c, bytes); }
 };
+
+// Device workspace of one call on stream s: the stream's cached block, grown when too small
+// and kept afterwards (calls on one stream run in stream order, so the next call may reuse it
+// at once), or a one-off block when another host thread holds it.  The pool allocator is
+// slow when many workspaces of varying sizes come and go, so steady-state calls allocate
+// nothing.  An idle cached block is not charged to the budget; the call's Reservation is.
+struct Ws {
+    tk_ctx* c = nullptr;
+    hipStream_t s = nullptr;
+    int slot = 0;
+    void* p = nullptr;
+    bool cached = false;
+    Ws() = default;
+    Ws(const Ws&) = delete;
+    Ws& operator=(const Ws&) = delete;
+    ~Ws()
+    {
+        if (!p) return;
+        if (cached) {
+            std::lock_guard<std::mutex> g(c->ws_mu);
+            c->ws[{s, slot}].busy = false;
+        } else {
+            (void)hipFreeAsync(p, s);
+        }
+    }
+};
+
+hipError_t ws_get(tk_ctx* c, hipStream_t s, int slot, size_t bytes, Ws& w)
+{
+    w.c = c;
+    w.s = s;
+    w.slot = slot;
+    std::lock_guard<std::mutex> g(c->ws_mu);
+    tk_ctx::WsBlock& b = c->ws[{s, slot}];
+    if (b.busy) {
+        hipError_t e = hipMallocAsync(&w.p, bytes, s);
+        if (e != hipSuccess) w.p = nullptr;
+        return e;
+    }
+    if (b.bytes < bytes) {
+        if (b.ptr) (void)hipFreeAsync(b.ptr, s);   // after the earlier calls on s, in stream order
+        b.ptr = nullptr;
+        b.bytes = 0;
+        const size_t want = align_up(bytes, (size_t)1 << 24);
+        hipError_t e = hipMallocAsync(&b.ptr, want, s);
+        if (e == hipSuccess) {
+            b.bytes = want;
+        } else {
+            (void)hipGetLastError();
+            e = hipMallocAsync(&b.ptr, bytes, s);
+            if (e != hipSuccess) {
+                b.ptr = nullptr;
+                return e;
+            }
+            b.bytes = bytes;
+        }
+    }
+    b.busy = true;
+    w.p = b.ptr;
+    w.cached = true;
+    return hipSuccess;
+}
 
 bool finite(double x) { return std::isfinite(x); }
 
@@ -879,14 +952,10 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void
     Reservation res(ctx, need);
     if (!res.take()) return fail(TK_ENOMEM, "compress needs %zu bytes; budget %zu, in use %zu", need, ctx->budget,
                                  ctx->in_use.load());
-    void* base = nullptr;
-    hipError_t he = hipMallocAsync(&base, total, s);
-    if (he != hipSuccess) return fail(TK_ENOMEM, "hipMallocAsync(%zu): %s", total, hipGetErrorString(he));
-    struct Freer {
-        void* p;
-        hipStream_t s;
-        ~Freer() { if (p) hipFreeAsync(p, s); }
-    } freer{base, s};
+    Ws wsp;
+    hipError_t he = ws_get(ctx, s, 0, total, wsp);
+    if (he != hipSuccess) return fail(TK_ENOMEM, "workspace of %zu bytes: %s", total, hipGetErrorString(he));
+    void* base = wsp.p;
     Arena ar;
     ar.base = (char*)base;
     Work w;
@@ -1103,14 +1172,10 @@ tk_status matvec_impl(tk_ctx* ctx, const tk_tucker* t, const T* z, T* y, hipStre
     Reservation res(ctx, need);
     if (!res.take()) return fail(TK_ENOMEM, "matvec needs %zu bytes; budget %zu, in use %zu", need, ctx->budget,
                                  ctx->in_use.load());
-    void* base = nullptr;
-    hipError_t he = hipMallocAsync(&base, need, s);
-    if (he != hipSuccess) return fail(TK_ENOMEM, "hipMallocAsync(%zu): %s", need, hipGetErrorString(he));
-    struct Freer {
-        void* p;
-        hipStream_t s;
-        ~Freer() { if (p) hipFreeAsync(p, s); }
-    } freer{base, s};
+    Ws wsp;
+    hipError_t he = ws_get(ctx, s, 0, need, wsp);
+    if (he != hipSuccess) return fail(TK_ENOMEM, "workspace of %zu bytes: %s", need, hipGetErrorString(he));
+    void* base = wsp.p;
     Arena ar;
     ar.base = (char*)base;
     T* W = ar.take<T>((size_t)r0 * r1 * t->n[2]);
@@ -1225,14 +1290,10 @@ tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, 
     Reservation res(ctx, plan.off);
     if (!res.take()) return fail(TK_ENOMEM, "matvec needs %zu bytes; budget %zu, in use %zu", plan.off, ctx->budget,
                                  ctx->in_use.load());
-    void* base = nullptr;
-    hipError_t he = hipMallocAsync(&base, plan.off, s);
-    if (he != hipSuccess) return fail(TK_ENOMEM, "hipMallocAsync(%zu): %s", plan.off, hipGetErrorString(he));
-    struct Freer {
-        void* p;
-        hipStream_t s;
-        ~Freer() { if (p) (void)hipFreeAsync(p, s); }
-    } freer{base, s};
+    Ws wsp;
+    hipError_t he = ws_get(ctx, s, 0, plan.off, wsp);
+    if (he != hipSuccess) return fail(TK_ENOMEM, "workspace of %zu bytes: %s", plan.off, hipGetErrorString(he));
+    void* base = wsp.p;
     Arena ar;
     ar.base = (char*)base;
     lay(ar, &Uh0, &Uh1, &Uh2, &M1, &Hs, &Uh3, &A1, &A2, &dots, tw);
@@ -1386,6 +1447,13 @@ tk_status tk_ctx_create(int device, size_t hbm_budget_bytes, tk_ctx** out)
     TK_HIP(hipDeviceGetDefaultMemPool(&pool, device));
     uint64_t thr = UINT64_MAX;
     TK_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+    // memory freed on one stream goes to another only once the free has completed: reuse that
+    // follows event dependencies would make a worker's next allocation wait for the kernels
+    // another worker still runs on memory it has just released
+    int off = 0;
+    TK_HIP(hipMemPoolSetAttribute(pool, hipMemPoolReuseFollowEventDependencies, &off));
+    TK_HIP(hipMemPoolSetAttribute(pool, hipMemPoolReuseAllowOpportunistic, &off));
+    TK_HIP(hipMemPoolSetAttribute(pool, hipMemPoolReuseAllowInternalDependencies, &off));
     TK_HIP(eig_set_attributes());
     TK_HIP(kron_set_attributes());
     TK_HIP(fft_set_attributes());
@@ -1413,6 +1481,13 @@ void tk_ctx_destroy(tk_ctx* ctx)
     if (ctx->dev_slots) (void)hipFree(ctx->dev_slots);
     ctx->pinned = nullptr;
     ctx->dev_slots = nullptr;
+    {
+        std::lock_guard<std::mutex> g(ctx->ws_mu);
+        for (auto& kv : ctx->ws)
+            if (kv.second.ptr) (void)hipFreeAsync(kv.second.ptr, nullptr);
+        ctx->ws.clear();
+    }
+    hipDeviceSynchronize();
     for (hipStream_t st : ctx->streams) (void)hipStreamDestroy(st);
     ctx->streams.clear();
     bool now = false;
@@ -1422,6 +1497,22 @@ void tk_ctx_destroy(tk_ctx* ctx)
         now = (ctx->live_results == 0);
     }
     if (now) delete ctx;
+}
+
+tk_status tk_ctx_release_stream(tk_ctx* ctx, void* hip_stream)
+{
+    if (!ctx) return fail(TK_EINVAL, "ctx is NULL");
+    TK_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::lock_guard<std::mutex> g(ctx->ws_mu);
+    for (int slot = 0; slot < 2; ++slot) {
+        auto it = ctx->ws.find({s, slot});
+        if (it == ctx->ws.end()) continue;
+        if (it->second.busy) return fail(TK_EINVAL, "a call on this stream is still running");
+        if (it->second.ptr) (void)hipFreeAsync(it->second.ptr, s);
+        ctx->ws.erase(it);
+    }
+    return TK_OK;
 }
 
 tk_status tk_ctx_set_workers(tk_ctx* ctx, int workers)
@@ -1469,6 +1560,34 @@ tk_status tk_compress_tensor(tk_ctx* ctx, const void* A_dev, const tk_grid* grid
 {
     if (!A_dev) return fail(TK_EINVAL, "A_dev is NULL");
     return compress_any(ctx, nullptr, A_dev, grid, opts, hip_stream, out);
+}
+
+tk_status tk_compress_group(tk_ctx* ctx, int count, const tk_kernel* kernels, const tk_grid* grid,
+                            const tk_opts* opts, void* hip_stream, tk_tucker** outs, int* statuses)
+{
+    if (!ctx || !kernels || !grid || !opts || !outs || !statuses) return fail(TK_EINVAL, "NULL argument");
+    if (count < 1 || count > BATCH_MAX) return fail(TK_EINVAL, "count=%d: 1..%d problems per group", count, BATCH_MAX);
+    for (int i = 0; i < count; ++i) { outs[i] = nullptr; statuses[i] = TK_OK; }
+    tk_status st[BATCH_MAX];
+    tk_status r;
+    if (count == 1 || !groupable(opts)) {
+        for (int i = 0; i < count; ++i) {
+            r = compress_any(ctx, &kernels[i], nullptr, grid, opts, hip_stream, &outs[i]);
+            if (r == TK_ENOCONV) { statuses[i] = TK_ENOCONV; continue; }
+            if (r != TK_OK) {
+                std::string m = g_last_error;
+                for (int j = 0; j < i; ++j) { free_result(outs[j]); outs[j] = nullptr; }
+                return fail(r, "%s", m.c_str());
+            }
+        }
+        return TK_OK;
+    }
+    const tk_kernel* ks[BATCH_MAX];
+    for (int i = 0; i < count; ++i) ks[i] = &kernels[i];
+    r = compress_group(ctx, ks, count, grid, opts, (hipStream_t)hip_stream, outs, st);
+    if (r != TK_OK) return r;
+    for (int i = 0; i < count; ++i) statuses[i] = st[i];
+    return TK_OK;
 }
 
 tk_status tk_compress_batch(tk_ctx* ctx, int count, const tk_kernel* kernels, const tk_grid* grids,
@@ -1681,12 +1800,9 @@ tk_status tk_reconstruct(tk_ctx* ctx, const tk_tucker* t, void* A_dev, int io, v
     Reservation res(ctx, need);
     if (!res.take()) return fail(TK_ENOMEM, "reconstruct needs %zu bytes", need);
     void* base = nullptr;
-    TK_HIP(hipMallocAsync(&base, need, s));
-    struct Freer {
-        void* p;
-        hipStream_t s;
-        ~Freer() { if (p) hipFreeAsync(p, s); }
-    } freer{base, s};
+    Ws wsp;
+    TK_HIP(ws_get(ctx, s, 0, need, wsp));
+    base = wsp.p;
     Arena ar;
     ar.base = (char*)base;
     double* M1 = ar.take<double>((size_t)n[0] * r[1] * r[2]);
@@ -1739,14 +1855,15 @@ tk_status tk_quadratic_form(tk_ctx* ctx, const tk_tucker* t, const void* z_dev, 
     int off[3], m[3];
     if (!cov_geometry(t, off, m)) return fail(TK_ELAYOUT, "even-sized centred grid has no origin node");
     void* ybuf = y_dev;
-    void* owned = nullptr;
     size_t esz = io == TK_FP32 ? 4 : 8;
     size_t ybytes = esz * (size_t)m[0] * m[1] * m[2];
     Reservation res(ctx, y_dev ? 0 : ybytes);
+    Ws yws;
     if (!y_dev) {
         if (!res.take()) return fail(TK_ENOMEM, "quadratic form needs %zu bytes", ybytes);
-        TK_HIP(hipMallocAsync(&owned, ybytes, s));
-        ybuf = owned;
+        hipError_t he = ws_get(ctx, s, 1, ybytes, yws);
+        if (he != hipSuccess) return fail(TK_ENOMEM, "y of %zu bytes: %s", ybytes, hipGetErrorString(he));
+        ybuf = yws.p;
     }
     tk_status st;
     if (io == TK_FP64 && ctx->matvec_method == TK_MV_FFT) st = fail(TK_EINVAL, "the FFT matvec is FP32 only");
@@ -1756,7 +1873,6 @@ tk_status tk_quadratic_form(tk_ctx* ctx, const tk_tucker* t, const void* z_dev, 
         st = matvec_impl<float>(ctx, t, (const float*)z_dev, (float*)ybuf, s, out);
     else
         st = matvec_impl<double>(ctx, t, (const double*)z_dev, (double*)ybuf, s, out);
-    if (owned) hipFreeAsync(owned, s);
     return st;
 }
 
@@ -1896,10 +2012,9 @@ tk_status tk_gram(tk_ctx* ctx, const void* A_dev, const int n[3], int mode, int 
     size_t wb = gram_work_bytes(n, mode, prec);
     Reservation res(ctx, wb);
     if (!res.take()) return fail(TK_ENOMEM, "gram needs %zu bytes", wb);
-    void* work = nullptr;
-    TK_HIP(hipMallocAsync(&work, wb, s));
-    hipError_t e = launch_gram(A_dev, n, mode, prec, G_dev, work, s);
-    hipFreeAsync(work, s);
+    Ws wsp;
+    TK_HIP(ws_get(ctx, s, 0, wb, wsp));
+    hipError_t e = launch_gram(A_dev, n, mode, prec, G_dev, wsp.p, s);
     if (e != hipSuccess) return fail(TK_EHIP, "gram launch: %s", hipGetErrorString(e));
     return TK_OK;
 }
@@ -1917,10 +2032,10 @@ tk_status tk_eig_topr(tk_ctx* ctx, int count, int n, int r, const double* G_dev,
     size_t need = sizeof(double) * (size_t)count * (2 * (size_t)n * p + 2 * (size_t)p * p + 64) + 4096;
     Reservation res(ctx, need);
     if (!res.take()) return fail(TK_ENOMEM, "eig needs %zu bytes", need);
-    void* base = nullptr;
-    TK_HIP(hipMallocAsync(&base, need, s));
+    Ws wsp;
+    TK_HIP(ws_get(ctx, s, 0, need, wsp));
     Arena ar;
-    ar.base = (char*)base;
+    ar.base = (char*)wsp.p;
     EigBatch b{};
     b.count = count; b.n = n; b.p = p; b.r = r;
     b.G = G_dev; b.sG = (long)n * n;
@@ -1931,7 +2046,6 @@ tk_status tk_eig_topr(tk_ctx* ctx, int count, int n, int r, const double* G_dev,
     b.U = U_dev; b.sU = (long)n * r; b.ldu = r;
     b.lam = lambda_dev; b.sL = r;
     hipError_t e = launch_eig(b, COLD_ITERS, s);
-    hipFreeAsync(base, s);
     if (e != hipSuccess) return fail(TK_EHIP, "eig launch: %s", hipGetErrorString(e));
     return TK_OK;
 }

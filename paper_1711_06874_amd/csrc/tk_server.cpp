@@ -41,7 +41,19 @@ struct Pending {
     Clock::time_point t_submit;
     size_t est = 0;          // admission estimate (0 until computed)
     hipEvent_t ready = nullptr;   // recorded on the submitter's stream; the worker waits for it
+    bool solo = false;       // run alone (a group it was part of did not fit)
 };
+
+// Compress requests that may share launches: same grid, same options.
+bool same_problem_shape(const tk_request& a, const tk_request& b)
+{
+    if (a.kind != TK_REQ_COMPRESS || b.kind != TK_REQ_COMPRESS) return false;
+    for (int k = 0; k < 3; ++k)
+        if (a.grid.n[k] != b.grid.n[k] || a.grid.b[k] != b.grid.b[k] || a.opts.ranks[k] != b.opts.ranks[k])
+            return false;
+    return a.grid.layout == b.grid.layout && a.opts.eps == b.opts.eps && a.opts.r_max == b.opts.r_max &&
+           a.opts.hooi_sweeps == b.opts.hooi_sweeps && a.opts.prec == b.opts.prec;
+}
 
 }  // namespace
 
@@ -52,6 +64,7 @@ struct tk_server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     bool stop = false;
+    int group_max = 32;                           // compress requests one pass may take
     long long next_id = 1;
     int running = 0;
     size_t admitted = 0;                          // estimates of running requests
@@ -151,6 +164,42 @@ void run_one(tk_server* sv, const Pending& p, hipStream_t s, tk_result* res, tk_
     if (st != TK_OK) set_error(res, tk_last_error());
 }
 
+// Compress requests on one grid in one pass (tk_compress_group); res[b] per member.
+void run_group(tk_server* sv, const std::vector<Pending>& g, hipStream_t s, std::vector<tk_result>& res,
+               std::vector<tk_tucker*>& made)
+{
+    const int nb = (int)g.size();
+    made.assign(nb, nullptr);
+    for (const Pending& p : g)
+        if (p.ready && hipStreamWaitEvent(s, p.ready, 0) != hipSuccess) {
+            for (tk_result& r : res) {
+                r.status = TK_EHIP;
+                set_error(&r, "hipStreamWaitEvent on a request's ready event failed");
+            }
+            return;
+        }
+    std::vector<tk_kernel> ks(nb);
+    for (int b = 0; b < nb; ++b) ks[b] = g[b].r.kernel;
+    std::vector<int> sts(nb, TK_OK);
+    const tk_status st = tk_compress_group(sv->ctx, nb, ks.data(), &g[0].r.grid, &g[0].r.opts, s, made.data(),
+                                           sts.data());
+    for (int b = 0; b < nb; ++b) {
+        if (st != TK_OK) {
+            res[b].status = st;
+            set_error(&res[b], tk_last_error());
+            made[b] = nullptr;
+            continue;
+        }
+        res[b].status = sts[b];
+        int n[3], rk[3], lay;
+        double e, na;
+        tk_tucker_info(made[b], n, rk, &e, &na, &lay);
+        std::memcpy(res[b].ranks, rk, sizeof(rk));
+        res[b].rel_err = e;
+        if (sts[b] != TK_OK) set_error(&res[b], "eps not reached within r_max");
+    }
+}
+
 void worker(tk_server* sv, int wi)
 {
     int dev = 0;
@@ -188,41 +237,76 @@ void worker(tk_server* sv, int wi)
             sv->cv_done.notify_all();
             continue;
         }
+        // continuous batching: queued compress requests on the same grid join this pass while
+        // their estimates fit the budget
+        std::vector<Pending> group{p};
+        size_t est_sum = p.est;
+        if (p.r.kind == TK_REQ_COMPRESS && !p.solo && sv->group_max > 1) {
+            size_t budget = 0, in_use = 0;
+            tk_ctx_budget(sv->ctx, &budget, &in_use);
+            for (auto jt = sv->queue.begin(); jt != sv->queue.end() && (int)group.size() < sv->group_max;) {
+                tk_status jf = TK_OK;
+                if (!jt->solo && same_problem_shape(jt->r, p.r) && admissible(sv, *jt, &jf) == 1 &&
+                    in_use + sv->admitted + est_sum + jt->est <= budget) {
+                    est_sum += jt->est;
+                    group.push_back(*jt);
+                    jt = sv->queue.erase(jt);
+                    continue;
+                }
+                ++jt;
+            }
+        }
+        const int nb = (int)group.size();
         ++sv->running;
-        sv->admitted += p.est;
+        sv->admitted += est_sum;
         if (p.r.kind != TK_REQ_COMPRESS) ++sv->resident[p.r.target].users;
         lk.unlock();
-        res.t_start = secs(sv, Clock::now());
-        tk_tucker* made = nullptr;
-        run_one(sv, p, s, &res, &made);
-        res.t_end = secs(sv, Clock::now());
+        std::vector<tk_result> rs(nb, res);
+        for (int b = 0; b < nb; ++b) {
+            rs[b].kind = group[b].r.kind;
+            rs[b].t_submit = secs(sv, group[b].t_submit);
+        }
+        const double t0 = secs(sv, Clock::now());
+        std::vector<tk_tucker*> made(nb, nullptr);
+        if (nb == 1) run_one(sv, p, s, &rs[0], &made[0]);
+        else run_group(sv, group, s, rs, made);
+        const double t1 = secs(sv, Clock::now());
+        for (tk_result& r : rs) { r.t_start = t0; r.t_end = t1; }
         std::vector<tk_tucker*> to_free;
         lk.lock();
         --sv->running;
-        sv->admitted -= p.est;
-        if (res.status == TK_ENOMEM && sv->running > 0) {
-            // memory went to requests admitted meanwhile: queue it again at the front
-            if (made) to_free.push_back(made);
+        sv->admitted -= est_sum;
+        if (rs[0].status == TK_ENOMEM && (sv->running > 0 || nb > 1)) {
+            // memory went to requests admitted meanwhile (or the group was too large): queue
+            // the requests again at the front, a group's members to run alone
+            for (tk_tucker* t : made)
+                if (t) to_free.push_back(t);
             if (p.r.kind != TK_REQ_COMPRESS) --sv->resident[p.r.target].users;
-            sv->queue.push_front(p);
-        } else {
-            if (p.ready) (void)hipEventDestroy(p.ready);
-            if (p.r.kind == TK_REQ_COMPRESS) {
-                if (made && (res.status == TK_OK || res.status == TK_ENOCONV)) {
-                    sv->resident[p.id].t = made;
-                    sv->compress_state[p.id] = 1;
-                } else {
-                    if (made) to_free.push_back(made);
-                    sv->compress_state[p.id] = -1;
-                }
-            } else {
-                Resident& rs = sv->resident[p.r.target];
-                if (--rs.users == 0 && rs.released) {
-                    to_free.push_back(rs.t);
-                    sv->resident.erase(p.r.target);
-                }
+            for (int b = nb - 1; b >= 0; --b) {
+                if (nb > 1) group[b].solo = true;
+                sv->queue.push_front(group[b]);
             }
-            sv->done[p.id] = res;
+        } else {
+            for (int b = 0; b < nb; ++b) {
+                const Pending& q = group[b];
+                if (q.ready) (void)hipEventDestroy(q.ready);
+                if (q.r.kind == TK_REQ_COMPRESS) {
+                    if (made[b] && (rs[b].status == TK_OK || rs[b].status == TK_ENOCONV)) {
+                        sv->resident[q.id].t = made[b];
+                        sv->compress_state[q.id] = 1;
+                    } else {
+                        if (made[b]) to_free.push_back(made[b]);
+                        sv->compress_state[q.id] = -1;
+                    }
+                } else {
+                    Resident& rsd = sv->resident[q.r.target];
+                    if (--rsd.users == 0 && rsd.released) {
+                        to_free.push_back(rsd.t);
+                        sv->resident.erase(q.r.target);
+                    }
+                }
+                sv->done[q.id] = rs[b];
+            }
             sv->cv_done.notify_all();
         }
         sv->cv_work.notify_all();
@@ -266,6 +350,14 @@ tk_status tk_server_create(tk_ctx* ctx, int workers, tk_server** out)
     return TK_OK;
 }
 
+tk_status tk_server_set_batching(tk_server* sv, int max_group)
+{
+    if (!sv || max_group < 1 || max_group > 32) return TK_EINVAL;
+    std::lock_guard<std::mutex> g(sv->mu);
+    sv->group_max = max_group;
+    return TK_OK;
+}
+
 tk_status tk_server_submit(tk_server* sv, const tk_request* req, long long* ticket)
 {
     if (!sv || !req || !ticket) return TK_EINVAL;
@@ -273,15 +365,20 @@ tk_status tk_server_submit(tk_server* sv, const tk_request* req, long long* tick
     if ((req->kind == TK_REQ_MATVEC && (!req->z_dev || !req->y_dev)) ||
         (req->kind == TK_REQ_QUADFORM && !req->z_dev))
         return TK_EINVAL;
+    // only the vectors of a matvec or quadratic form are device inputs that the submitter may
+    // still be producing; an event on its stream orders the request after that work
     hipEvent_t ready = nullptr;
-    if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess) return TK_EHIP;
-    if (hipEventRecord(ready, (hipStream_t)req->stream) != hipSuccess) {
-        (void)hipEventDestroy(ready);
-        return TK_EHIP;
+    const bool vectors = req->kind == TK_REQ_MATVEC || req->kind == TK_REQ_QUADFORM;
+    if (vectors && req->stream != TK_STREAM_READY) {
+        if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess) return TK_EHIP;
+        if (hipEventRecord(ready, (hipStream_t)req->stream) != hipSuccess) {
+            (void)hipEventDestroy(ready);
+            return TK_EHIP;
+        }
     }
     std::lock_guard<std::mutex> g(sv->mu);
     if (sv->stop) {
-        (void)hipEventDestroy(ready);
+        if (ready) (void)hipEventDestroy(ready);
         return TK_EINVAL;
     }
     Pending p;
@@ -354,7 +451,11 @@ void tk_server_destroy(tk_server* sv)
     for (auto& th : sv->threads) th.join();
     for (auto& kv : sv->resident)
         if (kv.second.t) tk_tucker_free(kv.second.t);
-    for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
+    for (hipStream_t s : sv->streams) {
+        (void)hipStreamSynchronize(s);
+        (void)tk_ctx_release_stream(sv->ctx, s);
+        (void)hipStreamDestroy(s);
+    }
     delete sv;
 }
 

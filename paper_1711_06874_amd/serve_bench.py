@@ -7,7 +7,7 @@ request loop (tk_server_*), one JSON line per arrival rate.
 70% compress requests (Matern nu in {1/2, 3/2, 5/2}, ell log-uniform on [0.05, 1], eps 1e-6,
 FP32, offset grid n in {64, 128, 256, 384}), 30% follow-ups split evenly among the covariance
 matvec, the trace and the quadratic form on an earlier compress (seeded N(0,1) vectors drawn on
-the device).  Admission is capped by the HBM budget.  Reported per request type: p50 / p99 of
+the device before the replay).  Admission is capped by the HBM budget.  Reported per request type: p50 / p99 of
 the latency (finish - arrival, queueing included) and of the service time (finish - start),
 and the throughput over the whole stream.
 """
@@ -25,21 +25,35 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+ZPOOL = 4   # distinct seeded input vectors per grid size
+YPOOL = 12  # matvec outputs per grid size allocated before the replay
+
+
 def pct(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs, dtype=float), q)) if xs else None
 
 
-def run_rate(tk, ctx, rate, count, workers, prec, trace=None):
+def run_rate(tk, ctx, rate, count, workers, prec, trace=None, batching=32):
     import torch
     import synth
     reqs = synth.serving_stream(rate, count)
     sv = tk.Server(ctx, workers)
+    sv.set_batching(batching)
     opts = tk.make_opts(eps=1e-6, hooi_sweeps=2, prec=prec)
     tickets = {}          # rid -> ticket
     sizes = {}            # compress rid -> n
-    keep = {}             # ticket -> device vectors in use until the request finished
-    spare = {}            # n -> free (z, y) pairs: vectors are reused, not reallocated per request
+    keep = {}             # ticket -> output vector in use until the request finished
+    spare = {}            # n -> free output vectors (reused, not reallocated per request)
+    # seeded N(0,1) inputs, drawn before the replay (ZPOOL per size, read-only, shared by the
+    # requests), so the client does no device work while the server is measured
+    zpool = {n: [synth.normal_vector_device((n, n, n), 1_000_000 * n + j) for j in range(ZPOOL)]
+             for n in synth.STREAM_SIZES}
+    # matvec outputs, allocated before the replay as well (more only if all are in use)
+    for n in synth.STREAM_SIZES:
+        spare[n] = [torch.empty((n, n, n), dtype=torch.float32, device="cuda") for _ in range(YPOOL)]
+    extra = [0]
+    torch.cuda.synchronize()
     order = []            # (ticket, kind, rid)
     results = {}
     lock = threading.Lock()
@@ -53,9 +67,9 @@ def run_rate(tk, ctx, rate, count, workers, prec, trace=None):
             r = sv.wait(t)
             with lock:
                 results[t] = (kind, rid, r)
-                pair = keep.pop(t, None)
-                if pair is not None:
-                    spare.setdefault(pair[0].shape[0], []).append(pair)
+                y = keep.pop(t, None)
+                if y is not None:
+                    spare.setdefault(y.shape[0], []).append(y)
                 if len(results) % 250 == 0:
                     print("rate %g: %d of %d finished" % (rate, len(results), len(reqs)), file=sys.stderr, flush=True)
 
@@ -77,19 +91,18 @@ def run_rate(tk, ctx, rate, count, workers, prec, trace=None):
                 n = sizes[q.target]
                 if q.kind == "trace":
                     t = sv.submit_trace(target)
+                elif q.kind == "quadform":
+                    t = sv.submit_quadform(target, zpool[n][q.rid % ZPOOL], stream=tk.STREAM_READY)
                 else:
                     with lock:
                         free = spare.get(n)
-                        pair = free.pop() if free else None
-                    if pair is None:
-                        pair = (torch.empty((n, n, n), dtype=torch.float32, device="cuda"),
-                                torch.empty((n, n, n), dtype=torch.float32, device="cuda"))
-                    z, y = pair
-                    synth.fill_normal_device(z, q.rid)
-                    t = (sv.submit_matvec(target, z, y) if q.kind == "matvec"
-                         else sv.submit_quadform(target, z, y=y))
+                        y = free.pop() if free else None
+                    if y is None:
+                        extra[0] += 1
+                        y = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
+                    t = sv.submit_matvec(target, zpool[n][q.rid % ZPOOL], y, stream=tk.STREAM_READY)
                     with lock:
-                        keep[t] = pair
+                        keep[t] = y
             tickets[q.rid] = t
             with lock:
                 order.append((t, q.kind, q.rid))
@@ -122,6 +135,7 @@ def run_rate(tk, ctx, rate, count, workers, prec, trace=None):
     span = (t_last - t_first) if done else 0.0
     return {
         "rate_req_s": rate, "requests": len(reqs), "completed": done, "failed": len(failures),
+        "outputs_allocated_during_replay": extra[0],
         "failures": failures,
         "compress_eps_missed": eps_miss,
         "throughput_req_s": done / span if span > 0 else None,
@@ -139,6 +153,7 @@ def main():
     ap.add_argument("--workers", type=int, default=4)
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--prec", choices=["fp32", "bf16x3"], default="fp32")
+    ap.add_argument("--batching", type=int, default=32, help="compress requests one pass may take (1: off)")
     ap.add_argument("--trace", default=None, help="append one CSV row per request: rate, id, kind, n, "
                                                   "t_submit, t_start, t_end, status")
     args = ap.parse_args()
@@ -149,8 +164,9 @@ def main():
     prec = tk.TK_FP32 if args.prec == "fp32" else tk.TK_BF16X3
     try:
         for rate in args.rates:
-            out = run_rate(tk, ctx, rate, args.count, args.workers, prec, args.trace)
+            out = run_rate(tk, ctx, rate, args.count, args.workers, prec, args.trace, args.batching)
             out.update({"workers": args.workers, "budget_gib": args.budget_gib, "precision": args.prec,
+                        "batching": args.batching,
                         "workload": "Poisson stream: 70% compress (Matern, offset grid n in {64,128,256,384}, "
                                     "eps 1e-6), 30% matvec / trace / quadratic form on earlier results"})
             print(json.dumps(out), flush=True)

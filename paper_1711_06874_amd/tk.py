@@ -71,6 +71,8 @@ _SIGS = {
                           ctypes.POINTER(_vp)]),
     "tk_compress_tensor": (_st, [_vp, _vp, ctypes.POINTER(tk_grid), ctypes.POINTER(tk_opts), _vp,
                                  ctypes.POINTER(_vp)]),
+    "tk_compress_group": (_st, [_vp, ctypes.c_int, ctypes.POINTER(tk_kernel), ctypes.POINTER(tk_grid),
+                                ctypes.POINTER(tk_opts), _vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int)]),
     "tk_compress_batch": (_st, [_vp, ctypes.c_int, ctypes.POINTER(tk_kernel), ctypes.POINTER(tk_grid),
                                 ctypes.POINTER(tk_opts), _vp, ctypes.POINTER(_vp)]),
     "tk_tucker_info": (_st, [_vp, _ip, _ip, _dp, _dp, _ip]),
@@ -88,9 +90,11 @@ _SIGS = {
     "tk_gram": (_st, [_vp, _vp, _ip, ctypes.c_int, ctypes.c_int, _vp, _vp]),
     "tk_eig_topr": (_st, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "tk_set_matvec_method": (_st, [_vp, ctypes.c_int]),
+    "tk_ctx_release_stream": (_st, [_vp, _vp]),
     "tk_ctx_set_workers": (_st, [_vp, ctypes.c_int]),
     "tk_estimate_matvec_bytes": (_st, [_vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "tk_server_create": (_st, [_vp, ctypes.c_int, ctypes.POINTER(_vp)]),
+    "tk_server_set_batching": (_st, [_vp, ctypes.c_int]),
     "tk_server_submit": (_st, [_vp, ctypes.POINTER(tk_request), ctypes.POINTER(ctypes.c_longlong)]),
     "tk_server_wait": (_st, [_vp, ctypes.c_longlong, ctypes.POINTER(tk_result)]),
     "tk_server_tucker": (_st, [_vp, ctypes.c_longlong, ctypes.POINTER(_vp)]),
@@ -216,6 +220,17 @@ def tk_compress_batch(ctx: int, kernels, grids, opts: tk_opts, stream=None):
     outs = (_vp * n)()
     _check(_lib.tk_compress_batch(ctx, n, ks, gs, ctypes.byref(opts), _stream(stream), outs), "tk_compress_batch")
     return [o for o in outs]
+
+
+def tk_compress_group(ctx: int, kernels, grid: tk_grid, opts: tk_opts, stream=None):
+    """Returns [(handle, status)] for problems sharing `grid` (status TK_OK or TK_ENOCONV)."""
+    n = len(kernels)
+    ks = (tk_kernel * n)(*kernels)
+    outs = (_vp * n)()
+    sts = (ctypes.c_int * n)()
+    _check(_lib.tk_compress_group(ctx, n, ks, ctypes.byref(grid), ctypes.byref(opts), _stream(stream), outs, sts),
+           "tk_compress_group")
+    return [(o, s) for o, s in zip(outs, sts)]
 
 
 def tk_tucker_info(t: int):
@@ -372,6 +387,9 @@ class Context:
     def compress_tensor(self, A, grid, opts, stream=None, allow_noconv=False) -> Tucker:
         return Tucker(tk_compress_tensor(self.handle, A, grid, opts, stream, allow_noconv), self)
 
+    def compress_group(self, kernels, grid, opts, stream=None):
+        return [Tucker(h, self) for h, _ in tk_compress_group(self.handle, kernels, grid, opts, stream)]
+
     def compress_batch(self, kernels, grids, opts, stream=None):
         return [Tucker(h, self) for h in tk_compress_batch(self.handle, kernels, grids, opts, stream)]
 
@@ -389,6 +407,9 @@ class Context:
 
     def set_matvec_method(self, method: int):
         tk_set_matvec_method(self.handle, method)
+
+    def release_stream(self, stream):
+        _check(_lib.tk_ctx_release_stream(self.handle, _stream(stream)), "tk_ctx_release_stream")
 
     def set_workers(self, workers: int):
         _check(_lib.tk_ctx_set_workers(self.handle, workers), "tk_ctx_set_workers")
@@ -412,6 +433,9 @@ class TuckerView:
         return tk_tucker_get(self.handle)
 
 
+STREAM_READY = object()   # submit stream marker: the request's vectors are complete already (TK_STREAM_READY)
+
+
 class Server:
     """Request loop over resident results (tk_server_*): submit returns a ticket, wait blocks
     until that request finished and returns its result as a dict.  Work queued on `stream`
@@ -426,7 +450,10 @@ class Server:
 
     @staticmethod
     def _order(stream):
-        # default: the stream the caller's device work (torch's current stream) is queued on
+        # default: the stream the caller's device work (torch's current stream) is queued on;
+        # STREAM_READY: the vectors are complete, no ordering
+        if stream is STREAM_READY:
+            return (1 << 64) - 1
         if stream is None:
             try:
                 import torch
@@ -436,6 +463,9 @@ class Server:
                 pass
             return 0
         return _stream(stream)
+
+    def set_batching(self, max_group: int):
+        _check(_lib.tk_server_set_batching(self.handle, int(max_group)), "tk_server_set_batching")
 
     def _submit(self, req: tk_request) -> int:
         t = ctypes.c_longlong()

@@ -233,3 +233,40 @@ def test_serving_stream_sampled_against_oracle(tk, oracle):
     finally:
         sv.destroy()
         ctx.destroy()
+
+
+@pytest.mark.parametrize("max_group", [32, 1])
+def test_serving_groups_same_grid(tk, max_group):
+    """A burst of compress requests on two grids (with follow-ups): with batching on, queued
+    requests on one grid share a pass; every result is still bitwise the one alone."""
+    require_gpu()
+    rng = np.random.default_rng(21)
+    specs = [(96, 1) if i % 3 else (81, 0) for i in range(15)]
+    kers = [(float(rng.choice([0.5, 1.5, 2.5])), float(np.exp(rng.uniform(np.log(0.05), 0.0)))) for _ in specs]
+    opts = tk.make_opts(eps=1e-6, hooi_sweeps=2, prec=1)
+    ctx = tk.Context(0)
+    try:
+        alone = []
+        for (n, lay), (nu, ell) in zip(specs, kers):
+            t = ctx.compress(tk.make_kernel(0, nu=nu, ell=ell), tk.make_grid(n, 1.0, lay), opts)
+            alone.append((t.ranks, t.rel_err, t.factors(), ctx.trace(t)))
+            t.free()
+        sv = tk.Server(ctx, 2)
+        sv.set_batching(max_group)
+        try:
+            tickets = [sv.submit_compress(tk.make_kernel(0, nu=nu, ell=ell), tk.make_grid(n, 1.0, lay), opts)
+                       for (n, lay), (nu, ell) in zip(specs, kers)]
+            traces = [sv.submit_trace(t) for t in tickets[::2]]
+            for i, t in enumerate(tickets):
+                r = sv.wait(t)
+                rk, e, (U, C), _ = alone[i]
+                assert r["status"] == tk.TK_OK and r["ranks"] == tuple(rk) and r["rel_err"] == e, f"request {i}"
+                Ub, Cb = sv.tucker(t).factors()
+                assert np.array_equal(Cb, C) and all(np.array_equal(a, b) for a, b in zip(U, Ub)), f"request {i}"
+            for j, t in enumerate(traces):
+                r = sv.wait(t)
+                assert r["status"] == tk.TK_OK and r["value"] == alone[2 * j][3], f"trace {j}"
+        finally:
+            sv.destroy()
+    finally:
+        ctx.destroy()
