@@ -262,6 +262,14 @@ tk_status tk_trace(tk_ctx *ctx, const tk_tucker *t, void *hip_stream, double *ou
  * receives C z (same type and size as z).  Synchronising (one scalar read). */
 tk_status tk_quadratic_form(tk_ctx *ctx, const tk_tucker *t, const void *z_dev, int io,
                             void *hip_stream, double *out, void *y_dev);
+/* tk_quadratic_form for `count` results at once: out[i] = z_i^T C_i z_i (and y_devs[i] = C_i z_i
+ * when y_devs and y_devs[i] are not NULL), the items running concurrently on the context's worker
+ * streams (tk_ctx_set_workers) after the work queued on hip_stream.  Each value is bitwise the
+ * one the single call returns.  Synchronising.  Errors: as tk_quadratic_form, for the first
+ * failing item. */
+tk_status tk_quadratic_form_batch(tk_ctx *ctx, int count, const tk_tucker *const *ts,
+                                  const void *const *z_devs, int io, void *hip_stream, double *out,
+                                  void *const *y_devs);
 
 /* ---------------------------------------------------------------------------------------- */
 /* Individual steps (the same kernels tk_compress runs), exposed for testing and profiling   */

@@ -1876,6 +1876,54 @@ tk_status tk_quadratic_form(tk_ctx* ctx, const tk_tucker* t, const void* z_dev, 
     return st;
 }
 
+tk_status tk_quadratic_form_batch(tk_ctx* ctx, int count, const tk_tucker* const* ts, const void* const* z_devs,
+                                  int io, void* hip_stream, double* out, void* const* y_devs)
+{
+    if (!ctx || !ts || !z_devs || !out || count < 0) return fail(TK_EINVAL, "bad batch arguments");
+    if (count == 0) return TK_OK;
+    for (int i = 0; i < count; ++i)
+        if (!ts[i] || !z_devs[i]) return fail(TK_EINVAL, "item %d: NULL result or vector", i);
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    const int W = std::min(count, ctx->workers);
+    std::vector<hipStream_t> ws(W);
+    {
+        std::lock_guard<std::mutex> g(ctx->pool_mu);
+        while ((int)ctx->streams.size() < W) {
+            hipStream_t st;
+            TK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            ctx->streams.push_back(st);
+        }
+        for (int i = 0; i < W; ++i) ws[i] = ctx->streams[i];
+    }
+    // the items start after the work already queued on the caller's stream
+    hipEvent_t fork;
+    TK_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    TK_HIP(hipEventRecord(fork, (hipStream_t)hip_stream));
+    std::atomic<int> next{0};
+    std::vector<tk_status> st(count, TK_OK);
+    std::vector<std::string> msg(count);
+    auto worker = [&](int wi) {
+        if (hipSetDevice(ctx->device) != hipSuccess) return;
+        hipStream_t s = ws[wi];
+        if (hipStreamWaitEvent(s, fork, 0) != hipSuccess) return;
+        for (;;) {
+            const int i = next.fetch_add(1);
+            if (i >= count) break;
+            st[i] = tk_quadratic_form(ctx, ts[i], z_devs[i], io, s, &out[i], y_devs ? y_devs[i] : nullptr);
+            if (st[i] != TK_OK) msg[i] = g_last_error;
+        }
+    };
+    std::vector<std::thread> th;
+    th.reserve(W);
+    for (int i = 0; i < W; ++i) th.emplace_back(worker, i);
+    for (auto& t : th) t.join();
+    (void)hipEventDestroy(fork);
+    for (int i = 0; i < count; ++i)
+        if (st[i] != TK_OK) return fail(st[i], "batch item %d: %s", i, msg[i].c_str());
+    return TK_OK;
+}
+
 tk_status tk_estimate_matvec_bytes(tk_ctx* ctx, const tk_tucker* t, int io, size_t* bytes)
 {
     if (!ctx || !t || !bytes) return fail(TK_EINVAL, "NULL argument");

@@ -92,6 +92,8 @@ _SIGS = {
     "tk_set_matvec_method": (_st, [_vp, ctypes.c_int]),
     "tk_ctx_release_stream": (_st, [_vp, _vp]),
     "tk_ctx_set_workers": (_st, [_vp, ctypes.c_int]),
+    "tk_quadratic_form_batch": (_st, [_vp, ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, _vp,
+                                      _dp, ctypes.POINTER(_vp)]),
     "tk_estimate_matvec_bytes": (_st, [_vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "tk_server_create": (_st, [_vp, ctypes.c_int, ctypes.POINTER(_vp)]),
     "tk_server_set_batching": (_st, [_vp, ctypes.c_int]),
@@ -301,6 +303,16 @@ def tk_quadratic_form(ctx: int, t: int, z, io=TK_FP32, stream=None, y=None) -> f
     return out.value
 
 
+def tk_quadratic_form_batch(ctx: int, ts, zs, io=TK_FP32, stream=None, ys=None):
+    n = len(ts)
+    th = (_vp * n)(*[int(t) for t in ts])
+    zp = (_vp * n)(*[_ptr(z) for z in zs])
+    yp = (_vp * n)(*[_ptr(y) if y is not None else None for y in ys]) if ys is not None else None
+    out = (ctypes.c_double * n)()
+    _check(_lib.tk_quadratic_form_batch(ctx, n, th, zp, int(io), _stream(stream), out, yp), "tk_quadratic_form_batch")
+    return list(out)
+
+
 def tk_grid_eval(ctx: int, kernel: tk_kernel, grid: tk_grid, prec: int, A, stream=None) -> None:
     _check(_lib.tk_grid_eval(ctx, ctypes.byref(kernel), ctypes.byref(grid), int(prec), _ptr(A), _stream(stream)),
            "tk_grid_eval")
@@ -401,6 +413,9 @@ class Context:
 
     def quadratic_form(self, t: Tucker, z, io=TK_FP32, stream=None, y=None) -> float:
         return tk_quadratic_form(self.handle, t.handle, z, io, stream, y)
+
+    def quadratic_form_batch(self, ts, zs, io=TK_FP32, stream=None, ys=None):
+        return tk_quadratic_form_batch(self.handle, [t.handle for t in ts], zs, io, stream, ys)
 
     def budget(self):
         return tk_ctx_budget(self.handle)

@@ -352,3 +352,26 @@ def test_matvec_fft_matches_oracle_and_dense(ctx, tk, oracle, layout, n):
     ctx.set_matvec_method(tk.TK_MV_AUTO)
     for name in outs:
         assert np.all(np.abs(outs[name] - want) <= 2e-5 * bound), name
+
+
+def test_quadratic_form_batch_matches_single(ctx, tk):
+    """The batch runs its items concurrently on the worker streams; every value (and y, when
+    given) is bitwise the single call's."""
+    opts = tk.make_opts(eps=1e-6, hooi_sweeps=2, prec=1)
+    ts = [ctx.compress(tk.make_kernel(0, nu=nu, ell=ell), tk.make_grid(n, 1.0, lay), opts)
+          for (n, nu, ell, lay) in [(64, 0.5, 0.2, 1), (96, 1.5, 0.3, 1), (65, 2.5, 0.5, 0), (64, 1.5, 1.0, 1)]]
+    zs = [dev(synth.normal_vector(t.cov_dims(), 40 + i)) for i, t in enumerate(ts)]
+    single, ys_single = [], []
+    for t, z in zip(ts, zs):
+        y = torch.empty_like(z)
+        single.append(ctx.quadratic_form(t, z, y=y))
+        ys_single.append(host(y))
+    for workers in (4, 2):
+        ctx.set_workers(workers)
+        assert ctx.quadratic_form_batch(ts, zs) == single
+        ys = [torch.empty_like(z) for z in zs]
+        assert ctx.quadratic_form_batch(ts, zs, ys=ys) == single
+        assert all(np.array_equal(host(y), ya) for y, ya in zip(ys, ys_single))
+    ctx.set_workers(4)
+    for t in ts:
+        t.free()
