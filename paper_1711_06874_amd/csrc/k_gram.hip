@@ -35,6 +35,31 @@ struct Unfold {
         if (MODE == 1) { long i0 = Kg / n2; return i0 * n1n2 + (long)row * n2 + (Kg - i0 * n2); }
         return Kg * n2 + row;
     }
+    __device__ __forceinline__ long rowstride() const { return MODE == 0 ? n1n2 : (long)n2; }
+};
+
+// Column cursor of modes 0 and 1, where every load of a thread reads one column Kg (rows vary)
+// and Kg advances by BK per chunk: the column's base address without a division per chunk
+// (mode 1: Kg = q n2 + r, base = q n1 n2 + r).
+template <int MODE>
+struct KCursor {
+    long q;
+    int r;
+    __device__ __forceinline__ void init(const Unfold<MODE>& u, long Kg)
+    {
+        if (MODE == 1) { q = Kg / u.n2; r = (int)(Kg - q * u.n2); }
+        else { q = Kg; r = 0; }
+    }
+    __device__ __forceinline__ long base(const Unfold<MODE>& u) const { return MODE == 1 ? q * u.n1n2 + r : q; }
+    __device__ __forceinline__ void advance(const Unfold<MODE>& u, int step)
+    {
+        if (MODE == 1) {
+            r += step;
+            while (r >= u.n2) { r -= u.n2; ++q; }
+        } else {
+            q += step;
+        }
+    }
 };
 
 // Map a tile-pair index to (ti, tj) with ti <= tj, row-major over the upper triangle.
@@ -60,8 +85,11 @@ __global__ void __launch_bounds__(NT) k_gram_tiles(const T* __restrict__ A, Unfo
     A = bshift(A, bs);
     partials = bshift(partials, bs);
     const int tid = threadIdx.x;
-    const int split = blockIdx.x % nsplit;
-    const int pidx = blockIdx.x / nsplit;
+    // split-major order: the work-groups resident together share one K range, so each row tile
+    // of that range is fetched from memory once and re-read by its other pairs from cache
+    const int npairs = T_tiles * (T_tiles + 1) / 2;
+    const int split = blockIdx.x / npairs;
+    const int pidx = blockIdx.x - split * npairs;
     int ti, tj;
     pair_of(pidx, T_tiles, ti, tj);
     const bool diag = (ti == tj);
@@ -85,16 +113,23 @@ __global__ void __launch_bounds__(NT) k_gram_tiles(const T* __restrict__ A, Unfo
         for (int v = 0; v < (sizeof(T) == 8 ? 4 : 16); ++v) acc[q][v] = 0;
 
     T ra[PER], rb[PER];
+    KCursor<MODE> cur;
+    if (MODE != 2) cur.init(u, kbeg + lk);
+    const long rs = u.rowstride();
     auto gload = [&](long k0) {
+        const long cb = (MODE != 2) ? cur.base(u) : 0;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             int m = lm + e * mstep, kk = lk + e * kstep;
             long Kg = k0 + kk;
             bool kin = Kg < kend;
             int rowa = r0a + m, rowb = r0b + m;
-            ra[e] = (kin && rowa < nrow) ? A[u.addr(rowa, Kg)] : (T)0;
-            if (!diag) rb[e] = (kin && rowb < nrow) ? A[u.addr(rowb, Kg)] : (T)0;
+            const long aa = (MODE != 2) ? cb + (long)rowa * rs : u.addr(rowa, Kg);
+            const long ab = (MODE != 2) ? cb + (long)rowb * rs : u.addr(rowb, Kg);
+            ra[e] = (kin && rowa < nrow) ? A[aa] : (T)0;
+            if (!diag) rb[e] = (kin && rowb < nrow) ? A[ab] : (T)0;
         }
+        if (MODE != 2) cur.advance(u, BK);
     };
     auto sstore = [&]() {
 #pragma unroll
@@ -172,8 +207,11 @@ __global__ void __launch_bounds__(NT) k_gram_tiles_bf16x3(const float* __restric
     A = bshift(A, bs);
     partials = bshift(partials, bs);
     const int tid = threadIdx.x;
-    const int split = blockIdx.x % nsplit;
-    const int pidx = blockIdx.x / nsplit;
+    // split-major order: the work-groups resident together share one K range, so each row tile
+    // of that range is fetched from memory once and re-read by its other pairs from cache
+    const int npairs = T_tiles * (T_tiles + 1) / 2;
+    const int split = blockIdx.x / npairs;
+    const int pidx = blockIdx.x - split * npairs;
     int ti, tj;
     pair_of(pidx, T_tiles, ti, tj);
     const bool diag = (ti == tj);
@@ -191,16 +229,23 @@ __global__ void __launch_bounds__(NT) k_gram_tiles_bf16x3(const float* __restric
     f32x16 acc;
     for (int v = 0; v < 16; ++v) acc[v] = 0.f;
     float ra[PER], rb[PER];
+    KCursor<MODE> cur;
+    if (MODE != 2) cur.init(u, kbeg + lk);
+    const long rs = u.rowstride();
     auto gload = [&](long k0) {
+        const long cb = (MODE != 2) ? cur.base(u) : 0;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             int m = lm + e * mstep, kk = lk + e * kstep;
             long Kg = k0 + kk;
             bool kin = Kg < kend;
             int rowa = r0a + m, rowb = r0b + m;
-            ra[e] = (kin && rowa < nrow) ? A[u.addr(rowa, Kg)] : 0.f;
-            if (!diag) rb[e] = (kin && rowb < nrow) ? A[u.addr(rowb, Kg)] : 0.f;
+            const long aa = (MODE != 2) ? cb + (long)rowa * rs : u.addr(rowa, Kg);
+            const long ab = (MODE != 2) ? cb + (long)rowb * rs : u.addr(rowb, Kg);
+            ra[e] = (kin && rowa < nrow) ? A[aa] : 0.f;
+            if (!diag) rb[e] = (kin && rowb < nrow) ? A[ab] : 0.f;
         }
+        if (MODE != 2) cur.advance(u, BK);
     };
     auto sstore = [&]() {
 #pragma unroll
