@@ -139,6 +139,9 @@ __global__ void __launch_bounds__(256) k_ttm_first(const float* __restrict__ A, 
 // are double and the reconstruction runs on mfma_f64_16x16x4 (D[i][j] at lane j + 16 (i%4),
 // register i/4), so the measured error has no FP32 arithmetic floor.
 // H: rows x r (ld r), U3: n2 x r (ld r); the contraction runs over r rounded up to 4.
+// Wave w reconstructs rows 16w..16w+15 of the tile: its H fragments stay in registers for the
+// whole work-group, the U3^T chunk of 64 columns is staged in LDS, and the A values of the
+// next chunk are loaded into registers while the current chunk is multiplied.
 template <int NB>
 __global__ void __launch_bounds__(256) k_recon_diff(const float* __restrict__ A, long rows, int n2,
                                                     const double* __restrict__ H, const double* __restrict__ U3,
@@ -148,41 +151,66 @@ __global__ void __launch_bounds__(256) k_recon_diff(const float* __restrict__ A,
     H = bshift(H, bs);
     U3 = bshift(U3, bs);
     partials = bshift(partials, bs);
-    __shared__ double Hs[TR][NB * 16 + 1];     // [row][c]
-    __shared__ double Ut[NB * 16][TR + 1];     // [c][k] for a 64-column chunk of U3^T
+    constexpr int KC = NB * 16;                // contraction capacity (zero beyond r)
+    constexpr int KS = KC / 4;                 // MFMA k-steps at most
+    __shared__ double Ut[KC][TR + 1];          // [c][k] for a 64-column chunk of U3^T
     __shared__ double red[2][4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const long row0 = (long)blockIdx.x * TR;
-    const int r4 = (r + 3) & ~3;
-    for (int e = tid; e < TR * NB * 16; e += 256) {
-        int i = e / (NB * 16), c = e % (NB * 16);
-        long row = row0 + i;
-        Hs[i][c] = (row < rows && c < r) ? H[row * r + c] : 0.0;
+    const int ks_n = ((r + 3) & ~3) / 4;
+    // A operand (H): row 16w + lane%16, contraction index 4 ks + lane/16
+    double af[KS];
+    {
+        const long row = row0 + 16 * w + (lane & 15);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int c = 4 * ks + (lane >> 4);
+            af[ks] = (row < rows && c < r) ? H[row * r + c] : 0.0;
+        }
     }
+    // this lane's A values: rows 16w + 4v + lane/16, columns 16cb + lane%16 of the chunk
+    float xa[16];
+    auto load_x = [&](int k0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const long row = row0 + 16 * w + 4 * v + (lane >> 4);
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+                const int col = k0 + 16 * cb + (lane & 15);
+                xa[v * 4 + cb] = (row < rows && col < n2) ? A[row * n2 + col] : 0.f;
+            }
+        }
+    };
     double d2 = 0.0, a2 = 0.0;
+    load_x(0);
     for (int k0 = 0; k0 < n2; k0 += TR) {
         __syncthreads();
-        for (int e = tid; e < TR * NB * 16; e += 256) {
-            int kk = e / (NB * 16), c = e % (NB * 16);
+        for (int e = tid; e < TR * KC; e += 256) {
+            const int kk = e / KC, c = e % KC;
             Ut[c][kk] = (k0 + kk < n2 && c < r) ? U3[(long)(k0 + kk) * r + c] : 0.0;
         }
         __syncthreads();
-        // wave w: rows 16w..16w+15 of the tile, 4 column blocks of 16
+        float xc[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) xc[q] = xa[q];
+        if (k0 + TR < n2) load_x(k0 + TR);     // in flight while this chunk is multiplied
 #pragma unroll
         for (int cb = 0; cb < TR / 16; ++cb) {
             f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-            for (int ks = 0; ks < r4; ks += 4) {
-                double a = Hs[16 * w + (lane & 15)][ks + (lane >> 4)];
-                double b = Ut[ks + (lane >> 4)][16 * cb + (lane & 15)];
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                if (ks < ks_n) {
+                    const double b = Ut[4 * ks + (lane >> 4)][16 * cb + (lane & 15)];
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks], b, acc, 0, 0, 0);
+                }
             }
-            int col = k0 + 16 * cb + (lane & 15);
+            const int col = k0 + 16 * cb + (lane & 15);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                long row = row0 + 16 * w + 4 * v + (lane >> 4);
+                const long row = row0 + 16 * w + 4 * v + (lane >> 4);
                 if (row < rows && col < n2) {
-                    double x = (double)A[row * n2 + col];
-                    double d = x - acc[v];
+                    const double x = (double)xc[v * 4 + cb];
+                    const double d = x - acc[v];
                     d2 += d * d;
                     a2 += x * x;
                 }
