@@ -113,6 +113,8 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
+    # tile shapes: the Gram split count of each mode, tuned for this grid and precision (untimed)
+    tuned = ctx.autotune(grid, prec, stream)
     grids = [grid] * len(tkernels)
     lat = {"compress_batch": [], "quadform_batch": [], "trace": []}
     ranks_seen = []
@@ -250,6 +252,7 @@ def main():
         "max_rel_err": max(e for _, e in ranks_seen),
         "roofline": roofline,
         "kernels": kernels_out,
+        "gram_autotune": {"nsplit_per_mode": list(tuned["nsplit"]), "ms_per_mode": list(tuned["ms"])},
     }
     ctx.destroy()
     if not args.no_cpu_baseline:

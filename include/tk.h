@@ -179,6 +179,21 @@ tk_status tk_compress_batch(tk_ctx *ctx, int count, const tk_kernel *kernels,
 tk_status tk_compress_group(tk_ctx *ctx, int count, const tk_kernel *kernels, const tk_grid *grid,
                             const tk_opts *opts, void *hip_stream, tk_tucker **outs, int *statuses);
 
+/* Autotuning of the Gram contraction: for grids of grid->n and precision prec, times each mode's
+ * Gram with its default number of K chunks per 64 x 64 tile pair and with half and a quarter of
+ * it (on a synthetic tensor of that shape, on hip_stream) and keeps the fastest in the context.
+ * Later compressions of that shape and precision, alone or batched, use it (so batched and
+ * single results stay bitwise equal; untuned shapes keep the default).  nsplit_out / ms_out
+ * (optional): the chosen counts and their times per mode.  Synchronising.
+ * Errors: TK_EINVAL, TK_ENOMEM, TK_EHIP. */
+tk_status tk_autotune(tk_ctx *ctx, const tk_grid *grid, int prec, void *hip_stream, int nsplit_out[3],
+                      double ms_out[3]);
+/* Write / read the context's tuned entries as JSON ({"format": "tk-autotune-1", "entries":
+ * [{"n": [n0, n1, n2], "mode": k, "prec": p, "nsplit": s}, ...]}); loading adds to (and
+ * overrides) the entries present.  Errors: TK_EINVAL (unreadable or malformed file). */
+tk_status tk_autotune_save(tk_ctx *ctx, const char *path);
+tk_status tk_autotune_load(tk_ctx *ctx, const char *path);
+
 /* Workspaces: each call takes its device workspace from a block the context keeps per HIP
  * stream, grown when a call needs more and reused by the next call on that stream, so calls in
  * steady state allocate nothing.  The budget charges each call's workspace while the call runs;

@@ -48,6 +48,7 @@ def main():
     ap.add_argument("--reps", type=int, default=3, help="timed batch calls per worker count")
     ap.add_argument("--no-seq", action="store_true", help="skip the 256 sequential calls")
     ap.add_argument("--profile", action="store_true", help="per-class kernel times of one batch call")
+    ap.add_argument("--autotune", action="store_true", help="tune the Gram split of every size first")
     args = ap.parse_args()
 
     import torch
@@ -69,6 +70,9 @@ def main():
               "workload": "256 Matern tensors, n uniform over {32,...,256}, centred grids, eps 1e-6"}
     ctx = tk.Context(0)
     try:
+        if args.autotune:
+            common["gram_autotune"] = {str(n): ctx.autotune(tk.make_grid(n, 1.0, 0), prec)["nsplit"]
+                                       for n in sorted(set(sizes))}
         # warm-up: one batch call (kernels loaded, workspaces pooled)
         for t in ctx.compress_batch(kernels, grids, opts):
             t.free()

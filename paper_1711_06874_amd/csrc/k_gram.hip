@@ -323,7 +323,7 @@ struct GramPlan {
     long K, kchunk;
 };
 
-GramPlan make_plan(const int n[3], int mode, int BK)
+GramPlan make_plan(const int n[3], int mode, int BK, int nsplit_req = 0)
 {
     GramPlan p;
     long N = (long)n[0] * n[1] * n[2];
@@ -334,6 +334,7 @@ GramPlan make_plan(const int n[3], int mode, int BK)
     long want = (2048 + p.npairs - 1) / p.npairs;               // ~2048 work-groups
     if (want > (p.K + 63) / 64) want = (p.K + 63) / 64;          // but at least 64 of K each
     long maxsplit = (p.K + BK - 1) / BK;
+    if (nsplit_req > 0) want = nsplit_req;                      // a tuned split count
     long s = want < maxsplit ? want : maxsplit;
     if (s < 1) s = 1;
     long kc = (p.K + s - 1) / s;
@@ -349,18 +350,23 @@ int bk_for(int prec) { return prec == 0 ? BK_F64 : (prec == 1 ? BK_F32 : BK_BF);
 
 }  // namespace
 
-size_t gram_work_bytes(const int n[3], int mode, int prec)
+int gram_default_splits(const int n[3], int mode, int prec)
 {
-    GramPlan p = make_plan(n, mode, bk_for(prec));
+    return make_plan(n, mode, bk_for(prec)).nsplit;
+}
+
+size_t gram_work_bytes(const int n[3], int mode, int prec, int nsplit)
+{
+    GramPlan p = make_plan(n, mode, bk_for(prec), nsplit);
     size_t elt = (prec == 0) ? 8 : 4;
     return (size_t)p.npairs * p.nsplit * BM * BM * elt;
 }
 
 template <int MODE>
 static hipError_t launch_mode(const void* A, const int n[3], int prec, double* G, void* work, hipStream_t s,
-                              Bat bt)
+                              Bat bt, int nsplit)
 {
-    GramPlan p = make_plan(n, MODE, bk_for(prec));
+    GramPlan p = make_plan(n, MODE, bk_for(prec), nsplit);
     Unfold<MODE> u;
     u.n1n2 = (long)n[1] * n[2];
     u.n1 = n[1];
@@ -389,12 +395,12 @@ static hipError_t launch_mode(const void* A, const int n[3], int prec, double* G
 }
 
 hipError_t launch_gram(const void* A, const int n[3], int mode, int prec, double* G, void* work,
-                       hipStream_t s, Bat bt)
+                       hipStream_t s, Bat bt, int nsplit)
 {
     if (bt.nb < 1) return hipErrorInvalidValue;
-    if (mode == 0) return launch_mode<0>(A, n, prec, G, work, s, bt);
-    if (mode == 1) return launch_mode<1>(A, n, prec, G, work, s, bt);
-    return launch_mode<2>(A, n, prec, G, work, s, bt);
+    if (mode == 0) return launch_mode<0>(A, n, prec, G, work, s, bt, nsplit);
+    if (mode == 1) return launch_mode<1>(A, n, prec, G, work, s, bt, nsplit);
+    return launch_mode<2>(A, n, prec, G, work, s, bt, nsplit);
 }
 
 }  // namespace tk

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -152,6 +153,9 @@ struct tk_ctx {
     };
     std::mutex ws_mu;
     std::map<std::pair<hipStream_t, int>, WsBlock> ws;
+    // autotuned Gram split counts, key {n0, n1, n2, mode, prec}
+    std::mutex tune_mu;
+    std::map<std::array<int, 5>, int> tune;
 };
 
 struct tk_tucker {
@@ -324,6 +328,7 @@ struct Plan {
     double eps;
     int sweeps;
     bool cubic;
+    int gsplit[3];     // K chunks per tile pair of the Gram of A per mode (0: default)
 };
 
 tk_status make_plan(const tk_grid* g, const tk_opts* o, Plan* P)
@@ -353,7 +358,19 @@ tk_status make_plan(const tk_grid* g, const tk_opts* o, Plan* P)
         P->p[k] = (g->n[k] <= EIG_PMAX) ? g->n[k] : ((P->R[k] + 8 < EIG_PMAX) ? P->R[k] + 8 : EIG_PMAX);
     }
     P->cubic = (g->n[0] == g->n[1] && g->n[1] == g->n[2]);
+    for (int k = 0; k < 3; ++k) P->gsplit[k] = 0;
     return TK_OK;
+}
+
+// The tuned Gram split counts of the context for P's shape and precision (if any).
+void apply_tuning(tk_ctx* ctx, Plan* P)
+{
+    std::lock_guard<std::mutex> g(ctx->tune_mu);
+    if (ctx->tune.empty()) return;
+    for (int k = 0; k < 3; ++k) {
+        auto it = ctx->tune.find({P->n[0], P->n[1], P->n[2], k, P->prec});
+        if (it != ctx->tune.end()) P->gsplit[k] = it->second;
+    }
 }
 
 // Device workspace of one compression.
@@ -393,7 +410,7 @@ void layout_work(Arena& ar, const Plan& P, bool own_A, Work& w)
     int Rmax = std::max(R[0], std::max(R[1], R[2]));
     w.A = own_A ? (void*)ar.take<char>(N * esz) : nullptr;
     size_t gw = 0;
-    for (int k = 0; k < 3; ++k) gw = std::max(gw, gram_work_bytes(n, k, P.prec));
+    for (int k = 0; k < 3; ++k) gw = std::max(gw, gram_work_bytes(n, k, P.prec, P.gsplit[k]));
     {
         // the FP64 projected Grams of the HOOI sweep and the core Grams use the same workspace
         const int R0 = P.R[0], R1 = P.R[1], R2 = P.R[2];
@@ -976,7 +993,7 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void
     // ---- HOSVD: Grams and leading eigenvectors
     for (int k = 0; k < 3; ++k) {
         ProfScope ps(TK_PROF_GRAM, s);
-        TK_LAUNCH(launch_gram(A, P.n, k, P.prec, w.G + (long)k * nmax * nmax, w.gram_work, s, w.bt));
+        TK_LAUNCH(launch_gram(A, P.n, k, P.prec, w.G + (long)k * nmax * nmax, w.gram_work, s, w.bt, P.gsplit[k]));
     }
     if ((st = eig_modes(P, w, nmax, s)) != TK_OK) return st;
 
@@ -1107,6 +1124,7 @@ tk_status compress_any(tk_ctx* ctx, const tk_kernel* kernel, const void* A_in, c
     if (!A_in && (st = check_kernel(kernel, &kp)) != TK_OK) return st;
     Plan P;
     if ((st = make_plan(grid, opts, &P)) != TK_OK) return st;
+    apply_tuning(ctx, &P);
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(TK_EHIP, "hipSetDevice(%d) failed", ctx->device);
     (void)hipGetLastError();   // drop errors left by earlier, unrelated HIP calls
     hipStream_t s = (hipStream_t)stream;
@@ -1128,6 +1146,7 @@ tk_status compress_group(tk_ctx* ctx, const tk_kernel* const* kernels, int nb, c
         if ((st = check_kernel(kernels[b], &kps[b])) != TK_OK) return st;
     Plan P;
     if ((st = make_plan(grid, opts, &P)) != TK_OK) return st;
+    apply_tuning(ctx, &P);
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(TK_EHIP, "hipSetDevice(%d) failed", ctx->device);
     (void)hipGetLastError();
     if (P.prec == TK_FP64) return compress_impl<double>(ctx, kps, nb, nullptr, grid, P, s, outs, sts);
@@ -1497,6 +1516,119 @@ void tk_ctx_destroy(tk_ctx* ctx)
         now = (ctx->live_results == 0);
     }
     if (now) delete ctx;
+}
+
+tk_status tk_autotune(tk_ctx* ctx, const tk_grid* grid, int prec, void* hip_stream, int nsplit_out[3],
+                      double ms_out[3])
+{
+    if (!ctx || !grid) return fail(TK_EINVAL, "NULL argument");
+    if (prec < TK_FP64 || prec > TK_BF16X3) return fail(TK_EINVAL, "unknown precision %d", prec);
+    tk_status st;
+    if ((st = check_grid(grid)) != TK_OK) return st;
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int* n = grid->n;
+    const size_t N = (size_t)n[0] * n[1] * n[2];
+    const size_t esz = prec == TK_FP64 ? 8 : 4;
+    const int nmax = std::max(n[0], std::max(n[1], n[2]));
+    size_t wb = 0;
+    for (int k = 0; k < 3; ++k) wb = std::max(wb, gram_work_bytes(n, k, prec));   // the largest candidate
+    const size_t need = align_up(N * esz, 256) + align_up(sizeof(double) * nmax * nmax, 256) + wb;
+    Reservation res(ctx, need);
+    if (!res.take()) return fail(TK_ENOMEM, "autotune needs %zu bytes", need);
+    Ws wsp;
+    TK_HIP(ws_get(ctx, s, 0, need, wsp));
+    char* base = (char*)wsp.p;
+    void* A = base;
+    double* G = (double*)(base + align_up(N * esz, 256));
+    void* work = base + align_up(N * esz, 256) + align_up(sizeof(double) * nmax * nmax, 256);
+    // a Matern 3/2 covariance on the grid (the timing does not depend on the values)
+    tk_kernel kk{};
+    kk.family = TK_MATERN; kk.nu = 1.5; kk.ell = 0.3; kk.sigma2 = 1.0; kk.alpha = 1.0; kk.p = 1.0;
+    KernelParams kp{};
+    if ((st = check_kernel(&kk, &kp)) != TK_OK) return st;
+    GridAxes ax = axes_of(grid);
+    if (esz == 4) TK_LAUNCH(launch_grid_eval_f32((float*)A, ax, &kp, s));
+    else TK_LAUNCH(launch_grid_eval_f64((double*)A, ax, &kp, s));
+    hipEvent_t e0, e1;
+    TK_HIP(hipEventCreate(&e0));
+    TK_HIP(hipEventCreate(&e1));
+    for (int k = 0; k < 3; ++k) {
+        const int s0 = gram_default_splits(n, k, prec);
+        int cand[3] = {s0, std::max(1, s0 / 2), std::max(1, s0 / 4)};
+        int best = s0;
+        float best_ms = 1e30f;
+        for (int c = 0; c < 3; ++c) {
+            if (c > 0 && cand[c] == cand[c - 1]) continue;
+            TK_LAUNCH(launch_gram(A, n, k, prec, G, work, s, Bat(), cand[c]));   // warm-up
+            TK_HIP(hipEventRecord(e0, s));
+            for (int rep = 0; rep < 5; ++rep) TK_LAUNCH(launch_gram(A, n, k, prec, G, work, s, Bat(), cand[c]));
+            TK_HIP(hipEventRecord(e1, s));
+            TK_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            TK_HIP(hipEventElapsedTime(&ms, e0, e1));
+            ms /= 5.f;
+            if (ms < best_ms) { best_ms = ms; best = cand[c]; }
+        }
+        {
+            std::lock_guard<std::mutex> g(ctx->tune_mu);
+            ctx->tune[{n[0], n[1], n[2], k, prec}] = best;
+        }
+        if (nsplit_out) nsplit_out[k] = best;
+        if (ms_out) ms_out[k] = best_ms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return TK_OK;
+}
+
+tk_status tk_autotune_save(tk_ctx* ctx, const char* path)
+{
+    if (!ctx || !path) return fail(TK_EINVAL, "NULL argument");
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(TK_EINVAL, "cannot write %s", path);
+    std::lock_guard<std::mutex> g(ctx->tune_mu);
+    std::fprintf(f, "{\"format\": \"tk-autotune-1\", \"entries\": [");
+    bool first = true;
+    for (const auto& kv : ctx->tune) {
+        std::fprintf(f, "%s\n  {\"n\": [%d, %d, %d], \"mode\": %d, \"prec\": %d, \"nsplit\": %d}", first ? "" : ",",
+                     kv.first[0], kv.first[1], kv.first[2], kv.first[3], kv.first[4], kv.second);
+        first = false;
+    }
+    std::fprintf(f, "\n]}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok ? TK_OK : fail(TK_EINVAL, "cannot write %s", path);
+}
+
+tk_status tk_autotune_load(tk_ctx* ctx, const char* path)
+{
+    if (!ctx || !path) return fail(TK_EINVAL, "NULL argument");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(TK_EINVAL, "cannot read %s", path);
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+    std::fclose(f);
+    if (text.find("\"tk-autotune-1\"") == std::string::npos) return fail(TK_EINVAL, "%s is not an autotune file", path);
+    std::map<std::array<int, 5>, int> add;
+    size_t pos = 0;
+    while ((pos = text.find("{\"n\":", pos)) != std::string::npos) {
+        int a, b, c, mode, prec, ns;
+        const size_t end = text.find('}', pos);
+        if (end == std::string::npos) break;
+        const std::string obj = text.substr(pos, end - pos + 1);
+        if (std::sscanf(obj.c_str(), "{\"n\": [%d, %d, %d], \"mode\": %d, \"prec\": %d, \"nsplit\": %d}", &a, &b, &c,
+                        &mode, &prec, &ns) != 6 ||
+            a < 1 || b < 1 || c < 1 || mode < 0 || mode > 2 || prec < TK_FP64 || prec > TK_BF16X3 || ns < 1)
+            return fail(TK_EINVAL, "%s: bad entry %s", path, obj.c_str());
+        add[{a, b, c, mode, prec}] = ns;
+        pos = end;
+    }
+    std::lock_guard<std::mutex> g(ctx->tune_mu);
+    for (const auto& kv : add) ctx->tune[kv.first] = kv.second;
+    return TK_OK;
 }
 
 tk_status tk_ctx_release_stream(tk_ctx* ctx, void* hip_stream)

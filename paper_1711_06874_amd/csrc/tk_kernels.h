@@ -36,10 +36,13 @@ hipError_t launch_grid_eval_f64(double* A, const GridAxes& g, const KernelParams
 
 // ----------------------------------------------------------------- a2: Gram (SYRK) ----
 // G (n_mode x n_mode, double, full) = A_(mode) A_(mode)^T.  `work` must hold
-// gram_work_bytes(...) bytes.
-size_t gram_work_bytes(const int n[3], int mode, int prec);
+// gram_work_bytes(...) bytes.  nsplit: the number of K chunks per tile pair (0: the default
+// for the shape, gram_default_splits); the partial sums of the chunks are added in FP64 in
+// chunk order, so a given split count gives the same result every time.
+int gram_default_splits(const int n[3], int mode, int prec);
+size_t gram_work_bytes(const int n[3], int mode, int prec, int nsplit = 0);
 hipError_t launch_gram(const void* A, const int n[3], int mode, int prec, double* G, void* work,
-                       hipStream_t s, Bat bt = Bat());
+                       hipStream_t s, Bat bt = Bat(), int nsplit = 0);
 
 // ------------------------------------------------------------ small dense products ----
 // C[b](m,n) = alpha * sum_k A[b](m,k) B[b](k,n) + beta * C[b](m,n) with arbitrary element

@@ -90,6 +90,9 @@ _SIGS = {
     "tk_gram": (_st, [_vp, _vp, _ip, ctypes.c_int, ctypes.c_int, _vp, _vp]),
     "tk_eig_topr": (_st, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "tk_set_matvec_method": (_st, [_vp, ctypes.c_int]),
+    "tk_autotune": (_st, [_vp, ctypes.POINTER(tk_grid), ctypes.c_int, _vp, _ip, _dp]),
+    "tk_autotune_save": (_st, [_vp, ctypes.c_char_p]),
+    "tk_autotune_load": (_st, [_vp, ctypes.c_char_p]),
     "tk_ctx_release_stream": (_st, [_vp, _vp]),
     "tk_ctx_set_workers": (_st, [_vp, ctypes.c_int]),
     "tk_quadratic_form_batch": (_st, [_vp, ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, _vp,
@@ -422,6 +425,20 @@ class Context:
 
     def set_matvec_method(self, method: int):
         tk_set_matvec_method(self.handle, method)
+
+    def autotune(self, grid, prec, stream=None):
+        """Tune the Gram split of each mode for this grid shape and precision; returns
+        {"nsplit": (s0, s1, s2), "ms": (t0, t1, t2)}."""
+        ns = (ctypes.c_int * 3)()
+        ms = (ctypes.c_double * 3)()
+        _check(_lib.tk_autotune(self.handle, ctypes.byref(grid), int(prec), _stream(stream), ns, ms), "tk_autotune")
+        return {"nsplit": tuple(ns), "ms": tuple(ms)}
+
+    def autotune_save(self, path: str):
+        _check(_lib.tk_autotune_save(self.handle, str(path).encode()), "tk_autotune_save")
+
+    def autotune_load(self, path: str):
+        _check(_lib.tk_autotune_load(self.handle, str(path).encode()), "tk_autotune_load")
 
     def release_stream(self, stream):
         _check(_lib.tk_ctx_release_stream(self.handle, _stream(stream)), "tk_ctx_release_stream")

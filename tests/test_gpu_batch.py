@@ -186,3 +186,48 @@ def test_concurrent_large_n_matches_single(tk):
                     t.free()
     finally:
         ctx.destroy()
+
+
+def test_autotune_keeps_batch_equal_single_and_roundtrips(tk, tmp_path):
+    """Tuned Gram split counts apply to single and batched calls alike (bitwise equal), meet eps,
+    and a saved table gives a second context the same results."""
+    require_gpu()
+    g = tk.make_grid(96, 1.0, 1)
+    opts = tk.make_opts(eps=1e-6, hooi_sweeps=2, prec=1)
+    ks = [tk.make_kernel(0, nu=nu, ell=ell) for nu, ell in [(0.5, 0.1), (1.5, 0.3), (2.5, 0.6), (1.5, 0.05)]]
+    ctx = tk.Context(0)
+    try:
+        for prec in (1, 2):
+            r = ctx.autotune(g, prec)
+            say("autotune prec", prec, r)
+            assert all(s >= 1 for s in r["nsplit"]) and all(m > 0 for m in r["ms"])
+        ref = []
+        for k in ks:
+            t = ctx.compress(k, g, opts)
+            assert t.rel_err <= 1e-6
+            ref.append((t.ranks, t.rel_err, t.factors()))
+            t.free()
+        mix = ctx.compress_batch(ks, [g] * len(ks), opts)
+        for i, (t, (rk, e, (U, C))) in enumerate(zip(mix, ref)):
+            Ub, Cb = t.factors()
+            assert t.ranks == rk and t.rel_err == e and np.array_equal(Cb, C), f"item {i}"
+            assert all(np.array_equal(x, y) for x, y in zip(U, Ub)), f"item {i}"
+            t.free()
+        path = tmp_path / "tune.json"
+        ctx.autotune_save(str(path))
+        bad = tmp_path / "bad.json"
+        bad.write_text('{"format": "tk-autotune-1", "entries": [{"n": [96, 96], "mode": 0}]}')
+        ctx2 = tk.Context(0)
+        try:
+            with pytest.raises(tk.TkError):
+                ctx2.autotune_load(str(bad))
+            ctx2.autotune_load(str(path))
+            for k, (rk, e, (U, C)) in zip(ks, ref):
+                t = ctx2.compress(k, g, opts)
+                Ub, Cb = t.factors()
+                assert t.ranks == rk and t.rel_err == e and np.array_equal(Cb, C)
+                t.free()
+        finally:
+            ctx2.destroy()
+    finally:
+        ctx.destroy()
