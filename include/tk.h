@@ -203,6 +203,16 @@ tk_status tk_autotune_load(tk_ctx *ctx, const char *path);
  * Errors: TK_EINVAL (ctx NULL, a call on the stream still running), TK_EHIP. */
 tk_status tk_ctx_release_stream(tk_ctx *ctx, void *hip_stream);
 
+/* Graph replay of the compression pipeline (off by default).  When on, the launches of a call
+ * that samples its own tensor (tk_compress, tk_compress_batch, tk_compress_group; not the FP64
+ * eps path, which reads ranks back between steps, and not while tk_profile_enable is on) are
+ * captured into a HIP graph the first time a shape, option set and problem count meets a given
+ * workspace, and replayed on later calls with the sampling launch updated to the call's kernels
+ * and grid: one graph launch instead of some hundred kernel launches.  Results are bitwise those
+ * of the direct launches.  The context keeps at most 64 graphs (all dropped when more are
+ * needed) until tk_ctx_destroy.  Host only.  Errors: TK_EINVAL (ctx NULL). */
+tk_status tk_ctx_set_graphs(tk_ctx *ctx, int on);
+
 /* Number of worker streams / host workers tk_compress_batch uses (1..16; default 4, the
  * number of hardware queues a process gets by default).  Host only. */
 tk_status tk_ctx_set_workers(tk_ctx *ctx, int workers);

@@ -61,6 +61,39 @@ static hipError_t launch(T* A, const GridAxes& g, const KernelParams* kps, hipSt
     return hipGetLastError();
 }
 
+template <typename T>
+static void node_params(T* A, const GridAxes& g, const KernelParams* kps, Bat bt, GridEvalNode* nd)
+{
+    nd->A = A;
+    nd->g = g;
+    for (int b = 0; b < bt.nb; ++b) nd->kps.k[b] = kps[b];
+    nd->qpr = (g.n[2] + 3) / 4;
+    nd->total = (long)g.n[0] * g.n[1] * nd->qpr;
+    nd->bs = bt.bs;
+    nd->args[0] = &nd->A;
+    nd->args[1] = &nd->g;
+    nd->args[2] = &nd->kps;
+    nd->args[3] = &nd->total;
+    nd->args[4] = &nd->qpr;
+    nd->args[5] = &nd->bs;
+    nd->p.func = reinterpret_cast<void*>(&k_grid_eval<T>);
+    nd->p.gridDim = dim3((unsigned)((nd->total + 255) / 256), 1, bt.nb);
+    nd->p.blockDim = dim3(256);
+    nd->p.sharedMemBytes = 0;
+    nd->p.kernelParams = nd->args;
+    nd->p.extra = nullptr;
+}
+
+void grid_eval_node_f32(float* A, const GridAxes& g, const KernelParams* kps, Bat bt, GridEvalNode* nd)
+{
+    node_params(A, g, kps, bt, nd);
+}
+
+void grid_eval_node_f64(double* A, const GridAxes& g, const KernelParams* kps, Bat bt, GridEvalNode* nd)
+{
+    node_params(A, g, kps, bt, nd);
+}
+
 hipError_t launch_grid_eval_f32(float* A, const GridAxes& g, const KernelParams* kps, hipStream_t s, Bat bt)
 {
     return launch(A, g, kps, s, bt);

@@ -156,6 +156,15 @@ struct tk_ctx {
     // autotuned Gram split counts, key {n0, n1, n2, mode, prec}
     std::mutex tune_mu;
     std::map<std::array<int, 5>, int> tune;
+    // captured compression pipelines (tk_ctx_set_graphs), key: shape, options, batch, workspace
+    struct GraphEntry {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ex = nullptr;
+        hipGraphNode_t grid_node = nullptr;
+    };
+    bool graphs_on = false;
+    std::mutex graph_mu;
+    std::map<std::array<long, 19>, GraphEntry> graphs;
 };
 
 struct tk_tucker {
@@ -938,6 +947,82 @@ tk_status fill_result_from(tk_tucker* t, const double* const Usrc[3], const int 
     return TK_OK;
 }
 
+// Replay of a captured pipeline: the launches of `pipeline` are captured once per shape,
+// options, batch size and workspace address and replayed afterwards, with the grid evaluation
+// node updated to this call's kernel parameters.
+template <typename Real, typename F>
+tk_status run_captured(tk_ctx* ctx, const Plan& P, int nb, void* base, const tk_grid* grid, const KernelParams* kps,
+                       const Work& w, hipStream_t s, F& pipeline)
+{
+    std::array<long, 19> key{};
+    long epsbits = 0;
+    std::memcpy(&epsbits, &P.eps, sizeof(epsbits));
+    const long vals[19] = {P.n[0], P.n[1], P.n[2], P.R[0], P.R[1], P.R[2], P.p[0], P.p[1], P.p[2], P.prec,
+                           epsbits, P.sweeps, P.gsplit[0], P.gsplit[1], P.gsplit[2], nb,
+                           (long)(intptr_t)base, (long)sizeof(Real), P.eps_mode ? 1 : 0};
+    for (int i = 0; i < 19; ++i) key[i] = vals[i];
+    GridEvalNode nd;
+    const GridAxes ax = axes_of(grid);
+    if (sizeof(Real) == 4) grid_eval_node_f32((float*)w.A, ax, kps, w.bt, &nd);
+    else grid_eval_node_f64((double*)w.A, ax, kps, w.bt, &nd);
+    std::lock_guard<std::mutex> g(ctx->graph_mu);
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        if (ctx->graphs.size() >= 64) {
+            for (auto& kv : ctx->graphs) {
+                (void)hipGraphExecDestroy(kv.second.ex);
+                (void)hipGraphDestroy(kv.second.g);
+            }
+            ctx->graphs.clear();
+        }
+        // captured on a stream of its own (the caller's may be the null stream, which cannot
+        // capture); the graph then runs on the caller's stream
+        tk_ctx::GraphEntry e;
+        hipStream_t cs = nullptr;
+        TK_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipError_t be = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (be != hipSuccess) {
+            (void)hipStreamDestroy(cs);
+            return fail(TK_EHIP, "stream capture: %s", hipGetErrorString(be));
+        }
+        const tk_status st = pipeline(cs);
+        const hipError_t ce = hipStreamEndCapture(cs, &e.g);
+        (void)hipStreamDestroy(cs);
+        if (st != TK_OK) {
+            if (e.g) (void)hipGraphDestroy(e.g);
+            return st;
+        }
+        if (ce != hipSuccess) return fail(TK_EHIP, "stream capture: %s", hipGetErrorString(ce));
+        size_t cnt = 0;
+        TK_HIP(hipGraphGetNodes(e.g, nullptr, &cnt));
+        std::vector<hipGraphNode_t> nodes(cnt);
+        TK_HIP(hipGraphGetNodes(e.g, nodes.data(), &cnt));
+        for (hipGraphNode_t node : nodes) {
+            hipGraphNodeType t;
+            if (hipGraphNodeGetType(node, &t) != hipSuccess || t != hipGraphNodeTypeKernel) continue;
+            hipKernelNodeParams kp{};
+            if (hipGraphKernelNodeGetParams(node, &kp) == hipSuccess && kp.func == nd.p.func) {
+                e.grid_node = node;
+                break;
+            }
+        }
+        if (!e.grid_node) {
+            (void)hipGraphDestroy(e.g);
+            return fail(TK_EHIP, "captured pipeline has no grid evaluation node");
+        }
+        hipError_t ie = hipGraphInstantiate(&e.ex, e.g, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            (void)hipGraphDestroy(e.g);
+            return fail(TK_EHIP, "graph instantiation: %s", hipGetErrorString(ie));
+        }
+        it = ctx->graphs.emplace(key, e).first;
+    } else {
+        TK_HIP(hipGraphExecKernelNodeSetParams(it->second.ex, it->second.grid_node, &nd.p));
+    }
+    TK_HIP(hipGraphLaunch(it->second.ex, s));
+    return TK_OK;
+}
+
 // Bytes of nb workspaces of plan P laid out back to back (stride ws), plus the gather area of
 // the final readback.
 size_t batch_layout(const Plan& P, bool own_A, int nb, size_t* ws)
@@ -982,74 +1067,89 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void
     char* gather = (char*)base + ws * (size_t)nb;
     const int nmax = std::max(P.n[0], std::max(P.n[1], P.n[2]));
     const Real* A = own_A ? (const Real*)w.A : (const Real*)A_in;
-    tk_status st;
 
-    if (own_A) {
-        GridAxes ax = axes_of(grid);
-        ProfScope ps(TK_PROF_GRID, s);
-        if (sizeof(Real) == 4) TK_LAUNCH(launch_grid_eval_f32((float*)w.A, ax, kps, s, w.bt));
-        else TK_LAUNCH(launch_grid_eval_f64((double*)w.A, ax, kps, s, w.bt));
-    }
-    // ---- HOSVD: Grams and leading eigenvectors
-    for (int k = 0; k < 3; ++k) {
-        ProfScope ps(TK_PROF_GRAM, s);
-        TK_LAUNCH(launch_gram(A, P.n, k, P.prec, w.G + (long)k * nmax * nmax, w.gram_work, s, w.bt, P.gsplit[k]));
-    }
-    if ((st = eig_modes(P, w, nmax, s)) != TK_OK) return st;
-
-    if (P.eps_mode && P.prec == TK_FP64) {
-        // rank rule on the Gram eigenvalues: tail(r) = trace - sum_{i<r} lambda_i
-        TK_HIP(hipMemcpyAsync(w.scal, w.trace, sizeof(double), hipMemcpyDeviceToDevice, s));   // ||A||^2
-        TK_LAUNCH(launch_rank_rule(w.lam, 64, P.R[0], 1, w.trace, 1, w.scal, 0, P.eps * P.eps, w.ranks + 0,
-                                   w.ranks + 3, s));
-        TK_LAUNCH(launch_rank_rule(w.lam + 64, 64, P.R[1], 1, w.trace + 1, 1, w.scal, 0, P.eps * P.eps, w.ranks + 1,
-                                   w.ranks + 4, s));
-        TK_LAUNCH(launch_rank_rule(w.lam + 128, 64, P.R[2], 1, w.trace + 2, 1, w.scal, 0, P.eps * P.eps,
-                                   w.ranks + 2, w.ranks + 5, s));
-        int hr[6];
-        if ((st = readback(ctx, s, w.ranks, sizeof(hr), hr)) != TK_OK) return st;
-        // continue with the selected ranks: the leading columns of the factors are kept
-        Plan Q = P;
-        for (int k = 0; k < 3; ++k) Q.R[k] = hr[k];
-        for (int k = 0; k < 3; ++k) {
-            if (Q.R[k] != P.R[k]) {
-                TK_HIP(hipMemcpy2DAsync(w.Urot[k], sizeof(double) * Q.R[k], w.U[k], sizeof(double) * P.R[k],
-                                        sizeof(double) * Q.R[k], P.n[k], hipMemcpyDeviceToDevice, s));
-                TK_HIP(hipMemcpyAsync(w.U[k], w.Urot[k], sizeof(double) * Q.R[k] * P.n[k], hipMemcpyDeviceToDevice, s));
-            }
-            Q.p[k] = (P.n[k] <= EIG_PMAX) ? P.n[k] : std::min(Q.R[k] + 8, EIG_PMAX);
+    // the launches of the pipeline, from the grid evaluation to the final error (the FP64 eps
+    // path reads ranks back in between)
+    auto pipeline = [&](hipStream_t s) -> tk_status {
+        tk_status st;
+        if (own_A) {
+            GridAxes ax = axes_of(grid);
+            ProfScope ps(TK_PROF_GRID, s);
+            if (sizeof(Real) == 4) TK_LAUNCH(launch_grid_eval_f32((float*)w.A, ax, kps, s, w.bt));
+            else TK_LAUNCH(launch_grid_eval_f64((double*)w.A, ax, kps, s, w.bt));
         }
-        P = Q;
-    }
-    for (int k = 0; k < 3; ++k)
-        if ((st = refresh_u32<Real>(P, w, k, s)) != TK_OK) return st;
+        // ---- HOSVD: Grams and leading eigenvectors
+        for (int k = 0; k < 3; ++k) {
+            ProfScope ps(TK_PROF_GRAM, s);
+            TK_LAUNCH(launch_gram(A, P.n, k, P.prec, w.G + (long)k * nmax * nmax, w.gram_work, s, w.bt, P.gsplit[k]));
+        }
+        if ((st = eig_modes(P, w, nmax, s)) != TK_OK) return st;
 
-    // ---- HOOI sweeps, then the core
-    if (P.sweeps == 0) {
-        if ((st = hosvd_core<Real>(P, w, A, s)) != TK_OK) return st;
-    } else {
-        for (int it = 0; it < P.sweeps; ++it)
-            if ((st = hooi_sweep<Real>(P, w, A, nmax, s)) != TK_OK) return st;
-    }
-    // ---- reconstruction error
-    if ((st = recon_norm<Real>(P, w, A, w.U, w.core, s)) != TK_OK) return st;
+        if (P.eps_mode && P.prec == TK_FP64) {
+            // rank rule on the Gram eigenvalues: tail(r) = trace - sum_{i<r} lambda_i
+            TK_HIP(hipMemcpyAsync(w.scal, w.trace, sizeof(double), hipMemcpyDeviceToDevice, s));   // ||A||^2
+            TK_LAUNCH(launch_rank_rule(w.lam, 64, P.R[0], 1, w.trace, 1, w.scal, 0, P.eps * P.eps, w.ranks + 0,
+                                       w.ranks + 3, s));
+            TK_LAUNCH(launch_rank_rule(w.lam + 64, 64, P.R[1], 1, w.trace + 1, 1, w.scal, 0, P.eps * P.eps, w.ranks + 1,
+                                       w.ranks + 4, s));
+            TK_LAUNCH(launch_rank_rule(w.lam + 128, 64, P.R[2], 1, w.trace + 2, 1, w.scal, 0, P.eps * P.eps,
+                                       w.ranks + 2, w.ranks + 5, s));
+            int hr[6];
+            if ((st = readback(ctx, s, w.ranks, sizeof(hr), hr)) != TK_OK) return st;
+            // continue with the selected ranks: the leading columns of the factors are kept
+            Plan Q = P;
+            for (int k = 0; k < 3; ++k) Q.R[k] = hr[k];
+            for (int k = 0; k < 3; ++k) {
+                if (Q.R[k] != P.R[k]) {
+                    TK_HIP(hipMemcpy2DAsync(w.Urot[k], sizeof(double) * Q.R[k], w.U[k], sizeof(double) * P.R[k],
+                                            sizeof(double) * Q.R[k], P.n[k], hipMemcpyDeviceToDevice, s));
+                    TK_HIP(hipMemcpyAsync(w.U[k], w.Urot[k], sizeof(double) * Q.R[k] * P.n[k], hipMemcpyDeviceToDevice, s));
+                }
+                Q.p[k] = (P.n[k] <= EIG_PMAX) ? P.n[k] : std::min(Q.R[k] + 8, EIG_PMAX);
+            }
+            P = Q;
+        }
+        for (int k = 0; k < 3; ++k)
+            if ((st = refresh_u32<Real>(P, w, k, s)) != TK_OK) return st;
 
+        // ---- HOOI sweeps, then the core
+        if (P.sweeps == 0) {
+            if ((st = hosvd_core<Real>(P, w, A, s)) != TK_OK) return st;
+        } else {
+            for (int it = 0; it < P.sweeps; ++it)
+                if ((st = hooi_sweep<Real>(P, w, A, nmax, s)) != TK_OK) return st;
+        }
+        // ---- reconstruction error
+        if ((st = recon_norm<Real>(P, w, A, w.U, w.core, s)) != TK_OK) return st;
+
+        const bool trunc = P.eps_mode && P.prec != TK_FP64;
+        if (trunc) {
+            // ranks from the core HOSVD with the (conservative) error bound, then the error of the
+            // truncated result measured directly against A
+            if ((st = core_truncate(P, w, s)) != TK_OK) return st;
+            TK_LAUNCH(launch_mask_rank(w.Urot, P.n, P.R, w.coreA, w.ranks, s, w.bt));
+            if ((st = recon_norm<Real>(P, w, A, w.Urot, w.coreA, s)) != TK_OK) return st;
+            TK_LAUNCH(launch_fill_f64(w.scal + 2, 0.0, 1, s, w.bt));
+            TK_LAUNCH(launch_final_err(w.scal, s, w.bt));
+        } else {
+            TK_LAUNCH(launch_fill_f64(w.scal + 2, 0.0, 1, s, w.bt));   // no truncation: t2 = 0
+            TK_LAUNCH(launch_final_err(w.scal, s, w.bt));
+        }
+        return TK_OK;
+    };
+    tk_status st;
+    const bool capturable = own_A && wsp.cached && !(P.eps_mode && P.prec == TK_FP64) && !g_prof_on.load();
+    if (ctx->graphs_on && capturable) {
+        if ((st = run_captured<Real>(ctx, P, nb, base, grid, kps, w, s, pipeline)) != TK_OK) return st;
+    } else if ((st = pipeline(s)) != TK_OK) {
+        return st;
+    }
     const bool trunc = P.eps_mode && P.prec != TK_FP64;
     const double* Usrc[3] = {w.U[0], w.U[1], w.U[2]};
     const double* csrc = w.core;
     if (trunc) {
-        // ranks from the core HOSVD with the (conservative) error bound, then the error of the
-        // truncated result measured directly against A
-        if ((st = core_truncate(P, w, s)) != TK_OK) return st;
-        TK_LAUNCH(launch_mask_rank(w.Urot, P.n, P.R, w.coreA, w.ranks, s, w.bt));
-        if ((st = recon_norm<Real>(P, w, A, w.Urot, w.coreA, s)) != TK_OK) return st;
-        TK_LAUNCH(launch_fill_f64(w.scal + 2, 0.0, 1, s, w.bt));
-        TK_LAUNCH(launch_final_err(w.scal, s, w.bt));
         for (int k = 0; k < 3; ++k) Usrc[k] = w.Urot[k];
         csrc = w.coreA;
-    } else {
-        TK_LAUNCH(launch_fill_f64(w.scal + 2, 0.0, 1, s, w.bt));   // no truncation: t2 = 0
-        TK_LAUNCH(launch_final_err(w.scal, s, w.bt));
     }
     // ---- per problem: ranks (6 ints, padded to 8) and scal[0..3] (4 doubles)
     std::vector<int> hr((size_t)nb * 8);
@@ -1501,6 +1601,14 @@ void tk_ctx_destroy(tk_ctx* ctx)
     ctx->pinned = nullptr;
     ctx->dev_slots = nullptr;
     {
+        std::lock_guard<std::mutex> g(ctx->graph_mu);
+        for (auto& kv : ctx->graphs) {
+            (void)hipGraphExecDestroy(kv.second.ex);
+            (void)hipGraphDestroy(kv.second.g);
+        }
+        ctx->graphs.clear();
+    }
+    {
         std::lock_guard<std::mutex> g(ctx->ws_mu);
         for (auto& kv : ctx->ws)
             if (kv.second.ptr) (void)hipFreeAsync(kv.second.ptr, nullptr);
@@ -1644,6 +1752,14 @@ tk_status tk_ctx_release_stream(tk_ctx* ctx, void* hip_stream)
         if (it->second.ptr) (void)hipFreeAsync(it->second.ptr, s);
         ctx->ws.erase(it);
     }
+    return TK_OK;
+}
+
+tk_status tk_ctx_set_graphs(tk_ctx* ctx, int on)
+{
+    if (!ctx) return fail(TK_EINVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> g(ctx->graph_mu);
+    ctx->graphs_on = on != 0;
     return TK_OK;
 }
 

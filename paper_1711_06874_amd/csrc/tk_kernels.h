@@ -34,6 +34,22 @@ hipError_t launch_grid_eval_f32(float* A, const GridAxes& g, const KernelParams*
 hipError_t launch_grid_eval_f64(double* A, const GridAxes& g, const KernelParams* kps, hipStream_t s,
                                 Bat bt = Bat());
 
+// Kernel-node parameters of the grid evaluation as launch_grid_eval_* would launch it (for
+// updating a captured graph); the argument values live in the struct, which must outlive the
+// update call.
+struct GridEvalNode {
+    hipKernelNodeParams p;
+    void* args[6];
+    void* A;
+    GridAxes g;
+    KernelParamsBatch kps;
+    long total;
+    int qpr;
+    long bs;
+};
+void grid_eval_node_f32(float* A, const GridAxes& g, const KernelParams* kps, Bat bt, GridEvalNode* nd);
+void grid_eval_node_f64(double* A, const GridAxes& g, const KernelParams* kps, Bat bt, GridEvalNode* nd);
+
 // ----------------------------------------------------------------- a2: Gram (SYRK) ----
 // G (n_mode x n_mode, double, full) = A_(mode) A_(mode)^T.  `work` must hold
 // gram_work_bytes(...) bytes.  nsplit: the number of K chunks per tile pair (0: the default

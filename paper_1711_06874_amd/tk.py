@@ -95,6 +95,7 @@ _SIGS = {
     "tk_autotune_load": (_st, [_vp, ctypes.c_char_p]),
     "tk_ctx_release_stream": (_st, [_vp, _vp]),
     "tk_ctx_set_workers": (_st, [_vp, ctypes.c_int]),
+    "tk_ctx_set_graphs": (_st, [_vp, ctypes.c_int]),
     "tk_quadratic_form_batch": (_st, [_vp, ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, _vp,
                                       _dp, ctypes.POINTER(_vp)]),
     "tk_estimate_matvec_bytes": (_st, [_vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
@@ -445,6 +446,9 @@ class Context:
 
     def set_workers(self, workers: int):
         _check(_lib.tk_ctx_set_workers(self.handle, workers), "tk_ctx_set_workers")
+
+    def set_graphs(self, on: bool):
+        _check(_lib.tk_ctx_set_graphs(self.handle, 1 if on else 0), "tk_ctx_set_graphs")
 
     def destroy(self):
         if self.handle:

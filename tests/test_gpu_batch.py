@@ -231,3 +231,50 @@ def test_autotune_keeps_batch_equal_single_and_roundtrips(tk, tmp_path):
             ctx2.destroy()
     finally:
         ctx.destroy()
+
+
+def test_graph_replay_matches_direct_launches(tk):
+    """With graph replay on, the first call of a shape captures the pipeline and later calls
+    replay it with the sampling launch updated to their own kernels and grids: every replay,
+    with direct-launch work of the same context in between, gives bitwise the direct result
+    (single calls, shared-grid groups, concurrent batches, fixed ranks and eps truncation)."""
+    require_gpu()
+    rng = np.random.default_rng(23)
+    ks = [tk.make_kernel(0, nu=float(rng.choice([0.5, 1.5, 2.5])), ell=float(np.exp(rng.uniform(np.log(0.05), 0.0))))
+          for _ in range(6)]
+    # same sizes, different extents and layouts: the replayed graph must take the call's grid
+    gs = [tk.make_grid(48, 1.0, 1), tk.make_grid(48, 0.5, 0), tk.make_grid(48, 2.0, 1),
+          tk.make_grid(96, 1.0, 0), tk.make_grid(48, 1.0, 0), tk.make_grid(96, 0.7, 1)]
+    for prec, eps, ranks in [(1, 1e-6, (0, 0, 0)), (2, 1e-6, (0, 0, 0)), (0, 0.0, (4, 5, 6))]:
+        opts = tk.make_opts(eps=eps, ranks=ranks, hooi_sweeps=2, prec=prec)
+        ctx = tk.Context(0)
+        try:
+            alone = [ctx.compress(k, g, opts, allow_noconv=True) for k, g in zip(ks, gs)]
+            group_ref = ctx.compress_group(ks[:3], gs[0], opts)
+            ctx.set_graphs(True)
+            for rep in range(3):
+                say("graph replay prec", prec, "eps", eps, "rep", rep)
+                for i, (k, g) in enumerate(zip(ks, gs)):
+                    t = ctx.compress(k, g, opts, allow_noconv=True)
+                    assert _same(t, alone[i]), f"single {i} differs on replay {rep}"
+                    t.free()
+                grp = ctx.compress_group(ks[:3], gs[0], opts)
+                for i, (a, b) in enumerate(zip(group_ref, grp)):
+                    assert _same(a, b), f"group item {i} differs on replay {rep}"
+                for t in grp:
+                    t.free()
+                mix = ctx.compress_batch(ks, gs, opts)
+                for i, (a, b) in enumerate(zip(alone, mix)):
+                    assert _same(a, b), f"batch item {i} differs on replay {rep}"
+                for t in mix:
+                    t.free()
+                # direct launches between the replays
+                ctx.set_graphs(False)
+                t = ctx.compress(ks[rep], gs[rep], opts, allow_noconv=True)
+                assert _same(t, alone[rep])
+                t.free()
+                ctx.set_graphs(True)
+            for t in alone + group_ref:
+                t.free()
+        finally:
+            ctx.destroy()
