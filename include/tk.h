@@ -284,14 +284,17 @@ tk_status tk_estimate_matvec_bytes(tk_ctx *ctx, const tk_tucker *t, int io, size
 tk_status tk_trace(tk_ctx *ctx, const tk_tucker *t, void *hip_stream, double *out);
 
 /* z^T C z (FP64 accumulation of the dot product with C z).  If y_dev is not NULL it also
- * receives C z (same type and size as z).  Synchronising (one scalar read). */
+ * receives C z (same type and size as z); on the FFT path the dot product is summed as C z is
+ * formed, so without y_dev C z is never stored.  Synchronising (one scalar read). */
 tk_status tk_quadratic_form(tk_ctx *ctx, const tk_tucker *t, const void *z_dev, int io,
                             void *hip_stream, double *out, void *y_dev);
 /* tk_quadratic_form for `count` results at once: out[i] = z_i^T C_i z_i (and y_devs[i] = C_i z_i
- * when y_devs and y_devs[i] are not NULL), the items running concurrently on the context's worker
- * streams (tk_ctx_set_workers) after the work queued on hip_stream.  Each value is bitwise the
- * one the single call returns.  Synchronising.  Errors: as tk_quadratic_form, for the first
- * failing item. */
+ * when y_devs and y_devs[i] are not NULL), after the work queued on hip_stream.  On the FFT path
+ * the small per-item preambles run on a worker stream of the context while the five data passes
+ * of the items run back to back on hip_stream (one pair of spectrum buffers serves them all, and
+ * the values are read back together); on the dense path the items run concurrently on the
+ * worker streams (tk_ctx_set_workers).  Each value is bitwise the one the single call returns.
+ * Synchronising.  Errors: as tk_quadratic_form, for the first failing item. */
 tk_status tk_quadratic_form_batch(tk_ctx *ctx, int count, const tk_tucker *const *ts,
                                   const void *const *z_devs, int io, void *hip_stream, double *out,
                                   void *const *y_devs);

@@ -15,7 +15,8 @@
 //   P2  axis 1, forward                                             (m0 x H2 fibres)
 //   P3  axis 0, forward, times chat, inverse, keeps i0 < m0          (L1 x H2 fibres, in place)
 //   P4  axis 1, inverse, keeps i1 < m1
-//   P5  axis 2, inverse from the half spectrum (Hermitian), real part, keeps i2 < m2, 1/(L0 L1 L2)
+//   P5  axis 2, inverse from the half spectrum (Hermitian), real part, keeps i2 < m2, 1/(L0 L1 L2);
+//       for the quadratic form z^T C z it also sums z . y as y is stored (z fetched with the input)
 // with H2 = L2/2 + 1.  chat is evaluated on the fly in P3 from Hs[f0][f1][c] = sum_ab
 // G_abc Uh1[f0][a] Uh2[f1][b] and Uh3.
 //
@@ -28,7 +29,8 @@
 // the natural order straight from registers and the last one leaves it there; the stages in
 // between exchange through the fibre's own LDS buffer with wavefront-level ordering only.
 // Because m <= L / 2 for every axis of the embedding, forward transforms see zeros in the upper
-// half and inverse transforms need only the lower half: both are pruned at compile time.
+// half and inverse transforms need only the lower half: both are pruned at compile time (the
+// first radix-8 stage of a forward transform skips the additions of its four zero inputs).
 //
 // Passes with contiguous fibres (P1, P5) load and store the registers directly (coalesced
 // along the fibre).  Strided passes (P2, P3, P4) stage a tile of F neighbouring fibres
@@ -139,6 +141,29 @@ __device__ __forceinline__ void dft(float2 (&v)[R])
     }
 }
 
+// dft<8> of v[0..3] with v[4..7] = 0 (the first stage of a zero-padded forward transform):
+// the additions with the zero inputs are left out.
+template <bool INV>
+__device__ __forceinline__ void dft8_half(float2 (&v)[8])
+{
+    const float2 e0 = cadd(v[0], v[2]), e2 = csub(v[0], v[2]);
+    const float2 e1 = cadd(v[0], cmul_mi<INV>(v[2])), e3 = csub(v[0], cmul_mi<INV>(v[2]));
+    float2 o0 = cadd(v[1], v[3]), o2 = csub(v[1], v[3]);
+    float2 o1 = cadd(v[1], cmul_mi<INV>(v[3])), o3 = csub(v[1], cmul_mi<INV>(v[3]));
+    const float h = 0.70710678118654752f;
+    o1 = INV ? make_float2(h * (o1.x - o1.y), h * (o1.x + o1.y)) : make_float2(h * (o1.x + o1.y), h * (o1.y - o1.x));
+    o2 = cmul_mi<INV>(o2);
+    o3 = INV ? make_float2(-h * (o3.x + o3.y), h * (o3.x - o3.y)) : make_float2(h * (o3.y - o3.x), -h * (o3.x + o3.y));
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1);
+    v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2);
+    v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3);
+    v[7] = csub(e3, o3);
+}
+
 template <int LOGL, int S, bool TWR>
 __device__ __forceinline__ void load_twiddles_from(TwRegs<LOGL, TWR>& tr, int p, const float2* __restrict__ tw)
 {
@@ -188,7 +213,8 @@ __device__ __forceinline__ void fft_stage(float2 (&x)[Shape<LOGL>::V], float2* f
             }
             u[r] = v;
         }
-        dft<R, INV>(u);
+        if constexpr (HALF_IN && S == 0 && R == 8) dft8_half<INV>(u);
+        else dft<R, INV>(u);
         if (LAST) {
 #pragma unroll
             for (int r = 0; r < R; ++r) x[b + B * r] = u[r];
@@ -227,9 +253,12 @@ __device__ __forceinline__ void load_twiddles(TwRegs<LOGL, TWR>& tr, int p, cons
 
 // ct[ff][f0] (row stride CS) = chat[f0][o][i0 + ff] = sum_c Uh3[i0 + ff][c] Hs[o][f0][c] for the F
 // fibres of the work-group: an (F x r2p) x (r2p x L) product on mfma_f32_16x16x4f32, 16 x 16
-// output tiles shared out over the wavefronts (operand A: row lane % 16, k lane / 16; B: k
-// lane / 16, column lane % 16; result v of a lane: row 4 (lane / 16) + v, column lane % 16).
-// The Uh3 rows of the work-group are staged in LDS (u3s, F x r2p) when they fit.
+// output tiles shared out over the wavefronts (operand A: row lane % 16; B: column lane % 16;
+// result v of a lane: row 4 (lane / 16) + v, column lane % 16).  The sum over c runs in groups
+// of 16: lane group q = lane / 16 loads c = 16 g + 4 q .. + 3 of its row as one float4 and
+// MFMA j of the group takes the j-th of them, so every operand of a tile is loaded by
+// 16-byte loads issued together before the products.  The Uh3 rows of the work-group are
+// staged in LDS (u3s, F x r2p) when they fit.
 template <int LOGL>
 __device__ __forceinline__ void chat_table(float* ct, float* u3s, long o, int i0, int nf, int r2p,
                                            const float* __restrict__ Hs, const float* __restrict__ Uh3)
@@ -237,27 +266,39 @@ __device__ __forceinline__ void chat_table(float* ct, float* u3s, long o, int i0
     using Sh = Shape<LOGL>;
     constexpr int L = Sh::L, NT = Sh::NT, F = Sh::F, NW = Sh::NW, CS = Sh::CS;
     constexpr int TR = (F + 15) / 16, TC = (L + 15) / 16;
+    constexpr int NG = 48 / 16;                 // groups of 16 in the widest row (r2p <= 48)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if constexpr (Sh::STAGE_U3) {
         for (int e = tid; e < F * r2p; e += NT) u3s[e] = (e < nf * r2p) ? Uh3[(long)i0 * r2p + e] : 0.f;
         __syncthreads();
     }
-    const int lr = lane & 15, lk = lane >> 4;
+    const int lr = lane & 15, lq = lane >> 4;
     for (int t = wv; t < TR * TC; t += NW) {
         const int tr = t % TR, tc = t / TR;
         const int ff = 16 * tr + lr, f0 = 16 * tc + lr;
         const float* urow = Sh::STAGE_U3 ? u3s + (ff < F ? ff : 0) * r2p
                                          : Uh3 + (long)((ff < nf) ? i0 + ff : i0) * r2p;
         const float* hrow = Hs + ((long)o * L + (f0 < L ? f0 : 0)) * r2p;
+        float4 av[NG], bv[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            const int c = 16 * g + 4 * lq;
+            av[g] = (c < r2p && ff < F) ? *reinterpret_cast<const float4*>(urow + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+            bv[g] = (c < r2p && f0 < L) ? *reinterpret_cast<const float4*>(hrow + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        for (int ks = 0; ks < r2p; ks += 4) {
-            const float av = (ff < F) ? urow[ks + lk] : 0.f;
-            const float bv = (f0 < L) ? hrow[ks + lk] : 0.f;
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            if (16 * g < r2p) {
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].x, bv[g].x, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].y, bv[g].y, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].z, bv[g].z, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].w, bv[g].w, acc, 0, 0, 0);
+            }
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int row = 16 * tr + 4 * lk + v;
+            const int row = 16 * tr + 4 * lq + v;
             if (row < F && f0 < L) ct[row * CS + f0] = acc[v];
         }
     }
@@ -318,11 +359,25 @@ __global__ void __launch_bounds__(Shape<LOGL>::NT) k_fft_pass(FftPassArgs a)
     constexpr int VIN = (PK == PK_INV) ? V : V / 2;
     constexpr int NREG = CONTIG ? V : Sh::QT;
     float2 pre[NREG];
+    // mode 2 with dot_part: the z values of the next chunk's outputs (rows ra, rb), fetched with it
+    constexpr int VZ = (PK == PK_C2R) ? V / 2 : 1;
+    float zpa[VZ], zpb[VZ];
     auto fetch = [&](const Chunk& ch) {
         const int nf = (nfib - ch.i0 < F) ? (nfib - ch.i0) : F;
         if constexpr (CONTIG) {
             const long ra = 2L * (ch.i0 + f), rb = ra + 1;
             const bool la = f < nf && ra < a.n_inner, lb = f < nf && rb < a.n_inner;
+            if constexpr (PK == PK_C2R) {
+                if (a.dot_part) {
+                    const float* zz = a.dot_z + ch.o * a.s_out_o;
+#pragma unroll
+                    for (int v = 0; v < VZ; ++v) {
+                        const int k = p + P * v;
+                        zpa[v] = (la && k < a.len_out) ? zz[ra * a.s_out_i + k] : 0.f;
+                        zpb[v] = (lb && k < a.len_out) ? zz[rb * a.s_out_i + k] : 0.f;
+                    }
+                }
+            }
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const int k = p + P * v;
@@ -357,8 +412,12 @@ __global__ void __launch_bounds__(Shape<LOGL>::NT) k_fft_pass(FftPassArgs a)
         }
     };
 
+    double dsum = 0.0;                                 // mode 2 with dot_part: z . y over this block's outputs
     Chunk ch;
-    if (!chunk_at<F>(0, nbx, a.n_outer, xcd_planes, &ch)) return;
+    if (!chunk_at<F>(0, nbx, a.n_outer, xcd_planes, &ch)) {
+        if (PK == PK_C2R && a.dot_part && tid == 0) a.dot_part[blockIdx.x] = 0.0;
+        return;
+    }
     fetch(ch);
     for (long j = 0;; ++j) {
         const Chunk cur = ch;
@@ -366,9 +425,17 @@ __global__ void __launch_bounds__(Shape<LOGL>::NT) k_fft_pass(FftPassArgs a)
         const long o = cur.o;
         const int nf = (nfib - i0 < F) ? (nfib - i0) : F;
         float2 x[V];
+        float zca[VZ], zcb[VZ];
         if constexpr (CONTIG) {
 #pragma unroll
             for (int v = 0; v < V; ++v) x[v] = pre[v];
+            if constexpr (PK == PK_C2R) {
+#pragma unroll
+                for (int v = 0; v < VZ; ++v) {
+                    zca[v] = zpa[v];
+                    zcb[v] = zpb[v];
+                }
+            }
         } else {
             __syncthreads();          // the previous chunk has finished reading the tile
 #pragma unroll
@@ -435,8 +502,15 @@ __global__ void __launch_bounds__(Shape<LOGL>::NT) k_fft_pass(FftPassArgs a)
                 for (int v = 0; v < V / 2; ++v) {
                     const int k = p + P * v;
                     if (k < a.len_out) {
-                        if (la) out[ra * a.s_out_i + k] = x[v].x * a.scale;
-                        if (lb) out[rb * a.s_out_i + k] = x[v].y * a.scale;
+                        const float ya = x[v].x * a.scale, yb = x[v].y * a.scale;
+                        if (!a.no_store) {
+                            if (la) out[ra * a.s_out_i + k] = ya;
+                            if (lb) out[rb * a.s_out_i + k] = yb;
+                        }
+                        if (a.dot_part) {
+                            if (la) dsum += (double)ya * (double)zca[v];
+                            if (lb) dsum += (double)yb * (double)zcb[v];
+                        }
                     }
                 }
             }
@@ -461,6 +535,21 @@ __global__ void __launch_bounds__(Shape<LOGL>::NT) k_fft_pass(FftPassArgs a)
         }
         if (!more) break;
     }
+    if constexpr (PK == PK_C2R) {
+        if (a.dot_part) {
+            // fixed-order reduction: each wavefront by butterflies, then the wavefronts in order
+            __syncthreads();
+            double* red = reinterpret_cast<double*>(fsm);
+            dsum = wave_sum(dsum);
+            if (lane == 0) red[wv] = dsum;
+            __syncthreads();
+            if (tid == 0) {
+                double t = 0.0;
+                for (int w = 0; w < Sh::NW; ++w) t += red[w];
+                a.dot_part[blockIdx.x] = t;
+            }
+        }
+    }
 }
 
 }  // namespace
@@ -482,25 +571,89 @@ hipError_t launch_twiddles(float2* tw, int L, hipStream_t s)
 }
 
 // Uh[f][a] = u_a[off] + 2 sum_{t=1}^{m-1} u_a[off + t] cos(2 pi f t / L) for f < nf, a < r
-// (U: n x r row-major FP64; output nf x r FP64).  cos(2 pi q / L) comes from a per-block FP64
-// table; the phase f t is reduced exactly modulo L (a power of two).
-__global__ void __launch_bounds__(256) k_fourier_factor(const double* __restrict__ U, int r, int off, int m, int L,
-                                                        int nf, double* __restrict__ Uh)
+// (U: n x r row-major FP64; output nf x r FP64), for the three axes in one launch (grid y).
+// cos(2 pi q / L) comes from a per-block FP64 table; the phase f t is reduced exactly modulo L
+// (a power of two).  Eight lanes share one output, lane g summing t = 1 + g + 8 j in order
+// (four loads issued together); the eight partial sums are combined by butterfly shuffles,
+// which give every lane of the eight the same bits (each addition is commutative).
+constexpr int FF_SEG = 8;
+constexpr int FF_OUT = 256 / FF_SEG;          // outputs per work-group
+
+__global__ void __launch_bounds__(256) k_fourier_factor(FourierAxes fa)
 {
     extern __shared__ double ctab[];
+    const FourierAxis& ax = fa.ax[blockIdx.y];
+    const int r = ax.r, m = ax.m, L = ax.L;
+    if ((long)blockIdx.x * FF_OUT >= (long)ax.nf * r) return;           // uniform over the block
     for (int q = threadIdx.x; q < L; q += blockDim.x) ctab[q] = cospi(2.0 * (double)q / (double)L);
     __syncthreads();
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (long)nf * r) return;
-    const int f = (int)(e / r), a = (int)(e % r);
-    const double* u = U + (long)off * r + a;
+    const int g = threadIdx.x & (FF_SEG - 1);
+    const long e = (long)blockIdx.x * FF_OUT + (threadIdx.x / FF_SEG);
+    const bool live = e < (long)ax.nf * r;
+    const long ee = live ? e : 0;
+    const int f = (int)(ee / r), a = (int)(ee % r);
+    const double* u = ax.U + (long)ax.off * r + a;
     double s = 0.0;
-    int ph = 0;
-    for (int t = 1; t < m; ++t) {
-        ph = (ph + f) & (L - 1);
-        s += u[(long)t * r] * ctab[ph];
+    int t = 1 + g;
+    for (; t + 3 * FF_SEG < m; t += 4 * FF_SEG) {
+        const double u0 = u[(long)t * r], u1 = u[(long)(t + FF_SEG) * r];
+        const double u2 = u[(long)(t + 2 * FF_SEG) * r], u3 = u[(long)(t + 3 * FF_SEG) * r];
+        s += u0 * ctab[(f * t) & (L - 1)];
+        s += u1 * ctab[(f * (t + FF_SEG)) & (L - 1)];
+        s += u2 * ctab[(f * (t + 2 * FF_SEG)) & (L - 1)];
+        s += u3 * ctab[(f * (t + 3 * FF_SEG)) & (L - 1)];
     }
-    Uh[e] = u[0] + 2.0 * s;
+    for (; t < m; t += FF_SEG) s += u[(long)t * r] * ctab[(f * t) & (L - 1)];
+#pragma unroll
+    for (int d = 1; d < FF_SEG; d <<= 1) s += __shfl_xor(s, d, FF_SEG);
+    if (live && g == 0) ax.Uh[e] = u[0] + 2.0 * s;
+}
+
+// Hs[f1][f0][c] = sum_b Uh1[f1][b] M1[f0][b][c] (FP64 sums stored as FP32) for c < r2, and 0 for
+// r2 <= c < r2p: the Fourier-side core contracted with the axis-1 factor, one row of r2p values
+// per (f1, f0).  A work-group owns 256 / r2p consecutive f0 and HS_F1 consecutive f1; thread
+// (f0, c) keeps M1[f0][:][c] in registers, the Uh1 rows of its f1 block sit in LDS, and each f1
+// writes one contiguous run of the f0 block's rows.
+constexpr int HS_F1 = 32;
+constexpr int HS_RMAX = 48;
+
+__global__ void __launch_bounds__(256) k_spectral_core(const double* __restrict__ Uh1, const double* __restrict__ M1,
+                                                       int L0, int L1, int r1, int r2, int r2p, float* __restrict__ Hs)
+{
+    __shared__ double us[HS_F1][HS_RMAX];
+    const int nf0 = 256 / r2p;
+    const int c = threadIdx.x % r2p, fl = threadIdx.x / r2p;
+    const int f0 = blockIdx.x * nf0 + fl;
+    const int f1b = blockIdx.y * HS_F1;
+    const bool row = fl < nf0 && f0 < L0;
+    const bool live = row && c < r2;
+    double mr[HS_RMAX];
+#pragma unroll
+    for (int b = 0; b < HS_RMAX; ++b) mr[b] = (live && b < r1) ? M1[((long)f0 * r1 + b) * r2 + c] : 0.0;
+    for (int e = threadIdx.x; e < HS_F1 * r1; e += blockDim.x) {
+        const int j = e / r1, b = e - j * r1;
+        us[j][b] = (f1b + j < L1) ? Uh1[(long)(f1b + j) * r1 + b] : 0.0;
+    }
+    __syncthreads();
+    if (!row) return;
+    const int nj = (L1 - f1b < HS_F1) ? (L1 - f1b) : HS_F1;
+    for (int j = 0; j < nj; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < HS_RMAX; ++b)
+            if (b < r1) acc += us[j][b] * mr[b];
+        Hs[((long)(f1b + j) * L0 + f0) * r2p + c] = live ? (float)acc : 0.f;
+    }
+}
+
+hipError_t launch_spectral_core(const double* Uh1, const double* M1, int L0, int L1, int r1, int r2, int r2p,
+                                float* Hs, hipStream_t s)
+{
+    if (r1 < 1 || r1 > HS_RMAX || r2 < 1 || r2p < r2 || r2p > 256 || L0 < 1 || L1 < 1) return hipErrorInvalidValue;
+    const int nf0 = 256 / r2p;
+    const dim3 grid((unsigned)((L0 + nf0 - 1) / nf0), (unsigned)((L1 + HS_F1 - 1) / HS_F1));
+    hipLaunchKernelGGL(k_spectral_core, grid, dim3(256), 0, s, Uh1, M1, L0, L1, r1, r2, r2p, Hs);
+    return hipGetLastError();
 }
 
 // Y[i][c] = c < cols ? (float)X[i * cols + c] : 0 for c < cols_pad.
@@ -522,30 +675,19 @@ hipError_t launch_f64_to_f32_padded(const double* X, long rows, int cols, int co
     return hipGetLastError();
 }
 
-// X[i][c] = 0 for cols <= c < cols_pad (rows of length cols_pad).
-__global__ void k_zero_pad_cols(float* __restrict__ X, long rows, int cols, int cols_pad)
+hipError_t launch_fourier_factors(const FourierAxes& fa, hipStream_t s)
 {
-    const int w = cols_pad - cols;
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= rows * w) return;
-    const long i = e / w;
-    X[i * cols_pad + cols + (int)(e - i * w)] = 0.f;
-}
-
-hipError_t launch_zero_pad_cols(float* X, long rows, int cols, int cols_pad, hipStream_t s)
-{
-    if (cols_pad <= cols) return hipSuccess;
-    const long tot = rows * (cols_pad - cols);
-    hipLaunchKernelGGL(k_zero_pad_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, X, rows, cols,
-                       cols_pad);
-    return hipGetLastError();
-}
-
-hipError_t launch_fourier_factor(const double* U, int r, int off, int m, int L, int nf, double* Uh, hipStream_t s)
-{
-    long tot = (long)nf * r;
-    hipLaunchKernelGGL(k_fourier_factor, dim3((unsigned)((tot + 255) / 256)), dim3(256), sizeof(double) * L, s, U, r,
-                       off, m, L, nf, Uh);
+    long blocks = 1;
+    int lmax = 2;
+    for (int k = 0; k < 3; ++k) {
+        const FourierAxis& x = fa.ax[k];
+        if (!x.U || !x.Uh || x.r < 1 || x.m < 1 || x.nf < 1 || x.L < 2 || (x.L & (x.L - 1)) || x.L > 2048 || x.m > x.L ||
+            (long)x.nf * x.L > (1L << 30))
+            return hipErrorInvalidValue;
+        blocks = std::max(blocks, ((long)x.nf * x.r + FF_OUT - 1) / FF_OUT);
+        lmax = std::max(lmax, x.L);
+    }
+    hipLaunchKernelGGL(k_fourier_factor, dim3((unsigned)blocks, 3), dim3(256), sizeof(double) * lmax, s, fa);
     return hipGetLastError();
 }
 
@@ -556,14 +698,16 @@ int g_resident[FFT_MAX_LOGL + 1][5];
 int g_cus = 0;
 
 template <int LOGL>
-hipError_t launch_len(FftPassArgs a, int kind, long n_outer, hipStream_t s)
+hipError_t launch_len(FftPassArgs a, int kind, long n_outer, hipStream_t s, unsigned* blocks)
 {
     using Sh = Shape<LOGL>;
     const int nfib = (kind == PK_R2C || kind == PK_C2R) ? (a.n_inner + 1) / 2 : a.n_inner;
     const long chunks = (long)((nfib + Sh::F - 1) / Sh::F) * n_outer;
     const int per_cu = g_resident[LOGL][kind] > 0 ? g_resident[LOGL][kind] : 1;
-    const long slots = (long)(g_cus > 0 ? g_cus : 256) * per_cu;
+    long slots = (long)(g_cus > 0 ? g_cus : 256) * per_cu;
+    if (a.dot_part && slots > a.dot_cap) slots = a.dot_cap;
     const dim3 grid((unsigned)(chunks < slots ? chunks : slots));
+    if (blocks) *blocks = grid.x;
     a.n_outer = n_outer;
     const size_t lds = (kind == PK_CORE) ? Sh::LDS_CORE : Sh::LDS_TILE;
     switch (kind) {
@@ -608,18 +752,14 @@ hipError_t set_attrs_upto()
 }
 }  // namespace
 
-int fft_fibres_per_block(int L)
-{
-    int F = 8192 / L;
-    return F > 1024 ? 1024 : F;
-}
-
-hipError_t launch_fft_pass(const FftPassArgs& a, long n_outer, hipStream_t s)
+hipError_t launch_fft_pass(const FftPassArgs& a, long n_outer, hipStream_t s, unsigned* blocks)
 {
     const int L = a.L;
     if (a.logL < 1 || a.logL > FFT_MAX_LOGL || L != (1 << a.logL) || n_outer < 1 || a.n_inner < 1 ||
-        a.len_in < 1 || a.len_out < 1 || !a.in || !a.out || !a.tw)
+        a.len_in < 1 || a.len_out < 1 || !a.in || !a.tw)
         return hipErrorInvalidValue;
+    if (a.dot_part && (a.mode != 2 || !a.dot_z || a.dot_cap < 1)) return hipErrorInvalidValue;
+    if (a.no_store ? (a.mode != 2 || !a.dot_part) : !a.out) return hipErrorInvalidValue;
     const bool contig = a.s_in_k == 1 && a.s_out_k == 1;
     const bool strided = a.s_in_i == 1 && a.s_out_i == 1 && !contig;
     int kind;
@@ -632,17 +772,17 @@ hipError_t launch_fft_pass(const FftPassArgs& a, long n_outer, hipStream_t s)
     else if (a.mode == 2 && !a.in_real && contig && a.len_in == L / 2 + 1 && a.len_out <= L / 2) kind = PK_C2R;
     else return hipErrorInvalidValue;
     switch (a.logL) {
-    case 1: return launch_len<1>(a, kind, n_outer, s);
-    case 2: return launch_len<2>(a, kind, n_outer, s);
-    case 3: return launch_len<3>(a, kind, n_outer, s);
-    case 4: return launch_len<4>(a, kind, n_outer, s);
-    case 5: return launch_len<5>(a, kind, n_outer, s);
-    case 6: return launch_len<6>(a, kind, n_outer, s);
-    case 7: return launch_len<7>(a, kind, n_outer, s);
-    case 8: return launch_len<8>(a, kind, n_outer, s);
-    case 9: return launch_len<9>(a, kind, n_outer, s);
-    case 10: return launch_len<10>(a, kind, n_outer, s);
-    default: return launch_len<11>(a, kind, n_outer, s);
+    case 1: return launch_len<1>(a, kind, n_outer, s, blocks);
+    case 2: return launch_len<2>(a, kind, n_outer, s, blocks);
+    case 3: return launch_len<3>(a, kind, n_outer, s, blocks);
+    case 4: return launch_len<4>(a, kind, n_outer, s, blocks);
+    case 5: return launch_len<5>(a, kind, n_outer, s, blocks);
+    case 6: return launch_len<6>(a, kind, n_outer, s, blocks);
+    case 7: return launch_len<7>(a, kind, n_outer, s, blocks);
+    case 8: return launch_len<8>(a, kind, n_outer, s, blocks);
+    case 9: return launch_len<9>(a, kind, n_outer, s, blocks);
+    case 10: return launch_len<10>(a, kind, n_outer, s, blocks);
+    default: return launch_len<11>(a, kind, n_outer, s, blocks);
     }
 }
 

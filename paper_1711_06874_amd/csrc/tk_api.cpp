@@ -1366,70 +1366,77 @@ int ilog2(int L)
     return l;
 }
 
-// y = C z by the 3-D DFT (see k_fft.hip); FP32 data.
-// plan_bytes != nullptr: only report the workspace the call needs (nothing runs).
-tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, hipStream_t s, double* dot_out,
-                     size_t* plan_bytes = nullptr)
+// y = C z by the 3-D DFT (see k_fft.hip); FP32 data.  A matvec is a preamble (the Fourier-side
+// factors and the core contracted with two of them, small kernels) and five passes over the
+// data; a batch of quadratic forms runs its preambles on a side stream and the passes of all
+// items back to back.
+struct MvGeom {
+    int off[3], m[3], L[3], lg[3], r[3];
+    int H2, H2p, r2p;
+};
+
+bool mv_geom(const tk_tucker* t, MvGeom* g)
 {
-    int off[3], m[3];
-    if (!cov_geometry(t, off, m)) return fail(TK_ELAYOUT, "even-sized centred grid has no origin node");
-    const int r0 = t->r[0], r1 = t->r[1], r2 = t->r[2];
-    int L[3], lg[3];
+    if (!cov_geometry(t, g->off, g->m)) return false;
     for (int k = 0; k < 3; ++k) {
-        L[k] = next_pow2(std::max(2 * m[k] - 1, 2));
-        lg[k] = ilog2(L[k]);
+        g->L[k] = next_pow2(std::max(2 * g->m[k] - 1, 2));
+        g->lg[k] = ilog2(g->L[k]);
+        g->r[k] = t->r[k];
     }
-    const int H2 = L[2] / 2 + 1;
-    const int H2p = (H2 + 15) & ~15;     // row pitch of the half spectra: whole 128-byte lines per 16 fibres
-    const int r2p = (r2 + 3) & ~3;
-    const long M3 = (long)m[0] * m[1] * m[2];
-    Arena plan;
-    auto lay = [&](Arena& ar, double** Uh0, double** Uh1, double** Uh2, double** M1, float** Hs, float** Uh3,
-                   float2** A1, float2** A2, double** dots, float2** tw) {
-        for (int k = 0; k < 3; ++k) tw[k] = ar.take<float2>((size_t)L[k]);
-        *Uh0 = ar.take<double>((size_t)L[0] * r0);
-        *Uh1 = ar.take<double>((size_t)L[1] * r1);
-        *Uh2 = ar.take<double>((size_t)H2 * r2);
-        *M1 = ar.take<double>((size_t)L[0] * r1 * r2);
-        *Hs = ar.take<float>((size_t)L[0] * L[1] * r2p);
-        *Uh3 = ar.take<float>((size_t)H2 * r2p);
-        *A1 = ar.take<float2>((size_t)m[0] * m[1] * H2p);
-        *A2 = ar.take<float2>((size_t)m[0] * L[1] * H2p);
-        *dots = ar.take<double>(2048);
-    };
+    g->H2 = g->L[2] / 2 + 1;
+    g->H2p = (g->H2 + 15) & ~15;     // row pitch of the half spectra: whole 128-byte lines per 16 fibres
+    g->r2p = (g->r[2] + 3) & ~3;
+    return true;
+}
+
+// per-item buffers: twiddles, Fourier-side factors, Hs[f1][f0][c], Uh3[f2][c], dot partials
+struct MvPre {
+    float2* tw[3];
     double *Uh0, *Uh1, *Uh2, *M1, *dots;
     float *Hs, *Uh3;
-    float2 *A1, *A2;
-    float2* tw[3];
-    lay(plan, &Uh0, &Uh1, &Uh2, &M1, &Hs, &Uh3, &A1, &A2, &dots, tw);
-    if (plan_bytes) {
-        *plan_bytes = plan.off;
-        return TK_OK;
-    }
-    Reservation res(ctx, plan.off);
-    if (!res.take()) return fail(TK_ENOMEM, "matvec needs %zu bytes; budget %zu, in use %zu", plan.off, ctx->budget,
-                                 ctx->in_use.load());
-    Ws wsp;
-    hipError_t he = ws_get(ctx, s, 0, plan.off, wsp);
-    if (he != hipSuccess) return fail(TK_ENOMEM, "workspace of %zu bytes: %s", plan.off, hipGetErrorString(he));
-    void* base = wsp.p;
-    Arena ar;
-    ar.base = (char*)base;
-    lay(ar, &Uh0, &Uh1, &Uh2, &M1, &Hs, &Uh3, &A1, &A2, &dots, tw);
-    for (int k = 0; k < 3; ++k) TK_LAUNCH(launch_twiddles(tw[k], L[k], s));
-    {
-        ProfScope ps(TK_PROF_SMALL, s);
-        // Fourier-side factors and Hs[f1][f0][c] = sum_ab G_abc Uh1[f0][a] Uh2[f1][b] (c padded to r2p)
-        TK_LAUNCH(launch_fourier_factor(t->U[0], r0, off[0], m[0], L[0], L[0], Uh0, s));
-        TK_LAUNCH(launch_fourier_factor(t->U[1], r1, off[1], m[1], L[1], L[1], Uh1, s));
-        TK_LAUNCH(launch_fourier_factor(t->U[2], r2, off[2], m[2], L[2], H2, Uh2, s));
-        GemmArgs g = gemm(L[0], r1 * r2, r0, 1, Uh0, 0, r0, 1, t->core, 0, (long)r1 * r2, 1, M1, 0, (long)r1 * r2, 1);
-        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
-        GemmArgs g1 = gemm(L[1], r2, r1, L[0], Uh1, 0, r1, 1, M1, (long)r1 * r2, r2, 1, Hs, r2p, (long)L[0] * r2p, 1);
-        TK_LAUNCH((launch_gemm<double, double, float>(g1, s)));
-        TK_LAUNCH(launch_zero_pad_cols(Hs, (long)L[0] * L[1], r2, r2p, s));
-        TK_LAUNCH(launch_f64_to_f32_padded(Uh2, H2, r2, r2p, Uh3, s));
-    }
+};
+void lay_pre(Arena& ar, const MvGeom& g, MvPre* b)
+{
+    for (int k = 0; k < 3; ++k) b->tw[k] = ar.take<float2>((size_t)g.L[k]);
+    b->Uh0 = ar.take<double>((size_t)g.L[0] * g.r[0]);
+    b->Uh1 = ar.take<double>((size_t)g.L[1] * g.r[1]);
+    b->Uh2 = ar.take<double>((size_t)g.H2 * g.r[2]);
+    b->M1 = ar.take<double>((size_t)g.L[0] * g.r[1] * g.r[2]);
+    b->Hs = ar.take<float>((size_t)g.L[0] * g.L[1] * g.r2p);
+    b->Uh3 = ar.take<float>((size_t)g.H2 * g.r2p);
+    b->dots = ar.take<double>(2048);
+}
+// the half spectra between the passes (shared by the items of a batch, which run in turn)
+size_t mv_a1_elems(const MvGeom& g) { return (size_t)g.m[0] * g.m[1] * g.H2p; }
+size_t mv_a2_elems(const MvGeom& g) { return (size_t)g.m[0] * g.L[1] * g.H2p; }
+
+tk_status mv_preamble(const tk_tucker* t, const MvGeom& g, const MvPre& b, hipStream_t s)
+{
+    ProfScope ps(TK_PROF_SMALL, s);
+    for (int k = 0; k < 3; ++k) TK_LAUNCH(launch_twiddles(b.tw[k], g.L[k], s));
+    // Fourier-side factors and Hs[f1][f0][c] = sum_ab G_abc Uh1[f0][a] Uh2[f1][b] (c padded to r2p)
+    const int r0 = g.r[0], r1 = g.r[1], r2 = g.r[2];
+    FourierAxes fa;
+    fa.ax[0] = FourierAxis{t->U[0], r0, g.off[0], g.m[0], g.L[0], g.L[0], b.Uh0};
+    fa.ax[1] = FourierAxis{t->U[1], r1, g.off[1], g.m[1], g.L[1], g.L[1], b.Uh1};
+    fa.ax[2] = FourierAxis{t->U[2], r2, g.off[2], g.m[2], g.L[2], g.H2, b.Uh2};
+    TK_LAUNCH(launch_fourier_factors(fa, s));
+    GemmArgs gm = gemm(g.L[0], r1 * r2, r0, 1, b.Uh0, 0, r0, 1, t->core, 0, (long)r1 * r2, 1, b.M1, 0, (long)r1 * r2, 1);
+    TK_LAUNCH((launch_gemm<double, double, double>(gm, s)));
+    TK_LAUNCH(launch_spectral_core(b.Uh1, b.M1, g.L[0], g.L[1], r1, r2, g.r2p, b.Hs, s));
+    TK_LAUNCH(launch_f64_to_f32_padded(b.Uh2, g.H2, r2, g.r2p, b.Uh3, s));
+    return TK_OK;
+}
+
+// The five passes.  dot_dst (device, optional): z . y, summed by the last pass (y_out may then
+// be NULL: y is not stored).
+tk_status mv_passes(const MvGeom& g, const MvPre& b, float2* A1, float2* A2, const float* z, float* y,
+                    double* dot_dst, hipStream_t s)
+{
+    const int* m = g.m;
+    const int* L = g.L;
+    const int* lg = g.lg;
+    const int H2 = g.H2, H2p = g.H2p;
     FftPassArgs a{};
     {
         ProfScope ps(TK_PROF_FFT, s);
@@ -1438,7 +1445,7 @@ tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, 
         a.L = L[2]; a.logL = lg[2];
         a.n_inner = m[0] * m[1]; a.len_in = m[2]; a.len_out = H2;
         a.s_in_o = 0; a.s_in_i = m[2]; a.s_in_k = 1; a.s_out_o = 0; a.s_out_i = H2p; a.s_out_k = 1;
-        a.in = z; a.out = A1; a.in_real = 1; a.out_real = 0; a.mode = 0; a.scale = 1.f; a.tw = tw[2];
+        a.in = z; a.out = A1; a.in_real = 1; a.out_real = 0; a.mode = 0; a.scale = 1.f; a.tw = b.tw[2];
         TK_LAUNCH(launch_fft_pass(a, 1, s));
         // P2: axis 1 forward, fibres (i0, f2) over i1
         a = FftPassArgs{};
@@ -1446,7 +1453,7 @@ tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, 
         a.n_inner = H2; a.len_in = m[1]; a.len_out = L[1];
         a.s_in_o = (long)m[1] * H2p; a.s_in_i = 1; a.s_in_k = H2p;
         a.s_out_o = (long)L[1] * H2p; a.s_out_i = 1; a.s_out_k = H2p;
-        a.in = A1; a.out = A2; a.mode = 0; a.scale = 1.f; a.tw = tw[1];
+        a.in = A1; a.out = A2; a.mode = 0; a.scale = 1.f; a.tw = b.tw[1];
         TK_LAUNCH(launch_fft_pass(a, m[0], s));
     }
     {
@@ -1458,7 +1465,7 @@ tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, 
         a.s_in_o = H2p; a.s_in_i = 1; a.s_in_k = (long)L[1] * H2p;
         a.s_out_o = H2p; a.s_out_i = 1; a.s_out_k = (long)L[1] * H2p;
         a.in = A2; a.out = A2; a.mode = 3; a.scale = 1.f;
-        a.Hs = Hs; a.Uh3 = Uh3; a.r2p = r2p; a.tw = tw[0];
+        a.Hs = b.Hs; a.Uh3 = b.Uh3; a.r2p = g.r2p; a.tw = b.tw[0];
         TK_LAUNCH(launch_fft_pass(a, L[1], s));
     }
     {
@@ -1469,23 +1476,124 @@ tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, 
         a.n_inner = H2; a.len_in = L[1]; a.len_out = m[1];
         a.s_in_o = (long)L[1] * H2p; a.s_in_i = 1; a.s_in_k = H2p;
         a.s_out_o = (long)m[1] * H2p; a.s_out_i = 1; a.s_out_k = H2p;
-        a.in = A2; a.out = A1; a.mode = 1; a.scale = 1.f; a.tw = tw[1];
+        a.in = A2; a.out = A1; a.mode = 1; a.scale = 1.f; a.tw = b.tw[1];
         TK_LAUNCH(launch_fft_pass(a, m[0], s));
         // P5: axis 2 inverse from the half spectrum, real part, keep i2 < m2, scale
         a = FftPassArgs{};
         a.L = L[2]; a.logL = lg[2];
         a.n_inner = m[0] * m[1]; a.len_in = H2; a.len_out = m[2];
         a.s_in_o = 0; a.s_in_i = H2p; a.s_in_k = 1; a.s_out_o = 0; a.s_out_i = m[2]; a.s_out_k = 1;
-        a.in = A1; a.out = y; a.out_real = 1; a.mode = 2; a.tw = tw[2];
+        a.in = A1; a.out = y; a.no_store = y ? 0 : 1; a.out_real = 1; a.mode = 2; a.tw = b.tw[2];
         a.scale = (float)(1.0 / ((double)L[0] * L[1] * L[2]));
-        TK_LAUNCH(launch_fft_pass(a, 1, s));
+        if (dot_dst) {
+            // z . y summed while y is formed: one FP64 partial per work-group, then added in order
+            a.dot_z = z; a.dot_part = b.dots; a.dot_cap = 1024;
+        }
+        unsigned blocks = 0;
+        TK_LAUNCH(launch_fft_pass(a, 1, s, &blocks));
+        if (dot_dst) TK_LAUNCH(launch_reduce_partials(b.dots, (int)blocks, 1, dot_dst, s));
     }
+    return TK_OK;
+}
+
+// One matvec (y != NULL) or quadratic form (dot_out != NULL; y may then be NULL).
+// plan_bytes != nullptr: only report the workspace the call needs (nothing runs).
+tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, hipStream_t s, double* dot_out,
+                     size_t* plan_bytes = nullptr)
+{
+    MvGeom g;
+    if (!mv_geom(t, &g)) return fail(TK_ELAYOUT, "even-sized centred grid has no origin node");
+    auto lay = [&](Arena& ar, MvPre* b, float2** A1, float2** A2) {
+        lay_pre(ar, g, b);
+        *A1 = ar.take<float2>(mv_a1_elems(g));
+        *A2 = ar.take<float2>(mv_a2_elems(g));
+    };
+    Arena plan;
+    MvPre b;
+    float2 *A1, *A2;
+    lay(plan, &b, &A1, &A2);
+    if (plan_bytes) {
+        *plan_bytes = plan.off;
+        return TK_OK;
+    }
+    Reservation res(ctx, plan.off);
+    if (!res.take()) return fail(TK_ENOMEM, "matvec needs %zu bytes; budget %zu, in use %zu", plan.off, ctx->budget,
+                                 ctx->in_use.load());
+    Ws wsp;
+    hipError_t he = ws_get(ctx, s, 0, plan.off, wsp);
+    if (he != hipSuccess) return fail(TK_ENOMEM, "workspace of %zu bytes: %s", plan.off, hipGetErrorString(he));
+    Arena ar;
+    ar.base = (char*)wsp.p;
+    lay(ar, &b, &A1, &A2);
+    tk_status st;
+    if ((st = mv_preamble(t, g, b, s)) != TK_OK) return st;
+    if ((st = mv_passes(g, b, A1, A2, z, y, dot_out ? b.dots + 1024 : nullptr, s)) != TK_OK) return st;
     if (dot_out) {
-        TK_LAUNCH(launch_dot<float>(z, y, M3, dots, 1024, dots + 1024, s));
-        tk_status rs = readback(ctx, s, dots + 1024, sizeof(double), dot_out);
+        tk_status rs = readback(ctx, s, b.dots + 1024, sizeof(double), dot_out);
         if (rs != TK_OK) return rs;
     }
     return TK_OK;
+}
+
+// Quadratic forms of `count` results on the FFT path: the preambles on a side stream (each
+// followed by an event), the passes of the items in turn on s, sharing one pair of spectrum
+// buffers, the values gathered and read back once.  Same kernels and launch shapes as
+// matvec_fft, so each value is bitwise the single call's.
+tk_status quadform_fft_batch(tk_ctx* ctx, int count, const tk_tucker* const* ts, const void* const* z_devs,
+                             void* const* y_devs, hipStream_t s, hipStream_t side, double* out)
+{
+    std::vector<MvGeom> g(count);
+    size_t a1 = 0, a2 = 0;
+    for (int i = 0; i < count; ++i) {
+        if (!mv_geom(ts[i], &g[i])) return fail(TK_ELAYOUT, "item %d: even-sized centred grid has no origin node", i);
+        a1 = std::max(a1, mv_a1_elems(g[i]));
+        a2 = std::max(a2, mv_a2_elems(g[i]));
+    }
+    std::vector<MvPre> b(count);
+    float2 *A1, *A2;
+    double* gather;
+    auto lay = [&](Arena& ar) {
+        for (int i = 0; i < count; ++i) lay_pre(ar, g[i], &b[i]);
+        A1 = ar.take<float2>(a1);
+        A2 = ar.take<float2>(a2);
+        gather = ar.take<double>((size_t)count);
+    };
+    Arena plan;
+    lay(plan);
+    Reservation res(ctx, plan.off);
+    if (!res.take()) return fail(TK_ENOMEM, "quadratic forms need %zu bytes; budget %zu, in use %zu", plan.off,
+                                 ctx->budget, ctx->in_use.load());
+    Ws wsp;
+    hipError_t he = ws_get(ctx, s, 0, plan.off, wsp);
+    if (he != hipSuccess) return fail(TK_ENOMEM, "workspace of %zu bytes: %s", plan.off, hipGetErrorString(he));
+    Arena ar;
+    ar.base = (char*)wsp.p;
+    lay(ar);
+    std::vector<hipEvent_t> ev(count + 1, nullptr);
+    tk_status st = TK_OK;
+    auto run = [&]() -> tk_status {
+        for (auto& e : ev) TK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        // the preambles start after the work queued on s
+        TK_HIP(hipEventRecord(ev[count], s));
+        TK_HIP(hipStreamWaitEvent(side, ev[count], 0));
+        tk_status r;
+        for (int i = 0; i < count; ++i) {
+            if ((r = mv_preamble(ts[i], g[i], b[i], side)) != TK_OK) return r;
+            TK_HIP(hipEventRecord(ev[i], side));
+        }
+        for (int i = 0; i < count; ++i) {
+            TK_HIP(hipStreamWaitEvent(s, ev[i], 0));
+            if ((r = mv_passes(g[i], b[i], A1, A2, (const float*)z_devs[i], y_devs ? (float*)y_devs[i] : nullptr,
+                               gather + i, s)) != TK_OK)
+                return r;
+        }
+        return readback(ctx, s, gather, sizeof(double) * count, out);
+    };
+    st = run();
+    if (st != TK_OK) (void)hipStreamSynchronize(side);   // no preamble left running on the workspace
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return st;
 }
 
 bool use_fft(const tk_ctx* ctx, int io) { return io == TK_FP32 && ctx->matvec_method != TK_MV_DENSE; }
@@ -2105,9 +2213,10 @@ tk_status tk_quadratic_form(tk_ctx* ctx, const tk_tucker* t, const void* z_dev, 
     void* ybuf = y_dev;
     size_t esz = io == TK_FP32 ? 4 : 8;
     size_t ybytes = esz * (size_t)m[0] * m[1] * m[2];
-    Reservation res(ctx, y_dev ? 0 : ybytes);
+    const bool fft = use_fft(ctx, io);       // the FFT path sums z . y without storing y
+    Reservation res(ctx, (y_dev || fft) ? 0 : ybytes);
     Ws yws;
-    if (!y_dev) {
+    if (!y_dev && !fft) {
         if (!res.take()) return fail(TK_ENOMEM, "quadratic form needs %zu bytes", ybytes);
         hipError_t he = ws_get(ctx, s, 1, ybytes, yws);
         if (he != hipSuccess) return fail(TK_ENOMEM, "y of %zu bytes: %s", ybytes, hipGetErrorString(he));
@@ -2115,7 +2224,7 @@ tk_status tk_quadratic_form(tk_ctx* ctx, const tk_tucker* t, const void* z_dev, 
     }
     tk_status st;
     if (io == TK_FP64 && ctx->matvec_method == TK_MV_FFT) st = fail(TK_EINVAL, "the FFT matvec is FP32 only");
-    else if (use_fft(ctx, io))
+    else if (fft)
         st = matvec_fft(ctx, t, (const float*)z_dev, (float*)ybuf, s, out);
     else if (io == TK_FP32)
         st = matvec_impl<float>(ctx, t, (const float*)z_dev, (float*)ybuf, s, out);
@@ -2133,6 +2242,22 @@ tk_status tk_quadratic_form_batch(tk_ctx* ctx, int count, const tk_tucker* const
         if (!ts[i] || !z_devs[i]) return fail(TK_EINVAL, "item %d: NULL result or vector", i);
     TK_HIP(hipSetDevice(ctx->device));
     (void)hipGetLastError();
+    if (io != TK_FP64 && io != TK_FP32) return fail(TK_EINVAL, "io must be TK_FP64 or TK_FP32");
+    if (use_fft(ctx, io)) {
+        for (int i = 0; i < count; ++i)
+            if (!usable(ts[i])) return fail(TK_EINVAL, "item %d: result of a destroyed context", i);
+        hipStream_t side;
+        {
+            std::lock_guard<std::mutex> g(ctx->pool_mu);
+            if (ctx->streams.empty()) {
+                hipStream_t st;
+                TK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+                ctx->streams.push_back(st);
+            }
+            side = ctx->streams[0];
+        }
+        return quadform_fft_batch(ctx, count, ts, z_devs, y_devs, (hipStream_t)hip_stream, side, out);
+    }
     const int W = std::min(count, ctx->workers);
     std::vector<hipStream_t> ws(W);
     {

@@ -176,13 +176,29 @@ struct FftPassArgs {
     float scale;
     const float* Hs; const float* Uh3; int r2p;               // mode 3: Hs[f1][f0][c], Uh3[f2][c], c < r2p
     const float2* tw;                                          // exp(-2 pi i q / L), q < L
+    // mode 2 only, optional: dot_part[b] = the FP64 sum of z * y over the outputs work-group b
+    // stored (z laid out like the output); at most dot_cap work-groups run
+    const float* dot_z; double* dot_part; int dot_cap;
+    int no_store;              // mode 2 with dot_part: y is not stored (out may be NULL)
 };
 hipError_t launch_twiddles(float2* tw, int L, hipStream_t s);
-int fft_fibres_per_block(int L);            // fibres one work-group of a pass transforms
 hipError_t launch_f64_to_f32_padded(const double* X, long rows, int cols, int cols_pad, float* Y, hipStream_t s);
-hipError_t launch_zero_pad_cols(float* X, long rows, int cols, int cols_pad, hipStream_t s);
-hipError_t launch_fft_pass(const FftPassArgs& a, long n_outer, hipStream_t s);
-hipError_t launch_fourier_factor(const double* U, int r, int off, int m, int L, int nf, double* Uh, hipStream_t s);
+// Hs[f1][f0][c] = sum_b Uh1[f1][b] M1[f0][b][c] (c < r2), 0 for r2 <= c < r2p (Uh1: L1 x r1,
+// M1: L0 x r1 x r2, FP64; Hs: L1 x L0 x r2p, FP32).  r1 <= 48, r2 <= r2p <= 256.
+hipError_t launch_spectral_core(const double* Uh1, const double* M1, int L0, int L1, int r1, int r2, int r2p,
+                                float* Hs, hipStream_t s);
+// blocks (optional): the number of work-groups launched (partials written with dot_part)
+hipError_t launch_fft_pass(const FftPassArgs& a, long n_outer, hipStream_t s, unsigned* blocks = nullptr);
+// Fourier-side factors of the three axes: ax[k].Uh[f][a] = u_a[off] + 2 sum_{t=1}^{m-1}
+// u_a[off + t] cos(2 pi f t / L), f < nf, a < r (U: n x r, Uh: nf x r, FP64; L a power of two
+// <= 2048, m <= L).
+struct FourierAxis {
+    const double* U; int r, off, m, L, nf; double* Uh;
+};
+struct FourierAxes {
+    FourierAxis ax[3];
+};
+hipError_t launch_fourier_factors(const FourierAxes& fa, hipStream_t s);
 hipError_t fft_set_attributes();
 
 // ------------------------------------------------------------ small scalar kernels ----

@@ -355,8 +355,10 @@ def test_matvec_fft_matches_oracle_and_dense(ctx, tk, oracle, layout, n):
 
 
 def test_quadratic_form_batch_matches_single(ctx, tk):
-    """The batch runs its items concurrently on the worker streams; every value (and y, when
-    given) is bitwise the single call's."""
+    """FFT path: the batch runs the preambles on a worker stream and the passes of the items in
+    turn with shared spectrum buffers; dense path: items concurrently on the worker streams.
+    Every value (and y, when given) is bitwise the single call's, and a single call without y
+    (C z never stored) gives the same value as with it."""
     opts = tk.make_opts(eps=1e-6, hooi_sweeps=2, prec=1)
     ts = [ctx.compress(tk.make_kernel(0, nu=nu, ell=ell), tk.make_grid(n, 1.0, lay), opts)
           for (n, nu, ell, lay) in [(64, 0.5, 0.2, 1), (96, 1.5, 0.3, 1), (65, 2.5, 0.5, 0), (64, 1.5, 1.0, 1)]]
@@ -373,5 +375,15 @@ def test_quadratic_form_batch_matches_single(ctx, tk):
         assert ctx.quadratic_form_batch(ts, zs, ys=ys) == single
         assert all(np.array_equal(host(y), ya) for y, ya in zip(ys, ys_single))
     ctx.set_workers(4)
+    assert [ctx.quadratic_form(t, z) for t, z in zip(ts, zs)] == single
+    # mixed shapes in a different order: the shared buffers are sized for the largest item
+    order = [3, 1, 0, 2]
+    assert ctx.quadratic_form_batch([ts[i] for i in order], [zs[i] for i in order]) == [single[i] for i in order]
+    ctx.set_matvec_method(tk.TK_MV_DENSE)
+    try:
+        dense = [ctx.quadratic_form(t, z) for t, z in zip(ts[:2], zs[:2])]
+        assert ctx.quadratic_form_batch(ts[:2], zs[:2]) == dense
+    finally:
+        ctx.set_matvec_method(tk.TK_MV_AUTO)
     for t in ts:
         t.free()
