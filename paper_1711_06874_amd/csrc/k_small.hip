@@ -2,103 +2,118 @@
 // contractions of the HOOI sweep with the small factors, small Gram matrices B B^T, the
 // eigensolver's G Q products, core contractions, conversions and FP64 dot products.
 //
-// The products are batched, with arbitrary element strides on every operand, FP64
-// accumulation and a 32 x 32 output tile per 256-thread work-group (2 x 2 outputs per
-// thread); operands are staged through LDS in 64-deep K chunks, the next chunk being loaded into
-// registers while the current one is multiplied.
+// The products are batched, with arbitrary element strides on every operand and FP64
+// accumulation on mfma_f64_16x16x4f64: one wavefront computes a (16 TM) x (16 TN) block of one
+// item's output (TM, TN in {1, 2}, chosen from M and N so that small ranks do not pay for a
+// 32 x 32 block).  Operands are read straight from memory (they are small and cached), four
+// k-steps of 4 at a time, all loads of a group issued before its products; lane l supplies
+// A[m0 + l % 16][k + l / 16] and B[k + l / 16][n0 + l % 16] and receives the outputs of rows
+// 4 v + l / 16, column l % 16 of each 16 x 16 tile.  The sum over k (and, in the batch-reducing
+// form, over the batch, outermost) runs in a fixed order.
 #include "tk_kernels.h"
 
 namespace tk {
 
 namespace {
-constexpr int GT = 32;   // output tile edge
-constexpr int GK = 64;   // K chunk
+constexpr int GKU = 4;   // k-steps of 4 whose operands are loaded together
 }
 
-template <typename TA, typename TB, typename TC>
-__global__ void __launch_bounds__(256) k_gemm(GemmArgs g)
+template <typename TA, typename TB, typename TC, int TM, int TN>
+__global__ void __launch_bounds__(64) k_gemm(GemmArgs g)
 {
-    constexpr int PER = GT * GK / 256;     // elements of each operand a thread stages per chunk
-    __shared__ double As[GK][GT + 1];
-    __shared__ double Bs[GK][GT + 1];
     g.A = bshift(g.A, g.bs);
     g.B = bshift(g.B, g.bs);
     g.C = bshift(g.C, g.bs);
-    const int tid = threadIdx.x;
-    const int tiles_n = (g.N + GT - 1) / GT;
+    const int lane = threadIdx.x;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int tiles_n = (g.N + 16 * TN - 1) / (16 * TN);
     const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
-    const int m0 = tm * GT, n0 = tn * GT;
-    const int tx = tid % 16, ty = tid / 16;           // outputs (m0 + ty + 16i, n0 + tx + 16j)
-    double acc[2][2] = {{0, 0}, {0, 0}};
+    const int m0 = tm * 16 * TM, n0 = tn * 16 * TN;
     // batch-reducing form: one output, the batch loop runs inside (fixed order)
     const long b_first = g.reduce_batch ? 0 : (long)blockIdx.y;
     const long b_last = g.reduce_batch ? (long)g.batch : (long)blockIdx.y + 1;
     TC* C = (TC*)g.C + (g.reduce_batch ? 0 : (long)blockIdx.y * g.sCb);
-    const int kchunks = (g.K + GK - 1) / GK;
-    const long nchunks = (b_last - b_first) * kchunks;
-    // staging positions: consecutive threads walk the unit-stride index of each operand
-    int am[PER], ak[PER], bn[PER], bk[PER];
+    bool mv[TM], nv[TN];
+    long aoff[TM], boff[TN];
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-        const int idx = tid + e * 256;
-        if (g.sAm == 1) { am[e] = idx % GT; ak[e] = idx / GT; } else { ak[e] = idx % GK; am[e] = idx / GK; }
-        if (g.sBn == 1) { bn[e] = idx % GT; bk[e] = idx / GT; } else { bk[e] = idx % GK; bn[e] = idx / GK; }
+    for (int i = 0; i < TM; ++i) {
+        const int gm = m0 + 16 * i + lr;
+        mv[i] = gm < g.M;
+        aoff[i] = (long)(mv[i] ? gm : 0) * g.sAm;
     }
-    double ra[PER], rb[PER];
-    auto load = [&](long q) {
-        const long b = b_first + q / kchunks;
-        const int k0 = (int)(q % kchunks) * GK;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+        const int gn = n0 + 16 * j + lr;
+        nv[j] = gn < g.N;
+        boff[j] = (long)(nv[j] ? gn : 0) * g.sBn;
+    }
+    f64x4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (long b = b_first; b < b_last; ++b) {
         const TA* A = (const TA*)g.A + b * g.sAb;
         const TB* B = (const TB*)g.B + b * g.sBb;
+        for (int k0 = 0; k0 < g.K; k0 += 4 * GKU) {
+            double av[GKU][TM], bv[GKU][TN];
 #pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            const int gm = m0 + am[e], gk = k0 + ak[e];
-            ra[e] = (gm < g.M && gk < g.K) ? (double)A[(long)gm * g.sAm + (long)gk * g.sAk] : 0.0;
-            const int gn = n0 + bn[e], gk2 = k0 + bk[e];
-            rb[e] = (gn < g.N && gk2 < g.K) ? (double)B[(long)gk2 * g.sBk + (long)gn * g.sBn] : 0.0;
-        }
-    };
-    if (nchunks > 0) load(0);
-    for (long q = 0; q < nchunks; ++q) {
+            for (int u = 0; u < GKU; ++u) {
+                const int k = k0 + 4 * u + lk;
+                const bool kv = k < g.K;
 #pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            As[ak[e]][am[e]] = ra[e];
-            Bs[bk[e]][bn[e]] = rb[e];
-        }
-        __syncthreads();
-        if (q + 1 < nchunks) load(q + 1);     // in flight while this chunk is multiplied
-#pragma unroll 16
-        for (int kk = 0; kk < GK; ++kk) {
-            const double a0 = As[kk][ty], a1 = As[kk][ty + 16];
-            const double b0 = Bs[kk][tx], b1 = Bs[kk][tx + 16];
-            acc[0][0] += a0 * b0; acc[0][1] += a0 * b1;
-            acc[1][0] += a1 * b0; acc[1][1] += a1 * b1;
-        }
-        __syncthreads();
-    }
+                for (int i = 0; i < TM; ++i) av[u][i] = (kv && mv[i]) ? (double)A[aoff[i] + (long)k * g.sAk] : 0.0;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < TN; ++j) bv[u][j] = (kv && nv[j]) ? (double)B[(long)k * g.sBk + boff[j]] : 0.0;
+            }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int gm = m0 + ty + 16 * i, gn = n0 + tx + 16 * j;
-            if (gm < g.M && gn < g.N) {
-                TC* c = C + (long)gm * g.sCm + (long)gn * g.sCn;
-                double v = g.alpha * acc[i][j];
-                if (g.beta != 0.0) v += g.beta * (double)(*c);
-                *c = (TC)v;
+            for (int u = 0; u < GKU; ++u) {
+                if (k0 + 4 * u < g.K) {
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][i], bv[u][j], acc[i][j], 0, 0, 0);
+                }
             }
         }
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gm = m0 + 16 * i + 4 * v + lk, gn = n0 + 16 * j + lr;
+                if (gm < g.M && gn < g.N) {
+                    TC* c = C + (long)gm * g.sCm + (long)gn * g.sCn;
+                    double val = g.alpha * acc[i][j][v];
+                    if (g.beta != 0.0) val += g.beta * (double)(*c);
+                    *c = (TC)val;
+                }
+            }
+}
+
+template <typename TA, typename TB, typename TC, int TM, int TN>
+static hipError_t launch_gemm_tiles(const GemmArgs& a, hipStream_t s)
+{
+    const long tiles = (long)((a.M + 16 * TM - 1) / (16 * TM)) * ((a.N + 16 * TN - 1) / (16 * TN));
+    const unsigned gy = a.reduce_batch ? 1u : (unsigned)a.batch;
+    const unsigned gz = a.nb > 1 ? (unsigned)a.nb : 1u;
+    hipLaunchKernelGGL((k_gemm<TA, TB, TC, TM, TN>), dim3((unsigned)tiles, gy, gz), dim3(64), 0, s, a);
+    return hipGetLastError();
 }
 
 template <typename TA, typename TB, typename TC>
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s)
 {
     if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return hipSuccess;
-    long tiles = (long)((a.M + GT - 1) / GT) * ((a.N + GT - 1) / GT);
-    unsigned gy = a.reduce_batch ? 1u : (unsigned)a.batch;
-    const unsigned gz = a.nb > 1 ? (unsigned)a.nb : 1u;
-    hipLaunchKernelGGL((k_gemm<TA, TB, TC>), dim3((unsigned)tiles, gy, gz), dim3(256), 0, s, a);
-    return hipGetLastError();
+    if (!a.reduce_batch && a.batch > 65535) return hipErrorInvalidValue;
+    const bool wm = a.M > 16, wn = a.N > 16;
+    if (wm && wn) return launch_gemm_tiles<TA, TB, TC, 2, 2>(a, s);
+    if (wm) return launch_gemm_tiles<TA, TB, TC, 2, 1>(a, s);
+    if (wn) return launch_gemm_tiles<TA, TB, TC, 1, 2>(a, s);
+    return launch_gemm_tiles<TA, TB, TC, 1, 1>(a, s);
 }
 
 template hipError_t launch_gemm<double, double, double>(const GemmArgs&, hipStream_t);
