@@ -154,8 +154,9 @@ tk_status tk_compress_tensor(tk_ctx *ctx, const void *A_dev, const tk_grid *grid
 
 /* Compress `count` independent problems (kernels[i] on grids[i], sizes may differ, all with
  * *opts) in one call.  Problems on the same grid share their launches: up to 32 of them (fewer
- * if the HBM budget asks; a larger group is split into up to tk_ctx_set_workers near-equal
- * parts of at least three problems, which run concurrently) run every step of the pipeline as one launch whose
+ * if the HBM budget asks; a group is also split into near-equal parts of at least three
+ * problems, up to its share of the tk_ctx_set_workers streams in proportion to its problems,
+ * which run concurrently) run every step of the pipeline as one launch whose
  * third grid dimension walks the problems, so one eigensolve or Gram launch serves them all.  Such groups
  * (and problems that run alone: other grids, or the FP64 eps path, which reads ranks back
  * between steps) run concurrently, largest first, on the context's worker streams

@@ -1997,10 +1997,11 @@ tk_status tk_compress_batch(tk_ctx* ctx, int count, const tk_kernel* kernels, co
                     }
                 }
             }
-            // a large group is also split over the worker streams (at least 3 problems per part):
-            // the latency-bound steps of one part (eigensolver panels, small products) then
-            // overlap the streaming steps of the others
-            const int nchunk = std::max((m + cap - 1) / cap, std::min(ctx->workers, m / 3));
+            // a group is also split into its share of the worker streams (in proportion to its
+            // problems, at least 3 per part): the latency-bound steps of one part (eigensolver
+            // panels, small products) then overlap the streaming steps of the others
+            const int share = (int)(((long)ctx->workers * m + count - 1) / count);
+            const int nchunk = std::max((m + cap - 1) / cap, std::min(share, m / 3));
             const double per = (double)grids[i].n[0] * grids[i].n[1] * grids[i].n[2];
             for (int c = 0, pos = 0; c < nchunk; ++c) {
                 const int len = m / nchunk + (c < m % nchunk ? 1 : 0);
