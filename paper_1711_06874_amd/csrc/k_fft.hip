@@ -304,6 +304,79 @@ __device__ __forceinline__ void chat_table(float* ct, float* u3s, long o, int i0
     }
 }
 
+// The same table when the Uh3 rows sit in LDS already (u3s, staged with the chunk's tile), in two
+// steps so that the Hs operands can be requested before the barrier that publishes u3s:
+// chat_hs_load issues this wavefront's Hs loads (its tiles t = wv, wv + NW, ...), chat_products
+// takes the Uh3 operands from u3s and writes ct.  Same products in the same order as chat_table.
+template <int LOGL>
+struct ChatRegs {
+    static constexpr int TPW = ((Shape<LOGL>::F + 15) / 16 * ((Shape<LOGL>::L + 15) / 16) + Shape<LOGL>::NW - 1) /
+                               Shape<LOGL>::NW;    // tiles per wavefront
+    float4 bv[TPW][3];
+};
+
+template <int LOGL>
+__device__ __forceinline__ void chat_hs_load(ChatRegs<LOGL>& cr, long o, int r2p, const float* __restrict__ Hs)
+{
+    using Sh = Shape<LOGL>;
+    constexpr int L = Sh::L, F = Sh::F, NW = Sh::NW;
+    constexpr int TR = (F + 15) / 16, TC = (L + 15) / 16;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
+#pragma unroll
+    for (int u = 0; u < ChatRegs<LOGL>::TPW; ++u) {
+        const int t = wv + NW * u;
+        const int tc = t / TR;
+        const int f0 = 16 * tc + lr;
+        const bool live = t < TR * TC && f0 < L;
+        const float* hrow = Hs + ((long)o * L + (live ? f0 : 0)) * r2p;
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            const int c = 16 * g + 4 * lq;
+            cr.bv[u][g] = (live && c < r2p) ? *reinterpret_cast<const float4*>(hrow + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+}
+
+template <int LOGL>
+__device__ __forceinline__ void chat_products(float* ct, const float* u3s, const ChatRegs<LOGL>& cr, int r2p)
+{
+    using Sh = Shape<LOGL>;
+    constexpr int L = Sh::L, F = Sh::F, NW = Sh::NW, CS = Sh::CS;
+    constexpr int TR = (F + 15) / 16, TC = (L + 15) / 16;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
+#pragma unroll
+    for (int u = 0; u < ChatRegs<LOGL>::TPW; ++u) {
+        const int t = wv + NW * u;
+        if (t >= TR * TC) break;
+        const int tr = t % TR, tc = t / TR;
+        const int ff = 16 * tr + lr, f0 = 16 * tc + lr;
+        const float* urow = u3s + (ff < F ? ff : 0) * r2p;
+        float4 av[3];
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            const int c = 16 * g + 4 * lq;
+            av[g] = (c < r2p && ff < F) ? *reinterpret_cast<const float4*>(urow + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            if (16 * g < r2p) {
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].x, cr.bv[u][g].x, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].y, cr.bv[u][g].y, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].z, cr.bv[u][g].z, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[g].w, cr.bv[u][g].w, acc, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * tr + 4 * lq + v;
+            if (row < F && f0 < L) ct[row * CS + f0] = acc[v];
+        }
+    }
+}
+
 // Pass kinds
 enum { PK_R2C = 0, PK_FWD = 1, PK_CORE = 2, PK_INV = 3, PK_C2R = 4 };
 
@@ -362,8 +435,20 @@ __global__ void __launch_bounds__(Shape<LOGL>::NT) k_fft_pass(FftPassArgs a)
     // mode 2 with dot_part: the z values of the next chunk's outputs (rows ra, rb), fetched with it
     constexpr int VZ = (PK == PK_C2R) ? V / 2 : 1;
     float zpa[VZ], zpb[VZ];
+    // P3 with staged Uh3 rows (when at most two multiplier tiles fall to a wavefront): the next
+    // chunk's rows (F x r2p, r2p <= 48), fetched with its tile
+    constexpr bool STAGED = (PK == PK_CORE) && Sh::STAGE_U3 && ChatRegs<LOGL>::TPW <= 2;
+    constexpr int UPT = STAGED ? (F * 48 + NT - 1) / NT : 1;
+    float upre[UPT];
     auto fetch = [&](const Chunk& ch) {
         const int nf = (nfib - ch.i0 < F) ? (nfib - ch.i0) : F;
+        if constexpr (STAGED) {
+#pragma unroll
+            for (int j = 0; j < UPT; ++j) {
+                const int e = tid + NT * j;
+                upre[j] = (e < nf * a.r2p) ? a.Uh3[(long)ch.i0 * a.r2p + e] : 0.f;
+            }
+        }
         if constexpr (CONTIG) {
             const long ra = 2L * (ch.i0 + f), rb = ra + 1;
             const bool la = f < nf && ra < a.n_inner, lb = f < nf && rb < a.n_inner;
@@ -426,6 +511,7 @@ __global__ void __launch_bounds__(Shape<LOGL>::NT) k_fft_pass(FftPassArgs a)
         const int nf = (nfib - i0 < F) ? (nfib - i0) : F;
         float2 x[V];
         float zca[VZ], zcb[VZ];
+        bool more;
         if constexpr (CONTIG) {
 #pragma unroll
             for (int v = 0; v < V; ++v) x[v] = pre[v];
@@ -436,7 +522,14 @@ __global__ void __launch_bounds__(Shape<LOGL>::NT) k_fft_pass(FftPassArgs a)
                     zcb[v] = zpb[v];
                 }
             }
+            // the next chunk's loads are in flight while this one is transformed
+            more = chunk_at<F>(j + 1, nbx, a.n_outer, xcd_planes, &ch);
+            if (more) fetch(ch);
         } else {
+            ChatRegs<LOGL> cr;
+            // the Hs operands of this chunk's multiplier table are requested first; they arrive
+            // while the tile and the Uh3 rows are written to LDS
+            if constexpr (STAGED) chat_hs_load<LOGL>(cr, o, a.r2p, a.Hs);
             __syncthreads();          // the previous chunk has finished reading the tile
 #pragma unroll
             for (int t = 0; t < Sh::QT; ++t) {
@@ -444,14 +537,24 @@ __global__ void __launch_bounds__(Shape<LOGL>::NT) k_fft_pass(FftPassArgs a)
                 const int ff = e & (F - 1), k = e / F;
                 if (k < KIN) fsm[ff * LB + pos(k)] = pre[t];
             }
-        }
-        // the next chunk's loads are in flight while this one is transformed
-        const bool more = chunk_at<F>(j + 1, nbx, a.n_outer, xcd_planes, &ch);
-        if (more) fetch(ch);
-        if constexpr (!CONTIG) {
-            if constexpr (PK == PK_CORE)
-                chat_table<LOGL>(reinterpret_cast<float*>(fsm + F * LB),
-                                 reinterpret_cast<float*>(fsm + F * LB) + F * Sh::CS, o, i0, nf, a.r2p, a.Hs, a.Uh3);
+            float* const ctab = reinterpret_cast<float*>(fsm + F * LB);
+            float* const u3s = ctab + F * Sh::CS;
+            if constexpr (STAGED) {
+#pragma unroll
+                for (int jj = 0; jj < UPT; ++jj) {
+                    const int e = tid + NT * jj;
+                    if (e < F * 48) u3s[e] = upre[jj];
+                }
+            }
+            // the next chunk's loads are in flight while this one is transformed
+            more = chunk_at<F>(j + 1, nbx, a.n_outer, xcd_planes, &ch);
+            if (more) fetch(ch);
+            if constexpr (STAGED) {
+                __syncthreads();      // tile and Uh3 rows published
+                chat_products<LOGL>(ctab, u3s, cr, a.r2p);
+            } else if constexpr (PK == PK_CORE) {
+                chat_table<LOGL>(ctab, u3s, o, i0, nf, a.r2p, a.Hs, a.Uh3);
+            }
             __syncthreads();
 #pragma unroll
             for (int v = 0; v < VIN; ++v) x[v] = fb[pos(p + P * v)];
