@@ -62,6 +62,8 @@ struct Shape {
     static constexpr size_t LDS_TILE = sizeof(float2) * (size_t)F * LB;
     static constexpr bool STAGE_U3 = LDS_TILE + sizeof(float) * (size_t)F * (CS + 48) <= 150 * 1024;
     static constexpr size_t LDS_CORE = LDS_TILE + sizeof(float) * (size_t)F * (CS + (STAGE_U3 ? 48 : 0));
+    // the other passes keep the L twiddles in LDS after the tile (P3 holds its own in registers)
+    static constexpr size_t LDS_PASS = LDS_TILE + sizeof(float2) * (size_t)L;
 };
 
 // log2 of the radix of stage s: 3 while at least 3 bits remain, then the rest
@@ -426,6 +428,16 @@ __global__ void __launch_bounds__(Shape<LOGL>::NT) k_fft_pass(FftPassArgs a)
     float2* fb = fsm + f * LB;
     TwRegs<LOGL, PK == PK_CORE> tr;
     load_twiddles<LOGL, PK == PK_CORE>(tr, p, a.tw);
+    // passes other than P3 read their twiddles from an LDS copy of the table (written before the
+    // first barrier of the chunk loop; contiguous passes, which have none before their first
+    // transform, wait here); P3 keeps them in registers, or reads the global table for long L
+    const float2* twp = a.tw;
+    if constexpr (PK != PK_CORE) {
+        float2* tws = fsm + (size_t)F * LB;
+        for (int qq = tid; qq < L; qq += NT) tws[qq] = a.tw[qq];
+        if constexpr (CONTIG) __syncthreads();
+        twp = tws;
+    }
 
     // ---- loads of one chunk into registers: rows of the pair (contiguous) or the tile (strided)
     constexpr int KIN = (PK == PK_INV) ? L : L / 2;    // forward passes: only the lower half is non-zero
@@ -564,18 +576,18 @@ __global__ void __launch_bounds__(Shape<LOGL>::NT) k_fft_pass(FftPassArgs a)
 
         // ------------------------------------------------------------ transform(s)
         if constexpr (PK == PK_R2C || PK == PK_FWD) {
-            fft_stages<LOGL, 0, false, true>(x, fb, p, a.tw, tr);
+            fft_stages<LOGL, 0, false, true>(x, fb, p, twp, tr);
         } else if constexpr (PK == PK_CORE) {
-            fft_stages<LOGL, 0, false, true>(x, fb, p, a.tw, tr);
+            fft_stages<LOGL, 0, false, true>(x, fb, p, twp, tr);
             const float* ct = reinterpret_cast<const float*>(fsm + F * LB) + f * Sh::CS;
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const float c = ct[p + P * v];
                 x[v] = make_float2(x[v].x * c, x[v].y * c);
             }
-            fft_stages<LOGL, 0, true, false>(x, fb, p, a.tw, tr);
+            fft_stages<LOGL, 0, true, false>(x, fb, p, twp, tr);
         } else {
-            fft_stages<LOGL, 0, true, false>(x, fb, p, a.tw, tr);
+            fft_stages<LOGL, 0, true, false>(x, fb, p, twp, tr);
         }
 
         // ------------------------------------------------------------ store
@@ -812,7 +824,7 @@ hipError_t launch_len(FftPassArgs a, int kind, long n_outer, hipStream_t s, unsi
     const dim3 grid((unsigned)(chunks < slots ? chunks : slots));
     if (blocks) *blocks = grid.x;
     a.n_outer = n_outer;
-    const size_t lds = (kind == PK_CORE) ? Sh::LDS_CORE : Sh::LDS_TILE;
+    const size_t lds = (kind == PK_CORE) ? Sh::LDS_CORE : Sh::LDS_PASS;
     switch (kind) {
     case PK_R2C: hipLaunchKernelGGL((k_fft_pass<LOGL, PK_R2C>), grid, dim3(Sh::NT), lds, s, a); break;
     case PK_FWD: hipLaunchKernelGGL((k_fft_pass<LOGL, PK_FWD>), grid, dim3(Sh::NT), lds, s, a); break;
@@ -827,7 +839,7 @@ template <int LOGL>
 hipError_t set_attrs_len()
 {
     using Sh = Shape<LOGL>;
-    const int lds = (int)Sh::LDS_TILE;
+    const int lds = (int)Sh::LDS_PASS;
     const int lds_core = (int)Sh::LDS_CORE;
     const void* ks[] = {(const void*)k_fft_pass<LOGL, PK_R2C>, (const void*)k_fft_pass<LOGL, PK_FWD>,
                         (const void*)k_fft_pass<LOGL, PK_CORE>, (const void*)k_fft_pass<LOGL, PK_INV>,
