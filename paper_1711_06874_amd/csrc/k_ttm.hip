@@ -6,7 +6,8 @@
 //   recon_diff: sum over A of (A - H U^T)^2 and A^2,    H = G x_1 U1 x_2 U2 as (n0 n1) x r
 //
 // All three read A exactly once with coalesced loads.  The TTMs stage 64 x 64 float tiles in
-// LDS and contract them on FP32 MFMA (16x16x4) with FP32 accumulation; the error norm
+// LDS (the next tile and U chunk are loaded into registers while the current one is multiplied)
+// and contract them on FP32 MFMA (16x16x4) with FP32 accumulation; the error norm
 // reconstructs A on FP64 MFMA.  The rank dimension r is covered by NB = ceil(r/16) blocks of
 // 16.  The error sums are accumulated per thread in FP64 and reduced in a fixed order (per
 // work-group partials, then one ordered pass).
@@ -20,31 +21,68 @@ constexpr int TR = 64;       // rows (or columns) of A per work-group
 constexpr int BK = 64;       // contraction chunk
 constexpr int LDA = BK + 4;  // LDS pitch: lanes of one MFMA operand read hit distinct banks
 
-// Stage a TR x BK float tile of a row-major matrix (row pitch ld) into S[TR][LDA];
-// rows >= nrows or columns >= ncols read as zero.
-__device__ __forceinline__ void stage_tile(float (*S)[LDA], const float* __restrict__ X, long ld, long row0,
-                                           long nrows, long col0, long ncols, int tid)
+// A TR x BK float tile of a row-major matrix (row pitch ld), four float4 per thread: loaded into
+// registers (tile_load, rows >= nrows or columns >= ncols read as zero) while the previous tile
+// is multiplied, then written to S[TR][LDA] (tile_store).
+constexpr int TQ = (TR * BK / 4) / 256;      // float4 per thread
+
+__device__ __forceinline__ void tile_load(float4 (&v)[TQ], const float* __restrict__ X, long ld, long row0,
+                                          long nrows, long col0, long ncols, int tid)
 {
     const bool vec = ((ld & 3) == 0) && ((col0 & 3) == 0);
 #pragma unroll
-    for (int e = 0; e < (TR * BK / 4) / 256; ++e) {
+    for (int e = 0; e < TQ; ++e) {
         int q = tid + 256 * e;           // float4 index within the tile
         int r = q / (BK / 4), c4 = (q % (BK / 4)) * 4;
         long gr = row0 + r, gc = col0 + c4;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        v[e] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (gr < nrows) {
             const float* p = X + gr * ld + gc;
-            if (vec && gc + 3 < ncols) v = *reinterpret_cast<const float4*>(p);
+            if (vec && gc + 3 < ncols) v[e] = *reinterpret_cast<const float4*>(p);
             else {
-                if (gc + 0 < ncols) v.x = p[0];
-                if (gc + 1 < ncols) v.y = p[1];
-                if (gc + 2 < ncols) v.z = p[2];
-                if (gc + 3 < ncols) v.w = p[3];
+                if (gc + 0 < ncols) v[e].x = p[0];
+                if (gc + 1 < ncols) v[e].y = p[1];
+                if (gc + 2 < ncols) v[e].z = p[2];
+                if (gc + 3 < ncols) v[e].w = p[3];
             }
         }
-        *reinterpret_cast<float4*>(&S[r][c4]) = v;
     }
 }
+
+__device__ __forceinline__ void tile_store(float (*S)[LDA], const float4 (&v)[TQ], int tid)
+{
+#pragma unroll
+    for (int e = 0; e < TQ; ++e) {
+        int q = tid + 256 * e;
+        int r = q / (BK / 4), c4 = (q % (BK / 4)) * 4;
+        *reinterpret_cast<float4*>(&S[r][c4]) = v[e];
+    }
+}
+
+// The BK x NB*16 chunk of U (n x r row-major) from row k0, zero beyond n and r: UQ values per
+// thread, loaded with the A tile and stored beside it.
+template <int NB>
+struct UChunk {
+    static constexpr int UQ = (BK * NB * 16 + 255) / 256;
+    float v[UQ];
+    __device__ __forceinline__ void load(const float* __restrict__ U, int k0, int n, int r, int tid)
+    {
+#pragma unroll
+        for (int i = 0; i < UQ; ++i) {
+            const int e = tid + 256 * i;
+            const int kk = e / (NB * 16), j = e % (NB * 16);
+            v[i] = (e < BK * NB * 16 && k0 + kk < n && j < r) ? U[(long)(k0 + kk) * r + j] : 0.f;
+        }
+    }
+    __device__ __forceinline__ void store(float (*Us)[NB * 16], int tid) const
+    {
+#pragma unroll
+        for (int i = 0; i < UQ; ++i) {
+            const int e = tid + 256 * i;
+            if (e < BK * NB * 16) Us[e / (NB * 16)][e % (NB * 16)] = v[i];
+        }
+    }
+};
 
 // T = A x_3 U^T.  Work-group: 64 rows of A (4 waves x 16 rows); U chunk in LDS.
 template <int NB>
@@ -62,13 +100,18 @@ __global__ void __launch_bounds__(256) k_ttm_last(const float* __restrict__ A, l
     f32x4 acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float4 tv[TQ];
+    UChunk<NB> uc;
+    tile_load(tv, A, n2, row0, rows, 0, n2, tid);
+    uc.load(U, 0, n2, r, tid);
     for (int k0 = 0; k0 < n2; k0 += BK) {
-        stage_tile(As, A, n2, row0, rows, k0, n2, tid);
-        for (int e = tid; e < BK * NB * 16; e += 256) {
-            int kk = e / (NB * 16), j = e % (NB * 16);
-            Us[kk][j] = (k0 + kk < n2 && j < r) ? U[(long)(k0 + kk) * r + j] : 0.f;
-        }
+        tile_store(As, tv, tid);
+        uc.store(Us, tid);
         __syncthreads();
+        if (k0 + BK < n2) {            // the next chunk is in flight while this one is multiplied
+            tile_load(tv, A, n2, row0, rows, k0 + BK, n2, tid);
+            uc.load(U, k0 + BK, n2, r, tid);
+        }
 #pragma unroll 4
         for (int ks = 0; ks < BK; ks += 4) {
             float a = As[16 * w + (lane & 15)][ks + (lane >> 4)];
@@ -106,13 +149,18 @@ __global__ void __launch_bounds__(256) k_ttm_first(const float* __restrict__ A, 
     f32x4 acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float4 tv[TQ];
+    UChunk<NB> uc;
+    tile_load(tv, A, cols, 0, n0, col0, cols, tid);
+    uc.load(U, 0, n0, r, tid);
     for (int k0 = 0; k0 < n0; k0 += BK) {
-        stage_tile(As, A, cols, k0, n0, col0, cols, tid);
-        for (int e = tid; e < BK * NB * 16; e += 256) {
-            int kk = e / (NB * 16), j = e % (NB * 16);
-            Us[kk][j] = (k0 + kk < n0 && j < r) ? U[(long)(k0 + kk) * r + j] : 0.f;
-        }
+        tile_store(As, tv, tid);
+        uc.store(Us, tid);
         __syncthreads();
+        if (k0 + BK < n0) {            // the next chunk is in flight while this one is multiplied
+            tile_load(tv, A, cols, k0 + BK, n0, col0, cols, tid);
+            uc.load(U, k0 + BK, n0, r, tid);
+        }
 #pragma unroll 4
         for (int ks = 0; ks < BK; ks += 4) {
             // B operand: A[k][col], k = ks + lane/16, col = 16w + lane%16
