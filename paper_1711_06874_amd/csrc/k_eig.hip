@@ -788,7 +788,11 @@ hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s)
     gq.nb = bt.nb; gq.bs = bt.bs;
     if (p < n) {
         const bool start_orthonormal = b.warm && b.rw == p;   // previous factor, no extra columns
-        if (!start_orthonormal && (e = qr_launch(b.Q, b.Q, b.count, n, p, s, bt)) != hipSuccess) return e;
+        // a span-only iteration needs no orthonormal start: G times the random block spans the
+        // same space as G times its orthonormalisation, and every iteration ends with a QR
+        const bool skip_start_qr = b.span_only && !b.warm && iters > 0;
+        if (!start_orthonormal && !skip_start_qr && (e = qr_launch(b.Q, b.Q, b.count, n, p, s, bt)) != hipSuccess)
+            return e;
         for (int it = 0; it < iters; ++it) {
             if ((e = launch_gemm<double, double, double>(gq, s)) != hipSuccess) return e;
             if ((e = qr_launch(b.Y, b.Q, b.count, n, p, s, bt)) != hipSuccess) return e;
