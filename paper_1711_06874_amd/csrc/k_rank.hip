@@ -78,6 +78,51 @@ hipError_t launch_copy_block(const TI* X, int D1, int D2, TO* Y, int d0, int d1,
 template hipError_t launch_copy_block<double, double>(const double*, int, int, double*, int, int, int, hipStream_t);
 template hipError_t launch_copy_block<double, float>(const double*, int, int, float*, int, int, int, hipStream_t);
 
+__global__ void __launch_bounds__(256) k_extract_results(ExtractArgs a)
+{
+    const int b = blockIdx.z;
+    const ResultDst& d = a.dst[b];
+    const long e0 = (long)a.n[0] * d.r[0], e1 = e0 + (long)a.n[1] * d.r[1], e2 = e1 + (long)a.n[2] * d.r[2];
+    const long tot = e2 + (long)d.r[0] * d.r[1] * d.r[2];
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+        if (e < e2) {
+            const int k = (e < e0) ? 0 : (e < e1 ? 1 : 2);
+            const long f = e - (k == 0 ? 0 : (k == 1 ? e0 : e1));
+            const int r = d.r[k];
+            const long i = f / r;
+            const int c = (int)(f - i * r);
+            const double v = bshift(a.Usrc[k], a.bs)[i * a.ld[k] + c];      // problem b = blockIdx.z
+            d.U[k][f] = v;
+            d.U32[k][f] = (float)v;
+        } else {
+            const long f = e - e2;
+            const int d12 = d.r[1] * d.r[2];
+            const int x = (int)(f / d12), rem = (int)(f - (long)x * d12);
+            const int y = rem / d.r[2], z = rem - y * d.r[2];
+            const double v = bshift(a.core_src, a.bs)[((long)x * a.Rc[1] + y) * a.Rc[2] + z];
+            d.core[f] = v;
+            d.core32[f] = (float)v;
+        }
+    }
+}
+
+hipError_t launch_extract_results(const ExtractArgs& a, hipStream_t s)
+{
+    if (a.nb < 1 || a.nb > BATCH_MAX) return hipErrorInvalidValue;
+    long most = 0;
+    for (int b = 0; b < a.nb; ++b) {
+        const ResultDst& d = a.dst[b];
+        long tot = (long)d.r[0] * d.r[1] * d.r[2];
+        for (int k = 0; k < 3; ++k) tot += (long)a.n[k] * d.r[k];
+        most = tot > most ? tot : most;
+    }
+    if (most <= 0) return hipSuccess;
+    long blocks = (most + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_extract_results, dim3((unsigned)blocks, 1, a.nb), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_rank_rule(const double* lam, long sLam, int len, int count, const double* total, long sTotal,
                             const double* scal, int has_d2, double eps2, int* ranks, int* ok, hipStream_t s, Bat bt)
 {

@@ -1174,27 +1174,41 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void
     auto drop_all = [&]() {
         for (int b = 0; b < nb; ++b) { free_result(outs[b]); outs[b] = nullptr; }
     };
-    const int ld[3] = {P.R[0], P.R[1], P.R[2]};
-    const int Rc[3] = {P.R[0], P.R[1], P.R[2]};
+    // all results first, then one launch copies every problem's factors and core into them
+    ExtractArgs ea{};
+    ea.nb = nb;
+    ea.bs = (long)ws;
+    ea.core_src = csrc;
+    for (int k = 0; k < 3; ++k) {
+        ea.n[k] = P.n[k];
+        ea.ld[k] = P.R[k];
+        ea.Rc[k] = P.R[k];
+        ea.Usrc[k] = Usrc[k];
+    }
     for (int b = 0; b < nb; ++b) {
-        const long off = (long)b * (long)ws;
         int final_r[3];
-        const double* Ub[3];
-        for (int k = 0; k < 3; ++k) {
-            final_r[k] = hr[(size_t)b * 8 + k];
-            Ub[k] = (const double*)((const char*)Usrc[k] + off);
-        }
-        const double* cb = (const double*)((const char*)csrc + off);
+        for (int k = 0; k < 3; ++k) final_r[k] = hr[(size_t)b * 8 + k];
         tk_tucker* t = nullptr;
         if ((st = alloc_result(ctx, P.n, final_r, s, &t, &res)) != TK_OK) {
             drop_all();
             return st;
         }
         outs[b] = t;
-        if ((st = fill_result_from(t, Ub, ld, cb, Rc, s)) != TK_OK) {
-            drop_all();
-            return st;
+        ResultDst& d = ea.dst[b];
+        for (int k = 0; k < 3; ++k) {
+            d.U[k] = t->U[k];
+            d.U32[k] = t->U32[k];
+            d.r[k] = final_r[k];
         }
+        d.core = t->core;
+        d.core32 = t->core32;
+    }
+    if (launch_extract_results(ea, s) != hipSuccess) {
+        drop_all();
+        return fail(TK_EHIP, "result extraction: %s", hipGetErrorString(hipGetLastError()));
+    }
+    for (int b = 0; b < nb; ++b) {
+        tk_tucker* t = outs[b];
         for (int k = 0; k < 3; ++k) t->b[k] = grid->b[k];
         t->layout = grid->layout;
         t->prec = P.prec;

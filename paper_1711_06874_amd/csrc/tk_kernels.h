@@ -209,6 +209,19 @@ hipError_t launch_trunc_err(const double* X, int R0, int R1, int R2, const int* 
                             hipStream_t s, Bat bt = Bat());
 template <typename TI, typename TO>
 hipError_t launch_copy_block(const TI* X, int D1, int D2, TO* Y, int d0, int d1, int d2, hipStream_t s);
+// Results of a batch of problems in one launch: problem b's factors U_k (n_k x r_k[b], the
+// leading columns of the n_k x ld_k block at Usrc[k] + b bs bytes) and core (the leading
+// r_0 x r_1 x r_2 block of the Rc_0 x Rc_1 x Rc_2 array at core_src + b bs bytes) are copied
+// to its result block, in FP64 and rounded to FP32.
+struct ResultDst {
+    double* U[3]; float* U32[3]; double* core; float* core32; int r[3];
+};
+struct ExtractArgs {
+    int nb; int n[3]; int ld[3]; int Rc[3];
+    const double* Usrc[3]; const double* core_src; long bs;
+    ResultDst dst[BATCH_MAX];
+};
+hipError_t launch_extract_results(const ExtractArgs& a, hipStream_t s);
 hipError_t launch_cov_trace(const double* G, int r0, int r1, int r2, const double* u0, const double* u1,
                             const double* u2, double scale, double* out, hipStream_t s);
 hipError_t launch_final_err(double* scal, hipStream_t s, Bat bt = Bat());
