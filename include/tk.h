@@ -241,7 +241,10 @@ tk_status tk_reconstruct(tk_ctx *ctx, const tk_tucker *t, void *A_dev, int io, v
 tk_status tk_tucker_save(const tk_tucker *t, const char *path);
 tk_status tk_tucker_load(tk_ctx *ctx, const char *path, tk_tucker **out);
 
-/* Release a result and its device memory (after the work queued on it).  NULL is ignored. */
+/* Release a result (after the work queued on it) and its device memory.  The context keeps the
+ * device block (at most 256 blocks and 256 MB) for its next results of a similar size, so
+ * steady-state compression allocates nothing; the kept blocks are freed with the context.
+ * NULL is ignored. */
 void tk_tucker_free(tk_tucker *t);
 
 /* ---------------------------------------------------------------------------------------- */

@@ -163,6 +163,13 @@ struct tk_ctx {
         hipGraphNode_t grid_node = nullptr;
     };
     bool graphs_on = false;
+    // device blocks of freed results, kept for the next results (size -> block); at most
+    // kResultCache blocks and kResultCacheBytes bytes, freed with the context
+    static constexpr size_t kResultCache = 256;
+    static constexpr size_t kResultCacheBytes = (size_t)256 << 20;
+    std::mutex rc_mu;
+    std::multimap<size_t, void*> rcache;
+    size_t rcache_bytes = 0;
     std::mutex graph_mu;
     std::map<std::array<long, 19>, GraphEntry> graphs;
 };
@@ -175,6 +182,7 @@ struct tk_tucker {
     int prec = TK_FP32;
     double rel_err = 0.0, norm_a = 0.0;
     void* block = nullptr;        // one device allocation for everything below
+    size_t block_bytes = 0;       // its size (a reused block may be larger than `bytes`)
     double* U[3] = {nullptr, nullptr, nullptr};
     double* core = nullptr;
     float* U32[3] = {nullptr, nullptr, nullptr};
@@ -878,15 +886,31 @@ tk_status alloc_result(tk_ctx* ctx, const int n[3], const int r[3], hipStream_t 
     }
     t->bytes = bytes;
     // results live long and are small: they come from the device heap, not from the
-    // stream-ordered pool of the (large, short-lived) workspaces, which they would fragment
+    // stream-ordered pool of the (large, short-lived) workspaces, which they would fragment;
+    // the block of a freed result of the same size class (at most twice the size) is reused
     void* blk = nullptr;
-    hipError_t e = hipMalloc(&blk, bytes);
-    if (e != hipSuccess) {
-        release(ctx, bytes);
-        delete t;
-        return fail(TK_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    size_t blk_bytes = 0;
+    {
+        std::lock_guard<std::mutex> g(ctx->rc_mu);
+        auto it = ctx->rcache.lower_bound(bytes);
+        if (it != ctx->rcache.end() && it->first <= 2 * bytes) {
+            blk = it->second;
+            blk_bytes = it->first;
+            ctx->rcache_bytes -= it->first;
+            ctx->rcache.erase(it);
+        }
+    }
+    if (!blk) {
+        hipError_t e = hipMalloc(&blk, bytes);
+        if (e != hipSuccess) {
+            release(ctx, bytes);
+            delete t;
+            return fail(TK_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        }
+        blk_bytes = bytes;
     }
     t->block = blk;
+    t->block_bytes = blk_bytes;
     t->stream = s;
     Arena ar;
     ar.base = (char*)blk;
@@ -909,13 +933,27 @@ tk_status alloc_result(tk_ctx* ctx, const int n[3], const int r[3], hipStream_t 
 void free_result(tk_tucker* t)
 {
     if (!t) return;
-    if (t->block) {
-        // the result may have been read on any stream: free it once the device is idle
-        hipSetDevice(t->ctx->device);
-        hipDeviceSynchronize();
-        hipFree(t->block);
-    }
     tk_ctx* ctx = t->ctx;
+    if (t->block) {
+        // the result may have been read on any stream: its block is released (kept for the
+        // next result, or freed) once the device is idle
+        hipSetDevice(ctx->device);
+        hipDeviceSynchronize();
+        bool kept = false;
+        {
+            std::lock_guard<std::mutex> g(ctx->life_mu);
+            if (!ctx->closing) {
+                std::lock_guard<std::mutex> g2(ctx->rc_mu);
+                if (ctx->rcache.size() < tk_ctx::kResultCache &&
+                    ctx->rcache_bytes + t->block_bytes <= tk_ctx::kResultCacheBytes) {
+                    ctx->rcache.emplace(t->block_bytes, t->block);
+                    ctx->rcache_bytes += t->block_bytes;
+                    kept = true;
+                }
+            }
+        }
+        if (!kept) hipFree(t->block);
+    }
     release(ctx, t->bytes);
     delete t;
     bool last = false;
@@ -1743,6 +1781,10 @@ void tk_ctx_destroy(tk_ctx* ctx)
     {
         std::lock_guard<std::mutex> g(ctx->life_mu);
         ctx->closing = true;
+        std::lock_guard<std::mutex> g2(ctx->rc_mu);
+        for (auto& kv : ctx->rcache) (void)hipFree(kv.second);
+        ctx->rcache.clear();
+        ctx->rcache_bytes = 0;
         now = (ctx->live_results == 0);
     }
     if (now) delete ctx;
