@@ -404,6 +404,9 @@ typedef enum {
     TK_PROF_FFT_AXIS0 = 9, TK_PROF_COUNT = 10
 } tk_prof_class;
 tk_status tk_profile_enable(int on);
+/* Only the classes whose bit (1 << class) is set in mask are bracketed (default: all).  Each
+ * pair of events costs the stream a few microseconds between its launches. */
+tk_status tk_profile_select(unsigned mask);
 tk_status tk_profile_reset(void);
 tk_status tk_profile_read(int cls, long long *launches, double *total_ms);
 

@@ -84,6 +84,7 @@ struct ProfRec {
 };
 std::mutex g_prof_mu;
 std::atomic<bool> g_prof_on{false};
+std::atomic<unsigned> g_prof_mask{~0u};    // classes whose launches are bracketed (tk_profile_select)
 std::vector<ProfRec> g_prof;
 std::vector<hipEvent_t> g_event_pool;
 
@@ -105,7 +106,7 @@ struct ProfScope {
     hipEvent_t a = nullptr;
     ProfScope(int c, hipStream_t st) : cls(c), s(st)
     {
-        if (!g_prof_on.load()) return;
+        if (!g_prof_on.load() || !((g_prof_mask.load() >> c) & 1u)) return;
         std::lock_guard<std::mutex> lk(g_prof_mu);
         a = pool_event();
         if (a) (void)hipEventRecord(a, s);
@@ -1662,6 +1663,12 @@ const char* tk_version(void) { return "tk-mi355x 0.1 (gfx950)"; }
 tk_status tk_profile_enable(int on)
 {
     g_prof_on.store(on != 0);
+    return TK_OK;
+}
+
+tk_status tk_profile_select(unsigned mask)
+{
+    g_prof_mask.store(mask);
     return TK_OK;
 }
 

@@ -107,6 +107,7 @@ _SIGS = {
     "tk_server_release": (_st, [_vp, ctypes.c_longlong]),
     "tk_server_destroy": (None, [_vp]),
     "tk_profile_enable": (_st, [ctypes.c_int]),
+    "tk_profile_select": (_st, [ctypes.c_uint]),
     "tk_profile_reset": (_st, []),
     "tk_profile_read": (_st, [ctypes.c_int, ctypes.POINTER(ctypes.c_longlong), _dp]),
     "tk_last_error": (ctypes.c_char_p, []),
@@ -343,6 +344,12 @@ def tk_set_matvec_method(ctx: int, method: int) -> None:
 
 def tk_profile_enable(on: bool = True) -> None:
     _check(_lib.tk_profile_enable(1 if on else 0), "tk_profile_enable")
+
+
+def tk_profile_select(classes=None) -> None:
+    """Bracket only the launches of the given classes (names of PROF_CLASSES); None: all."""
+    mask = 0xFFFFFFFF if classes is None else sum(1 << PROF_CLASSES[c] for c in classes)
+    _check(_lib.tk_profile_select(mask), "tk_profile_select")
 
 
 def tk_profile_reset() -> None:
