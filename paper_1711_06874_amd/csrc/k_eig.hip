@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(NT) k_hqr_reg(const double* __restrict__ In, d
 }
 
 // ---------------------------------------------------------------------------------------------
-// Two-sided Jacobi on a p x p symmetric matrix (p <= JW_PMAX) by one wavefront, parallel
+// Two-sided Jacobi on a p x p symmetric matrix (p <= JW_PMAX) by one work-group, parallel
 // round-robin ordering.  After the rotations of a step are formed, every 2 x 2 block (P, Q) of
 // the pair partition is replaced by J_P^T B J_Q in one pass (upper blocks, mirrored), the
 // diagonal blocks by the closed form (a_pp - t a_pq, a_qq + t a_pq, 0), and the rows of V by
@@ -448,13 +448,32 @@ __global__ void __launch_bounds__(NT) k_hqr_reg(const double* __restrict__ In, d
 constexpr int JW_PMAX = 32;
 constexpr int JW_NP = JW_PMAX / 2;                          // pairs per step
 constexpr int JW_NBLK = JW_NP * (JW_NP + 1) / 2;            // 2 x 2 blocks (P <= Q)
-constexpr int JW_BPL = (JW_NBLK + 63) / 64;                 // blocks per lane
-constexpr int JW_VPL = JW_NP / 2;                           // V pairs per lane
-
-__global__ void __launch_bounds__(64) k_jacobi_w(const double* __restrict__ Hin, long sH, int p, int r,
-                                                 double* __restrict__ Vs, long sV, int ldv, double* __restrict__ lam,
-                                                 long sLam, int max_sweeps, double tol, long bs)
+// Sum over the NTJ threads of a work-group (one wavefront, or four through LDS), the same value in
+// every thread.
+template <int NTJ>
+__device__ __forceinline__ double jw_sum(double v, double* red)
 {
+    v = wave_sum(v);
+    if constexpr (NTJ == 64) {
+        return v;
+    } else {
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        return (red[0] + red[1]) + (red[2] + red[3]);
+    }
+}
+
+// NTJ threads (64: one wavefront; 256: the 2 x 2 blocks and the rows of V spread over four)
+template <int NTJ>
+__global__ void __launch_bounds__(NTJ) k_jacobi_w(const double* __restrict__ Hin, long sH, int p, int r,
+                                                  double* __restrict__ Vs, long sV, int ldv, double* __restrict__ lam,
+                                                  long sLam, int max_sweeps, double tol, long bs)
+{
+    constexpr int JW_BPL = (JW_NBLK + NTJ - 1) / NTJ;      // blocks per thread
+    constexpr int JW_VG = NTJ / 32;                        // thread groups over the rows of V
+    constexpr int JW_VPL = (JW_NP + JW_VG - 1) / JW_VG;    // V pairs per thread
+    __shared__ double red[4];
     Hin = bshift(Hin, bs);
     Vs = bshift(Vs, bs);
     lam = bshift(lam, bs);
@@ -464,9 +483,9 @@ __global__ void __launch_bounds__(64) k_jacobi_w(const double* __restrict__ Hin,
     __shared__ int pq[JW_NP][2];
     __shared__ unsigned char blk[JW_NBLK][2];
     __shared__ int rank_of[JW_PMAX];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x;     // thread index (not only within a wavefront)
     const double* Hp = Hin + (long)blockIdx.x * sH;
-    for (int e = lane; e < p * p; e += 64) {
+    for (int e = lane; e < p * p; e += NTJ) {
         const int i = e / p, j = e - (e / p) * p;
         H[i][j] = 0.5 * (Hp[(long)i * p + j] + Hp[(long)j * p + i]);
         V[i][j] = (i == j) ? 1.0 : 0.0;
@@ -481,21 +500,21 @@ __global__ void __launch_bounds__(64) k_jacobi_w(const double* __restrict__ Hin,
     }
     __syncthreads();
     double f = 0.0;
-    for (int e = lane; e < p * p; e += 64) {
+    for (int e = lane; e < p * p; e += NTJ) {
         const double x = H[e / p][e - (e / p) * p];
         f += x * x;
     }
-    const double fro = sqrt(wave_sum(f));
+    const double fro = sqrt(jw_sum<NTJ>(f, red));
     tol = fmax(tol, (double)p * 2.220446049250313e-16);
     double prev_off = INFINITY;
 
     for (int sweep = 0; sweep < max_sweeps && p > 1; ++sweep) {
         double o = 0.0;
-        for (int e = lane; e < p * p; e += 64) {
+        for (int e = lane; e < p * p; e += NTJ) {
             const int i = e / p, j = e - (e / p) * p;
             if (i != j) o += H[i][j] * H[i][j];
         }
-        const double off = sqrt(wave_sum(o));
+        const double off = sqrt(jw_sum<NTJ>(o, red));
         if (off <= tol * fro) break;
         // at the rounding floor (eigenvalues below u ||H|| keep off(H) near p u ||H||): a sweep
         // that no longer halves off(H) once it is below 1e-12 ||H|| changes nothing that matters
@@ -531,7 +550,7 @@ __global__ void __launch_bounds__(64) k_jacobi_w(const double* __restrict__ Hin,
             bool diag[JW_BPL], live[JW_BPL];
 #pragma unroll
             for (int u = 0; u < JW_BPL; ++u) {
-                const int e = lane + 64 * u;
+                const int e = lane + NTJ * u;
                 live[u] = e < nblk;
                 const int P = live[u] ? blk[e][0] : 0, Q = live[u] ? blk[e][1] : 0;
                 diag[u] = P == Q;
@@ -549,7 +568,7 @@ __global__ void __launch_bounds__(64) k_jacobi_w(const double* __restrict__ Hin,
             int va[JW_VPL], vb[JW_VPL];
 #pragma unroll
             for (int u = 0; u < JW_VPL; ++u) {
-                const int kk = vhalf + 2 * u;
+                const int kk = vhalf + JW_VG * u;
                 va[u] = (kk < np) ? pq[kk][0] : 0;
                 vb[u] = (kk < np) ? pq[kk][1] : p;
                 const bool ok = vrow < p && vb[u] < p;
@@ -583,7 +602,7 @@ __global__ void __launch_bounds__(64) k_jacobi_w(const double* __restrict__ Hin,
             }
 #pragma unroll
             for (int u = 0; u < JW_VPL; ++u) {
-                const int kk = vhalf + 2 * u;
+                const int kk = vhalf + JW_VG * u;
                 if (kk >= np || vrow >= p || vb[u] >= p) continue;
                 const double c = cs[kk][0], sn = cs[kk][1];
                 V[vrow][va[u]] = c * vx[u] - sn * vy[u];
@@ -604,7 +623,7 @@ __global__ void __launch_bounds__(64) k_jacobi_w(const double* __restrict__ Hin,
     }
     __syncthreads();
     double* Vo = Vs + (long)blockIdx.x * sV;
-    for (int e = lane; e < p * p; e += 64) {
+    for (int e = lane; e < p * p; e += NTJ) {
         const int i = e / p, j = e - (e / p) * p;
         const int rk = rank_of[j];
         if (rk < r) Vo[(long)i * ldv + rk] = V[i][j];
@@ -729,7 +748,7 @@ static hipError_t jacobi_launch(const double* H, long sH, int count, int p, int 
 {
     const dim3 grid(count, 1, bt.nb);
     if (p <= JW_PMAX) {
-        hipLaunchKernelGGL(k_jacobi_w, grid, dim3(64), 0, s, H, sH, p, r, V, sV, ldv, lam, sL, 60, 1e-15, bt.bs);
+        hipLaunchKernelGGL(k_jacobi_w<256>, grid, dim3(256), 0, s, H, sH, p, r, V, sV, ldv, lam, sL, 60, 1e-15, bt.bs);
         return hipGetLastError();
     }
     if (sH != (long)p * p || sV != (long)p * r || ldv != r) return hipErrorInvalidValue;
