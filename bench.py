@@ -3,15 +3,18 @@
 One step = the whole path over one batch: the 9 Matern covariances (nu in {1/2, 3/2, 5/2} x
 ell in {0.1, 0.3, 1.0}, sigma2 = 1) sampled on the 256^3 offset grid of [-1, 1]^3 (h = 2/255)
 are compressed by one tk_compress_batch call (per grid: grid evaluation, three Gram
-contractions, eigensolves, 2 HOOI sweeps, core, error norm, eps truncation; the nine grids share
-every launch); then one tk_quadratic_form_batch call, per grid the quadratic form with a seeded
-N(0,1) FP32 vector (the Kronecker-Toeplitz covariance matvec y = C z and z^T y; the grids run
-concurrently on the context's worker streams), and per grid tk_trace.  Inputs (the z vectors) are resident in HBM before the timed region.  After the
-timed region each grid is also compressed alone (single-request latency; per-class kernel
-times without the overlap of the batch).
+contractions, eigensolves, 2 HOOI sweeps, core, error norm, eps truncation; three groups of three
+grids, each group sharing every launch, run concurrently on the context's worker streams); then
+one tk_quadratic_form_batch call, per grid the quadratic form with a seeded N(0,1) FP32 vector
+(the Kronecker-Toeplitz covariance matvec y = C z and z^T y; the five FFT passes of the grids run
+back to back, their small preambles on a worker stream), and per grid tk_trace.  Inputs (the z vectors)
+are resident in HBM before the timed region.  Inside it only the roofline kernel (the axis-0 FFT
+pass) is bracketed by HIP events.  After it, one more quadratic-form batch times the other FFT
+passes, and each grid is compressed alone (single-request latency; per-class kernel times
+without the overlap of the batch).
 
-Prints one JSON line (see the keys below).  --gpus N with N > 1 exits: this build runs on one
-GPU.
+Prints one JSON line (see the keys below).  --gpus N with N > 1 exits: the benchmark runs on
+one GPU.
 """
 from __future__ import annotations
 
@@ -93,7 +96,7 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
