@@ -6,7 +6,8 @@
 // accumulation on mfma_f64_16x16x4f64: one wavefront computes a (16 TM) x (16 TN) block of one
 // item's output (TM, TN in {1, 2}, chosen from M and N so that small ranks do not pay for a
 // 32 x 32 block).  Operands are read straight from memory (they are small and cached), four
-// k-steps of 4 at a time, all loads of a group issued before its products; lane l supplies
+// k-steps of 4 at a time, all loads of a group issued before its products (for K >= 128 four
+// wavefronts split K, their sums added in a fixed order); lane l supplies
 // A[m0 + l % 16][k + l / 16] and B[k + l / 16][n0 + l % 16] and receives the outputs of rows
 // 4 v + l / 16, column l % 16 of each 16 x 16 tile.  The sum over k (and, in the batch-reducing
 // form, over the batch, outermost) runs in a fixed order.
@@ -18,13 +19,17 @@ namespace {
 constexpr int GKU = 4;   // k-steps of 4 whose operands are loaded together
 }
 
-template <typename TA, typename TB, typename TC, int TM, int TN>
-__global__ void __launch_bounds__(64) k_gemm(GemmArgs g)
+// KS wavefronts per block: wavefront w takes the w-th of KS near-equal K ranges (multiples of 16),
+// and the KS partial sums are added in the order w = 0, 1, ... through LDS.
+template <typename TA, typename TB, typename TC, int TM, int TN, int KS>
+__global__ void __launch_bounds__(64 * KS) k_gemm(GemmArgs g)
 {
     g.A = bshift(g.A, g.bs);
     g.B = bshift(g.B, g.bs);
     g.C = bshift(g.C, g.bs);
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int kq = ((g.K + KS - 1) / KS + 4 * GKU - 1) / (4 * GKU) * (4 * GKU);
+    const int kbeg = wv * kq, kend = (kbeg + kq < g.K) ? kbeg + kq : g.K;
     const int lr = lane & 15, lk = lane >> 4;
     const int tiles_n = (g.N + 16 * TN - 1) / (16 * TN);
     const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
@@ -55,12 +60,12 @@ __global__ void __launch_bounds__(64) k_gemm(GemmArgs g)
     for (long b = b_first; b < b_last; ++b) {
         const TA* A = (const TA*)g.A + b * g.sAb;
         const TB* B = (const TB*)g.B + b * g.sBb;
-        for (int k0 = 0; k0 < g.K; k0 += 4 * GKU) {
+        for (int k0 = kbeg; k0 < kend; k0 += 4 * GKU) {
             double av[GKU][TM], bv[GKU][TN];
 #pragma unroll
             for (int u = 0; u < GKU; ++u) {
                 const int k = k0 + 4 * u + lk;
-                const bool kv = k < g.K;
+                const bool kv = k < kend;
 #pragma unroll
                 for (int i = 0; i < TM; ++i) av[u][i] = (kv && mv[i]) ? (double)A[aoff[i] + (long)k * g.sAk] : 0.0;
 #pragma unroll
@@ -68,7 +73,7 @@ __global__ void __launch_bounds__(64) k_gemm(GemmArgs g)
             }
 #pragma unroll
             for (int u = 0; u < GKU; ++u) {
-                if (k0 + 4 * u < g.K) {
+                if (k0 + 4 * u < kend) {
 #pragma unroll
                     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -77,6 +82,27 @@ __global__ void __launch_bounds__(64) k_gemm(GemmArgs g)
                 }
             }
         }
+    }
+    if constexpr (KS > 1) {
+        __shared__ double part[KS - 1][TM * TN * 4][64];
+        if (wv > 0) {
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) part[wv - 1][(i * TN + j) * 4 + v][lane] = acc[i][j][v];
+        }
+        __syncthreads();
+        if (wv > 0) return;
+#pragma unroll
+        for (int w = 1; w < KS; ++w)
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[i][j][v] += part[w - 1][(i * TN + j) * 4 + v][lane];
     }
 #pragma unroll
     for (int i = 0; i < TM; ++i)
@@ -94,13 +120,18 @@ __global__ void __launch_bounds__(64) k_gemm(GemmArgs g)
             }
 }
 
+// Products with K >= 128 split K over four wavefronts (a choice that depends on the shape only, so
+// one problem and a batch of problems of that shape take the same sums).
 template <typename TA, typename TB, typename TC, int TM, int TN>
 static hipError_t launch_gemm_tiles(const GemmArgs& a, hipStream_t s)
 {
     const long tiles = (long)((a.M + 16 * TM - 1) / (16 * TM)) * ((a.N + 16 * TN - 1) / (16 * TN));
     const unsigned gy = a.reduce_batch ? 1u : (unsigned)a.batch;
     const unsigned gz = a.nb > 1 ? (unsigned)a.nb : 1u;
-    hipLaunchKernelGGL((k_gemm<TA, TB, TC, TM, TN>), dim3((unsigned)tiles, gy, gz), dim3(64), 0, s, a);
+    if (a.K >= 128)
+        hipLaunchKernelGGL((k_gemm<TA, TB, TC, TM, TN, 4>), dim3((unsigned)tiles, gy, gz), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_gemm<TA, TB, TC, TM, TN, 1>), dim3((unsigned)tiles, gy, gz), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
