@@ -812,10 +812,14 @@ hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s)
         const bool skip_start_qr = b.span_only && !b.warm && iters > 0;
         if (!start_orthonormal && !skip_start_qr && (e = qr_launch(b.Q, b.Q, b.count, n, p, s, bt)) != hipSuccess)
             return e;
+        // span-only with a compact U: the last QR writes the factor itself
+        const bool direct = b.span_only && p == r && iters > 0 && b.ldu == p && (b.count == 1 || b.sU == np_);
         for (int it = 0; it < iters; ++it) {
             if ((e = launch_gemm<double, double, double>(gq, s)) != hipSuccess) return e;
-            if ((e = qr_launch(b.Y, b.Q, b.count, n, p, s, bt)) != hipSuccess) return e;
+            double* out = (direct && it == iters - 1) ? b.U : b.Q;
+            if ((e = qr_launch(b.Y, out, b.count, n, p, s, bt)) != hipSuccess) return e;
         }
+        if (direct) return hipSuccess;
     }
     if (b.span_only) {
         // the block spans G^iters W: hand it over as the factor (ld p == r)

@@ -3,7 +3,7 @@
 //
 //   ttm_last : T[row, c] = sum_k A[row, k] U[k, c]      A viewed as (n0 n1) x n2   (A x_3 U^T)
 //   ttm_first: S[a, col] = sum_i U[i, a] A[i, col]      A viewed as n0 x (n1 n2)   (A x_1 U^T)
-//   recon_diff: sum over A of (A - H U^T)^2 and A^2,    H = G x_1 U1 x_2 U2 as (n0 n1) x r
+//   recon_diff: sum over A of A^2 and (A - H U^T)^2,    H = G x_1 U1 x_2 U2 as (n0 n1) x r
 //
 // All three read A exactly once with coalesced loads.  The TTMs stage 64 x 64 float tiles in
 // LDS (the next tile and U chunk are loaded into registers while the current one is multiplied)
@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(256) k_ttm_first(const float* __restrict__ A, 
         }
 }
 
-// Partial sums of (A - H U3^T)^2 and A^2 for 64 rows of A per work-group, in FP64: H and U3
+// Partial sums of A^2 and (A - H U3^T)^2 for 64 rows of A per work-group, in FP64: H and U3
 // are double and the reconstruction runs on mfma_f64_16x16x4 (D[i][j] at lane j + 16 (i%4),
 // register i/4), so the measured error has no FP32 arithmetic floor.
 // H: rows x r (ld r), U3: n2 x r (ld r); the contraction runs over r rounded up to 4.
@@ -269,13 +269,13 @@ __global__ void __launch_bounds__(256) k_recon_diff(const float* __restrict__ A,
     a2 = wave_sum(a2);
     if (lane == 0) { red[0][w] = d2; red[1][w] = a2; }
     __syncthreads();
-    if (tid == 0) {
-        partials[2 * blockIdx.x + 0] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
-        partials[2 * blockIdx.x + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    if (tid == 0) {   // (||A||^2, ||A - A_r||^2) of this work-group
+        partials[2 * blockIdx.x + 0] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        partials[2 * blockIdx.x + 1] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
     }
 }
 
-// Generic (any type) partial sums of (X - Y)^2 and X^2.
+// Generic (any type) partial sums of X^2 and (X - Y)^2.
 template <typename T>
 __global__ void __launch_bounds__(256) k_diff_norm(const T* __restrict__ X, const T* __restrict__ Y, long n,
                                                    double* __restrict__ partials, long bs)
@@ -296,9 +296,9 @@ __global__ void __launch_bounds__(256) k_diff_norm(const T* __restrict__ X, cons
     a2 = wave_sum(a2);
     if (lane == 0) { red[0][w] = d2; red[1][w] = a2; }
     __syncthreads();
-    if (tid == 0) {
-        partials[2 * blockIdx.x + 0] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
-        partials[2 * blockIdx.x + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    if (tid == 0) {   // (||A||^2, ||A - A_r||^2) of this work-group
+        partials[2 * blockIdx.x + 0] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        partials[2 * blockIdx.x + 1] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
     }
 }
 

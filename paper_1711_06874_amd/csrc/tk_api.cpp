@@ -630,7 +630,9 @@ tk_status eig_update(const Plan& P, Work& w, int k, const double* Gs, hipStream_
     b.rw = P.R[k]; b.ldw = P.R[k]; b.warm = w.U[k]; b.sW = 0;
     b.G = Gs; b.sG = 0;
     b.Q = w.Q; b.Y = w.Y; b.H = w.H; b.Vs = w.Vs;
-    b.U = w.Y + (long)P.n[k] * P.p[k];   // staging: the start block reads U[k]
+    // span-only: the last QR writes U[k] itself (the start block has read it by then); otherwise
+    // a staging area, copied to U[k] afterwards
+    b.U = span ? w.U[k] : w.Y + (long)P.n[k] * P.p[k];
     b.sU = 0; b.ldu = P.R[k];
     b.lam = w.lam + 64 * k; b.sL = 64;
     b.trace = nullptr;
@@ -639,7 +641,7 @@ tk_status eig_update(const Plan& P, Work& w, int k, const double* Gs, hipStream_
         ProfScope ps(TK_PROF_EIG, s);
         TK_LAUNCH(launch_eig(b, P.prec == TK_FP64 ? WARM_ITERS : WARM_ITERS_F32, s));
     }
-    TK_LAUNCH(launch_copy_f64(b.U, w.U[k], (long)P.n[k] * P.R[k], s, w.bt));
+    if (!span) TK_LAUNCH(launch_copy_f64(b.U, w.U[k], (long)P.n[k] * P.R[k], s, w.bt));
     return TK_OK;
 }
 
@@ -793,17 +795,15 @@ tk_status recon_norm(const Plan& P, Work& w, const Real* A, double* const Uf[3],
     if (sizeof(Real) == 4) {
         int parts = recon_diff_parts(rows);
         TK_LAUNCH(launch_recon_diff_f32((const float*)A, rows, n2, w.Hrec, Uf[2], R2, w.partials, s, w.bt));
-        TK_LAUNCH(launch_reduce_partials(w.partials, parts, 2, w.scal + 8, s, w.bt));
+        TK_LAUNCH(launch_reduce_partials(w.partials, parts, 2, w.scal, s, w.bt));
     } else {
         GemmArgs g = gemm((int)rows, n2, R2, 1, w.Hrec, 0, R2, 1, Uf[2], 0, 1, R2, w.Ahat, 0, n2, 1);
         TK_LAUNCH((wgemm<double, double, double>(g, w, s)));
         int parts = 1024;
         TK_LAUNCH(launch_diff_norm<double>((const double*)A, w.Ahat, rows * n2, w.partials, parts, s, w.bt));
-        TK_LAUNCH(launch_reduce_partials(w.partials, parts, 2, w.scal + 8, s, w.bt));
+        TK_LAUNCH(launch_reduce_partials(w.partials, parts, 2, w.scal, s, w.bt));
     }
-    // scal[8] = d2, scal[9] = a2 -> scal[0] = a2, scal[1] = d2
-    TK_LAUNCH(launch_copy_f64(w.scal + 8, w.scal + 1, 1, s, w.bt));
-    TK_LAUNCH(launch_copy_f64(w.scal + 9, w.scal + 0, 1, s, w.bt));
+    // the partials are (a2, d2) per work-group: scal[0] = a2, scal[1] = d2
     return TK_OK;
 }
 

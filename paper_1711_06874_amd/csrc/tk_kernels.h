@@ -114,12 +114,12 @@ hipError_t launch_ttm_first_f32(const float* A, int n0, long cols, const float* 
                                 hipStream_t s, Bat bt = Bat());
 
 // ------------------------------------------------------------------ a7: error norm ----
-// partials[2b] = sum (A - H U3^T)^2, partials[2b+1] = sum A^2 over work-group b's rows;
+// partials[2b] = sum A^2, partials[2b+1] = sum (A - H U3^T)^2 over work-group b's rows;
 // H: rows x r, U3: n2 x r.  recon_diff_parts(rows) work-groups.
 int recon_diff_parts(long rows);
 hipError_t launch_recon_diff_f32(const float* A, long rows, int n2, const double* H, const double* U3,
                                  int r, double* partials, hipStream_t s, Bat bt = Bat());
-// partials[2b] = sum (X - Y)^2, partials[2b+1] = sum X^2 (grid-stride, nparts work-groups)
+// partials[2b] = sum X^2, partials[2b+1] = sum (X - Y)^2 (grid-stride, nparts work-groups)
 template <typename T>
 hipError_t launch_diff_norm(const T* X, const T* Y, long n, double* partials, int nparts,
                             hipStream_t s, Bat bt = Bat());
