@@ -412,11 +412,12 @@ __device__ __forceinline__ void qr_backward(double (&w)[PM], double* T, double* 
 // time, so every register index is static.  The explicit Q is then accumulated backwards in
 // the same registers.
 template <int PM, int NT>
-__global__ void __launch_bounds__(NT) k_hqr_reg(const double* __restrict__ In, double* __restrict__ Out, int n, int p,
-                                                long bs)
+__global__ void __launch_bounds__(NT) k_hqr_reg(const double* __restrict__ In, double* __restrict__ Out,
+                                                float* __restrict__ Out32, int n, int p, long bs)
 {
     In = bshift(In, bs);
     Out = bshift(Out, bs);
+    if (Out32) Out32 = bshift(Out32, bs);
     extern __shared__ double T[];
     __shared__ double S[PM];
     __shared__ double rowjb[2][PM];     // row j, double-buffered by column parity
@@ -436,6 +437,11 @@ __global__ void __launch_bounds__(NT) k_hqr_reg(const double* __restrict__ In, d
 #pragma unroll
         for (int c = 0; c < PM; ++c)
             if (c < p) Out[off + (long)i * p + c] = w[c];
+        if (Out32) {
+#pragma unroll
+            for (int c = 0; c < PM; ++c)
+                if (c < p) Out32[off + (long)i * p + c] = (float)w[c];
+        }
     }
 }
 
@@ -715,7 +721,9 @@ __global__ void k_trace(const double* __restrict__ G, long sG, int n, double* __
 
 }  // namespace
 
-static hipError_t qr_launch(const double* in, double* out, int count, int n, int p, hipStream_t s, Bat bt)
+// out32 (optional, register kernel only): an FP32 copy of the factor, same layout
+static hipError_t qr_launch(const double* in, double* out, int count, int n, int p, hipStream_t s, Bat bt,
+                            float* out32 = nullptr)
 {
     const dim3 grid(count, 1, bt.nb);
     if (n <= 512 && p <= 32) {
@@ -724,8 +732,8 @@ static hipError_t qr_launch(const double* in, double* out, int count, int n, int
         const size_t lds = sizeof(double) * (size_t)pm * nt;
 #define TK_QR_LAUNCH(PM)                                                                                         \
     do {                                                                                                        \
-        if (nt == 256) hipLaunchKernelGGL((k_hqr_reg<PM, 256>), grid, dim3(256), lds, s, in, out, n, p, bt.bs); \
-        else hipLaunchKernelGGL((k_hqr_reg<PM, 512>), grid, dim3(512), lds, s, in, out, n, p, bt.bs);          \
+        if (nt == 256) hipLaunchKernelGGL((k_hqr_reg<PM, 256>), grid, dim3(256), lds, s, in, out, out32, n, p, bt.bs); \
+        else hipLaunchKernelGGL((k_hqr_reg<PM, 512>), grid, dim3(512), lds, s, in, out, out32, n, p, bt.bs);          \
     } while (0)
         switch (pm) {
         case 8: TK_QR_LAUNCH(8); break;
@@ -736,6 +744,7 @@ static hipError_t qr_launch(const double* in, double* out, int count, int n, int
 #undef TK_QR_LAUNCH
         return hipGetLastError();
     }
+    if (out32) return hipErrorInvalidValue;
     size_t bytes = (size_t)n * p * sizeof(double);
     int in_lds = bytes <= QR_LDS_BYTES ? 1 : 0;
     hipLaunchKernelGGL(k_hqr, grid, dim3(256), in_lds ? bytes : 0, s, in, out, n, p, in_lds, bt.bs);
@@ -775,7 +784,7 @@ hipError_t eig_set_attributes()
     return hipSuccess;
 }
 
-hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s)
+static hipError_t eig_body(const EigBatch& b, int iters, hipStream_t s, bool& wrote32)
 {
     hipError_t e;
     const int n = b.n, p = b.p, r = b.r;
@@ -795,9 +804,12 @@ hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s)
         hipLaunchKernelGGL(k_signfix, dim3(r, b.count, bt.nb), dim3(256), 0, s, b.U, b.sU, b.ldu, n, bt.bs);
         return hipGetLastError();
     }
-    // start block
-    hipLaunchKernelGGL(k_eig_init, dim3((unsigned)((np_ + 255) / 256), b.count, bt.nb), dim3(256), 0, s, b);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // start block: a warm block of exactly p columns is read in place by the first product
+    const bool warm_direct = b.warm && b.rw == p && p < n && iters > 0;
+    if (!warm_direct) {
+        hipLaunchKernelGGL(k_eig_init, dim3((unsigned)((np_ + 255) / 256), b.count, bt.nb), dim3(256), 0, s, b);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     GemmArgs gq{};   // Y = G Q
     gq.M = n; gq.N = p; gq.K = n; gq.batch = b.count;
     gq.A = b.G; gq.sAb = b.sG; gq.sAm = n; gq.sAk = 1;
@@ -814,12 +826,21 @@ hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s)
             return e;
         // span-only with a compact U: the last QR writes the factor itself
         const bool direct = b.span_only && p == r && iters > 0 && b.ldu == p && (b.count == 1 || b.sU == np_);
+        // the FP32 copy comes out of the last QR when it writes the factor in place
+        const bool direct32 = direct && b.U32 && b.count == 1 && p <= 32 && n <= 512;
         for (int it = 0; it < iters; ++it) {
-            if ((e = launch_gemm<double, double, double>(gq, s)) != hipSuccess) return e;
-            double* out = (direct && it == iters - 1) ? b.U : b.Q;
-            if ((e = qr_launch(b.Y, out, b.count, n, p, s, bt)) != hipSuccess) return e;
+            GemmArgs g = gq;
+            if (it == 0 && warm_direct) { g.B = b.warm; g.sBb = b.sW; g.sBk = b.ldw; g.sBn = 1; }
+            if ((e = launch_gemm<double, double, double>(g, s)) != hipSuccess) return e;
+            const bool last = direct && it == iters - 1;
+            if ((e = qr_launch(b.Y, last ? b.U : b.Q, b.count, n, p, s, bt, last && direct32 ? b.U32 : nullptr)) !=
+                hipSuccess)
+                return e;
         }
-        if (direct) return hipSuccess;
+        if (direct) {
+            wrote32 = direct32;
+            return hipSuccess;
+        }
     }
     if (b.span_only) {
         // the block spans G^iters W: hand it over as the factor (ld p == r)
@@ -859,6 +880,19 @@ hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s)
     if ((e = launch_gemm<double, double, double>(uq, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_signfix, dim3(r, b.count, bt.nb), dim3(256), 0, s, b.U, b.sU, b.ldu, n, bt.bs);
     return hipGetLastError();
+}
+
+hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s)
+{
+    bool wrote32 = false;
+    hipError_t e = eig_body(b, iters, s, wrote32);
+    if (e != hipSuccess || !b.U32 || wrote32) return e;
+    // FP32 copy of the factor where no kernel of the path wrote it
+    if (b.ldu != b.r || (b.count > 1 && b.sU != (long)b.n * b.r)) return hipErrorInvalidValue;
+    Bat bt;
+    bt.nb = b.nb > 1 ? b.nb : 1;
+    bt.bs = b.bs;
+    return launch_convert_f64_to_f32(b.U, b.U32, (long)b.count * b.n * b.r, s, bt);
 }
 
 }  // namespace tk

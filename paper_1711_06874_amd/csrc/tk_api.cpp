@@ -613,8 +613,9 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
     return TK_OK;
 }
 
-// Leading R_k eigenvectors of one symmetric n_k x n_k matrix Gs, warm-started from w.U[k].
-tk_status eig_update(const Plan& P, Work& w, int k, const double* Gs, hipStream_t s)
+// Leading R_k eigenvectors of one symmetric n_k x n_k matrix Gs, warm-started from w.U[k];
+// u32 (optional) receives the FP32 copy of the new factor.
+tk_status eig_update(const Plan& P, Work& w, int k, const double* Gs, hipStream_t s, float* u32)
 {
     EigBatch b{};
     // warm start from the current factor.  Float paths: the block is the factor itself
@@ -637,6 +638,7 @@ tk_status eig_update(const Plan& P, Work& w, int k, const double* Gs, hipStream_
     b.lam = w.lam + 64 * k; b.sL = 64;
     b.trace = nullptr;
     b.nb = w.bt.nb; b.bs = w.bt.bs;
+    b.U32 = u32;
     {
         ProfScope ps(TK_PROF_EIG, s);
         TK_LAUNCH(launch_eig(b, P.prec == TK_FP64 ? WARM_ITERS : WARM_ITERS_F32, s));
@@ -726,8 +728,7 @@ tk_status hooi_sweep(const Plan& P, Work& w, const Real* A, int nmax, hipStream_
         const int d[3] = {n0, R1, R2};
         if ((st = small_gram(d, 0, w.B, Gs, w.gram_work, s, w.bt)) != TK_OK) return st;
     }
-    if ((st = eig_update(P, w, 0, Gs, s)) != TK_OK) return st;
-    if ((st = refresh_u32<Real>(P, w, 0, s)) != TK_OK) return st;
+    if ((st = eig_update(P, w, 0, Gs, s, sizeof(Real) == 4 ? w.U32[0] : nullptr)) != TK_OK) return st;
     // ---- mode 2: B2[i1][a][c] = sum_i0 U1[i0][a] T[i0][i1][c]  (T still holds A x_3 U3^T)
     {
         GemmArgs g = gemm(R0, R2, n0, n1, w.U[0], 0, 1, R0, w.T, R2, (long)n1 * R2, 1, w.B, (long)R0 * R2, R2, 1);
@@ -737,8 +738,7 @@ tk_status hooi_sweep(const Plan& P, Work& w, const Real* A, int nmax, hipStream_
         const int d[3] = {n1, R0, R2};
         if ((st = small_gram(d, 0, w.B, Gs, w.gram_work, s, w.bt)) != TK_OK) return st;
     }
-    if ((st = eig_update(P, w, 1, Gs, s)) != TK_OK) return st;
-    if ((st = refresh_u32<Real>(P, w, 1, s)) != TK_OK) return st;
+    if ((st = eig_update(P, w, 1, Gs, s, sizeof(Real) == 4 ? w.U32[1] : nullptr)) != TK_OK) return st;
     // ---- mode 3: S = A x_1 U1^T, B3[a][i2][b] = sum_i1 S[a][i1][i2] U2[i1][b]
     if ((st = ttm_first<Real>(P, w, A, s)) != TK_OK) return st;
     {
@@ -750,8 +750,7 @@ tk_status hooi_sweep(const Plan& P, Work& w, const Real* A, int nmax, hipStream_
         const int d[3] = {R0, n2, R1};
         if ((st = small_gram(d, 1, w.B, Gs, w.gram_work, s, w.bt)) != TK_OK) return st;
     }
-    if ((st = eig_update(P, w, 2, Gs, s)) != TK_OK) return st;
-    if ((st = refresh_u32<Real>(P, w, 2, s)) != TK_OK) return st;
+    if ((st = eig_update(P, w, 2, Gs, s, sizeof(Real) == 4 ? w.U32[2] : nullptr)) != TK_OK) return st;
     // ---- core[a][b][c] = sum_i2 B3[a][i2][b] U3[i2][c]
     {
         GemmArgs g = gemm(R1, R2, n2, R0, w.B, (long)n2 * R1, 1, R1, w.U[2], 0, R2, 1, w.core, (long)R1 * R2, R2, 1);

@@ -96,6 +96,8 @@ struct EigBatch {
                      // random one), no Rayleigh-Ritz (for callers that rotate the factors afterwards)
     int nb;          // batched problems (0 counts as 1): every pointer above moves by bs bytes
     long bs;
+    float* U32;      // optional FP32 copy of U (ld r, stride n r); written by the last QR where it
+                     // writes U itself, by a conversion otherwise; moves by bs like the others
 };
 hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s);
 // Sign rule on the columns of U (n x r, ld ldu): a column whose entry of largest magnitude (ties
