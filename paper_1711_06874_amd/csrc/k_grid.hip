@@ -2,7 +2,9 @@
 //
 // A[i0,i1,i2] = sigma2 * k(||(x_i0, y_i1, z_i2)||), C-order.  Node coordinates and the radius
 // are formed in double (x = x0 + i h, r = sqrt((x^2 + y^2) + z^2)) and the kernel is
-// evaluated in double, then rounded once to the storage type.  Each thread writes 4
+// evaluated in double, then rounded once to the storage type (for float storage with a
+// shorter exponential and square root whose ~1e-10 relative error is far below half a float
+// ulp).  Each thread writes 4
 // consecutive elements of one i2-row (one 16-byte store for float rows whose length is a
 // multiple of 4); the grid is a flat 1-D launch over rows x ceil(n2/4) quads, so stores
 // from a wave cover contiguous 1 KiB (float) / 2 KiB (double) spans.
@@ -18,10 +20,23 @@ __global__ void __launch_bounds__(256) k_grid_eval(T* __restrict__ A, GridAxes g
     if (q >= total_quads) return;
     A = bshift(A, bs);
     const KernelParams& kp = kps.k[blockIdx.z];
-    long row = q / quads_per_row;
-    int i2 = (int)(q - row * quads_per_row) * 4;
-    int i1 = (int)(row % g.n[1]);
-    int i0 = (int)(row / g.n[1]);
+    long row;
+    int i0, i1, i2;
+    if (total_quads <= 0x7fffffffL) {
+        // 32-bit unsigned divisions (a 64-bit division costs several times more)
+        const unsigned q32 = (unsigned)q, qpr = (unsigned)quads_per_row, n1 = (unsigned)g.n[1];
+        const unsigned row32 = q32 / qpr;
+        const unsigned i0u = row32 / n1;
+        i2 = (int)(q32 - row32 * qpr) * 4;
+        i1 = (int)(row32 - i0u * n1);
+        i0 = (int)i0u;
+        row = (long)row32;
+    } else {
+        row = q / quads_per_row;
+        i2 = (int)(q - row * quads_per_row) * 4;
+        i1 = (int)(row % g.n[1]);
+        i0 = (int)(row / g.n[1]);
+    }
     double x = g.x0[0] + (double)i0 * g.h[0];
     double y = g.x0[1] + (double)i1 * g.h[1];
     double xy = x * x + y * y;
@@ -29,8 +44,9 @@ __global__ void __launch_bounds__(256) k_grid_eval(T* __restrict__ A, GridAxes g
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         double z = g.x0[2] + (double)(i2 + t) * g.h[2];
-        double r = sqrt(xy + z * z);
-        out[t] = (T)cov_value(kp, r);
+        const double r2 = xy + z * z;
+        if constexpr (sizeof(T) == 4) out[t] = (T)cov_value_for_float(kp, r2);
+        else out[t] = (T)cov_value(kp, sqrt(r2));
     }
     T* dst = A + row * g.n[2] + i2;
     if (i2 + 4 <= g.n[2]) {

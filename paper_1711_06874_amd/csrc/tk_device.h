@@ -61,6 +61,54 @@ __device__ __forceinline__ double cov_value(const KernelParams& kp, double r)
     return kp.sigma2 * v;
 }
 
+// e^{-s} for s >= 0 to about 2e-10 relative, for values that are rounded once to float:
+// 2^u with u = -s log2(e) = k + f (k an integer, |f| <= 1/2), 2^f = e^{f ln 2} from its
+// degree-8 Taylor polynomial (remainder below 0.35^9 / 9!), and 2^k applied exactly.
+__device__ __forceinline__ double exp_neg_for_float(double s)
+{
+    if (s > 256.0) return 0.0;   // far below the float range
+    const double u = -s * 1.4426950408889634;
+    const double k = rint(u);
+    const double f = (u - k) * 0.6931471805599453;
+    double p = 1.0 / 40320.0;
+    p = fma(p, f, 1.0 / 5040.0);
+    p = fma(p, f, 1.0 / 720.0);
+    p = fma(p, f, 1.0 / 120.0);
+    p = fma(p, f, 1.0 / 24.0);
+    p = fma(p, f, 1.0 / 6.0);
+    p = fma(p, f, 0.5);
+    p = fma(p, f, 1.0);
+    p = fma(p, f, 1.0);
+    return ldexp(p, (int)k);
+}
+
+// cov_value at r = sqrt(r2) for a value rounded once to float: the same closed forms, with the
+// radius from the hardware reciprocal square root refined by one Newton step (relative error
+// ~1e-14) and exp_neg_for_float.
+__device__ __forceinline__ double cov_value_for_float(const KernelParams& kp, double r2)
+{
+    double r = 0.0;
+    if (r2 > 0.0) {
+        double y = __builtin_amdgcn_rsq(r2);
+        y = y * fma(-0.5 * r2 * y, y, 1.5);
+        r = r2 * y;
+    }
+    double v;
+    if (kp.family == FAM_MATERN) {
+        double s = r * kp.inv_len;
+        double poly = (kp.half == 0) ? 1.0 : (kp.half == 1) ? (1.0 + s) : (1.0 + s + s * s * (1.0 / 3.0));
+        v = poly * exp_neg_for_float(s);
+    } else if (kp.family == FAM_SLATER) {
+        double t = r * kp.inv_len;
+        double tp = (kp.p == 1.0) ? t : ((t == 0.0) ? 0.0 : pow(t, kp.p));
+        v = exp_neg_for_float(kp.alpha * tp);
+    } else {
+        double t = r * kp.inv_len;
+        v = exp_neg_for_float(t * t);
+    }
+    return kp.sigma2 * v;
+}
+
 // Wave-level sum (64 lanes) of a double.
 __device__ __forceinline__ double wave_sum(double v)
 {
