@@ -32,6 +32,9 @@ KERNELS = [
     ("slater_p1", dict(family=1, alpha=1.0, p=1.0, ell=0.3)),
     ("slater_p19", dict(family=1, alpha=0.7, p=1.9, ell=0.5)),
     ("gauss", dict(family=2, ell=0.6)),
+    # short lengths: values down through the float subnormals to zero (s up to ~150 and ~370)
+    ("matern05_short", dict(family=0, nu=0.5, ell=0.012)),
+    ("slater_short", dict(family=1, alpha=2.0, p=1.0, ell=0.01)),
 ]
 
 
@@ -47,7 +50,13 @@ def test_grid_eval(ctx, tk, oracle, name, kw, layout):
     d64 = torch.empty(n, dtype=torch.float64, device="cuda")
     tk.tk_grid_eval(ctx.handle, k, g, tk.TK_FP64, d64)
     got = host(d64)
-    np.testing.assert_allclose(got, A, rtol=2e-14, atol=1e-300)
+    # e^{-s} turns an absolute error in s into the same relative error.  Coordinates, radius,
+    # 1/ell and the products each round (fused or not) on either side, up to a few u s, so
+    # the bound adds 8 u s to the exponential's own error (s = -ln(A / sigma2)).
+    sigma2 = kw.get("sigma2", 1.0)
+    s_exp = -np.log(np.maximum(np.abs(A) / sigma2, 1e-300))
+    rtol = 2e-14 + 8 * 2.220446049250313e-16 * s_exp
+    assert np.all(np.abs(got - A) <= rtol * np.abs(A) + 1e-300)
     d32 = torch.empty(n, dtype=torch.float32, device="cuda")
     tk.tk_grid_eval(ctx.handle, k, g, tk.TK_FP32, d32)
     g32 = host(d32)
