@@ -11,8 +11,10 @@
 // (entries within 1e-10 relative of the maximum tie, the lowest index wins).  When p == n
 // the block is the identity and the whole matrix is diagonalised by Jacobi directly.
 //
-// Kernels: k_eig_init (start block), k_hqr (one work-group per problem, Householder QR with
-// the n x p block resident in LDS when it fits, producing the explicit Q in place),
+// Kernels: k_eig_init (start block; a warm block of exactly p columns is read in place by the
+// first product instead), k_hqr_reg (rows in registers, n <= 512 and p <= 32; it can also write
+// an FP32 copy of the factor) and k_hqr (one work-group per problem, Householder QR with the
+// n x p block resident in LDS when it fits, producing the explicit Q in place), k_jacobi_w /
 // k_jacobi (one work-group per problem, p x p in LDS), k_signfix; the products G Q, Q^T Y and
 // Q V use the batched small-product kernel.
 #include "tk_kernels.h"
