@@ -845,10 +845,16 @@ tk_status core_truncate(const Plan& P, Work& w, hipStream_t s)
             TK_LAUNCH(launch_eig(b, 0, s));
         }
     }
-    // ranks: budget = (eps^2 a2 - d2) / 3 per mode
-    for (int k = 0; k < 3; ++k)
-        TK_LAUNCH(launch_rank_rule(w.lamc + 64 * k, 64, P.R[k], 1, nullptr, 0, w.scal, 1, P.eps * P.eps,
-                                   w.ranks + k, w.ranks + 3 + k, s, w.bt));
+    // ranks: budget = (eps^2 a2 - d2) / 3 per mode (one launch for the three modes when their
+    // rank caps agree)
+    if (P.R[0] == P.R[1] && P.R[1] == P.R[2]) {
+        TK_LAUNCH(launch_rank_rule(w.lamc, 64, P.R[0], 3, nullptr, 0, w.scal, 1, P.eps * P.eps, w.ranks, w.ranks + 3,
+                                   s, w.bt));
+    } else {
+        for (int k = 0; k < 3; ++k)
+            TK_LAUNCH(launch_rank_rule(w.lamc + 64 * k, 64, P.R[k], 1, nullptr, 0, w.scal, 1, P.eps * P.eps,
+                                       w.ranks + k, w.ranks + 3 + k, s, w.bt));
+    }
     // rotate factors: Urot_k = U_k V_k
     for (int k = 0; k < 3; ++k) {
         GemmArgs g = gemm(P.n[k], P.R[k], P.R[k], 1, w.U[k], 0, P.R[k], 1, w.Vc + k * RR, 0, P.R[k], 1, w.Urot[k], 0,
