@@ -1,5 +1,5 @@
-// Small single-work-group kernels around the compression: the eps rank rule, the error of a
-// core truncation, compaction of truncated factors / cores, and the covariance trace.
+// Small single-work-group kernels around the compression: the eps rank rule, compaction of
+// truncated factors / cores, and the covariance trace.
 #include "tk_kernels.h"
 
 namespace tk {
@@ -32,27 +32,6 @@ __global__ void k_rank_rule(const double* __restrict__ lam, long sLam, int len, 
     }
     ranks[blockIdx.x] = r;
     ok[blockIdx.x] = met;
-}
-
-// out[0] = sum of X[a][b][c]^2 over entries outside [0,r0) x [0,r1) x [0,r2) (R0 x R1 x R2),
-// ranks read from device memory.
-__global__ void __launch_bounds__(256) k_trunc_err(const double* __restrict__ X, int R0, int R1, int R2,
-                                                   const int* __restrict__ ranks, double* __restrict__ out, long bs)
-{
-    __shared__ double red[4];
-    X = bshift(X, bs);
-    ranks = bshift(ranks, bs);
-    out = bshift(out, bs);
-    const int r0 = ranks[0], r1 = ranks[1], r2 = ranks[2];
-    double s = 0.0;
-    for (int e = threadIdx.x; e < R0 * R1 * R2; e += 256) {
-        int a = e / (R1 * R2), b = (e / R2) % R1, c = e % R2;
-        if (a >= r0 || b >= r1 || c >= r2) s += X[e] * X[e];
-    }
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // Copy the leading d0 x d1 x d2 block of a D0 x D1 x D2 array (C-order) to a dense array.
@@ -128,13 +107,6 @@ hipError_t launch_rank_rule(const double* lam, long sLam, int len, int count, co
 {
     hipLaunchKernelGGL(k_rank_rule, dim3(count, 1, bt.nb), dim3(64), 0, s, lam, sLam, len, total, sTotal, scal,
                        has_d2, eps2, ranks, ok, bt.bs);
-    return hipGetLastError();
-}
-
-hipError_t launch_trunc_err(const double* X, int R0, int R1, int R2, const int* ranks, double* out, hipStream_t s,
-                            Bat bt)
-{
-    hipLaunchKernelGGL(k_trunc_err, dim3(1, 1, bt.nb), dim3(256), 0, s, X, R0, R1, R2, ranks, out, bt.bs);
     return hipGetLastError();
 }
 

@@ -806,9 +806,9 @@ tk_status recon_norm(const Plan& P, Work& w, const Real* A, double* const Uf[3],
     return TK_OK;
 }
 
-// eps truncation of a rank-R result by the HOSVD of its core (float paths).  The error of
-// the truncated result satisfies E^2 = (d2 + ||G - G_r||^2) / ||A||^2 exactly, because
-// A - A_R is orthogonal to the tensor subspace that holds A_R - A_r.
+// eps truncation of a rank-R result by the HOSVD of its core (float paths): the eigenvectors
+// of the three core Grams rotate the factors and the core to the core's HOSVD basis, and the
+// eps rule on their eigenvalues (with the measured d2 = ||A - A_R||^2) picks the ranks.
 tk_status core_truncate(const Plan& P, Work& w, hipStream_t s)
 {
     const int R0 = P.R[0], R1 = P.R[1], R2 = P.R[2];
@@ -873,8 +873,8 @@ tk_status core_truncate(const Plan& P, Work& w, hipStream_t s)
         GemmArgs g2 = gemm(R0 * R1, R2, R2, 1, w.coreB, 0, R2, 1, w.Vc + 2 * RR, 0, R2, 1, w.coreA, 0, R2, 1);
         TK_LAUNCH((wgemm<double, double, double>(g2, w, s)));
     }
-    TK_LAUNCH(launch_trunc_err(w.coreA, R0, R1, R2, w.ranks, w.scal + 2, s, w.bt));
-    TK_LAUNCH(launch_final_err(w.scal, s, w.bt));
+    // the error of the truncated result is measured against A afterwards (its caller), so the
+    // core's discarded energy is not formed here
     return TK_OK;
 }
 

@@ -207,8 +207,6 @@ hipError_t fft_set_attributes();
 hipError_t launch_rank_rule(const double* lam, long sLam, int len, int count, const double* total, long sTotal,
                             const double* scal, int has_d2, double eps2, int* ranks, int* ok, hipStream_t s,
                             Bat bt = Bat());
-hipError_t launch_trunc_err(const double* X, int R0, int R1, int R2, const int* ranks, double* out,
-                            hipStream_t s, Bat bt = Bat());
 template <typename TI, typename TO>
 hipError_t launch_copy_block(const TI* X, int D1, int D2, TO* Y, int d0, int d1, int d2, hipStream_t s);
 // Results of a batch of problems in one launch: problem b's factors U_k (n_k x r_k[b], the
