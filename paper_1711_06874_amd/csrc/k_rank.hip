@@ -136,19 +136,21 @@ hipError_t launch_cov_trace(const double* G, int r0, int r1, int r2, const doubl
     return hipGetLastError();
 }
 
-// E^2 = (d2 + t2) / a2 from scal = {a2, d2, t2, ...}; out = sqrt.
-__global__ void k_final_err(double* scal, long bs)
+// E^2 = (d2 + t2) / a2 from scal = {a2, d2, t2, ...}; scal[3] = E.  With zero_t2 the t2 slot is
+// cleared first (the error was measured directly, no extra term).
+__global__ void k_final_err(double* scal, int zero_t2, long bs)
 {
     scal = bshift(scal, bs);
     if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (zero_t2) scal[2] = 0.0;
         double a2 = scal[0];
         scal[3] = a2 > 0.0 ? sqrt(fmax(scal[1] + scal[2], 0.0) / a2) : 0.0;
     }
 }
 
-hipError_t launch_final_err(double* scal, hipStream_t s, Bat bt)
+hipError_t launch_final_err(double* scal, hipStream_t s, Bat bt, bool zero_t2)
 {
-    hipLaunchKernelGGL(k_final_err, dim3(1, 1, bt.nb), dim3(64), 0, s, scal, bt.bs);
+    hipLaunchKernelGGL(k_final_err, dim3(1, 1, bt.nb), dim3(64), 0, s, scal, zero_t2 ? 1 : 0, bt.bs);
     return hipGetLastError();
 }
 

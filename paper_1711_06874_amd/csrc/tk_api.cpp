@@ -1173,11 +1173,9 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void
             if ((st = core_truncate(P, w, s)) != TK_OK) return st;
             TK_LAUNCH(launch_mask_rank(w.Urot, P.n, P.R, w.coreA, w.ranks, s, w.bt));
             if ((st = recon_norm<Real>(P, w, A, w.Urot, w.coreA, s)) != TK_OK) return st;
-            TK_LAUNCH(launch_fill_f64(w.scal + 2, 0.0, 1, s, w.bt));
-            TK_LAUNCH(launch_final_err(w.scal, s, w.bt));
+            TK_LAUNCH(launch_final_err(w.scal, s, w.bt, true));
         } else {
-            TK_LAUNCH(launch_fill_f64(w.scal + 2, 0.0, 1, s, w.bt));   // no truncation: t2 = 0
-            TK_LAUNCH(launch_final_err(w.scal, s, w.bt));
+            TK_LAUNCH(launch_final_err(w.scal, s, w.bt, true));   // no truncation: t2 = 0
         }
         return TK_OK;
     };

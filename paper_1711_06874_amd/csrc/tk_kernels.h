@@ -224,7 +224,7 @@ struct ExtractArgs {
 hipError_t launch_extract_results(const ExtractArgs& a, hipStream_t s);
 hipError_t launch_cov_trace(const double* G, int r0, int r1, int r2, const double* u0, const double* u1,
                             const double* u2, double scale, double* out, hipStream_t s);
-hipError_t launch_final_err(double* scal, hipStream_t s, Bat bt = Bat());
+hipError_t launch_final_err(double* scal, hipStream_t s, Bat bt = Bat(), bool zero_t2 = false);
 hipError_t launch_mask_rank(double* const U[3], const int n[3], const int R[3], double* core, const int* ranks,
                             hipStream_t s, Bat bt = Bat());
 
