@@ -154,39 +154,48 @@ hipError_t launch_final_err(double* scal, hipStream_t s, Bat bt, bool zero_t2)
     return hipGetLastError();
 }
 
-// Zero the columns c >= rank of an n x R factor and the core entries outside the leading
-// r0 x r1 x r2 block (ranks from device memory), so that rank-R kernels evaluate the rank-r
-// result exactly.
-__global__ void k_mask_factor(double* __restrict__ U, long n, int R, const int* __restrict__ rank, long bs)
+// Zero the columns c >= rank_k of the three n_k x R_k factors and the core entries outside the
+// leading r0 x r1 x r2 block (ranks from device memory), so that rank-R kernels evaluate the
+// rank-r result exactly.  One launch: elements [off[k], off[k+1]) of the flat index space belong
+// to factor k, the rest to the core.
+struct MaskArgs {
+    double* U[3];
+    int R[3];
+    long off[4];
+    double* core;
+    long total;
+};
+
+__global__ void k_mask_all(MaskArgs a, const int* __restrict__ ranks, long bs)
 {
-    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * R) return;
-    U = bshift(U, bs);
-    rank = bshift(rank, bs);
-    if ((int)(e % R) >= rank[0]) U[e] = 0.0;
-}
-__global__ void k_mask_core(double* __restrict__ X, int R0, int R1, int R2, const int* __restrict__ ranks, long bs)
-{
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= R0 * R1 * R2) return;
-    X = bshift(X, bs);
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.total) return;
     ranks = bshift(ranks, bs);
-    int a = e / (R1 * R2), b = (e / R2) % R1, c = e % R2;
-    if (a >= ranks[0] || b >= ranks[1] || c >= ranks[2]) X[e] = 0.0;
+    if (e < a.off[3]) {
+        const int k = (e < a.off[1]) ? 0 : ((e < a.off[2]) ? 1 : 2);
+        const long i = e - a.off[k];
+        if ((int)(i % a.R[k]) >= ranks[k]) bshift(a.U[k], bs)[i] = 0.0;
+    } else {
+        const int i = (int)(e - a.off[3]);
+        const int R12 = a.R[1] * a.R[2];
+        const int x = i / R12, y = (i - x * R12) / a.R[2], z = i - x * R12 - y * a.R[2];
+        if (x >= ranks[0] || y >= ranks[1] || z >= ranks[2]) bshift(a.core, bs)[i] = 0.0;
+    }
 }
 
 hipError_t launch_mask_rank(double* const U[3], const int n[3], const int R[3], double* core, const int* ranks,
                             hipStream_t s, Bat bt)
 {
+    MaskArgs a{};
+    a.off[0] = 0;
     for (int k = 0; k < 3; ++k) {
-        long tot = (long)n[k] * R[k];
-        hipLaunchKernelGGL(k_mask_factor, dim3((unsigned)((tot + 255) / 256), 1, bt.nb), dim3(256), 0, s, U[k],
-                           (long)n[k], R[k], ranks + k, bt.bs);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        a.U[k] = U[k];
+        a.R[k] = R[k];
+        a.off[k + 1] = a.off[k] + (long)n[k] * R[k];
     }
-    int tot = R[0] * R[1] * R[2];
-    hipLaunchKernelGGL(k_mask_core, dim3((tot + 255) / 256, 1, bt.nb), dim3(256), 0, s, core, R[0], R[1], R[2], ranks,
+    a.core = core;
+    a.total = a.off[3] + (long)R[0] * R[1] * R[2];
+    hipLaunchKernelGGL(k_mask_all, dim3((unsigned)((a.total + 255) / 256), 1, bt.nb), dim3(256), 0, s, a, ranks,
                        bt.bs);
     return hipGetLastError();
 }
