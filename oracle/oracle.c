@@ -44,18 +44,62 @@ static double bessel_k_half_integer(int m, double x)
     return sqrt(M_PI / (2.0 * x)) * exp(-x) * sum;
 }
 
+/* K_nu(x) for any real order and x > 0 from the integral representation
+ *   K_nu(x) = int_0^inf exp(-x cosh t) cosh(nu t) dt          (DLMF 10.32.9),
+ * summed by the trapezoidal rule.  The integrand is even and analytic in the strip
+ * |Im t| < pi/2 (where Re cosh t > 0); relative to its value at t = 0 it stays bounded in the
+ * strip |Im t| < min(pi/4, 1/sqrt(x)) (there exp(-x cosh t) grows by at most exp(x(1 - cos y))),
+ * so the rule with step h = min(1/16, 0.1/sqrt(x)) errs by about exp(-2 pi d / h) <= e^-39
+ * relative.  Every term is positive, so the sum is accurate to a few ulp.  Summation stops
+ * once x cosh t - |nu| t exceeds 760 and grows (the rest of the terms lie below the double
+ * range).  A plain, slow route: hundreds of exponentials per value. */
+double tko_bessel_k(double nu, double x)
+{
+    const double h = fmin(1.0 / 16.0, 0.1 / sqrt(x));
+    nu = fabs(nu);
+    if (!(x > 0.0)) return NAN;
+    /* compensated (Kahan) summation: hundreds of terms would otherwise add ~n u of rounding */
+    double sum = 0.5 * exp(-x), comp = 0.0;   /* t = 0 carries half weight (even integrand) */
+    for (int k = 1; k < 1000000; ++k) {
+        double t = k * h;
+        double e = -x * cosh(t);
+        double term = 0.5 * (exp(e + nu * t) + exp(e - nu * t)) - comp;
+        double next = sum + term;
+        comp = (next - sum) - term;
+        sum = next;
+        if (-e - nu * t > 760.0 && x * sinh(t) > nu) break;
+    }
+    return sum * h;
+}
+
 /* Matern covariance, Sec. 2.2 eq. (2.3):
  *   C_{nu,ell}(r) = 2^{1-nu}/Gamma(nu) * (sqrt(2 nu) r/ell)^nu * K_nu(sqrt(2 nu) r/ell),
- * scaled by the variance sigma2.  Only half-integer nu (m + 1/2) is supported by this oracle;
- * the value at r = 0 is the limit sigma2.  Returns NaN for an unsupported nu. */
+ * scaled by the variance sigma2.  Half-integer nu = m + 1/2 (m <= 8) takes the terminating
+ * Bessel series; any other nu > 0 the integral above.  The value at r = 0 is the limit sigma2.
+ * Returns NaN for nu <= 0. */
 double tko_matern(double nu, double ell, double sigma2, double r)
 {
-    int m = (int)floor(nu);
-    if (fabs(nu - (m + 0.5)) > 1e-12 || m < 0 || m > 8) return NAN;
+    if (!(nu > 0.0)) return NAN;
     if (r == 0.0) return sigma2;
     double s = sqrt(2.0 * nu) * r / ell;
-    double c = pow(2.0, 1.0 - nu) / tgamma(nu) * pow(s, nu) * bessel_k_half_integer(m, s);
+    int m = (int)floor(nu);
+    double k;
+    if (fabs(nu - (m + 0.5)) <= 1e-12 && m <= 8) k = bessel_k_half_integer(m, s);
+    else k = tko_bessel_k(nu, s);
+    /* 2^{1-nu}/Gamma(nu) s^nu in log form (s^nu alone may overflow for large nu) */
+    double c = exp((1.0 - nu) * log(2.0) - lgamma(nu) + nu * log(s)) * k;
     return sigma2 * c;
+}
+
+/* Matern spectral density in d = 3 (the Fourier side of Diagram 1 in Sec. 2.2; Sec. 3.7
+ * eq. (3.28) with its constant written out):
+ *   f_{alpha,nu}(rho) = Gamma(nu + 3/2) alpha^{2 nu} / (pi^{3/2} Gamma(nu)) (alpha^2 + rho^2)^{-(nu + 3/2)},
+ * a probability density on R^3, scaled by sigma2. */
+double tko_spectral(double nu, double alpha, double sigma2, double rho)
+{
+    if (!(nu > 0.0) || !(alpha > 0.0)) return NAN;
+    double lc = lgamma(nu + 1.5) - lgamma(nu) + 2.0 * nu * log(alpha) - 1.5 * log(M_PI);
+    return sigma2 * exp(lc - (nu + 1.5) * log(alpha * alpha + rho * rho));
 }
 
 /* p-Slater function, Sec. 3.7 eq. (3.27): C(r) = exp(-r^p), generalised here with an
@@ -74,7 +118,7 @@ double tko_gauss(double ell, double sigma2, double r)
     return sigma2 * exp(-(t * t));
 }
 
-/* family: 0 = Matern, 1 = Slater, 2 = Gauss */
+/* family: 0 = Matern, 1 = Slater, 2 = Gauss, 3 = Matern spectral density (alpha, nu) */
 double tko_kernel(int family, double nu, double ell, double sigma2, double alpha, double p,
                   double r)
 {
@@ -82,6 +126,7 @@ double tko_kernel(int family, double nu, double ell, double sigma2, double alpha
     case 0: return tko_matern(nu, ell, sigma2, r);
     case 1: return tko_slater(alpha, p, ell, sigma2, r);
     case 2: return tko_gauss(ell, sigma2, r);
+    case 3: return tko_spectral(nu, alpha, sigma2, r);
     default: return NAN;
     }
 }
@@ -97,6 +142,29 @@ void tko_grid_coords(int n, double b, int layout, double *x)
 {
     double h = 2.0 * b / (double)(n - 1);
     for (int i = 0; i < n; ++i) x[i] = (layout == 0) ? (-b + (double)i * h) : ((double)i * h);
+}
+
+/* A[i0,i1,i2] = k(r) with r = sqrt((a0 x^2 + a1 y^2) + a2 z^2): the anisotropic distance of
+ * Sec. 2.2 with a positive diagonal metric a (metric == NULL: the identity, r = ||x||). */
+void tko_grid_eval_metric(int family, double nu, double ell, double sigma2, double alpha, double p,
+                          const int n[3], const double b[3], int layout, const double *metric,
+                          double *A)
+{
+    double a0 = metric ? metric[0] : 1.0, a1 = metric ? metric[1] : 1.0, a2 = metric ? metric[2] : 1.0;
+    double *x = (double *)malloc(sizeof(double) * (size_t)(n[0] + n[1] + n[2]));
+    double *y = x + n[0], *z = y + n[1];
+    tko_grid_coords(n[0], b[0], layout, x);
+    tko_grid_coords(n[1], b[1], layout, y);
+    tko_grid_coords(n[2], b[2], layout, z);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n[0]; ++i)
+        for (int j = 0; j < n[1]; ++j)
+            for (int k = 0; k < n[2]; ++k) {
+                double r = sqrt((a0 * x[i] * x[i] + a1 * y[j] * y[j]) + a2 * z[k] * z[k]);
+                A[((size_t)i * n[1] + j) * n[2] + k] =
+                    tko_kernel(family, nu, ell, sigma2, alpha, p, r);
+            }
+    free(x);
 }
 
 /* A[i0,i1,i2] = k(||(x_i0, y_i1, z_i2)||) with r = sqrt((x^2 + y^2) + z^2). */

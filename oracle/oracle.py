@@ -34,7 +34,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-MATERN, SLATER, GAUSS = 0, 1, 2
+MATERN, SLATER, GAUSS, SPECTRAL = 0, 1, 2, 3
 CENTERED, OFFSET = 0, 1
 
 
@@ -62,6 +62,9 @@ def _load():
     lib.tko_kernel.argtypes = [ctypes.c_int] + [ctypes.c_double] * 6
     lib.tko_grid_coords.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, dp]
     lib.tko_grid_eval.argtypes = [ctypes.c_int] + [ctypes.c_double] * 5 + [ip, dp, ctypes.c_int, dp]
+    lib.tko_grid_eval_metric.argtypes = [ctypes.c_int] + [ctypes.c_double] * 5 + [ip, dp, ctypes.c_int, dp, dp]
+    lib.tko_bessel_k.restype = ctypes.c_double
+    lib.tko_bessel_k.argtypes = [ctypes.c_double, ctypes.c_double]
     lib.tko_gram.argtypes = [dp, ip, ctypes.c_int, dp]
     lib.tko_jacobi_eig.restype = ctypes.c_int
     lib.tko_jacobi_eig.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_double]
@@ -100,12 +103,16 @@ def num_threads() -> int:
 
 @dataclass(frozen=True)
 class Kernel:
+    """family MATERN (nu, ell), SLATER (alpha, p, ell), GAUSS (ell) or SPECTRAL (the Matern
+    spectral density, alpha, nu); every family is scaled by sigma2.  metric: the diagonal of the
+    anisotropic distance r^2 = sum_k metric_k x_k^2 (Sec. 2.2), None for ||x||."""
     family: int = MATERN
     nu: float = 0.5
     ell: float = 1.0
     sigma2: float = 1.0
     alpha: float = 1.0
     p: float = 1.0
+    metric: tuple = None
 
 
 @dataclass(frozen=True)
@@ -116,8 +123,13 @@ class Grid:
 
 
 def kernel_value(k: Kernel, r: float) -> float:
-    """Covariance value at distance r (Sec. 2.2 eq. (2.3); Sec. 3.7 eq. (3.27))."""
+    """Covariance value at distance r (Sec. 2.2 eq. (2.3); Sec. 3.7 eqs. (3.27), (3.28))."""
     return float(_load().tko_kernel(k.family, k.nu, k.ell, k.sigma2, k.alpha, k.p, float(r)))
+
+
+def bessel_k(nu: float, x: float) -> float:
+    """K_nu(x) from its integral representation (trapezoidal rule), any real order, x > 0."""
+    return float(_load().tko_bessel_k(float(nu), float(x)))
 
 
 def grid_coords(n: int, b: float, layout: int) -> np.ndarray:
@@ -129,8 +141,13 @@ def grid_coords(n: int, b: float, layout: int) -> np.ndarray:
 def grid_eval(k: Kernel, g: Grid) -> np.ndarray:
     """Collocation tensor A[i0,i1,i2] = k(||x_i||) on the grid (Sec. 3.7 eq. (3.25))."""
     A = np.empty(tuple(g.n), dtype=np.float64)
-    _load().tko_grid_eval(k.family, k.nu, k.ell, k.sigma2, k.alpha, k.p, _ip(g.n),
-                          (ctypes.c_double * 3)(*g.b), int(g.layout), _dp(A))
+    if k.metric is None:
+        _load().tko_grid_eval(k.family, k.nu, k.ell, k.sigma2, k.alpha, k.p, _ip(g.n),
+                              (ctypes.c_double * 3)(*g.b), int(g.layout), _dp(A))
+    else:
+        _load().tko_grid_eval_metric(k.family, k.nu, k.ell, k.sigma2, k.alpha, k.p, _ip(g.n),
+                                     (ctypes.c_double * 3)(*g.b), int(g.layout),
+                                     (ctypes.c_double * 3)(*[float(a) for a in k.metric]), _dp(A))
     return A
 
 

@@ -49,8 +49,9 @@ def test_kernel_at_zero_is_variance(oracle):
         assert oracle.kernel_value(oracle.Kernel(fam, ell=0.2, sigma2=3.5, **kw), 0.0) == 3.5
 
 
-def test_unsupported_nu_is_nan(oracle):
-    assert np.isnan(oracle.kernel_value(oracle.Kernel(oracle.MATERN, nu=0.7), 0.3))
+def test_nonpositive_nu_is_nan(oracle):
+    assert np.isnan(oracle.kernel_value(oracle.Kernel(oracle.MATERN, nu=0.0), 0.3))
+    assert np.isnan(oracle.kernel_value(oracle.Kernel(oracle.MATERN, nu=-1.0), 0.3))
 
 
 def test_slater_p1_equals_exponential_matern(oracle):
@@ -59,6 +60,132 @@ def test_slater_p1_equals_exponential_matern(oracle):
             a = oracle.kernel_value(oracle.Kernel(oracle.SLATER, alpha=1.0, p=1.0, ell=ell), r)
             b = oracle.kernel_value(oracle.Kernel(oracle.MATERN, nu=0.5, ell=ell), r)
             assert a == pytest.approx(b, rel=1e-14, abs=1e-300)
+
+
+@pytest.mark.parametrize("p", [0.1, 0.5, 1.9, 2.0])
+@pytest.mark.parametrize("alpha", [0.7, 2.0])
+@pytest.mark.parametrize("ell", [0.05, 0.5])
+def test_slater_special_points(oracle, p, alpha, ell):
+    """p-Slater sigma2 exp(-alpha (r/ell)^p) (Sec. 3.7 eq. (3.27) with rate and length) at points
+    where the exponent is a plain number: r = ell gives exp(-alpha) for every p, r = 2 ell gives
+    exp(-alpha 2^p), r = ell/4 gives exp(-alpha 4^-p).  A length applied after the power
+    (r^p / ell) or a rate applied inside it fails these for p != 1."""
+    k = oracle.Kernel(oracle.SLATER, alpha=alpha, p=p, ell=ell, sigma2=1.3)
+    for r, expo in [(ell, 1.0), (2 * ell, 2.0 ** p), (ell / 4, 0.25 ** p)]:
+        assert oracle.kernel_value(k, r) == pytest.approx(1.3 * np.exp(-alpha * expo), rel=1e-14)
+
+
+@pytest.mark.parametrize("p", [0.1, 0.5, 1.9])
+def test_slater_scaling_laws(oracle, p):
+    """C(r; alpha, p, ell) = C(c r; alpha, p, c ell) (a length scale), and
+    C(r; alpha, p, ell) = C(r; alpha c^p, p, c ell) (rate and length trade through the power)."""
+    base = oracle.Kernel(oracle.SLATER, alpha=0.9, p=p, ell=0.3)
+    for c in (0.37, 4.1):
+        stretched = oracle.Kernel(oracle.SLATER, alpha=0.9, p=p, ell=0.3 * c)
+        traded = oracle.Kernel(oracle.SLATER, alpha=0.9 * c ** p, p=p, ell=0.3 * c)
+        for r in np.linspace(0.01, 1.7, 12):
+            v = oracle.kernel_value(base, r)
+            assert oracle.kernel_value(stretched, c * r) == pytest.approx(v, rel=1e-13, abs=1e-300)
+            assert oracle.kernel_value(traded, r) == pytest.approx(v, rel=1e-13, abs=1e-300)
+
+
+@pytest.mark.parametrize("alpha", [0.7, 2.0])
+def test_slater_p2_is_gaussian(oracle, alpha):
+    """p = 2: exp(-alpha (r/ell)^2) is the Gaussian of length ell / sqrt(alpha)."""
+    for ell in (0.05, 0.5):
+        s = oracle.Kernel(oracle.SLATER, alpha=alpha, p=2.0, ell=ell, sigma2=0.8)
+        g = oracle.Kernel(oracle.GAUSS, ell=ell / np.sqrt(alpha), sigma2=0.8)
+        for r in np.linspace(0.0, 3 * ell, 13):
+            assert oracle.kernel_value(s, r) == pytest.approx(oracle.kernel_value(g, r), rel=1e-13, abs=1e-300)
+
+
+@pytest.mark.parametrize("a", [0.3, 1.0, 2.5])
+def test_slater_p1_laplace_representation(oracle, a):
+    """Sec. 3.5: exp(-2 sqrt(a q)) = sqrt(a/pi) int_0^inf t^(-3/2) exp(-a/t - q t) dt with
+    q = ||x||^2, i.e. the Slater function of rate 2 sqrt(a) (p = 1) -- evaluated by quadrature."""
+    from scipy import integrate
+    k = oracle.Kernel(oracle.SLATER, alpha=2 * np.sqrt(a), p=1.0, ell=1.0)
+    for r in (0.05, 0.4, 1.3):
+        q = r * r
+        f = lambda t: t ** -1.5 * np.exp(-a / t - q * t)
+        val = np.sqrt(a / np.pi) * (integrate.quad(f, 0, 1, limit=200, epsabs=0, epsrel=1e-13)[0] +
+                                    integrate.quad(f, 1, np.inf, limit=200, epsabs=0, epsrel=1e-13)[0])
+        assert oracle.kernel_value(k, r) == pytest.approx(val, rel=1e-9)
+
+
+# ------------------------------------------------------- general Matern order, spectral density ----
+
+@pytest.mark.parametrize("nu", [0.05, 0.3, 0.8, 1.2, 2.0, 3.7, 7.3, 15.0])
+def test_bessel_k_integral_matches_mpmath(oracle, nu):
+    """K_nu by the trapezoidal rule on its integral representation against mpmath's
+    arbitrary-precision K_nu (test-only library).  Each term exp(nu t - x cosh t) is rounded
+    once in its exponent, whose size reaches ~200 at small x and large nu: 1e-13 relative."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 30
+    for x in [1e-4, 1e-3, 0.01, 0.3, 1.0, 2.0, 2.5, 10.0, 50.0, 200.0, 600.0]:
+        ref = float(mpmath.besselk(nu, x))
+        assert oracle.bessel_k(nu, x) == pytest.approx(ref, rel=1e-13), (nu, x)
+
+
+@pytest.mark.parametrize("nu", [0.4, 0.75, 1.0, 2.2, 4.0])
+def test_matern_general_order(oracle, nu):
+    """Sec. 2.2 eq. (2.3) at orders that are not half-integers, against mpmath; r = 0 gives
+    sigma2; the value is continuous in nu across a half-integer (the series branch)."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 30
+    ell, s2 = 0.35, 1.7
+    k = oracle.Kernel(oracle.MATERN, nu=nu, ell=ell, sigma2=s2)
+    assert oracle.kernel_value(k, 0.0) == s2
+    for r in [1e-5, 0.01, 0.2, 0.7, 1.5, 3.0]:
+        sv = mpmath.sqrt(2 * mpmath.mpf(nu)) * r / ell
+        ref = s2 * float(2 ** (1 - mpmath.mpf(nu)) / mpmath.gamma(nu) * sv ** nu * mpmath.besselk(nu, sv))
+        assert oracle.kernel_value(k, r) == pytest.approx(ref, rel=5e-14), (nu, r)
+    a = oracle.kernel_value(oracle.Kernel(oracle.MATERN, nu=1.5 + 1e-9, ell=ell), 0.4)
+    b = oracle.kernel_value(oracle.Kernel(oracle.MATERN, nu=1.5, ell=ell), 0.4)
+    assert a == pytest.approx(b, rel=1e-8)
+
+
+@pytest.mark.parametrize("nu,alpha", [(0.4, 0.1), (0.4, 100.0), (1.5, 2.0), (2.7, 0.5)])
+def test_spectral_density_is_a_probability_density(oracle, nu, alpha):
+    """The constant of the spectral density in Diagram 1 (Sec. 2.2) makes it integrate to one
+    over R^3: 4 pi int_0^inf rho^2 f(rho) d rho = 1 (quadrature)."""
+    from scipy import integrate
+    k = oracle.Kernel(oracle.SPECTRAL, nu=nu, alpha=alpha)
+    f = lambda rho: 4 * np.pi * rho * rho * oracle.kernel_value(k, rho)
+    tot = sum(integrate.quad(f, a, b, limit=400, epsabs=0, epsrel=1e-12)[0]
+              for a, b in [(0, alpha), (alpha, 10 * alpha), (10 * alpha, np.inf)])
+    assert tot == pytest.approx(1.0, rel=1e-9)
+
+
+@pytest.mark.parametrize("nu,ell", [(0.5, 0.3), (1.5, 0.5), (2.3, 0.4)])
+def test_spectral_density_transforms_to_matern(oracle, nu, ell):
+    """Diagram 1 (Sec. 2.2): the 3-D Fourier transform of the spectral density with
+    alpha = sqrt(2 nu)/ell is the Matern covariance, C(r) = (4 pi / r) int rho sin(rho r) f(rho).
+    Pins the spectral family against the Matern family (two independent code paths)."""
+    from scipy import integrate
+    alpha = np.sqrt(2 * nu) / ell
+    ks = oracle.Kernel(oracle.SPECTRAL, nu=nu, alpha=alpha)
+    km = oracle.Kernel(oracle.MATERN, nu=nu, ell=ell)
+    for r in (0.1, 0.4, 1.0):
+        g = lambda rho: rho * oracle.kernel_value(ks, rho)
+        val = 4 * np.pi / r * integrate.quad(g, 0, np.inf, weight="sin", wvar=r, limlst=200)[0]
+        assert val == pytest.approx(oracle.kernel_value(km, r), rel=1e-6), (nu, r)
+
+
+def test_anisotropic_metric(oracle):
+    """r^2 = sum_k a_k x_k^2 with a positive diagonal metric (Sec. 2.2): the identity metric is
+    the isotropic tensor, and metric a on the box b equals the isotropic tensor on the box
+    sqrt(a) b (coordinates scaled per axis)."""
+    n = (7, 9, 8)
+    for layout in (oracle.CENTERED, oracle.OFFSET):
+        g = oracle.Grid(n=n, b=(1.0, 0.8, 1.3), layout=layout)
+        iso = oracle.Kernel(oracle.MATERN, nu=1.5, ell=0.4)
+        same = oracle.Kernel(oracle.MATERN, nu=1.5, ell=0.4, metric=(1.0, 1.0, 1.0))
+        assert np.array_equal(oracle.grid_eval(iso, g), oracle.grid_eval(same, g))
+        a = (4.0, 1.0, 0.25)
+        an = oracle.Kernel(oracle.MATERN, nu=1.5, ell=0.4, metric=a)
+        g2 = oracle.Grid(n=n, b=tuple(np.sqrt(a) * np.asarray(g.b)), layout=layout)
+        np.testing.assert_allclose(oracle.grid_eval(an, g), oracle.grid_eval(iso, g2), rtol=1e-14, atol=0)
 
 
 # ------------------------------------------------------------------------------- grid ----
@@ -313,9 +440,12 @@ def test_table_4_2_n129(oracle):
     _table_case(oracle, 129, range(1, 11))
 
 
-@pytest.mark.slow
 def test_table_4_2_n257(oracle):
     _table_case(oracle, 257, range(1, 11))
+
+
+def test_table_4_2_n513(oracle):
+    _table_case(oracle, 513, range(1, 11))
 
 
 # ------------------------------------------------------------ covariance operator ----
