@@ -96,13 +96,20 @@ typedef struct {
 typedef struct {
     double eps;      /* > 0: choose ranks so the relative Frobenius error is <= eps;
                         0: use ranks[] */
-    int ranks[3];    /* fixed Tucker ranks (used when eps == 0); clamped to n_k */
+    int ranks[3];    /* fixed Tucker ranks (used when eps == 0); clamped to n_k.  After
+                        clamping at most 48 on TK_FP32 / TK_BF16X3 and at most 56 on TK_FP64
+                        (TK_EUNSUPPORTED above)                                            */
     int r_max;       /* eps mode: largest rank considered per mode (0 = library default 24);
                         at most 48 */
-    int hooi_sweeps; /* Tucker-ALS sweeps after HOSVD (0 = HOSVD only); < 0 = library
+    int hooi_sweeps; /* Tucker-ALS sweeps after HOSVD (0 = HOSVD only); TK_HOOI_CONVERGE =
+                        sweep until | ||G|| - ||G_prev|| | <= 1e-13 ||A|| (the first G_prev
+                        is the HOSVD core; at most 50 sweeps; one problem per pass, the core
+                        norm is read back after every sweep); other values < 0 = library
                         default (2) */
     int prec;        /* tk_precision */
 } tk_opts;
+
+#define TK_HOOI_CONVERGE (-2)   /* tk_opts.hooi_sweeps: Tucker-ALS to convergence (Sec. 3.2) */
 
 typedef struct tk_ctx tk_ctx;
 typedef struct tk_tucker tk_tucker;
@@ -122,7 +129,11 @@ tk_status tk_ctx_create(int device, size_t hbm_budget_bytes, tk_ctx **out);
  * NULL is ignored. */
 void tk_ctx_destroy(tk_ctx *ctx);
 
-/* Bytes of the budget currently reserved by the context's calls and resident results. */
+/* Bytes of the budget currently reserved by the context's calls and resident results.  Idle
+ * cached device blocks (workspaces kept per stream, blocks of freed results) are not included,
+ * but they count against the budget as well: a reservation that would take reserved + idle
+ * bytes past the budget first frees every idle block, so the device memory the context holds
+ * stays within the budget plus at most 16 MiB of rounding per busy workspace block. */
 tk_status tk_ctx_budget(const tk_ctx *ctx, size_t *budget_bytes, size_t *in_use_bytes);
 
 /* Peak device bytes a tk_compress of this grid with these options needs (workspace plus the
@@ -140,6 +151,9 @@ tk_status tk_estimate_bytes(const tk_grid *grid, const tk_opts *opts, size_t *pe
  *    HOSVD to the smallest ranks whose error bound stays <= eps.  TK_ENOCONV if r_max does
  *    not reach eps (the result is still returned through *out, at rank r_max).
  *  - eps == 0: fixed ranks[] (clamped to n_k).
+ * On the FP64 path every eigensolve iterates until its Ritz pairs pass the residual test of
+ * tk_eig_topr; one that does not within its cap makes the call return TK_ENOCONV (the result
+ * is still returned through *out).
  * The result keeps its factors and core resident on the device.  Synchronising: when the call
  * returns the result is complete and may be used from any stream.
  * Errors: TK_EINVAL, TK_EUNSUPPORTED, TK_ENOMEM, TK_EHIP, TK_ENOCONV. */
@@ -158,8 +172,9 @@ tk_status tk_compress_tensor(tk_ctx *ctx, const void *A_dev, const tk_grid *grid
  * problems, up to its share of the tk_ctx_set_workers streams in proportion to its problems,
  * which run concurrently) run every step of the pipeline as one launch whose
  * third grid dimension walks the problems, so one eigensolve or Gram launch serves them all.  Such groups
- * (and problems that run alone: other grids, or the FP64 eps path, which reads ranks back
- * between steps) run concurrently, largest first, on the context's worker streams
+ * (and problems that run alone: other grids, the FP64 path, which reads the eigensolver's
+ * convergence flags and in eps mode the ranks back between steps, and converged HOOI) run
+ * concurrently, largest first, on the context's worker streams
  * (tk_ctx_set_workers, default 4) with one host worker each, so the latency-bound steps of one
  * group overlap the bandwidth-bound passes of others.  They start after the work queued on
  * hip_stream.  Admission follows the HBM budget: a group that does not fit while others run
@@ -175,7 +190,7 @@ tk_status tk_compress_batch(tk_ctx *ctx, int count, const tk_kernel *kernels,
  * hip_stream: every step of the pipeline is one launch over all of them (as for a group inside
  * tk_compress_batch).  outs[i] / statuses[i]: the result of kernels[i], bitwise what tk_compress
  * returns for it alone, and TK_OK or TK_ENOCONV (eps not reached; the result is returned
- * anyway).  The FP64 eps path runs the problems one after another.  Synchronising: the results
+ * anyway).  The FP64 path and converged HOOI run the problems one after another.  Synchronising: the results
  * are complete when the call returns.  Errors (no results): TK_EINVAL, TK_EUNSUPPORTED,
  * TK_ENOMEM (the group's workspaces and results exceed the budget), TK_EHIP. */
 tk_status tk_compress_group(tk_ctx *ctx, int count, const tk_kernel *kernels, const tk_grid *grid,
@@ -198,9 +213,11 @@ tk_status tk_autotune_load(tk_ctx *ctx, const char *path);
 
 /* Workspaces: each call takes its device workspace from a block the context keeps per HIP
  * stream, grown when a call needs more and reused by the next call on that stream, so calls in
- * steady state allocate nothing.  The budget charges each call's workspace while the call runs;
- * an idle block (at most two per stream: the largest workspace a call on it needed, and a
- * quadratic form's own y) is not charged.  tk_ctx_release_stream frees the blocks of a stream
+ * steady state allocate nothing.  The budget charges each call's workspace while the call runs
+ * (a kept block more than 16 MiB larger than the call needs is charged at its full size, or
+ * replaced when that does not fit); idle blocks (at most two per stream: the largest workspace a
+ * call on it needed, and a quadratic form's own y) are freed when a reservation needs their room
+ * (see tk_ctx_budget).  tk_ctx_release_stream frees the blocks of a stream
  * (call it before destroying a stream the context has worked on); tk_ctx_destroy frees all.
  * Errors: TK_EINVAL (ctx NULL, a call on the stream still running), TK_EHIP. */
 tk_status tk_ctx_release_stream(tk_ctx *ctx, void *hip_stream);
@@ -243,7 +260,8 @@ tk_status tk_tucker_load(tk_ctx *ctx, const char *path, tk_tucker **out);
 
 /* Release a result (after the work queued on it) and its device memory.  The context keeps the
  * device block (at most 256 blocks and 256 MB) for its next results of a similar size, so
- * steady-state compression allocates nothing; the kept blocks are freed with the context.
+ * steady-state compression allocates nothing; the kept blocks are freed with the context, or
+ * earlier when a reservation needs their room in the budget.
  * NULL is ignored. */
 void tk_tucker_free(tk_tucker *t);
 
@@ -269,7 +287,8 @@ tk_status tk_kron_matvec(tk_ctx *ctx, const tk_tucker *t, const void *z_dev, voi
                          int io, void *hip_stream);
 
 /* Matvec algorithm of a context: TK_MV_AUTO (default: the FFT form for io = TK_FP32, dense
- * Toeplitz mode products for TK_FP64), TK_MV_FFT (FP32 only), TK_MV_DENSE.
+ * Toeplitz mode products for TK_FP64), TK_MV_FFT (FP32 only), TK_MV_DENSE.  A result whose
+ * third rank exceeds 48 (an FP64 compression or a loaded file) always takes the dense form.
  * FFT form: every Toeplitz factor embeds in a circulant of length L >= 2m - 1 (Sec. 3.6:
  * O(n log n) Toeplitz products), so C = P F^-H diag(chat) F P^T with F the 3-D DFT and chat
  * the Tucker tensor with DFT'd, circulant-embedded factors; five FP32 FFT passes.
@@ -323,7 +342,11 @@ tk_status tk_gram(tk_ctx *ctx, const void *A_dev, const int n[3], int mode, int 
  * (G_dev: count consecutive n*n doubles).  lambda_dev: count x r (descending);
  * U_dev: count x n x r row-major, unit columns, each signed so that its entry of largest
  * magnitude is positive (ties within 1e-10 relative go to the lowest index).  r <= 48.
- * Stream-ordered. */
+ * n > 56: block subspace iteration with r + 8 columns and Rayleigh-Ritz, repeated until every
+ * Ritz pair has ||G u - lambda u|| <= max(1e-12 lambda, 4 sqrt(n) u ||G||_F) (u = 2^-53), at
+ * most 35 iterations; n <= 56: Jacobi on G itself.  Synchronising.  Errors: TK_EINVAL,
+ * TK_EUNSUPPORTED, TK_ENOMEM, TK_EHIP, TK_ENOCONV (the residual test was not met; the outputs
+ * hold the last iterate). */
 tk_status tk_eig_topr(tk_ctx *ctx, int count, int n, int r, const double *G_dev,
                       double *lambda_dev, double *U_dev, void *hip_stream);
 

@@ -706,6 +706,83 @@ __global__ void __launch_bounds__(256) k_signfix_pair(double* __restrict__ U, in
     }
 }
 
+// Convergence test of the Ritz pairs (lam_j, u_j), j < r, of problem blockIdx.x:
+// rho_j = ||G u_j - lam_j u_j||_2 against max(tau lam_j, cfloor sqrt(n) u ||G||_F), u the FP64
+// unit roundoff.  The first term asks converged vectors of the large eigenvalues; below
+// cfloor sqrt(n) u ||G||_F / tau the test falls back to the rounding level of the product
+// G u itself, which no further iteration can go below.  flags[problem] = 1 when every column
+// passes (a NaN fails).  G is symmetric, so lane i reads column i of row k (coalesced); U is
+// staged in LDS RES_CB columns at a time.
+constexpr int RES_CB = 4;
+__global__ void __launch_bounds__(256) k_eig_residual(const double* __restrict__ G, long sG, int n,
+                                                      const double* __restrict__ U, long sU, int ldu, int r,
+                                                      const double* __restrict__ lam, long sL, double tau,
+                                                      double cfloor, int* __restrict__ flags, long bs)
+{
+    G = bshift(G, bs);
+    U = bshift(U, bs);
+    lam = bshift(lam, bs);
+    flags = bshift(flags, bs);
+    extern __shared__ double us[];   // n x RES_CB
+    __shared__ double red[4][RES_CB];
+    __shared__ double gnorm_s;
+    __shared__ int ok_s;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const double* g = G + blockIdx.x * sG;
+    const double* u = U + blockIdx.x * sU;
+    const double* l = lam + blockIdx.x * sL;
+    double gs = 0.0;
+    for (long e = tid; e < (long)n * n; e += 256) gs += g[e] * g[e];
+    gs = wave_sum(gs);
+    if (lane == 0) red[wv][0] = gs;
+    __syncthreads();
+    if (tid == 0) {
+        gnorm_s = sqrt((red[0][0] + red[1][0]) + (red[2][0] + red[3][0]));
+        ok_s = 1;
+    }
+    __syncthreads();
+    const double floor_level = cfloor * sqrt((double)n) * 2.220446049250313e-16 * gnorm_s;
+    for (int c0 = 0; c0 < r; c0 += RES_CB) {
+        const int cb = min(RES_CB, r - c0);
+        for (int e = tid; e < n * RES_CB; e += 256) {
+            const int i = e / RES_CB, j = e % RES_CB;
+            us[e] = j < cb ? u[(long)i * ldu + c0 + j] : 0.0;
+        }
+        __syncthreads();
+        double acc[RES_CB];
+#pragma unroll
+        for (int j = 0; j < RES_CB; ++j) acc[j] = 0.0;
+        for (int i = tid; i < n; i += 256) {
+            double y[RES_CB];
+#pragma unroll
+            for (int j = 0; j < RES_CB; ++j) y[j] = 0.0;
+            for (int k = 0; k < n; ++k) {
+                const double gv = g[(long)k * n + i];
+#pragma unroll
+                for (int j = 0; j < RES_CB; ++j) y[j] = fma(gv, us[k * RES_CB + j], y[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < RES_CB; ++j) {
+                const double d = (j < cb) ? y[j] - l[c0 + (j < cb ? j : 0)] * us[i * RES_CB + j] : 0.0;
+                acc[j] = fma(d, d, acc[j]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < RES_CB; ++j) {
+            const double v = wave_sum(acc[j]);
+            if (lane == 0) red[wv][j] = v;
+        }
+        __syncthreads();
+        if (tid < cb) {
+            const double rho = sqrt((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]));
+            const double thr = fmax(tau * l[c0 + tid], floor_level);
+            if (!(rho <= thr)) ok_s = 0;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) flags[blockIdx.x] = ok_s;
+}
+
 __global__ void k_trace(const double* __restrict__ G, long sG, int n, double* __restrict__ out, long sOut, long bs)
 {
     G = bshift(G, bs);
@@ -881,6 +958,16 @@ static hipError_t eig_body(const EigBatch& b, int iters, hipStream_t s, bool& wr
     uq.nb = bt.nb; uq.bs = bt.bs;
     if ((e = launch_gemm<double, double, double>(uq, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_signfix, dim3(r, b.count, bt.nb), dim3(256), 0, s, b.U, b.sU, b.ldu, n, bt.bs);
+    return hipGetLastError();
+}
+
+hipError_t launch_eig_check(const EigBatch& b, double tau, double cfloor, int* flags, hipStream_t s)
+{
+    if (b.n < 1 || b.n > 1024 || b.r < 1) return hipErrorInvalidValue;
+    const int nb = b.nb > 1 ? b.nb : 1;
+    const size_t lds = sizeof(double) * (size_t)b.n * RES_CB;
+    hipLaunchKernelGGL(k_eig_residual, dim3(b.count, 1, nb), dim3(256), lds, s, b.G, b.sG, b.n, b.U, b.sU, b.ldu,
+                       b.r, b.lam, b.sL, tau, cfloor, flags, b.bs);
     return hipGetLastError();
 }
 

@@ -55,6 +55,8 @@ tk_status fail(tk_status s, const char* fmt, ...)
 constexpr int LIB_RMAX = 48;          // largest rank the kernels support
 constexpr int DEFAULT_RMAX = 24;      // eps mode working rank when r_max == 0
 constexpr int DEFAULT_SWEEPS = 2;
+constexpr int CONVERGE_MAX_SWEEPS = 50;   // cap of the converged-HOOI mode
+constexpr double CONVERGE_TOL = 1e-13;    // ... its test on the core norm, relative to ||A||
 constexpr int COLD_ITERS = 3;         // subspace iterations from a random start (FP64 path)
 constexpr int COLD_ITERS_F32 = 2;     // ... float paths (HOOI refines the subspaces anyway)
 constexpr int WARM_ITERS = 2;         // ... from the previous factor (FP64 path: exact HOOI steps)
@@ -154,6 +156,11 @@ struct tk_ctx {
     };
     std::mutex ws_mu;
     std::map<std::pair<hipStream_t, int>, WsBlock> ws;
+    // bytes of device blocks the context keeps while no call uses them: idle workspace blocks
+    // and the result-block cache.  A reservation that would take in_use + idle past the budget
+    // frees them first (trim_idle), so the context never holds more than the budget plus the
+    // rounding of the busy workspace blocks.
+    std::atomic<size_t> idle{0};
     // autotuned Gram split counts, key {n0, n1, n2, mode, prec}
     std::mutex tune_mu;
     std::map<std::array<int, 5>, int> tune;
@@ -194,13 +201,20 @@ struct tk_tucker {
 
 namespace {
 
-bool reserve(tk_ctx* c, size_t bytes)
+void trim_idle(tk_ctx* c);
+
+// Charge `bytes` to the budget.  Idle cached blocks count against it too: when they are in the
+// way they are freed (trim_idle) and the check is repeated once.
+bool reserve(tk_ctx* c, size_t bytes, bool may_trim = true)
 {
-    size_t cur = c->in_use.load();
-    while (true) {
-        if (cur + bytes > c->budget) return false;
-        if (c->in_use.compare_exchange_weak(cur, cur + bytes)) return true;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        size_t cur = c->in_use.load();
+        while (cur + bytes + c->idle.load() <= c->budget)
+            if (c->in_use.compare_exchange_weak(cur, cur + bytes)) return true;
+        if (cur + bytes > c->budget || !may_trim || c->idle.load() == 0) return false;
+        trim_idle(c);
     }
+    return false;
 }
 void release(tk_ctx* c, size_t bytes) { c->in_use.fetch_sub(bytes); }
 
@@ -231,6 +245,7 @@ struct Ws {
     int slot = 0;
     void* p = nullptr;
     bool cached = false;
+    size_t extra = 0;    // bytes of the cached block beyond the call's request, charged while busy
     Ws() = default;
     Ws(const Ws&) = delete;
     Ws& operator=(const Ws&) = delete;
@@ -239,7 +254,10 @@ struct Ws {
         if (!p) return;
         if (cached) {
             std::lock_guard<std::mutex> g(c->ws_mu);
-            c->ws[{s, slot}].busy = false;
+            tk_ctx::WsBlock& b = c->ws[{s, slot}];
+            b.busy = false;
+            c->idle.fetch_add(b.bytes);
+            release(c, extra);
         } else {
             (void)hipFreeAsync(p, s);
         }
@@ -258,11 +276,22 @@ hipError_t ws_get(tk_ctx* c, hipStream_t s, int slot, size_t bytes, Ws& w)
         if (e != hipSuccess) w.p = nullptr;
         return e;
     }
+    c->idle.fetch_sub(b.bytes);   // the block leaves the idle set (or is replaced below)
+    // a kept block much larger than this call needs would hold budget it does not charge:
+    // its excess is charged while the call runs, or, when that does not fit, it is replaced
+    const size_t round = (size_t)1 << 24;
+    if (b.bytes >= bytes && b.bytes - bytes > round && !reserve(c, b.bytes - bytes, false)) {
+        (void)hipFreeAsync(b.ptr, s);
+        b.ptr = nullptr;
+        b.bytes = 0;
+    } else if (b.bytes >= bytes && b.bytes - bytes > round) {
+        w.extra = b.bytes - bytes;
+    }
     if (b.bytes < bytes) {
         if (b.ptr) (void)hipFreeAsync(b.ptr, s);   // after the earlier calls on s, in stream order
         b.ptr = nullptr;
         b.bytes = 0;
-        const size_t want = align_up(bytes, (size_t)1 << 24);
+        const size_t want = align_up(bytes, round);
         hipError_t e = hipMallocAsync(&b.ptr, want, s);
         if (e == hipSuccess) {
             b.bytes = want;
@@ -280,6 +309,33 @@ hipError_t ws_get(tk_ctx* c, hipStream_t s, int slot, size_t bytes, Ws& w)
     w.p = b.ptr;
     w.cached = true;
     return hipSuccess;
+}
+
+// Free every idle workspace block and the result-block cache, and hand the freed memory of
+// the stream-ordered pool back to the device.
+void trim_idle(tk_ctx* c)
+{
+    {
+        std::lock_guard<std::mutex> g(c->ws_mu);
+        for (auto it = c->ws.begin(); it != c->ws.end();) {
+            if (it->second.busy) { ++it; continue; }
+            if (it->second.ptr) (void)hipFreeAsync(it->second.ptr, it->first.first);
+            c->idle.fetch_sub(it->second.bytes);
+            it = c->ws.erase(it);
+        }
+    }
+    {
+        std::lock_guard<std::mutex> g(c->rc_mu);
+        for (auto& kv : c->rcache) (void)hipFree(kv.second);
+        c->idle.fetch_sub(c->rcache_bytes);
+        c->rcache.clear();
+        c->rcache_bytes = 0;
+    }
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, c->device) == hipSuccess) {
+        (void)hipDeviceSynchronize();
+        (void)hipMemPoolTrimTo(pool, 0);
+    }
 }
 
 bool finite(double x) { return std::isfinite(x); }
@@ -345,6 +401,7 @@ struct Plan {
     bool eps_mode;
     double eps;
     int sweeps;
+    bool converge;     // HOOI until | ||G|| - ||G_prev|| | <= 1e-13 ||A|| (at most `sweeps`)
     bool cubic;
     int gsplit[3];     // K chunks per tile pair of the Gram of A per mode (0: default)
 };
@@ -357,7 +414,8 @@ tk_status make_plan(const tk_grid* g, const tk_opts* o, Plan* P)
     P->prec = o->prec;
     P->eps_mode = o->eps > 0;
     P->eps = o->eps;
-    P->sweeps = o->hooi_sweeps < 0 ? DEFAULT_SWEEPS : o->hooi_sweeps;
+    P->converge = o->hooi_sweeps == TK_HOOI_CONVERGE;
+    P->sweeps = P->converge ? CONVERGE_MAX_SWEEPS : o->hooi_sweeps < 0 ? DEFAULT_SWEEPS : o->hooi_sweeps;
     if (P->sweeps > 100) return fail(TK_EINVAL, "hooi_sweeps=%d too large", o->hooi_sweeps);
     int rmax = o->r_max > 0 ? o->r_max : DEFAULT_RMAX;
     if (rmax > LIB_RMAX) return fail(TK_EUNSUPPORTED, "r_max=%d exceeds %d", rmax, LIB_RMAX);
@@ -373,6 +431,11 @@ tk_status make_plan(const tk_grid* g, const tk_opts* o, Plan* P)
         }
         P->R[k] = want < g->n[k] ? want : g->n[k];
         if (P->R[k] > EIG_PMAX) return fail(TK_EUNSUPPORTED, "rank %d exceeds %d", P->R[k], EIG_PMAX);
+        // the float paths' A-streaming TTMs and error norm hold at most LIB_RMAX rank columns
+        // in registers (three 16-column MFMA blocks); only the FP64 path goes up to EIG_PMAX
+        if (P->prec != TK_FP64 && P->R[k] > LIB_RMAX)
+            return fail(TK_EUNSUPPORTED, "rank %d (n[%d]=%d) exceeds %d on the FP32/BF16x3 paths", P->R[k], k,
+                        g->n[k], LIB_RMAX);
         P->p[k] = (g->n[k] <= EIG_PMAX) ? g->n[k] : ((P->R[k] + 8 < EIG_PMAX) ? P->R[k] + 8 : EIG_PMAX);
     }
     P->cubic = (g->n[0] == g->n[1] && g->n[1] == g->n[2]);
@@ -413,8 +476,11 @@ struct Work {
     int* ranks;              // 3 ranks + 3 ok flags
     // eps truncation (float paths)
     double *Gc, *Vc, *lamc, *tQ, *tY, *tH, *tVs, *coreA, *coreB, *Urot[3];
+    int* eflags;             // eigensolver convergence flags (FP64 path)
     int nparts;
     Bat bt;                  // problems sharing this layout, bt.bs bytes apart (pointers: problem 0)
+    tk_ctx* ctx = nullptr;   // for the FP64 path's convergence readbacks
+    bool noconv = false;     // an FP64 eigensolve stopped at its iteration cap
 };
 
 void layout_work(Arena& ar, const Plan& P, bool own_A, Work& w)
@@ -472,6 +538,7 @@ void layout_work(Arena& ar, const Plan& P, bool own_A, Work& w)
     w.coreA = ar.take<double>((size_t)R[0] * R[1] * R[2]);
     w.coreB = ar.take<double>((size_t)R[0] * R[1] * R[2]);
     for (int k = 0; k < 3; ++k) w.Urot[k] = ar.take<double>((size_t)n[k] * R[k]);
+    w.eflags = ar.take<int>(64);
 }
 
 size_t result_bytes(const int n[3], const int r[3])
@@ -568,6 +635,42 @@ tk_status readback(tk_ctx* ctx, hipStream_t s, const void* src0, size_t bytes0, 
     return TK_OK;
 }
 
+// FP64 path: the block subspace iteration runs until its Ritz pairs pass the residual test of
+// launch_eig_check (|| G u_j - lam_j u_j || <= max(EIG_TAU lam_j, EIG_CFLOOR sqrt(n) u ||G||_F)),
+// EIG_ROUND_ITERS more iterations per failed test, at most EIG_MAX_ROUNDS rounds; the flags are
+// read back after each test.  A problem still failing at the cap sets w.noconv (the call then
+// returns TK_ENOCONV with its result).  The block Q of the last iteration is the warm start of
+// the next round, so every round continues the same iteration.
+constexpr double EIG_TAU = 1e-12;
+constexpr double EIG_CFLOOR = 4.0;
+constexpr int EIG_ROUND_ITERS = 2;
+constexpr int EIG_MAX_ROUNDS = 16;
+tk_status eig_converge(const EigBatch& b, Work& w, hipStream_t s)
+{
+    if (b.span_only || b.p >= b.n || b.count > 64 || !w.ctx) return TK_OK;
+    for (int round = 0;; ++round) {
+        TK_LAUNCH(launch_eig_check(b, EIG_TAU, EIG_CFLOOR, w.eflags, s));
+        int fl[64];
+        tk_status st = readback(w.ctx, s, w.eflags, sizeof(int) * (size_t)b.count, fl);
+        if (st != TK_OK) return st;
+        bool all = true;
+        for (int c = 0; c < b.count; ++c) all = all && fl[c] == 1;
+        if (all) return TK_OK;
+        if (round == EIG_MAX_ROUNDS) {
+            w.noconv = true;
+            return TK_OK;
+        }
+        EigBatch rb = b;
+        rb.warm = b.Q;
+        rb.sW = (long)b.n * b.p;
+        rb.rw = b.p;
+        rb.ldw = b.p;
+        rb.trace = nullptr;
+        ProfScope ps(TK_PROF_EIG, s);
+        TK_LAUNCH(launch_eig(rb, EIG_ROUND_ITERS, s));
+    }
+}
+
 // Leading R_k eigenvectors of the three Grams in w.G (stride nmax^2), HOSVD start.
 tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
 {
@@ -593,6 +696,10 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
             ProfScope ps(TK_PROF_EIG, s);
             TK_LAUNCH(launch_eig(b, b.span_only ? SPAN_ITERS_F32 : (P.prec == TK_FP64 ? COLD_ITERS : COLD_ITERS_F32), s));
         }
+        if (P.prec == TK_FP64) {
+            tk_status st = eig_converge(b, w, s);
+            if (st != TK_OK) return st;
+        }
         for (int k = 0; k < 3; ++k)
             TK_LAUNCH(launch_copy_f64(w.Y + (long)k * P.n[0] * P.R[0], w.U[k], (long)P.n[0] * P.R[0], s, w.bt));
     } else {
@@ -606,8 +713,14 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
             b.trace = w.trace + k; b.sTrace = 1;
             b.nb = w.bt.nb; b.bs = w.bt.bs;
             if (span && P.R[k] < P.n[k]) { b.p = P.R[k]; b.span_only = 1; }
-            ProfScope ps(TK_PROF_EIG, s);
-            TK_LAUNCH(launch_eig(b, b.span_only ? SPAN_ITERS_F32 : (P.prec == TK_FP64 ? COLD_ITERS : COLD_ITERS_F32), s));
+            {
+                ProfScope ps(TK_PROF_EIG, s);
+                TK_LAUNCH(launch_eig(b, b.span_only ? SPAN_ITERS_F32 : (P.prec == TK_FP64 ? COLD_ITERS : COLD_ITERS_F32), s));
+            }
+            if (P.prec == TK_FP64) {
+                tk_status st = eig_converge(b, w, s);
+                if (st != TK_OK) return st;
+            }
         }
     }
     return TK_OK;
@@ -642,6 +755,10 @@ tk_status eig_update(const Plan& P, Work& w, int k, const double* Gs, hipStream_
     {
         ProfScope ps(TK_PROF_EIG, s);
         TK_LAUNCH(launch_eig(b, P.prec == TK_FP64 ? WARM_ITERS : WARM_ITERS_F32, s));
+    }
+    if (P.prec == TK_FP64) {
+        tk_status st = eig_converge(b, w, s);
+        if (st != TK_OK) return st;
     }
     if (!span) TK_LAUNCH(launch_copy_f64(b.U, w.U[k], (long)P.n[k] * P.R[k], s, w.bt));
     return TK_OK;
@@ -903,6 +1020,7 @@ tk_status alloc_result(tk_ctx* ctx, const int n[3], const int r[3], hipStream_t 
             blk = it->second;
             blk_bytes = it->first;
             ctx->rcache_bytes -= it->first;
+            ctx->idle.fetch_sub(it->first);
             ctx->rcache.erase(it);
         }
     }
@@ -914,6 +1032,23 @@ tk_status alloc_result(tk_ctx* ctx, const int n[3], const int r[3], hipStream_t 
             return fail(TK_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
         }
         blk_bytes = bytes;
+    }
+    // a reused block larger than the result is charged at its full size (or not reused)
+    if (blk_bytes > bytes) {
+        if (reserve(ctx, blk_bytes - bytes, false)) {
+            bytes = blk_bytes;
+        } else {
+            (void)hipFree(blk);
+            blk = nullptr;
+            hipError_t e = hipMalloc(&blk, bytes);
+            if (e != hipSuccess) {
+                release(ctx, bytes);
+                delete t;
+                return fail(TK_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+            }
+            blk_bytes = bytes;
+        }
+        t->bytes = bytes;
     }
     t->block = blk;
     t->block_bytes = blk_bytes;
@@ -954,6 +1089,7 @@ void free_result(tk_tucker* t)
                     ctx->rcache_bytes + t->block_bytes <= tk_ctx::kResultCacheBytes) {
                     ctx->rcache.emplace(t->block_bytes, t->block);
                     ctx->rcache_bytes += t->block_bytes;
+                    ctx->idle.fetch_add(t->block_bytes);
                     kept = true;
                 }
             }
@@ -1089,8 +1225,8 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void
 {
     const bool own_A = (A_in == nullptr);
     if (nb < 1 || nb > BATCH_MAX || (!own_A && nb != 1)) return fail(TK_EINVAL, "batch of %d problems", nb);
-    if (nb > 1 && P.eps_mode && P.prec == TK_FP64)
-        return fail(TK_EINVAL, "the FP64 eps path picks ranks between steps: one problem per call");
+    if (nb > 1 && (P.prec == TK_FP64 || P.converge))
+        return fail(TK_EINVAL, "the FP64 path and converged HOOI read back between steps: one problem per call");
     for (int b = 0; b < nb; ++b) { outs[b] = nullptr; sts[b] = TK_OK; }
     size_t ws = 0;
     const size_t total = batch_layout(P, own_A, nb, &ws);
@@ -1108,6 +1244,7 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void
     layout_work(ar, P, own_A, w);
     w.bt.nb = nb;
     w.bt.bs = (long)ws;
+    w.ctx = ctx;
     char* gather = (char*)base + ws * (size_t)nb;
     const int nmax = std::max(P.n[0], std::max(P.n[1], P.n[2]));
     const Real* A = own_A ? (const Real*)w.A : (const Real*)A_in;
@@ -1159,6 +1296,24 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void
         // ---- HOOI sweeps, then the core
         if (P.sweeps == 0) {
             if ((st = hosvd_core<Real>(P, w, A, s)) != TK_OK) return st;
+        } else if (P.converge) {
+            // sweeps until the core norm stops changing: | ||G|| - ||G_prev|| | <= tol ||A||, the
+            // first ||G_prev|| being that of the HOSVD core (norms read back after each sweep)
+            const long ncore = (long)P.R[0] * P.R[1] * P.R[2];
+            double na2 = 0.0, g2 = 0.0;
+            if ((st = readback(ctx, s, w.trace, sizeof(double), &na2)) != TK_OK) return st;
+            if ((st = hosvd_core<Real>(P, w, A, s)) != TK_OK) return st;
+            TK_LAUNCH(launch_dot<double>(w.core, w.core, ncore, w.partials, 64, w.scal + 12, s));
+            if ((st = readback(ctx, s, w.scal + 12, sizeof(double), &g2)) != TK_OK) return st;
+            double prev = std::sqrt(g2);
+            for (int it = 0; it < P.sweeps; ++it) {
+                if ((st = hooi_sweep<Real>(P, w, A, nmax, s)) != TK_OK) return st;
+                TK_LAUNCH(launch_dot<double>(w.core, w.core, ncore, w.partials, 64, w.scal + 12, s));
+                if ((st = readback(ctx, s, w.scal + 12, sizeof(double), &g2)) != TK_OK) return st;
+                const double cur = std::sqrt(g2);
+                if (std::fabs(cur - prev) <= CONVERGE_TOL * std::sqrt(na2)) break;
+                prev = cur;
+            }
         } else {
             for (int it = 0; it < P.sweeps; ++it)
                 if ((st = hooi_sweep<Real>(P, w, A, nmax, s)) != TK_OK) return st;
@@ -1180,7 +1335,7 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void
         return TK_OK;
     };
     tk_status st;
-    const bool capturable = own_A && wsp.cached && !(P.eps_mode && P.prec == TK_FP64) && !g_prof_on.load();
+    const bool capturable = own_A && wsp.cached && P.prec != TK_FP64 && !P.converge && !g_prof_on.load();
     if (ctx->graphs_on && capturable) {
         if ((st = run_captured<Real>(ctx, P, nb, base, grid, kps, w, s, pipeline)) != TK_OK) return st;
     } else if ((st = pipeline(s)) != TK_OK) {
@@ -1256,7 +1411,7 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void
         t->prec = P.prec;
         t->rel_err = hs[(size_t)b * 4 + 3];
         t->norm_a = std::sqrt(hs[(size_t)b * 4 + 0]);
-        if (P.eps_mode && !(t->rel_err <= P.eps)) sts[b] = TK_ENOCONV;
+        if ((P.eps_mode && !(t->rel_err <= P.eps)) || w.noconv) sts[b] = TK_ENOCONV;
     }
     // the results are complete when the call returns, for work on any stream
     if (hipStreamSynchronize(s) != hipSuccess) {
@@ -1309,9 +1464,10 @@ tk_status compress_group(tk_ctx* ctx, const tk_kernel* const* kernels, int nb, c
     return compress_impl<float>(ctx, kps, nb, nullptr, grid, P, s, outs, sts);
 }
 
-// Can problems with these options share launches?  (The FP64 eps path reads ranks back between
-// steps, so its problems run one per call.)
-bool groupable(const tk_opts* o) { return !(o->eps > 0 && o->prec == TK_FP64); }
+// Can problems with these options share launches?  (The FP64 path reads the eigensolver's
+// convergence flags -- and in eps mode the ranks -- back between steps, and converged HOOI the
+// core norm, so their problems run one per call.)
+bool groupable(const tk_opts* o) { return o->prec != TK_FP64 && o->hooi_sweeps != TK_HOOI_CONVERGE; }
 
 bool cov_geometry(const tk_tucker* t, int off[3], int m[3])
 {
@@ -1652,7 +1808,13 @@ tk_status quadform_fft_batch(tk_ctx* ctx, int count, const tk_tucker* const* ts,
     return st;
 }
 
-bool use_fft(const tk_ctx* ctx, int io) { return io == TK_FP32 && ctx->matvec_method != TK_MV_DENSE; }
+// The FFT form keeps the third factor's columns (padded to a multiple of 4) in one register
+// tile of at most LIB_RMAX; results of a higher third rank (FP64 compressions up to EIG_PMAX,
+// loaded files) take the dense form, which has no rank limit.
+bool use_fft(const tk_ctx* ctx, const tk_tucker* t, int io)
+{
+    return io == TK_FP32 && ctx->matvec_method != TK_MV_DENSE && ((t->r[2] + 3) & ~3) <= LIB_RMAX;
+}
 
 }  // namespace
 
@@ -1795,6 +1957,7 @@ void tk_ctx_destroy(tk_ctx* ctx)
         for (auto& kv : ctx->rcache) (void)hipFree(kv.second);
         ctx->rcache.clear();
         ctx->rcache_bytes = 0;
+        ctx->idle.store(0);
         now = (ctx->live_results == 0);
     }
     if (now) delete ctx;
@@ -1924,6 +2087,7 @@ tk_status tk_ctx_release_stream(tk_ctx* ctx, void* hip_stream)
         if (it == ctx->ws.end()) continue;
         if (it->second.busy) return fail(TK_EINVAL, "a call on this stream is still running");
         if (it->second.ptr) (void)hipFreeAsync(it->second.ptr, s);
+        ctx->idle.fetch_sub(it->second.bytes);
         ctx->ws.erase(it);
     }
     return TK_OK;
@@ -2262,7 +2426,7 @@ tk_status tk_kron_matvec(tk_ctx* ctx, const tk_tucker* t, const void* z_dev, voi
     TK_HIP(hipSetDevice(ctx->device));
     (void)hipGetLastError();
     if (io == TK_FP64 && ctx->matvec_method == TK_MV_FFT) return fail(TK_EINVAL, "the FFT matvec is FP32 only");
-    if (use_fft(ctx, io))
+    if (use_fft(ctx, t, io))
         return matvec_fft(ctx, t, (const float*)z_dev, (float*)y_dev, (hipStream_t)hip_stream, nullptr);
     if (io == TK_FP32)
         return matvec_impl<float>(ctx, t, (const float*)z_dev, (float*)y_dev, (hipStream_t)hip_stream, nullptr);
@@ -2283,7 +2447,7 @@ tk_status tk_quadratic_form(tk_ctx* ctx, const tk_tucker* t, const void* z_dev, 
     void* ybuf = y_dev;
     size_t esz = io == TK_FP32 ? 4 : 8;
     size_t ybytes = esz * (size_t)m[0] * m[1] * m[2];
-    const bool fft = use_fft(ctx, io);       // the FFT path sums z . y without storing y
+    const bool fft = use_fft(ctx, t, io);       // the FFT path sums z . y without storing y
     Reservation res(ctx, (y_dev || fft) ? 0 : ybytes);
     Ws yws;
     if (!y_dev && !fft) {
@@ -2313,7 +2477,9 @@ tk_status tk_quadratic_form_batch(tk_ctx* ctx, int count, const tk_tucker* const
     TK_HIP(hipSetDevice(ctx->device));
     (void)hipGetLastError();
     if (io != TK_FP64 && io != TK_FP32) return fail(TK_EINVAL, "io must be TK_FP64 or TK_FP32");
-    if (use_fft(ctx, io)) {
+    bool all_fft = true;
+    for (int i = 0; i < count; ++i) all_fft = all_fft && use_fft(ctx, ts[i], io);
+    if (all_fft) {
         for (int i = 0; i < count; ++i)
             if (!usable(ts[i])) return fail(TK_EINVAL, "item %d: result of a destroyed context", i);
         hipStream_t side;
@@ -2373,7 +2539,7 @@ tk_status tk_estimate_matvec_bytes(tk_ctx* ctx, const tk_tucker* t, int io, size
     if (io != TK_FP64 && io != TK_FP32) return fail(TK_EINVAL, "io must be TK_FP64 or TK_FP32");
     int off[3], m[3];
     if (!cov_geometry(t, off, m)) return fail(TK_ELAYOUT, "even-sized centred grid has no origin node");
-    if (use_fft(ctx, io)) return matvec_fft(ctx, t, nullptr, nullptr, nullptr, nullptr, bytes);
+    if (use_fft(ctx, t, io)) return matvec_fft(ctx, t, nullptr, nullptr, nullptr, nullptr, bytes);
     *bytes = matvec_work_bytes(t, io == TK_FP32 ? 4 : 8);
     return TK_OK;
 }
@@ -2520,7 +2686,7 @@ tk_status tk_eig_topr(tk_ctx* ctx, int count, int n, int r, const double* G_dev,
     (void)hipGetLastError();
     hipStream_t s = (hipStream_t)hip_stream;
     int p = (n <= EIG_PMAX) ? n : std::min(r + 8, EIG_PMAX);
-    size_t need = sizeof(double) * (size_t)count * (2 * (size_t)n * p + 2 * (size_t)p * p + 64) + 4096;
+    size_t need = sizeof(double) * (size_t)count * (2 * (size_t)n * p + 2 * (size_t)p * p + 64) + 8192;
     Reservation res(ctx, need);
     if (!res.take()) return fail(TK_ENOMEM, "eig needs %zu bytes", need);
     Ws wsp;
@@ -2538,6 +2704,25 @@ tk_status tk_eig_topr(tk_ctx* ctx, int count, int n, int r, const double* G_dev,
     b.lam = lambda_dev; b.sL = r;
     hipError_t e = launch_eig(b, COLD_ITERS, s);
     if (e != hipSuccess) return fail(TK_EHIP, "eig launch: %s", hipGetErrorString(e));
+    // iterate until the Ritz pairs pass the residual test, in groups of at most 64 problems
+    Work w{};
+    w.ctx = ctx;
+    w.eflags = ar.take<int>(64);
+    for (int c0 = 0; c0 < count; c0 += 64) {
+        EigBatch bc = b;
+        bc.count = std::min(64, count - c0);
+        bc.G = b.G + (long)c0 * b.sG;
+        bc.Q = b.Q + (long)c0 * n * p;
+        bc.Y = b.Y + (long)c0 * n * p;
+        bc.H = b.H + (long)c0 * p * p;
+        bc.Vs = b.Vs + (long)c0 * p * p;
+        bc.U = b.U + (long)c0 * b.sU;
+        bc.lam = b.lam + (long)c0 * b.sL;
+        tk_status st = eig_converge(bc, w, s);
+        if (st != TK_OK) return st;
+    }
+    TK_HIP(hipStreamSynchronize(s));
+    if (w.noconv) return fail(TK_ENOCONV, "eigensolver: residual test not met after %d rounds", EIG_MAX_ROUNDS);
     return TK_OK;
 }
 

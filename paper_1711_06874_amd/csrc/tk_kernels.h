@@ -100,6 +100,10 @@ struct EigBatch {
                      // writes U itself, by a conversion otherwise; moves by bs like the others
 };
 hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s);
+// Convergence test of the r Ritz pairs (lam, U) of each problem of b against its G:
+// flags[c] (c < count, moving by bs per batched problem) = 1 when every column has
+// ||G u_j - lam_j u_j|| <= max(tau lam_j, cfloor sqrt(n) u ||G||_F), else 0.  n <= 1024.
+hipError_t launch_eig_check(const EigBatch& b, double tau, double cfloor, int* flags, hipStream_t s);
 // Sign rule on the columns of U (n x r, ld ldu): a column whose entry of largest magnitude (ties
 // within 1e-10 relative, lowest index) is negative is negated, together with column c of V
 // (nv x r, ld ldv).

@@ -26,6 +26,7 @@ TK_OK, TK_EINVAL, TK_EUNSUPPORTED, TK_ELAYOUT, TK_ENOMEM, TK_EHIP, TK_ENOCONV = 
 TK_MATERN, TK_SLATER, TK_GAUSS = 0, 1, 2
 TK_CENTERED, TK_OFFSET = 0, 1
 TK_FP64, TK_FP32, TK_BF16X3 = 0, 1, 2
+TK_HOOI_CONVERGE = -2   # tk_opts.hooi_sweeps: Tucker-ALS until the core norm stops changing
 
 
 class tk_kernel(ctypes.Structure):
@@ -135,6 +136,17 @@ def _check(status: int, where: str, allow=()):
     return status
 
 
+def _check_result(status: int, out, where: str, allow_noconv: bool):
+    """A call that returns TK_ENOCONV still hands over a live result through `out`: free it
+    before raising, so an eps miss holds no device memory or budget."""
+    if status == TK_ENOCONV and not allow_noconv and out.value:
+        err = TkError(status, where)
+        _lib.tk_tucker_free(out.value)
+        out.value = None
+        raise err
+    _check(status, where, allow=(TK_ENOCONV,) if allow_noconv else ())
+
+
 def make_kernel(family=TK_MATERN, nu=0.5, ell=1.0, sigma2=1.0, alpha=1.0, p=1.0) -> tk_kernel:
     return tk_kernel(int(family), float(nu), float(ell), float(sigma2), float(alpha), float(p))
 
@@ -202,7 +214,7 @@ def tk_compress(ctx: int, kernel: tk_kernel, grid: tk_grid, opts: tk_opts, strea
     out = _vp()
     st = _lib.tk_compress(ctx, ctypes.byref(kernel), ctypes.byref(grid), ctypes.byref(opts), _stream(stream),
                           ctypes.byref(out))
-    _check(st, "tk_compress", allow=(TK_ENOCONV,) if allow_noconv else ())
+    _check_result(st, out, "tk_compress", allow_noconv)
     return out.value
 
 
@@ -210,7 +222,7 @@ def tk_compress_tensor(ctx: int, A, grid: tk_grid, opts: tk_opts, stream=None, a
     out = _vp()
     st = _lib.tk_compress_tensor(ctx, _ptr(A), ctypes.byref(grid), ctypes.byref(opts), _stream(stream),
                                  ctypes.byref(out))
-    _check(st, "tk_compress_tensor", allow=(TK_ENOCONV,) if allow_noconv else ())
+    _check_result(st, out, "tk_compress_tensor", allow_noconv)
     return out.value
 
 

@@ -40,3 +40,19 @@ def sign_align(V, ref):
 
 def say(*args):
     print(*args, flush=True)
+
+
+U64 = 2.0 ** -53
+
+
+def fp64_e_tolerance(lams, r, e, na2, n):
+    """Parity tolerance of an FP64 HOSVD/HOOI error E against the oracle: 1e-10 E, or the
+    Gram route's floor if larger.  Both eigensolvers are backward stable (exact for a Gram
+    perturbed by about n u ||G||); E is stationary in the factors at the exact eigenvectors, so
+    the perturbation moves it at second order, by about
+    (n u lambda_1)^2 / ((lambda_r - lambda_{r+1}) E ||A||^2) per mode."""
+    floor = 0.0
+    for lam in lams:
+        gap = lam[r - 1] - lam[r] if r < len(lam) else lam[r - 1]
+        floor += (n * U64 * lam[0]) ** 2 / (max(gap, 1e-300) * max(e, 1e-300) * na2)
+    return max(1e-10 * e, floor)
