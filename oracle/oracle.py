@@ -424,3 +424,68 @@ def quadratic_form(t: Tucker, g: Grid, z: np.ndarray) -> float:
     """z^T C z with the plain matrix-vector product."""
     y = cov_matvec(t, g, z)
     return float(np.dot(_f64(z).reshape(-1), y.reshape(-1)))
+
+
+# ----------------------------------------------------------------------------------------
+# Multigrid Tucker (Sec. 3.2, last paragraph; Sec. 3.7 Fig. 7)
+# ----------------------------------------------------------------------------------------
+
+def multigrid_sizes(n: int, levels: int) -> list:
+    """Points per axis from the coarsest level to n: each coarser level has (n + 1) // 2 points
+    (dyadic refinement: 2^k + 1 -> 2^(k-1) + 1 nests the vertex grids; 2^k -> 2^(k-1))."""
+    sizes = [int(n)]
+    for _ in range(int(levels)):
+        sizes.append((sizes[-1] + 1) // 2)
+    return sizes[::-1]
+
+
+def interpolate_factor(U: np.ndarray, x_coarse: np.ndarray, x_fine: np.ndarray) -> np.ndarray:
+    """Each column of U, read as a function sampled at x_coarse (uniform), linearly interpolated
+    to the nodes x_fine of the same interval."""
+    nc = x_coarse.shape[0]
+    h = (x_coarse[-1] - x_coarse[0]) / (nc - 1)
+    V = np.empty((x_fine.shape[0], U.shape[1]), dtype=np.float64)
+    for j, x in enumerate(x_fine):
+        t = (x - x_coarse[0]) / h
+        i = min(max(int(np.floor(t)), 0), nc - 2)
+        w = t - i
+        for c in range(U.shape[1]):
+            V[j, c] = (1.0 - w) * U[i, c] + w * U[i + 1, c]
+    return V
+
+
+def orthonormalize(U: np.ndarray) -> np.ndarray:
+    """Modified Gram-Schmidt, applied twice (columns orthonormal to rounding)."""
+    Q = _f64(U).copy()
+    for _ in range(2):
+        for c in range(Q.shape[1]):
+            for p in range(c):
+                Q[:, c] -= np.dot(Q[:, p], Q[:, c]) * Q[:, p]
+            Q[:, c] /= np.sqrt(np.dot(Q[:, c], Q[:, c]))
+    return Q
+
+
+def multigrid_compress(k: Kernel, g: Grid, ranks, levels: int, sweeps=2) -> Tucker:
+    """Multigrid Tucker: truncated HOSVD only on the coarsest grid; on each finer grid the
+    factors of the previous level, interpolated to the new nodes and orthonormalised, start
+    `sweeps` Tucker-ALS sweeps (None = to convergence) on that level's tensor.  No Gram of a
+    fine-grid tensor is formed."""
+    sizes = [multigrid_sizes(n, levels) for n in g.n]
+    t = None
+    xs_prev = None
+    for lev in range(levels + 1):
+        gl = Grid(n=tuple(s[lev] for s in sizes), b=g.b, layout=g.layout)
+        A = grid_eval(k, gl)
+        xs = [grid_coords(gl.n[a], gl.b[a], gl.layout) for a in range(3)]
+        r = tuple(min(int(ranks[a]), gl.n[a]) for a in range(3))
+        if t is None:
+            t = hosvd(A, r)
+        else:
+            U = [orthonormalize(interpolate_factor(t.U[a], xs_prev[a], xs[a])) for a in range(3)]
+            init = Tucker(U=U, core=project_core(A, U), norm_a2=sumsq(A))
+            init.rel_err = rel_error(A, init)
+            t = init
+        if sweeps != 0:
+            t = hooi(A, t, sweeps=sweeps)
+        xs_prev = xs
+    return t

@@ -538,3 +538,55 @@ def test_quadratic_form_is_dot(oracle):
     C = _dense_cov_from_generator(oracle.reconstruct(t.core, t.U), (0, 0, 0), g.n)
     assert oracle.quadratic_form(t, g, z) == pytest.approx(z.reshape(-1) @ C @ z.reshape(-1),
                                                            rel=1e-12)
+
+
+# ------------------------------------------------------------------- multigrid Tucker ----
+
+def test_multigrid_sizes(oracle):
+    assert oracle.multigrid_sizes(513, 3) == [65, 129, 257, 513]
+    assert oracle.multigrid_sizes(1024, 3) == [128, 256, 512, 1024]
+    assert oracle.multigrid_sizes(100, 1) == [50, 100]
+
+
+def test_multigrid_interpolation_is_exact_on_linear_columns(oracle):
+    """Linear interpolation reproduces affine functions exactly, nested (2^k+1 grids) or not."""
+    for (nc, nf, layout) in [(9, 17, oracle.CENTERED), (16, 32, oracle.OFFSET), (7, 20, oracle.CENTERED)]:
+        xc = oracle.grid_coords(nc, 1.3, layout)
+        xf = oracle.grid_coords(nf, 1.3, layout)
+        U = np.stack([1.0 + 2.0 * xc, 3.0 - 0.5 * xc], axis=1)
+        want = np.stack([1.0 + 2.0 * xf, 3.0 - 0.5 * xf], axis=1)
+        np.testing.assert_allclose(oracle.interpolate_factor(U, xc, xf), want, rtol=0, atol=1e-14)
+
+
+def test_orthonormalize_keeps_the_span(oracle):
+    U = synth.random_tensor((40, 6, 1), 3)[:, :, 0]
+    Q = oracle.orthonormalize(U)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(6), rtol=0, atol=1e-14)
+    # U = Q (Q^T U): the columns of U lie in the span of Q
+    np.testing.assert_allclose(Q @ (Q.T @ U), U, rtol=0, atol=1e-13)
+
+
+def test_multigrid_reaches_the_direct_optimum(oracle):
+    """Sec. 3.2: the multigrid start (coarse HOSVD, interpolated factors) and the direct start
+    (HOSVD on the fine grid) lead converged Tucker-ALS to the same approximation."""
+    k = oracle.Kernel(oracle.MATERN, nu=1.5, ell=0.3)
+    g = oracle.Grid(n=(65, 65, 65), b=(1.0, 1.0, 1.0))
+    A = oracle.grid_eval(k, g)
+    f = oracle.hosvd_factors(A)
+    for r in (3, 5, 7):
+        mg = oracle.multigrid_compress(k, g, (r, r, r), 2, sweeps=None)
+        d = oracle.hooi(A, oracle.hosvd(A, (r, r, r), f), sweeps=None)
+        assert mg.rel_err == pytest.approx(d.rel_err, rel=1e-6), r
+
+
+def test_multigrid_table_4_2_n129(oracle):
+    """Table 4.2 at n = 129 reproduced through the multigrid route 33 -> 65 -> 129."""
+    tab = json.load(open(os.path.join(GOLDEN, "table_4_2.json")))
+    b = tab["box_half_width"]
+    printed = tab["printed"]["129"]
+    k = oracle.Kernel(oracle.SLATER, alpha=1.0, p=1.0, ell=1.0)
+    g = oracle.Grid(n=(129, 129, 129), b=(b, b, b))
+    for r in (1, 3, 5, 7, 9):
+        t = oracle.multigrid_compress(k, g, (r, r, r), 2, sweeps=None)
+        err = 1.0 - oracle.reconstruct(t.core, t.U)[64, 64, 64]
+        assert err == pytest.approx(printed[r - 1], rel=tab["rel_tol"]), (r, err)
