@@ -470,6 +470,54 @@ void tko_cov_rows(const double *Q, const int q[3], const int off[3], const int m
     }
 }
 
+/* ------------------------------------------------------------------------------------ */
+/* Separable (rank-1 Kronecker) covariance, Sec. 4 "Separable covariance matrices":      */
+/* C = C_1 (x) C_2 (x) C_3, Cholesky, inverse and log-determinant per factor.            */
+/* ------------------------------------------------------------------------------------ */
+
+/* In-place Cholesky C = L L^T of a symmetric positive definite n x n matrix (row-major; the
+ * lower triangle receives L, the strict upper triangle is zeroed).  Plain column-by-column
+ * algorithm: L_jj = sqrt(C_jj - sum_k L_jk^2), L_ij = (C_ij - sum_k L_ik L_jk) / L_jj.
+ * Returns 0, or j + 1 if the j-th pivot is not positive. */
+int tko_cholesky(int n, double *C)
+{
+    for (int j = 0; j < n; ++j) {
+        double d = C[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= C[(size_t)j * n + k] * C[(size_t)j * n + k];
+        if (!(d > 0.0)) return j + 1;
+        double ljj = sqrt(d);
+        C[(size_t)j * n + j] = ljj;
+#pragma omp parallel for schedule(static)
+        for (int i = j + 1; i < n; ++i) {
+            double v = C[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) v -= C[(size_t)i * n + k] * C[(size_t)j * n + k];
+            C[(size_t)i * n + j] = v / ljj;
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) C[(size_t)i * n + j] = 0.0;
+    return 0;
+}
+
+/* Solve (L L^T) x = b for `nrhs` right-hand sides stored as the columns of B (n x nrhs,
+ * row-major), in place: forward substitution with L, then back substitution with L^T. */
+void tko_chol_solve(int n, const double *L, int nrhs, double *B)
+{
+#pragma omp parallel for schedule(static)
+    for (int c = 0; c < nrhs; ++c) {
+        for (int i = 0; i < n; ++i) {
+            double v = B[(size_t)i * nrhs + c];
+            for (int k = 0; k < i; ++k) v -= L[(size_t)i * n + k] * B[(size_t)k * nrhs + c];
+            B[(size_t)i * nrhs + c] = v / L[(size_t)i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double v = B[(size_t)i * nrhs + c];
+            for (int k = i + 1; k < n; ++k) v -= L[(size_t)k * n + i] * B[(size_t)k * nrhs + c];
+            B[(size_t)i * nrhs + c] = v / L[(size_t)i * n + i];
+        }
+    }
+}
+
 int tko_num_threads(void)
 {
 #ifdef _OPENMP

@@ -590,3 +590,58 @@ def test_multigrid_table_4_2_n129(oracle):
         t = oracle.multigrid_compress(k, g, (r, r, r), 2, sweeps=None)
         err = 1.0 - oracle.reconstruct(t.core, t.U)[64, 64, 64]
         assert err == pytest.approx(printed[r - 1], rel=tab["rel_tol"]), (r, err)
+
+
+# ------------------------------------------------- separable covariance (rank-1 Kronecker) ----
+
+def _kron3(a, b, c):
+    return np.kron(np.kron(a, b), c)
+
+
+def test_kron1_cholesky_matches_numpy(oracle):
+    """Backward error ||L L^T - C|| at the rounding level, and numpy's factor to within the
+    forward error that the condition number allows (cond(C) u)."""
+    for n, ell in [(7, 0.4), (30, 0.9), (64, 0.2)]:
+        C = oracle.cov_factor_1d(oracle.Kernel(oracle.GAUSS, ell=ell), n, 1.0, nugget=1e-6)
+        L = oracle.cholesky(C)
+        assert np.abs(L @ L.T - C).max() <= 4 * n * 2.2e-16 * np.abs(C).max()
+        tol = 10 * np.linalg.cond(C) * 2.2e-16
+        np.testing.assert_allclose(L, np.linalg.cholesky(C), rtol=0, atol=tol)
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle.cholesky(-np.eye(3))
+
+
+def test_gaussian_covariance_is_a_kronecker_product(oracle):
+    """Sec. 4: the Gaussian covariance exp(-|x - y|^2 / ell^2) of the 3-D grid is exactly
+    C_1 (x) C_2 (x) C_3 of its 1-D factors (checked against the plain covariance product of the
+    offset generator, a different route)."""
+    n = (4, 5, 3)
+    k = oracle.Kernel(oracle.GAUSS, ell=0.7)
+    Cs = [oracle.cov_factor_1d(k, n[a], 1.0) for a in range(3)]
+    g = oracle.Grid(n=n, layout=oracle.OFFSET)
+    Q = oracle.grid_eval(k, g)
+    N = int(np.prod(n))
+    dense = np.stack([oracle.cov_rows_from_generator(Q, g, np.eye(N)[j], np.arange(N)) for j in range(N)], axis=1)
+    np.testing.assert_allclose(_kron3(*Cs), dense, rtol=1e-14, atol=1e-15)
+
+
+def test_kron1_lemmas_against_dense(oracle):
+    """Cholesky, inverse, log-determinant and log-likelihood of C = C_1 (x) C_2 (x) C_3 (the
+    lemmas of Sec. 4) against the dense N x N matrix: numpy's Cholesky, slogdet and solve and
+    scipy's multivariate normal log-density (test-only libraries)."""
+    from scipy.stats import multivariate_normal
+    n = (4, 6, 5)
+    ks = [oracle.Kernel(oracle.GAUSS, ell=0.6), oracle.Kernel(oracle.MATERN, nu=1.5, ell=0.4),
+          oracle.Kernel(oracle.GAUSS, ell=1.1)]
+    Cs = [oracle.cov_factor_1d(ks[a], n[a], 1.0, nugget=1e-2) for a in range(3)]
+    Ls = [oracle.cholesky(C) for C in Cs]
+    C = _kron3(*Cs)
+    L = _kron3(*Ls)
+    np.testing.assert_allclose(L, np.linalg.cholesky(C), rtol=0, atol=1e-12)
+    z = synth.random_tensor(n, 8)
+    zf = z.reshape(-1)
+    assert oracle.kron1_logdet(Ls) == pytest.approx(np.linalg.slogdet(C)[1], rel=1e-12)
+    np.testing.assert_allclose(oracle.kron1_solve(Ls, z).reshape(-1), np.linalg.solve(C, zf), rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(oracle.kron1_chol_apply(Ls, z).reshape(-1), L @ zf, rtol=1e-13, atol=1e-14)
+    ref = multivariate_normal(mean=np.zeros(zf.size), cov=C).logpdf(zf)
+    assert oracle.kron1_loglik(Ls, z) == pytest.approx(ref, rel=1e-11)
