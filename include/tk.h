@@ -40,8 +40,8 @@ typedef enum {
     TK_OK = 0,
     TK_EINVAL = -1,        /* bad argument: NULL pointer, n < 2, ell <= 0, sigma2 <= 0,
                               non-finite value, neither eps nor ranks given, ...            */
-    TK_EUNSUPPORTED = -2,  /* valid but not implemented: Matern nu not in {1/2, 3/2, 5/2},
-                              more than 1024 points per axis, rank above the library cap     */
+    TK_EUNSUPPORTED = -2,  /* valid but not implemented: Matern nu above 30, more than
+                              1024 points per axis, rank above the library cap               */
     TK_ELAYOUT = -3,       /* covariance operation on a grid without an origin node
                               (an even-sized centred grid)                                   */
     TK_ENOMEM = -4,        /* the estimated device memory exceeds the context's remaining
@@ -55,10 +55,16 @@ typedef enum {
 /* Problem description                                                                       */
 /* ---------------------------------------------------------------------------------------- */
 typedef enum {
-    TK_MATERN = 0,  /* sigma2 * C_{nu,ell}(r), Sec. 2.2 eq. (2.3); nu in {0.5, 1.5, 2.5}      */
+    TK_MATERN = 0,  /* sigma2 * C_{nu,ell}(r), Sec. 2.2 eq. (2.3); 0 < nu <= 30.  nu = 1/2, 3/2,
+                       5/2 take the closed forms, other orders K_nu (Temme's series for
+                       arguments <= 2, Steed's continued fraction above, upward recurrence)   */
     TK_SLATER = 1,  /* sigma2 * exp(-alpha * (r/ell)^p), the p-Slater function of Sec. 3.7
                        eq. (3.27) with an amplitude, a rate and a length scale               */
     TK_GAUSS = 2,   /* sigma2 * exp(-(r/ell)^2): the separable (rank-1) case of Sec. 4.4      */
+    TK_SPECTRAL = 3,/* sigma2 * f_{alpha,nu}(rho), the Matern spectral density of Diagram 1
+                       in Sec. 2.2 / eq. (3.28) in d = 3: Gamma(nu+3/2) alpha^(2nu) /
+                       (pi^(3/2) Gamma(nu)) (alpha^2 + rho^2)^-(nu+3/2), rho the grid radius;
+                       uses nu and alpha (ell is ignored)                                     */
 } tk_family;
 
 typedef enum {
@@ -83,8 +89,11 @@ typedef struct {
     double nu;       /* Matern smoothness (TK_MATERN only) */
     double ell;      /* length scale, > 0 */
     double sigma2;   /* variance, > 0 */
-    double alpha;    /* Slater rate, > 0 (TK_SLATER only) */
+    double alpha;    /* Slater rate, > 0 (TK_SLATER); spectral density parameter (TK_SPECTRAL) */
     double p;        /* Slater exponent, in (0, 2] (TK_SLATER only) */
+    double metric[3];/* anisotropic distance r^2 = sum_k metric[k] x_k^2, a positive diagonal
+                        metric (Sec. 2.2); all zero = the Euclidean distance.  The covariance
+                        stays stationary, so the Toeplitz operators of Sec. 3.6 still apply   */
 } tk_kernel;
 
 typedef struct {
@@ -165,6 +174,20 @@ tk_status tk_compress(tk_ctx *ctx, const tk_kernel *kernel, const tk_grid *grid,
  * the sizes and the layout that later covariance calls use.  Synchronising. */
 tk_status tk_compress_tensor(tk_ctx *ctx, const void *A_dev, const tk_grid *grid,
                              const tk_opts *opts, void *hip_stream, tk_tucker **out);
+
+/* Multigrid Tucker (Sec. 3.2, last paragraph; Fig. 7 of Sec. 3.7): the truncated HOSVD runs
+ * only on the coarsest of levels + 1 grids over the same box (each coarser grid has (n + 1) / 2
+ * points per axis: 2^k + 1 -> 2^(k-1) + 1 nests the vertex grids, 2^k -> 2^(k-1) halves them).
+ * On each finer grid the factors of the previous level, linearly interpolated to the new nodes
+ * and orthonormalised (Householder QR), start opts->hooi_sweeps Tucker-ALS sweeps (at least
+ * one; TK_HOOI_CONVERGE on the FP64 path) on that grid's tensor: no Gram of a fine-grid tensor
+ * is formed, so the cost is linear in the number of grid points.  The ranks are those of the
+ * coarsest level (fixed ranks, or the eps rule applied there); the error returned is measured
+ * on the finest grid, and TK_ENOCONV is returned with the result when it exceeds eps.
+ * levels = 0 is tk_compress.  Synchronising.  Errors: as tk_compress; TK_EINVAL when the
+ * coarsest grid would have fewer than 2 points per axis or levels > 8. */
+tk_status tk_compress_multigrid(tk_ctx *ctx, const tk_kernel *kernel, const tk_grid *grid, int levels,
+                                const tk_opts *opts, void *hip_stream, tk_tucker **out);
 
 /* Compress `count` independent problems (kernels[i] on grids[i], sizes may differ, all with
  * *opts) in one call.  Problems on the same grid share their launches: up to 32 of them (fewer
@@ -322,6 +345,48 @@ tk_status tk_quadratic_form(tk_ctx *ctx, const tk_tucker *t, const void *z_dev, 
 tk_status tk_quadratic_form_batch(tk_ctx *ctx, int count, const tk_tucker *const *ts,
                                   const void *const *z_devs, int io, void *hip_stream, double *out,
                                   void *const *y_devs);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Separable covariance: rank-1 Kronecker algebra (Sec. 4, "Separable covariance matrices")   */
+/* ---------------------------------------------------------------------------------------- */
+/* A covariance that factors over the axes, C = C_1 (x) C_2 (x) C_3 with
+ * C_k[i][j] = kernels[k](|x_i - x_j|) + nugget[k] [i == j] on axis k of the grid (for the
+ * Gaussian exp(-|x - y|^2 / ell^2) this is exactly its covariance on the 3-D grid).  The
+ * product of the three kernels' sigma2 scales C (give it on one axis and 1 on the others).
+ * The operator acts on n1 x n2 x n3 vectors in C order, (M1 (x) M2 (x) M3) vec(Z) =
+ * vec(Z x_1 M1 x_2 M2 x_3 M3).  The lemmas of Sec. 4 reduce every operation to the factors:
+ *   Cholesky: C = L L^T with L = L_1 (x) L_2 (x) L_3 (each L_k by a blocked FP64 Cholesky);
+ *   inverse: C^-1 = C_1^-1 (x) C_2^-1 (x) C_3^-1;
+ *   log det C = sum_j (N / n_j) log det C_j, log det C_j = 2 sum_i log L_j[i][i];
+ *   log-likelihood of z under N(0, C): -1/2 (N log(2 pi) + log det C + z^T C^-1 z).
+ * (The printed log-likelihood formula of that section is garbled; this is the Gaussian one.) */
+typedef struct tk_kron1 tk_kron1;
+typedef enum { TK_KRON1_SOLVE = 0, TK_KRON1_CHOL = 1 } tk_kron1_op;
+
+/* Build the three factors on the device and their Cholesky factors and log-determinants.
+ * kernels: 3 covariance functions (any family; metric ignored), grid: points and box per axis
+ * (n_k <= 16384; layout as for tk_compress), nugget: 3 values >= 0 (NULL = none).  The
+ * factors stay resident (8 n_k^2 bytes each, charged to the budget) until tk_kron1_free.
+ * Synchronising.  Errors: TK_EINVAL (NULL, bad kernel, a factor that is not positive definite:
+ * add a nugget), TK_EUNSUPPORTED, TK_ENOMEM, TK_EHIP. */
+tk_status tk_kron1_create(tk_ctx *ctx, const tk_kernel kernels[3], const tk_grid *grid, const double nugget[3],
+                          void *hip_stream, tk_kron1 **out);
+/* log det C (and, if logdet_axis is not NULL, log det C_k per axis).  Host only. */
+tk_status tk_kron1_logdet(const tk_kron1 *k, double *out, double logdet_axis[3]);
+/* Copy L_axis (n x n row-major, lower triangular) to host memory.  Synchronising. */
+tk_status tk_kron1_factor(const tk_kron1 *k, int axis, double *L_host);
+/* y = C^-1 z (op TK_KRON1_SOLVE) or y = L z (op TK_KRON1_CHOL: with z ~ N(0, I), y ~ N(0, C)).
+ * z_dev, y_dev: N = n1 n2 n3 doubles on the device, y may not alias z.  The solve forms
+ * C_k^-1 = L_k^-T L_k^-1 once (n_k <= 1024, kept with the object; synchronising the first time)
+ * and applies it along each mode on FP64 MFMA.  Stream-ordered.
+ * Errors: TK_EINVAL, TK_EUNSUPPORTED (solve with an axis above 1024), TK_ENOMEM, TK_EHIP. */
+tk_status tk_kron1_apply(tk_ctx *ctx, tk_kron1 *k, int op, const double *z_dev, double *y_dev, void *hip_stream);
+/* Gaussian log-likelihood of z (device, N doubles) under N(0, C); quad_out (optional) receives
+ * z^T C^-1 z.  Synchronising.  Errors: as tk_kron1_apply. */
+tk_status tk_kron1_loglik(tk_ctx *ctx, tk_kron1 *k, const double *z_dev, void *hip_stream, double *out,
+                          double *quad_out);
+/* Release the factors (after the work queued on them).  NULL is ignored. */
+void tk_kron1_free(tk_kron1 *k);
 
 /* ---------------------------------------------------------------------------------------- */
 /* Individual steps (the same kernels tk_compress runs), exposed for testing and profiling   */

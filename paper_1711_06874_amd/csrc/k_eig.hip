@@ -961,6 +961,37 @@ static hipError_t eig_body(const EigBatch& b, int iters, hipStream_t s, bool& wr
     return hipGetLastError();
 }
 
+hipError_t launch_qr(const double* in, double* out, int count, int n, int p, hipStream_t s)
+{
+    if (n < 1 || p < 1 || p > n || p > EIG_PMAX) return hipErrorInvalidValue;
+    return qr_launch(in, out, count, n, p, s, Bat());
+}
+
+// Column c of the fine factor at node j: the coarse column, read as a function on the uniform
+// coarse nodes x0c + i hc, linearly interpolated at x0f + j hf (the same interval).
+__global__ void __launch_bounds__(256) k_interp_factor(const double* __restrict__ Uc, int nc, double x0c, double hc,
+                                                       double* __restrict__ Uf, int nf, double x0f, double hf, int r)
+{
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)nf * r) return;
+    const int j = (int)(e / r), c = (int)(e - (long)j * r);
+    const double t = ((x0f + j * hf) - x0c) / hc;
+    int i = (int)floor(t);
+    i = i < 0 ? 0 : (i > nc - 2 ? nc - 2 : i);
+    const double w = t - i;
+    Uf[e] = (1.0 - w) * Uc[(long)i * r + c] + w * Uc[(long)(i + 1) * r + c];
+}
+
+hipError_t launch_interp_factor(const double* Uc, int nc, double x0c, double hc, double* Uf, int nf, double x0f,
+                                double hf, int r, hipStream_t s)
+{
+    if (nc < 2 || nf < 1 || r < 1) return hipErrorInvalidValue;
+    const long tot = (long)nf * r;
+    hipLaunchKernelGGL(k_interp_factor, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Uc, nc, x0c, hc, Uf,
+                       nf, x0f, hf, r);
+    return hipGetLastError();
+}
+
 hipError_t launch_eig_check(const EigBatch& b, double tau, double cfloor, int* flags, hipStream_t s)
 {
     if (b.n < 1 || b.n > 1024 || b.r < 1) return hipErrorInvalidValue;

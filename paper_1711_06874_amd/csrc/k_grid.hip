@@ -37,13 +37,14 @@ __global__ void __launch_bounds__(256) k_grid_eval(T* __restrict__ A, GridAxes g
         i1 = (int)(row % g.n[1]);
         i0 = (int)(row / g.n[1]);
     }
-    double x = g.x0[0] + (double)i0 * g.h[0];
-    double y = g.x0[1] + (double)i1 * g.h[1];
+    // coordinates scaled by sqrt(a_k) for an anisotropic metric (exactly 1 otherwise)
+    double x = (g.x0[0] + (double)i0 * g.h[0]) * kp.axs[0];
+    double y = (g.x0[1] + (double)i1 * g.h[1]) * kp.axs[1];
     double xy = x * x + y * y;
     T out[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        double z = g.x0[2] + (double)(i2 + t) * g.h[2];
+        double z = (g.x0[2] + (double)(i2 + t) * g.h[2]) * kp.axs[2];
         const double r2 = xy + z * z;
         if constexpr (sizeof(T) == 4) out[t] = (T)cov_value_for_float(kp, r2);
         else out[t] = (T)cov_value(kp, sqrt(r2));

@@ -63,6 +63,8 @@ constexpr int WARM_ITERS = 2;         // ... from the previous factor (FP64 path
 constexpr int WARM_ITERS_F32 = 1;     // ... float paths: one block power step per HOOI update
 constexpr int SPAN_ITERS_F32 = 3;     // float eps path, HOSVD start: R-column block, subspace only
 constexpr int NMAX = 1024;
+constexpr double MATERN_NU_MAX = 30.0;
+constexpr int KRON1_NMAX = 16384;       // points per axis of a separable covariance factor   // general orders: K_nu s^nu stays inside the double range
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -343,27 +345,46 @@ bool finite(double x) { return std::isfinite(x); }
 tk_status check_kernel(const tk_kernel* k, KernelParams* kp)
 {
     if (!k) return fail(TK_EINVAL, "kernel is NULL");
-    if (!finite(k->ell) || k->ell <= 0) return fail(TK_EINVAL, "ell must be finite and > 0");
     if (!finite(k->sigma2) || k->sigma2 <= 0) return fail(TK_EINVAL, "sigma2 must be finite and > 0");
+    if (k->family != TK_SPECTRAL && (!finite(k->ell) || k->ell <= 0))
+        return fail(TK_EINVAL, "ell must be finite and > 0");
     kp->family = k->family;
     kp->sigma2 = k->sigma2;
     kp->alpha = k->alpha;
     kp->p = k->p;
     kp->half = 0;
+    kp->nu = k->nu;
+    kp->lpref = 0.0;
+    // anisotropic metric: all zero = the identity; otherwise every entry finite and > 0
+    const bool iso = k->metric[0] == 0.0 && k->metric[1] == 0.0 && k->metric[2] == 0.0;
+    for (int a = 0; a < 3; ++a) {
+        if (!iso && !(finite(k->metric[a]) && k->metric[a] > 0))
+            return fail(TK_EINVAL, "metric[%d]=%g: the diagonal metric needs entries > 0 (or all 0)", a, k->metric[a]);
+        kp->axs[a] = iso ? 1.0 : std::sqrt(k->metric[a]);
+    }
     if (k->family == TK_MATERN) {
-        if (!finite(k->nu)) return fail(TK_EINVAL, "nu must be finite");
+        if (!finite(k->nu) || k->nu <= 0) return fail(TK_EINVAL, "Matern nu must be finite and > 0");
+        if (k->nu > MATERN_NU_MAX) return fail(TK_EUNSUPPORTED, "Matern nu=%g exceeds %g", k->nu, MATERN_NU_MAX);
         int half = -1;
         for (int h = 0; h < 3; ++h)
             if (std::fabs(k->nu - (h + 0.5)) < 1e-12) half = h;
-        if (half < 0) return fail(TK_EUNSUPPORTED, "Matern nu=%g: only 0.5, 1.5, 2.5 are supported", k->nu);
         kp->half = half;
-        kp->inv_len = std::sqrt(2.0 * (half + 0.5)) / k->ell;
+        kp->inv_len = std::sqrt(2.0 * (half >= 0 ? half + 0.5 : k->nu)) / k->ell;
+        if (half < 0) kp->lpref = (1.0 - k->nu) * std::log(2.0) - std::lgamma(k->nu);
     } else if (k->family == TK_SLATER) {
         if (!finite(k->alpha) || k->alpha <= 0) return fail(TK_EINVAL, "Slater alpha must be > 0");
         if (!finite(k->p) || k->p <= 0 || k->p > 2) return fail(TK_EINVAL, "Slater p must be in (0, 2]");
         kp->inv_len = 1.0 / k->ell;
     } else if (k->family == TK_GAUSS) {
         kp->inv_len = 1.0 / k->ell;
+    } else if (k->family == TK_SPECTRAL) {
+        if (!finite(k->nu) || k->nu <= 0 || k->nu > MATERN_NU_MAX)
+            return fail(TK_EINVAL, "spectral density nu must be in (0, %g]", MATERN_NU_MAX);
+        if (!finite(k->alpha) || k->alpha <= 0) return fail(TK_EINVAL, "spectral density alpha must be > 0");
+        kp->alpha = k->alpha * k->alpha;
+        kp->inv_len = 1.0;
+        kp->lpref = std::lgamma(k->nu + 1.5) - std::lgamma(k->nu) + 2.0 * k->nu * std::log(k->alpha) -
+                    1.5 * std::log(M_PI);
     } else {
         return fail(TK_EINVAL, "unknown kernel family %d", k->family);
     }
@@ -402,6 +423,7 @@ struct Plan {
     double eps;
     int sweeps;
     bool converge;     // HOOI until | ||G|| - ||G_prev|| | <= 1e-13 ||A|| (at most `sweeps`)
+    const double* init_U[3];   // start factors (n_k x R_k, orthonormal) instead of the HOSVD
     bool cubic;
     int gsplit[3];     // K chunks per tile pair of the Gram of A per mode (0: default)
 };
@@ -440,6 +462,7 @@ tk_status make_plan(const tk_grid* g, const tk_opts* o, Plan* P)
     }
     P->cubic = (g->n[0] == g->n[1] && g->n[1] == g->n[2]);
     for (int k = 0; k < 3; ++k) P->gsplit[k] = 0;
+    for (int k = 0; k < 3; ++k) P->init_U[k] = nullptr;
     return TK_OK;
 }
 
@@ -1259,12 +1282,19 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void
             if (sizeof(Real) == 4) TK_LAUNCH(launch_grid_eval_f32((float*)w.A, ax, kps, s, w.bt));
             else TK_LAUNCH(launch_grid_eval_f64((double*)w.A, ax, kps, s, w.bt));
         }
-        // ---- HOSVD: Grams and leading eigenvectors
-        for (int k = 0; k < 3; ++k) {
-            ProfScope ps(TK_PROF_GRAM, s);
-            TK_LAUNCH(launch_gram(A, P.n, k, P.prec, w.G + (long)k * nmax * nmax, w.gram_work, s, w.bt, P.gsplit[k]));
+        if (P.init_U[0]) {
+            // ---- given start factors (multigrid): no Gram; ||A||^2 for the convergence test
+            for (int k = 0; k < 3; ++k)
+                TK_LAUNCH(launch_copy_f64(P.init_U[k], w.U[k], (long)P.n[k] * P.R[k], s));
+            TK_LAUNCH(launch_dot<Real>(A, A, (long)P.n[0] * P.n[1] * P.n[2], w.partials, 1024, w.trace, s));
+        } else {
+            // ---- HOSVD: Grams and leading eigenvectors
+            for (int k = 0; k < 3; ++k) {
+                ProfScope ps(TK_PROF_GRAM, s);
+                TK_LAUNCH(launch_gram(A, P.n, k, P.prec, w.G + (long)k * nmax * nmax, w.gram_work, s, w.bt, P.gsplit[k]));
+            }
+            if ((st = eig_modes(P, w, nmax, s)) != TK_OK) return st;
         }
-        if ((st = eig_modes(P, w, nmax, s)) != TK_OK) return st;
 
         if (P.eps_mode && P.prec == TK_FP64) {
             // rank rule on the Gram eigenvalues: tail(r) = trace - sum_{i<r} lambda_i
@@ -1335,7 +1365,8 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void
         return TK_OK;
     };
     tk_status st;
-    const bool capturable = own_A && wsp.cached && P.prec != TK_FP64 && !P.converge && !g_prof_on.load();
+    const bool capturable = own_A && wsp.cached && P.prec != TK_FP64 && !P.converge && !P.init_U[0] &&
+                            !g_prof_on.load();
     if (ctx->graphs_on && capturable) {
         if ((st = run_captured<Real>(ctx, P, nb, base, grid, kps, w, s, pipeline)) != TK_OK) return st;
     } else if ((st = pipeline(s)) != TK_OK) {
@@ -2148,6 +2179,86 @@ tk_status tk_compress_tensor(tk_ctx* ctx, const void* A_dev, const tk_grid* grid
     return compress_any(ctx, nullptr, A_dev, grid, opts, hip_stream, out);
 }
 
+tk_status tk_compress_multigrid(tk_ctx* ctx, const tk_kernel* kernel, const tk_grid* grid, int levels,
+                                const tk_opts* opts, void* hip_stream, tk_tucker** out)
+{
+    if (!ctx || !kernel || !grid || !opts || !out) return fail(TK_EINVAL, "NULL argument");
+    *out = nullptr;
+    tk_status st;
+    if ((st = check_grid(grid)) != TK_OK) return st;
+    KernelParams kp{};
+    if ((st = check_kernel(kernel, &kp)) != TK_OK) return st;
+    if (levels < 0 || levels > 8) return fail(TK_EINVAL, "levels=%d: 0..8", levels);
+    // points per axis per level, coarsest first: each coarser level keeps (n + 1) / 2 points
+    std::vector<std::array<int, 3>> sz((size_t)levels + 1);
+    for (int k = 0; k < 3; ++k) {
+        int n = grid->n[k];
+        for (int l = levels; l >= 0; --l) {
+            sz[(size_t)l][k] = n;
+            n = (n + 1) / 2;
+        }
+        if (sz[0][k] < 2) return fail(TK_EINVAL, "axis %d: %d levels leave fewer than 2 points", k, levels);
+    }
+    Plan Pchk;
+    if ((st = make_plan(grid, opts, &Pchk)) != TK_OK) return st;
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    hipStream_t s = (hipStream_t)hip_stream;
+    // coarsest level: the plain compression (HOSVD, its ALS sweeps, eps rule or fixed ranks)
+    tk_grid g0 = *grid;
+    for (int k = 0; k < 3; ++k) g0.n[k] = sz[0][k];
+    tk_opts o0 = *opts;
+    if (o0.hooi_sweeps == TK_HOOI_CONVERGE && Pchk.prec != TK_FP64) o0.hooi_sweeps = -1;
+    tk_tucker* t = nullptr;
+    st = compress_any(ctx, kernel, nullptr, &g0, &o0, s, &t);
+    if (st != TK_OK && st != TK_ENOCONV) return st;
+    for (int l = 1; l <= levels; ++l) {
+        tk_grid gl = *grid;
+        for (int k = 0; k < 3; ++k) gl.n[k] = sz[(size_t)l][k];
+        tk_grid gp = *grid;
+        for (int k = 0; k < 3; ++k) gp.n[k] = sz[(size_t)l - 1][k];
+        const GridAxes ac = axes_of(&gp), af = axes_of(&gl);
+        // fixed ranks from the coarsest level, the sweeps of the options (at least one)
+        tk_opts ol = *opts;
+        ol.eps = 0.0;
+        for (int k = 0; k < 3; ++k) ol.ranks[k] = t->r[k];
+        if (ol.hooi_sweeps == 0) ol.hooi_sweeps = 1;
+        Plan P;
+        if ((st = make_plan(&gl, &ol, &P)) != TK_OK) { free_result(t); return st; }
+        // interpolated, orthonormalised start factors in the stream's second workspace slot
+        size_t ib = 0;
+        for (int k = 0; k < 3; ++k) ib += align_up(sizeof(double) * (size_t)gl.n[k] * P.R[k], 256);
+        Reservation res(ctx, ib);
+        if (!res.take()) { free_result(t); return fail(TK_ENOMEM, "multigrid start factors (%zu bytes)", ib); }
+        Ws iw;
+        hipError_t he = ws_get(ctx, s, 1, ib, iw);
+        if (he != hipSuccess) { free_result(t); return fail(TK_ENOMEM, "multigrid start factors: %s", hipGetErrorString(he)); }
+        char* p = (char*)iw.p;
+        for (int k = 0; k < 3; ++k) {
+            double* Uk = (double*)p;
+            p += align_up(sizeof(double) * (size_t)gl.n[k] * P.R[k], 256);
+            he = launch_interp_factor(t->U[k], gp.n[k], ac.x0[k], ac.h[k], Uk, gl.n[k], af.x0[k], af.h[k], P.R[k], s);
+            if (he == hipSuccess) he = launch_qr(Uk, Uk, 1, gl.n[k], P.R[k], s);
+            if (he != hipSuccess) { free_result(t); return fail(TK_EHIP, "multigrid prolongation: %s", hipGetErrorString(he)); }
+            P.init_U[k] = Uk;
+        }
+        // the coarse result was last used by the prolongation on s
+        if (hipStreamSynchronize(s) != hipSuccess) { free_result(t); return fail(TK_EHIP, "multigrid: stream error"); }
+        free_result(t);
+        t = nullptr;
+        apply_tuning(ctx, &P);
+        tk_status lst = TK_OK;
+        st = (P.prec == TK_FP64) ? compress_impl<double>(ctx, &kp, 1, nullptr, &gl, P, s, &t, &lst)
+                                 : compress_impl<float>(ctx, &kp, 1, nullptr, &gl, P, s, &t, &lst);
+        if (st != TK_OK) return st;
+        if (lst != TK_OK && lst != TK_ENOCONV) { free_result(t); return lst; }
+        if (lst == TK_ENOCONV && l == levels) st = TK_ENOCONV;
+    }
+    *out = t;
+    if (opts->eps > 0 && !(t->rel_err <= opts->eps)) return fail(TK_ENOCONV, "multigrid: E=%g > eps=%g", t->rel_err, opts->eps);
+    return st;
+}
+
 tk_status tk_compress_group(tk_ctx* ctx, int count, const tk_kernel* kernels, const tk_grid* grid,
                             const tk_opts* opts, void* hip_stream, tk_tucker** outs, int* statuses)
 {
@@ -2724,6 +2835,231 @@ tk_status tk_eig_topr(tk_ctx* ctx, int count, int n, int r, const double* G_dev,
     TK_HIP(hipStreamSynchronize(s));
     if (w.noconv) return fail(TK_ENOCONV, "eigensolver: residual test not met after %d rounds", EIG_MAX_ROUNDS);
     return TK_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Separable covariance C = C_1 (x) C_2 (x) C_3 (Sec. 4, "Separable covariance matrices")
+// ------------------------------------------------------------------------------------------
+}  // extern "C"
+
+struct tk_kron1 {
+    tk_ctx* ctx = nullptr;
+    int n[3] = {0, 0, 0};
+    void* block = nullptr;        // L_k, then (after the first solve) C_k^-1 and scratch
+    size_t bytes = 0;             // charged to the context's budget
+    double* L[3] = {nullptr, nullptr, nullptr};
+    double* Cinv[3] = {nullptr, nullptr, nullptr};
+    void* inv_block = nullptr;    // L_k^-1 and C_k^-1, formed at the first solve
+    double logdet = 0.0;
+    double logdet_k[3] = {0, 0, 0};
+};
+
+namespace {
+
+// Lazily form C_k^-1 = L_k^-T L_k^-1 (n_k <= 1024) for the solves.
+tk_status kron1_inverses(tk_kron1* k, hipStream_t s)
+{
+    if (k->Cinv[0]) return TK_OK;
+    for (int a = 0; a < 3; ++a)
+        if (k->n[a] > NMAX) return fail(TK_EUNSUPPORTED, "solve: axis %d has %d > %d points", a, k->n[a], NMAX);
+    size_t need = 0;
+    for (int a = 0; a < 3; ++a) need += 2 * align_up(sizeof(double) * (size_t)k->n[a] * k->n[a], 256);
+    if (!reserve(k->ctx, need)) return fail(TK_ENOMEM, "inverse factors need %zu bytes", need);
+    void* blk = nullptr;
+    hipError_t e = hipMalloc(&blk, need);
+    if (e != hipSuccess) { release(k->ctx, need); return fail(TK_ENOMEM, "hipMalloc(%zu): %s", need, hipGetErrorString(e)); }
+    char* p = (char*)blk;
+    for (int a = 0; a < 3; ++a) {
+        const int n = k->n[a];
+        double* Li = (double*)p;
+        p += align_up(sizeof(double) * (size_t)n * n, 256);
+        double* Ci = (double*)p;
+        p += align_up(sizeof(double) * (size_t)n * n, 256);
+        TK_LAUNCH(launch_trinv(k->L[a], n, Li, s));
+        // C^-1 = Li^T Li
+        GemmArgs g = gemm(n, n, n, 1, Li, 0, 1, n, Li, 0, n, 1, Ci, 0, n, 1);
+        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+        k->Cinv[a] = Ci;
+    }
+    TK_HIP(hipStreamSynchronize(s));
+    k->inv_block = blk;
+    k->bytes += need;
+    return TK_OK;
+}
+
+// y = x x_1 M_1 x_2 M_2 x_3 M_3 (M_k: n_k x n_k row-major, applied along mode k) through two
+// scratch volumes; the result lands in y.
+tk_status kron1_apply(const int n[3], double* const M[3], const double* x, double* y, double* tmp, hipStream_t s)
+{
+    const long N12 = (long)n[1] * n[2], N01 = (long)n[0] * n[1];
+    // mode 1: tmp[i0][.] = sum_j M0[i0][j] x[j][.]
+    GemmArgs g0 = gemm(n[0], (int)N12, n[0], 1, M[0], 0, n[0], 1, x, 0, N12, 1, tmp, 0, N12, 1);
+    TK_LAUNCH((launch_gemm<double, double, double>(g0, s)));
+    // mode 2: y[i0][i1][.] = sum_j M1[i1][j] tmp[i0][j][.]   (batch over i0)
+    GemmArgs g1 = gemm(n[1], n[2], n[1], n[0], M[1], 0, n[1], 1, tmp, N12, n[2], 1, y, N12, n[2], 1);
+    TK_LAUNCH((launch_gemm<double, double, double>(g1, s)));
+    // mode 3: tmp[r][i2] = sum_j y[r][j] M2[i2][j]
+    GemmArgs g2 = gemm((int)N01, n[2], n[2], 1, y, 0, n[2], 1, M[2], 0, 1, n[2], tmp, 0, n[2], 1);
+    TK_LAUNCH((launch_gemm<double, double, double>(g2, s)));
+    TK_HIP(hipMemcpyAsync(y, tmp, sizeof(double) * (size_t)N01 * n[2], hipMemcpyDeviceToDevice, s));
+    return TK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tk_status tk_kron1_create(tk_ctx* ctx, const tk_kernel kernels[3], const tk_grid* grid, const double nugget[3],
+                          void* hip_stream, tk_kron1** out)
+{
+    if (!ctx || !kernels || !grid || !out) return fail(TK_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (!grid) return fail(TK_EINVAL, "grid is NULL");
+    KernelParams kp[3];
+    tk_status st;
+    for (int a = 0; a < 3; ++a) {
+        if (grid->n[a] < 1 || grid->n[a] > KRON1_NMAX)
+            return fail(TK_EUNSUPPORTED, "axis %d: %d points (1..%d)", a, grid->n[a], KRON1_NMAX);
+        if (!std::isfinite(grid->b[a]) || grid->b[a] <= 0) return fail(TK_EINVAL, "grid b[%d] must be > 0", a);
+        if ((st = check_kernel(&kernels[a], &kp[a])) != TK_OK) return st;
+        const double ng = nugget ? nugget[a] : 0.0;
+        if (!std::isfinite(ng) || ng < 0) return fail(TK_EINVAL, "nugget[%d] must be finite and >= 0", a);
+    }
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    hipStream_t s = (hipStream_t)hip_stream;
+    size_t bytes = 0;
+    for (int a = 0; a < 3; ++a) bytes += align_up(sizeof(double) * (size_t)grid->n[a] * grid->n[a], 256);
+    size_t wb = 0;
+    for (int a = 0; a < 3; ++a) wb = std::max(wb, cholesky_work_bytes(grid->n[a]));
+    Reservation res(ctx, bytes + wb + 256);
+    if (!res.take()) return fail(TK_ENOMEM, "separable covariance needs %zu bytes", bytes + wb);
+    tk_kron1* k = new (std::nothrow) tk_kron1();
+    if (!k) return fail(TK_ENOMEM, "host allocation failed");
+    k->ctx = ctx;
+    hipError_t e = hipMalloc(&k->block, bytes);
+    if (e != hipSuccess) { delete k; return fail(TK_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e)); }
+    Ws wsp;
+    e = ws_get(ctx, s, 0, wb + 256, wsp);
+    if (e != hipSuccess) { hipFree(k->block); delete k; return fail(TK_ENOMEM, "workspace: %s", hipGetErrorString(e)); }
+    int* info = (int*)wsp.p;
+    double* ld = (double*)((char*)wsp.p + 64);
+    void* work = (char*)wsp.p + 256;
+    char* p = (char*)k->block;
+    const GridAxes ax = axes_of(grid);
+    int hinfo[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+        const int n = grid->n[a];
+        k->n[a] = n;
+        k->L[a] = (double*)p;
+        p += align_up(sizeof(double) * (size_t)n * n, 256);
+        const double h = (n > 1) ? ax.h[a] : 0.0;
+        TK_HIP(hipMemsetAsync(info + a, 0, sizeof(int), s));
+        tk_status ls = TK_OK;
+        if (launch_cov1d(k->L[a], n, ax.x0[a], h, kp[a], nugget ? nugget[a] : 0.0, s) != hipSuccess ||
+            launch_cholesky(k->L[a], n, work, info + a, s) != hipSuccess ||
+            launch_logdet_chol(k->L[a], n, ld + a, s) != hipSuccess)
+            ls = fail(TK_EHIP, "separable covariance factor %d: %s", a, hipGetErrorString(hipGetLastError()));
+        if (ls != TK_OK) { hipFree(k->block); delete k; return ls; }
+    }
+    double hld[3];
+    TK_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+    TK_HIP(hipMemcpyAsync(hld, ld, sizeof(hld), hipMemcpyDeviceToHost, s));
+    TK_HIP(hipStreamSynchronize(s));
+    for (int a = 0; a < 3; ++a)
+        if (hinfo[a] != 0) {
+            hipFree(k->block);
+            delete k;
+            return fail(TK_EINVAL, "axis %d: the covariance factor is not positive definite (pivot %d); add a nugget",
+                        a, hinfo[a] - 1);
+        }
+    const double N = (double)grid->n[0] * grid->n[1] * grid->n[2];
+    k->logdet = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        k->logdet_k[a] = hld[a];
+        k->logdet += (N / grid->n[a]) * hld[a];
+    }
+    k->bytes = bytes;
+    res.hand_over(bytes);
+    *out = k;
+    return TK_OK;
+}
+
+tk_status tk_kron1_logdet(const tk_kron1* k, double* out, double logdet_axis[3])
+{
+    if (!k || !out) return fail(TK_EINVAL, "NULL argument");
+    *out = k->logdet;
+    if (logdet_axis)
+        for (int a = 0; a < 3; ++a) logdet_axis[a] = k->logdet_k[a];
+    return TK_OK;
+}
+
+tk_status tk_kron1_factor(const tk_kron1* k, int axis, double* L_host)
+{
+    if (!k || !L_host || axis < 0 || axis > 2) return fail(TK_EINVAL, "bad argument");
+    TK_HIP(hipSetDevice(k->ctx->device));
+    TK_HIP(hipMemcpy(L_host, k->L[axis], sizeof(double) * (size_t)k->n[axis] * k->n[axis], hipMemcpyDeviceToHost));
+    return TK_OK;
+}
+
+tk_status tk_kron1_apply(tk_ctx* ctx, tk_kron1* k, int op, const double* z_dev, double* y_dev, void* hip_stream)
+{
+    if (!ctx || !k || !z_dev || !y_dev) return fail(TK_EINVAL, "NULL argument");
+    if (z_dev == y_dev) return fail(TK_EINVAL, "y must not alias z");
+    if (op != TK_KRON1_SOLVE && op != TK_KRON1_CHOL) return fail(TK_EINVAL, "unknown operation %d", op);
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    hipStream_t s = (hipStream_t)hip_stream;
+    tk_status st;
+    if (op == TK_KRON1_SOLVE && (st = kron1_inverses(k, s)) != TK_OK) return st;
+    const size_t N = (size_t)k->n[0] * k->n[1] * k->n[2];
+    Reservation res(ctx, sizeof(double) * N);
+    if (!res.take()) return fail(TK_ENOMEM, "scratch of %zu bytes", sizeof(double) * N);
+    Ws wsp;
+    hipError_t e = ws_get(ctx, s, 0, sizeof(double) * N, wsp);
+    if (e != hipSuccess) return fail(TK_ENOMEM, "workspace: %s", hipGetErrorString(e));
+    double* M[3];
+    for (int a = 0; a < 3; ++a) M[a] = (op == TK_KRON1_SOLVE) ? k->Cinv[a] : k->L[a];
+    return kron1_apply(k->n, M, z_dev, y_dev, (double*)wsp.p, s);
+}
+
+tk_status tk_kron1_loglik(tk_ctx* ctx, tk_kron1* k, const double* z_dev, void* hip_stream, double* out,
+                          double* quad_out)
+{
+    if (!ctx || !k || !z_dev || !out) return fail(TK_EINVAL, "NULL argument");
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    hipStream_t s = (hipStream_t)hip_stream;
+    tk_status st;
+    if ((st = kron1_inverses(k, s)) != TK_OK) return st;
+    const size_t N = (size_t)k->n[0] * k->n[1] * k->n[2];
+    const size_t need = 2 * sizeof(double) * N + sizeof(double) * 2048 + 256;
+    Reservation res(ctx, need);
+    if (!res.take()) return fail(TK_ENOMEM, "log-likelihood needs %zu bytes", need);
+    Ws wsp;
+    hipError_t e = ws_get(ctx, s, 0, need, wsp);
+    if (e != hipSuccess) return fail(TK_ENOMEM, "workspace: %s", hipGetErrorString(e));
+    double* w = (double*)wsp.p;
+    double* tmp = w + N;
+    double* parts = tmp + N;
+    if ((st = kron1_apply(k->n, k->Cinv, z_dev, w, tmp, s)) != TK_OK) return st;
+    TK_LAUNCH(launch_dot<double>(z_dev, w, (long)N, parts, 1024, parts + 1024, s));
+    double q = 0.0;
+    if ((st = readback(ctx, s, parts + 1024, sizeof(double), &q)) != TK_OK) return st;
+    if (quad_out) *quad_out = q;
+    *out = -0.5 * ((double)N * std::log(2.0 * M_PI) + k->logdet + q);
+    return TK_OK;
+}
+
+void tk_kron1_free(tk_kron1* k)
+{
+    if (!k) return;
+    hipSetDevice(k->ctx->device);
+    hipDeviceSynchronize();
+    if (k->block) hipFree(k->block);
+    if (k->inv_block) hipFree(k->inv_block);
+    release(k->ctx, k->bytes);
+    delete k;
 }
 
 }  // extern "C"

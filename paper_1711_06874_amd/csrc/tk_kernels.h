@@ -104,6 +104,24 @@ hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s);
 // flags[c] (c < count, moving by bs per batched problem) = 1 when every column has
 // ||G u_j - lam_j u_j|| <= max(tau lam_j, cfloor sqrt(n) u ||G||_F), else 0.  n <= 1024.
 hipError_t launch_eig_check(const EigBatch& b, double tau, double cfloor, int* flags, hipStream_t s);
+// ------------------------------------------- separable covariance (rank-1 Kronecker) ----
+// C (n x n, row-major) = k(|x_i - x_j|) + nugget on the diagonal, x_i = x0 + i h.
+hipError_t launch_cov1d(double* C, int n, double x0, double h, const KernelParams& kp, double nugget, hipStream_t s);
+// In-place Cholesky A = L L^T (lower triangle, strict upper zeroed); `work` holds
+// cholesky_work_bytes(n); *info (device, zero on entry) = index + 1 of the first pivot <= 0.
+size_t cholesky_work_bytes(int n);
+hipError_t launch_cholesky(double* A, int n, void* work, int* info, hipStream_t s);
+// out[0] = 2 sum log L_ii;  X = L^-1 (lower-triangular, n x n)
+hipError_t launch_logdet_chol(const double* L, int n, double* out, hipStream_t s);
+hipError_t launch_trinv(const double* L, int n, double* X, hipStream_t s);
+
+// Householder QR of `count` n x p row-major blocks (consecutive): out = the explicit orthonormal
+// factor (in == out allowed).  p <= EIG_PMAX.
+hipError_t launch_qr(const double* in, double* out, int count, int n, int p, hipStream_t s);
+// Multigrid prolongation of a factor: Uf (nf x r) = the columns of Uc (nc x r), read as functions
+// on the uniform nodes x0c + i hc, linearly interpolated at x0f + j hf.
+hipError_t launch_interp_factor(const double* Uc, int nc, double x0c, double hc, double* Uf, int nf, double x0f,
+                                double hf, int r, hipStream_t s);
 // Sign rule on the columns of U (n x r, ld ldu): a column whose entry of largest magnitude (ties
 // within 1e-10 relative, lowest index) is negative is negated, together with column c of V
 // (nv x r, ld ldv).

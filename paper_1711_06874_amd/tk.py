@@ -23,7 +23,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 # ----------------------------------------------------------------------------- constants
 TK_OK, TK_EINVAL, TK_EUNSUPPORTED, TK_ELAYOUT, TK_ENOMEM, TK_EHIP, TK_ENOCONV = 0, -1, -2, -3, -4, -5, -6
-TK_MATERN, TK_SLATER, TK_GAUSS = 0, 1, 2
+TK_MATERN, TK_SLATER, TK_GAUSS, TK_SPECTRAL = 0, 1, 2, 3
 TK_CENTERED, TK_OFFSET = 0, 1
 TK_FP64, TK_FP32, TK_BF16X3 = 0, 1, 2
 TK_HOOI_CONVERGE = -2   # tk_opts.hooi_sweeps: Tucker-ALS until the core norm stops changing
@@ -31,7 +31,8 @@ TK_HOOI_CONVERGE = -2   # tk_opts.hooi_sweeps: Tucker-ALS until the core norm st
 
 class tk_kernel(ctypes.Structure):
     _fields_ = [("family", ctypes.c_int), ("nu", ctypes.c_double), ("ell", ctypes.c_double),
-                ("sigma2", ctypes.c_double), ("alpha", ctypes.c_double), ("p", ctypes.c_double)]
+                ("sigma2", ctypes.c_double), ("alpha", ctypes.c_double), ("p", ctypes.c_double),
+                ("metric", ctypes.c_double * 3)]
 
 
 class tk_grid(ctypes.Structure):
@@ -72,6 +73,8 @@ _SIGS = {
                           ctypes.POINTER(_vp)]),
     "tk_compress_tensor": (_st, [_vp, _vp, ctypes.POINTER(tk_grid), ctypes.POINTER(tk_opts), _vp,
                                  ctypes.POINTER(_vp)]),
+    "tk_compress_multigrid": (_st, [_vp, ctypes.POINTER(tk_kernel), ctypes.POINTER(tk_grid), ctypes.c_int,
+                                    ctypes.POINTER(tk_opts), _vp, ctypes.POINTER(_vp)]),
     "tk_compress_group": (_st, [_vp, ctypes.c_int, ctypes.POINTER(tk_kernel), ctypes.POINTER(tk_grid),
                                 ctypes.POINTER(tk_opts), _vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int)]),
     "tk_compress_batch": (_st, [_vp, ctypes.c_int, ctypes.POINTER(tk_kernel), ctypes.POINTER(tk_grid),
@@ -111,6 +114,12 @@ _SIGS = {
     "tk_profile_select": (_st, [ctypes.c_uint]),
     "tk_profile_reset": (_st, []),
     "tk_profile_read": (_st, [ctypes.c_int, ctypes.POINTER(ctypes.c_longlong), _dp]),
+    "tk_kron1_create": (_st, [_vp, ctypes.POINTER(tk_kernel), ctypes.POINTER(tk_grid), _dp, _vp, ctypes.POINTER(_vp)]),
+    "tk_kron1_logdet": (_st, [_vp, _dp, _dp]),
+    "tk_kron1_factor": (_st, [_vp, ctypes.c_int, _vp]),
+    "tk_kron1_apply": (_st, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp]),
+    "tk_kron1_loglik": (_st, [_vp, _vp, _vp, _vp, _dp, _dp]),
+    "tk_kron1_free": (None, [_vp]),
     "tk_last_error": (ctypes.c_char_p, []),
     "tk_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "tk_version": (ctypes.c_char_p, []),
@@ -147,8 +156,9 @@ def _check_result(status: int, out, where: str, allow_noconv: bool):
     _check(status, where, allow=(TK_ENOCONV,) if allow_noconv else ())
 
 
-def make_kernel(family=TK_MATERN, nu=0.5, ell=1.0, sigma2=1.0, alpha=1.0, p=1.0) -> tk_kernel:
-    return tk_kernel(int(family), float(nu), float(ell), float(sigma2), float(alpha), float(p))
+def make_kernel(family=TK_MATERN, nu=0.5, ell=1.0, sigma2=1.0, alpha=1.0, p=1.0, metric=None) -> tk_kernel:
+    m = (ctypes.c_double * 3)(*([0.0, 0.0, 0.0] if metric is None else [float(a) for a in metric]))
+    return tk_kernel(int(family), float(nu), float(ell), float(sigma2), float(alpha), float(p), m)
 
 
 def make_grid(n, b=(1.0, 1.0, 1.0), layout=TK_CENTERED) -> tk_grid:
@@ -223,6 +233,15 @@ def tk_compress_tensor(ctx: int, A, grid: tk_grid, opts: tk_opts, stream=None, a
     st = _lib.tk_compress_tensor(ctx, _ptr(A), ctypes.byref(grid), ctypes.byref(opts), _stream(stream),
                                  ctypes.byref(out))
     _check_result(st, out, "tk_compress_tensor", allow_noconv)
+    return out.value
+
+
+def tk_compress_multigrid(ctx: int, kernel: tk_kernel, grid: tk_grid, levels: int, opts: tk_opts, stream=None,
+                          allow_noconv=False):
+    out = _vp()
+    st = _lib.tk_compress_multigrid(ctx, ctypes.byref(kernel), ctypes.byref(grid), int(levels), ctypes.byref(opts),
+                                    _stream(stream), ctypes.byref(out))
+    _check_result(st, out, "tk_compress_multigrid", allow_noconv)
     return out.value
 
 
@@ -419,6 +438,9 @@ class Context:
     def compress(self, kernel, grid, opts, stream=None, allow_noconv=False) -> Tucker:
         return Tucker(tk_compress(self.handle, kernel, grid, opts, stream, allow_noconv), self)
 
+    def compress_multigrid(self, kernel, grid, levels, opts, stream=None, allow_noconv=False) -> Tucker:
+        return Tucker(tk_compress_multigrid(self.handle, kernel, grid, levels, opts, stream, allow_noconv), self)
+
     def compress_tensor(self, A, grid, opts, stream=None, allow_noconv=False) -> Tucker:
         return Tucker(tk_compress_tensor(self.handle, A, grid, opts, stream, allow_noconv), self)
 
@@ -489,6 +511,61 @@ class TuckerView:
 
 
 STREAM_READY = object()   # submit stream marker: the request's vectors are complete already (TK_STREAM_READY)
+
+
+TK_KRON1_SOLVE, TK_KRON1_CHOL = 0, 1
+
+
+class Kron1:
+    """Separable covariance C = C_1 (x) C_2 (x) C_3 (tk_kron1_*): Cholesky factors, log det,
+    solves, Cholesky products and the Gaussian log-likelihood on the device."""
+
+    def __init__(self, ctx: "Context", kernels, grid: tk_grid, nugget=None, stream=None):
+        ks = (tk_kernel * 3)(*kernels)
+        ng = (ctypes.c_double * 3)(*([0.0] * 3 if nugget is None else [float(x) for x in nugget]))
+        h = _vp()
+        _check(_lib.tk_kron1_create(ctx.handle, ks, ctypes.byref(grid), ng, _stream(stream), ctypes.byref(h)),
+               "tk_kron1_create")
+        self.handle = h.value
+        self.ctx = ctx
+        self.n = tuple(int(x) for x in grid.n)
+
+    def logdet(self):
+        out = ctypes.c_double()
+        per = (ctypes.c_double * 3)()
+        _check(_lib.tk_kron1_logdet(self.handle, ctypes.byref(out), per), "tk_kron1_logdet")
+        return out.value, tuple(per)
+
+    def factor(self, axis: int) -> np.ndarray:
+        n = self.n[axis]
+        L = np.empty((n, n), dtype=np.float64)
+        _check(_lib.tk_kron1_factor(self.handle, int(axis), L.ctypes.data), "tk_kron1_factor")
+        return L
+
+    def solve(self, z, y, stream=None):
+        _check(_lib.tk_kron1_apply(self.ctx.handle, self.handle, TK_KRON1_SOLVE, _ptr(z), _ptr(y), _stream(stream)),
+               "tk_kron1_apply")
+
+    def chol_apply(self, z, y, stream=None):
+        _check(_lib.tk_kron1_apply(self.ctx.handle, self.handle, TK_KRON1_CHOL, _ptr(z), _ptr(y), _stream(stream)),
+               "tk_kron1_apply")
+
+    def loglik(self, z, stream=None):
+        out, q = ctypes.c_double(), ctypes.c_double()
+        _check(_lib.tk_kron1_loglik(self.ctx.handle, self.handle, _ptr(z), _stream(stream), ctypes.byref(out),
+                                    ctypes.byref(q)), "tk_kron1_loglik")
+        return out.value, q.value
+
+    def free(self):
+        if self.handle:
+            _lib.tk_kron1_free(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 class Server:

@@ -84,7 +84,7 @@ def test_batch_empty_and_errors(tk):
         assert ctx.compress_batch([], [], tk.make_opts(eps=1e-6)) == []
         ks, gs = _problems(tk)
         bad = list(ks)
-        bad[3] = tk.make_kernel(0, nu=0.7, ell=0.3)        # unsupported order
+        bad[3] = tk.make_kernel(0, nu=31.0, ell=0.3)       # unsupported order (above 30)
         with pytest.raises(tk.TkError) as ei:
             ctx.compress_batch(bad, gs, tk.make_opts(eps=1e-6))
         assert ei.value.status == tk.TK_EUNSUPPORTED

@@ -243,9 +243,10 @@ def test_covariance_errors(ctx, tk):
 
 def test_argument_errors(ctx, tk):
     with pytest.raises(tk.TkError) as ei:
-        ctx.compress(tk.make_kernel(0, nu=0.7, ell=0.3), tk.make_grid(16), tk.make_opts(eps=1e-6))
+        ctx.compress(tk.make_kernel(0, nu=31.0, ell=0.3), tk.make_grid(16), tk.make_opts(eps=1e-6))
     assert "TK_EUNSUPPORTED" in str(ei.value)
-    for bad in (dict(ell=-1.0), dict(ell=float("nan")), dict(sigma2=0.0)):
+    for bad in (dict(ell=-1.0), dict(ell=float("nan")), dict(sigma2=0.0), dict(nu=0.0),
+                dict(metric=(1.0, -1.0, 1.0)), dict(metric=(1.0, 0.0, 1.0))):
         kw = dict(family=0, nu=0.5, ell=0.3)
         kw.update(bad)
         with pytest.raises(tk.TkError) as ei:

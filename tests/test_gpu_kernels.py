@@ -66,6 +66,60 @@ def test_grid_eval(ctx, tk, oracle, name, kw, layout):
     assert np.all(np.abs(g32.astype(np.float64) - ref32.astype(np.float64)) <= ulp)
 
 
+FAMILIES = [
+    # Matern orders without a closed form (Temme's series below argument 2, Steed's fraction
+    # above, upward recurrence); arguments from 0 to ~120
+    ("matern_nu03", dict(family=0, nu=0.3, ell=0.2)),
+    ("matern_nu075_short", dict(family=0, nu=0.75, ell=0.02)),
+    ("matern_nu12", dict(family=0, nu=1.2, ell=0.35, sigma2=1.3)),
+    ("matern_nu37", dict(family=0, nu=3.7, ell=0.5)),
+    ("matern_nu11", dict(family=0, nu=11.0, ell=0.9)),
+    # the Matern spectral density of Sec. 3.7 (Fig. 8: nu = 0.4, alpha = 0.1 and 100)
+    ("spectral_a01", dict(family=3, nu=0.4, alpha=0.1)),
+    ("spectral_a100", dict(family=3, nu=0.4, alpha=100.0)),
+    ("spectral_nu15", dict(family=3, nu=1.5, alpha=2.0, sigma2=3.0)),
+    # anisotropic diagonal metric (Sec. 2.2)
+    ("matern15_aniso", dict(family=0, nu=1.5, ell=0.3, metric=(4.0, 1.0, 0.25))),
+    ("slater_aniso", dict(family=1, alpha=0.7, p=1.9, ell=0.5, metric=(0.5, 2.0, 1.0))),
+    ("matern_nu12_aniso", dict(family=0, nu=1.2, ell=0.3, metric=(1.0, 3.0, 0.7))),
+]
+
+
+@pytest.mark.parametrize("name,kw", FAMILIES)
+@pytest.mark.parametrize("layout", [0, 1])
+def test_grid_eval_families(ctx, tk, oracle, name, kw, layout):
+    """General Matern orders, the spectral density and the anisotropic metric against the
+    oracle (which takes K_nu from its integral representation, a different algorithm).  FP64:
+    both sides evaluate exp(log constant + nu log s) K_nu(s) or (alpha^2 + rho^2)^-(nu+3/2)
+    through exponents of size up to ~200, each rounded once: 2e-13, plus the 8 u s of the
+    radius rounding as in test_grid_eval.  FP32: rounded once from double, so within one unit
+    in the last place of the oracle rounded to float."""
+    n = (37, 70, 67)
+    b = (1.0, 0.8, 1.3)
+    say("grid_eval family", name, layout, n)
+    okw = dict(kw)
+    if "metric" in okw:
+        okw["metric"] = tuple(okw["metric"])
+    A = oracle.grid_eval(oracle.Kernel(**okw), oracle.Grid(n=n, b=b, layout=layout))
+    k = tk.make_kernel(**kw)
+    g = tk.make_grid(n, b, layout)
+    d64 = torch.empty(n, dtype=torch.float64, device="cuda")
+    tk.tk_grid_eval(ctx.handle, k, g, tk.TK_FP64, d64)
+    got = host(d64)
+    sigma2 = kw.get("sigma2", 1.0)
+    s_exp = np.abs(np.log(np.maximum(np.abs(A) / sigma2, 1e-300)))
+    rtol = 2e-13 + 8 * 2.220446049250313e-16 * s_exp
+    err = np.abs(got - A) / np.maximum(np.abs(A), 1e-300)
+    say("  max rel err / tol %.3e" % np.max(err / rtol))
+    assert np.all(np.abs(got - A) <= rtol * np.abs(A) + 1e-300)
+    d32 = torch.empty(n, dtype=torch.float32, device="cuda")
+    tk.tk_grid_eval(ctx.handle, k, g, tk.TK_FP32, d32)
+    g32 = host(d32)
+    ref32 = A.astype(np.float32)
+    ulp = np.spacing(np.abs(ref32))
+    assert np.all(np.abs(g32.astype(np.float64) - ref32.astype(np.float64)) <= ulp)
+
+
 @pytest.mark.parametrize("shape", [(64, 64, 64), (70, 33, 129), (5, 7, 200)])
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_gram(ctx, tk, oracle, shape, prec):

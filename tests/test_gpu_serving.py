@@ -137,7 +137,7 @@ def test_serving_errors(tk):
     ctx = tk.Context(0)
     sv = tk.Server(ctx, 2)
     try:
-        bad = sv.submit_compress(tk.make_kernel(0, nu=0.7, ell=0.3), tk.make_grid(32, 1.0, 1), tk.make_opts(eps=1e-6))
+        bad = sv.submit_compress(tk.make_kernel(0, nu=31.0, ell=0.3), tk.make_grid(32, 1.0, 1), tk.make_opts(eps=1e-6))
         rb = sv.wait(bad)
         assert rb["status"] == tk.TK_EUNSUPPORTED and "nu" in rb["error"]       # the worker's message
         rt = sv.wait(sv.submit_trace(bad))
