@@ -564,3 +564,101 @@ def kron1_loglik(Ls, z: np.ndarray) -> float:
     zf = _f64(z).reshape(-1)
     w = kron1_solve(Ls, zf).reshape(-1)
     return float(-0.5 * (zf.size * np.log(2.0 * np.pi) + kron1_logdet(Ls) + np.dot(zf, w)))
+
+
+# ----------------------------------------------------------------------------------------
+# Sinc-quadrature canonical (CP) tensor and canonical-to-Tucker (Sec. 3.4, Sec. 3.5)
+# ----------------------------------------------------------------------------------------
+
+def laplace_weight(nu: float, ell: float, t: float) -> float:
+    """omega(t) with Matern_nu(r) = int_0^inf omega(t) exp(-r^2 t) dt (sigma2 = 1), nu = 1/2,
+    3/2, 5/2.  Sec. 3.5 gives exp(-2 sqrt(a p)) = sqrt(a/pi) int t^-3/2 exp(-a/t - p t) dt
+    (p = r^2); with c = sqrt(2 nu)/ell and g(t) = c/(2 sqrt(pi)) t^-3/2 exp(-c^2/(4t)) that is
+    e^{-c r} = int g(t) e^{-r^2 t} dt.  Since s^j e^{-s} = c^j d^j/dc^j e^{-c r} (s = c r),
+    the polynomial factors of the half-integer closed forms act on g:
+      nu = 1/2: g;   nu = 3/2: (1 - c d/dc) g = g c^2/(2t);
+      nu = 5/2: (1 - c d/dc + c^2/3 d^2/dc^2) g = g c^4/(12 t^2)."""
+    m = int(round(nu - 0.5))
+    c = np.sqrt(2.0 * nu) / ell
+    g = c / (2.0 * np.sqrt(np.pi)) * t ** -1.5 * np.exp(-c * c / (4.0 * t))
+    return g * {0: 1.0, 1: c * c / (2.0 * t), 2: c ** 4 / (12.0 * t * t)}[m]
+
+
+def sinc_cp(k: Kernel, g: Grid, M: int, C0: float = 1.0):
+    """Rank R = 2M+1 canonical tensor of the Matern collocation tensor (Sec. 3.4 eq. (3.9),
+    (3.10) and (3.13), collocation form): with t = (c^2/4) e^u the Laplace integral becomes
+    int_R omega(t(u)) t(u) e^{-r^2 t(u)} du, and the sinc rule with step h = C0 log(M)/M and
+    nodes u_k = k h, k = -M..M gives
+        A(x) ~ sum_k w_k prod_l exp(-t_k x_l^2),  w_k = sigma2 h omega(t_k) t_k.
+    Returns (Q, w, t): Q[l] is n_l x R with columns w_k^(1/3) exp(-t_k x_{l,i}^2)."""
+    if k.family != MATERN or abs(k.nu - round(k.nu - 0.5) - 0.5) > 1e-12 or k.nu > 2.6:
+        raise ValueError("sinc CP: Matern nu in {1/2, 3/2, 5/2}")
+    h = C0 * np.log(M) / M
+    c = np.sqrt(2.0 * k.nu) / k.ell
+    u = h * np.arange(-M, M + 1, dtype=np.float64)
+    t = (c * c / 4.0) * np.exp(u)
+    w = np.array([k.sigma2 * h * laplace_weight(k.nu, k.ell, tk) * tk for tk in t])
+    Q = []
+    for a in range(3):
+        x = grid_coords(g.n[a], g.b[a], g.layout)
+        Qa = np.empty((g.n[a], t.size))
+        for i in range(g.n[a]):
+            for j in range(t.size):
+                Qa[i, j] = np.cbrt(w[j]) * np.exp(-t[j] * x[i] * x[i])
+        Q.append(Qa)
+    return Q, w, t
+
+
+def cp_full(Q) -> np.ndarray:
+    """The full tensor sum_k q1_k (x) q2_k (x) q3_k."""
+    n = [q.shape[0] for q in Q]
+    A = np.zeros(n)
+    for j in range(Q[0].shape[1]):
+        A += np.einsum("i,j,k->ijk", Q[0][:, j], Q[1][:, j], Q[2][:, j])
+    return A
+
+
+def cp_norm2(Q) -> float:
+    """||sum_k q1_k (x) q2_k (x) q3_k||^2 = sum_{k,k'} prod_l <q_l,k, q_l,k'>."""
+    P = Q[0].T @ Q[0] * (Q[1].T @ Q[1]) * (Q[2].T @ Q[2])
+    return float(P.sum())
+
+
+def c2t_core(Q, V) -> np.ndarray:
+    """Core of the projection of the CP tensor onto the factor spans:
+    G = sum_k (V1^T q1_k) (x) (V2^T q2_k) (x) (V3^T q3_k)."""
+    P = [V[a].T @ Q[a] for a in range(3)]
+    r = [p.shape[0] for p in P]
+    G = np.zeros(r)
+    for j in range(Q[0].shape[1]):
+        G += np.einsum("a,b,c->abc", P[0][:, j], P[1][:, j], P[2][:, j])
+    return G
+
+
+def c2t(Q, ranks, sweeps=0) -> Tucker:
+    """Canonical-to-Tucker (Sec. 3.4, after eq. (3.14)): RHOSVD initial guess -- the leading
+    left singular vectors of each side matrix Q_l, here the leading eigenvectors of Q_l Q_l^T
+    (Jacobi) -- then `sweeps` ALS sweeps on the canonical data: for mode l the single-hole
+    tensor B = CP x_{j != l} V_j^T has the unfolding Q_l W with W[k] = (V_j^T q_j,k) (x)
+    (V_m^T q_m,k), so B_(l) B_(l)^T = Q_l (W W^T) Q_l^T, W W^T = P_j^T P_j o P_m^T P_m.  No full
+    tensor is formed; the error against the canonical tensor follows from Pythagoras,
+    ||CP - T||^2 = ||CP||^2 - ||G||^2."""
+    V = []
+    for a in range(3):
+        lam, E, s = jacobi_eig(Q[a] @ Q[a].T)
+        V.append(E[:, : int(ranks[a])].copy())
+    history = []
+    for _ in range(int(sweeps)):
+        for a in range(3):
+            j, m = [x for x in range(3) if x != a]
+            Pj = V[j].T @ Q[j]
+            Pm = V[m].T @ Q[m]
+            Wg = (Pj.T @ Pj) * (Pm.T @ Pm)
+            lam, E, s = jacobi_eig(Q[a] @ Wg @ Q[a].T)
+            V[a] = E[:, : int(ranks[a])].copy()
+            history.append(float(np.sqrt(sumsq(c2t_core(Q, V)))))
+    core = c2t_core(Q, V)
+    n2 = cp_norm2(Q)
+    t = Tucker(U=V, core=core, norm_a2=n2, history=history, sweeps=int(sweeps))
+    t.rel_err = float(np.sqrt(max(n2 - sumsq(core), 0.0) / n2))
+    return t

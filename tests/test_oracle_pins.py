@@ -645,3 +645,63 @@ def test_kron1_lemmas_against_dense(oracle):
     np.testing.assert_allclose(oracle.kron1_chol_apply(Ls, z).reshape(-1), L @ zf, rtol=1e-13, atol=1e-14)
     ref = multivariate_normal(mean=np.zeros(zf.size), cov=C).logpdf(zf)
     assert oracle.kron1_loglik(Ls, z) == pytest.approx(ref, rel=1e-11)
+
+
+# --------------------------------------------- sinc-quadrature CP, canonical-to-Tucker ----
+
+@pytest.mark.parametrize("nu", [0.5, 1.5, 2.5])
+def test_laplace_weights_reproduce_matern(oracle, nu):
+    """int_0^inf omega(t) exp(-r^2 t) dt equals the half-integer Matern (Sec. 3.5's Laplace
+    representation and its derivatives in the rate), by adaptive quadrature (scipy)."""
+    from scipy import integrate
+    ell = 0.4
+    k = oracle.Kernel(oracle.MATERN, nu=nu, ell=ell)
+    for r in (0.05, 0.3, 1.0):
+        f = lambda t: oracle.laplace_weight(nu, ell, t) * np.exp(-r * r * t)
+        c2 = 2 * nu / ell ** 2
+        val = sum(integrate.quad(f, a, b, limit=400, epsabs=0, epsrel=1e-12)[0]
+                  for a, b in [(0, c2 / 40), (c2 / 40, c2), (c2, 40 * c2 / max(r * r * c2, 1e-3)), (40 * c2 / max(r * r * c2, 1e-3), np.inf)])
+        assert val == pytest.approx(oracle.kernel_value(k, r), rel=1e-9), (nu, r)
+
+
+@pytest.mark.parametrize("nu", [0.5, 1.5, 2.5])
+def test_sinc_cp_converges_exponentially(oracle, nu):
+    """Sec. 3.4 eq. (3.11): the sinc rule with R = 2M+1 terms converges exponentially in M away
+    from the origin; at M = 40, C0 = 2 it reproduces the tensor to ~1e-9 of sigma2."""
+    k = oracle.Kernel(oracle.MATERN, nu=nu, ell=0.3)
+    g = oracle.Grid(n=(17, 20, 15), layout=oracle.OFFSET)
+    A = oracle.grid_eval(k, g)
+    mask = np.ones(A.shape, bool)
+    mask[0, 0, 0] = False                         # r = 0: the rule's tail decays only like e^{-u/2}
+    errs = []
+    for M in (10, 20, 40):
+        Q, w, t = oracle.sinc_cp(k, g, M, 2.0)
+        errs.append(np.abs(oracle.cp_full(Q) - A)[mask].max())
+    assert errs[0] > errs[1] > errs[2] and errs[2] <= 2e-9, errs
+
+
+def test_c2t_full_rank_is_exact(oracle):
+    k = oracle.Kernel(oracle.MATERN, nu=0.5, ell=0.5)
+    g = oracle.Grid(n=(9, 11, 10), layout=oracle.CENTERED)
+    Q, w, t = oracle.sinc_cp(k, g, 6, 2.0)
+    Ac = oracle.cp_full(Q)
+    c = oracle.c2t(Q, (9, 11, 10), sweeps=0)
+    T = oracle.reconstruct(c.core, c.U)
+    assert np.abs(T - Ac).max() <= 1e-12 * np.abs(Ac).max()
+
+
+def test_c2t_matches_tucker_als_of_the_full_cp_tensor(oracle):
+    """Canonical-to-Tucker with ALS on the canonical data reaches what Tucker-ALS on the
+    materialised canonical tensor reaches (converged both), without forming that tensor;
+    ||G|| grows with every mode update."""
+    k = oracle.Kernel(oracle.MATERN, nu=1.5, ell=0.3)
+    g = oracle.Grid(n=(33, 30, 36), layout=oracle.OFFSET)
+    Q, w, t = oracle.sinc_cp(k, g, 30, 2.0)
+    Ac = oracle.cp_full(Q)
+    for r in (3, 6):
+        c = oracle.c2t(Q, (r, r, r), sweeps=12)
+        e_c2t = np.sqrt(oracle.diff_sumsq(Ac, oracle.reconstruct(c.core, c.U)) / oracle.sumsq(Ac))
+        d = oracle.hooi(Ac, oracle.hosvd(Ac, (r, r, r)), sweeps=None)
+        assert e_c2t == pytest.approx(d.rel_err, rel=1e-6), r
+        hist = np.asarray(c.history)
+        assert np.all(np.diff(hist) >= -1e-12 * hist[0])
