@@ -45,14 +45,45 @@ def say(*args):
 U64 = 2.0 ** -53
 
 
-def fp64_e_tolerance(lams, r, e, na2, n):
-    """Parity tolerance of an FP64 HOSVD/HOOI error E against the oracle: 1e-10 E, or the
-    Gram route's floor if larger.  Both eigensolvers are backward stable (exact for a Gram
-    perturbed by about n u ||G||); E is stationary in the factors at the exact eigenvectors, so
-    the perturbation moves it at second order, by about
-    (n u lambda_1)^2 / ((lambda_r - lambda_{r+1}) E ||A||^2) per mode."""
+def _tucker_err(A, Us):
+    """||A - A x_k U_k U_k^T|| / ||A|| by explicit reconstruction (orthonormal U_k)."""
+    C = np.einsum("ijk,ia,jb,kc->abc", A, *Us, optimize=True)
+    Ah = np.einsum("abc,ia,jb,kc->ijk", C, *Us, optimize=True)
+    return float(np.sqrt(np.sum((A - Ah) ** 2) / np.sum(A * A)))
+
+
+def fp64_e_tolerance(A, f, r, e):
+    """Parity tolerance of an FP64 HOSVD error E against the oracle: 1e-10 E, or the Gram
+    route's floor where that is larger.
+
+    Two correct FP64 implementations form the mode Grams with different rounding; each
+    eigenvector u_j of G_k is then fixed only up to a rotation toward u_i by about
+    u lambda_1 / |lambda_j - lambda_i| (u the unit roundoff; a factor 4 for the two Grams and
+    the two eigensolvers).  HOSVD factors are not a stationary point of E (the leading subspaces
+    of A_(k) A_(k)^T are not those of the single-hole Grams that would make them one), so E moves
+    at first order under such rotations.  The floor adds |dE/dtheta| times that angle over the
+    kept columns j in [r-3, r) and the discarded directions i in [r, r+2) of every mode (the
+    nearest pairs: the angle falls like 1/gap), with dE/dtheta from central differences on the
+    oracle's own factors.  f holds the oracle's full eigendecompositions (lambda_k, V_k)."""
+    if np.isscalar(r):
+        r = (int(r),) * 3
+    lams = [np.asarray(x[0]) for x in f]
+    Vs = [np.asarray(x[1]) for x in f]
+    base = [Vs[k][:, :r[k]] for k in range(3)]
+    d = 1e-6
     floor = 0.0
-    for lam in lams:
-        gap = lam[r - 1] - lam[r] if r < len(lam) else lam[r - 1]
-        floor += (n * U64 * lam[0]) ** 2 / (max(gap, 1e-300) * max(e, 1e-300) * na2)
+    for k in range(3):
+        n, lam = Vs[k].shape[0], lams[k]
+        for j in range(max(0, r[k] - 3), r[k]):
+            for i in range(r[k], min(r[k] + 2, n)):
+                gap = lam[j] - lam[i]
+                if gap <= 0:
+                    return float("inf")
+                theta = 4.0 * U64 * lam[0] / gap
+                es = []
+                for sgn in (1.0, -1.0):
+                    Us = [b.copy() for b in base]
+                    Us[k][:, j] = np.cos(d) * Vs[k][:, j] + sgn * np.sin(d) * Vs[k][:, i]
+                    es.append(_tucker_err(A, Us))
+                floor += abs(es[0] - es[1]) / (2 * d) * theta
     return max(1e-10 * e, floor)

@@ -50,7 +50,7 @@ def test_c1_hosvd_error_curve_fp64(ctx, tk, oracle):
         ref = oracle.hosvd(A, (r, r, r), f)
         lam = f[0][0]
         gap = (lam[r - 1] - lam[r]) / lam[r - 1] if r < len(lam) else 1.0
-        tol = fp64_e_tolerance([x[0] for x in f], r, ref.rel_err, oracle.sumsq(A), g.n[0])
+        tol = fp64_e_tolerance(A, f, r, ref.rel_err)
         say("  E_gpu %.6e E_oracle %.6e tol %.2e" % (t.rel_err, ref.rel_err, tol))
         if tol <= 1e-2 * ref.rel_err:
             assert abs(t.rel_err - ref.rel_err) <= tol, (r, t.rel_err, ref.rel_err, tol)

@@ -2,12 +2,12 @@
 
 The GPU's leading eigenvectors come from block subspace iteration with Rayleigh-Ritz, iterated
 until every Ritz pair passes ||G u - lambda u|| <= max(1e-12 lambda, 4 sqrt(n) u ||G||_F); the
-oracle diagonalises the same Gram by Jacobi.  Both are backward stable, so each is exact for a
-Gram perturbed by about n u ||G||.  The HOSVD error E is stationary in the factors at the exact
-eigenvectors, so such a perturbation moves E only at second order: by about
-(n u lambda_1)^2 / ((lambda_r - lambda_{r+1}) E ||A||^2) per mode.  The parity tolerance is that
-floor or 1e-10 E, whichever is larger (Sec. 3.2: HOSVD by the leading singular subspaces of
-the unfoldings, here from their Grams).
+oracle diagonalises the same Gram by Jacobi.  The two Grams differ by rounding, so each
+eigenvector is fixed only up to a rotation of about u lambda_1 / gap toward its neighbours, and
+the HOSVD error E (not stationary in the factors) moves at first order under it.  The parity
+tolerance is 1e-10 E, or that first-order floor where it is larger (tests/gpu_util.py,
+fp64_e_tolerance; Sec. 3.2: HOSVD by the leading singular subspaces of the unfoldings, here
+from their Grams).
 """
 import numpy as np
 import pytest
@@ -38,13 +38,12 @@ def test_fp64_hosvd_at_slow_spectra(ctx, tk, oracle, n, nu, ell, layout, ranks):
     og = oracle.Grid(n=(n, n, n), layout=layout)
     A = oracle.grid_eval(oracle.Kernel(oracle.MATERN, nu=nu, ell=ell), og)
     f = oracle.hosvd_factors(A)
-    na2 = oracle.sumsq(A)
     kern = tk.make_kernel(0, nu=nu, ell=ell)
     grid = tk.make_grid(n, 1.0, layout)
     for r in ranks:
         t = ctx.compress(kern, grid, tk.make_opts(ranks=r, hooi_sweeps=0, prec=tk.TK_FP64))
         ref = oracle.hosvd(A, (r, r, r), f)
-        tol = fp64_e_tolerance([x[0] for x in f], r, ref.rel_err, na2, n)
+        tol = fp64_e_tolerance(A, f, r, ref.rel_err)
         say("n=%d r=%d E_gpu %.6e E_oracle %.6e diff %.2e tol %.2e" % (n, r, t.rel_err, ref.rel_err,
                                                                           abs(t.rel_err - ref.rel_err), tol))
         assert abs(t.rel_err - ref.rel_err) <= tol, (r, t.rel_err, ref.rel_err, tol)
