@@ -58,32 +58,36 @@ def fp64_e_tolerance(A, f, r, e):
 
     Two correct FP64 implementations form the mode Grams with different rounding; each
     eigenvector u_j of G_k is then fixed only up to a rotation toward u_i by about
-    u lambda_1 / |lambda_j - lambda_i| (u the unit roundoff; a factor 4 for the two Grams and
-    the two eigensolvers).  HOSVD factors are not a stationary point of E (the leading subspaces
-    of A_(k) A_(k)^T are not those of the single-hole Grams that would make them one), so E moves
-    at first order under such rotations.  The floor adds |dE/dtheta| times that angle over the
-    kept columns j in [r-3, r) and the discarded directions i in [r, r+2) of every mode (the
-    nearest pairs: the angle falls like 1/gap), with dE/dtheta from central differences on the
-    oracle's own factors.  f holds the oracle's full eigendecompositions (lambda_k, V_k)."""
+    theta = 4 u lambda_1 / |lambda_j - lambda_i| (u the unit roundoff; a factor 4 for the two
+    Grams and the two eigensolvers).  HOSVD factors are not a stationary point of E (the leading
+    subspaces of A_(k) A_(k)^T are not those of the single-hole Grams that would make them one),
+    so E moves at first order under such rotations.  The floor adds, over the kept columns j in
+    [r-4, r) and the discarded directions i in [r, r+4) of every mode (the nearest pairs: theta
+    falls like 1/gap), |dE/dtheta| theta (central differences on the oracle's own factors), or,
+    for angles of 1e-4 and more, where the first-order term no longer describes the change, the
+    larger change of E under the rotation by +theta or -theta itself (theta capped at pi/4).
+    f holds the oracle's full eigendecompositions (lambda_k, V_k)."""
     if np.isscalar(r):
         r = (int(r),) * 3
     lams = [np.asarray(x[0]) for x in f]
     Vs = [np.asarray(x[1]) for x in f]
     base = [Vs[k][:, :r[k]] for k in range(3)]
-    d = 1e-6
+    e0 = _tucker_err(A, base)
     floor = 0.0
     for k in range(3):
         n, lam = Vs[k].shape[0], lams[k]
-        for j in range(max(0, r[k] - 3), r[k]):
-            for i in range(r[k], min(r[k] + 2, n)):
+        for j in range(max(0, r[k] - 4), r[k]):
+            for i in range(r[k], min(r[k] + 4, n)):
                 gap = lam[j] - lam[i]
-                if gap <= 0:
-                    return float("inf")
-                theta = 4.0 * U64 * lam[0] / gap
+                theta = 4.0 * U64 * lam[0] / gap if gap > 0 else np.inf
+                step = 1e-6 if theta < 1e-4 else min(theta, np.pi / 4)
                 es = []
                 for sgn in (1.0, -1.0):
                     Us = [b.copy() for b in base]
-                    Us[k][:, j] = np.cos(d) * Vs[k][:, j] + sgn * np.sin(d) * Vs[k][:, i]
+                    Us[k][:, j] = np.cos(step) * Vs[k][:, j] + sgn * np.sin(step) * Vs[k][:, i]
                     es.append(_tucker_err(A, Us))
-                floor += abs(es[0] - es[1]) / (2 * d) * theta
+                if theta < 1e-4:
+                    floor += abs(es[0] - es[1]) / (2 * step) * theta
+                else:
+                    floor += max(abs(es[0] - e0), abs(es[1] - e0))
     return max(1e-10 * e, floor)
