@@ -309,6 +309,23 @@ tk_status tk_cov_dims(const tk_tucker *t, int m[3]);
 tk_status tk_kron_matvec(tk_ctx *ctx, const tk_tucker *t, const void *z_dev, void *y_dev,
                          int io, void *hip_stream);
 
+/* Allocation-free y = C z, for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  The FP32 FFT form of
+ * tk_kron_matvec (same kernels, same launch shapes, so the same y bit for bit) with its whole
+ * workspace in a fixed 16 MiB device array that the library holds on every device it runs on
+ * until the process ends: operators of up to 64 points per axis (an OFFSET grid up to n = 64,
+ * an odd CENTERED grid up to n = 127), at every rank the FFT form takes.  The call allocates
+ * nothing, charges nothing to the context's budget and never synchronises.
+ * z_dev, y_dev: caller-owned device float arrays of m1*m2*m3 elements (tk_cov_dims), C-order;
+ * y must not overlap z.  The scratch array is shared by every call on a device and keeps the
+ * last call's contents (nothing in it needs to start at zero): calls that overlap on one
+ * device, on any streams or contexts, race and must be ordered by the caller.
+ * Errors: TK_EINVAL (NULL argument, y aliases z), TK_ELAYOUT (even CENTERED grid),
+ * TK_EUNSUPPORTED (third rank above 48), TK_ENOMEM (operator larger than the scratch holds:
+ * nothing runs), TK_EHIP. */
+tk_status tk_kron_matvec_noalloc(tk_ctx *ctx, const tk_tucker *t, const float *z_dev, float *y_dev,
+                                 void *hip_stream);
+
 /* Matvec algorithm of a context: TK_MV_AUTO (default: the FFT form for io = TK_FP32, dense
  * Toeplitz mode products for TK_FP64), TK_MV_FFT (FP32 only), TK_MV_DENSE.  A result whose
  * third rank exceeds 48 (an FP64 compression or a loaded file) always takes the dense form.

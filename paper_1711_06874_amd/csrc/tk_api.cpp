@@ -31,6 +31,14 @@
 
 using namespace tk;
 
+// Device scratch of the allocation-free matvec (tk_kron_matvec_noalloc): the whole FFT workspace
+// of one call (twiddles, Fourier-side factors, spectral core, both half spectra) for operators
+// of up to 64 points per axis at every rank (12.9 MB at m = 64, r = 48).  Each device holds its
+// own copy until the process ends.  Host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (scratch_address below), never through this name.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -67,6 +75,25 @@ constexpr double MATERN_NU_MAX = 30.0;
 constexpr int KRON1_NMAX = 16384;       // points per axis of a separable covariance factor   // general orders: K_nu s^nu stays inside the double range
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Device address of `scratch` on `device` (which must be current), looked up once per device.
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+hipError_t scratch_address(int device, void** out)
+{
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 // Two-pass arena: pass 1 (base == nullptr) sums sizes, pass 2 hands out aligned pointers.
 struct Arena {
@@ -131,6 +158,7 @@ struct ProfScope {
 struct tk_ctx {
     int device = 0;
     int matvec_method = TK_MV_AUTO;
+    void* scratch = nullptr;   // this device's copy of the no-allocation scratch
     size_t budget = 0;
     std::atomic<size_t> in_use{0};
     // results made with the context; a destroyed context is deleted with its last result
@@ -1739,6 +1767,14 @@ tk_status mv_passes(const MvGeom& g, const MvPre& b, float2* A1, float2* A2, con
     return TK_OK;
 }
 
+// The workspace of one matvec: per-item buffers, then the two half spectra.
+void mv_lay(Arena& ar, const MvGeom& g, MvPre* b, float2** A1, float2** A2)
+{
+    lay_pre(ar, g, b);
+    *A1 = ar.take<float2>(mv_a1_elems(g));
+    *A2 = ar.take<float2>(mv_a2_elems(g));
+}
+
 // One matvec (y != NULL) or quadratic form (dot_out != NULL; y may then be NULL).
 // plan_bytes != nullptr: only report the workspace the call needs (nothing runs).
 tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, hipStream_t s, double* dot_out,
@@ -1746,11 +1782,7 @@ tk_status matvec_fft(tk_ctx* ctx, const tk_tucker* t, const float* z, float* y, 
 {
     MvGeom g;
     if (!mv_geom(t, &g)) return fail(TK_ELAYOUT, "even-sized centred grid has no origin node");
-    auto lay = [&](Arena& ar, MvPre* b, float2** A1, float2** A2) {
-        lay_pre(ar, g, b);
-        *A1 = ar.take<float2>(mv_a1_elems(g));
-        *A2 = ar.take<float2>(mv_a2_elems(g));
-    };
+    auto lay = [&](Arena& ar, MvPre* b, float2** A1, float2** A2) { mv_lay(ar, g, b, A1, A2); };
     Arena plan;
     MvPre b;
     float2 *A1, *A2;
@@ -1939,9 +1971,12 @@ tk_status tk_ctx_create(int device, size_t hbm_budget_bytes, tk_ctx** out)
     TK_HIP(eig_set_attributes());
     TK_HIP(kron_set_attributes());
     TK_HIP(fft_set_attributes());
+    void* scr = nullptr;
+    TK_HIP(scratch_address(device, &scr));
     tk_ctx* c = new (std::nothrow) tk_ctx();
     if (!c) return fail(TK_ENOMEM, "host allocation failed");
     c->device = device;
+    c->scratch = scr;
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)freeb);
     const size_t slot_bytes = (size_t)tk_ctx::kSlots * tk_ctx::kSlotBytes;
     if (hipHostMalloc((void**)&c->pinned, slot_bytes, hipHostMallocDefault) != hipSuccess ||
@@ -2542,6 +2577,40 @@ tk_status tk_kron_matvec(tk_ctx* ctx, const tk_tucker* t, const void* z_dev, voi
     if (io == TK_FP32)
         return matvec_impl<float>(ctx, t, (const float*)z_dev, (float*)y_dev, (hipStream_t)hip_stream, nullptr);
     return matvec_impl<double>(ctx, t, (const double*)z_dev, (double*)y_dev, (hipStream_t)hip_stream, nullptr);
+}
+
+// The FFT matvec of tk_kron_matvec on the device's fixed scratch area: the same kernels and
+// launch shapes (so the same y, bit for bit), no allocation, no budget charge.  Nothing in the
+// workspace needs to start at zero (every buffer is written before it is read), so the contents
+// a previous call left behind do not matter; two calls that overlap on one device race.
+tk_status tk_kron_matvec_noalloc(tk_ctx* ctx, const tk_tucker* t, const float* z_dev, float* y_dev,
+                                 void* hip_stream)
+{
+    if (!ctx || !t || !z_dev || !y_dev) return fail(TK_EINVAL, "NULL argument");
+    if (!usable(t)) return fail(TK_EINVAL, "result of a destroyed context");
+    if ((const void*)z_dev == (const void*)y_dev) return fail(TK_EINVAL, "y must not alias z");
+    if (!ctx->scratch) return fail(TK_EHIP, "no scratch address on device %d", ctx->device);
+    MvGeom g;
+    if (!mv_geom(t, &g)) return fail(TK_ELAYOUT, "even-sized centred grid has no origin node");
+    if (g.r2p > LIB_RMAX)
+        return fail(TK_EUNSUPPORTED, "third rank %d exceeds %d (the FFT matvec's register tile)", g.r[2], LIB_RMAX);
+    Arena plan;
+    MvPre b;
+    float2 *A1, *A2;
+    mv_lay(plan, g, &b, &A1, &A2);
+    if (plan.off > NOALLOC_SCRATCH_BYTES)
+        return fail(TK_ENOMEM, "operator %dx%dx%d at ranks (%d,%d,%d) needs %zu bytes of workspace; the "
+                    "no-allocation scratch holds %zu (up to 64 points per axis)", g.m[0], g.m[1], g.m[2], g.r[0],
+                    g.r[1], g.r[2], plan.off, NOALLOC_SCRATCH_BYTES);
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    hipStream_t s = (hipStream_t)hip_stream;
+    Arena ar;
+    ar.base = (char*)ctx->scratch;
+    mv_lay(ar, g, &b, &A1, &A2);
+    tk_status st;
+    if ((st = mv_preamble(t, g, b, s)) != TK_OK) return st;
+    return mv_passes(g, b, A1, A2, z_dev, y_dev, nullptr, s);
 }
 
 tk_status tk_quadratic_form(tk_ctx* ctx, const tk_tucker* t, const void* z_dev, int io, void* hip_stream,

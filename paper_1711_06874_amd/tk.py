@@ -88,6 +88,7 @@ _SIGS = {
     "tk_tucker_free": (None, [_vp]),
     "tk_cov_dims": (_st, [_vp, _ip]),
     "tk_kron_matvec": (_st, [_vp, _vp, _vp, _vp, ctypes.c_int, _vp]),
+    "tk_kron_matvec_noalloc": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "tk_trace": (_st, [_vp, _vp, _vp, _dp]),
     "tk_quadratic_form": (_st, [_vp, _vp, _vp, ctypes.c_int, _vp, _dp, _vp]),
     "tk_grid_eval": (_st, [_vp, ctypes.POINTER(tk_kernel), ctypes.POINTER(tk_grid), ctypes.c_int, _vp, _vp]),
@@ -326,6 +327,10 @@ def tk_kron_matvec(ctx: int, t: int, z, y, io=TK_FP32, stream=None) -> None:
     _check(_lib.tk_kron_matvec(ctx, t, _ptr(z), _ptr(y), int(io), _stream(stream)), "tk_kron_matvec")
 
 
+def tk_kron_matvec_noalloc(ctx: int, t: int, z, y, stream=None) -> None:
+    _check(_lib.tk_kron_matvec_noalloc(ctx, t, _ptr(z), _ptr(y), _stream(stream)), "tk_kron_matvec_noalloc")
+
+
 def tk_trace(ctx: int, t: int, stream=None) -> float:
     out = ctypes.c_double()
     _check(_lib.tk_trace(ctx, t, _stream(stream), ctypes.byref(out)), "tk_trace")
@@ -452,6 +457,9 @@ class Context:
 
     def kron_matvec(self, t: Tucker, z, y, io=TK_FP32, stream=None):
         tk_kron_matvec(self.handle, t.handle, z, y, io, stream)
+
+    def kron_matvec_noalloc(self, t: Tucker, z, y, stream=None):
+        tk_kron_matvec_noalloc(self.handle, t.handle, z, y, stream)
 
     def trace(self, t: Tucker, stream=None) -> float:
         return tk_trace(self.handle, t.handle, stream)
