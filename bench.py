@@ -7,11 +7,14 @@ contractions, eigensolves, 2 HOOI sweeps, core, error norm, eps truncation; thre
 grids, each group sharing every launch, run concurrently on the context's worker streams); then
 one tk_quadratic_form_batch call, per grid the quadratic form with a seeded N(0,1) FP32 vector
 (the Kronecker-Toeplitz covariance matvec y = C z and z^T y; the five FFT passes of the grids run
-back to back, their small preambles on a worker stream), and per grid tk_trace.  Inputs (the z vectors)
-are resident in HBM before the timed region.  Inside it only the roofline kernel (the axis-0 FFT
-pass) is bracketed by HIP events.  After it, one more quadratic-form batch times the other FFT
-passes, and each grid is compressed alone (single-request latency; per-class kernel times
-without the overlap of the batch).
+back to back, their small preambles on a worker stream), and per grid tk_trace.  Inputs (the z
+vectors, made on the device by tk_normal_fill: Philox4x32-10 keyed by the master seed and the
+grid) are resident in HBM before the timed region.  Inside it only the roofline kernel (the
+axis-0 FFT pass) is bracketed by HIP events.  After it, one more quadratic-form batch times the
+other FFT passes, and each grid is compressed alone, --alone-reps passes over the nine grids
+(single-request latency p50/p99 over 27 compressions by default; per-class kernel times without
+the overlap of the batch).  The compression-only rate is also reported against its algorithmic
+bound, and the FP64 oracle is timed on all host cores and on one.
 
 Prints one JSON line (see the keys below).  --gpus N with N > 1 exits: the benchmark runs on
 one GPU.
@@ -45,28 +48,36 @@ def kernel_source_hash(files):
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(n, rows_sample, seed_stream):
+def cpu_baseline(n, rows_sample, seed_stream, threads=None):
     """Time the FP64 oracle on a bounded sample of the same workload: one 256^3 compress
     (Matern 1/2, ell = 0.1, eps = 1e-6, 2 HOOI sweeps) plus `rows_sample` rows of the plain
-    covariance product; the matvec time is extrapolated to all n^3 rows."""
+    covariance product; the matvec time is extrapolated to all n^3 rows.  threads: the oracle's
+    OpenMP thread count (None: all host cores)."""
     import numpy as np
     from oracle import oracle as o
     import synth
     o.build()
-    k = o.Kernel(o.MATERN, nu=0.5, ell=0.1)
-    g = o.Grid(n=(n, n, n), layout=o.OFFSET)
-    t0 = time.perf_counter()
-    t = o.compress(k, g, eps=1e-6, sweeps=2)
-    t1 = time.perf_counter()
-    z = synth.normal_vector((n, n, n), seed_stream).astype(np.float64)
-    rows = (np.arange(rows_sample, dtype=np.int64) * 1000003) % (n ** 3)
-    t2 = time.perf_counter()
-    o.cov_matvec_rows(t, g, z, rows)
-    t3 = time.perf_counter()
+    all_threads = o.num_threads()
+    if threads:
+        o.set_num_threads(threads)
+    try:
+        k = o.Kernel(o.MATERN, nu=0.5, ell=0.1)
+        g = o.Grid(n=(n, n, n), layout=o.OFFSET)
+        t0 = time.perf_counter()
+        t = o.compress(k, g, eps=1e-6, sweeps=2)
+        t1 = time.perf_counter()
+        z = o.normal_philox(n ** 3, synth.MASTER_SEED, seed_stream).astype(np.float64)
+        rows = (np.arange(rows_sample, dtype=np.int64) * 1000003) % (n ** 3)
+        t2 = time.perf_counter()
+        o.cov_matvec_rows(t, g, z, rows)
+        t3 = time.perf_counter()
+        cores = o.num_threads()
+    finally:
+        o.set_num_threads(all_threads)
     per_row = (t3 - t2) / rows_sample
     grid_s = (t1 - t0) + per_row * n ** 3
     return {
-        "value": 1.0 / grid_s, "unit": "grids/s", "cores": o.num_threads(), "kind": "oracle",
+        "value": 1.0 / grid_s, "unit": "grids/s", "cores": cores, "kind": "oracle",
         "sample": (f"one {n}^3 Matern nu=1/2 ell=0.1 compress (eps 1e-6, 2 HOOI sweeps) = {t1 - t0:.2f} s, "
                    f"plus {rows_sample} rows of the plain covariance product ({per_row * 1e3:.1f} ms/row) "
                    f"extrapolated to all {n ** 3} rows"),
@@ -83,18 +94,9 @@ def main():
     ap.add_argument("--prec", choices=["fp32", "bf16x3"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=8192)
-    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
-                    help="only run 5 plain device-to-device copies of BYTES bytes (HBM counter calibration)")
+    ap.add_argument("--alone-reps", type=int, default=3,
+                    help="passes over the nine grids compressed one at a time after the timed region")
     args = ap.parse_args()
-    if args.calibrate_copy:
-        import torch
-        x = torch.ones(args.calibrate_copy // 4, dtype=torch.float32, device="cuda")
-        yb = torch.empty_like(x)
-        for _ in range(5):
-            yb.copy_(x)
-        torch.cuda.synchronize()
-        print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy}))
-        return
     if args.gpus != 1:
         print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
@@ -112,7 +114,10 @@ def main():
     tkernels = [tk.make_kernel(k.family, nu=k.nu, ell=k.ell, sigma2=k.sigma2) for k in kernels]
     grid = tk.make_grid(n, 1.0, tk.TK_OFFSET)
     opts = tk.make_opts(eps=1e-6, hooi_sweeps=2, prec=prec)
-    zs = [torch.from_numpy(synth.normal_vector((n, n, n), i + 1)).cuda() for i in range(len(kernels))]
+    # seeded N(0,1) vectors made on the device (Philox4x32-10 keyed by the master seed and the grid)
+    zs = [torch.empty((n, n, n), dtype=torch.float32, device="cuda") for _ in kernels]
+    for i, z in enumerate(zs):
+        tk.tk_normal_fill(ctx.handle, synth.MASTER_SEED, i + 1, z)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
@@ -187,11 +192,12 @@ def main():
     # per-class kernel times free of the overlap inside the batch)
     alone_ms = []
     tk.tk_profile_enable(True)
-    for k in tkernels:
-        t0 = time.perf_counter()
-        t = ctx.compress(k, grid, opts, stream)
-        alone_ms.append((time.perf_counter() - t0) * 1e3)
-        t.free()
+    for _ in range(args.alone_reps):
+        for k in tkernels:
+            t0 = time.perf_counter()
+            t = ctx.compress(k, grid, opts, stream)
+            alone_ms.append((time.perf_counter() - t0) * 1e3)
+            t.free()
     torch.cuda.synchronize()
     tk.tk_profile_enable(False)
     alone = {}
@@ -210,7 +216,7 @@ def main():
     fft_bytes = (4.0 * N + 8.0 * m * m * H2) + (8.0 * m * m * H2 + 8.0 * m * L * H2) \
         + (8.0 * m * L * H2 + 8.0 * m * m * H2) + (8.0 * m * m * H2 + 4.0 * N)
     axis0_bytes = 16.0 * m * L * H2
-    n_alone = len(tkernels)
+    n_alone = len(tkernels) * args.alone_reps
     work_alone = {
         "grid": 4.0 * N * n_alone,                                  # bytes written (FP32)
         "gram": 3 * float(n) ** 3 * (n + 1) * n_alone,              # unique Gram entries x 2 flops
@@ -264,6 +270,18 @@ def main():
                 "frac": d["frac"], "traffic": traffic,
                 "ms_per_launch": d["ms_total"] / max(1, d["launches"])}
 
+    # compression alone against its algorithmic bound: HBM traffic (20 + 8 s) n^3 bytes (grid
+    # write, three Gram reads, two A-streaming products per sweep, the error norm; s = 2 sweeps)
+    # at peak bandwidth plus the unique Gram flops 3 n^3 (n + 1) at the MFMA peak of the precision
+    sweeps = 2
+    gram_peak = PEAK["fp32_mfma_TFs"] if prec == tk.TK_FP32 else PEAK["bf16_mfma_TFs"] / 3.0
+    bound_s = (20 + 8 * sweeps) * float(N) / (PEAK["hbm_GBs"] * 1e9) + 3 * float(n) ** 3 * (n + 1) / (gram_peak * 1e12)
+    cb_p50 = percentile(lat["compress_batch"], 50)
+    compress_rate = len(tkernels) / (cb_p50 * 1e-3)
+    compress_out = {"grids_per_s": compress_rate, "bound_grids_per_s": 1.0 / bound_s,
+                    "frac": compress_rate * bound_s,
+                    "measured": "p50 of the timed steps' compress_batch calls (nine grids each)"}
+
     out = {
         "metric": "Tucker-compressed Matern grids/sec at n=256^3, eps=1e-6",
         "value": value, "unit": "grids/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -279,12 +297,15 @@ def main():
         "ranks": sorted(set(r for r, _ in ranks_seen)),
         "max_rel_err": max(e for _, e in ranks_seen),
         "roofline": roofline,
+        "compress": compress_out,
         "kernels": kernels_out,
         "gram_autotune": {"nsplit_per_mode": list(tuned["nsplit"]), "ms_per_mode": list(tuned["ms"])},
     }
     ctx.destroy()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_rows, 1)
+        # the same oracle on one host core (a smaller row sample: about a second per 1000 rows)
+        out["cpu_baseline_1core"] = cpu_baseline(n, max(64, args.cpu_rows // 16), 1, threads=1)
     print(json.dumps(out), flush=True)
 
 

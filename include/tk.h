@@ -406,6 +406,27 @@ tk_status tk_kron1_loglik(tk_ctx *ctx, tk_kron1 *k, const double *z_dev, void *h
 void tk_kron1_free(tk_kron1 *k);
 
 /* ---------------------------------------------------------------------------------------- */
+/* Seeded inputs                                                                             */
+/* ---------------------------------------------------------------------------------------- */
+
+/* Seeded N(0,1) input vectors made on the device (the z of the covariance matvec and quadratic
+ * form).  Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11: ten rounds with multipliers
+ * 0xD2511F53, 0xCD9E8D57 and key increments 0x9E3779B9, 0xBB67AE85) keyed by (seed, stream_id);
+ * counter block c = (c mod 2^32, c / 2^32, 0, 0) yields words x0..x3, the FP64 uniforms
+ * u_a = ((x1 2^32 + x0) >> 11) 2^-53 and u_b = ((x3 2^32 + x2) >> 11) 2^-53, and by the
+ * Box-Muller transform z[2c] = rho cos(phi), z[2c+1] = rho sin(phi) with
+ * rho = sqrt(-2 log(1 - u_a)), phi = 2 pi u_b, each rounded once to float.
+ * z_dev: caller-owned device floats, count <= 2^32.  Stream-ordered.  Errors: TK_EINVAL, TK_EHIP. */
+tk_status tk_normal_fill(tk_ctx *ctx, uint32_t seed, uint32_t stream_id, float *z_dev, size_t count,
+                         void *hip_stream);
+
+/* The raw Philox4x32-10 words of counter blocks counter0 .. counter0 + nblocks - 1 (counter
+ * (c mod 2^32, c / 2^32, 0, 0)) under key[2]: 4 nblocks words to out_dev (16-byte aligned).
+ * nblocks <= 2^31.  Stream-ordered.  Errors: TK_EINVAL, TK_EHIP. */
+tk_status tk_philox4x32(tk_ctx *ctx, const uint32_t key[2], uint64_t counter0, size_t nblocks,
+                        uint32_t *out_dev, void *hip_stream);
+
+/* ---------------------------------------------------------------------------------------- */
 /* Individual steps (the same kernels tk_compress runs), exposed for testing and profiling   */
 /* ---------------------------------------------------------------------------------------- */
 

@@ -526,3 +526,13 @@ int tko_num_threads(void)
     return 1;
 #endif
 }
+
+/* Thread count of the OpenMP loops (timing runs only: every result is independent of it). */
+void tko_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -76,6 +76,7 @@ def _load():
     lib.tko_cov_rows.argtypes = [dp, ip, ip, ip, dp, ctypes.POINTER(ctypes.c_longlong),
                                  ctypes.c_int, dp]
     lib.tko_num_threads.restype = ctypes.c_int
+    lib.tko_set_num_threads.argtypes = [ctypes.c_int]
     lib.tko_cholesky.restype = ctypes.c_int
     lib.tko_cholesky.argtypes = [ctypes.c_int, dp]
     lib.tko_chol_solve.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp]
@@ -98,6 +99,11 @@ def _f64(a) -> np.ndarray:
 
 def num_threads() -> int:
     return int(_load().tko_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Thread count of the oracle's OpenMP loops (results do not depend on it)."""
+    _load().tko_set_num_threads(int(n))
 
 
 # ----------------------------------------------------------------------------------------
@@ -662,3 +668,62 @@ def c2t(Q, ranks, sweeps=0) -> Tucker:
     t = Tucker(U=V, core=core, norm_a2=n2, history=history, sweeps=int(sweeps))
     t.rel_err = float(np.sqrt(max(n2 - sumsq(core), 0.0) / n2))
     return t
+
+
+# ----------------------------------------------------------------------------------------
+# Seeded N(0,1) inputs: Philox4x32-10 and the Box-Muller transform
+# ----------------------------------------------------------------------------------------
+# (not part of the paper's method: the matvec and quadratic form take z as an input; this is
+# the published counter-based generator the device implements on its own, written out here
+# from its definition: Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2,
+# 3", SC'11)
+
+_PHILOX_M = (0xD2511F53, 0xCD9E8D57)   # round multipliers
+_PHILOX_W = (0x9E3779B9, 0xBB67AE85)   # key increments (golden ratio, sqrt(3) - 1)
+
+
+def philox4x32_10(counters, key) -> np.ndarray:
+    """Philox4x32 with ten rounds.  counters: (N, 4) words; key: two words.  One round maps
+    (c0, c1, c2, c3) to (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)),
+    with hi/lo the upper/lower 32 bits of the 64-bit product; the key grows by the Weyl
+    increments before every round but the first.  Returns the (N, 4) output words."""
+    c = np.asarray(counters, dtype=np.uint64).reshape(-1, 4) & 0xFFFFFFFF
+    k0, k1 = int(key[0]) & 0xFFFFFFFF, int(key[1]) & 0xFFFFFFFF
+    mask = np.uint64(0xFFFFFFFF)
+    for r in range(10):
+        if r > 0:
+            k0 = (k0 + _PHILOX_W[0]) & 0xFFFFFFFF
+            k1 = (k1 + _PHILOX_W[1]) & 0xFFFFFFFF
+        p0 = c[:, 0] * np.uint64(_PHILOX_M[0])      # < 2^64: exact in uint64
+        p1 = c[:, 2] * np.uint64(_PHILOX_M[1])
+        hi0, lo0 = p0 >> np.uint64(32), p0 & mask
+        hi1, lo1 = p1 >> np.uint64(32), p1 & mask
+        c = np.stack([hi1 ^ c[:, 1] ^ np.uint64(k0), lo1, hi0 ^ c[:, 3] ^ np.uint64(k1), lo0], axis=1)
+    return c.astype(np.uint32)
+
+
+def philox_blocks(key, counter0: int, nblocks: int) -> np.ndarray:
+    """Words of counter blocks counter0 .. counter0 + nblocks - 1, counter (c mod 2^32,
+    c / 2^32, 0, 0)."""
+    c = np.arange(nblocks, dtype=np.uint64) + np.uint64(counter0)
+    ctr = np.zeros((nblocks, 4), dtype=np.uint64)
+    ctr[:, 0] = c & np.uint64(0xFFFFFFFF)
+    ctr[:, 1] = c >> np.uint64(32)
+    return philox4x32_10(ctr, key)
+
+
+def normal_philox(count: int, seed: int, stream: int) -> np.ndarray:
+    """count N(0,1) values as float32: block c gives the FP64 uniforms
+    u_a = ((x1 2^32 + x0) >> 11) 2^-53, u_b = ((x3 2^32 + x2) >> 11) 2^-53 and, by the
+    Box-Muller transform, z[2c] = rho cos(phi), z[2c+1] = rho sin(phi), rho = sqrt(-2 log(1 - u_a)),
+    phi = 2 pi u_b, each rounded once to float."""
+    nb = (count + 1) // 2
+    w = philox_blocks((seed, stream), 0, nb).astype(np.uint64)
+    ua = (((w[:, 1] << np.uint64(32)) | w[:, 0]) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    ub = (((w[:, 3] << np.uint64(32)) | w[:, 2]) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    rho = np.sqrt(-2.0 * np.log(1.0 - ua))
+    phi = 2.0 * np.pi * ub
+    z = np.empty(2 * nb, dtype=np.float64)
+    z[0::2] = rho * np.cos(phi)
+    z[1::2] = rho * np.sin(phi)
+    return z[:count].astype(np.float32)

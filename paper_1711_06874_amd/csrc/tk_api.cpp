@@ -2819,6 +2819,30 @@ tk_status tk_tucker_load(tk_ctx* ctx, const char* path, tk_tucker** out)
 
 void tk_tucker_free(tk_tucker* t) { free_result(t); }
 
+tk_status tk_normal_fill(tk_ctx* ctx, uint32_t seed, uint32_t stream_id, float* z_dev, size_t count,
+                         void* hip_stream)
+{
+    if (!ctx || (!z_dev && count)) return fail(TK_EINVAL, "NULL argument");
+    if (count > ((size_t)1 << 32)) return fail(TK_EINVAL, "count %zu above 2^32", count);
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    TK_LAUNCH(launch_philox_normal(seed, stream_id, (long)count, z_dev, (hipStream_t)hip_stream));
+    return TK_OK;
+}
+
+tk_status tk_philox4x32(tk_ctx* ctx, const uint32_t key[2], uint64_t counter0, size_t nblocks, uint32_t* out_dev,
+                        void* hip_stream)
+{
+    if (!ctx || !key || (!out_dev && nblocks)) return fail(TK_EINVAL, "NULL argument");
+    if (((uintptr_t)out_dev & 15) != 0) return fail(TK_EINVAL, "out_dev must be 16-byte aligned");
+    if (nblocks > ((size_t)1 << 31)) return fail(TK_EINVAL, "nblocks %zu above 2^31", nblocks);
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    TK_LAUNCH(launch_philox_words(key[0], key[1], (unsigned long long)counter0, (long)nblocks, out_dev,
+                                  (hipStream_t)hip_stream));
+    return TK_OK;
+}
+
 tk_status tk_grid_eval(tk_ctx* ctx, const tk_kernel* kernel, const tk_grid* grid, int prec, void* A_dev,
                        void* hip_stream)
 {

@@ -250,4 +250,12 @@ hipError_t launch_final_err(double* scal, hipStream_t s, Bat bt = Bat(), bool ze
 hipError_t launch_mask_rank(double* const U[3], const int n[3], const int R[3], double* core, const int* ranks,
                             hipStream_t s, Bat bt = Bat());
 
+// ------------------------------------------------------------ seeded N(0,1) inputs ----
+// Philox4x32-10 words of counter blocks c0 .. c0 + nblocks - 1 under key (k0, k1): four words
+// per block (out holds 4 nblocks words, 16-byte aligned).
+hipError_t launch_philox_words(uint32_t k0, uint32_t k1, unsigned long long c0, long nblocks, uint32_t* out,
+                               hipStream_t s);
+// z[e] for e < count: the Box-Muller normals of blocks 0 .. ceil(count / 2) - 1 (k_rng.hip).
+hipError_t launch_philox_normal(uint32_t k0, uint32_t k1, long count, float* z, hipStream_t s);
+
 }  // namespace tk

@@ -47,8 +47,13 @@ def run_rate(tk, ctx, rate, count, workers, prec, trace=None, batching=32):
     spare = {}            # n -> free output vectors (reused, not reallocated per request)
     # seeded N(0,1) inputs, drawn before the replay (ZPOOL per size, read-only, shared by the
     # requests), so the client does no device work while the server is measured
-    zpool = {n: [synth.normal_vector_device((n, n, n), 1_000_000 * n + j) for j in range(ZPOOL)]
-             for n in synth.STREAM_SIZES}
+    zpool = {}
+    for n in synth.STREAM_SIZES:
+        zpool[n] = []
+        for j in range(ZPOOL):
+            z = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
+            tk.tk_normal_fill(ctx.handle, synth.MASTER_SEED, 1_000_000 * n + j, z)
+            zpool[n].append(z)
     # matvec outputs, allocated before the replay as well (more only if all are in use)
     for n in synth.STREAM_SIZES:
         spare[n] = [torch.empty((n, n, n), dtype=torch.float32, device="cuda") for _ in range(YPOOL)]

@@ -91,6 +91,8 @@ _SIGS = {
     "tk_kron_matvec_noalloc": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "tk_trace": (_st, [_vp, _vp, _vp, _dp]),
     "tk_quadratic_form": (_st, [_vp, _vp, _vp, ctypes.c_int, _vp, _dp, _vp]),
+    "tk_normal_fill": (_st, [_vp, ctypes.c_uint32, ctypes.c_uint32, _vp, ctypes.c_size_t, _vp]),
+    "tk_philox4x32": (_st, [_vp, ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint64, ctypes.c_size_t, _vp, _vp]),
     "tk_grid_eval": (_st, [_vp, ctypes.POINTER(tk_kernel), ctypes.POINTER(tk_grid), ctypes.c_int, _vp, _vp]),
     "tk_gram": (_st, [_vp, _vp, _ip, ctypes.c_int, ctypes.c_int, _vp, _vp]),
     "tk_eig_topr": (_st, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]),
@@ -352,6 +354,20 @@ def tk_quadratic_form_batch(ctx: int, ts, zs, io=TK_FP32, stream=None, ys=None):
     out = (ctypes.c_double * n)()
     _check(_lib.tk_quadratic_form_batch(ctx, n, th, zp, int(io), _stream(stream), out, yp), "tk_quadratic_form_batch")
     return list(out)
+
+
+def tk_normal_fill(ctx: int, seed: int, stream_id: int, z, stream=None) -> None:
+    """z (a float32 device tensor) <- seeded N(0,1) values (Philox4x32-10 + Box-Muller)."""
+    _check(_lib.tk_normal_fill(ctx, int(seed) & 0xffffffff, int(stream_id) & 0xffffffff, _ptr(z), int(z.numel()),
+                               _stream(stream)), "tk_normal_fill")
+
+
+def tk_philox4x32(ctx: int, key, counter0: int, out, stream=None) -> None:
+    """out (an int32/uint32 device tensor of 4 n words) <- Philox4x32-10 of counters
+    counter0 .. counter0 + n - 1 under key (two 32-bit words)."""
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xffffffff for x in key])
+    _check(_lib.tk_philox4x32(ctx, k, int(counter0), int(out.numel()) // 4, _ptr(out), _stream(stream)),
+           "tk_philox4x32")
 
 
 def tk_grid_eval(ctx: int, kernel: tk_kernel, grid: tk_grid, prec: int, A, stream=None) -> None:

@@ -135,21 +135,3 @@ def random_tensor(shape, stream: int, seed: int = MASTER_SEED) -> np.ndarray:
     rng = np.random.default_rng([seed, 11, int(stream)])
     return rng.uniform(-1.0, 1.0, size=tuple(shape))
 
-
-def normal_vector_device(shape, stream: int, seed: int = MASTER_SEED):
-    """Seeded N(0,1) float32 vector drawn on the GPU (torch's generator keyed by seed and
-    stream): the input of follow-up requests in the serving workload, where drawing hundreds
-    of MB per request on the host would distort the arrival times."""
-    import torch
-    g = torch.Generator(device="cuda")
-    g.manual_seed(int(seed) * 1_000_003 + int(stream))
-    return torch.randn(tuple(shape), generator=g, device="cuda", dtype=torch.float32)
-
-
-def fill_normal_device(x, stream: int, seed: int = MASTER_SEED):
-    """Refill an existing float32 device tensor with the draws of normal_vector_device."""
-    import torch
-    g = torch.Generator(device="cuda")
-    g.manual_seed(int(seed) * 1_000_003 + int(stream))
-    x.normal_(generator=g)
-    return x

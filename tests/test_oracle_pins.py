@@ -705,3 +705,50 @@ def test_c2t_matches_tucker_als_of_the_full_cp_tensor(oracle):
         assert e_c2t == pytest.approx(d.rel_err, rel=1e-6), r
         hist = np.asarray(c.history)
         assert np.all(np.diff(hist) >= -1e-12 * hist[0])
+
+
+# ------------------------------------------------------------------ seeded N(0,1) inputs ----
+
+def _kat():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "philox_kat.json")
+    return json.load(open(path))["vectors"]
+
+
+def test_philox_known_answer_vectors(oracle):
+    """Philox4x32-10 reproduces the known-answer vectors published with the generator's
+    reference implementation (tests/golden/philox_kat.json)."""
+    for v in _kat():
+        ctr = [[int(x, 16) for x in v["counter"]]]
+        key = [int(x, 16) for x in v["key"]]
+        out = oracle.philox4x32_10(ctr, key)[0]
+        assert ["%08x" % int(x) for x in out] == v["output"]
+
+
+def test_philox_blocks_counter_layout(oracle):
+    """Block c is the counter (c mod 2^32, c / 2^32, 0, 0): blocks across the 2^32 boundary
+    equal the generator applied to those counters one by one."""
+    c0 = (1 << 32) - 2
+    w = oracle.philox_blocks((5, 9), c0, 4)
+    for i in range(4):
+        c = c0 + i
+        assert np.array_equal(w[i], oracle.philox4x32_10([[c & 0xFFFFFFFF, c >> 32, 0, 0]], (5, 9))[0])
+
+
+def test_normal_philox_is_box_muller_of_the_words(oracle):
+    """z[2c]^2 + z[2c+1]^2 = -2 log(1 - u_a) and atan2(z[2c+1], z[2c]) = 2 pi u_b (mod 2 pi)
+    for the block's uniforms; the values are N(0,1) (Kolmogorov-Smirnov at 1e6 draws)."""
+    from scipy import stats
+    z = oracle.normal_philox(1_000_000, 1711, 4).astype(np.float64)
+    w = oracle.philox_blocks((1711, 4), 0, 500_000).astype(np.uint64)
+    ua = (((w[:, 1] << np.uint64(32)) | w[:, 0]) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    ub = (((w[:, 3] << np.uint64(32)) | w[:, 2]) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    r2 = z[0::2] ** 2 + z[1::2] ** 2
+    assert np.allclose(r2, -2.0 * np.log(1.0 - ua), rtol=1e-6, atol=1e-6)
+    ang = np.mod(np.arctan2(z[1::2], z[0::2]), 2 * np.pi)
+    d = np.abs(ang - 2 * np.pi * ub)
+    d = np.minimum(d, 2 * np.pi - d)
+    assert np.all(d[r2 > 1e-6] < 1e-5)
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    assert abs(z.mean()) < 5e-3 and abs(z.var() - 1.0) < 5e-3
+    # an odd count drops the last sine value only
+    assert np.array_equal(oracle.normal_philox(7, 1711, 4), z[:7].astype(np.float32))
