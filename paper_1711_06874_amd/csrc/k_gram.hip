@@ -11,6 +11,11 @@
 // every entry in split order in FP64 and writes both G[i][j] and G[j][i] (diagonal tiles are
 // mirrored from their upper half), so the result is deterministic and exactly symmetric.
 //
+// Large FP32 grids (every n_k a multiple of 32 and the mode's n_k >= 256) take k_gram_big:
+// 128 x 128 tiles, each wave a 64 x 64 block (four independent 32 x 32 MFMA accumulators), K
+// chunks of 32 loaded as float4 and staged in LDS, and the splits of K given to the XCDs so
+// that all tile pairs of one split run on one XCD (its L2 holds the split's row panels once).
+//
 // Precision variants:
 //   double : mfma_f64_16x16x4f64, FP64 accumulation and FP64 partials
 //   float  : mfma_f32_32x32x2f32, FP32 accumulation
@@ -194,6 +199,147 @@ __global__ void __launch_bounds__(NT) k_gram_tiles(const T* __restrict__ A, Unfo
 }
 
 // ----------------------------------------------------------------------------------------
+// FP32, large tiles.  Work-group = 4 waves (2 x 2), output tile BG x BG, each wave a 64 x 64
+// block of four mfma_f32_32x32x2f32 accumulators.  Within a K chunk of 32, MFMA step j (0..15)
+// takes k = j on lanes 0-31 and k = 16 + j on lanes 32-63 (any fixed assignment of the chunk's
+// k values to the steps sums the same products).  LDS layout: modes 0/1 (unfoldings contiguous
+// along K) [m][k] with row stride 36 floats, read as float4 runs of k; mode 2 (contiguous along
+// the rows) [k][m] with row stride 132, read one float per lane.  Both strides keep the float4
+// stores and the operand reads free of bank conflicts.
+// ----------------------------------------------------------------------------------------
+constexpr int BG = 128;
+constexpr int BKG = 32;
+
+template <int MODE>
+__global__ void __launch_bounds__(NT) k_gram_big(const float* __restrict__ A, Unfold<MODE> u, int nrow, long K,
+                                                 long kchunk, int T_tiles, int npairs,
+                                                 float* __restrict__ partials, long bs)
+{
+    constexpr int SM = (MODE == 2) ? BKG : BG;           // LDS rows
+    constexpr int SL = (MODE == 2) ? BG + 4 : BKG + 4;   // LDS row stride (floats)
+    __shared__ __attribute__((aligned(16))) float As[SM * SL];
+    __shared__ __attribute__((aligned(16))) float Bs[SM * SL];
+    A = bshift(A, bs);
+    partials = bshift(partials, bs);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // blocks b with equal b mod 8 share an XCD: the npairs tile pairs of split
+    // (b mod 8) + 8 floor(b / (8 npairs)) are consecutive blocks of one XCD
+    const int b = blockIdx.x;
+    const int xcd = b & 7, l = b >> 3;
+    const int grp = l / npairs;
+    const int pidx = l - grp * npairs;
+    const int split = xcd + 8 * grp;
+    const int nsplit = (int)(gridDim.x / npairs);
+    int ti, tj;
+    pair_of(pidx, T_tiles, ti, tj);
+    const bool diag = (ti == tj);
+    const int r0a = ti * BG, r0b = tj * BG;
+    const long kbeg = (long)split * kchunk;
+    const long kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[bi][bj][v] = 0.f;
+
+    // global -> register staging: 4 runs of 4 floats per tile per thread (native vector type:
+    // the HIP float4 class kept these arrays in scratch memory)
+    f32x4 ra[4], rb[4];
+    // modes 0/1: thread (rr = tid / 8, c4 = tid % 8) loads rows rr + 32 e, k = 4 c4 .. 4 c4 + 3
+    // mode 2:    thread (c32 = tid % 32, kq = tid / 32) loads rows 4 c32 .. 4 c32 + 3, k = kq + 8 e
+    const int rr = tid >> 3, c4 = tid & 7;
+    const int c32 = tid & 31, kq = tid >> 5;
+    long q1 = 0;   // mode 1: the chunk's i0 block and offset within it (K = q1 n2 + o1)
+    int o1 = 0;
+    if (MODE == 1) { q1 = kbeg / u.n2; o1 = (int)(kbeg - q1 * u.n2); }
+    const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
+    auto gload = [&](long k0) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (MODE == 2) {
+                const long base = (k0 + kq + 8 * e) * (long)u.n2;
+                const int ra_ = r0a + 4 * c32, rb_ = r0b + 4 * c32;
+                ra[e] = ra_ < nrow ? *reinterpret_cast<const f32x4*>(A + base + ra_) : z4;
+                if (!diag) rb[e] = rb_ < nrow ? *reinterpret_cast<const f32x4*>(A + base + rb_) : z4;
+            } else {
+                const int rowa = r0a + rr + 32 * e, rowb = r0b + rr + 32 * e;
+                const long kb = (MODE == 0) ? k0 + 4 * c4 : q1 * u.n1n2 + o1 + 4 * c4;
+                const long rs = u.rowstride();
+                ra[e] = rowa < nrow ? *reinterpret_cast<const f32x4*>(A + kb + (long)rowa * rs) : z4;
+                if (!diag) rb[e] = rowb < nrow ? *reinterpret_cast<const f32x4*>(A + kb + (long)rowb * rs) : z4;
+            }
+        }
+        if (MODE == 1) {
+            o1 += BKG;
+            if (o1 >= u.n2) { o1 -= u.n2; ++q1; }
+        }
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int off = (MODE == 2) ? (kq + 8 * e) * SL + 4 * c32 : (rr + 32 * e) * SL + 4 * c4;
+            *reinterpret_cast<f32x4*>(&As[off]) = ra[e];
+            if (!diag) *reinterpret_cast<f32x4*>(&Bs[off]) = rb[e];
+        }
+    };
+
+    if (kbeg < kend) gload(kbeg);
+    for (long k0 = kbeg; k0 < kend; k0 += BKG) {
+        __syncthreads();
+        sstore();
+        __syncthreads();
+        if (k0 + BKG < kend) gload(k0 + BKG);     // the next chunk, in flight during the products
+        const float* Bp = diag ? As : Bs;
+        const int li = lane & 31, h = lane >> 5;
+        if (MODE == 2) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int kr = (16 * h + j) * SL;
+                const float a0 = As[kr + wm + li], a1 = As[kr + wm + 32 + li];
+                const float b0 = Bp[kr + wn + li], b1 = Bp[kr + wn + 32 + li];
+                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int kc = 16 * h + 4 * q;
+                const f32x4 av0 = *reinterpret_cast<const f32x4*>(&As[(wm + li) * SL + kc]);
+                const f32x4 av1 = *reinterpret_cast<const f32x4*>(&As[(wm + 32 + li) * SL + kc]);
+                const f32x4 bv0 = *reinterpret_cast<const f32x4*>(&Bp[(wn + li) * SL + kc]);
+                const f32x4 bv1 = *reinterpret_cast<const f32x4*>(&Bp[(wn + 32 + li) * SL + kc]);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av0[t], bv0[t], acc[0][0], 0, 0, 0);
+                    acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av0[t], bv1[t], acc[0][1], 0, 0, 0);
+                    acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av1[t], bv0[t], acc[1][0], 0, 0, 0);
+                    acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av1[t], bv1[t], acc[1][1], 0, 0, 0);
+                }
+            }
+        }
+    }
+
+    // the BG x BG partial (row-major) of this (pair, split)
+    float* P = partials + ((long)pidx * nsplit + split) * (BG * BG);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int i = wm + 32 * bi + (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
+                const int j = wn + 32 * bj + (lane & 31);
+                P[i * BG + j] = acc[bi][bj][v];
+            }
+}
+
+// ----------------------------------------------------------------------------------------
 // BF16x3 tiles.  LDS holds [BM][BK + 8] bf16 hi and lo parts (row-major, so that each lane
 // reads its 8 consecutive k values with one 16-byte load).
 // ----------------------------------------------------------------------------------------
@@ -288,10 +434,10 @@ __global__ void __launch_bounds__(NT) k_gram_tiles_bf16x3(const float* __restric
     }
 }
 
-// G[ti*64 + ii][tj*64 + jj] = sum_s P[pair][s][ii][jj] in FP64; mirrored.  Each entry is
+// G[ti*TB + ii][tj*TB + jj] = sum_s P[pair][s][ii][jj] in FP64 (TB: the tile edge); mirrored.  Each entry is
 // summed by 4 threads (thread g takes splits g, g + 4, g + 8, ... in order) and the four
 // sums are added in the fixed order g = 0, 1, 2, 3, so the result does not depend on timing.
-template <typename T>
+template <typename T, int TB>
 __global__ void __launch_bounds__(256) k_gram_reduce(const T* __restrict__ partials, int T_tiles,
                                                      int nsplit, int nrow, double* __restrict__ G, long bs)
 {
@@ -303,15 +449,15 @@ __global__ void __launch_bounds__(256) k_gram_reduce(const T* __restrict__ parti
     pair_of(pidx, T_tiles, ti, tj);
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int e = blockIdx.x * 64 + lane;             // entry within the tile
-    const T* P = partials + (long)pidx * nsplit * (BM * BM) + e;
+    const T* P = partials + (long)pidx * nsplit * (TB * TB) + e;
     double s = 0.0;
-    for (int q = g; q < nsplit; q += 4) s += (double)P[(long)q * (BM * BM)];
+    for (int q = g; q < nsplit; q += 4) s += (double)P[(long)q * (TB * TB)];
     part[g][lane] = s;
     __syncthreads();
     if (g != 0) return;
-    const int ii = e / BM, jj = e % BM;
+    const int ii = e / TB, jj = e % TB;
     if (ti == tj && ii > jj) return;                  // diagonal tiles: upper half only
-    const int gi = ti * BM + ii, gj = tj * BM + jj;
+    const int gi = ti * TB + ii, gj = tj * TB + jj;
     if (gi >= nrow || gj >= nrow) return;
     const double v = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
     G[(long)gi * nrow + gj] = v;
@@ -348,15 +494,78 @@ constexpr int BK_F32 = 32, BK_F64 = 16, BK_BF = 32;
 
 int bk_for(int prec) { return prec == 0 ? BK_F64 : (prec == 1 ? BK_F32 : BK_BF); }
 
+// The large-tile kernel takes FP32 modes with n_mode >= 256 when every extent is a multiple of
+// 32 (float4 runs and whole K chunks inside one i0 block of the mode-1 unfolding).
+bool use_big(const int n[3], int mode, int prec)
+{
+    return prec == 1 && n[mode] >= 256 && n[0] % 32 == 0 && n[1] % 32 == 0 && n[2] % 32 == 0;
+}
+
+// Large-tile split count for about `per_cu` resident work-groups on each of the 256 CUs (164
+// VGPRs per lane: three waves per SIMD, so three work-groups per CU at most), rounded down to a
+// multiple of 8 (the XCD grouping), at least 8.
+int big_splits(int npairs, int per_cu)
+{
+    const int s = (256 * per_cu / npairs) / 8 * 8;
+    return s > 8 ? s : 8;
+}
+
+// Large-tile plan: nsplit a multiple of 8 (default: three work-groups per CU; a requested split
+// count is rounded up to a multiple of 8).
+GramPlan make_plan_big(const int n[3], int mode, int nsplit_req = 0)
+{
+    GramPlan p;
+    long N = (long)n[0] * n[1] * n[2];
+    p.nrow = n[mode];
+    p.K = N / n[mode];
+    p.T_tiles = (p.nrow + BG - 1) / BG;
+    p.npairs = p.T_tiles * (p.T_tiles + 1) / 2;
+    long s = nsplit_req > 0 ? nsplit_req : big_splits(p.npairs, 3);
+    s = (s + 7) / 8 * 8;
+    const long maxs = (p.K + BKG - 1) / BKG;
+    if (s > (maxs + 7) / 8 * 8) s = (maxs + 7) / 8 * 8;
+    long kc = (p.K + s - 1) / s;
+    kc = (kc + BKG - 1) / BKG * BKG;
+    p.kchunk = kc;
+    p.nsplit = (int)s;   // trailing splits past K (if any) add zeros
+    return p;
+}
+
 }  // namespace
 
 int gram_default_splits(const int n[3], int mode, int prec)
 {
+    if (use_big(n, mode, prec)) return make_plan_big(n, mode).nsplit;
     return make_plan(n, mode, bk_for(prec)).nsplit;
+}
+
+int gram_split_candidates(const int n[3], int mode, int prec, int out[4])
+{
+    if (use_big(n, mode, prec)) {
+        // about 3, 2 and 1 work-groups per CU (all within the default's workspace)
+        const GramPlan p = make_plan_big(n, mode);
+        int c = 0;
+        for (int per = 3; per >= 1; --per) {
+            const GramPlan q = make_plan_big(n, mode, big_splits(p.npairs, per));
+            if (q.nsplit <= p.nsplit && (c == 0 || q.nsplit != out[c - 1])) out[c++] = q.nsplit;
+        }
+        return c;
+    }
+    const int s0 = make_plan(n, mode, bk_for(prec)).nsplit;
+    int c = 0;
+    for (int d = 1; d <= 4; d *= 2) {
+        const int v = s0 / d > 1 ? s0 / d : 1;
+        if (c == 0 || v != out[c - 1]) out[c++] = v;
+    }
+    return c;
 }
 
 size_t gram_work_bytes(const int n[3], int mode, int prec, int nsplit)
 {
+    if (use_big(n, mode, prec)) {
+        GramPlan p = make_plan_big(n, mode, nsplit);
+        return (size_t)p.npairs * p.nsplit * BG * BG * 4;
+    }
     GramPlan p = make_plan(n, mode, bk_for(prec), nsplit);
     size_t elt = (prec == 0) ? 8 : 4;
     return (size_t)p.npairs * p.nsplit * BM * BM * elt;
@@ -366,11 +575,23 @@ template <int MODE>
 static hipError_t launch_mode(const void* A, const int n[3], int prec, double* G, void* work, hipStream_t s,
                               Bat bt, int nsplit)
 {
-    GramPlan p = make_plan(n, MODE, bk_for(prec), nsplit);
     Unfold<MODE> u;
     u.n1n2 = (long)n[1] * n[2];
     u.n1 = n[1];
     u.n2 = n[2];
+    if (use_big(n, MODE, prec)) {
+        GramPlan p = make_plan_big(n, MODE, nsplit);
+        dim3 grid((unsigned)(p.npairs * p.nsplit), 1, bt.nb);
+        hipLaunchKernelGGL(k_gram_big<MODE>, grid, dim3(NT), 0, s, (const float*)A, u, p.nrow, p.K, p.kchunk,
+                           p.T_tiles, p.npairs, (float*)work, bt.bs);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        dim3 rgrid(BG * BG / 64, p.npairs, bt.nb);
+        hipLaunchKernelGGL((k_gram_reduce<float, BG>), rgrid, dim3(256), 0, s, (const float*)work, p.T_tiles,
+                           p.nsplit, p.nrow, G, bt.bs);
+        return hipGetLastError();
+    }
+    GramPlan p = make_plan(n, MODE, bk_for(prec), nsplit);
     dim3 grid((unsigned)(p.npairs * p.nsplit), 1, bt.nb);
     if (prec == 0) {
         hipLaunchKernelGGL((k_gram_tiles<MODE, double, BK_F64>), grid, dim3(NT), 0, s, (const double*)A, u,
@@ -386,10 +607,10 @@ static hipError_t launch_mode(const void* A, const int n[3], int prec, double* G
     if (e != hipSuccess) return e;
     dim3 rgrid(BM * BM / 64, p.npairs, bt.nb);
     if (prec == 0)
-        hipLaunchKernelGGL(k_gram_reduce<double>, rgrid, dim3(256), 0, s, (const double*)work, p.T_tiles,
+        hipLaunchKernelGGL((k_gram_reduce<double, BM>), rgrid, dim3(256), 0, s, (const double*)work, p.T_tiles,
                            p.nsplit, p.nrow, G, bt.bs);
     else
-        hipLaunchKernelGGL(k_gram_reduce<float>, rgrid, dim3(256), 0, s, (const float*)work, p.T_tiles,
+        hipLaunchKernelGGL((k_gram_reduce<float, BM>), rgrid, dim3(256), 0, s, (const float*)work, p.T_tiles,
                            p.nsplit, p.nrow, G, bt.bs);
     return hipGetLastError();
 }

@@ -2066,12 +2066,11 @@ tk_status tk_autotune(tk_ctx* ctx, const tk_grid* grid, int prec, void* hip_stre
     TK_HIP(hipEventCreate(&e0));
     TK_HIP(hipEventCreate(&e1));
     for (int k = 0; k < 3; ++k) {
-        const int s0 = gram_default_splits(n, k, prec);
-        int cand[3] = {s0, std::max(1, s0 / 2), std::max(1, s0 / 4)};
-        int best = s0;
+        int cand[4];
+        const int nc = gram_split_candidates(n, k, prec, cand);
+        int best = cand[0];
         float best_ms = 1e30f;
-        for (int c = 0; c < 3; ++c) {
-            if (c > 0 && cand[c] == cand[c - 1]) continue;
+        for (int c = 0; c < nc; ++c) {
             TK_LAUNCH(launch_gram(A, n, k, prec, G, work, s, Bat(), cand[c]));   // warm-up
             TK_HIP(hipEventRecord(e0, s));
             for (int rep = 0; rep < 5; ++rep) TK_LAUNCH(launch_gram(A, n, k, prec, G, work, s, Bat(), cand[c]));

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -22,10 +23,14 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // Batched launches: grid z runs over problems of equal shape whose device workspaces lie `bs`
 // bytes apart; a kernel moves each of its workspace pointers by blockIdx.z * bs (null pointers
 // stay null).  With one problem (grid z = 1) nothing moves.
+// The offset is applied as byte pointer arithmetic (not through an integer), so the compiler
+// still sees a global-memory pointer and emits global loads and stores: a flat access would
+// also count against the LDS wait counter and make every LDS wait drain the loads in flight.
 template <typename T>
 __device__ __forceinline__ T* bshift(T* p, long bs)
 {
-    return p ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)((long)blockIdx.z * bs)) : p;
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return p ? reinterpret_cast<T*>(reinterpret_cast<B*>(p) + (long)blockIdx.z * bs) : p;
 }
 
 // Covariance families (values match the public tk_family enum).

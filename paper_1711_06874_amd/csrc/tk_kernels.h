@@ -56,6 +56,9 @@ void grid_eval_node_f64(double* A, const GridAxes& g, const KernelParams* kps, B
 // for the shape, gram_default_splits); the partial sums of the chunks are added in FP64 in
 // chunk order, so a given split count gives the same result every time.
 int gram_default_splits(const int n[3], int mode, int prec);
+// Split counts worth timing for the shape (out[0] the default; none needs more workspace than
+// the default): returns how many were written (at most 4).
+int gram_split_candidates(const int n[3], int mode, int prec, int out[4]);
 size_t gram_work_bytes(const int n[3], int mode, int prec, int nsplit = 0);
 hipError_t launch_gram(const void* A, const int n[3], int mode, int prec, double* G, void* work,
                        hipStream_t s, Bat bt = Bat(), int nsplit = 0);

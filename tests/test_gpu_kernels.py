@@ -120,7 +120,9 @@ def test_grid_eval_families(ctx, tk, oracle, name, kw, layout):
     assert np.all(np.abs(g32.astype(np.float64) - ref32.astype(np.float64)) <= ulp)
 
 
-@pytest.mark.parametrize("shape", [(64, 64, 64), (70, 33, 129), (5, 7, 200)])
+# (256, 288, 32) and (64, 32, 320): FP32 modes with n_mode >= 256 take the large-tile kernel
+# (128 x 128 tiles; 288 and 320 leave a ragged last tile)
+@pytest.mark.parametrize("shape", [(64, 64, 64), (70, 33, 129), (5, 7, 200), (256, 288, 32), (64, 32, 320)])
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_gram(ctx, tk, oracle, shape, prec):
     say("gram", shape, prec)
@@ -141,12 +143,13 @@ def test_gram(ctx, tk, oracle, shape, prec):
         assert np.array_equal(got, got.T)          # mirrored exactly
 
 
-def test_gram_deterministic(ctx, tk):
-    X = dev(synth.random_tensor((96, 80, 72), 5), np.float32)
+@pytest.mark.parametrize("shape,mode", [((96, 80, 72), 1), ((32, 256, 64), 1), ((256, 32, 256), 2)])
+def test_gram_deterministic(ctx, tk, shape, mode):
+    X = dev(synth.random_tensor(shape, 5), np.float32)
     outs = []
     for _ in range(2):
-        G = torch.empty((80, 80), dtype=torch.float64, device="cuda")
-        tk.tk_gram(ctx.handle, X, (96, 80, 72), 1, tk.TK_FP32, G)
+        G = torch.empty((shape[mode], shape[mode]), dtype=torch.float64, device="cuda")
+        tk.tk_gram(ctx.handle, X, shape, mode, tk.TK_FP32, G)
         outs.append(host(G))
     assert np.array_equal(outs[0], outs[1])
 

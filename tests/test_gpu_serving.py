@@ -49,6 +49,8 @@ def _run_mix(tk, ctx, workers, prec):
                 fol.append(sv.submit_quadform(tickets[ci], z, y=y))
         comp = [sv.wait(t) for t in tickets]
         res = [sv.wait(t) for t in fol]
+        bad = [(i, c["status"], c["error"]) for i, c in enumerate(comp) if c["status"] != tk.TK_OK]
+        assert not bad, bad
         facs = [sv.tucker(t).factors() for t in tickets]
         ys = [host(y) for (_, y) in vecs]
         return comp, res, facs, ys
