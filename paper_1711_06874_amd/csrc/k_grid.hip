@@ -1,13 +1,22 @@
 // a1: collocation tensor of a radial covariance function (Sec. 3.7 eq. (3.25)).
 //
 // A[i0,i1,i2] = sigma2 * k(||(x_i0, y_i1, z_i2)||), C-order.  Node coordinates and the radius
-// are formed in double (x = x0 + i h, r = sqrt((x^2 + y^2) + z^2)) and the kernel is
-// evaluated in double, then rounded once to the storage type (for float storage with a
-// shorter exponential and square root whose ~1e-10 relative error is far below half a float
-// ulp).  Each thread writes 4
-// consecutive elements of one i2-row (one 16-byte store for float rows whose length is a
-// multiple of 4); the grid is a flat 1-D launch over rows x ceil(n2/4) quads, so stores
-// from a wave cover contiguous 1 KiB (float) / 2 KiB (double) spans.
+// are formed in double (x = x0 + i h, r = sqrt((x^2 + y^2) + z^2)).
+//
+// Double storage (k_grid_eval): the kernel in double with the library exponential, one thread
+// per 4 consecutive elements of an i2-row.
+//
+// Float storage (k_grid_eval_f32): one wavefront per i2-row (i0, i1), each lane a float4 of the
+// row.  When the first two axes carry the same nodes (equal n, first node, spacing and metric
+// scale), x^2 + y^2 is symmetric in (i0, i1) (up to the last bit of a fused multiply-add, far
+// below float resolution), so only rows with i0 <= i1 are evaluated and each is stored as row
+// (i0, i1) and row (i1, i0).  The closed forms
+// (Matern nu = 1/2, 3/2, 5/2, Slater with p = 1, Gauss) take exp(-s) = 2^k 2^f with
+// u = -s log2(e) = k + f, |f| <= 1/2, in double, 2^f from the hardware FP32 exp2 of f (rounded
+// to float), the polynomial factor and the scaling by 2^k in double, and one final rounding to
+// float.  The value is within 3.2 * 2^-24 relative of the exact one (the exp2's 1 ulp of a value
+// in [0.70, 1.42] is at most 2^-23 relative, f's rounding ln2 2^-26, the final rounding 2^-24);
+// the other families take the double evaluation.
 #include "tk_kernels.h"
 
 namespace tk {
@@ -63,6 +72,165 @@ __global__ void __launch_bounds__(256) k_grid_eval(T* __restrict__ A, GridAxes g
     }
 }
 
+// exp(-s) scaled by the polynomial factor P(s), rounded once to float (see the header).
+__device__ __forceinline__ float poly_exp_neg_f32(double s, double c0, double c1, double c2)
+{
+    const double u = s * -1.4426950408889634;
+    const double k = rint(u);
+    const float f = (float)(u - k);
+    const double e = (double)__builtin_amdgcn_exp2f(f);
+    const double poly = fma(fma(c2, s, c1), s, c0);
+    return (float)ldexp(poly * e, (int)fmax(k, -2000.0));
+}
+
+enum { GF_M12 = 0, GF_M32 = 1, GF_M52 = 2, GF_SLATER1 = 3, GF_GAUSS = 4, GF_GENERAL = 5 };
+
+__device__ __forceinline__ int grid_fast_kind(const KernelParams& kp)
+{
+    if (kp.family == FAM_MATERN && kp.half >= 0 && kp.half <= 2) return kp.half;
+    if (kp.family == FAM_SLATER && kp.p == 1.0) return GF_SLATER1;
+    if (kp.family == FAM_GAUSS) return GF_GAUSS;
+    return GF_GENERAL;
+}
+
+template <int KIND>
+__device__ __forceinline__ float grid_value_f32(const KernelParams& kp, double r2)
+{
+    if (KIND == GF_GENERAL) return (float)cov_value_for_float(kp, r2);
+    double r = 0.0;
+    if (r2 > 0.0) {
+        double y = __builtin_amdgcn_rsq(r2);
+        y = y * fma(-0.5 * r2 * y, y, 1.5);
+        r = r2 * y;
+    }
+    const double t = r * kp.inv_len;
+    const double sg = kp.sigma2;
+    if (KIND == GF_M12) return poly_exp_neg_f32(t, sg, 0.0, 0.0);
+    if (KIND == GF_M32) return poly_exp_neg_f32(t, sg, sg, 0.0);
+    if (KIND == GF_M52) return poly_exp_neg_f32(t, sg, sg, sg * (1.0 / 3.0));
+    if (KIND == GF_SLATER1) return poly_exp_neg_f32(kp.alpha * t, sg, 0.0, 0.0);
+    return poly_exp_neg_f32(t * t, sg, 0.0, 0.0);
+}
+
+template <int KIND>
+__device__ __forceinline__ void grid_row_f32(float* __restrict__ dst, float* __restrict__ dst2, const GridAxes& g,
+                                             const KernelParams& kp, double xy, int qpr, int lane)
+{
+    const int n2 = g.n[2];
+    const bool vec = (n2 & 3) == 0;
+    for (int q = lane; q < qpr; q += 64) {
+        const int i2 = 4 * q;
+        float out[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const double z = (g.x0[2] + (double)(i2 + t) * g.h[2]) * kp.axs[2];
+            out[t] = grid_value_f32<KIND>(kp, xy + z * z);
+        }
+        if (vec) {
+            const f32x4 v = {out[0], out[1], out[2], out[3]};
+            *reinterpret_cast<f32x4*>(dst + i2) = v;
+            if (dst2) *reinterpret_cast<f32x4*>(dst2 + i2) = v;
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (i2 + t < n2) {
+                    dst[i2 + t] = out[t];
+                    if (dst2) dst2[i2 + t] = out[t];
+                }
+        }
+    }
+}
+
+// Float storage.  Block (x, y) takes the two i0-planes x and n0 - 1 - x (together n1 + 1 rows
+// under the symmetry, so every block has the same work) and its 4 waves rows i1 = lo + 4 y + w,
+// stepping by 4 gridDim.y, where lo = i0 with the symmetry (rows i1 >= i0 only) and 0 without.
+template <int KIND>
+__device__ __forceinline__ void grid_rows_f32(float* __restrict__ A, const GridAxes& g, const KernelParams& kp,
+                                              int qpr, int sym, int lane)
+{
+    const int wv = __builtin_amdgcn_readfirstlane((int)blockIdx.y * 4 + (int)(threadIdx.x >> 6));
+    const int nw = (int)gridDim.y * 4;
+    const int n0 = g.n[0], n1 = g.n[1];
+    for (int h = 0; h < 2; ++h) {
+        const int i0 = h == 0 ? (int)blockIdx.x : n0 - 1 - (int)blockIdx.x;
+        if (h == 1 && i0 <= (int)blockIdx.x) break;   // the middle plane of an odd n0: once
+        const double x = (g.x0[0] + (double)i0 * g.h[0]) * kp.axs[0];
+        for (int i1 = (sym ? i0 : 0) + wv; i1 < n1; i1 += nw) {
+            const double y = (g.x0[1] + (double)i1 * g.h[1]) * kp.axs[1];
+            const double xy = x * x + y * y;
+            float* dst = A + ((long)i0 * n1 + i1) * g.n[2];
+            float* dst2 = (sym && i0 != i1) ? A + ((long)i1 * n1 + i0) * g.n[2] : nullptr;
+            grid_row_f32<KIND>(dst, dst2, g, kp, xy, qpr, lane);
+        }
+    }
+}
+
+// GENERAL: also the families without a closed form (kept out of the closed-form instance, whose
+// register count they would raise).
+template <bool GENERAL>
+__global__ void __launch_bounds__(256) k_grid_eval_f32(float* __restrict__ A, GridAxes g, KernelParamsBatch kps,
+                                                       int qpr, int sym, long bs)
+{
+    A = bshift(A, bs);
+    const KernelParams& kp = kps.k[blockIdx.z];
+    const int lane = threadIdx.x & 63;
+    switch (grid_fast_kind(kp)) {
+    case GF_M12: grid_rows_f32<GF_M12>(A, g, kp, qpr, sym, lane); break;
+    case GF_M32: grid_rows_f32<GF_M32>(A, g, kp, qpr, sym, lane); break;
+    case GF_M52: grid_rows_f32<GF_M52>(A, g, kp, qpr, sym, lane); break;
+    case GF_SLATER1: grid_rows_f32<GF_SLATER1>(A, g, kp, qpr, sym, lane); break;
+    case GF_GAUSS: grid_rows_f32<GF_GAUSS>(A, g, kp, qpr, sym, lane); break;
+    default:
+        if constexpr (GENERAL) grid_rows_f32<GF_GENERAL>(A, g, kp, qpr, sym, lane);
+        break;
+    }
+}
+
+// Launch shape of k_grid_eval_f32: ceil(n0/2) plane pairs, and about 8192 waves in all.
+static dim3 grid_f32_shape(const GridAxes& g, int nb)
+{
+    const int pairs = (g.n[0] + 1) / 2;
+    int sy = (2048 + pairs - 1) / pairs;
+    const int cap = (g.n[1] + 3) / 4;
+    if (sy > cap) sy = cap;
+    if (sy < 1) sy = 1;
+    return dim3((unsigned)pairs, (unsigned)sy, (unsigned)nb);
+}
+
+static bool grid_general(const KernelParams* kps, int nb)
+{
+    for (int b = 0; b < nb; ++b) {
+        const KernelParams& k = kps[b];
+        const bool fast = (k.family == FAM_MATERN && k.half >= 0 && k.half <= 2) ||
+                          (k.family == FAM_SLATER && k.p == 1.0) || k.family == FAM_GAUSS;
+        if (!fast) return true;
+    }
+    return false;
+}
+
+static int grid_symmetric(const GridAxes& g, const KernelParams* kps, int nb)
+{
+    if (g.n[0] != g.n[1] || g.x0[0] != g.x0[1] || g.h[0] != g.h[1]) return 0;
+    for (int b = 0; b < nb; ++b)
+        if (kps[b].axs[0] != kps[b].axs[1]) return 0;
+    return 1;
+}
+
+static hipError_t launch_f32(float* A, const GridAxes& g, const KernelParams* kps, hipStream_t s, Bat bt)
+{
+    if (bt.nb < 1 || bt.nb > BATCH_MAX) return hipErrorInvalidValue;
+    KernelParamsBatch kb{};
+    for (int b = 0; b < bt.nb; ++b) kb.k[b] = kps[b];
+    const int qpr = (g.n[2] + 3) / 4;
+    const int sym = grid_symmetric(g, kps, bt.nb);
+    const dim3 grid = grid_f32_shape(g, bt.nb);
+    if (grid_general(kps, bt.nb))
+        hipLaunchKernelGGL(k_grid_eval_f32<true>, grid, dim3(256), 0, s, A, g, kb, qpr, sym, bt.bs);
+    else
+        hipLaunchKernelGGL(k_grid_eval_f32<false>, grid, dim3(256), 0, s, A, g, kb, qpr, sym, bt.bs);
+    return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t launch(T* A, const GridAxes& g, const KernelParams* kps, hipStream_t s, Bat bt)
 {
@@ -103,7 +271,25 @@ static void node_params(T* A, const GridAxes& g, const KernelParams* kps, Bat bt
 
 void grid_eval_node_f32(float* A, const GridAxes& g, const KernelParams* kps, Bat bt, GridEvalNode* nd)
 {
-    node_params(A, g, kps, bt, nd);
+    nd->A = A;
+    nd->g = g;
+    for (int b = 0; b < bt.nb; ++b) nd->kps.k[b] = kps[b];
+    nd->qpr = (g.n[2] + 3) / 4;
+    nd->sym = grid_symmetric(g, kps, bt.nb);
+    nd->bs = bt.bs;
+    nd->args[0] = &nd->A;
+    nd->args[1] = &nd->g;
+    nd->args[2] = &nd->kps;
+    nd->args[3] = &nd->qpr;
+    nd->args[4] = &nd->sym;
+    nd->args[5] = &nd->bs;
+    nd->p.func = grid_general(kps, bt.nb) ? reinterpret_cast<void*>(&k_grid_eval_f32<true>)
+                                          : reinterpret_cast<void*>(&k_grid_eval_f32<false>);
+    nd->p.gridDim = grid_f32_shape(g, bt.nb);
+    nd->p.blockDim = dim3(256);
+    nd->p.sharedMemBytes = 0;
+    nd->p.kernelParams = nd->args;
+    nd->p.extra = nullptr;
 }
 
 void grid_eval_node_f64(double* A, const GridAxes& g, const KernelParams* kps, Bat bt, GridEvalNode* nd)
@@ -113,7 +299,7 @@ void grid_eval_node_f64(double* A, const GridAxes& g, const KernelParams* kps, B
 
 hipError_t launch_grid_eval_f32(float* A, const GridAxes& g, const KernelParams* kps, hipStream_t s, Bat bt)
 {
-    return launch(A, g, kps, s, bt);
+    return launch_f32(A, g, kps, s, bt);
 }
 
 hipError_t launch_grid_eval_f64(double* A, const GridAxes& g, const KernelParams* kps, hipStream_t s, Bat bt)

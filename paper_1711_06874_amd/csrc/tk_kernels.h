@@ -39,11 +39,12 @@ hipError_t launch_grid_eval_f64(double* A, const GridAxes& g, const KernelParams
 // update call.
 struct GridEvalNode {
     hipKernelNodeParams p;
-    void* args[6];
+    void* args[7];
     void* A;
     GridAxes g;
     KernelParamsBatch kps;
-    long total;
+    long total;      // double storage: quads of 4 elements
+    int sym;         // float storage: whether rows (i0, i1), (i1, i0) coincide
     int qpr;
     long bs;
 };

@@ -3,6 +3,8 @@
     python -m paper_1711_06874_amd.profile_driver copy --bytes 1073741824
         five plain device-to-device copies of that many bytes (the scale of FETCH_SIZE and
         WRITE_SIZE per byte moved)
+    python -m paper_1711_06874_amd.profile_driver fill --bytes 67108864
+        plain fills of a float buffer of that many bytes (the write-only rate of the device)
     python -m paper_1711_06874_amd.profile_driver gram --n 512 --prec fp32
         the three mode Grams (tk_gram) of the Matern 3/2 (ell = 0.2) tensor on the centred n^3
         grid, --reps times each
@@ -22,7 +24,7 @@ import time
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["copy", "gram", "grid"])
+    ap.add_argument("what", choices=["copy", "fill", "gram", "grid"])
     ap.add_argument("--bytes", type=int, default=1 << 30)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--prec", choices=["fp64", "fp32", "bf16x3"], default="fp32")
@@ -39,6 +41,13 @@ def main(argv=None):
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": args.bytes, "reps": args.reps}), flush=True)
+        return 0
+    if args.what == "fill":
+        x = torch.empty(args.bytes // 4, dtype=torch.float32, device="cuda")
+        for i in range(args.reps):
+            x.fill_(float(i))
+        torch.cuda.synchronize()
+        print(json.dumps({"fill_bytes": args.bytes, "reps": args.reps}), flush=True)
         return 0
     prec = {"fp64": tk.TK_FP64, "fp32": tk.TK_FP32, "bf16x3": tk.TK_BF16X3}[args.prec]
     ctx = tk.Context(0)

@@ -40,9 +40,9 @@ KERNELS = [
 
 @pytest.mark.parametrize("name,kw", KERNELS)
 @pytest.mark.parametrize("layout", [0, 1])
-def test_grid_eval(ctx, tk, oracle, name, kw, layout):
-    n = (37, 70, 67)
-    b = (1.0, 0.8, 1.3)
+@pytest.mark.parametrize("n,b", [((37, 70, 67), (1.0, 0.8, 1.3)),     # every row evaluated
+                                 ((66, 66, 45), (0.9, 0.9, 1.2))])    # rows (i0,i1), (i1,i0) shared
+def test_grid_eval(ctx, tk, oracle, name, kw, layout, n, b):
     say("grid_eval", name, layout, n)
     A = oracle.grid_eval(oracle.Kernel(**kw), oracle.Grid(n=n, b=b, layout=layout))
     k = tk.make_kernel(**kw)
@@ -57,13 +57,24 @@ def test_grid_eval(ctx, tk, oracle, name, kw, layout):
     s_exp = -np.log(np.maximum(np.abs(A) / sigma2, 1e-300))
     rtol = 2e-14 + 8 * 2.220446049250313e-16 * s_exp
     assert np.all(np.abs(got - A) <= rtol * np.abs(A) + 1e-300)
+    _check_f32(ctx, tk, k, g, n, A)
+
+
+def _check_f32(ctx, tk, k, g, n, A):
+    """Float storage against the oracle rounded to float.  The closed forms take exp(-s) as
+    2^k 2^f with 2^f (in [0.70, 1.42]) from the hardware FP32 exp2 of f: its 1 ulp is at most
+    2^-23 relative; rounding f (|f| <= 1/2) to float moves 2^f by at most ln2 2^-26 relative; the
+    final rounding to float adds at most 2^-24 relative.  So the value is within 3.2 * 2^-24 of the
+    exact one, and the oracle rounded to float within 2^-24.  Bound: 4.25 * 2^-24 |A|, plus two
+    subnormal spacings where the values leave the normal range."""
     d32 = torch.empty(n, dtype=torch.float32, device="cuda")
     tk.tk_grid_eval(ctx.handle, k, g, tk.TK_FP32, d32)
-    g32 = host(d32)
-    ref32 = A.astype(np.float32)
-    # rounded once from double: at most one unit in the last place from the oracle rounded
-    ulp = np.spacing(np.abs(ref32))
-    assert np.all(np.abs(g32.astype(np.float64) - ref32.astype(np.float64)) <= ulp)
+    g32 = host(d32).astype(np.float64)
+    ref32 = A.astype(np.float32).astype(np.float64)
+    err = np.abs(g32 - ref32)
+    bound = 4.25 * 2.0 ** -24 * np.abs(ref32) + 2.0 ** -148
+    say("  FP32 max err / bound %.3f, %.4f of the values equal" % (float(np.max(err / bound)), float(np.mean(err == 0))))
+    assert np.all(err <= bound)
 
 
 FAMILIES = [
@@ -92,8 +103,7 @@ def test_grid_eval_families(ctx, tk, oracle, name, kw, layout):
     oracle (which takes K_nu from its integral representation, a different algorithm).  FP64:
     both sides evaluate exp(log constant + nu log s) K_nu(s) or (alpha^2 + rho^2)^-(nu+3/2)
     through exponents of size up to ~200, each rounded once: 2e-13, plus the 8 u s of the
-    radius rounding as in test_grid_eval.  FP32: rounded once from double, so within one unit
-    in the last place of the oracle rounded to float."""
+    radius rounding as in test_grid_eval.  FP32 as in _check_f32."""
     n = (37, 70, 67)
     b = (1.0, 0.8, 1.3)
     say("grid_eval family", name, layout, n)
@@ -112,12 +122,7 @@ def test_grid_eval_families(ctx, tk, oracle, name, kw, layout):
     err = np.abs(got - A) / np.maximum(np.abs(A), 1e-300)
     say("  max rel err / tol %.3e" % np.max(err / rtol))
     assert np.all(np.abs(got - A) <= rtol * np.abs(A) + 1e-300)
-    d32 = torch.empty(n, dtype=torch.float32, device="cuda")
-    tk.tk_grid_eval(ctx.handle, k, g, tk.TK_FP32, d32)
-    g32 = host(d32)
-    ref32 = A.astype(np.float32)
-    ulp = np.spacing(np.abs(ref32))
-    assert np.all(np.abs(g32.astype(np.float64) - ref32.astype(np.float64)) <= ulp)
+    _check_f32(ctx, tk, k, g, n, A)
 
 
 # (256, 288, 32) and (64, 32, 320): FP32 modes with n_mode >= 256 take the large-tile kernel
