@@ -189,6 +189,24 @@ tk_status tk_compress_tensor(tk_ctx *ctx, const void *A_dev, const tk_grid *grid
 tk_status tk_compress_multigrid(tk_ctx *ctx, const tk_kernel *kernel, const tk_grid *grid, int levels,
                                 const tk_opts *opts, void *hip_stream, tk_tucker **out);
 
+/* Sinc-quadrature canonical tensor and canonical-to-Tucker (Sec. 3.4; Laplace weights of
+ * Sec. 3.5).  For a Matern covariance of order nu in {1/2, 3/2, 5/2} (isotropic distance) the
+ * Laplace representation C(r) = sigma2 int_0^inf omega(t) exp(-r^2 t) dt is discretised by the
+ * sinc rule on t = (c^2/4) e^u, c = sqrt(2 nu)/ell, with step h = C0 log(M)/M at u = k h,
+ * k = -M..M: a canonical tensor of rank R = 2M + 1 whose side matrices are
+ * Q_l[i][k] = w_k^(1/3) exp(-t_k x_{l,i}^2) on the grid's nodes.  Its Tucker form: factors from
+ * the leading ranks[l] eigenvectors of Q_l Q_l^T (reduced HOSVD), then `sweeps` ALS sweeps on the
+ * canonical data (single-hole Gram Q_a (P_j^T P_j o P_m^T P_m) Q_a^T, P_l = V_l^T Q_l), core
+ * G = sum_k (V_1^T q_1k) (x) (V_2^T q_2k) (x) (V_3^T q_3k).  Everything runs on products of the
+ * n_l x R side matrices (FP64); the n1 n2 n3 tensor is never formed.  The result's rel_err is
+ * ||CP - T|| / ||CP|| against the canonical tensor (from ||CP||^2 - ||G||^2, so values below
+ * about 1e-7 are not resolved) and norm_a is ||CP||.  ranks are clamped to n_l and R; 1 <= M <= 256,
+ * C0 > 0, 0 <= sweeps <= 50.  Synchronising.  Errors: TK_EINVAL, TK_EUNSUPPORTED (another family
+ * or order, an anisotropic metric, a rank above 48), TK_ENOMEM, TK_EHIP, TK_ENOCONV (an
+ * eigensolve missed its residual test; the result is returned). */
+tk_status tk_compress_sinc(tk_ctx *ctx, const tk_kernel *kernel, const tk_grid *grid, int M, double C0,
+                           const int ranks[3], int sweeps, void *hip_stream, tk_tucker **out);
+
 /* Compress `count` independent problems (kernels[i] on grids[i], sizes may differ, all with
  * *opts) in one call.  Problems on the same grid share their launches: up to 32 of them (fewer
  * if the HBM budget asks; a group is also split into near-equal parts of at least three

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libtk.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["k_grid.hip", "k_gram.hip", "k_small.hip", "k_eig.hip", "k_ttm.hip", "k_kron.hip",
-           "k_rank.hip", "k_fft.hip", "k_chol.hip", "k_rng.hip", "tk_api.cpp", "tk_server.cpp"]
+           "k_rank.hip", "k_fft.hip", "k_chol.hip", "k_rng.hip", "k_sinc.hip", "tk_api.cpp", "tk_server.cpp"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wno-unused-value",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", CSRC, "-I", INCLUDE]

@@ -510,8 +510,9 @@ int big_splits(int npairs, int per_cu)
     return s > 8 ? s : 8;
 }
 
-// Large-tile plan: nsplit a multiple of 8 (default: three work-groups per CU; a requested split
-// count is rounded up to a multiple of 8).
+// Large-tile plan: nsplit a multiple of 8 (default: three work-groups per CU, capped so that the
+// partials hold at most a quarter of the tensor's elements; a requested split count is rounded up
+// to a multiple of 8).
 GramPlan make_plan_big(const int n[3], int mode, int nsplit_req = 0)
 {
     GramPlan p;
@@ -520,7 +521,14 @@ GramPlan make_plan_big(const int n[3], int mode, int nsplit_req = 0)
     p.K = N / n[mode];
     p.T_tiles = (p.nrow + BG - 1) / BG;
     p.npairs = p.T_tiles * (p.T_tiles + 1) / 2;
-    long s = nsplit_req > 0 ? nsplit_req : big_splits(p.npairs, 3);
+    long s = nsplit_req;
+    if (s <= 0) {
+        // three work-groups per CU, but no more split partials than a quarter of the tensor
+        // (their write and read-back in the reduction would cost more than the extra parallelism)
+        s = big_splits(p.npairs, 3);
+        const long cap = (N / (4L * p.npairs * BG * BG)) / 8 * 8;
+        if (s > cap) s = cap > 8 ? cap : 8;
+    }
     s = (s + 7) / 8 * 8;
     const long maxs = (p.K + BKG - 1) / BKG;
     if (s > (maxs + 7) / 8 * 8) s = (maxs + 7) / 8 * 8;

@@ -2293,6 +2293,163 @@ tk_status tk_compress_multigrid(tk_ctx* ctx, const tk_kernel* kernel, const tk_g
     return st;
 }
 
+// Sec. 3.4: the sinc-quadrature canonical tensor of a half-integer Matern (R = 2M + 1 terms,
+// side matrices Q_l) and its Tucker form by canonical-to-Tucker: the RHOSVD start (leading
+// eigenvectors of Q_l Q_l^T) and `sweeps` ALS sweeps on the canonical data, where the
+// single-hole Gram of mode a is Q_a (P_j^T P_j o P_m^T P_m) Q_a^T with P_l = V_l^T Q_l; core
+// G_(0) = P_0 KR(P_1, P_2); error against the canonical tensor from ||CP||^2 - ||G||^2.  No full
+// tensor is formed: everything is a product of the n_l x R side matrices.
+tk_status tk_compress_sinc(tk_ctx* ctx, const tk_kernel* kernel, const tk_grid* grid, int M, double C0,
+                           const int ranks[3], int sweeps, void* hip_stream, tk_tucker** out)
+{
+    if (!ctx || !kernel || !grid || !ranks || !out) return fail(TK_EINVAL, "NULL argument");
+    *out = nullptr;
+    tk_status st;
+    if ((st = check_grid(grid)) != TK_OK) return st;
+    KernelParams kp{};
+    if ((st = check_kernel(kernel, &kp)) != TK_OK) return st;
+    if (kernel->family != TK_MATERN || kp.half < 0)
+        return fail(TK_EUNSUPPORTED, "sinc canonical tensor: Matern nu in {1/2, 3/2, 5/2} only");
+    if (kp.axs[0] != 1.0 || kp.axs[1] != 1.0 || kp.axs[2] != 1.0)
+        return fail(TK_EUNSUPPORTED, "sinc canonical tensor: isotropic distance only");
+    if (M < 1 || M > 256) return fail(TK_EINVAL, "M=%d: 1..256", M);
+    if (!std::isfinite(C0) || C0 <= 0) return fail(TK_EINVAL, "C0 must be finite and > 0");
+    if (sweeps < 0 || sweeps > CONVERGE_MAX_SWEEPS) return fail(TK_EINVAL, "sweeps=%d: 0..%d", sweeps, CONVERGE_MAX_SWEEPS);
+    const int R = 2 * M + 1;
+    int r[3];
+    for (int k = 0; k < 3; ++k) {
+        r[k] = ranks[k];
+        if (r[k] < 1) return fail(TK_EINVAL, "ranks[%d]=%d", k, r[k]);
+        r[k] = std::min(r[k], std::min(grid->n[k], R));
+        if (r[k] > LIB_RMAX) return fail(TK_EUNSUPPORTED, "rank %d exceeds %d", r[k], LIB_RMAX);
+    }
+    TK_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int* n = grid->n;
+    const int nmax = std::max(n[0], std::max(n[1], n[2]));
+    const int rmax = std::max(r[0], std::max(r[1], r[2]));
+    const int pmax = (nmax <= EIG_PMAX) ? nmax : std::min(rmax + 8, EIG_PMAX);
+    double *t, *w, *Q[3], *Gq[3], *S, *P[3], *Ga, *Gb, *Wg, *T1, *KR, *core, *V[3], *eQ, *eY, *eH, *eVs, *lam, *scal;
+    int* eflags;
+    auto lay = [&](Arena& ar) {
+        t = ar.take<double>(R);
+        w = ar.take<double>(R);
+        for (int k = 0; k < 3; ++k) Q[k] = ar.take<double>((size_t)n[k] * R);
+        for (int k = 0; k < 3; ++k) Gq[k] = ar.take<double>((size_t)R * R);
+        S = ar.take<double>((size_t)nmax * nmax);
+        for (int k = 0; k < 3; ++k) P[k] = ar.take<double>((size_t)r[k] * R);
+        Ga = ar.take<double>((size_t)R * R);
+        Gb = ar.take<double>((size_t)R * R);
+        Wg = ar.take<double>((size_t)R * R);
+        T1 = ar.take<double>((size_t)nmax * R);
+        KR = ar.take<double>((size_t)R * r[1] * r[2]);
+        core = ar.take<double>((size_t)r[0] * r[1] * r[2]);
+        for (int k = 0; k < 3; ++k) V[k] = ar.take<double>((size_t)n[k] * r[k]);
+        eQ = ar.take<double>((size_t)nmax * pmax);
+        eY = ar.take<double>((size_t)nmax * pmax);
+        eH = ar.take<double>((size_t)pmax * pmax);
+        eVs = ar.take<double>((size_t)pmax * pmax);
+        lam = ar.take<double>(64);
+        scal = ar.take<double>(16);
+        eflags = ar.take<int>(64);
+    };
+    Arena plan;
+    lay(plan);
+    Reservation res(ctx, plan.off);
+    if (!res.take()) return fail(TK_ENOMEM, "sinc compression needs %zu bytes", plan.off);
+    Ws wsp;
+    TK_HIP(ws_get(ctx, s, 0, plan.off, wsp));
+    Arena ar;
+    ar.base = (char*)wsp.p;
+    lay(ar);
+    Work wk{};
+    wk.ctx = ctx;
+    wk.eflags = eflags;
+    // leading r_a eigenvectors of the n_a x n_a matrix S into V[a] (FP64, iterated to the
+    // residual test like every FP64 eigensolve)
+    auto eig_into = [&](int a) -> tk_status {
+        EigBatch b{};
+        b.count = 1; b.n = n[a]; b.r = r[a];
+        b.p = (n[a] <= EIG_PMAX) ? n[a] : std::min(r[a] + 8, EIG_PMAX);
+        b.G = S; b.sG = (long)n[a] * n[a];
+        b.Q = eQ; b.Y = eY; b.H = eH; b.Vs = eVs;
+        b.U = V[a]; b.sU = (long)n[a] * r[a]; b.ldu = r[a];
+        b.lam = lam; b.sL = 64;
+        TK_LAUNCH(launch_eig(b, COLD_ITERS, s));
+        return eig_converge(b, wk, s);
+    };
+    const double h = C0 * std::log((double)M) / (double)M;
+    const double c = kp.inv_len;            // sqrt(2 nu) / ell
+    TK_LAUNCH(launch_sinc_nodes(M, h, c, kp.half, kp.sigma2, t, w, s));
+    const GridAxes ax = axes_of(grid);
+    TK_LAUNCH(launch_sinc_factors(ax, R, t, w, Q, s));
+    // RHOSVD start: S = Q_a Q_a^T
+    for (int a = 0; a < 3; ++a) {
+        GemmArgs g = gemm(n[a], n[a], R, 1, Q[a], 0, R, 1, Q[a], 0, 1, R, S, 0, n[a], 1);
+        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+        if ((st = eig_into(a)) != TK_OK) return st;
+    }
+    // P_l = V_l^T Q_l (r_l x R)
+    auto project = [&](int l) -> tk_status {
+        GemmArgs g = gemm(r[l], R, n[l], 1, V[l], 0, 1, r[l], Q[l], 0, R, 1, P[l], 0, R, 1);
+        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+        return TK_OK;
+    };
+    for (int l = 0; l < 3; ++l)
+        if ((st = project(l)) != TK_OK) return st;
+    for (int sw = 0; sw < sweeps; ++sw) {
+        for (int a = 0; a < 3; ++a) {
+            const int j = a == 0 ? 1 : 0, m = a == 2 ? 1 : 2;
+            // Wg = (P_j^T P_j) o (P_m^T P_m)
+            GemmArgs gj = gemm(R, R, r[j], 1, P[j], 0, 1, R, P[j], 0, R, 1, Ga, 0, R, 1);
+            TK_LAUNCH((launch_gemm<double, double, double>(gj, s)));
+            GemmArgs gm = gemm(R, R, r[m], 1, P[m], 0, 1, R, P[m], 0, R, 1, Gb, 0, R, 1);
+            TK_LAUNCH((launch_gemm<double, double, double>(gm, s)));
+            TK_LAUNCH(launch_hadamard(Ga, Gb, Wg, (long)R * R, s));
+            // S = (Q_a Wg) Q_a^T
+            GemmArgs g1 = gemm(n[a], R, R, 1, Q[a], 0, R, 1, Wg, 0, R, 1, T1, 0, R, 1);
+            TK_LAUNCH((launch_gemm<double, double, double>(g1, s)));
+            GemmArgs g2 = gemm(n[a], n[a], R, 1, T1, 0, R, 1, Q[a], 0, 1, R, S, 0, n[a], 1);
+            TK_LAUNCH((launch_gemm<double, double, double>(g2, s)));
+            if ((st = eig_into(a)) != TK_OK) return st;
+            if ((st = project(a)) != TK_OK) return st;
+        }
+    }
+    // core G_(0) = P_0 KR(P_1, P_2)
+    TK_LAUNCH(launch_khatri_rao(P[1], P[2], R, r[1], r[2], KR, s));
+    GemmArgs gc = gemm(r[0], r[1] * r[2], R, 1, P[0], 0, R, 1, KR, 0, (long)r[1] * r[2], 1, core, 0,
+                       (long)r[1] * r[2], 1);
+    TK_LAUNCH((launch_gemm<double, double, double>(gc, s)));
+    // ||CP||^2 = sum_{k,k'} prod_l (Q_l^T Q_l)[k][k'],  ||G||^2
+    for (int l = 0; l < 3; ++l) {
+        GemmArgs g = gemm(R, R, n[l], 1, Q[l], 0, 1, R, Q[l], 0, R, 1, Gq[l], 0, R, 1);
+        TK_LAUNCH((launch_gemm<double, double, double>(g, s)));
+    }
+    TK_LAUNCH(launch_triple_sum(Gq[0], Gq[1], Gq[2], (long)R * R, scal, s));
+    const long ncore = (long)r[0] * r[1] * r[2];
+    TK_LAUNCH(launch_dot<double>(core, core, ncore, scal + 4, 8, scal + 1, s));
+    double sc[2];
+    if ((st = readback(ctx, s, scal, sizeof(sc), sc)) != TK_OK) return st;
+    tk_tucker* tt = nullptr;
+    if ((st = alloc_result(ctx, n, r, s, &tt)) != TK_OK) return st;
+    for (int k = 0; k < 3; ++k) {
+        TK_LAUNCH(launch_copy_f64(V[k], tt->U[k], (long)n[k] * r[k], s, Bat()));
+        TK_LAUNCH(launch_convert_f64_to_f32(tt->U[k], tt->U32[k], (long)n[k] * r[k], s, Bat()));
+    }
+    TK_LAUNCH(launch_copy_f64(core, tt->core, ncore, s, Bat()));
+    TK_LAUNCH(launch_convert_f64_to_f32(tt->core, tt->core32, ncore, s, Bat()));
+    TK_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < 3; ++k) tt->b[k] = grid->b[k];
+    tt->layout = grid->layout;
+    tt->prec = TK_FP64;
+    tt->norm_a = std::sqrt(sc[0]);
+    tt->rel_err = std::sqrt(std::max(sc[0] - sc[1], 0.0) / sc[0]);
+    *out = tt;
+    if (wk.noconv) return fail(TK_ENOCONV, "sinc compression: an eigensolve did not pass its residual test");
+    return TK_OK;
+}
+
 tk_status tk_compress_group(tk_ctx* ctx, int count, const tk_kernel* kernels, const tk_grid* grid,
                             const tk_opts* opts, void* hip_stream, tk_tucker** outs, int* statuses)
 {

@@ -262,4 +262,18 @@ hipError_t launch_philox_words(uint32_t k0, uint32_t k1, unsigned long long c0, 
 // z[e] for e < count: the Box-Muller normals of blocks 0 .. ceil(count / 2) - 1 (k_rng.hip).
 hipError_t launch_philox_normal(uint32_t k0, uint32_t k1, long count, float* z, hipStream_t s);
 
+// ------------------------------------- sinc-quadrature canonical tensor (k_sinc.hip) ----
+// t_k, w_k (k = 0..2M) of the R = 2M + 1 term sinc rule for the Matern of order half + 1/2
+// with c = sqrt(2 nu)/ell, step h.
+hipError_t launch_sinc_nodes(int M, double h, double c, int half, double sigma2, double* t, double* w, hipStream_t s);
+// Side matrices Q_l (n_l x R, row-major): Q_l[i][k] = w_k^(1/3) exp(-t_k x_{l,i}^2).
+hipError_t launch_sinc_factors(const GridAxes& g, int R, const double* t, const double* w, double* const Q[3],
+                               hipStream_t s);
+// C = A o B (n elements)
+hipError_t launch_hadamard(const double* A, const double* B, double* C, long n, hipStream_t s);
+// KR (R x r1 r2) with KR[k][b r2 + c] = P1[b][k] P2[c][k]
+hipError_t launch_khatri_rao(const double* P1, const double* P2, int R, int r1, int r2, double* KR, hipStream_t s);
+// out[0] = sum_e A[e] B[e] C[e] (fixed order)
+hipError_t launch_triple_sum(const double* A, const double* B, const double* C, long n, double* out, hipStream_t s);
+
 }  // namespace tk

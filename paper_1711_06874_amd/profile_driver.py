@@ -10,6 +10,9 @@
         grid, --reps times each
     python -m paper_1711_06874_amd.profile_driver grid --n 256
         FP32 grid evaluation of the 256^3 offset Matern grid (tk_grid_eval), --reps times
+    python -m paper_1711_06874_amd.profile_driver compress --n 256 --prec fp32
+        single compressions (tk_compress, Matern 3/2, ell = 0.3, eps 1e-6, two sweeps) of the
+        offset n^3 grid, --reps times, each timed on the host
 
 Every kernel runs in the library; the driver only allocates device memory and prints one line
 per step.
@@ -24,7 +27,7 @@ import time
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["copy", "fill", "gram", "grid"])
+    ap.add_argument("what", choices=["copy", "fill", "gram", "grid", "compress"])
     ap.add_argument("--bytes", type=int, default=1 << 30)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--prec", choices=["fp64", "fp32", "bf16x3"], default="fp32")
@@ -52,6 +55,21 @@ def main(argv=None):
     prec = {"fp64": tk.TK_FP64, "fp32": tk.TK_FP32, "bf16x3": tk.TK_BF16X3}[args.prec]
     ctx = tk.Context(0)
     n = args.n
+    if args.what == "compress":
+        kern = tk.make_kernel(tk.TK_MATERN, nu=1.5, ell=0.3)
+        grid = tk.make_grid(n, 1.0, tk.TK_OFFSET)
+        opts = tk.make_opts(eps=1e-6, hooi_sweeps=2, prec=prec)
+        ms = []
+        for _ in range(args.reps):
+            t0 = time.perf_counter()
+            t = ctx.compress(kern, grid, opts)
+            ms.append((time.perf_counter() - t0) * 1e3)
+            t.free()
+        ms.sort()
+        print(json.dumps({"compress": n, "prec": args.prec, "reps": args.reps, "ms_p50": ms[len(ms) // 2],
+                          "ms_min": ms[0]}), flush=True)
+        ctx.destroy()
+        return 0
     if args.what == "grid":
         kern = tk.make_kernel(tk.TK_MATERN, nu=1.5, ell=0.3)
         grid = tk.make_grid(n, 1.0, tk.TK_OFFSET)

@@ -75,6 +75,8 @@ _SIGS = {
                                  ctypes.POINTER(_vp)]),
     "tk_compress_multigrid": (_st, [_vp, ctypes.POINTER(tk_kernel), ctypes.POINTER(tk_grid), ctypes.c_int,
                                     ctypes.POINTER(tk_opts), _vp, ctypes.POINTER(_vp)]),
+    "tk_compress_sinc": (_st, [_vp, ctypes.POINTER(tk_kernel), ctypes.POINTER(tk_grid), ctypes.c_int,
+                               ctypes.c_double, _ip, ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
     "tk_compress_group": (_st, [_vp, ctypes.c_int, ctypes.POINTER(tk_kernel), ctypes.POINTER(tk_grid),
                                 ctypes.POINTER(tk_opts), _vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int)]),
     "tk_compress_batch": (_st, [_vp, ctypes.c_int, ctypes.POINTER(tk_kernel), ctypes.POINTER(tk_grid),
@@ -236,6 +238,16 @@ def tk_compress_tensor(ctx: int, A, grid: tk_grid, opts: tk_opts, stream=None, a
     st = _lib.tk_compress_tensor(ctx, _ptr(A), ctypes.byref(grid), ctypes.byref(opts), _stream(stream),
                                  ctypes.byref(out))
     _check_result(st, out, "tk_compress_tensor", allow_noconv)
+    return out.value
+
+
+def tk_compress_sinc(ctx: int, kernel: tk_kernel, grid: tk_grid, M: int, C0: float, ranks, sweeps: int = 0,
+                     stream=None, allow_noconv=False):
+    out = _vp()
+    rk = (ctypes.c_int * 3)(*([int(ranks)] * 3 if isinstance(ranks, int) else [int(x) for x in ranks]))
+    st = _lib.tk_compress_sinc(ctx, ctypes.byref(kernel), ctypes.byref(grid), int(M), float(C0), rk, int(sweeps),
+                               _stream(stream), ctypes.byref(out))
+    _check_result(st, out, "tk_compress_sinc", allow_noconv)
     return out.value
 
 
@@ -461,6 +473,9 @@ class Context:
 
     def compress_multigrid(self, kernel, grid, levels, opts, stream=None, allow_noconv=False) -> Tucker:
         return Tucker(tk_compress_multigrid(self.handle, kernel, grid, levels, opts, stream, allow_noconv), self)
+
+    def compress_sinc(self, kernel, grid, M, C0, ranks, sweeps=0, stream=None, allow_noconv=False) -> Tucker:
+        return Tucker(tk_compress_sinc(self.handle, kernel, grid, M, C0, ranks, sweeps, stream, allow_noconv), self)
 
     def compress_tensor(self, A, grid, opts, stream=None, allow_noconv=False) -> Tucker:
         return Tucker(tk_compress_tensor(self.handle, A, grid, opts, stream, allow_noconv), self)
