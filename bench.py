@@ -299,7 +299,9 @@ def main():
         "roofline": roofline,
         "compress": compress_out,
         "kernels": kernels_out,
-        "gram_autotune": {"nsplit_per_mode": list(tuned["nsplit"]), "ms_per_mode": list(tuned["ms"])},
+        "gram_autotune": {"tile_per_mode": [128 if c >= (1 << 20) else 64 for c in tuned["nsplit"]],
+                          "nsplit_per_mode": [c % (1 << 20) for c in tuned["nsplit"]],
+                          "ms_per_mode": list(tuned["ms"])},
     }
     ctx.destroy()
     if not args.no_cpu_baseline:

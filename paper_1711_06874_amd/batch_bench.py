@@ -2,7 +2,7 @@
 eps = 1e-6, as one batch call and as 256 sequential single calls, one JSON line per form.
 
     python -m paper_1711_06874_amd.batch_bench [--count 256] [--workers 4 8] [--prec fp32]
-                                               [--no-seq] [--profile]
+                                               [--no-seq] [--profile] [--autotune] [--graphs]
 
 Per tensor (seeded, in order): n uniform over {32, 48, 64, 96, 128, 192, 256}, nu uniform over
 {1/2, 3/2, 5/2}, ell log-uniform on [0.05, 1], sigma2 = 1, centred grid on [-1, 1]^3; HOSVD,
@@ -48,7 +48,9 @@ def main():
     ap.add_argument("--reps", type=int, default=3, help="timed batch calls per worker count")
     ap.add_argument("--no-seq", action="store_true", help="skip the 256 sequential calls")
     ap.add_argument("--profile", action="store_true", help="per-class kernel times of one batch call")
-    ap.add_argument("--autotune", action="store_true", help="tune the Gram split of every size first")
+    ap.add_argument("--autotune", action="store_true", help="tune the Gram kernel and split of every size first")
+    ap.add_argument("--graphs", action="store_true", help="replay the captured compression pipeline of every "
+                    "shape (tk_ctx_set_graphs)")
     args = ap.parse_args()
 
     import torch
@@ -69,7 +71,10 @@ def main():
               "bound_ms": bound_ms,
               "workload": "256 Matern tensors, n uniform over {32,...,256}, centred grids, eps 1e-6"}
     ctx = tk.Context(0)
+    common["graphs"] = bool(args.graphs)
     try:
+        if args.graphs:
+            ctx.set_graphs(True)
         if args.autotune:
             common["gram_autotune"] = {str(n): ctx.autotune(tk.make_grid(n, 1.0, 0), prec)["nsplit"]
                                        for n in sorted(set(sizes))}

@@ -11,7 +11,8 @@
 // every entry in split order in FP64 and writes both G[i][j] and G[j][i] (diagonal tiles are
 // mirrored from their upper half), so the result is deterministic and exactly symmetric.
 //
-// Large FP32 grids (every n_k a multiple of 32 and the mode's n_k >= 256) take k_gram_big:
+// Large FP32 grids (every n_k a multiple of 32 and, by default, the mode's n_k >= 256; from 128
+// on when the autotuner finds it faster) take k_gram_big:
 // 128 x 128 tiles, each wave a 64 x 64 block (four independent 32 x 32 MFMA accumulators), K
 // chunks of 32 loaded as float4 and staged in LDS, and the splits of K given to the XCDs so
 // that all tile pairs of one split run on one XCD (its L2 holds the split's row panels once).
@@ -494,12 +495,24 @@ constexpr int BK_F32 = 32, BK_F64 = 16, BK_BF = 32;
 
 int bk_for(int prec) { return prec == 0 ? BK_F64 : (prec == 1 ? BK_F32 : BK_BF); }
 
-// The large-tile kernel takes FP32 modes with n_mode >= 256 when every extent is a multiple of
-// 32 (float4 runs and whole K chunks inside one i0 block of the mode-1 unfolding).
-bool use_big(const int n[3], int mode, int prec)
+// The large-tile kernel can take FP32 modes with n_mode >= 128 when every extent is a multiple
+// of 32 (float4 runs and whole K chunks inside one i0 block of the mode-1 unfolding); it is the
+// default from n_mode >= 256 on.  A split request ("code") of GRAM_BIG + s asks for the
+// large-tile kernel with s splits, 0 < s < GRAM_BIG for the 64-tile kernel, 0 for the default.
+bool big_eligible(const int n[3], int mode, int prec)
 {
-    return prec == 1 && n[mode] >= 256 && n[0] % 32 == 0 && n[1] % 32 == 0 && n[2] % 32 == 0;
+    return prec == 1 && n[mode] >= 128 && n[0] % 32 == 0 && n[1] % 32 == 0 && n[2] % 32 == 0;
 }
+
+bool use_big(const int n[3], int mode, int prec, int code)
+{
+    if (!big_eligible(n, mode, prec)) return false;
+    if (code >= GRAM_BIG) return true;
+    if (code > 0) return false;
+    return n[mode] >= 256;
+}
+
+int split_of(int code) { return code >= GRAM_BIG ? code - GRAM_BIG : code; }
 
 // Large-tile split count for about `per_cu` resident work-groups on each of the 256 CUs (164
 // VGPRs per lane: three waves per SIMD, so three work-groups per CU at most), rounded down to a
@@ -543,40 +556,42 @@ GramPlan make_plan_big(const int n[3], int mode, int nsplit_req = 0)
 
 int gram_default_splits(const int n[3], int mode, int prec)
 {
-    if (use_big(n, mode, prec)) return make_plan_big(n, mode).nsplit;
+    if (use_big(n, mode, prec, 0)) return GRAM_BIG + make_plan_big(n, mode).nsplit;
     return make_plan(n, mode, bk_for(prec)).nsplit;
 }
 
-int gram_split_candidates(const int n[3], int mode, int prec, int out[4])
+size_t gram_work_bytes(const int n[3], int mode, int prec, int code)
 {
-    if (use_big(n, mode, prec)) {
-        // about 3, 2 and 1 work-groups per CU (all within the default's workspace)
-        const GramPlan p = make_plan_big(n, mode);
-        int c = 0;
-        for (int per = 3; per >= 1; --per) {
-            const GramPlan q = make_plan_big(n, mode, big_splits(p.npairs, per));
-            if (q.nsplit <= p.nsplit && (c == 0 || q.nsplit != out[c - 1])) out[c++] = q.nsplit;
-        }
-        return c;
-    }
-    const int s0 = make_plan(n, mode, bk_for(prec)).nsplit;
-    int c = 0;
-    for (int d = 1; d <= 4; d *= 2) {
-        const int v = s0 / d > 1 ? s0 / d : 1;
-        if (c == 0 || v != out[c - 1]) out[c++] = v;
-    }
-    return c;
-}
-
-size_t gram_work_bytes(const int n[3], int mode, int prec, int nsplit)
-{
-    if (use_big(n, mode, prec)) {
-        GramPlan p = make_plan_big(n, mode, nsplit);
+    if (use_big(n, mode, prec, code)) {
+        GramPlan p = make_plan_big(n, mode, split_of(code));
         return (size_t)p.npairs * p.nsplit * BG * BG * 4;
     }
-    GramPlan p = make_plan(n, mode, bk_for(prec), nsplit);
+    GramPlan p = make_plan(n, mode, bk_for(prec), split_of(code));
     size_t elt = (prec == 0) ? 8 : 4;
     return (size_t)p.npairs * p.nsplit * BM * BM * elt;
+}
+
+int gram_split_candidates(const int n[3], int mode, int prec, int out[GRAM_MAX_CANDIDATES])
+{
+    // out[0] the default; then, within the default's workspace, about 3, 2 and 1 work-groups per
+    // CU of the large-tile kernel (where it can run) and the 64-tile kernel at its default split,
+    // half and a quarter of it
+    const int def = gram_default_splits(n, mode, prec);
+    const size_t wmax = gram_work_bytes(n, mode, prec, def);
+    int c = 0;
+    out[c++] = def;
+    auto add = [&](int code) {
+        for (int i = 0; i < c; ++i)
+            if (out[i] == code) return;
+        if (c < GRAM_MAX_CANDIDATES && gram_work_bytes(n, mode, prec, code) <= wmax) out[c++] = code;
+    };
+    if (big_eligible(n, mode, prec)) {
+        const GramPlan p = make_plan_big(n, mode);
+        for (int per = 3; per >= 1; --per) add(GRAM_BIG + make_plan_big(n, mode, big_splits(p.npairs, per)).nsplit);
+    }
+    const int s0 = make_plan(n, mode, bk_for(prec)).nsplit;
+    for (int d = 1; d <= 4; d *= 2) add(s0 / d > 1 ? s0 / d : 1);
+    return c;
 }
 
 template <int MODE>
@@ -587,8 +602,8 @@ static hipError_t launch_mode(const void* A, const int n[3], int prec, double* G
     u.n1n2 = (long)n[1] * n[2];
     u.n1 = n[1];
     u.n2 = n[2];
-    if (use_big(n, MODE, prec)) {
-        GramPlan p = make_plan_big(n, MODE, nsplit);
+    if (use_big(n, MODE, prec, nsplit)) {
+        GramPlan p = make_plan_big(n, MODE, split_of(nsplit));
         dim3 grid((unsigned)(p.npairs * p.nsplit), 1, bt.nb);
         hipLaunchKernelGGL(k_gram_big<MODE>, grid, dim3(NT), 0, s, (const float*)A, u, p.nrow, p.K, p.kchunk,
                            p.T_tiles, p.npairs, (float*)work, bt.bs);
@@ -599,7 +614,7 @@ static hipError_t launch_mode(const void* A, const int n[3], int prec, double* G
                            p.nsplit, p.nrow, G, bt.bs);
         return hipGetLastError();
     }
-    GramPlan p = make_plan(n, MODE, bk_for(prec), nsplit);
+    GramPlan p = make_plan(n, MODE, bk_for(prec), split_of(nsplit));
     dim3 grid((unsigned)(p.npairs * p.nsplit), 1, bt.nb);
     if (prec == 0) {
         hipLaunchKernelGGL((k_gram_tiles<MODE, double, BK_F64>), grid, dim3(NT), 0, s, (const double*)A, u,

@@ -186,6 +186,57 @@ __global__ void __launch_bounds__(256) k_grid_eval_f32(float* __restrict__ A, Gr
     }
 }
 
+// Uneven batches in one persistent launch: every work item is one plane pair (i0, n0 - 1 - i0)
+// of one job's grid; the resident work-groups take items from a device counter until none is
+// left (every group reaches the exit), each item in the order of the item list (jobs by
+// descending size, so the largest planes start first).  A job's rows and values are those of
+// k_grid_eval_f32 for the same grid.
+__global__ void __launch_bounds__(256) k_grid_eval_f32_queue(const GridJob* __restrict__ jobs, int njobs,
+                                                             const int* __restrict__ first_item, int nitems,
+                                                             unsigned* __restrict__ counter)
+{
+    __shared__ int item_s;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (;;) {
+        if (threadIdx.x == 0) item_s = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int item = item_s;
+        __syncthreads();
+        if (item >= nitems) return;
+        // the job holding this item: first_item is increasing, first_item[njobs] == nitems
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (first_item[mid] <= item) lo = mid; else hi = mid - 1;
+        }
+        const GridJob& jb = jobs[lo];
+        const int pair = item - first_item[lo];
+        const GridAxes& g = jb.g;
+        const KernelParams& kp = jb.kp;
+        const int n0 = g.n[0], n1 = g.n[1];
+        for (int h = 0; h < 2; ++h) {
+            const int i0 = h == 0 ? pair : n0 - 1 - pair;
+            if (h == 1 && i0 <= pair) break;
+            const double x = (g.x0[0] + (double)i0 * g.h[0]) * kp.axs[0];
+            for (int i1 = (jb.sym ? i0 : 0) + wv; i1 < n1; i1 += 4) {
+                const double y = (g.x0[1] + (double)i1 * g.h[1]) * kp.axs[1];
+                const double xy = x * x + y * y;
+                float* dst = jb.A + ((long)i0 * n1 + i1) * g.n[2];
+                float* dst2 = (jb.sym && i0 != i1) ? jb.A + ((long)i1 * n1 + i0) * g.n[2] : nullptr;
+                switch (grid_fast_kind(kp)) {
+                case GF_M12: grid_row_f32<GF_M12>(dst, dst2, g, kp, xy, jb.qpr, lane); break;
+                case GF_M32: grid_row_f32<GF_M32>(dst, dst2, g, kp, xy, jb.qpr, lane); break;
+                case GF_M52: grid_row_f32<GF_M52>(dst, dst2, g, kp, xy, jb.qpr, lane); break;
+                case GF_SLATER1: grid_row_f32<GF_SLATER1>(dst, dst2, g, kp, xy, jb.qpr, lane); break;
+                case GF_GAUSS: grid_row_f32<GF_GAUSS>(dst, dst2, g, kp, xy, jb.qpr, lane); break;
+                default: grid_row_f32<GF_GENERAL>(dst, dst2, g, kp, xy, jb.qpr, lane); break;
+                }
+            }
+        }
+    }
+}
+
 // Launch shape of k_grid_eval_f32: ceil(n0/2) plane pairs, and about 8192 waves in all.
 static dim3 grid_f32_shape(const GridAxes& g, int nb)
 {
@@ -295,6 +346,30 @@ void grid_eval_node_f32(float* A, const GridAxes& g, const KernelParams* kps, Ba
 void grid_eval_node_f64(double* A, const GridAxes& g, const KernelParams* kps, Bat bt, GridEvalNode* nd)
 {
     node_params(A, g, kps, bt, nd);
+}
+
+GridJob grid_job_f32(float* A, const GridAxes& g, const KernelParams& kp)
+{
+    GridJob j{};
+    j.A = A;
+    j.g = g;
+    j.kp = kp;
+    j.qpr = (g.n[2] + 3) / 4;
+    j.sym = grid_symmetric(g, &kp, 1);
+    return j;
+}
+
+int grid_job_items(const GridJob& j) { return (j.g.n[0] + 1) / 2; }
+
+hipError_t launch_grid_eval_f32_queue(const GridJob* jobs_dev, int njobs, const int* first_item_dev, int nitems,
+                                      unsigned* counter_dev, hipStream_t s)
+{
+    if (njobs < 1 || nitems < 1) return hipErrorInvalidValue;
+    // as many work-groups as stay resident (8 per CU), or one per item
+    const int groups = nitems < 2048 ? nitems : 2048;
+    hipLaunchKernelGGL(k_grid_eval_f32_queue, dim3(groups), dim3(256), 0, s, jobs_dev, njobs, first_item_dev, nitems,
+                       counter_dev);
+    return hipGetLastError();
 }
 
 hipError_t launch_grid_eval_f32(float* A, const GridAxes& g, const KernelParams* kps, hipStream_t s, Bat bt)

@@ -254,6 +254,13 @@ struct Reservation {
     bool held;
     Reservation(tk_ctx* c_, size_t b) : c(c_), bytes(b), held(false) {}
     bool take() { held = reserve(c, bytes); return held; }
+    // take `b` bytes (a reservation made empty and filled once its size is known)
+    bool take_bytes(size_t b)
+    {
+        if (held) return false;
+        bytes = b;
+        return take();
+    }
     // part of the reservation passes to an object that releases it itself (a result)
     bool hand_over(size_t b)
     {
@@ -1270,25 +1277,37 @@ size_t batch_layout(const Plan& P, bool own_A, int nb, size_t* ws)
 // every launch covers all of them (grid z), each problem running the work-groups it runs alone.
 // outs[b] / sts[b]: the result and TK_OK or TK_ENOCONV (eps not met; the result is returned
 // anyway).  Any other error is returned for the whole call, with no results.
+// A chunk of an uneven batch whose workspace the batch laid out (and charged) beforehand, with
+// the problems' tensors already evaluated there by the batch's persistent grid launch.
+struct BatchSlot {
+    void* base;
+};
+
 template <typename Real>
 tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void* A_in, const tk_grid* grid, Plan P,
-                        hipStream_t s, tk_tucker** outs, tk_status* sts)
+                        hipStream_t s, tk_tucker** outs, tk_status* sts, const BatchSlot* slot = nullptr)
 {
     const bool own_A = (A_in == nullptr);
     if (nb < 1 || nb > BATCH_MAX || (!own_A && nb != 1)) return fail(TK_EINVAL, "batch of %d problems", nb);
     if (nb > 1 && (P.prec == TK_FP64 || P.converge))
         return fail(TK_EINVAL, "the FP64 path and converged HOOI read back between steps: one problem per call");
+    if (slot && (!own_A || sizeof(Real) != 4)) return fail(TK_EINVAL, "batch slot: float tensors of the batch only");
     for (int b = 0; b < nb; ++b) { outs[b] = nullptr; sts[b] = TK_OK; }
     size_t ws = 0;
     const size_t total = batch_layout(P, own_A, nb, &ws);
-    const size_t need = total + (size_t)nb * result_bytes(P.n, P.R);
+    const size_t need = (slot ? 0 : total) + (size_t)nb * result_bytes(P.n, P.R);
     Reservation res(ctx, need);
     if (!res.take()) return fail(TK_ENOMEM, "compress needs %zu bytes; budget %zu, in use %zu", need, ctx->budget,
                                  ctx->in_use.load());
-    Ws wsp;
-    hipError_t he = ws_get(ctx, s, 0, total, wsp);
-    if (he != hipSuccess) return fail(TK_ENOMEM, "workspace of %zu bytes: %s", total, hipGetErrorString(he));
-    void* base = wsp.p;
+    Ws wsp;   // (unused with a batch slot: the batch owns that workspace)
+    void* base = nullptr;
+    if (slot) {
+        base = slot->base;
+    } else {
+        hipError_t he = ws_get(ctx, s, 0, total, wsp);
+        if (he != hipSuccess) return fail(TK_ENOMEM, "workspace of %zu bytes: %s", total, hipGetErrorString(he));
+        base = wsp.p;
+    }
     Arena ar;
     ar.base = (char*)base;
     Work w;
@@ -1304,7 +1323,7 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void
     // path reads ranks back in between)
     auto pipeline = [&](hipStream_t s) -> tk_status {
         tk_status st;
-        if (own_A) {
+        if (own_A && !slot) {
             GridAxes ax = axes_of(grid);
             ProfScope ps(TK_PROF_GRID, s);
             if (sizeof(Real) == 4) TK_LAUNCH(launch_grid_eval_f32((float*)w.A, ax, kps, s, w.bt));
@@ -1506,7 +1525,8 @@ tk_status compress_any(tk_ctx* ctx, const tk_kernel* kernel, const void* A_in, c
 // nb <= BATCH_MAX problems on one grid with one set of options, launched together.  outs[i] /
 // sts[i] as for compress_impl.
 tk_status compress_group(tk_ctx* ctx, const tk_kernel* const* kernels, int nb, const tk_grid* grid,
-                         const tk_opts* opts, hipStream_t s, tk_tucker** outs, tk_status* sts)
+                         const tk_opts* opts, hipStream_t s, tk_tucker** outs, tk_status* sts,
+                         const BatchSlot* slot = nullptr)
 {
     tk_status st;
     if ((st = check_grid(grid)) != TK_OK) return st;
@@ -1520,7 +1540,7 @@ tk_status compress_group(tk_ctx* ctx, const tk_kernel* const* kernels, int nb, c
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(TK_EHIP, "hipSetDevice(%d) failed", ctx->device);
     (void)hipGetLastError();
     if (P.prec == TK_FP64) return compress_impl<double>(ctx, kps, nb, nullptr, grid, P, s, outs, sts);
-    return compress_impl<float>(ctx, kps, nb, nullptr, grid, P, s, outs, sts);
+    return compress_impl<float>(ctx, kps, nb, nullptr, grid, P, s, outs, sts, slot);
 }
 
 // Can problems with these options share launches?  (The FP64 path reads the eigensolver's
@@ -2066,7 +2086,7 @@ tk_status tk_autotune(tk_ctx* ctx, const tk_grid* grid, int prec, void* hip_stre
     TK_HIP(hipEventCreate(&e0));
     TK_HIP(hipEventCreate(&e1));
     for (int k = 0; k < 3; ++k) {
-        int cand[4];
+        int cand[GRAM_MAX_CANDIDATES];
         const int nc = gram_split_candidates(n, k, prec, cand);
         int best = cand[0];
         float best_ms = 1e30f;
@@ -2558,6 +2578,60 @@ tk_status tk_compress_batch(tk_ctx* ctx, int count, const tk_kernel* kernels, co
         }
         for (int i = 0; i < W; ++i) ws[i] = ctx->streams[i];
     }
+    // ---- float tensors: one persistent launch evaluates the grids of every unit, of every size,
+    // into a workspace the batch lays out for all units at once (when it fits the budget; the
+    // units then run on their slots without a grid launch of their own)
+    std::vector<BatchSlot> slots;
+    Reservation batch_res(ctx, 0);
+    Ws batch_ws;
+    std::vector<GridJob> jobs;     // host copies stay alive until the call returns
+    std::vector<int> first;
+    if (count > 1 && groupable(opts) && opts->prec != TK_FP64) {
+        std::vector<size_t> off(nunits), wsz(nunits);
+        size_t tot = 0;
+        bool ok = true;
+        for (int u = 0; u < nunits && ok; ++u) {
+            Plan P;
+            ok = make_plan(&grids[units[u].idx[0]], opts, &P) == TK_OK;
+            if (!ok) break;
+            apply_tuning(ctx, &P);
+            off[u] = tot;
+            tot += align_up(batch_layout(P, true, (int)units[u].idx.size(), &wsz[u]), 256);
+        }
+        for (int u = 0; u < nunits && ok; ++u)
+            for (size_t b = 0; b < units[u].idx.size() && ok; ++b) {
+                const int i = units[u].idx[b];
+                KernelParams kp{};
+                ok = check_kernel(&kernels[i], &kp) == TK_OK;
+                if (ok) jobs.push_back(grid_job_f32(nullptr, axes_of(&grids[i]), kp));
+                if (ok) jobs.back().A = reinterpret_cast<float*>(off[u] + b * wsz[u]);   // offset for now
+            }
+        // largest grids first, so that their planes start first
+        std::stable_sort(jobs.begin(), jobs.end(), [](const GridJob& a, const GridJob& b) {
+            return (long)a.g.n[0] * a.g.n[1] * a.g.n[2] > (long)b.g.n[0] * b.g.n[1] * b.g.n[2];
+        });
+        first.assign(jobs.size() + 1, 0);
+        for (size_t j = 0; j < jobs.size(); ++j) first[j + 1] = first[j] + grid_job_items(jobs[j]);
+        const size_t tab = align_up(sizeof(GridJob) * jobs.size(), 256) + align_up(sizeof(int) * first.size(), 256) + 256;
+        if (ok && !jobs.empty() && batch_res.take_bytes(tot + tab) &&
+            ws_get(ctx, (hipStream_t)hip_stream, 1, tot + tab, batch_ws) == hipSuccess) {
+            char* base = (char*)batch_ws.p;
+            for (GridJob& j : jobs) j.A = reinterpret_cast<float*>(base + reinterpret_cast<size_t>(j.A));
+            GridJob* jobs_dev = (GridJob*)(base + tot);
+            int* first_dev = (int*)(base + tot + align_up(sizeof(GridJob) * jobs.size(), 256));
+            unsigned* counter = (unsigned*)(base + tot + tab - 256);
+            hipStream_t cs = (hipStream_t)hip_stream;
+            TK_HIP(hipMemcpyAsync(jobs_dev, jobs.data(), sizeof(GridJob) * jobs.size(), hipMemcpyHostToDevice, cs));
+            TK_HIP(hipMemcpyAsync(first_dev, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice, cs));
+            TK_HIP(hipMemsetAsync(counter, 0, sizeof(unsigned), cs));
+            {
+                ProfScope ps(TK_PROF_GRID, cs);
+                TK_LAUNCH(launch_grid_eval_f32_queue(jobs_dev, (int)jobs.size(), first_dev, first.back(), counter, cs));
+            }
+            slots.resize(nunits);
+            for (int u = 0; u < nunits; ++u) slots[u].base = base + off[u];
+        }
+    }
     // the items start after the work already queued on the caller's stream
     hipEvent_t fork;
     TK_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
@@ -2590,7 +2664,10 @@ tk_status tk_compress_batch(tk_ctx* ctx, int count, const tk_kernel* kernels, co
                     seen = finished;
                 }
                 tk_status r;
-                if (nb == 1) {
+                if (!slots.empty()) {
+                    r = compress_group(ctx, ks.data(), nb, &grids[u.idx[0]], opts, s, os.data(), ss.data(),
+                                       &slots[ui]);
+                } else if (nb == 1) {
                     r = compress_any(ctx, ks[0], nullptr, &grids[u.idx[0]], opts, s, &os[0]);
                     if (r == TK_ENOCONV) { ss[0] = TK_ENOCONV; r = TK_OK; }
                 } else {

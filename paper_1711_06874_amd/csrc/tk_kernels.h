@@ -34,6 +34,22 @@ hipError_t launch_grid_eval_f32(float* A, const GridAxes& g, const KernelParams*
 hipError_t launch_grid_eval_f64(double* A, const GridAxes& g, const KernelParams* kps, hipStream_t s,
                                 Bat bt = Bat());
 
+// Uneven batches: float grids of any sizes in one persistent launch.  A job is one grid (its
+// float tensor A, axes and kernel); its work items are its (n0 + 1) / 2 plane pairs.
+// first_item_dev[j] = items of the jobs before j (first_item_dev[njobs] = nitems); *counter_dev
+// must be zero when the launch starts.  Values equal launch_grid_eval_f32's for each grid.
+struct GridJob {
+    float* A;
+    GridAxes g;
+    KernelParams kp;
+    int qpr;
+    int sym;
+};
+GridJob grid_job_f32(float* A, const GridAxes& g, const KernelParams& kp);
+int grid_job_items(const GridJob& j);
+hipError_t launch_grid_eval_f32_queue(const GridJob* jobs_dev, int njobs, const int* first_item_dev, int nitems,
+                                      unsigned* counter_dev, hipStream_t s);
+
 // Kernel-node parameters of the grid evaluation as launch_grid_eval_* would launch it (for
 // updating a captured graph); the argument values live in the struct, which must outlive the
 // update call.
@@ -53,13 +69,17 @@ void grid_eval_node_f64(double* A, const GridAxes& g, const KernelParams* kps, B
 
 // ----------------------------------------------------------------- a2: Gram (SYRK) ----
 // G (n_mode x n_mode, double, full) = A_(mode) A_(mode)^T.  `work` must hold
-// gram_work_bytes(...) bytes.  nsplit: the number of K chunks per tile pair (0: the default
-// for the shape, gram_default_splits); the partial sums of the chunks are added in FP64 in
-// chunk order, so a given split count gives the same result every time.
+// gram_work_bytes(...) bytes.  nsplit (a "code"): the number of K chunks per tile pair of the
+// 64 x 64-tile kernel, or GRAM_BIG + that number for the 128 x 128-tile FP32 kernel (every n a
+// multiple of 32, n_mode >= 128), 0 for the default of the shape (gram_default_splits); the
+// partial sums of the chunks are added in FP64 in chunk order, so a given code gives the same
+// result every time.
+constexpr int GRAM_BIG = 1 << 20;
+constexpr int GRAM_MAX_CANDIDATES = 8;
 int gram_default_splits(const int n[3], int mode, int prec);
-// Split counts worth timing for the shape (out[0] the default; none needs more workspace than
-// the default): returns how many were written (at most 4).
-int gram_split_candidates(const int n[3], int mode, int prec, int out[4]);
+// Codes worth timing for the shape (out[0] the default; none needs more workspace than the
+// default): returns how many were written (at most GRAM_MAX_CANDIDATES).
+int gram_split_candidates(const int n[3], int mode, int prec, int out[GRAM_MAX_CANDIDATES]);
 size_t gram_work_bytes(const int n[3], int mode, int prec, int nsplit = 0);
 hipError_t launch_gram(const void* A, const int n[3], int mode, int prec, double* G, void* work,
                        hipStream_t s, Bat bt = Bat(), int nsplit = 0);

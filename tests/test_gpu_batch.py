@@ -278,3 +278,32 @@ def test_graph_replay_matches_direct_launches(tk):
                 t.free()
         finally:
             ctx.destroy()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_uneven_batch_grids_in_one_persistent_launch(tk, prec):
+    """Float batches of uneven sizes evaluate every grid in one persistent launch (work items
+    of all sizes taken from a device counter) into the workspace laid out for all units at
+    once; the results stay bitwise those of single calls."""
+    require_gpu()
+    ctx = tk.Context(0)
+    try:
+        ks, gs = _problems(tk)
+        opts = tk.make_opts(eps=1e-6, hooi_sweeps=2, prec=prec)
+        alone = [ctx.compress(k, g, opts) for k, g in zip(ks, gs)]
+        tk.tk_profile_reset()
+        tk.tk_profile_select(["grid"])
+        tk.tk_profile_enable(True)
+        mix = ctx.compress_batch(ks, gs, opts)
+        tk.tk_profile_enable(False)
+        launches, ms = tk.tk_profile_read(tk.PROF_CLASSES["grid"])
+        tk.tk_profile_reset()
+        tk.tk_profile_select(None)
+        say("grid launches in the batch: %d (%.3f ms)" % (launches, ms))
+        assert launches == 1
+        for i, (a, b) in enumerate(zip(alone, mix)):
+            assert _same(a, b), f"item {i} differs in the batch"
+        for t in mix + alone:
+            t.free()
+    finally:
+        ctx.destroy()
