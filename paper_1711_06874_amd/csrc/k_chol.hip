@@ -4,11 +4,11 @@
 // kernel (k_small.hip).
 //
 // Cholesky: blocked right-looking, CB = 64 columns per step.  One work-group factors the
-// diagonal block in LDS (column by column: pivot, scaling, rank-1 update of the block's
-// trailing part) and also forms the inverse of its triangular factor; the panel below is then
-// L21 = A21 L11^-T as one product with that inverse, and the trailing matrix takes
-// A22 -= L21 L21^T as another.  A pivot that is not positive records its index (plus one)
-// in `info` and the factor turns to NaN from there on.
+// diagonal block (one wavefront, rows in registers: pivot, scaling, rank-1 update of the
+// block's trailing part) and also forms the inverse of its triangular factor; the panel below is
+// then L21 = A21 L11^-T as one product with that inverse, and the lower tiles of the trailing
+// matrix take A22 -= L21 L21^T on FP64 MFMA (k_syrk_lower).  A pivot that is not positive
+// records its index (plus one) in `info` and the factor turns to NaN from there on.
 #include "tk_kernels.h"
 
 namespace tk {
@@ -33,45 +33,51 @@ __global__ void __launch_bounds__(256) k_cov1d(double* __restrict__ C, int n, do
 
 // Factor the nb x nb diagonal block at (k0, k0) of A (row-major, ld n) in place, zero its strict
 // upper part, and write the inverse of its lower-triangular factor to inv (nb x nb, ld CB).
-__global__ void __launch_bounds__(256) k_potrf_block(double* __restrict__ A, int n, int k0, int nb,
-                                                     double* __restrict__ inv, int* __restrict__ info)
+// One wavefront, lane i holding row i of the block in registers (the column loops are unrolled,
+// so every register index is static).  Column j: the pivot comes from lane j, the lanes below
+// scale their entry, publish it in LDS, and update their row with the broadcast column.  The
+// inverse is then formed column by column, lane c taking column c by forward substitution on
+// the factor kept in LDS.  A wavefront orders its own LDS accesses, so no barrier is needed.
+__global__ void __launch_bounds__(64) k_potrf_block(double* __restrict__ A, int n, int k0, int nb,
+                                                    double* __restrict__ inv, int* __restrict__ info)
 {
-    __shared__ double L[CB][CB + 1];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < nb * nb; e += 256) {
-        const int r = e / nb, c = e - r * nb;
-        L[r][c] = (c <= r) ? A[(long)(k0 + r) * n + k0 + c] : 0.0;
-    }
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        if (tid == 0) {
-            const double d = L[j][j];
-            if (!(d > 0.0) && *info == 0) *info = k0 + j + 1;
-            L[j][j] = sqrt(d);
+    __shared__ double col[CB];
+    __shared__ double Ls[CB][CB + 1];
+    const int i = threadIdx.x;
+    const bool live = i < nb;
+    double a[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) a[c] = (live && c <= i && c < nb) ? A[(long)(k0 + i) * n + k0 + c] : 0.0;
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+        if (j < nb) {
+            const double d = __shfl(a[j], j, 64);
+            if (i == 0 && !(d > 0.0) && *info == 0) *info = k0 + j + 1;
+            const double ljj = sqrt(d);
+            const double lij = (i > j) ? a[j] / ljj : (i == j ? ljj : 0.0);
+            a[j] = lij;
+            col[i] = (i > j && live) ? lij : 0.0;
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int c = j + 1; c < CB; ++c) a[c] -= lij * col[c];
+            __builtin_amdgcn_wave_barrier();
         }
-        __syncthreads();
-        for (int i = j + 1 + tid; i < nb; i += 256) L[i][j] /= L[j][j];
-        __syncthreads();
-        const int m = nb - j - 1;
-        for (int e = tid; e < m * m; e += 256) {
-            const int i = j + 1 + e / m, c = j + 1 + e % m;
-            if (c <= i) L[i][c] -= L[i][j] * L[c][j];
-        }
-        __syncthreads();
     }
-    for (int e = tid; e < nb * nb; e += 256) {
-        const int r = e / nb, c = e - r * nb;
-        A[(long)(k0 + r) * n + k0 + c] = (c <= r) ? L[r][c] : 0.0;
-    }
-    // inv = L^-1, column c by forward substitution in thread c (it reads back only its own
-    // column, so no barrier is needed)
-    if (tid < nb) {
-        const int c = tid;
-        for (int i = 0; i < nb; ++i) {
-            double v = (i == c) ? 1.0 : 0.0;
-            for (int k = c; k < i; ++k) v -= L[i][k] * inv[(long)k * CB + c];
-            inv[(long)i * CB + c] = (i < c) ? 0.0 : v / L[i][i];
-        }
+    // rows to LDS (lower triangle, zeros above), then out to A row by row (coalesced)
+#pragma unroll
+    for (int c = 0; c < CB; ++c) Ls[i][c] = (c <= i) ? a[c] : 0.0;
+    __builtin_amdgcn_wave_barrier();
+    for (int r = 0; r < nb; ++r)
+        if (live) A[(long)(k0 + r) * n + k0 + i] = Ls[r][i];
+    // inv = L^-1: lane c computes column c (x_k = 0 for k < c)
+    double x[CB];
+#pragma unroll
+    for (int r = 0; r < CB; ++r) {
+        double v = (r == i) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < r; ++k) v -= Ls[r][k] * x[k];
+        x[r] = (r < i || r >= nb) ? 0.0 : v / Ls[r][r];
+        if (live && r < nb) inv[(long)r * CB + i] = x[r];
     }
 }
 
@@ -85,7 +91,65 @@ __global__ void __launch_bounds__(256) k_store_panel(double* __restrict__ A, int
     A[(long)(k0 + nb + r) * n + k0 + c] = T[(long)r * CB + c];
 }
 
-// Zero the strict upper triangle of A (the trailing updates write full squares).
+// Trailing update of the blocked factorisation, lower tiles only: C[i][j] -= sum_k T[i][k] T[j][k]
+// for the 64 x 64 tiles (ti >= tj) of the rows x rows matrix C (ld n); T is rows x nb (ld CB).
+// Tiles above the diagonal are skipped: the factorisation reads only the lower part, and the
+// strict upper part is cleared at the end.  One work-group per tile: the two T panels are staged
+// in LDS k-major, 32 k at a time, and four waves each form a 32 x 32 block from 2 x 2 FP64 MFMA
+// 16 x 16 accumulators.
+constexpr int SB = 64;
+constexpr int SK = 32;
+__global__ void __launch_bounds__(256) k_syrk_lower(double* __restrict__ C, int n, int rows,
+                                                   const double* __restrict__ T, int nb)
+{
+    __shared__ double As[SK][SB + 1], Bs[SK][SB + 1];
+    const int pidx = blockIdx.x;
+    int ti = (int)((sqrt(8.0 * pidx + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= pidx) ++ti;
+    while (ti * (ti + 1) / 2 > pidx) --ti;
+    const int tj = pidx - ti * (ti + 1) / 2;
+    const int r0a = ti * SB, r0b = tj * SB;
+    const bool diag = (ti == tj);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+    f64x4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int kc = 0; kc < nb; kc += SK) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < SB * SK / 256; ++q) {
+            const int e = tid + 256 * q, m = e / SK, k = e - m * SK;
+            const int ra = r0a + m, rb = r0b + m, kg = kc + k;
+            As[k][m] = (ra < rows && kg < nb) ? T[(long)ra * CB + kg] : 0.0;
+            if (!diag) Bs[k][m] = (rb < rows && kg < nb) ? T[(long)rb * CB + kg] : 0.0;
+        }
+        __syncthreads();
+        const double (*Bp)[SB + 1] = diag ? As : Bs;
+#pragma unroll
+        for (int ks = 0; ks < SK; ks += 4) {
+            const int kr = ks + (lane >> 4);
+            const double a0 = As[kr][wm + (lane & 15)], a1 = As[kr][wm + 16 + (lane & 15)];
+            const double b0 = Bp[kr][wn + (lane & 15)], b1 = Bp[kr][wn + 16 + (lane & 15)];
+            acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[1], 0, 0, 0);
+            acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[2], 0, 0, 0);
+            acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[3], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gi = r0a + wm + 16 * bi + 4 * v + (lane >> 4);
+                const int gj = r0b + wn + 16 * bj + (lane & 15);
+                if (gi < rows && gj < rows) C[(long)gi * n + gj] -= acc[bi * 2 + bj][v];
+            }
+}
+
+// Zero the strict upper triangle of A (the trailing updates leave values above the diagonal).
 __global__ void __launch_bounds__(256) k_zero_upper(double* __restrict__ A, int n)
 {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -106,21 +170,25 @@ __global__ void __launch_bounds__(256) k_logdet(const double* __restrict__ L, in
     if (threadIdx.x == 0) out[0] = 2.0 * ((red[0] + red[1]) + (red[2] + red[3]));
 }
 
-// X = L^-1 for a lower-triangular n x n L (row-major): column j by forward substitution in
-// thread j; X is zero above the diagonal.  Every lane of a wave runs the same row loop (rows
-// above its own column contribute zeros), so the L entries are wave-wide broadcasts.
-__global__ void __launch_bounds__(256) k_trinv(const double* __restrict__ L, int n, double* __restrict__ X)
+// Diagonal block b of X = L^-1 (lower-triangular, row-major, ld n): the inverse of the
+// nb x nb block L_bb, lane c taking column c by forward substitution on the block in LDS.
+__global__ void __launch_bounds__(64) k_trinv_diag(const double* __restrict__ L, int n, double* __restrict__ X)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = j < n;
-    const int jj = live ? j : 0;
-    const int jw = (blockIdx.x * blockDim.x + (threadIdx.x & ~63));   // first column of the wave
-    for (int i = 0; i < n; ++i) {
-        double v = (i == jj) ? 1.0 : 0.0;
-        if (i >= jw) {
-            for (int k = jw; k < i; ++k) v -= L[(long)i * n + k] * (live && k >= jj ? X[(long)k * n + jj] : 0.0);
-        }
-        if (live) X[(long)i * n + jj] = (i < jj) ? 0.0 : v / L[(long)i * n + i];
+    __shared__ double Ls[CB][CB + 1];
+    const int r0 = blockIdx.x * CB;
+    const int nb = min(CB, n - r0);
+    const int i = threadIdx.x;
+    const bool live = i < nb;
+    for (int r = 0; r < nb; ++r) Ls[r][i] = live ? L[(long)(r0 + r) * n + r0 + i] : 0.0;
+    __builtin_amdgcn_wave_barrier();
+    double x[CB];
+#pragma unroll
+    for (int r = 0; r < CB; ++r) {
+        double v = (r == i) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < r; ++k) v -= Ls[r][k] * x[k];
+        x[r] = (r < i || r >= nb) ? 0.0 : v / Ls[r][r];
+        if (live && r < nb) X[(long)(r0 + r) * n + r0 + i] = x[r];
     }
 }
 
@@ -141,7 +209,7 @@ hipError_t launch_cholesky(double* A, int n, void* work, int* info, hipStream_t 
     hipError_t e;
     for (int k0 = 0; k0 < n; k0 += CB) {
         const int nb = (n - k0 < CB) ? n - k0 : CB;
-        hipLaunchKernelGGL(k_potrf_block, dim3(1), dim3(256), 0, s, A, n, k0, nb, inv, info);
+        hipLaunchKernelGGL(k_potrf_block, dim3(1), dim3(64), 0, s, A, n, k0, nb, inv, info);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int rows = n - k0 - nb;
         if (rows <= 0) break;
@@ -156,14 +224,11 @@ hipError_t launch_cholesky(double* A, int n, void* work, int* info, hipStream_t 
         const long pt = (long)rows * nb;
         hipLaunchKernelGGL(k_store_panel, dim3((unsigned)((pt + 255) / 256)), dim3(256), 0, s, A, n, k0, nb, rows, T);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        // A22 -= T T^T
-        GemmArgs u{};
-        u.M = rows; u.N = rows; u.K = nb; u.batch = 1;
-        u.A = T; u.sAm = CB; u.sAk = 1;
-        u.B = T; u.sBk = 1; u.sBn = CB;
-        u.C = A + (long)(k0 + nb) * n + k0 + nb; u.sCm = n; u.sCn = 1;
-        u.alpha = -1.0; u.beta = 1.0;
-        if ((e = launch_gemm<double, double, double>(u, s)) != hipSuccess) return e;
+        // A22 -= T T^T (lower tiles)
+        const long nt = (rows + SB - 1) / SB;
+        hipLaunchKernelGGL(k_syrk_lower, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, s,
+                           A + (long)(k0 + nb) * n + k0 + nb, n, rows, (const double*)T, nb);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const long tot = (long)n * n;
     hipLaunchKernelGGL(k_zero_upper, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, A, n);
@@ -176,10 +241,39 @@ hipError_t launch_logdet_chol(const double* L, int n, double* out, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_trinv(const double* L, int n, double* X, hipStream_t s)
+// Blocked: X's strict upper part is cleared, the diagonal blocks are inverted in one launch,
+// then block row b (b = 1, 2, ...) takes X[b, 0:b] = -X_bb (L[b, 0:b] X[0:b, 0:b]) as two
+// products (X[0:b, 0:b] is final by then).  work: CB x n doubles.
+hipError_t launch_trinv(const double* L, int n, double* X, double* work, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_trinv, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, L, n, X);
-    return hipGetLastError();
+    if (n < 1) return hipErrorInvalidValue;
+    const long tot = (long)n * n;
+    hipLaunchKernelGGL(k_zero_upper, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, X, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nbk = (n + CB - 1) / CB;
+    hipLaunchKernelGGL(k_trinv_diag, dim3(nbk), dim3(64), 0, s, L, n, X);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int bi = 1; bi < nbk; ++bi) {
+        const int r0 = bi * CB, rows = (n - r0 < CB) ? n - r0 : CB;
+        // work (rows x r0, ld r0) = L[r0:r0+rows, 0:r0] X[0:r0, 0:r0]
+        GemmArgs g{};
+        g.M = rows; g.N = r0; g.K = r0; g.batch = 1;
+        g.A = L + (long)r0 * n; g.sAm = n; g.sAk = 1;
+        g.B = X; g.sBk = n; g.sBn = 1;
+        g.C = work; g.sCm = r0; g.sCn = 1;
+        g.alpha = 1.0; g.beta = 0.0;
+        if ((e = launch_gemm<double, double, double>(g, s)) != hipSuccess) return e;
+        // X[r0:r0+rows, 0:r0] = -X_bb work
+        GemmArgs h{};
+        h.M = rows; h.N = r0; h.K = rows; h.batch = 1;
+        h.A = X + (long)r0 * n + r0; h.sAm = n; h.sAk = 1;
+        h.B = work; h.sBk = r0; h.sBn = 1;
+        h.C = X + (long)r0 * n; h.sCm = n; h.sCn = 1;
+        h.alpha = -1.0; h.beta = 0.0;
+        if ((e = launch_gemm<double, double, double>(h, s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace tk

@@ -12,7 +12,7 @@
 // the block is the identity and the whole matrix is diagonalised by Jacobi directly.
 //
 // Kernels: k_eig_init (start block; a warm block of exactly p columns is read in place by the
-// first product instead), k_hqr_reg (rows in registers, n <= 512 and p <= 32; it can also write
+// first product instead), k_hqr_reg (rows in registers, n <= 1024 and p <= 32; it can also write
 // an FP32 copy of the factor) and k_hqr (one work-group per problem, Householder QR with the
 // n x p block resident in LDS when it fits, producing the explicit Q in place), k_jacobi_w /
 // k_jacobi (one work-group per problem, p x p in LDS), k_signfix; the products G Q, Q^T Y and
@@ -310,14 +310,21 @@ __global__ void __launch_bounds__(256) k_jacobi(const double* __restrict__ Hin, 
 
 
 // ---------------------------------------------------------------------------------------------
-// S[c] = sum_i x_i w_i[c] for C0 <= c < PM: x is this thread's multiplier (0 for rows that take
-// no part).  T holds PM x NT doubles.  Everything but the row index is compile-time.
-template <int PM, int NT, int C0>
-__device__ __forceinline__ void block_col_sums(double* T, double* S, const double (&w)[PM], double x)
+// S[c] = sum_i x_i w_i[c] for C0 <= c < PM over the RPT rows of every thread (x[q]: the
+// multiplier of the thread's row q, 0 for rows that take no part).  T holds PM x NT doubles (the
+// thread's rows are summed before the LDS transpose).  Everything but the row index is
+// compile-time.
+template <int PM, int NT, int RPT, int C0>
+__device__ __forceinline__ void block_col_sums(double* T, double* S, const double (&w)[RPT][PM], const double (&x)[RPT])
 {
     const int t = threadIdx.x;
 #pragma unroll
-    for (int c = C0; c < PM; ++c) T[c * NT + t] = x * w[c];
+    for (int c = C0; c < PM; ++c) {
+        double v = x[0] * w[0][c];
+#pragma unroll
+        for (int q = 1; q < RPT; ++q) v += x[q] * w[q][c];
+        T[c * NT + t] = v;
+    }
     __syncthreads();
     constexpr int NC = PM - C0;
     constexpr int G = (NC * 64 <= NT) ? 64 : (NC * 32 <= NT ? 32 : (NC * 16 <= NT ? 16 : (NC * 8 <= NT ? 8 : (NC * 4 <= NT ? 4 : (NC * 2 <= NT ? 2 : 1)))));
@@ -345,22 +352,28 @@ __device__ __forceinline__ void block_col_sums(double* T, double* S, const doubl
     __syncthreads();
 }
 
-// Householder step for column J (rows in registers, columns >= p are zero and stay zero).
-template <int PM, int NT, int J>
-__device__ __forceinline__ void qr_forward(double (&w)[PM], double* T, double* S, double (*rowjb)[PM], double* taus,
-                                           int n, int p)
+// Householder step for column J (rows in registers, columns >= p are zero and stay zero).  Row q
+// of thread i is row i + q NT of the block; row J (J < p <= PM <= 32 < NT) is row 0 of thread J.
+template <int PM, int NT, int RPT, int J>
+__device__ __forceinline__ void qr_forward(double (&w)[RPT][PM], double* T, double* S, double (*rowjb)[PM],
+                                           double* taus, int n, int p)
 {
     if constexpr (J < PM) {
         if (J >= p) return;
         const int i = threadIdx.x;
-        const bool live = i < n;
-        const double x = w[J];
         double* rowj = rowjb[J & 1];
         if (i == J) {
 #pragma unroll
-            for (int c = 0; c < PM; ++c) rowj[c] = w[c];
+            for (int c = 0; c < PM; ++c) rowj[c] = w[0][c];
         }
-        block_col_sums<PM, NT, J>(T, S, w, (live && i > J) ? x : 0.0);
+        double x[RPT], xs[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int row = i + q * NT;
+            x[q] = w[q][J];
+            xs[q] = (row < n && row > J) ? x[q] : 0.0;
+        }
+        block_col_sums<PM, NT, RPT, J>(T, S, w, xs);
         const double xn2 = S[J];
         const double alpha = rowj[J];
         double t = 0.0, scale = 0.0, beta = alpha;
@@ -371,49 +384,66 @@ __device__ __forceinline__ void qr_forward(double (&w)[PM], double* T, double* S
             scale = 1.0 / (alpha - beta);
         }
         if (i == 0) taus[J] = t;
-        const double v = (i == J) ? 1.0 : ((live && i > J) ? x * scale : 0.0);
-        const double tv = t * v;
 #pragma unroll
-        for (int c = J + 1; c < PM; ++c) w[c] -= tv * (rowj[c] + scale * S[c]);
-        // column J: beta on the diagonal, the scaled reflector below it
-        w[J] = (i == J) ? beta : ((i > J) ? x * scale : x);
-        qr_forward<PM, NT, J + 1>(w, T, S, rowjb, taus, n, p);
+        for (int q = 0; q < RPT; ++q) {
+            const int row = i + q * NT;
+            const double v = (row == J) ? 1.0 : ((row < n && row > J) ? x[q] * scale : 0.0);
+            const double tv = t * v;
+#pragma unroll
+            for (int c = J + 1; c < PM; ++c) w[q][c] -= tv * (rowj[c] + scale * S[c]);
+            // column J: beta on the diagonal, the scaled reflector below it
+            w[q][J] = (row == J) ? beta : ((row > J) ? x[q] * scale : x[q]);
+        }
+        qr_forward<PM, NT, RPT, J + 1>(w, T, S, rowjb, taus, n, p);
     }
 }
 
 // Explicit Q, column J (from the last reflector to the first, in place).
-template <int PM, int NT, int J>
-__device__ __forceinline__ void qr_backward(double (&w)[PM], double* T, double* S, const double* taus, int n, int p)
+template <int PM, int NT, int RPT, int J>
+__device__ __forceinline__ void qr_backward(double (&w)[RPT][PM], double* T, double* S, const double* taus, int n,
+                                            int p)
 {
     if constexpr (J >= 0) {
         if (J < p) {
             const int i = threadIdx.x;
-            const double v = (i == J) ? 1.0 : ((i < n && i > J) ? w[J] : 0.0);
+            double v[RPT];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int row = i + q * NT;
+                v[q] = (row == J) ? 1.0 : ((row < n && row > J) ? w[q][J] : 0.0);
+            }
             const double t = taus[J];
             if constexpr (J + 1 < PM) {
                 if (J + 1 < p) {
-                    block_col_sums<PM, NT, J + 1>(T, S, w, v);
-                    const double tv = t * v;
+                    block_col_sums<PM, NT, RPT, J + 1>(T, S, w, v);
 #pragma unroll
-                    for (int c = J + 1; c < PM; ++c) w[c] -= tv * S[c];
+                    for (int q = 0; q < RPT; ++q) {
+                        const double tv = t * v[q];
+#pragma unroll
+                        for (int c = J + 1; c < PM; ++c) w[q][c] -= tv * S[c];
+                    }
                 }
             }
-            w[J] = (i < J) ? 0.0 : ((i == J) ? 1.0 - t : -t * v);
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int row = i + q * NT;
+                w[q][J] = (row < J) ? 0.0 : ((row == J) ? 1.0 - t : -t * v[q]);
+            }
         }
-        qr_backward<PM, NT, J - 1>(w, T, S, taus, n, p);
+        qr_backward<PM, NT, RPT, J - 1>(w, T, S, taus, n, p);
     }
 }
 
 // ---------------------------------------------------------------------------------------------
-// Householder QR with each row of the n x p block held in one thread's registers (n <= NT,
-// p <= PM, columns p..PM-1 carried as zeros).  Per column one block reduction gives both the
-// squared norm below the diagonal and the products of that part of the column with every later
-// column:  S[c] = sum_{i > j} W[i][j] W[i][c],  so with scale = 1 / (alpha - beta) the reflector
-// v = (1, scale W[j+1:, j]) satisfies  v^T W[j:, c] = W[j][c] + scale S[c].  The reduction goes
-// through an LDS transpose T[c][i] (two barriers).  The column loop is unrolled at compile
-// time, so every register index is static.  The explicit Q is then accumulated backwards in
-// the same registers.
-template <int PM, int NT>
+// Householder QR with the rows of the n x p block held in registers, RPT rows per thread
+// (n <= RPT NT, p <= PM, columns p..PM-1 carried as zeros).  Per column one block reduction
+// gives both the squared norm below the diagonal and the products of that part of the column
+// with every later column:  S[c] = sum_{i > j} W[i][j] W[i][c],  so with
+// scale = 1 / (alpha - beta) the reflector v = (1, scale W[j+1:, j]) satisfies
+// v^T W[j:, c] = W[j][c] + scale S[c].  The reduction goes through an LDS transpose T[c][i]
+// (two barriers).  The column loop is unrolled at compile time, so every register index is
+// static.  The explicit Q is then accumulated backwards in the same registers.
+template <int PM, int NT, int RPT>
 __global__ void __launch_bounds__(NT) k_hqr_reg(const double* __restrict__ In, double* __restrict__ Out,
                                                 float* __restrict__ Out32, int n, int p, long bs)
 {
@@ -426,23 +456,30 @@ __global__ void __launch_bounds__(NT) k_hqr_reg(const double* __restrict__ In, d
     __shared__ double taus[PM];
     const int i = threadIdx.x;
     const long off = (long)blockIdx.x * n * p;
-    const bool live = i < n;
-    double w[PM];
+    double w[RPT][PM];
 #pragma unroll
-    for (int c = 0; c < PM; ++c) w[c] = (live && c < p) ? In[off + (long)i * p + c] : 0.0;
-    qr_forward<PM, NT, 0>(w, T, S, rowjb, taus, n, p);
+    for (int q = 0; q < RPT; ++q) {
+        const int row = i + q * NT;
+#pragma unroll
+        for (int c = 0; c < PM; ++c) w[q][c] = (row < n && c < p) ? In[off + (long)row * p + c] : 0.0;
+    }
+    qr_forward<PM, NT, RPT, 0>(w, T, S, rowjb, taus, n, p);
     // thread 0 wrote the last tau after the last barrier of the forward pass, and the backward
     // pass reads it first
     __syncthreads();
-    qr_backward<PM, NT, PM - 1>(w, T, S, taus, n, p);
-    if (live) {
+    qr_backward<PM, NT, RPT, PM - 1>(w, T, S, taus, n, p);
 #pragma unroll
-        for (int c = 0; c < PM; ++c)
-            if (c < p) Out[off + (long)i * p + c] = w[c];
-        if (Out32) {
+    for (int q = 0; q < RPT; ++q) {
+        const int row = i + q * NT;
+        if (row < n) {
 #pragma unroll
             for (int c = 0; c < PM; ++c)
-                if (c < p) Out32[off + (long)i * p + c] = (float)w[c];
+                if (c < p) Out[off + (long)row * p + c] = w[q][c];
+            if (Out32) {
+#pragma unroll
+                for (int c = 0; c < PM; ++c)
+                    if (c < p) Out32[off + (long)row * p + c] = (float)w[q][c];
+            }
         }
     }
 }
@@ -706,81 +743,96 @@ __global__ void __launch_bounds__(256) k_signfix_pair(double* __restrict__ U, in
     }
 }
 
-// Convergence test of the Ritz pairs (lam_j, u_j), j < r, of problem blockIdx.x:
+// Convergence test of the Ritz pairs (lam_j, u_j), j < r, of each problem:
 // rho_j = ||G u_j - lam_j u_j||_2 against max(tau lam_j, cfloor sqrt(n) u ||G||_F), u the FP64
 // unit roundoff.  The first term asks converged vectors of the large eigenvalues; below
 // cfloor sqrt(n) u ||G||_F / tau the test falls back to the rounding level of the product
 // G u itself, which no further iteration can go below.  flags[problem] = 1 when every column
-// passes (a NaN fails).  G is symmetric, so lane i reads column i of row k (coalesced); U is
-// staged in LDS RES_CB columns at a time.
-constexpr int RES_CB = 4;
-__global__ void __launch_bounds__(256) k_eig_residual(const double* __restrict__ G, long sG, int n,
-                                                      const double* __restrict__ U, long sU, int ldu, int r,
-                                                      const double* __restrict__ lam, long sL, double tau,
-                                                      double cfloor, int* __restrict__ flags, long bs)
+// passes (a NaN fails).
+// Two kernels.  k_eig_resid_part: work-group (problem, rb) takes rows rb*64 .. rb*64+63 of
+// G u (lane = row; the four waves split k into quarters, added in wave order), and writes
+// per column the sum over its rows of (G u - lam u)^2 and, in slot EIG_CHECK_COLS, its part of
+// ||G||_F^2 (G symmetric, so lane i reads column i of row k: coalesced).  k_eig_resid_flags
+// adds the parts in row-block order and applies the test, so the outcome does not depend on
+// scheduling.
+constexpr int RES_CB = 8;
+__global__ void __launch_bounds__(256) k_eig_resid_part(const double* __restrict__ G, long sG, int n,
+                                                        const double* __restrict__ U, long sU, int ldu, int r,
+                                                        const double* __restrict__ lam, long sL,
+                                                        double* __restrict__ part, long bs)
 {
     G = bshift(G, bs);
     U = bshift(U, bs);
     lam = bshift(lam, bs);
-    flags = bshift(flags, bs);
-    extern __shared__ double us[];   // n x RES_CB
-    __shared__ double red[4][RES_CB];
-    __shared__ double gnorm_s;
-    __shared__ int ok_s;
+    part = bshift(part, bs);
+    __shared__ double red[4][64][RES_CB + 1];
+    __shared__ double gred[4];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int rb = blockIdx.y;
     const double* g = G + blockIdx.x * sG;
     const double* u = U + blockIdx.x * sU;
     const double* l = lam + blockIdx.x * sL;
+    double* pp = part + (long)blockIdx.x * EIG_CHECK_DOUBLES + (long)rb * (EIG_CHECK_COLS + 1);
+    const int i = rb * 64 + lane;
+    const bool live = i < n;
+    const int kq = (n + 3) / 4;
+    const int k0 = wv * kq, k1 = min(n, k0 + kq);
     double gs = 0.0;
-    for (long e = tid; e < (long)n * n; e += 256) gs += g[e] * g[e];
-    gs = wave_sum(gs);
-    if (lane == 0) red[wv][0] = gs;
-    __syncthreads();
-    if (tid == 0) {
-        gnorm_s = sqrt((red[0][0] + red[1][0]) + (red[2][0] + red[3][0]));
-        ok_s = 1;
-    }
-    __syncthreads();
-    const double floor_level = cfloor * sqrt((double)n) * 2.220446049250313e-16 * gnorm_s;
     for (int c0 = 0; c0 < r; c0 += RES_CB) {
-        const int cb = min(RES_CB, r - c0);
-        for (int e = tid; e < n * RES_CB; e += 256) {
-            const int i = e / RES_CB, j = e % RES_CB;
-            us[e] = j < cb ? u[(long)i * ldu + c0 + j] : 0.0;
+        double y[RES_CB];
+#pragma unroll
+        for (int j = 0; j < RES_CB; ++j) y[j] = 0.0;
+        for (int k = k0; k < k1; ++k) {
+            const double gv = live ? g[(long)k * n + i] : 0.0;
+            if (c0 == 0) gs = fma(gv, gv, gs);
+            const double* uk = u + (long)k * ldu + c0;
+#pragma unroll
+            for (int j = 0; j < RES_CB; ++j) y[j] = fma(gv, (c0 + j < r) ? uk[j] : 0.0, y[j]);
         }
+#pragma unroll
+        for (int j = 0; j < RES_CB; ++j) red[wv][lane][j] = y[j];
         __syncthreads();
-        double acc[RES_CB];
-#pragma unroll
-        for (int j = 0; j < RES_CB; ++j) acc[j] = 0.0;
-        for (int i = tid; i < n; i += 256) {
-            double y[RES_CB];
-#pragma unroll
-            for (int j = 0; j < RES_CB; ++j) y[j] = 0.0;
-            for (int k = 0; k < n; ++k) {
-                const double gv = g[(long)k * n + i];
-#pragma unroll
-                for (int j = 0; j < RES_CB; ++j) y[j] = fma(gv, us[k * RES_CB + j], y[j]);
-            }
+        if (wv == 0) {
 #pragma unroll
             for (int j = 0; j < RES_CB; ++j) {
-                const double d = (j < cb) ? y[j] - l[c0 + (j < cb ? j : 0)] * us[i * RES_CB + j] : 0.0;
-                acc[j] = fma(d, d, acc[j]);
+                const double yy = ((red[0][lane][j] + red[1][lane][j]) + red[2][lane][j]) + red[3][lane][j];
+                const int c = c0 + j;
+                const double d = (live && c < r) ? yy - l[c] * u[(long)i * ldu + c] : 0.0;
+                const double sq = wave_sum(d * d);
+                if (lane == 0 && c < r) pp[c] = sq;
             }
-        }
-#pragma unroll
-        for (int j = 0; j < RES_CB; ++j) {
-            const double v = wave_sum(acc[j]);
-            if (lane == 0) red[wv][j] = v;
-        }
-        __syncthreads();
-        if (tid < cb) {
-            const double rho = sqrt((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]));
-            const double thr = fmax(tau * l[c0 + tid], floor_level);
-            if (!(rho <= thr)) ok_s = 0;
         }
         __syncthreads();
     }
-    if (tid == 0) flags[blockIdx.x] = ok_s;
+    gs = wave_sum(gs);
+    if (lane == 0) gred[wv] = gs;
+    __syncthreads();
+    if (tid == 0) pp[EIG_CHECK_COLS] = (gred[0] + gred[1]) + (gred[2] + gred[3]);
+}
+
+__global__ void __launch_bounds__(64) k_eig_resid_flags(const double* __restrict__ part, int n, int r,
+                                                        const double* __restrict__ lam, long sL, double tau,
+                                                        double cfloor, int* __restrict__ flags, long bs)
+{
+    part = bshift(part, bs);
+    lam = bshift(lam, bs);
+    flags = bshift(flags, bs);
+    const int lane = threadIdx.x;
+    const int nrb = (n + 63) / 64;
+    const double* pp = part + (long)blockIdx.x * EIG_CHECK_DOUBLES;
+    const double* l = lam + blockIdx.x * sL;
+    double g2 = 0.0;
+    for (int rb = 0; rb < nrb; ++rb) g2 += pp[(long)rb * (EIG_CHECK_COLS + 1) + EIG_CHECK_COLS];
+    const double floor_level = cfloor * sqrt((double)n) * 2.220446049250313e-16 * sqrt(g2);
+    int ok = 1;
+    for (int c = lane; c < r; c += 64) {
+        double s2 = 0.0;
+        for (int rb = 0; rb < nrb; ++rb) s2 += pp[(long)rb * (EIG_CHECK_COLS + 1) + c];
+        const double rho = sqrt(s2);
+        if (!(rho <= fmax(tau * l[c], floor_level))) ok = 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) ok = min(ok, __shfl_xor(ok, o, 64));
+    if (lane == 0) flags[blockIdx.x] = ok;
 }
 
 __global__ void k_trace(const double* __restrict__ G, long sG, int n, double* __restrict__ out, long sOut, long bs)
@@ -805,14 +857,16 @@ static hipError_t qr_launch(const double* in, double* out, int count, int n, int
                             float* out32 = nullptr)
 {
     const dim3 grid(count, 1, bt.nb);
-    if (n <= 512 && p <= 32) {
-        const int nt = n <= 256 ? 256 : 512;
+    if (n <= 1024 && p <= 32) {
+        const int nt = n <= 256 ? 256 : 512;     // rows per thread: 1 up to 512 rows, 2 above
+        const bool two = n > 512;
         const int pm = (p + 7) / 8 * 8;
         const size_t lds = sizeof(double) * (size_t)pm * nt;
 #define TK_QR_LAUNCH(PM)                                                                                         \
     do {                                                                                                        \
-        if (nt == 256) hipLaunchKernelGGL((k_hqr_reg<PM, 256>), grid, dim3(256), lds, s, in, out, out32, n, p, bt.bs); \
-        else hipLaunchKernelGGL((k_hqr_reg<PM, 512>), grid, dim3(512), lds, s, in, out, out32, n, p, bt.bs);          \
+        if (nt == 256) hipLaunchKernelGGL((k_hqr_reg<PM, 256, 1>), grid, dim3(256), lds, s, in, out, out32, n, p, bt.bs); \
+        else if (!two) hipLaunchKernelGGL((k_hqr_reg<PM, 512, 1>), grid, dim3(512), lds, s, in, out, out32, n, p, bt.bs); \
+        else hipLaunchKernelGGL((k_hqr_reg<PM, 512, 2>), grid, dim3(512), lds, s, in, out, out32, n, p, bt.bs);           \
     } while (0)
         switch (pm) {
         case 8: TK_QR_LAUNCH(8); break;
@@ -855,9 +909,12 @@ hipError_t eig_set_attributes()
     hipError_t e = hipFuncSetAttribute((const void*)k_hqr, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)QR_LDS_BYTES);
     if (e != hipSuccess) return e;
-    const void* ks[] = {(const void*)k_hqr_reg<24, 512>, (const void*)k_hqr_reg<32, 512>};
-    const int bytes[] = {(int)(sizeof(double) * 24 * 512), (int)(sizeof(double) * 32 * 512)};
-    for (int i = 0; i < 2; ++i)
+    // dynamic LDS of the register QR above 64 KB: PM x 512 doubles
+    const void* ks[] = {(const void*)k_hqr_reg<24, 512, 1>, (const void*)k_hqr_reg<32, 512, 1>,
+                        (const void*)k_hqr_reg<24, 512, 2>, (const void*)k_hqr_reg<32, 512, 2>};
+    const int bytes[] = {(int)(sizeof(double) * 24 * 512), (int)(sizeof(double) * 32 * 512),
+                         (int)(sizeof(double) * 24 * 512), (int)(sizeof(double) * 32 * 512)};
+    for (int i = 0; i < 4; ++i)
         if ((e = hipFuncSetAttribute(ks[i], hipFuncAttributeMaxDynamicSharedMemorySize, bytes[i])) != hipSuccess)
             return e;
     return hipSuccess;
@@ -906,7 +963,7 @@ static hipError_t eig_body(const EigBatch& b, int iters, hipStream_t s, bool& wr
         // span-only with a compact U: the last QR writes the factor itself
         const bool direct = b.span_only && p == r && iters > 0 && b.ldu == p && (b.count == 1 || b.sU == np_);
         // the FP32 copy comes out of the last QR when it writes the factor in place
-        const bool direct32 = direct && b.U32 && b.count == 1 && p <= 32 && n <= 512;
+        const bool direct32 = direct && b.U32 && b.count == 1 && p <= 32 && n <= 1024;
         for (int it = 0; it < iters; ++it) {
             GemmArgs g = gq;
             if (it == 0 && warm_direct) { g.B = b.warm; g.sBb = b.sW; g.sBk = b.ldw; g.sBn = 1; }
@@ -992,13 +1049,17 @@ hipError_t launch_interp_factor(const double* Uc, int nc, double x0c, double hc,
     return hipGetLastError();
 }
 
-hipError_t launch_eig_check(const EigBatch& b, double tau, double cfloor, int* flags, hipStream_t s)
+hipError_t launch_eig_check(const EigBatch& b, double tau, double cfloor, int* flags, double* part, hipStream_t s)
 {
-    if (b.n < 1 || b.n > 1024 || b.r < 1) return hipErrorInvalidValue;
+    if (b.n < 1 || b.n > EIG_CHECK_NMAX || b.r < 1 || b.r > EIG_CHECK_COLS) return hipErrorInvalidValue;
     const int nb = b.nb > 1 ? b.nb : 1;
-    const size_t lds = sizeof(double) * (size_t)b.n * RES_CB;
-    hipLaunchKernelGGL(k_eig_residual, dim3(b.count, 1, nb), dim3(256), lds, s, b.G, b.sG, b.n, b.U, b.sU, b.ldu,
-                       b.r, b.lam, b.sL, tau, cfloor, flags, b.bs);
+    const int nrb = (b.n + 63) / 64;
+    hipLaunchKernelGGL(k_eig_resid_part, dim3(b.count, nrb, nb), dim3(256), 0, s, b.G, b.sG, b.n, b.U, b.sU, b.ldu,
+                       b.r, b.lam, b.sL, part, b.bs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_eig_resid_flags, dim3(b.count, 1, nb), dim3(64), 0, s, (const double*)part, b.n, b.r, b.lam,
+                       b.sL, tau, cfloor, flags, b.bs);
     return hipGetLastError();
 }
 

@@ -535,6 +535,7 @@ struct Work {
     // eps truncation (float paths)
     double *Gc, *Vc, *lamc, *tQ, *tY, *tH, *tVs, *coreA, *coreB, *Urot[3];
     int* eflags;             // eigensolver convergence flags (FP64 path)
+    double* eres;            // ... and the partial residual sums of their test
     int nparts;
     Bat bt;                  // problems sharing this layout, bt.bs bytes apart (pointers: problem 0)
     tk_ctx* ctx = nullptr;   // for the FP64 path's convergence readbacks
@@ -597,6 +598,7 @@ void layout_work(Arena& ar, const Plan& P, bool own_A, Work& w)
     w.coreB = ar.take<double>((size_t)R[0] * R[1] * R[2]);
     for (int k = 0; k < 3; ++k) w.Urot[k] = ar.take<double>((size_t)n[k] * R[k]);
     w.eflags = ar.take<int>(64);
+    w.eres = ar.take<double>(3 * (size_t)EIG_CHECK_DOUBLES);   // eigen batches of at most 3 here
 }
 
 size_t result_bytes(const int n[3], const int r[3])
@@ -707,7 +709,7 @@ tk_status eig_converge(const EigBatch& b, Work& w, hipStream_t s)
 {
     if (b.span_only || b.p >= b.n || b.count > 64 || !w.ctx) return TK_OK;
     for (int round = 0;; ++round) {
-        TK_LAUNCH(launch_eig_check(b, EIG_TAU, EIG_CFLOOR, w.eflags, s));
+        TK_LAUNCH(launch_eig_check(b, EIG_TAU, EIG_CFLOOR, w.eflags, w.eres, s));
         int fl[64];
         tk_status st = readback(w.ctx, s, w.eflags, sizeof(int) * (size_t)b.count, fl);
         if (st != TK_OK) return st;
@@ -2352,6 +2354,7 @@ tk_status tk_compress_sinc(tk_ctx* ctx, const tk_kernel* kernel, const tk_grid* 
     const int pmax = (nmax <= EIG_PMAX) ? nmax : std::min(rmax + 8, EIG_PMAX);
     double *t, *w, *Q[3], *Gq[3], *S, *P[3], *Ga, *Gb, *Wg, *T1, *KR, *core, *V[3], *eQ, *eY, *eH, *eVs, *lam, *scal;
     int* eflags;
+    double* eres;
     auto lay = [&](Arena& ar) {
         t = ar.take<double>(R);
         w = ar.take<double>(R);
@@ -2373,6 +2376,7 @@ tk_status tk_compress_sinc(tk_ctx* ctx, const tk_kernel* kernel, const tk_grid* 
         lam = ar.take<double>(64);
         scal = ar.take<double>(16);
         eflags = ar.take<int>(64);
+        eres = ar.take<double>(EIG_CHECK_DOUBLES);   // one eigenproblem at a time
     };
     Arena plan;
     lay(plan);
@@ -2386,6 +2390,7 @@ tk_status tk_compress_sinc(tk_ctx* ctx, const tk_kernel* kernel, const tk_grid* 
     Work wk{};
     wk.ctx = ctx;
     wk.eflags = eflags;
+    wk.eres = eres;
     // leading r_a eigenvectors of the n_a x n_a matrix S into V[a] (FP64, iterated to the
     // residual test like every FP64 eigensolve)
     auto eig_into = [&](int a) -> tk_status {
@@ -3123,7 +3128,8 @@ tk_status tk_eig_topr(tk_ctx* ctx, int count, int n, int r, const double* G_dev,
     (void)hipGetLastError();
     hipStream_t s = (hipStream_t)hip_stream;
     int p = (n <= EIG_PMAX) ? n : std::min(r + 8, EIG_PMAX);
-    size_t need = sizeof(double) * (size_t)count * (2 * (size_t)n * p + 2 * (size_t)p * p + 64) + 8192;
+    size_t need = sizeof(double) * ((size_t)count * (2 * (size_t)n * p + 2 * (size_t)p * p + 64) +
+                                    64 * (size_t)EIG_CHECK_DOUBLES) + 8192;
     Reservation res(ctx, need);
     if (!res.take()) return fail(TK_ENOMEM, "eig needs %zu bytes", need);
     Ws wsp;
@@ -3145,6 +3151,7 @@ tk_status tk_eig_topr(tk_ctx* ctx, int count, int n, int r, const double* G_dev,
     Work w{};
     w.ctx = ctx;
     w.eflags = ar.take<int>(64);
+    w.eres = ar.take<double>(64 * (size_t)EIG_CHECK_DOUBLES);
     for (int c0 = 0; c0 < count; c0 += 64) {
         EigBatch bc = b;
         bc.count = std::min(64, count - c0);
@@ -3201,7 +3208,7 @@ tk_status kron1_inverses(tk_kron1* k, hipStream_t s)
         p += align_up(sizeof(double) * (size_t)n * n, 256);
         double* Ci = (double*)p;
         p += align_up(sizeof(double) * (size_t)n * n, 256);
-        TK_LAUNCH(launch_trinv(k->L[a], n, Li, s));
+        TK_LAUNCH(launch_trinv(k->L[a], n, Li, Ci, s));   // Ci (n x n) is free until the product below
         // C^-1 = Li^T Li
         GemmArgs g = gemm(n, n, n, 1, Li, 0, 1, n, Li, 0, n, 1, Ci, 0, n, 1);
         TK_LAUNCH((launch_gemm<double, double, double>(g, s)));

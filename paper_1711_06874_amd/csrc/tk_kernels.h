@@ -126,8 +126,12 @@ struct EigBatch {
 hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s);
 // Convergence test of the r Ritz pairs (lam, U) of each problem of b against its G:
 // flags[c] (c < count, moving by bs per batched problem) = 1 when every column has
-// ||G u_j - lam_j u_j|| <= max(tau lam_j, cfloor sqrt(n) u ||G||_F), else 0.  n <= 1024.
-hipError_t launch_eig_check(const EigBatch& b, double tau, double cfloor, int* flags, hipStream_t s);
+// ||G u_j - lam_j u_j|| <= max(tau lam_j, cfloor sqrt(n) u ||G||_F), else 0.  n <= 1024,
+// r <= 48; `part` holds count * EIG_CHECK_DOUBLES doubles of partial sums (moving by bs).
+constexpr int EIG_CHECK_NMAX = 1024;
+constexpr int EIG_CHECK_COLS = 48;
+constexpr int EIG_CHECK_DOUBLES = (EIG_CHECK_NMAX / 64) * (EIG_CHECK_COLS + 1);
+hipError_t launch_eig_check(const EigBatch& b, double tau, double cfloor, int* flags, double* part, hipStream_t s);
 // ------------------------------------------- separable covariance (rank-1 Kronecker) ----
 // C (n x n, row-major) = k(|x_i - x_j|) + nugget on the diagonal, x_i = x0 + i h.
 hipError_t launch_cov1d(double* C, int n, double x0, double h, const KernelParams& kp, double nugget, hipStream_t s);
@@ -137,7 +141,8 @@ size_t cholesky_work_bytes(int n);
 hipError_t launch_cholesky(double* A, int n, void* work, int* info, hipStream_t s);
 // out[0] = 2 sum log L_ii;  X = L^-1 (lower-triangular, n x n)
 hipError_t launch_logdet_chol(const double* L, int n, double* out, hipStream_t s);
-hipError_t launch_trinv(const double* L, int n, double* X, hipStream_t s);
+// work: 64 x n doubles
+hipError_t launch_trinv(const double* L, int n, double* X, double* work, hipStream_t s);
 
 // Householder QR of `count` n x p row-major blocks (consecutive): out = the explicit orthonormal
 // factor (in == out allowed).  p <= EIG_PMAX.

@@ -183,6 +183,26 @@ def test_eig_topr(ctx, tk, oracle, n, r):
             assert np.abs(U_g[:, j] - V_o[:, j]).max() <= bound, (j, gap / l1)
 
 
+@pytest.mark.parametrize("n,r", [(640, 24), (1000, 12), (1024, 20)])
+def test_eig_topr_large(ctx, tk, oracle, n, r):
+    """Blocks of 513-1024 rows: the register QR holds two rows per thread.  Reference: LAPACK's
+    symmetric eigensolver (numpy.linalg.eigh) on the oracle's Gram."""
+    say("eig large", n, r)
+    A = oracle.grid_eval(oracle.Kernel(oracle.MATERN, nu=1.5, ell=0.3),
+                         oracle.Grid(n=(n, 16, 12), layout=oracle.CENTERED))
+    G = oracle.gram(A, 0)
+    w, V = np.linalg.eigh(G)
+    lam_o, V_o = w[::-1], V[:, ::-1]
+    lam = torch.empty(r, dtype=torch.float64, device="cuda")
+    U = torch.empty((n, r), dtype=torch.float64, device="cuda")
+    tk.tk_eig_topr(ctx.handle, 1, n, r, dev(G), lam, U)
+    lam_g, U_g = host(lam), host(U)
+    l1 = lam_o[0]
+    np.testing.assert_allclose(lam_g, lam_o[:r], rtol=0, atol=1e-12 * l1)
+    assert np.abs(U_g.T @ U_g - np.eye(r)).max() < 1e-12
+    assert np.abs(G @ U_g - U_g * lam_g).max() <= 1e-11 * l1
+
+
 def test_eig_batched_matches_single(ctx, tk, oracle):
     n, r = 96, 10
     Gs = []
