@@ -157,7 +157,7 @@ def row_kron1(tk, ctx, reps):
                            "frac_fp64_mfma": flops / ms / 1e9 / FP64_MFMA_TFS}
     n2 = 512
     kern2 = tk.make_kernel(tk.TK_MATERN, nu=1.5, ell=0.3)
-    k2 = tk.Kron1(ctx, [kern2] * 3, tk.make_grid(n2, 1.0), (1e-6, 1e-6, 1e-6))
+    k2 = tk.Kron1(ctx, [kern2] * 3, tk.make_grid(n2, 1.0), (1e-2, 1e-2, 1e-2))
     z32 = torch.empty((n2, n2, n2), dtype=torch.float32, device="cuda")
     tk.tk_normal_fill(ctx.handle, 1711, 1, z32)
     z = z32.double()
