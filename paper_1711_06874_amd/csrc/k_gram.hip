@@ -288,43 +288,60 @@ __global__ void __launch_bounds__(NT) k_gram_big(const float* __restrict__ A, Un
         }
     };
 
-    if (kbeg < kend) gload(kbeg);
-    for (long k0 = kbeg; k0 < kend; k0 += BKG) {
-        __syncthreads();
-        sstore();
-        __syncthreads();
-        if (k0 + BKG < kend) gload(k0 + BKG);     // the next chunk, in flight during the products
-        const float* Bp = diag ? As : Bs;
-        const int li = lane & 31, h = lane >> 5;
-        if (MODE == 2) {
+    // The K loop, in three copies by the wave's role (chosen once, outside the loop, so the loop
+    // body has no branches): ROLE 0 forms all four 32 x 32 blocks; in diagonal tiles the
+    // reduction reads only the upper half, so waves 0 and 3 (diagonal 64 x 64 blocks) leave out
+    // block (1, 0) (ROLE 1) and wave 2 (rows 64-127 x columns 0-63) forms nothing (ROLE 2).
+    // Every wave stages its share of the tiles and meets the same barriers; the skipped
+    // accumulators stay zero in the partial.
+    auto kloop = [&](auto rolec) {
+        constexpr int ROLE = decltype(rolec)::value;
+        if (kbeg < kend) gload(kbeg);
+        for (long k0 = kbeg; k0 < kend; k0 += BKG) {
+            __syncthreads();
+            sstore();
+            __syncthreads();
+            if (k0 + BKG < kend) gload(k0 + BKG);     // the next chunk, in flight during the products
+            if constexpr (ROLE < 2) {
+                const float* Bp = diag ? As : Bs;
+                const int li = lane & 31, h = lane >> 5;
+                if (MODE == 2) {
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int kr = (16 * h + j) * SL;
-                const float a0 = As[kr + wm + li], a1 = As[kr + wm + 32 + li];
-                const float b0 = Bp[kr + wn + li], b1 = Bp[kr + wn + 32 + li];
-                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
-                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
-                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
-                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
-            }
-        } else {
+                    for (int j = 0; j < 16; ++j) {
+                        const int kr = (16 * h + j) * SL;
+                        const float a0 = As[kr + wm + li], a1 = As[kr + wm + 32 + li];
+                        const float b0 = Bp[kr + wn + li], b1 = Bp[kr + wn + 32 + li];
+                        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+                        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+                        if constexpr (ROLE == 0)
+                            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+                        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+                    }
+                } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int kc = 16 * h + 4 * q;
-                const f32x4 av0 = *reinterpret_cast<const f32x4*>(&As[(wm + li) * SL + kc]);
-                const f32x4 av1 = *reinterpret_cast<const f32x4*>(&As[(wm + 32 + li) * SL + kc]);
-                const f32x4 bv0 = *reinterpret_cast<const f32x4*>(&Bp[(wn + li) * SL + kc]);
-                const f32x4 bv1 = *reinterpret_cast<const f32x4*>(&Bp[(wn + 32 + li) * SL + kc]);
+                    for (int q = 0; q < 4; ++q) {
+                        const int kc = 16 * h + 4 * q;
+                        const f32x4 av0 = *reinterpret_cast<const f32x4*>(&As[(wm + li) * SL + kc]);
+                        const f32x4 av1 = *reinterpret_cast<const f32x4*>(&As[(wm + 32 + li) * SL + kc]);
+                        const f32x4 bv0 = *reinterpret_cast<const f32x4*>(&Bp[(wn + li) * SL + kc]);
+                        const f32x4 bv1 = *reinterpret_cast<const f32x4*>(&Bp[(wn + 32 + li) * SL + kc]);
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av0[t], bv0[t], acc[0][0], 0, 0, 0);
-                    acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av0[t], bv1[t], acc[0][1], 0, 0, 0);
-                    acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av1[t], bv0[t], acc[1][0], 0, 0, 0);
-                    acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av1[t], bv1[t], acc[1][1], 0, 0, 0);
+                        for (int t = 0; t < 4; ++t) {
+                            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av0[t], bv0[t], acc[0][0], 0, 0, 0);
+                            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av0[t], bv1[t], acc[0][1], 0, 0, 0);
+                            if constexpr (ROLE == 0)
+                                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av1[t], bv0[t], acc[1][0], 0, 0, 0);
+                            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av1[t], bv1[t], acc[1][1], 0, 0, 0);
+                        }
+                    }
                 }
             }
         }
-    }
+    };
+    const int role = !diag ? 0 : (wave == 2 ? 2 : (wave == 1 ? 0 : 1));
+    if (role == 0) kloop(std::integral_constant<int, 0>{});
+    else if (role == 1) kloop(std::integral_constant<int, 1>{});
+    else kloop(std::integral_constant<int, 2>{});
 
     // the BG x BG partial (row-major) of this (pair, split)
     float* P = partials + ((long)pidx * nsplit + split) * (BG * BG);
