@@ -69,7 +69,7 @@ constexpr int COLD_ITERS = 3;         // subspace iterations from a random start
 constexpr int COLD_ITERS_F32 = 2;     // ... float paths (HOOI refines the subspaces anyway)
 constexpr int WARM_ITERS = 2;         // ... from the previous factor (FP64 path: exact HOOI steps)
 constexpr int WARM_ITERS_F32 = 1;     // ... float paths: one block power step per HOOI update
-constexpr int SPAN_ITERS_F32 = 3;     // float eps path, HOSVD start: R-column block, subspace only
+constexpr int SPAN_ITERS_F32 = 2;     // float eps path, HOSVD start: R-column block, subspace only
 constexpr int NMAX = 1024;
 constexpr double MATERN_NU_MAX = 30.0;
 constexpr int KRON1_NMAX = 16384;       // points per axis of a separable covariance factor   // general orders: K_nu s^nu stays inside the double range
