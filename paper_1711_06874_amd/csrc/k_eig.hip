@@ -963,7 +963,7 @@ static hipError_t eig_body(const EigBatch& b, int iters, hipStream_t s, bool& wr
         // span-only with a compact U: the last QR writes the factor itself
         const bool direct = b.span_only && p == r && iters > 0 && b.ldu == p && (b.count == 1 || b.sU == np_);
         // the FP32 copy comes out of the last QR when it writes the factor in place
-        const bool direct32 = direct && b.U32 && b.count == 1 && p <= 32 && n <= 1024;
+        const bool direct32 = direct && b.U32 && p <= 32 && n <= 1024;   // U32 strided like U (n p)
         for (int it = 0; it < iters; ++it) {
             GemmArgs g = gq;
             if (it == 0 && warm_direct) { g.B = b.warm; g.sBb = b.sW; g.sBk = b.ldw; g.sBn = 1; }

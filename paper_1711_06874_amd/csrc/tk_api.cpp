@@ -540,6 +540,7 @@ struct Work {
     Bat bt;                  // problems sharing this layout, bt.bs bytes apart (pointers: problem 0)
     tk_ctx* ctx = nullptr;   // for the FP64 path's convergence readbacks
     bool noconv = false;     // an FP64 eigensolve stopped at its iteration cap
+    bool u32_fresh = false;  // the HOSVD eigensolve wrote U32 itself (no conversion needed)
 };
 
 void layout_work(Arena& ar, const Plan& P, bool own_A, Work& w)
@@ -569,9 +570,22 @@ void layout_work(Arena& ar, const Plan& P, bool own_A, Work& w)
     w.Y = ar.take<double>(3 * (size_t)nmax * pmax);
     w.H = ar.take<double>(3 * (size_t)pmax * pmax);
     w.Vs = ar.take<double>(3 * (size_t)pmax * pmax);
-    for (int k = 0; k < 3; ++k) {
-        w.U[k] = ar.take<double>((size_t)n[k] * R[k]);
-        w.U32[k] = ar.take<float>((size_t)n[k] * R[k]);
+    // equal n R on every axis with 256-byte multiples: the three factors (and their FP32 copies)
+    // back to back, so one batched eigensolve writes them in place (eig_modes)
+    const size_t nr = (size_t)n[0] * R[0];
+    const bool packed = n[1] * R[1] == (int)nr && n[2] * R[2] == (int)nr && (nr * sizeof(float)) % 256 == 0;
+    if (packed) {
+        double* Ub = ar.take<double>(3 * nr);
+        float* Ub32 = ar.take<float>(3 * nr);
+        for (int k = 0; k < 3; ++k) {
+            w.U[k] = Ub + k * nr;
+            w.U32[k] = Ub32 + k * nr;
+        }
+    } else {
+        for (int k = 0; k < 3; ++k) {
+            w.U[k] = ar.take<double>((size_t)n[k] * R[k]);
+            w.U32[k] = ar.take<float>((size_t)n[k] * R[k]);
+        }
     }
     w.lam = ar.take<double>(3 * 64);
     w.trace = ar.take<double>(3);
@@ -746,8 +760,13 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
         if (span && P.R[0] < P.n[0]) { b.p = P.R[0]; b.span_only = 1; }
         b.G = w.G; b.sG = (long)nmax * nmax;
         b.Q = w.Q; b.Y = w.Y; b.H = w.H; b.Vs = w.Vs;
-        // U[0..2] are laid out consecutively only per arena; use a staging area then copy
-        b.U = w.Y; b.sU = (long)P.n[0] * P.R[0]; b.ldu = P.R[0];
+        // the factors are written in place when layout_work packed them back to back, else into a
+        // staging area and copied
+        const long nr = (long)P.n[0] * P.R[0];
+        const bool packed = w.U[1] == w.U[0] + nr && w.U[2] == w.U[1] + nr && w.U32[1] == w.U32[0] + nr &&
+                            w.U32[2] == w.U32[1] + nr;
+        b.U = packed ? w.U[0] : w.Y; b.sU = nr; b.ldu = P.R[0];
+        if (packed && P.prec != TK_FP64) b.U32 = w.U32[0];
         b.lam = w.lam; b.sL = 64;
         b.trace = w.trace; b.sTrace = 1;
         b.nb = w.bt.nb; b.bs = w.bt.bs;
@@ -760,8 +779,12 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
             tk_status st = eig_converge(b, w, s);
             if (st != TK_OK) return st;
         }
-        for (int k = 0; k < 3; ++k)
-            TK_LAUNCH(launch_copy_f64(w.Y + (long)k * P.n[0] * P.R[0], w.U[k], (long)P.n[0] * P.R[0], s, w.bt));
+        if (packed) {
+            w.u32_fresh = (b.U32 != nullptr);
+        } else {
+            for (int k = 0; k < 3; ++k)
+                TK_LAUNCH(launch_copy_f64(w.Y + (long)k * nr, w.U[k], nr, s, w.bt));
+        }
     } else {
         for (int k = 0; k < 3; ++k) {
             EigBatch b{};
@@ -1369,8 +1392,9 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void
             }
             P = Q;
         }
-        for (int k = 0; k < 3; ++k)
-            if ((st = refresh_u32<Real>(P, w, k, s)) != TK_OK) return st;
+        if (!w.u32_fresh)
+            for (int k = 0; k < 3; ++k)
+                if ((st = refresh_u32<Real>(P, w, k, s)) != TK_OK) return st;
 
         // ---- HOOI sweeps, then the core
         if (P.sweeps == 0) {
