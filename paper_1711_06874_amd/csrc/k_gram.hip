@@ -211,26 +211,25 @@ __global__ void __launch_bounds__(NT) k_gram_tiles(const T* __restrict__ A, Unfo
 constexpr int BG = 128;
 constexpr int BKG = 32;
 
+// LDS of one large-tile work-group: the two tiles, sized for the widest mode layout
+constexpr int BIG_LDS = (BG * (BKG + 4) > BKG * (BG + 4)) ? BG * (BKG + 4) : BKG * (BG + 4);
+
+// Work-group b of one mode's large-tile Gram (npairs x nsplit work-groups; A and partials already
+// moved to the batched problem).
 template <int MODE>
-__global__ void __launch_bounds__(NT) k_gram_big(const float* __restrict__ A, Unfold<MODE> u, int nrow, long K,
-                                                 long kchunk, int T_tiles, int npairs,
-                                                 float* __restrict__ partials, long bs)
+__device__ __forceinline__ void gram_big_body(float* __restrict__ As, float* __restrict__ Bs,
+                                              const float* __restrict__ A, const Unfold<MODE>& u, int nrow, long K,
+                                              long kchunk, int T_tiles, int npairs, int nsplit,
+                                              float* __restrict__ partials, int b)
 {
-    constexpr int SM = (MODE == 2) ? BKG : BG;           // LDS rows
     constexpr int SL = (MODE == 2) ? BG + 4 : BKG + 4;   // LDS row stride (floats)
-    __shared__ __attribute__((aligned(16))) float As[SM * SL];
-    __shared__ __attribute__((aligned(16))) float Bs[SM * SL];
-    A = bshift(A, bs);
-    partials = bshift(partials, bs);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // blocks b with equal b mod 8 share an XCD: the npairs tile pairs of split
     // (b mod 8) + 8 floor(b / (8 npairs)) are consecutive blocks of one XCD
-    const int b = blockIdx.x;
     const int xcd = b & 7, l = b >> 3;
     const int grp = l / npairs;
     const int pidx = l - grp * npairs;
     const int split = xcd + 8 * grp;
-    const int nsplit = (int)(gridDim.x / npairs);
     int ti, tj;
     pair_of(pidx, T_tiles, ti, tj);
     const bool diag = (ti == tj);
@@ -357,6 +356,46 @@ __global__ void __launch_bounds__(NT) k_gram_big(const float* __restrict__ A, Un
             }
 }
 
+template <int MODE>
+__global__ void __launch_bounds__(NT) k_gram_big(const float* __restrict__ A, Unfold<MODE> u, int nrow, long K,
+                                                 long kchunk, int T_tiles, int npairs,
+                                                 float* __restrict__ partials, long bs)
+{
+    __shared__ __attribute__((aligned(16))) float As[BIG_LDS];
+    __shared__ __attribute__((aligned(16))) float Bs[BIG_LDS];
+    gram_big_body<MODE>(As, Bs, bshift(A, bs), u, nrow, K, kchunk, T_tiles, npairs, (int)(gridDim.x / npairs),
+                        bshift(partials, bs), (int)blockIdx.x);
+}
+
+// The three mode Grams of one tensor in one launch: work-groups [first[m], first[m + 1]) are
+// those of mode m (each range a multiple of 8, so a work-group keeps the XCD it has in the
+// launch of its mode alone, and every partial is the same).
+struct Gram3Args {
+    Unfold<0> u0;
+    Unfold<1> u1;
+    Unfold<2> u2;
+    int nrow[3], T_tiles[3], npairs[3], nsplit[3], first[4];
+    long K[3], kchunk[3];
+    float* partials[3];
+};
+
+__global__ void __launch_bounds__(NT) k_gram_big3(const float* __restrict__ A, Gram3Args g, long bs)
+{
+    __shared__ __attribute__((aligned(16))) float As[BIG_LDS];
+    __shared__ __attribute__((aligned(16))) float Bs[BIG_LDS];
+    A = bshift(A, bs);
+    const int b = (int)blockIdx.x;
+    if (b < g.first[1])
+        gram_big_body<0>(As, Bs, A, g.u0, g.nrow[0], g.K[0], g.kchunk[0], g.T_tiles[0], g.npairs[0], g.nsplit[0],
+                         bshift(g.partials[0], bs), b);
+    else if (b < g.first[2])
+        gram_big_body<1>(As, Bs, A, g.u1, g.nrow[1], g.K[1], g.kchunk[1], g.T_tiles[1], g.npairs[1], g.nsplit[1],
+                         bshift(g.partials[1], bs), b - g.first[1]);
+    else
+        gram_big_body<2>(As, Bs, A, g.u2, g.nrow[2], g.K[2], g.kchunk[2], g.T_tiles[2], g.npairs[2], g.nsplit[2],
+                         bshift(g.partials[2], bs), b - g.first[2]);
+}
+
 // ----------------------------------------------------------------------------------------
 // BF16x3 tiles.  LDS holds [BM][BK + 8] bf16 hi and lo parts (row-major, so that each lane
 // reads its 8 consecutive k values with one 16-byte load).
@@ -456,17 +495,14 @@ __global__ void __launch_bounds__(NT) k_gram_tiles_bf16x3(const float* __restric
 // summed by 4 threads (thread g takes splits g, g + 4, g + 8, ... in order) and the four
 // sums are added in the fixed order g = 0, 1, 2, 3, so the result does not depend on timing.
 template <typename T, int TB>
-__global__ void __launch_bounds__(256) k_gram_reduce(const T* __restrict__ partials, int T_tiles,
-                                                     int nsplit, int nrow, double* __restrict__ G, long bs)
+__device__ __forceinline__ void gram_reduce_body(const T* __restrict__ partials, int T_tiles, int nsplit, int nrow,
+                                                 double* __restrict__ G, int pidx, int bx)
 {
     __shared__ double part[4][64];
-    partials = bshift(partials, bs);
-    G = bshift(G, bs);
-    const int pidx = blockIdx.y;
     int ti, tj;
     pair_of(pidx, T_tiles, ti, tj);
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int e = blockIdx.x * 64 + lane;             // entry within the tile
+    const int e = bx * 64 + lane;                     // entry within the tile
     const T* P = partials + (long)pidx * nsplit * (TB * TB) + e;
     double s = 0.0;
     for (int q = g; q < nsplit; q += 4) s += (double)P[(long)q * (TB * TB)];
@@ -480,6 +516,27 @@ __global__ void __launch_bounds__(256) k_gram_reduce(const T* __restrict__ parti
     const double v = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
     G[(long)gi * nrow + gj] = v;
     G[(long)gj * nrow + gi] = v;
+}
+
+template <typename T, int TB>
+__global__ void __launch_bounds__(256) k_gram_reduce(const T* __restrict__ partials, int T_tiles,
+                                                     int nsplit, int nrow, double* __restrict__ G, long bs)
+{
+    gram_reduce_body<T, TB>(bshift(partials, bs), T_tiles, nsplit, nrow, bshift(G, bs), (int)blockIdx.y,
+                            (int)blockIdx.x);
+}
+
+// The reductions of the three modes of k_gram_big3 in one launch: blockIdx.y runs over the tile
+// pairs of mode 0, then 1, then 2.
+__global__ void __launch_bounds__(256) k_gram_reduce3(Gram3Args g, double* __restrict__ G0, double* __restrict__ G1,
+                                                      double* __restrict__ G2, long bs)
+{
+    const int y = (int)blockIdx.y;
+    const int m = (y < g.npairs[0]) ? 0 : (y < g.npairs[0] + g.npairs[1] ? 1 : 2);
+    const int pidx = y - (m > 0 ? g.npairs[0] : 0) - (m > 1 ? g.npairs[1] : 0);
+    double* G = (m == 0) ? G0 : (m == 1 ? G1 : G2);
+    gram_reduce_body<float, BG>(bshift((const float*)g.partials[m], bs), g.T_tiles[m], g.nsplit[m], g.nrow[m],
+                                bshift(G, bs), pidx, (int)blockIdx.x);
 }
 
 struct GramPlan {
@@ -652,6 +709,52 @@ static hipError_t launch_mode(const void* A, const int n[3], int prec, double* G
     else
         hipLaunchKernelGGL((k_gram_reduce<float, BM>), rgrid, dim3(256), 0, s, (const float*)work, p.T_tiles,
                            p.nsplit, p.nrow, G, bt.bs);
+    return hipGetLastError();
+}
+
+bool gram3_eligible(const int n[3], int prec, const int codes[3])
+{
+    for (int k = 0; k < 3; ++k)
+        if (!use_big(n, k, prec, codes[k])) return false;
+    return true;
+}
+
+size_t gram3_work_bytes(const int n[3], int prec, const int codes[3])
+{
+    size_t t = 0;
+    for (int k = 0; k < 3; ++k) t += (gram_work_bytes(n, k, prec, codes[k]) + 255) / 256 * 256;
+    return t;
+}
+
+hipError_t launch_gram3(const void* A, const int n[3], int prec, double* G, long sG, void* work, hipStream_t s,
+                        Bat bt, const int codes[3])
+{
+    if (bt.nb < 1 || !gram3_eligible(n, prec, codes)) return hipErrorInvalidValue;
+    Gram3Args g;
+    g.u0.n1n2 = g.u1.n1n2 = g.u2.n1n2 = (long)n[1] * n[2];
+    g.u0.n1 = g.u1.n1 = g.u2.n1 = n[1];
+    g.u0.n2 = g.u1.n2 = g.u2.n2 = n[2];
+    char* wp = (char*)work;
+    g.first[0] = 0;
+    int npairs_total = 0;
+    for (int k = 0; k < 3; ++k) {
+        const GramPlan p = make_plan_big(n, k, split_of(codes[k]));
+        g.nrow[k] = p.nrow;
+        g.T_tiles[k] = p.T_tiles;
+        g.npairs[k] = p.npairs;
+        g.nsplit[k] = p.nsplit;
+        g.K[k] = p.K;
+        g.kchunk[k] = p.kchunk;
+        g.partials[k] = (float*)wp;
+        wp += ((size_t)p.npairs * p.nsplit * BG * BG * 4 + 255) / 256 * 256;
+        g.first[k + 1] = g.first[k] + p.npairs * p.nsplit;
+        npairs_total += p.npairs;
+    }
+    hipLaunchKernelGGL(k_gram_big3, dim3((unsigned)g.first[3], 1, bt.nb), dim3(NT), 0, s, (const float*)A, g, bt.bs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gram_reduce3, dim3(BG * BG / 64, npairs_total, bt.nb), dim3(256), 0, s, g, G, G + sG,
+                       G + 2 * sG, bt.bs);
     return hipGetLastError();
 }
 

@@ -555,6 +555,7 @@ void layout_work(Arena& ar, const Plan& P, bool own_A, Work& w)
     w.A = own_A ? (void*)ar.take<char>(N * esz) : nullptr;
     size_t gw = 0;
     for (int k = 0; k < 3; ++k) gw = std::max(gw, gram_work_bytes(n, k, P.prec, P.gsplit[k]));
+    if (gram3_eligible(n, P.prec, P.gsplit)) gw = std::max(gw, gram3_work_bytes(n, P.prec, P.gsplit));
     {
         // the FP64 projected Grams of the HOOI sweep and the core Grams use the same workspace
         const int R0 = P.R[0], R1 = P.R[1], R2 = P.R[2];
@@ -1360,10 +1361,17 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void
                 TK_LAUNCH(launch_copy_f64(P.init_U[k], w.U[k], (long)P.n[k] * P.R[k], s));
             TK_LAUNCH(launch_dot<Real>(A, A, (long)P.n[0] * P.n[1] * P.n[2], w.partials, 1024, w.trace, s));
         } else {
-            // ---- HOSVD: Grams and leading eigenvectors
-            for (int k = 0; k < 3; ++k) {
+            // ---- HOSVD: Grams (one launch for the three modes when all take the large-tile
+            // kernel) and leading eigenvectors
+            if (gram3_eligible(P.n, P.prec, P.gsplit)) {
                 ProfScope ps(TK_PROF_GRAM, s);
-                TK_LAUNCH(launch_gram(A, P.n, k, P.prec, w.G + (long)k * nmax * nmax, w.gram_work, s, w.bt, P.gsplit[k]));
+                TK_LAUNCH(launch_gram3(A, P.n, P.prec, w.G, (long)nmax * nmax, w.gram_work, s, w.bt, P.gsplit));
+            } else {
+                for (int k = 0; k < 3; ++k) {
+                    ProfScope ps(TK_PROF_GRAM, s);
+                    TK_LAUNCH(launch_gram(A, P.n, k, P.prec, w.G + (long)k * nmax * nmax, w.gram_work, s, w.bt,
+                                          P.gsplit[k]));
+                }
             }
             if ((st = eig_modes(P, w, nmax, s)) != TK_OK) return st;
         }

@@ -83,6 +83,13 @@ int gram_split_candidates(const int n[3], int mode, int prec, int out[GRAM_MAX_C
 size_t gram_work_bytes(const int n[3], int mode, int prec, int nsplit = 0);
 hipError_t launch_gram(const void* A, const int n[3], int mode, int prec, double* G, void* work,
                        hipStream_t s, Bat bt = Bat(), int nsplit = 0);
+// The three mode Grams of one tensor (G_k at G + k sG) in one launch plus one reduction launch,
+// when every mode takes the large-tile kernel with its split code; the partials of the three
+// modes lie back to back in `work` (gram3_work_bytes).  Same results as three launch_gram calls.
+bool gram3_eligible(const int n[3], int prec, const int codes[3]);
+size_t gram3_work_bytes(const int n[3], int prec, const int codes[3]);
+hipError_t launch_gram3(const void* A, const int n[3], int prec, double* G, long sG, void* work, hipStream_t s,
+                        Bat bt, const int codes[3]);
 
 // ------------------------------------------------------------ small dense products ----
 // C[b](m,n) = alpha * sum_k A[b](m,k) B[b](k,n) + beta * C[b](m,n) with arbitrary element
