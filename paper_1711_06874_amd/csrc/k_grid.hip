@@ -19,6 +19,9 @@
 // the other families take the double evaluation.
 #include "tk_kernels.h"
 
+#include <algorithm>
+#include <cmath>
+
 namespace tk {
 
 template <typename T>
@@ -369,6 +372,148 @@ hipError_t launch_grid_eval_f32_queue(const GridJob* jobs_dev, int njobs, const 
     const int groups = nitems < 2048 ? nitems : 2048;
     hipLaunchKernelGGL(k_grid_eval_f32_queue, dim3(groups), dim3(256), 0, s, jobs_dev, njobs, first_item_dev, nitems,
                        counter_dev);
+    return hipGetLastError();
+}
+
+// ---- radial tables ---------------------------------------------------------------------------
+// For Matern orders without a closed form (K_nu by series or continued fraction per value) on
+// grids whose axes share the
+// spacing h, with first nodes in (h/2) Z and an isotropic metric, every squared radius is
+// a (h/2)^2 m for an integer m = sum_k (c_k + 2 i_k)^2 (c_k = 2 x0_k / h, a the metric scale).
+// The kernel is then evaluated once per value of m (a table of at most sum_k (n_k - 1)^2 + 1
+// entries after dividing out the parity: all c_k even gives m = 4 m', all odd m = 8 m' + 3) and
+// the grid gathers from it: 195,076 Bessel evaluations instead of 16.8 M at 256^3.  The table
+// holds the FP64 values, rounded once to float for float storage.
+
+// The route pays for a Matern order without a closed form (hundreds of FP64 operations per value);
+// the spectral density and Slater p != 1 (one log / pow per value) are faster evaluated directly
+// than gathered from a table.
+static bool table_kind_host(const KernelParams& kp) { return kp.family == FAM_MATERN && kp.half < 0; }
+
+long radial_table_cap(const int n[3])
+{
+    long t = 1;
+    for (int k = 0; k < 3; ++k) t += (long)(n[k] - 1) * (n[k] - 1);
+    return t;
+}
+
+bool radial_plan(const GridAxes& g, const KernelParams* kps, int nb, RadialGrid* rg)
+{
+    if (nb < 1) return false;
+    for (int b = 0; b < nb; ++b) {
+        const KernelParams& kp = kps[b];
+        if (!table_kind_host(kp)) return false;
+        if (kp.axs[1] != kp.axs[0] || kp.axs[2] != kp.axs[0]) return false;
+        if (b > 0 && kp.axs[0] != kps[0].axs[0]) return false;
+    }
+    const double h = g.h[0];
+    if (!(h > 0.0)) return false;
+    int odd = 0;
+    long mmax = 0;
+    for (int k = 0; k < 3; ++k) {
+        if (std::fabs(g.h[k] - h) > 1e-15 * h) return false;
+        const double c = 2.0 * g.x0[k] / h;
+        const double cr = std::rint(c);
+        if (std::fabs(c - cr) > 1e-12 * std::fmax(1.0, std::fabs(c)) || std::fabs(cr) > (double)(1 << 20)) return false;
+        rg->c[k] = (int)cr;
+        odd += (rg->c[k] & 1);
+        const long u0 = rg->c[k], u1 = rg->c[k] + 2L * (g.n[k] - 1);
+        mmax += std::max(u0 * u0, u1 * u1);
+    }
+    rg->mode = (odd == 0) ? 4 : (odd == 3 ? 8 : 1);
+    rg->T = (rg->mode == 4) ? mmax / 4 + 1 : (rg->mode == 8 ? (mmax - 3) / 8 + 1 : mmax + 1);
+    if (rg->T > radial_table_cap(g.n)) return false;
+    const double a = kps[0].axs[0];
+    rg->q = a * a * 0.25 * h * h;
+    return true;
+}
+
+__global__ void __launch_bounds__(256) k_radial_table(double* __restrict__ table, RadialGrid rg, KernelParamsBatch kps,
+                                                      long bs)
+{
+    table = bshift(table, bs);
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= rg.T) return;
+    const long m = (rg.mode == 4) ? 4 * idx : (rg.mode == 8 ? 8 * idx + 3 : idx);
+    table[idx] = cov_value(kps.k[blockIdx.z], sqrt(rg.q * (double)m));
+}
+
+// sym: the first two axes carry the same nodes, so row (i1, i0) equals row (i0, i1): threads of
+// rows with i0 > i1 stop, the others store their values in both rows.
+template <typename T>
+__global__ void __launch_bounds__(256) k_grid_from_table(T* __restrict__ A, GridAxes g, RadialGrid rg,
+                                                         const double* __restrict__ table, long total_quads,
+                                                         int quads_per_row, int sym, long bs)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total_quads) return;
+    A = bshift(A, bs);
+    table = bshift(table, bs);
+    long row;
+    int i0, i1, i2;
+    if (total_quads <= 0x7fffffffL) {
+        const unsigned q32 = (unsigned)q, qpr = (unsigned)quads_per_row, n1 = (unsigned)g.n[1];
+        const unsigned row32 = q32 / qpr;
+        const unsigned i0u = row32 / n1;
+        i2 = (int)(q32 - row32 * qpr) * 4;
+        i1 = (int)(row32 - i0u * n1);
+        i0 = (int)i0u;
+        row = (long)row32;
+    } else {
+        row = q / quads_per_row;
+        i2 = (int)(q - row * quads_per_row) * 4;
+        i1 = (int)(row % g.n[1]);
+        i0 = (int)(row / g.n[1]);
+    }
+    if (sym && i0 > i1) return;
+    const long u0 = rg.c[0] + 2L * i0, u1 = rg.c[1] + 2L * i1;
+    const long m01 = u0 * u0 + u1 * u1;
+    T out[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const long u2 = rg.c[2] + 2L * (i2 + t < g.n[2] ? i2 + t : i2);
+        const long m = m01 + u2 * u2;
+        const long idx = (rg.mode == 4) ? (m >> 2) : (rg.mode == 8 ? (m - 3) >> 3 : m);
+        out[t] = (T)table[idx];
+    }
+    const int copies = (sym && i0 != i1) ? 2 : 1;
+    for (int cpy = 0; cpy < copies; ++cpy) {
+        const long r = (cpy == 0) ? row : (long)i1 * g.n[1] + i0;
+        T* dst = A + r * g.n[2] + i2;
+        if (i2 + 4 <= g.n[2]) {
+            if (sizeof(T) == 4 && (g.n[2] & 3) == 0) {
+                *reinterpret_cast<float4*>(dst) =
+                    make_float4((float)out[0], (float)out[1], (float)out[2], (float)out[3]);
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) dst[t] = out[t];
+            }
+        } else {
+            for (int t = 0; t < 4 && i2 + t < g.n[2]; ++t) dst[t] = out[t];
+        }
+    }
+}
+
+hipError_t launch_grid_eval_radial(void* A, int esz, const GridAxes& g, const KernelParams* kps, const RadialGrid& rg,
+                                   double* table, hipStream_t s, Bat bt)
+{
+    if (bt.nb < 1 || bt.nb > BATCH_MAX || (esz != 4 && esz != 8)) return hipErrorInvalidValue;
+    KernelParamsBatch kb;
+    for (int b = 0; b < bt.nb; ++b) kb.k[b] = kps[b];
+    hipLaunchKernelGGL(k_radial_table, dim3((unsigned)((rg.T + 255) / 256), 1, bt.nb), dim3(256), 0, s, table, rg, kb,
+                       bt.bs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int qpr = (g.n[2] + 3) / 4;
+    const long total = (long)g.n[0] * g.n[1] * qpr;
+    const int sym = (g.n[0] == g.n[1] && rg.c[0] == rg.c[1]) ? 1 : 0;
+    const dim3 grid((unsigned)((total + 255) / 256), 1, bt.nb);
+    if (esz == 4)
+        hipLaunchKernelGGL(k_grid_from_table<float>, grid, dim3(256), 0, s, (float*)A, g, rg, (const double*)table,
+                           total, qpr, sym, bt.bs);
+    else
+        hipLaunchKernelGGL(k_grid_from_table<double>, grid, dim3(256), 0, s, (double*)A, g, rg, (const double*)table,
+                           total, qpr, sym, bt.bs);
     return hipGetLastError();
 }
 

@@ -541,6 +541,7 @@ struct Work {
     tk_ctx* ctx = nullptr;   // for the FP64 path's convergence readbacks
     bool noconv = false;     // an FP64 eigensolve stopped at its iteration cap
     bool u32_fresh = false;  // the HOSVD eigensolve wrote U32 itself (no conversion needed)
+    double* rtab = nullptr;  // radial table of the grid evaluation (kernels without a fast closed form)
 };
 
 void layout_work(Arena& ar, const Plan& P, bool own_A, Work& w)
@@ -553,6 +554,7 @@ void layout_work(Arena& ar, const Plan& P, bool own_A, Work& w)
     int pmax = std::max(P.p[0], std::max(P.p[1], P.p[2]));
     int Rmax = std::max(R[0], std::max(R[1], R[2]));
     w.A = own_A ? (void*)ar.take<char>(N * esz) : nullptr;
+    w.rtab = own_A ? ar.take<double>((size_t)radial_table_cap(n)) : nullptr;
     size_t gw = 0;
     for (int k = 0; k < 3; ++k) gw = std::max(gw, gram_work_bytes(n, k, P.prec, P.gsplit[k]));
     if (gram3_eligible(n, P.prec, P.gsplit)) gw = std::max(gw, gram3_work_bytes(n, P.prec, P.gsplit));
@@ -1347,12 +1349,18 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void
 
     // the launches of the pipeline, from the grid evaluation to the final error (the FP64 eps
     // path reads ranks back in between)
+    // kernels without a fast closed form: the radial-table route, except in a captured graph (whose
+    // grid node is updated per call to the direct kernel)
+    bool table_route = false;
+    RadialGrid rg{};
     auto pipeline = [&](hipStream_t s) -> tk_status {
         tk_status st;
         if (own_A && !slot) {
             GridAxes ax = axes_of(grid);
             ProfScope ps(TK_PROF_GRID, s);
-            if (sizeof(Real) == 4) TK_LAUNCH(launch_grid_eval_f32((float*)w.A, ax, kps, s, w.bt));
+            if (table_route)
+                TK_LAUNCH(launch_grid_eval_radial(w.A, (int)sizeof(Real), ax, kps, rg, w.rtab, s, w.bt));
+            else if (sizeof(Real) == 4) TK_LAUNCH(launch_grid_eval_f32((float*)w.A, ax, kps, s, w.bt));
             else TK_LAUNCH(launch_grid_eval_f64((double*)w.A, ax, kps, s, w.bt));
         }
         if (P.init_U[0]) {
@@ -1448,6 +1456,7 @@ tk_status compress_impl(tk_ctx* ctx, const KernelParams* kps, int nb, const void
     tk_status st;
     const bool capturable = own_A && wsp.cached && P.prec != TK_FP64 && !P.converge && !P.init_U[0] &&
                             !g_prof_on.load();
+    if (own_A && !slot && !(ctx->graphs_on && capturable)) table_route = radial_plan(axes_of(grid), kps, nb, &rg);
     if (ctx->graphs_on && capturable) {
         if ((st = run_captured<Real>(ctx, P, nb, base, grid, kps, w, s, pipeline)) != TK_OK) return st;
     } else if ((st = pipeline(s)) != TK_OK) {
@@ -3125,8 +3134,20 @@ tk_status tk_grid_eval(tk_ctx* ctx, const tk_kernel* kernel, const tk_grid* grid
     TK_HIP(hipSetDevice(ctx->device));
     (void)hipGetLastError();
     GridAxes ax = axes_of(grid);
-    if (prec == TK_FP64) TK_LAUNCH(launch_grid_eval_f64((double*)A_dev, ax, &kp, (hipStream_t)hip_stream));
-    else TK_LAUNCH(launch_grid_eval_f32((float*)A_dev, ax, &kp, (hipStream_t)hip_stream));
+    hipStream_t s = (hipStream_t)hip_stream;
+    RadialGrid rg{};
+    if (radial_plan(ax, &kp, 1, &rg)) {
+        const size_t bytes = sizeof(double) * (size_t)rg.T;
+        Reservation res(ctx, bytes);
+        if (!res.take()) return fail(TK_ENOMEM, "radial table of %zu bytes", bytes);
+        Ws wsp;
+        hipError_t e = ws_get(ctx, s, 0, bytes, wsp);
+        if (e != hipSuccess) return fail(TK_ENOMEM, "workspace: %s", hipGetErrorString(e));
+        TK_LAUNCH(launch_grid_eval_radial(A_dev, prec == TK_FP64 ? 8 : 4, ax, &kp, rg, (double*)wsp.p, s));
+        return TK_OK;
+    }
+    if (prec == TK_FP64) TK_LAUNCH(launch_grid_eval_f64((double*)A_dev, ax, &kp, s));
+    else TK_LAUNCH(launch_grid_eval_f32((float*)A_dev, ax, &kp, s));
     return TK_OK;
 }
 

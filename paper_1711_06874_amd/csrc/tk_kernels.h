@@ -34,6 +34,23 @@ hipError_t launch_grid_eval_f32(float* A, const GridAxes& g, const KernelParams*
 hipError_t launch_grid_eval_f64(double* A, const GridAxes& g, const KernelParams* kps, hipStream_t s,
                                 Bat bt = Bat());
 
+// Radial-table route for Matern orders without a closed form on grids of common spacing h with
+// first nodes in (h/2) Z and an isotropic metric: every squared radius is q m for an integer m,
+// the kernel is tabulated once per m (T entries, at most radial_table_cap(n)) and the grid
+// gathers from the table.  radial_plan fills rg and returns true when the route applies to all
+// nb kernels; launch_grid_eval_radial then needs `table`: T doubles per problem (moving by bt.bs
+// like A).  Storage esz 4 (float) or 8 (double).
+struct RadialGrid {
+    double q;      // a (h/2)^2: r^2 = q m
+    long T;        // table entries
+    int c[3];      // 2 x0_k / h
+    int mode;      // m from the index: 4 idx (all c_k even), 8 idx + 3 (all odd), idx
+};
+long radial_table_cap(const int n[3]);
+bool radial_plan(const GridAxes& g, const KernelParams* kps, int nb, RadialGrid* rg);
+hipError_t launch_grid_eval_radial(void* A, int esz, const GridAxes& g, const KernelParams* kps, const RadialGrid& rg,
+                                   double* table, hipStream_t s, Bat bt = Bat());
+
 // Uneven batches: float grids of any sizes in one persistent launch.  A job is one grid (its
 // float tensor A, axes and kernel); its work items are its (n0 + 1) / 2 plane pairs.
 // first_item_dev[j] = items of the jobs before j (first_item_dev[njobs] = nitems); *counter_dev

@@ -125,6 +125,56 @@ def test_grid_eval_families(ctx, tk, oracle, name, kw, layout):
     _check_f32(ctx, tk, k, g, n, A)
 
 
+# Grids of one spacing h with first nodes in (h/2) Z: the Matern orders above without a closed
+# form take the radial-table route (one evaluation per squared radius, all parities of the
+# index compression: all even, all odd, mixed); the other families and the anisotropic metric
+# still take the direct route.
+RADIAL_GRIDS = [
+    ((40, 40, 40), (1.0, 1.0, 1.0), 1),          # offset: 2 x0 / h = 0 on every axis
+    ((40, 40, 40), (1.0, 1.0, 1.0), 0),          # centred, n even: odd c_k
+    ((33, 17, 25), (1.0, 0.5, 0.75), 0),         # centred, n odd, h = 1/16 on every axis
+    ((33, 18, 25), (1.0, 0.53125, 0.75), 0),     # centred, mixed parities
+]
+
+
+@pytest.mark.parametrize("name,kw", FAMILIES)
+@pytest.mark.parametrize("n,b,layout", RADIAL_GRIDS)
+def test_grid_eval_families_radial(ctx, tk, oracle, name, kw, n, b, layout):
+    """The radial-table route against the oracle (same bounds as test_grid_eval_families)."""
+    say("grid_eval radial", name, n, b, layout)
+    okw = dict(kw)
+    if "metric" in okw:
+        okw["metric"] = tuple(okw["metric"])
+    A = oracle.grid_eval(oracle.Kernel(**okw), oracle.Grid(n=n, b=b, layout=layout))
+    k = tk.make_kernel(**kw)
+    g = tk.make_grid(n, b, layout)
+    d64 = torch.empty(n, dtype=torch.float64, device="cuda")
+    tk.tk_grid_eval(ctx.handle, k, g, tk.TK_FP64, d64)
+    got = host(d64)
+    sigma2 = kw.get("sigma2", 1.0)
+    s_exp = np.abs(np.log(np.maximum(np.abs(A) / sigma2, 1e-300)))
+    rtol = 2e-13 + 8 * 2.220446049250313e-16 * s_exp
+    assert np.all(np.abs(got - A) <= rtol * np.abs(A) + 1e-300)
+    _check_f32(ctx, tk, k, g, n, A)
+
+
+@pytest.mark.parametrize("name,kw", [f for f in FAMILIES if "metric" not in f[1]][:3])
+def test_compress_radial_route_matches_direct(ctx, tk, oracle, name, kw):
+    """A compression whose grid takes the radial-table route against the same compression of the
+    oracle's tensor handed in (tk_compress_tensor, no grid evaluation on the GPU)."""
+    n = (48, 48, 48)
+    kern = tk.make_kernel(**kw)
+    grid = tk.make_grid(n, 1.0, 1)
+    A = oracle.grid_eval(oracle.Kernel(**kw), oracle.Grid(n=n, b=(1.0, 1.0, 1.0), layout=1))
+    opts = tk.make_opts(ranks=6, hooi_sweeps=2, prec=tk.TK_FP64)
+    t1 = ctx.compress(kern, grid, opts)
+    t2 = ctx.compress_tensor(dev(A), grid, opts)
+    say("  rel_err route %.6e tensor %.6e" % (t1.rel_err, t2.rel_err))
+    assert abs(t1.rel_err - t2.rel_err) <= 1e-9 * max(t2.rel_err, 1e-12) + 1e-14
+    t1.free()
+    t2.free()
+
+
 # (256, 288, 32) and (64, 32, 320): FP32 modes with n_mode >= 256 take the large-tile kernel
 # (128 x 128 tiles; 288 and 320 leave a ragged last tile)
 @pytest.mark.parametrize("shape", [(64, 64, 64), (70, 33, 129), (5, 7, 200), (256, 288, 32), (64, 32, 320)])
