@@ -3,12 +3,12 @@
 // products that apply them along a mode of an n1 x n2 x n3 vector run on the FP64 small-product
 // kernel (k_small.hip).
 //
-// Cholesky: blocked right-looking, CB = 64 columns per step.  One work-group factors the
-// diagonal block (one wavefront, rows in registers: pivot, scaling, rank-1 update of the
-// block's trailing part) and also forms the inverse of its triangular factor; the panel below is
-// then L21 = A21 L11^-T as one product with that inverse, and the lower tiles of the trailing
-// matrix take A22 -= L21 L21^T on FP64 MFMA (k_syrk_lower).  A pivot that is not positive
-// records its index (plus one) in `info` and the factor turns to NaN from there on.
+// Cholesky: blocked right-looking, CB = 64 columns per step.  One wavefront factors the
+// diagonal block (rows in registers: pivot, scaling, rank-1 update of the block's trailing
+// part); the panel below is then L21 = A21 L11^-T by forward substitution, one thread per row
+// (k_trsm_panel), and the lower tiles of the trailing matrix take A22 -= L21 L21^T on FP64 MFMA
+// (k_syrk_lower).  A pivot that is not positive records its index (plus one) in `info` and the
+// factor turns to NaN from there on.
 #include "tk_kernels.h"
 
 namespace tk {
@@ -31,15 +31,13 @@ __global__ void __launch_bounds__(256) k_cov1d(double* __restrict__ C, int n, do
     C[e] = v;
 }
 
-// Factor the nb x nb diagonal block at (k0, k0) of A (row-major, ld n) in place, zero its strict
-// upper part, and write the inverse of its lower-triangular factor to inv (nb x nb, ld CB).
-// One wavefront, lane i holding row i of the block in registers (the column loops are unrolled,
-// so every register index is static).  Column j: the pivot comes from lane j, the lanes below
-// scale their entry, publish it in LDS, and update their row with the broadcast column.  The
-// inverse is then formed column by column, lane c taking column c by forward substitution on
-// the factor kept in LDS.  A wavefront orders its own LDS accesses, so no barrier is needed.
+// Factor the nb x nb diagonal block at (k0, k0) of A (row-major, ld n) in place and zero its
+// strict upper part.  One wavefront, lane i holding row i of the block in registers (the column
+// loops are unrolled, so every register index is static).  Column j: the pivot comes from lane j,
+// the lanes below scale their entry, publish it in LDS, and update their row with the broadcast
+// column.  A wavefront orders its own LDS accesses, so no barrier is needed.
 __global__ void __launch_bounds__(64) k_potrf_block(double* __restrict__ A, int n, int k0, int nb,
-                                                    double* __restrict__ inv, int* __restrict__ info)
+                                                    int* __restrict__ info)
 {
     __shared__ double col[CB];
     __shared__ double Ls[CB][CB + 1];
@@ -69,26 +67,42 @@ __global__ void __launch_bounds__(64) k_potrf_block(double* __restrict__ A, int 
     __builtin_amdgcn_wave_barrier();
     for (int r = 0; r < nb; ++r)
         if (live) A[(long)(k0 + r) * n + k0 + i] = Ls[r][i];
-    // inv = L^-1: lane c computes column c (x_k = 0 for k < c)
-    double x[CB];
-#pragma unroll
-    for (int r = 0; r < CB; ++r) {
-        double v = (r == i) ? 1.0 : 0.0;
-#pragma unroll
-        for (int k = 0; k < r; ++k) v -= Ls[r][k] * x[k];
-        x[r] = (r < i || r >= nb) ? 0.0 : v / Ls[r][r];
-        if (live && r < nb) inv[(long)r * CB + i] = x[r];
-    }
 }
 
-// A21 (rows x nb at (k0 + nb, k0), ld n) = T (rows x nb, ld CB)
-__global__ void __launch_bounds__(256) k_store_panel(double* __restrict__ A, int n, int k0, int nb, int rows,
-                                                     const double* __restrict__ T)
+// The panel below the diagonal block: L21 = A21 L11^-T, row by row (L11 y^T = x^T by forward
+// substitution, one thread per row, L11 staged in LDS), written to A21 (ld n) and to T (ld CB)
+// for the trailing update.  Only full CB x CB diagonal blocks have a panel below them.
+__global__ void __launch_bounds__(256) k_trsm_panel(double* __restrict__ A, int n, int k0, int rows,
+                                                    double* __restrict__ T)
 {
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (long)rows * nb) return;
-    const int r = (int)(e / nb), c = (int)(e - (long)r * nb);
-    A[(long)(k0 + nb + r) * n + k0 + c] = T[(long)r * CB + c];
+    __shared__ double Ls[CB][CB + 1];
+    __shared__ double rdiag[CB];
+    for (int e = threadIdx.x; e < CB * CB; e += 256) {
+        const int r = e / CB, c = e - r * CB;
+        Ls[r][c] = (c <= r) ? A[(long)(k0 + r) * n + k0 + c] : 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x < CB) rdiag[threadIdx.x] = 1.0 / Ls[threadIdx.x][threadIdx.x];
+    __syncthreads();
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= rows) return;
+    double* x = A + (long)(k0 + CB + r) * n + k0;
+    double y[CB];
+#pragma unroll
+    for (int j = 0; j < CB; ++j) y[j] = x[j];
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+        double v = y[j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) v -= y[k] * Ls[j][k];
+        y[j] = v * rdiag[j];
+    }
+    double* t = T + (long)r * CB;
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+        x[j] = y[j];
+        t[j] = y[j];
+    }
 }
 
 // Trailing update of the blocked factorisation, lower tiles only: C[i][j] -= sum_k T[i][k] T[j][k]
@@ -199,30 +213,21 @@ hipError_t launch_cov1d(double* C, int n, double x0, double h, const KernelParam
     return hipGetLastError();
 }
 
-size_t cholesky_work_bytes(int n) { return sizeof(double) * ((size_t)CB * CB + (size_t)n * CB) + 256; }
+size_t cholesky_work_bytes(int n) { return sizeof(double) * ((size_t)n * CB) + 256; }
 
 hipError_t launch_cholesky(double* A, int n, void* work, int* info, hipStream_t s)
 {
     if (n < 1) return hipErrorInvalidValue;
-    double* inv = (double*)work;
-    double* T = inv + CB * CB;
+    double* T = (double*)work;
     hipError_t e;
     for (int k0 = 0; k0 < n; k0 += CB) {
         const int nb = (n - k0 < CB) ? n - k0 : CB;
-        hipLaunchKernelGGL(k_potrf_block, dim3(1), dim3(64), 0, s, A, n, k0, nb, inv, info);
+        hipLaunchKernelGGL(k_potrf_block, dim3(1), dim3(64), 0, s, A, n, k0, nb, info);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int rows = n - k0 - nb;
         if (rows <= 0) break;
-        // T = A21 L11^-T
-        GemmArgs g{};
-        g.M = rows; g.N = nb; g.K = nb; g.batch = 1;
-        g.A = A + (long)(k0 + nb) * n + k0; g.sAm = n; g.sAk = 1;
-        g.B = inv; g.sBk = 1; g.sBn = CB;
-        g.C = T; g.sCm = CB; g.sCn = 1;
-        g.alpha = 1.0; g.beta = 0.0;
-        if ((e = launch_gemm<double, double, double>(g, s)) != hipSuccess) return e;
-        const long pt = (long)rows * nb;
-        hipLaunchKernelGGL(k_store_panel, dim3((unsigned)((pt + 255) / 256)), dim3(256), 0, s, A, n, k0, nb, rows, T);
+        // L21 = A21 L11^-T, into A and T (a panel follows only full blocks: nb == CB here)
+        hipLaunchKernelGGL(k_trsm_panel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, A, n, k0, rows, T);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         // A22 -= T T^T (lower tiles)
         const long nt = (rows + SB - 1) / SB;
