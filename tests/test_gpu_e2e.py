@@ -287,11 +287,11 @@ def test_save_load_roundtrip(ctx, tk, tmp_path):
 
 # ------------------------------------------------- full size, in the benchmark's launch setup ----
 
-@pytest.mark.parametrize("nu,ell", [(0.5, 0.1), (2.5, 1.0)])
+@pytest.mark.parametrize("nu,ell", [(nu, ell) for nu in (0.5, 1.5, 2.5) for ell in (0.1, 0.3, 1.0)])
 def test_bench_configuration_256(ctx, tk, oracle, nu, ell):
-    """256^3 offset grid, eps 1e-6, 2 HOOI sweeps, FP32 -- exactly what bench.py times -- on
-    sampled outputs: error <= eps, ranks within one of the oracle's, reconstruction and
-    covariance matvec rows against the FP64 oracle."""
+    """256^3 offset grid, eps 1e-6, 2 HOOI sweeps, FP32 -- exactly what bench.py times, all nine of
+    its kernels -- on sampled outputs: error <= eps, ranks within one of the oracle's,
+    reconstruction and covariance matvec rows against the FP64 oracle."""
     n, eps = 256, 1e-6
     og = oracle.Grid(n=(n, n, n), layout=oracle.OFFSET)
     ok = oracle.Kernel(oracle.MATERN, nu=nu, ell=ell)
