@@ -444,30 +444,88 @@ __device__ __forceinline__ void qr_backward(double (&w)[RPT][PM], double* T, dou
 // (two barriers).  The column loop is unrolled at compile time, so every register index is
 // static.  The explicit Q is then accumulated backwards in the same registers.
 template <int PM, int NT, int RPT>
-__global__ void __launch_bounds__(NT) k_hqr_reg(const double* __restrict__ In, double* __restrict__ Out,
-                                                float* __restrict__ Out32, int n, int p, long bs)
+__device__ __forceinline__ void hqr_rows(double (&w)[RPT][PM], double* T, double* S, double (*rowjb)[PM],
+                                         double* taus, int n, int p)
 {
-    In = bshift(In, bs);
-    Out = bshift(Out, bs);
-    if (Out32) Out32 = bshift(Out32, bs);
-    extern __shared__ double T[];
-    __shared__ double S[PM];
-    __shared__ double rowjb[2][PM];     // row j, double-buffered by column parity
-    __shared__ double taus[PM];
+    qr_forward<PM, NT, RPT, 0>(w, T, S, rowjb, taus, n, p);
+    // thread 0 wrote the last tau after the last barrier of the forward pass, and the backward
+    // pass reads it first
+    __syncthreads();
+    qr_backward<PM, NT, RPT, PM - 1>(w, T, S, taus, n, p);
+}
+
+template <int PM, int NT, int RPT>
+__device__ __forceinline__ void load_rows(double (&w)[RPT][PM], const double* __restrict__ In, long off, int n,
+                                          int p)
+{
     const int i = threadIdx.x;
-    const long off = (long)blockIdx.x * n * p;
-    double w[RPT][PM];
+    if (p == PM) {
+        // no padding columns: one block of loads per row
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int row = i + q * NT;
+            const double* src = In + off + (long)(row < n ? row : 0) * PM;
+#pragma unroll
+            for (int c = 0; c < PM; ++c) w[q][c] = src[c];
+            if (row >= n) {
+#pragma unroll
+                for (int c = 0; c < PM; ++c) w[q][c] = 0.0;
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int row = i + q * NT;
 #pragma unroll
         for (int c = 0; c < PM; ++c) w[q][c] = (row < n && c < p) ? In[off + (long)row * p + c] : 0.0;
     }
-    qr_forward<PM, NT, RPT, 0>(w, T, S, rowjb, taus, n, p);
-    // thread 0 wrote the last tau after the last barrier of the forward pass, and the backward
-    // pass reads it first
-    __syncthreads();
-    qr_backward<PM, NT, RPT, PM - 1>(w, T, S, taus, n, p);
+}
+
+// The same without a branch per column: every load reads an in-bounds element (row and column
+// clamped) and the padding is selected to zero afterwards.
+template <int PM, int NT, int RPT>
+__device__ __forceinline__ void load_rows_clamped(double (&w)[RPT][PM], const double* __restrict__ In, long off,
+                                                  int n, int p)
+{
+    const int i = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int row = i + q * NT;
+        const double* src = In + off + (long)min(row, n - 1) * p;
+        const bool ok = row < n;
+#pragma unroll
+        for (int c = 0; c < PM; ++c) {
+            const double v = src[min(c, p - 1)];
+            w[q][c] = (ok && c < p) ? v : 0.0;
+        }
+    }
+}
+
+template <int PM, int NT, int RPT>
+__device__ __forceinline__ void store_rows(const double (&w)[RPT][PM], double* __restrict__ Out,
+                                           float* __restrict__ Out32, long off, int n, int p)
+{
+    const int i = threadIdx.x;
+    if (p == PM) {
+        // no padding columns: one block of stores per row (a branch per column makes the
+        // compiler wait for every store before the next)
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int row = i + q * NT;
+            if (row < n) {
+                double* dst = Out + off + (long)row * PM;
+#pragma unroll
+                for (int c = 0; c < PM; ++c) dst[c] = w[q][c];
+                if (Out32) {
+                    float* d32 = Out32 + off + (long)row * PM;
+#pragma unroll
+                    for (int c = 0; c < PM; ++c) d32[c] = (float)w[q][c];
+                }
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int row = i + q * NT;
@@ -482,6 +540,274 @@ __global__ void __launch_bounds__(NT) k_hqr_reg(const double* __restrict__ In, d
             }
         }
     }
+}
+
+template <int PM, int NT, int RPT>
+__global__ void __launch_bounds__(NT) k_hqr_reg(const double* __restrict__ In, double* __restrict__ Out,
+                                                float* __restrict__ Out32, int n, int p, long bs)
+{
+    In = bshift(In, bs);
+    Out = bshift(Out, bs);
+    if (Out32) Out32 = bshift(Out32, bs);
+    extern __shared__ double T[];
+    __shared__ double S[PM];
+    __shared__ double rowjb[2][PM];     // row j, double-buffered by column parity
+    __shared__ double taus[PM];
+    const long off = (long)blockIdx.x * n * p;
+    double w[RPT][PM];
+    load_rows<PM, NT, RPT>(w, In, off, n, p);
+    hqr_rows<PM, NT, RPT>(w, T, S, rowjb, taus, n, p);
+    store_rows<PM, NT, RPT>(w, Out, Out32, off, n, p);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Cholesky QR of the same register-resident block, for orthonormalisations that only need the
+// span (the float eps path).  One pass: W = Y^T Y, W = L D L^T, Q = Y L^-T D^-1/2 (the R of
+// Y = Q R is D^1/2 L^T, so Q is the thin QR factor with a positive diagonal in R).  A second
+// pass on Q restores orthogonality to the rounding level when the first one was conditioned
+// worse than the one-pass bound.
+//   Gram: every wavefront stages 64 of the rows in LDS and accumulates the 16 x 16 tiles of the
+//   lower triangle of W (one tile for p <= 16, three for p <= 32) over them on FP64 MFMA; the
+//   per-wavefront tiles are summed in LDS by all threads.
+//   LDL^T: wavefront 0, lane i holding row i of W; at step j row j is broadcast lane by lane
+//   (readlane), so the step has no LDS round trip.
+//   Apply: each thread solves z L^T = y for its rows with L^T read from LDS, then scales by
+//   D^-1/2.
+// The pivots decide, through s_j = d_j / W_jj (the squared sine of column j against the span of
+// the columns before it).  First pass: a pivot with s_j < floor is raised to floor W_jj: such a
+// column lies in the span of the earlier ones to rounding (a power step of a subspace whose
+// trailing directions are below the Gram's rounding level gives such columns), and the pass
+// leaves what remains of it, orthogonal to the earlier columns up to that rounding, with a small
+// norm.  All s_j >= one_pass: done; otherwise a second pass.  Second pass: all s_j >= accept2
+// (and W_jj > 0): its result is the factor.  Columns below that are, after the first pass,
+// rounding noise inside the span of the others: they are replaced by fixed pseudo-random
+// columns (an arbitrary completion of the span, as the Householder QR would make one) and a
+// third pass orthonormalises the block, again requiring all s_j >= accept2.  If it does not
+// pass, the block is reloaded and the Householder QR above runs instead.  Every pass multiplies
+// by an invertible triangle, so the span of the columns that carry information is Y's.
+template <int PM>
+__device__ __forceinline__ int stage_index(int row, int c)
+{
+    // p = 32: the halves of odd rows are swapped, so that the four rows one MFMA operand read
+    // touches do not fall on the same LDS banks
+    if constexpr (PM == 32) return row * 32 + (c ^ ((row & 1) << 4));
+    else return row * PM + c;
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// 1 / d to about one ulp without the IEEE division sequence: hardware reciprocal and two Newton
+// steps (d > 0)
+__device__ __forceinline__ double recip(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+
+template <int PM, int NT, int RPT>
+__global__ void __launch_bounds__(NT) k_cholqr_reg(const double* __restrict__ In, double* __restrict__ Out,
+                                                   float* __restrict__ Out32, int n, int p, double floor,
+                                                   double one_pass, double accept2, long bs)
+{
+    constexpr int NW = NT / 64;
+    constexpr int NTILE = PM <= 16 ? 1 : 3;     // (0,0), (1,0), (1,1)
+    In = bshift(In, bs);
+    Out = bshift(Out, bs);
+    if (Out32) Out32 = bshift(Out32, bs);
+    extern __shared__ double T[];               // NT x PM doubles: staging, then tile partials
+    __shared__ double Ws[PM][PM + 1];           // W, lower triangle and mirror
+    __shared__ double LT[PM][PM + 1];           // LT[k][j] = L[j][k], j > k
+    __shared__ double rsd[PM];                  // d_j^-1/2
+    __shared__ unsigned verdict_s[2];           // verdict, columns to replace
+    __shared__ double S[PM];
+    __shared__ double rowjb[2][PM];
+    __shared__ double taus[PM];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const long off = (long)blockIdx.x * n * p;
+    double y[RPT][PM];
+    load_rows<PM, NT, RPT>(y, In, off, n, p);
+    double* stg = T + wv * 64 * PM;
+    bool householder = false;
+
+    // verdicts: 0 done, 1 solve and take another pass, 2 Householder, 3 replace the columns in
+    // verdict_s[1] (numerically inside the span of the others) and take another pass
+    for (int pass = 0; pass < 3; ++pass) {
+        // ---- Gram of the NT RPT rows on MFMA, per wavefront over its own rows
+        f64x4 acc[NTILE];
+#pragma unroll
+        for (int t = 0; t < NTILE; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+#pragma unroll
+            for (int c = 0; c < PM; c += 2)
+                *reinterpret_cast<double2*>(stg + stage_index<PM>(lane, c)) = double2{y[q][c], y[q][c + 1]};
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int ks = 0; ks < 64; ks += 4) {
+                const int row = ks + (lane >> 4), c0 = lane & 15;
+                const double a0 = (c0 < PM) ? stg[stage_index<PM>(row, c0 < PM ? c0 : 0)] : 0.0;
+                if constexpr (NTILE == 1) {
+                    acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, acc[0], 0, 0, 0);
+                } else {
+                    const int c1 = 16 + c0;
+                    const double a1 = (c1 < PM) ? stg[stage_index<PM>(row, c1 < PM ? c1 : 0)] : 0.0;
+                    acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, acc[0], 0, 0, 0);
+                    acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a0, acc[1], 0, 0, 0);
+                    acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, acc[2], 0, 0, 0);
+                }
+            }
+            // the next round's staging (or the partials below) overwrite rows just read
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        // tile t, entry (i, j) (i = 4 v + lane / 16, j = lane % 16) of this wavefront
+#pragma unroll
+        for (int t = 0; t < NTILE; ++t) {
+            stg[t * 256 + (0 + (lane >> 4)) * 16 + (lane & 15)] = acc[t][0];
+            stg[t * 256 + (4 + (lane >> 4)) * 16 + (lane & 15)] = acc[t][1];
+            stg[t * 256 + (8 + (lane >> 4)) * 16 + (lane & 15)] = acc[t][2];
+            stg[t * 256 + (12 + (lane >> 4)) * 16 + (lane & 15)] = acc[t][3];
+        }
+        __syncthreads();
+        for (int e = tid; e < PM * PM; e += NT) {
+            const int i = e / PM, j = e - (e / PM) * PM;
+            if (i < j) continue;
+            const int t = (i < 16) ? 0 : (j < 16 ? 1 : 2);
+            const int x = (i & 15) * 16 + (j & 15);
+            double v = 0.0;
+#pragma unroll
+            for (int u = 0; u < NW; ++u) v += T[u * 64 * PM + t * 256 + x];
+            if (i >= p) v = (i == j) ? 1.0 : 0.0;     // padding columns: identity block
+            Ws[i][j] = v;
+            Ws[j][i] = v;
+        }
+        __syncthreads();
+        // ---- LDL^T in wavefront 0: lane i holds row i; lane j tests and floors its own pivot
+        if (wv == 0) {
+            double wr[PM];
+#pragma unroll
+            for (int c = 0; c < PM; ++c) wr[c] = (lane < PM) ? Ws[lane < PM ? lane : 0][c] : 0.0;
+            const double w0 = (lane < PM) ? Ws[lane < PM ? lane : 0][lane < PM ? lane : 0] : 1.0;
+            // pivot tests without divisions: d >= t W_jj (false for NaN)
+            bool weak = false, bad = false;
+            double mydiag = 1.0;
+#pragma unroll
+            for (int j = 0; j < PM; ++j) {
+                // lane j's candidate pivot (the other lanes' values are not used)
+                const double draw = wr[j];
+                const double cand = (pass > 0 || draw >= floor * w0) ? draw : floor * w0;
+                if (lane == j) {
+                    weak = !(draw >= one_pass * w0);
+                    bad = !(draw >= accept2 * w0) || !(w0 > 0.0);
+                    mydiag = cand;
+                }
+                const double djj = read_lane(cand, j);
+                const double inv = djj > 0.0 ? recip(djj) : 0.0;
+                // lanes <= j take l = 0 and keep their row (no branch; rows <= j are final)
+                const double l = (lane > j) ? wr[j] * inv : 0.0;
+#pragma unroll
+                for (int k = j + 1; k < PM; ++k) wr[k] = fma(-l, read_lane(wr[k], j), wr[k]);
+                wr[j] = (lane > j) ? l : wr[j];
+                __builtin_amdgcn_sched_barrier(0);     // one step's broadcasts live at a time
+            }
+            const unsigned long long weak_m = __ballot(weak && lane < PM);
+            const unsigned long long bad_m = __ballot(bad && lane < PM);
+            if (lane < PM) {
+#pragma unroll
+                for (int k = 0; k < PM; ++k)
+                    if (k < lane) LT[k][lane] = wr[k];
+                rsd[lane] = mydiag > 0.0 ? 1.0 / sqrt(mydiag) : 0.0;
+            }
+            if (lane == 0) {
+                unsigned v;
+                if (pass == 0) v = weak_m ? 1u : 0u;
+                else if (pass == 1) v = bad_m ? 3u : 0u;
+                else v = bad_m ? 2u : 0u;
+                verdict_s[0] = v;
+                verdict_s[1] = (unsigned)bad_m;
+            }
+        }
+        __syncthreads();
+        const unsigned verdict = verdict_s[0];
+        if (verdict == 2) {
+            householder = true;
+            break;
+        }
+        if (verdict == 3) {
+            // complete the span with fixed pseudo-random columns in place of the dependent ones
+            const unsigned repl = verdict_s[1];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int row = tid + q * NT;
+#pragma unroll
+                for (int c = 0; c < PM; ++c)
+                    if ((repl >> c) & 1u)
+                        y[q][c] = row < n ? start_value(((unsigned long long)blockIdx.x << 40) ^
+                                                        ((unsigned long long)row << 20) ^ (unsigned long long)c)
+                                          : 0.0;
+            }
+            __syncthreads();
+            continue;
+        }
+        // ---- z L^T = y, then z D^-1/2; row k + 1 of L^T is loaded while row k is applied (where
+        // the registers allow)
+        if constexpr (RPT * PM > 24) {
+#pragma unroll
+            for (int k = 0; k < PM; ++k) {
+#pragma unroll
+                for (int j = k + 1; j < PM; ++j) {
+                    const double l = LT[k][j];
+#pragma unroll
+                    for (int q = 0; q < RPT; ++q) y[q][j] = fma(-y[q][k], l, y[q][j]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+            double cur[PM];
+#pragma unroll
+            for (int j = 1; j < PM; ++j) cur[j] = LT[0][j];
+#pragma unroll
+            for (int k = 0; k < PM; ++k) {
+                double nxt[PM];
+#pragma unroll
+                for (int j = k + 2; j < PM; ++j) nxt[j] = LT[k + 1][j];
+#pragma unroll
+                for (int j = k + 1; j < PM; ++j) {
+#pragma unroll
+                    for (int q = 0; q < RPT; ++q) y[q][j] = fma(-y[q][k], cur[j], y[q][j]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int j = k + 2; j < PM; ++j) cur[j] = nxt[j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < PM; ++j) {
+            const double sc = rsd[j];
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) y[q][j] *= sc;
+        }
+        // (unconditional, so that the solve and its loads share one block) a further pass
+        // restages these rows and rewrites Ws / LT / rsd
+        __syncthreads();
+        if (verdict == 0) break;
+    }
+    if (householder) {
+        load_rows<PM, NT, RPT>(y, In, off, n, p);
+        hqr_rows<PM, NT, RPT>(y, T, S, rowjb, taus, n, p);
+    }
+    store_rows<PM, NT, RPT>(y, Out, Out32, off, n, p);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -852,9 +1178,12 @@ __global__ void k_trace(const double* __restrict__ G, long sG, int n, double* __
 
 }  // namespace
 
-// out32 (optional, register kernel only): an FP32 copy of the factor, same layout
+// out32 (optional, register kernels only): an FP32 copy of the factor, same layout.
+// chol.floor > 0 (register sizes only): Cholesky QR with these thresholds and the Householder
+// fallback; the factor then spans the same space, with R's diagonal positive where the Cholesky
+// route is taken.
 static hipError_t qr_launch(const double* in, double* out, int count, int n, int p, hipStream_t s, Bat bt,
-                            float* out32 = nullptr)
+                            float* out32 = nullptr, CholQr chol = CholQr{})
 {
     const dim3 grid(count, 1, bt.nb);
     if (n <= 1024 && p <= 32) {
@@ -862,19 +1191,36 @@ static hipError_t qr_launch(const double* in, double* out, int count, int n, int
         const bool two = n > 512;
         const int pm = (p + 7) / 8 * 8;
         const size_t lds = sizeof(double) * (size_t)pm * nt;
+        // Cholesky QR up to 256 rows (one per thread), and up to 512 for p <= 24: the larger
+        // register blocks spill
+        const bool use_chol = chol.floor > 0.0 && (n <= 256 || (n <= 512 && pm <= 24));
+#define TK_QR_LAUNCH3(K, PM, NT, RPT, ...)                                                                     \
+    hipLaunchKernelGGL((K<PM, NT, RPT>), grid, dim3(NT), lds, s, in, out, out32, n, p, ##__VA_ARGS__, bt.bs)
+#define TK_CHOL_LAUNCH(PM, NT) TK_QR_LAUNCH3(k_cholqr_reg, PM, NT, 1, chol.floor, chol.one_pass, chol.accept2)
 #define TK_QR_LAUNCH(PM)                                                                                         \
     do {                                                                                                        \
-        if (nt == 256) hipLaunchKernelGGL((k_hqr_reg<PM, 256, 1>), grid, dim3(256), lds, s, in, out, out32, n, p, bt.bs); \
-        else if (!two) hipLaunchKernelGGL((k_hqr_reg<PM, 512, 1>), grid, dim3(512), lds, s, in, out, out32, n, p, bt.bs); \
-        else hipLaunchKernelGGL((k_hqr_reg<PM, 512, 2>), grid, dim3(512), lds, s, in, out, out32, n, p, bt.bs);           \
+        if (nt == 256) TK_QR_LAUNCH3(k_hqr_reg, PM, 256, 1);                                                    \
+        else if (!two) TK_QR_LAUNCH3(k_hqr_reg, PM, 512, 1);                                                    \
+        else TK_QR_LAUNCH3(k_hqr_reg, PM, 512, 2);                                                              \
     } while (0)
-        switch (pm) {
-        case 8: TK_QR_LAUNCH(8); break;
-        case 16: TK_QR_LAUNCH(16); break;
-        case 24: TK_QR_LAUNCH(24); break;
-        default: TK_QR_LAUNCH(32);
+        if (use_chol) {
+            switch (pm) {
+            case 8: if (nt == 256) TK_CHOL_LAUNCH(8, 256); else TK_CHOL_LAUNCH(8, 512); break;
+            case 16: if (nt == 256) TK_CHOL_LAUNCH(16, 256); else TK_CHOL_LAUNCH(16, 512); break;
+            case 24: if (nt == 256) TK_CHOL_LAUNCH(24, 256); else TK_CHOL_LAUNCH(24, 512); break;
+            default: TK_CHOL_LAUNCH(32, 256);
+            }
+        } else {
+            switch (pm) {
+            case 8: TK_QR_LAUNCH(8); break;
+            case 16: TK_QR_LAUNCH(16); break;
+            case 24: TK_QR_LAUNCH(24); break;
+            default: TK_QR_LAUNCH(32);
+            }
         }
 #undef TK_QR_LAUNCH
+#undef TK_CHOL_LAUNCH
+#undef TK_QR_LAUNCH3
         return hipGetLastError();
     }
     if (out32) return hipErrorInvalidValue;
@@ -911,10 +1257,12 @@ hipError_t eig_set_attributes()
     if (e != hipSuccess) return e;
     // dynamic LDS of the register QR above 64 KB: PM x 512 doubles
     const void* ks[] = {(const void*)k_hqr_reg<24, 512, 1>, (const void*)k_hqr_reg<32, 512, 1>,
-                        (const void*)k_hqr_reg<24, 512, 2>, (const void*)k_hqr_reg<32, 512, 2>};
+                        (const void*)k_hqr_reg<24, 512, 2>, (const void*)k_hqr_reg<32, 512, 2>,
+                        (const void*)k_cholqr_reg<24, 512, 1>};
     const int bytes[] = {(int)(sizeof(double) * 24 * 512), (int)(sizeof(double) * 32 * 512),
-                         (int)(sizeof(double) * 24 * 512), (int)(sizeof(double) * 32 * 512)};
-    for (int i = 0; i < 4; ++i)
+                         (int)(sizeof(double) * 24 * 512), (int)(sizeof(double) * 32 * 512),
+                         (int)(sizeof(double) * 24 * 512)};
+    for (int i = 0; i < 5; ++i)
         if ((e = hipFuncSetAttribute(ks[i], hipFuncAttributeMaxDynamicSharedMemorySize, bytes[i])) != hipSuccess)
             return e;
     return hipSuccess;
@@ -969,8 +1317,11 @@ static hipError_t eig_body(const EigBatch& b, int iters, hipStream_t s, bool& wr
             if (it == 0 && warm_direct) { g.B = b.warm; g.sBb = b.sW; g.sBk = b.ldw; g.sBn = 1; }
             if ((e = launch_gemm<double, double, double>(g, s)) != hipSuccess) return e;
             const bool last = direct && it == iters - 1;
-            if ((e = qr_launch(b.Y, last ? b.U : b.Q, b.count, n, p, s, bt, last && direct32 ? b.U32 : nullptr)) !=
-                hipSuccess)
+            // span-only: Cholesky QR once the block is a power step of an orthonormal one (G times
+            // a random block has all its columns close to the leading eigenvector)
+            const CholQr chol = (b.span_only && (b.warm || it > 0)) ? b.cholqr : CholQr{};
+            if ((e = qr_launch(b.Y, last ? b.U : b.Q, b.count, n, p, s, bt, last && direct32 ? b.U32 : nullptr,
+                               chol)) != hipSuccess)
                 return e;
         }
         if (direct) {

@@ -201,6 +201,8 @@ struct tk_ctx {
         hipGraphNode_t grid_node = nullptr;
     };
     bool graphs_on = false;
+    // float eps path: thresholds of the Cholesky QR (tk_ctx_set_cholqr)
+    CholQr cholqr{1e-12, 1e-4, 0.25};
     // device blocks of freed results, kept for the next results (size -> block); at most
     // kResultCache blocks and kResultCacheBytes bytes, freed with the context
     static constexpr size_t kResultCache = 256;
@@ -773,6 +775,7 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
         b.lam = w.lam; b.sL = 64;
         b.trace = w.trace; b.sTrace = 1;
         b.nb = w.bt.nb; b.bs = w.bt.bs;
+        b.cholqr = w.ctx ? w.ctx->cholqr : CholQr{};
         // the eigensolver writes U after its last use of Y, so U may alias Y
         {
             ProfScope ps(TK_PROF_EIG, s);
@@ -798,6 +801,7 @@ tk_status eig_modes(const Plan& P, Work& w, int nmax, hipStream_t s)
             b.lam = w.lam + 64 * k; b.sL = 64;
             b.trace = w.trace + k; b.sTrace = 1;
             b.nb = w.bt.nb; b.bs = w.bt.bs;
+            b.cholqr = w.ctx ? w.ctx->cholqr : CholQr{};
             if (span && P.R[k] < P.n[k]) { b.p = P.R[k]; b.span_only = 1; }
             {
                 ProfScope ps(TK_PROF_EIG, s);
@@ -838,6 +842,7 @@ tk_status eig_update(const Plan& P, Work& w, int k, const double* Gs, hipStream_
     b.trace = nullptr;
     b.nb = w.bt.nb; b.bs = w.bt.bs;
     b.U32 = u32;
+    b.cholqr = w.ctx ? w.ctx->cholqr : CholQr{};
     {
         ProfScope ps(TK_PROF_EIG, s);
         TK_LAUNCH(launch_eig(b, P.prec == TK_FP64 ? WARM_ITERS : WARM_ITERS_F32, s));
@@ -2226,6 +2231,21 @@ tk_status tk_ctx_set_graphs(tk_ctx* ctx, int on)
     if (!ctx) return fail(TK_EINVAL, "ctx is NULL");
     std::lock_guard<std::mutex> g(ctx->graph_mu);
     ctx->graphs_on = on != 0;
+    return TK_OK;
+}
+
+tk_status tk_ctx_set_cholqr(tk_ctx* ctx, double floor, double one_pass, double accept2)
+{
+    if (!ctx || !(floor == floor) || !(one_pass == one_pass) || !(accept2 == accept2))
+        return fail(TK_EINVAL, "ctx is NULL or a threshold is NaN");
+    std::lock_guard<std::mutex> g(ctx->graph_mu);
+    ctx->cholqr = CholQr{floor > 0.0 ? floor : 0.0, one_pass, accept2};
+    // captured pipelines hold the old threshold in their launches
+    for (auto& kv : ctx->graphs) {
+        (void)hipGraphExecDestroy(kv.second.ex);
+        (void)hipGraphDestroy(kv.second.g);
+    }
+    ctx->graphs.clear();
     return TK_OK;
 }
 

@@ -132,6 +132,12 @@ hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
 // Outputs: U (n x r per problem, ld ldu, stride sU), lam (r per problem, stride sL),
 // trace (optional, trace(G), stride sTrace).
 constexpr int EIG_PMAX = 56;
+// Thresholds of the Cholesky QR (squared sines of its pivots): first-pass pivots below floor are
+// raised to it; one pass when all are >= one_pass; the second pass needs all >= accept2, else
+// the block takes Householder QR.  floor <= 0: Householder only.
+struct CholQr {
+    double floor = 0.0, one_pass = 1e-4, accept2 = 0.25;
+};
 struct EigBatch {
     int count, n, p, r, rw, ldw;
     const double* G; long sG;
@@ -146,6 +152,7 @@ struct EigBatch {
     long bs;
     float* U32;      // optional FP32 copy of U (ld r, stride n r); written by the last QR where it
                      // writes U itself, by a conversion otherwise; moves by bs like the others
+    CholQr cholqr;   // span-only: orthonormalise by Cholesky QR when cholqr.floor > 0
 };
 hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s);
 // Convergence test of the r Ritz pairs (lam, U) of each problem of b against its G:

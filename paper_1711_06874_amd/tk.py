@@ -105,6 +105,7 @@ _SIGS = {
     "tk_ctx_release_stream": (_st, [_vp, _vp]),
     "tk_ctx_set_workers": (_st, [_vp, ctypes.c_int]),
     "tk_ctx_set_graphs": (_st, [_vp, ctypes.c_int]),
+    "tk_ctx_set_cholqr": (_st, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "tk_quadratic_form_batch": (_st, [_vp, ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int, _vp,
                                       _dp, ctypes.POINTER(_vp)]),
     "tk_estimate_matvec_bytes": (_st, [_vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
@@ -529,6 +530,10 @@ class Context:
 
     def set_graphs(self, on: bool):
         _check(_lib.tk_ctx_set_graphs(self.handle, 1 if on else 0), "tk_ctx_set_graphs")
+
+    def set_cholqr(self, floor: float = 1e-12, one_pass: float = 1e-4, accept2: float = 0.25):
+        _check(_lib.tk_ctx_set_cholqr(self.handle, float(floor), float(one_pass), float(accept2)),
+               "tk_ctx_set_cholqr")
 
     def destroy(self):
         if self.handle:
