@@ -812,10 +812,10 @@ __global__ void __launch_bounds__(NT) k_cholqr_reg(const double* __restrict__ In
 
 // ---------------------------------------------------------------------------------------------
 // Two-sided Jacobi on a p x p symmetric matrix (p <= JW_PMAX) by one work-group, parallel
-// round-robin ordering.  After the rotations of a step are formed, every 2 x 2 block (P, Q) of
-// the pair partition is replaced by J_P^T B J_Q in one pass (upper blocks, mirrored), the
-// diagonal blocks by the closed form (a_pp - t a_pq, a_qq + t a_pq, 0), and the rows of V by
-// V J.  Stops when off(H) <= max(tol, p u) ||H||_F or after max_sweeps sweeps.
+// round-robin ordering.  In every step each 2 x 2 block (P, Q) of the pair partition is replaced
+// by J_P^T B J_Q (upper blocks, mirrored), the diagonal blocks by the closed form
+// (a_pp - t a_pq, a_qq + t a_pq, 0), and the rows of V by V J.  Stops when
+// off(H) <= max(tol, p u) ||H||_F or after max_sweeps sweeps.
 constexpr int JW_PMAX = 32;
 constexpr int JW_NP = JW_PMAX / 2;                          // pairs per step
 constexpr int JW_NBLK = JW_NP * (JW_NP + 1) / 2;            // 2 x 2 blocks (P <= Q)
@@ -835,7 +835,33 @@ __device__ __forceinline__ double jw_sum(double v, double* red)
     }
 }
 
-// NTJ threads (64: one wavefront; 256: the 2 x 2 blocks and the rows of V spread over four)
+// Rotation of the pair (a, b) of the symmetric matrix H (row stride JW_PMAX + 1): t = tan of the
+// smaller angle that annihilates h_ab, c = cos, s = sin; (1, 0, 0) when h_ab = 0 or b is the
+// padding index.  The quotients use the hardware reciprocal and reciprocal square root with
+// Newton steps (about one ulp).
+__device__ __forceinline__ void jw_rotation(const double (*H)[JW_PMAX + 1], int a, int b, int p, double& c,
+                                            double& sn, double& t)
+{
+    c = 1.0; sn = 0.0; t = 0.0;
+    if (b >= p) return;
+    const double apq = H[a][b];
+    if (apq == 0.0) return;
+    const double d = H[b][b] - H[a][a];
+    const double den = fabs(d) + sqrt(d * d + 4.0 * apq * apq);
+    t = 2.0 * apq * recip(den);
+    if (d < 0.0) t = -t;
+    const double x = 1.0 + t * t;
+    double rs = __builtin_amdgcn_rsq(x);
+    rs = rs * fma(-0.5 * x * rs, rs, 1.5);
+    rs = rs * fma(-0.5 * x * rs, rs, 1.5);
+    c = rs;
+    sn = t * c;
+}
+
+// NTJ threads (64: one wavefront; 256: the 2 x 2 blocks and the rows of V spread over four).
+// H is double-buffered: a step reads the rotations' entries and its blocks from one copy and
+// writes every entry of its blocks to the other, so each thread forms the rotations it needs
+// itself and a step takes one barrier.
 template <int NTJ>
 __global__ void __launch_bounds__(NTJ) k_jacobi_w(const double* __restrict__ Hin, long sH, int p, int r,
                                                   double* __restrict__ Vs, long sV, int ldv, double* __restrict__ lam,
@@ -848,31 +874,40 @@ __global__ void __launch_bounds__(NTJ) k_jacobi_w(const double* __restrict__ Hin
     Hin = bshift(Hin, bs);
     Vs = bshift(Vs, bs);
     lam = bshift(lam, bs);
-    __shared__ double H[JW_PMAX][JW_PMAX + 1];
+    __shared__ double Hb[2][JW_PMAX][JW_PMAX + 1];
     __shared__ double V[JW_PMAX][JW_PMAX + 1];
-    __shared__ double cs[JW_NP][3];          // c, s, t
-    __shared__ int pq[JW_NP][2];
+    __shared__ unsigned char pairs[JW_PMAX - 1][JW_NP][2];   // round-robin pairs (a < b) of every step
     __shared__ unsigned char blk[JW_NBLK][2];
     __shared__ int rank_of[JW_PMAX];
     const int lane = threadIdx.x;     // thread index (not only within a wavefront)
     const double* Hp = Hin + (long)blockIdx.x * sH;
     for (int e = lane; e < p * p; e += NTJ) {
         const int i = e / p, j = e - (e / p) * p;
-        H[i][j] = 0.5 * (Hp[(long)i * p + j] + Hp[(long)j * p + i]);
+        Hb[0][i][j] = 0.5 * (Hp[(long)i * p + j] + Hp[(long)j * p + i]);
         V[i][j] = (i == j) ? 1.0 : 0.0;
     }
     const int m = p + (p & 1);
     const int np = m / 2;
     const int nblk = np * (np + 1) / 2;
+    for (int e = lane; e < (m - 1) * np; e += NTJ) {
+        const int step = e / np, k = e - (e / np) * np;
+        int a, bb;
+        if (k == 0) { a = m - 1; bb = step; }
+        else { a = (step + k) % (m - 1); bb = (step - k + (m - 1)) % (m - 1); }
+        if (a > bb) { const int q = a; a = bb; bb = q; }
+        pairs[step][k][0] = (unsigned char)a;
+        pairs[step][k][1] = (unsigned char)bb;
+    }
     if (lane == 0) {
         int e = 0;
         for (int P = 0; P < np; ++P)
             for (int Q = P; Q < np; ++Q, ++e) { blk[e][0] = (unsigned char)P; blk[e][1] = (unsigned char)Q; }
     }
     __syncthreads();
+    int cur = 0;
     double f = 0.0;
     for (int e = lane; e < p * p; e += NTJ) {
-        const double x = H[e / p][e - (e / p) * p];
+        const double x = Hb[0][e / p][e - (e / p) * p];
         f += x * x;
     }
     const double fro = sqrt(jw_sum<NTJ>(f, red));
@@ -883,7 +918,7 @@ __global__ void __launch_bounds__(NTJ) k_jacobi_w(const double* __restrict__ Hin
         double o = 0.0;
         for (int e = lane; e < p * p; e += NTJ) {
             const int i = e / p, j = e - (e / p) * p;
-            if (i != j) o += H[i][j] * H[i][j];
+            if (i != j) o += Hb[cur][i][j] * Hb[cur][i][j];
         }
         const double off = sqrt(jw_sum<NTJ>(o, red));
         if (off <= tol * fro) break;
@@ -892,96 +927,67 @@ __global__ void __launch_bounds__(NTJ) k_jacobi_w(const double* __restrict__ Hin
         if (off <= 1e-12 * fro && off > 0.5 * prev_off) break;
         prev_off = off;
         for (int step = 0; step < m - 1; ++step) {
-            if (lane < np) {
-                int a, bb;
-                if (lane == 0) { a = m - 1; bb = step; }
-                else { a = (step + lane) % (m - 1); bb = (step - lane + (m - 1)) % (m - 1); }
-                if (a > bb) { const int q = a; a = bb; bb = q; }
-                double c = 1.0, sn = 0.0, t = 0.0;
-                if (bb < p) {
-                    const double apq = H[a][bb];
-                    if (apq != 0.0) {
-                        // t = tan(theta) of the smaller rotation annihilating a_pq
-                        const double d = H[bb][bb] - H[a][a];
-                        const double den = fabs(d) + sqrt(d * d + 4.0 * apq * apq);
-                        t = 2.0 * apq / den;
-                        if (d < 0.0) t = -t;
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        sn = t * c;
-                    }
-                }
-                pq[lane][0] = a; pq[lane][1] = bb;
-                cs[lane][0] = c; cs[lane][1] = sn; cs[lane][2] = t;
-            }
-            __syncthreads();
-            // ---- 2 x 2 blocks (P <= Q) of H: all loads of the lane first, then the updates
-            int ia[JW_BPL], ib[JW_BPL], ja[JW_BPL], jb[JW_BPL];
-            double x00[JW_BPL], x01[JW_BPL], x10[JW_BPL], x11[JW_BPL];
-            double cP[JW_BPL], sP[JW_BPL], tP[JW_BPL], cQ[JW_BPL], sQ[JW_BPL];
-            bool diag[JW_BPL], live[JW_BPL];
+            const double (*Hc)[JW_PMAX + 1] = Hb[cur];
+            double (*Hn)[JW_PMAX + 1] = Hb[cur ^ 1];
+            // ---- 2 x 2 blocks (P <= Q): rotations and entries from Hc, every entry to Hn
 #pragma unroll
             for (int u = 0; u < JW_BPL; ++u) {
                 const int e = lane + NTJ * u;
-                live[u] = e < nblk;
-                const int P = live[u] ? blk[e][0] : 0, Q = live[u] ? blk[e][1] : 0;
-                diag[u] = P == Q;
-                ia[u] = pq[P][0]; ib[u] = pq[P][1]; ja[u] = pq[Q][0]; jb[u] = pq[Q][1];
-                cP[u] = cs[P][0]; sP[u] = cs[P][1]; tP[u] = cs[P][2]; cQ[u] = cs[Q][0]; sQ[u] = cs[Q][1];
-                const bool rb = ib[u] < p, cb = jb[u] < p;
-                x00[u] = live[u] ? H[ia[u]][ja[u]] : 0.0;
-                x01[u] = (live[u] && cb) ? H[ia[u]][jb[u]] : 0.0;
-                x10[u] = (live[u] && rb) ? H[ib[u]][ja[u]] : 0.0;
-                x11[u] = (live[u] && rb && cb) ? H[ib[u]][jb[u]] : 0.0;
-            }
-            // ---- rows of V (row = lane % 32, pairs of one parity): loads first as well
-            const int vrow = lane & 31, vhalf = lane >> 5;
-            double vx[JW_VPL], vy[JW_VPL];
-            int va[JW_VPL], vb[JW_VPL];
-#pragma unroll
-            for (int u = 0; u < JW_VPL; ++u) {
-                const int kk = vhalf + JW_VG * u;
-                va[u] = (kk < np) ? pq[kk][0] : 0;
-                vb[u] = (kk < np) ? pq[kk][1] : p;
-                const bool ok = vrow < p && vb[u] < p;
-                vx[u] = ok ? V[vrow][va[u]] : 0.0;
-                vy[u] = ok ? V[vrow][vb[u]] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < JW_BPL; ++u) {
-                if (!live[u]) continue;
-                const bool rb = ib[u] < p, cb = jb[u] < p;
-                if (diag[u]) {
-                    if (rb && tP[u] != 0.0) {
+                if (e >= nblk) continue;
+                const int P = blk[e][0], Q = blk[e][1];
+                const int ia = pairs[step][P][0], ib = pairs[step][P][1];
+                const int ja = pairs[step][Q][0], jb = pairs[step][Q][1];
+                const bool rb = ib < p, cb = jb < p;
+                double cP, sP, tP;
+                jw_rotation(Hc, ia, ib, p, cP, sP, tP);
+                const double x00 = Hc[ia][ja];
+                const double x01 = cb ? Hc[ia][jb] : 0.0;
+                const double x10 = rb ? Hc[ib][ja] : 0.0;
+                const double x11 = (rb && cb) ? Hc[ib][jb] : 0.0;
+                if (P == Q) {
+                    if (rb) {
                         // closed form on the diagonal block: (a_pp - t a_pq, a_qq + t a_pq, 0)
-                        const double apq = x01[u];
-                        H[ia[u]][ia[u]] = x00[u] - tP[u] * apq;
-                        H[ib[u]][ib[u]] = x11[u] + tP[u] * apq;
-                        H[ia[u]][ib[u]] = 0.0;
-                        H[ib[u]][ia[u]] = 0.0;
+                        const bool rot = tP != 0.0;
+                        Hn[ia][ia] = rot ? x00 - tP * x01 : x00;
+                        Hn[ib][ib] = rot ? x11 + tP * x01 : x11;
+                        Hn[ia][ib] = rot ? 0.0 : x01;
+                        Hn[ib][ia] = rot ? 0.0 : x01;
+                    } else {
+                        Hn[ia][ia] = x00;
                     }
                 } else {
+                    double cQ, sQ, tQ;
+                    jw_rotation(Hc, ja, jb, p, cQ, sQ, tQ);
                     // rows: J_P^T [x0; x1]; columns: [y.0 y.1] J_Q
-                    const double y00 = cP[u] * x00[u] - sP[u] * x10[u], y10 = sP[u] * x00[u] + cP[u] * x10[u];
-                    const double y01 = cP[u] * x01[u] - sP[u] * x11[u], y11 = sP[u] * x01[u] + cP[u] * x11[u];
-                    const double z00 = cQ[u] * y00 - sQ[u] * y01, z01 = sQ[u] * y00 + cQ[u] * y01;
-                    const double z10 = cQ[u] * y10 - sQ[u] * y11, z11 = sQ[u] * y10 + cQ[u] * y11;
-                    H[ia[u]][ja[u]] = z00; H[ja[u]][ia[u]] = z00;
-                    if (cb) { H[ia[u]][jb[u]] = z01; H[jb[u]][ia[u]] = z01; }
-                    if (rb) { H[ib[u]][ja[u]] = z10; H[ja[u]][ib[u]] = z10; }
-                    if (rb && cb) { H[ib[u]][jb[u]] = z11; H[jb[u]][ib[u]] = z11; }
+                    const double y00 = cP * x00 - sP * x10, y10 = sP * x00 + cP * x10;
+                    const double y01 = cP * x01 - sP * x11, y11 = sP * x01 + cP * x11;
+                    const double z00 = cQ * y00 - sQ * y01, z01 = sQ * y00 + cQ * y01;
+                    const double z10 = cQ * y10 - sQ * y11, z11 = sQ * y10 + cQ * y11;
+                    Hn[ia][ja] = z00; Hn[ja][ia] = z00;
+                    if (cb) { Hn[ia][jb] = z01; Hn[jb][ia] = z01; }
+                    if (rb) { Hn[ib][ja] = z10; Hn[ja][ib] = z10; }
+                    if (rb && cb) { Hn[ib][jb] = z11; Hn[jb][ib] = z11; }
                 }
             }
+            // ---- rows of V (row = lane % 32, pairs of one parity): each entry has one owner
+            const int vrow = lane & 31, vhalf = lane >> 5;
 #pragma unroll
             for (int u = 0; u < JW_VPL; ++u) {
                 const int kk = vhalf + JW_VG * u;
-                if (kk >= np || vrow >= p || vb[u] >= p) continue;
-                const double c = cs[kk][0], sn = cs[kk][1];
-                V[vrow][va[u]] = c * vx[u] - sn * vy[u];
-                V[vrow][vb[u]] = sn * vx[u] + c * vy[u];
+                if (kk >= np || vrow >= p) continue;
+                const int va = pairs[step][kk][0], vb = pairs[step][kk][1];
+                if (vb >= p) continue;
+                double c, sn, t;
+                jw_rotation(Hc, va, vb, p, c, sn, t);
+                const double vx = V[vrow][va], vy = V[vrow][vb];
+                V[vrow][va] = c * vx - sn * vy;
+                V[vrow][vb] = sn * vx + c * vy;
             }
+            cur ^= 1;
             __syncthreads();
         }
     }
+    const double (*H)[JW_PMAX + 1] = Hb[cur];
     // stable descending ranks
     if (lane < p) {
         const double d = H[lane][lane];

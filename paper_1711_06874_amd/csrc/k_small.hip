@@ -57,11 +57,12 @@ __global__ void __launch_bounds__(64 * KS) k_gemm(GemmArgs g)
     for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // k-groups of 4 GKU, double-buffered in registers: the loads of group g + 1 are in flight while
+    // group g's products run (the order of the sum over k is unchanged)
     for (long b = b_first; b < b_last; ++b) {
         const TA* A = (const TA*)g.A + b * g.sAb;
         const TB* B = (const TB*)g.B + b * g.sBb;
-        for (int k0 = kbeg; k0 < kend; k0 += 4 * GKU) {
-            double av[GKU][TM], bv[GKU][TN];
+        auto load = [&](int k0, double (&av)[GKU][TM], double (&bv)[GKU][TN]) {
 #pragma unroll
             for (int u = 0; u < GKU; ++u) {
                 const int k = k0 + 4 * u + lk;
@@ -71,6 +72,8 @@ __global__ void __launch_bounds__(64 * KS) k_gemm(GemmArgs g)
 #pragma unroll
                 for (int j = 0; j < TN; ++j) bv[u][j] = (kv && nv[j]) ? (double)B[(long)k * g.sBk + boff[j]] : 0.0;
             }
+        };
+        auto products = [&](int k0, const double (&av)[GKU][TM], const double (&bv)[GKU][TN]) {
 #pragma unroll
             for (int u = 0; u < GKU; ++u) {
                 if (k0 + 4 * u < kend) {
@@ -81,6 +84,19 @@ __global__ void __launch_bounds__(64 * KS) k_gemm(GemmArgs g)
                             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][i], bv[u][j], acc[i][j], 0, 0, 0);
                 }
             }
+        };
+        double a0[GKU][TM], b0[GKU][TN], a1[GKU][TM], b1[GKU][TN];
+        int k0 = kbeg;
+        if (k0 < kend) load(k0, a0, b0);
+        while (k0 < kend) {
+            const int k1 = k0 + 4 * GKU;
+            if (k1 < kend) load(k1, a1, b1);
+            products(k0, a0, b0);
+            if (k1 >= kend) break;
+            const int k2 = k1 + 4 * GKU;
+            if (k2 < kend) load(k2, a0, b0);
+            products(k1, a1, b1);
+            k0 = k2;
         }
     }
     if constexpr (KS > 1) {
