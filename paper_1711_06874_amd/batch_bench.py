@@ -51,6 +51,8 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="tune the Gram kernel and split of every size first")
     ap.add_argument("--graphs", action="store_true", help="replay the captured compression pipeline of every "
                     "shape (tk_ctx_set_graphs)")
+    ap.add_argument("--qr", choices=["cholesky", "householder"], default="cholesky",
+                    help="orthonormalisation of the span-only steps (tk_ctx_set_cholqr)")
     args = ap.parse_args()
 
     import torch
@@ -72,9 +74,12 @@ def main():
               "workload": "256 Matern tensors, n uniform over {32,...,256}, centred grids, eps 1e-6"}
     ctx = tk.Context(0)
     common["graphs"] = bool(args.graphs)
+    common["qr"] = args.qr
     try:
         if args.graphs:
             ctx.set_graphs(True)
+        if args.qr == "householder":
+            ctx.set_cholqr(0.0)
         if args.autotune:
             common["gram_autotune"] = {str(n): ctx.autotune(tk.make_grid(n, 1.0, 0), prec)["nsplit"]
                                        for n in sorted(set(sizes))}
