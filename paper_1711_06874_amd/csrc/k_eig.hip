@@ -1237,16 +1237,18 @@ static hipError_t qr_launch(const double* in, double* out, int count, int n, int
 }
 
 // Jacobi on `count` p x p matrices (stride sH) -> leading r eigenvectors (stride sV, ld ldv)
+// tol: the stopping threshold on off(H) / ||H||_F (0: 1e-15)
 static hipError_t jacobi_launch(const double* H, long sH, int count, int p, int r, double* V, long sV, int ldv,
-                                double* lam, long sL, hipStream_t s, Bat bt)
+                                double* lam, long sL, hipStream_t s, Bat bt, double tol = 0.0)
 {
     const dim3 grid(count, 1, bt.nb);
+    if (!(tol > 0.0)) tol = 1e-15;
     if (p <= JW_PMAX) {
-        hipLaunchKernelGGL(k_jacobi_w<256>, grid, dim3(256), 0, s, H, sH, p, r, V, sV, ldv, lam, sL, 60, 1e-15, bt.bs);
+        hipLaunchKernelGGL(k_jacobi_w<256>, grid, dim3(256), 0, s, H, sH, p, r, V, sV, ldv, lam, sL, 60, tol, bt.bs);
         return hipGetLastError();
     }
     if (sH != (long)p * p || sV != (long)p * r || ldv != r) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_jacobi, grid, dim3(256), 0, s, H, p, r, V, lam, sL, 60, 1e-15, bt.bs);
+    hipLaunchKernelGGL(k_jacobi, grid, dim3(256), 0, s, H, p, r, V, lam, sL, 60, tol, bt.bs);
     return hipGetLastError();
 }
 
@@ -1288,7 +1290,8 @@ static hipError_t eig_body(const EigBatch& b, int iters, hipStream_t s, bool& wr
     }
     if (p == n && p <= JW_PMAX) {
         // the block is the identity: diagonalise G itself
-        if ((e = jacobi_launch(b.G, b.count > 1 ? b.sG : 0, b.count, p, r, b.U, b.sU, b.ldu, b.lam, b.sL, s, bt)) !=
+        if ((e = jacobi_launch(b.G, b.count > 1 ? b.sG : 0, b.count, p, r, b.U, b.sU, b.ldu, b.lam, b.sL, s, bt,
+                               b.jacobi_tol)) !=
             hipSuccess)
             return e;
         hipLaunchKernelGGL(k_signfix, dim3(r, b.count, bt.nb), dim3(256), 0, s, b.U, b.sU, b.ldu, n, bt.bs);

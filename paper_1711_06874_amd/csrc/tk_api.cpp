@@ -70,9 +70,14 @@ constexpr int COLD_ITERS_F32 = 2;     // ... float paths (HOOI refines the subsp
 constexpr int WARM_ITERS = 2;         // ... from the previous factor (FP64 path: exact HOOI steps)
 constexpr int WARM_ITERS_F32 = 1;     // ... float paths: one block power step per HOOI update
 constexpr int SPAN_ITERS_F32 = 2;     // float eps path, HOSVD start: R-column block, subspace only
+// Jacobi of the core Grams in the float eps truncation: off(H) <= 1e-10 ||H||_F leaves the
+// eigenvalues off by about off(H)^2 / gap, far below the eps^2 a2 / 3 budget of the rank rule,
+// and V orthogonal to rounding (a product of rotations); the truncated result's error is then
+// measured against A
+constexpr double CORE_JACOBI_TOL = 1e-10;
 constexpr int NMAX = 1024;
-constexpr double MATERN_NU_MAX = 30.0;
-constexpr int KRON1_NMAX = 16384;       // points per axis of a separable covariance factor   // general orders: K_nu s^nu stays inside the double range
+constexpr double MATERN_NU_MAX = 30.0;  // general orders: K_nu s^nu stays inside the double range
+constexpr int KRON1_NMAX = 16384;       // points per axis of a separable covariance factor
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -1039,6 +1044,7 @@ tk_status core_truncate(const Plan& P, Work& w, hipStream_t s)
         b.lam = w.lamc; b.sL = 64;
         b.trace = nullptr;
         b.nb = w.bt.nb; b.bs = w.bt.bs;
+        b.jacobi_tol = CORE_JACOBI_TOL;
         TK_LAUNCH(launch_eig(b, 0, s));
     } else {
         for (int k = 0; k < 3; ++k) {
@@ -1050,6 +1056,7 @@ tk_status core_truncate(const Plan& P, Work& w, hipStream_t s)
             b.lam = w.lamc + 64 * k; b.sL = 64;
             b.trace = nullptr;
             b.nb = w.bt.nb; b.bs = w.bt.bs;
+            b.jacobi_tol = CORE_JACOBI_TOL;
             TK_LAUNCH(launch_eig(b, 0, s));
         }
     }

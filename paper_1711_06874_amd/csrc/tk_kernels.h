@@ -153,6 +153,7 @@ struct EigBatch {
     float* U32;      // optional FP32 copy of U (ld r, stride n r); written by the last QR where it
                      // writes U itself, by a conversion otherwise; moves by bs like the others
     CholQr cholqr;   // span-only: orthonormalise by Cholesky QR when cholqr.floor > 0
+    double jacobi_tol;   // p == n: Jacobi stops at off(H) <= jacobi_tol ||H||_F (0: 1e-15)
 };
 hipError_t launch_eig(const EigBatch& b, int iters, hipStream_t s);
 // Convergence test of the r Ritz pairs (lam, U) of each problem of b against its G:
