@@ -12,8 +12,9 @@
 // the block is the identity and the whole matrix is diagonalised by Jacobi directly.
 //
 // Kernels: k_eig_init (start block; a warm block of exactly p columns is read in place by the
-// first product instead), k_hqr_reg (rows in registers, n <= 1024 and p <= 32; it can also write
-// an FP32 copy of the factor) and k_hqr (one work-group per problem, Householder QR with the
+// first product instead), k_cholqr_reg (Cholesky QR of the span-only blocks of the float eps
+// path, with a Householder fallback), k_hqr_reg (rows in registers, n <= 1024 and p <= 32; it can
+// also write an FP32 copy of the factor) and k_hqr (one work-group per problem, Householder QR with the
 // n x p block resident in LDS when it fits, producing the explicit Q in place), k_jacobi_w /
 // k_jacobi (one work-group per problem, p x p in LDS), k_signfix; the products G Q, Q^T Y and
 // Q V use the batched small-product kernel.
@@ -708,7 +709,8 @@ __global__ void __launch_bounds__(NT) k_cholqr_reg(const double* __restrict__ In
                 const double draw = wr[j];
                 const double cand = (pass > 0 || draw >= floor * w0) ? draw : floor * w0;
                 if (lane == j) {
-                    weak = !(draw >= one_pass * w0);
+                    // a zero column (W_jj = 0) is weak too: the second pass replaces it
+                    weak = !(draw >= one_pass * w0) || !(w0 > 0.0);
                     bad = !(draw >= accept2 * w0) || !(w0 > 0.0);
                     mydiag = cand;
                 }
