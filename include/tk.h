@@ -275,7 +275,8 @@ tk_status tk_ctx_set_graphs(tk_ctx *ctx, int on);
 
 /* Orthonormalisation of the float eps path (Sec. 3.2: the HOSVD start and the HOOI updates only
  * carry the leading subspace, which the core's HOSVD rotates at the end).  Its n x p block Y
- * (n <= 1024, p <= 32) is orthonormalised by Cholesky QR, W = Y^T Y = L D L^T,
+ * (n <= 256 and p <= 32, or n <= 512 and p <= 24; larger blocks take Householder QR) is
+ * orthonormalised by Cholesky QR, W = Y^T Y = L D L^T,
  * Q = Y L^-T D^-1/2, steered per block inside the kernel by the pivots' squared sines
  * s_j = d_j / W_jj.  First pass: pivots with s_j < floor are raised to floor W_jj (such columns
  * lie in the span of the earlier ones to rounding); all s_j >= one_pass ends there, else a
