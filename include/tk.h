@@ -280,11 +280,12 @@ tk_status tk_ctx_set_graphs(tk_ctx *ctx, int on);
  * Q = Y L^-T D^-1/2, steered per block inside the kernel by the pivots' squared sines
  * s_j = d_j / W_jj.  First pass: pivots with s_j < floor are raised to floor W_jj (such columns
  * lie in the span of the earlier ones to rounding); all s_j >= one_pass ends there, else a
- * second pass orthonormalises the result, and unless all its s_j >= accept2 the block is
- * orthonormalised by Householder QR instead.  The first block of a cold start always takes
- * Householder.  Defaults floor = 1e-12, one_pass = 1e-4, accept2 = 0.25.  floor <= 0:
- * Householder for every block; one_pass > 1: always two passes; accept2 > 1: every Cholesky
- * attempt falls back.  The factors then differ from the Householder route only by rounding
+ * second pass orthonormalises the result.  Columns whose second-pass s_j < accept2 (rounding
+ * noise inside the span of the others) are replaced by fixed pseudo-random columns and a third
+ * pass runs; if its s_j are not all >= accept2 either, the block is orthonormalised by
+ * Householder QR instead.  The first block of a cold start always takes Householder.  Defaults floor = 1e-12, one_pass = 1e-4, accept2 = 0.25.  floor <= 0:
+ * Householder for every block; one_pass > 1: always two passes; accept2 > 1 (with one_pass
+ * > 1): every Cholesky attempt falls back.  The factors then differ from the Householder route only by rounding
  * (the final factors are sign-normalised).  Drops the context's captured graphs.  Host only.
  * Errors: TK_EINVAL (ctx NULL, a threshold NaN). */
 tk_status tk_ctx_set_cholqr(tk_ctx *ctx, double floor, double one_pass, double accept2);
