@@ -627,7 +627,7 @@ __global__ void __launch_bounds__(NT) k_cholqr_reg(const double* __restrict__ In
     __shared__ double Ws[PM][PM + 1];           // W, lower triangle and mirror
     __shared__ double LT[PM][PM + 1];           // LT[k][j] = L[j][k], j > k
     __shared__ double rsd[PM];                  // d_j^-1/2
-    __shared__ unsigned verdict_s[2];           // verdict, columns to replace
+    __shared__ unsigned decision_s[2];          // decision, columns to replace
     __shared__ double S[PM];
     __shared__ double rowjb[2][PM];
     __shared__ double taus[PM];
@@ -638,8 +638,8 @@ __global__ void __launch_bounds__(NT) k_cholqr_reg(const double* __restrict__ In
     double* stg = T + wv * 64 * PM;
     bool householder = false;
 
-    // verdicts: 0 done, 1 solve and take another pass, 2 Householder, 3 replace the columns in
-    // verdict_s[1] (numerically inside the span of the others) and take another pass
+    // decisions: 0 done, 1 solve and take another pass, 2 Householder, 3 replace the columns in
+    // decision_s[1] (numerically inside the span of the others) and take another pass
     for (int pass = 0; pass < 3; ++pass) {
         // ---- Gram of the NT RPT rows on MFMA, per wavefront over its own rows
         f64x4 acc[NTILE];
@@ -736,19 +736,19 @@ __global__ void __launch_bounds__(NT) k_cholqr_reg(const double* __restrict__ In
                 if (pass == 0) v = weak_m ? 1u : 0u;
                 else if (pass == 1) v = bad_m ? 3u : 0u;
                 else v = bad_m ? 2u : 0u;
-                verdict_s[0] = v;
-                verdict_s[1] = (unsigned)bad_m;
+                decision_s[0] = v;
+                decision_s[1] = (unsigned)bad_m;
             }
         }
         __syncthreads();
-        const unsigned verdict = verdict_s[0];
-        if (verdict == 2) {
+        const unsigned decision = decision_s[0];
+        if (decision == 2) {
             householder = true;
             break;
         }
-        if (verdict == 3) {
+        if (decision == 3) {
             // complete the span with fixed pseudo-random columns in place of the dependent ones
-            const unsigned repl = verdict_s[1];
+            const unsigned repl = decision_s[1];
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
                 const int row = tid + q * NT;
@@ -803,7 +803,7 @@ __global__ void __launch_bounds__(NT) k_cholqr_reg(const double* __restrict__ In
         // (unconditional, so that the solve and its loads share one block) a further pass
         // restages these rows and rewrites Ws / LT / rsd
         __syncthreads();
-        if (verdict == 0) break;
+        if (decision == 0) break;
     }
     if (householder) {
         load_rows<PM, NT, RPT>(y, In, off, n, p);
